@@ -1,0 +1,473 @@
+"""Pins of the FP64 oracle against brute force, closed forms and invariants.
+
+Each test fixes one step of the oracle against something other than the
+oracle itself: definitions evaluated densely, Gram identities of the
+condensation steps, exactness of the method without truncation, scaling
+invariance of the block-relative error control and special cases.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import h2_oracle as OH
+import workloads as W
+from oracle_cases import dense, problem, product, rel2, relF
+
+CASES = ["1d", "2d", "2d64", "sph"]
+
+
+# --------------------------------------------------------------------------
+# P1: cluster tree and block tree (Definitions "Cluster tree", "Block tree"; R1-R3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+def test_cluster_tree_definition(name):
+    pts, tree, bt, _, _ = problem(name)
+    n, leaf = tree.n, {"1d": 16, "2d": 32, "2d64": 64, "sph": 32}[name]
+    assert sorted(tree.perm.tolist()) == list(range(n))
+    assert tree.size[0] == n and tree.off[0] == 0
+    for c in range(tree.nclusters):
+        idx = set(tree.perm[tree.rng(c)].tolist())
+        sub = pts[list(idx)]
+        # tight boxes
+        assert np.array_equal(tree.bmin[c], sub.min(axis=0))
+        assert np.array_equal(tree.bmax[c], sub.max(axis=0))
+        kids = tree.children[c]
+        if kids:
+            assert len(kids) == 2
+            parts = [set(tree.perm[tree.rng(k)].tolist()) for k in kids]
+            assert parts[0] | parts[1] == idx and not (parts[0] & parts[1])
+            assert len(parts[0]) == len(idx) // 2
+            # median split along the longest edge, (coordinate, index) order
+            ax = int(np.argmax(tree.bmax[c] - tree.bmin[c]))
+            key = lambda i: (pts[i, ax], i)
+            assert max(map(key, parts[0])) < min(map(key, parts[1]))
+        else:
+            assert tree.size[c] <= leaf and tree.level[c] == tree.depth
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_block_tree_partition_and_admissibility(name):
+    pts, tree, bt, _, _ = problem(name)
+    n = tree.n
+    cover = np.zeros((n, n), dtype=np.int32)
+    for (t, s), ty in bt.type.items():
+        if ty == O.SPLIT:
+            continue
+        cover[tree.rng(t), tree.rng(s)] += 1
+        P, Qp = pts[tree.perm[tree.rng(t)]], pts[tree.perm[tree.rng(s)]]
+        diam_t = np.linalg.norm(P.max(0) - P.min(0))
+        diam_s = np.linalg.norm(Qp.max(0) - Qp.min(0))
+        gap = np.maximum(0, np.maximum(Qp.min(0) - P.max(0), P.min(0) - Qp.max(0)))
+        dist = np.linalg.norm(gap)
+        adm = dist > 0 and max(diam_t, diam_s) <= bt.eta * dist
+        assert adm == (ty == O.ADM)
+        if ty == O.INADM:
+            assert tree.is_leaf(t) and tree.is_leaf(s)
+    assert np.all(cover == 1)
+    # every non-leaf block is inadmissible and has chil(t) x chil(s) as children
+    for (t, s), ty in bt.type.items():
+        if ty == O.SPLIT:
+            assert not bt.admissible(t, s)
+            assert sorted(bt.children[(t, s)]) == sorted(itertools.product(tree.children[t], tree.children[s]))
+
+
+# --------------------------------------------------------------------------
+# P2: Chebyshev H^2 construction (Example "Integral operator"; R4, R5)
+# --------------------------------------------------------------------------
+def test_lagrange_cardinality():
+    nodes = O.cheb_nodes(-0.3, 1.7, 5)
+    assert np.allclose(O.lagrange(nodes, nodes), np.eye(5), atol=1e-14)
+    # nodes are the roots of T_5 mapped to [-0.3, 1.7]
+    u = (nodes - 0.7) / 1.0
+    assert np.allclose(np.cos(5 * np.arccos(u)), 0, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_cluster_basis_nested(name):
+    _, tree, _, X, _ = problem(name)
+    Vf = X.V.full()
+    m = {"1d": 4, "2d": 3, "2d64": 4, "sph": 3}[name]
+    for c in range(1, tree.nclusters):
+        p = tree.parent[c]
+        direct = OH._tensor_lagrange(tree, p, m, tree.points[tree.rng(c)])   # V_parent restricted to c
+        assert np.abs(Vf[c] @ X.V.transfer[c] - direct).max() <= 1e-12 * max(1.0, np.abs(direct).max())
+
+
+@pytest.mark.parametrize("dim,order", [(1, 3), (2, 3), (3, 3)])
+def test_polynomial_kernel_reproduced_exactly(dim, order):
+    pts = W.make_points(5, 300, dim, "uniform")
+    tree = O.ClusterTree(pts, 16)
+    bt = O.BlockTree(tree, tree, 1.0)
+    X = O.kernel_h2(tree, bt, "poly2", order)
+    exact = (tree.points @ tree.points.T) ** 2
+    assert relF(X.dense(), exact) < 1e-12
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_matvec_equals_dense(name):
+    _, tree, _, X, Y = problem(name)
+    Xd, Yd, _ = dense(name)
+    x = W.probe_vectors(3, tree.n, 3)
+    assert relF(X.matvec(x), Xd @ x) < 1e-13
+    assert relF(Y.matvec(x), Yd @ x) < 1e-13
+    assert relF(X.transposed().matvec(x), Xd.T @ x) < 1e-13
+
+
+def test_kernel_entries_and_diagonal():
+    _, tree, _, X, Y = problem("2d")
+    Xd, Yd, _ = dense("2d")
+    p = tree.points
+    i, j = 5, 300
+    # a nearfield entry is the kernel itself; the diagonal follows R5
+    r = np.linalg.norm(p[i] - p[j])
+    for b, N in X.N.items():
+        t, s = b
+        if tree.off[t] <= i < tree.off[t] + tree.size[t] and tree.off[s] <= j < tree.off[s] + tree.size[s]:
+            assert np.isclose(Xd[i, j], np.log(r), rtol=1e-14)
+            assert np.isclose(Yd[i, j], np.exp(-r), rtol=1e-14)
+    assert np.all(np.diag(Xd) == 0.0) and np.all(np.diag(Yd) == 1.0)
+
+
+# --------------------------------------------------------------------------
+# P3-P5: set-up quantities (basis weights, basis products, total weights)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+def test_basis_weights_gram(name):
+    _, tree, _, _, Y = problem(name)
+    R = O.basis_weights(Y.W)
+    Wf = Y.W.full()
+    for r in range(tree.nclusters):
+        G = Wf[r].T @ Wf[r]
+        assert R[r].shape[0] == min(Y.W.rank[r], tree.size[r])
+        assert np.abs(R[r].T @ R[r] - G).max() <= 1e-13 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_cluster_basis_products_dense(name):
+    _, tree, _, X, Y = problem(name)
+    P = O.cluster_basis_products(X.W, Y.V)
+    Wf, Vf = X.W.full(), Y.V.full()
+    for s in range(tree.nclusters):
+        D = Wf[s].T @ Vf[s]
+        assert np.abs(P[s] - D).max() <= 1e-13 * np.abs(D).max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_total_weights_gram(name):
+    """V_{Y,s} Z_s^* Z_s V_{Y,s}^* equals the Gram matrix of the scaled dense
+    rows Y|_{s x r} of every admissible block (s*, r) with s* an ancestor of
+    s or s itself; the scale is 1/||S_{Y,s*r} W_{Y,r}^*||_2 (Section 5)."""
+    _, tree, _, _, Y = problem(name)
+    _, Yd, _ = dense(name)
+    Z = O.total_weights(Y, O.basis_weights(Y.W))
+    Vf, Wf = Y.V.full(), Y.W.full()
+    for s in range(tree.nclusters):
+        lhs = Vf[s] @ Z[s].T @ Z[s] @ Vf[s].T
+        rhs = np.zeros_like(lhs)
+        anc = s
+        while anc >= 0:
+            for (a, r), ty in Y.bt.type.items():
+                if a == anc and ty == O.ADM:
+                    w = np.linalg.norm(Y.S[(a, r)] @ Wf[r].T, 2)
+                    B = Yd[tree.rng(s), tree.rng(r)] / w
+                    rhs += B @ B.T
+            anc = tree.parent[anc]
+        assert np.abs(lhs - rhs).max() <= 1e-12 * max(np.abs(rhs).max(), 1e-300)
+
+
+# --------------------------------------------------------------------------
+# P6: phase 1 (Section 4, Figure "induced_basis"; Section 5)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_phase1_basis_isometric_and_keeps_VX(name, eps):
+    _, tree, _, X, _ = problem(name)
+    p1, _ = product(name, eps)
+    for side, VX in ((p1.row, X.V.full()), (p1.col, problem(name)[4].W.full())):
+        Qf = side.Q.full()
+        for t in range(tree.nclusters):
+            Q = Qf[t]
+            assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-13
+            res = VX[t] - Q @ (Q.T @ VX[t])
+            assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(VX[t])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_phase1_condensation_gram(name):
+    """The assembled remainder of induced_basis(t) has the Gram matrix of the
+    uncondensed block-scaled products X|_{t x s} Y|_{s x r} (leaf), projected
+    onto the children's bases (non-leaf)."""
+    _, tree, _, X, Y = problem(name)
+    Xd, Yd, _ = dense(name)
+    p1, _ = product(name, 1e-6)
+    Qf = p1.row.Q.full()
+    Vyf, Wyf = Y.V.full(), Y.W.full()
+    for t in range(tree.nclusters):
+        if tree.is_leaf(t):
+            U = np.eye(tree.size[t])
+        else:
+            U = np.zeros((tree.size[t], sum(p1.row.Q.rank[c] for c in tree.children[t])))
+            o = 0
+            for c in tree.children[t]:
+                sl = slice(tree.off[c] - tree.off[t], tree.off[c] - tree.off[t] + tree.size[c])
+                U[sl, o:o + p1.row.Q.rank[c]] = Qf[c]
+                o += p1.row.Q.rank[c]
+        B = []
+        for (a, s), ty in X.bt.type.items():
+            if a != t or ty == O.ADM:
+                continue
+            XV = U.T @ Xd[tree.rng(t), tree.rng(s)] @ Vyf[s]
+            ws = np.linalg.norm(XV, 2)
+            if ws == 0:
+                continue
+            anc = s
+            while anc >= 0:
+                for (b0, r), tyy in Y.bt.type.items():
+                    if b0 == anc and tyy == O.ADM:
+                        wr = np.linalg.norm(Y.S[(b0, r)] @ Wyf[r].T, 2)
+                        B.append(U.T @ Xd[tree.rng(t), tree.rng(s)] @ Yd[tree.rng(s), tree.rng(r)] / (ws * wr))
+                anc = tree.parent[anc]
+        VX, Vrest = p1.row.assembled[t]
+        assert np.abs(VX - U.T @ X.V.full()[t]).max() <= 1e-12 * np.abs(VX).max()
+        if not B:
+            assert Vrest.shape[1] == 0 or np.abs(Vrest).max() == 0
+            continue
+        Bm = np.hstack(B)
+        lhs, rhs = Vrest @ Vrest.T, Bm @ Bm.T
+        assert np.abs(lhs - rhs).max() <= 1e-11 * np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_phase1_exact_without_truncation(name):
+    """eps = 0: G represents X Y exactly (Section 3, exact induced representation)."""
+    _, _, XY = dense(name)
+    p1, _ = product(name, 0.0)
+    assert relF(p1.G.dense(), XY) < 1e-12
+
+
+def test_rank_rule_strict():
+    assert O.choose_rank(np.array([3.0, 1e-6, 1e-6 * (1 - 1e-15), 0.0]), 1e-6) == 1
+    assert O.choose_rank(np.array([]), 1e-3) == 0
+
+
+# --------------------------------------------------------------------------
+# P7: product block tree and the intermediate product (R13, R14)
+# --------------------------------------------------------------------------
+def _brute_triples(X, Y):
+    tree = X.V.tree
+    reached = {}
+    for lev in range(tree.depth + 1):
+        cl = list(tree.clusters_at(lev))
+        for t, s, r in itertools.product(cl, cl, cl):
+            if (t, s) not in X.bt.type or (s, r) not in Y.bt.type:
+                continue
+            if lev > 0:
+                pt, ps, pr = tree.parent[t], tree.parent[s], tree.parent[r]
+                if not (X.bt.type.get((pt, ps)) == O.SPLIT and Y.bt.type.get((ps, pr)) == O.SPLIT):
+                    continue
+            reached.setdefault((t, r), []).append(s)
+    return reached
+
+
+@pytest.mark.parametrize("name", ["1d", "2d"])
+def test_product_tree_brute_force(name):
+    _, tree, _, X, Y = problem(name)
+    PT = O.ProductTree(X, Y)
+    reached = _brute_triples(X, Y)
+    assert set(reached) == set(PT.type)
+    for b, mids in reached.items():
+        kinds = [(X.bt.type[(b[0], s)], Y.bt.type[(s, b[1])]) for s in mids]
+        if any(a == O.SPLIT and c == O.SPLIT for a, c in kinds):
+            want = O.SPLIT
+        elif any(a == O.INADM and c == O.INADM for a, c in kinds):
+            want = O.INADM
+        else:
+            want = O.ADM
+        assert PT.type[b] == want
+        assert sorted(PT.split[b] + [s for s, _ in PT.triples[b]]) == sorted(mids)
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "sph"])
+def test_intermediate_product_dense_definition(name):
+    """At eps > 0, G equals sum over terminated triples of
+    P_row X|_{ts} Y|_{sr} P_col evaluated densely (R14)."""
+    _, tree, _, X, Y = problem(name)
+    Xd, Yd, _ = dense(name)
+    p1, _ = product(name, 1e-4)
+    Qf, QWf = p1.row.Q.full(), p1.col.Q.full()
+    reached = _brute_triples(X, Y)
+    Gdef = np.zeros_like(Xd)
+    for (t, r), mids in reached.items():
+        for s in mids:
+            tx, ty = X.bt.type[(t, s)], Y.bt.type[(s, r)]
+            if tx == O.SPLIT and ty == O.SPLIT:
+                continue
+            M = Xd[tree.rng(t), tree.rng(s)] @ Yd[tree.rng(s), tree.rng(r)]
+            if not (tx == O.INADM and ty == O.INADM):
+                if tx != O.ADM:
+                    M = Qf[t] @ (Qf[t].T @ M)
+                if ty != O.ADM:
+                    M = (M @ QWf[r]) @ QWf[r].T
+            Gdef[tree.rng(t), tree.rng(r)] += M
+    assert relF(p1.G.dense(), Gdef) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P8: phase 2 (Section 6, Figures "match_column" and "basis"; R10-R12, R15)
+# --------------------------------------------------------------------------
+def _tik_rows(TIK, tree):
+    out = {}
+    for (t, r), ty in TIK.type.items():
+        if ty == O.ADM:
+            out.setdefault(t, []).append(r)
+    return out
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_phase2_condensation_gram(name):
+    """C_t (leaf) and Chat_t (non-leaf) carry the Gram matrix of the block-
+    scaled dense G_t = G|_{t x R_t} (projected onto the children's new
+    bases), with omega_b = 1/||G|_b||_F (R10)."""
+    _, tree, bt, _, _ = problem(name)
+    p1, p2 = product(name, 1e-6)
+    Gd = p1.G.dense()
+    QZ = p2.row.Q.full()
+    rows = _tik_rows(bt, tree)
+    for t in range(tree.nclusters):
+        if tree.is_leaf(t):
+            U = np.eye(tree.size[t])
+        else:
+            U = np.zeros((tree.size[t], sum(p2.row.Q.rank[c] for c in tree.children[t])))
+            o = 0
+            for c in tree.children[t]:
+                sl = slice(tree.off[c] - tree.off[t], tree.off[c] - tree.off[t] + tree.size[c])
+                U[sl, o:o + p2.row.Q.rank[c]] = QZ[c]
+                o += p2.row.Q.rank[c]
+        B = []
+        anc = t
+        while anc >= 0:
+            for r in rows.get(anc, []):
+                blk = Gd[tree.rng(anc), tree.rng(r)]
+                nb = np.linalg.norm(blk)
+                assert np.isclose(p2.row.omega.get((anc, r), 0.0) * nb, 1.0 if nb > 0 else 0.0, rtol=1e-12)
+                if nb > 0:
+                    B.append(U.T @ Gd[tree.rng(t), tree.rng(r)] / nb)
+            anc = tree.parent[anc]
+        C = p2.row.C[t]
+        if not B:
+            assert C.size == 0 or np.abs(C).max() < 1e-300
+            continue
+        Bm = np.hstack(B)
+        assert np.abs(C @ C.T - Bm @ Bm.T).max() <= 1e-11 * np.abs(Bm @ Bm.T).max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_phase2_bases_isometric(name):
+    _, tree, _, _, _ = problem(name)
+    _, p2 = product(name, 1e-6)
+    for side in (p2.row, p2.col):
+        Qf = side.Q.full()
+        for t in range(tree.nclusters):
+            if Qf[t].shape[1]:        # the root has no admissible block and may have rank 0
+                assert np.abs(Qf[t].T @ Qf[t] - np.eye(Qf[t].shape[1])).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "sph"])
+def test_final_product_dense_definition(name):
+    """Z equals the dense evaluation of R15 from the densified bases."""
+    _, tree, bt, _, _ = problem(name)
+    p1, p2 = product(name, 1e-4)
+    Gd = p1.G.dense()
+    QZ, QZW = p2.row.Q.full(), p2.col.Q.full()
+    Zdef = np.zeros_like(Gd)
+    for (t, r), ty in bt.type.items():
+        blk = Gd[tree.rng(t), tree.rng(r)]
+        if ty == O.ADM:
+            Zdef[tree.rng(t), tree.rng(r)] = QZ[t] @ (QZ[t].T @ blk @ QZW[r]) @ QZW[r].T
+        elif ty == O.INADM:
+            Zdef[tree.rng(t), tree.rng(r)] = blk
+    assert relF(p2.Z.dense(), Zdef) < 1e-12
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_final_exact_without_truncation(name):
+    """eps = 0 in both phases: Z = G = X Y."""
+    _, _, XY = dense(name)
+    _, p2 = product(name, 0.0)
+    assert relF(p2.Z.dense(), XY) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P9: error bound (Section 5; Tables "slp", "dlp": errors stay below eps)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-8])
+def test_final_error_below_eps(name, eps):
+    _, _, XY = dense(name)
+    p1, p2 = product(name, eps)
+    e1, e2 = rel2(p1.G.dense(), XY), rel2(p2.Z.dense(), XY)
+    assert e1 <= eps and e2 <= eps
+    # truncation actually happened (ranks below the untruncated ones)
+    _, p20 = product(name, 0.0)
+    assert sum(p2.row.Q.rank.values()) < sum(p20.row.Q.rank.values())
+
+
+# --------------------------------------------------------------------------
+# P10: special cases
+# --------------------------------------------------------------------------
+def test_identity_factor():
+    pts, tree, bt, _, Y = problem("2d")
+    I = O.identity_h2(tree, bt, 3)
+    _, Yd, _ = dense("2d")
+    _, p2 = O.multiply(I, Y, bt, 1e-6)
+    assert rel2(p2.Z.dense(), Yd) <= 1e-6
+
+
+def test_zero_factor():
+    _, tree, bt, X, Y = problem("2d")
+    _, p2 = O.multiply(O.scaled(X, 0.0), Y, bt, 1e-6)
+    assert np.abs(p2.Z.dense()).max() == 0.0
+
+
+@pytest.mark.parametrize("alpha", [1e-3, 7.5e4])
+def test_scaling_invariance_of_error_control(alpha):
+    """Block-relative error control (Section 5, R8-R10): scaling X scales Z
+    and leaves every rank unchanged."""
+    _, tree, bt, X, Y = problem("2d")
+    p1, p2 = product("2d", 1e-6)
+    q1, q2 = O.multiply(O.scaled(X, alpha), Y, bt, 1e-6)
+    assert q1.row.Q.rank == p1.row.Q.rank and q1.col.Q.rank == p1.col.Q.rank
+    assert q2.row.Q.rank == p2.row.Q.rank and q2.col.Q.rank == p2.col.Q.rank
+    assert relF(q2.Z.dense(), alpha * p2.Z.dense()) < 1e-11
+
+
+def test_low_rank_kernel_ranks():
+    """(x.y)^2 in 2-D has rank d(d+1)/2 = 3 and is reproduced exactly by
+    order-3 interpolation: above roundoff, phase 1 adds nothing to range(V_X)
+    (k2 = 0) and phase 2 finds rank 3 (rank 0 for coarse clusters without
+    any admissible block at or above them); Z is then exact.  At eps = 1e-4 block-relative
+    truncation may drop a weak direction, within the eps bound."""
+    pts = W.make_points(9, 400, 2, "uniform")
+    tree, bt, X, Y = O.build_problem(pts, 25, 1.0, 3, "poly2", "poly2")
+    XY = X.dense() @ Y.dense()
+    p1, p2 = O.multiply(X, Y, bt, 1e-10)
+    assert set(p1.row.Q.rank.values()) == {9} and set(p1.col.Q.rank.values()) == {9}
+    has_adm = {t for (t, r), ty in bt.type.items() if ty == O.ADM}
+    for c in range(tree.nclusters):
+        a, row_star = c, False
+        while a >= 0:
+            row_star |= a in has_adm
+            a = tree.parent[a]
+        assert p2.row.Q.rank[c] == (3 if row_star else 0)
+    assert rel2(p2.Z.dense(), XY) < 1e-13
+    _, q2 = O.multiply(X, Y, bt, 1e-4)
+    assert max(q2.row.Q.rank.values()) <= 3 and rel2(q2.Z.dense(), XY) <= 1e-4
+
+
+def test_symmetric_product_bases_coincide():
+    """X = Y symmetric: the column pass sees the same data as the row pass."""
+    p1, p2 = product("1d", 1e-6)
+    assert p1.row.Q.rank == p1.col.Q.rank
+    assert p2.row.Q.rank == p2.col.Q.rank
