@@ -24,6 +24,9 @@ import numpy as np
 
 ADM, INADM, SPLIT = "A", "I", "N"
 
+# Relative tolerance of the numerical rank of V_{X,t} (reading R18).
+VX_RTOL = 1e-12
+
 
 # ----------------------------------------------------------------------------
 # Cluster tree (Section 2, Definition "Cluster tree"; readings R1, R2)
@@ -505,8 +508,12 @@ def _pad_rows(M: np.ndarray, rows: int) -> np.ndarray:
 def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float) -> InducedBasis:
     """Compressed induced row basis of the product X Y.
 
-    R18: Q_{X,t} is the full orthogonal Householder factor, so the remainder
-    has (rows - k1) rows, k1 = min(k, rows).  R8: the block of s is scaled by
+    R18: Q_{X,t} is a full orthogonal factor whose first k1 columns span the
+    range of V_{X,t}; k1 is the numerical rank of V_{X,t} (singular values
+    above VX_RTOL times the largest), which equals the paper's min(k, rows)
+    whenever V_{X,t} has full numerical rank, and Q_{X,t} is taken from the
+    SVD of V_{X,t} so that the kept range is unique; the remainder has
+    (rows - k1) rows.  R8: the block of s is scaled by
     1/||X|_{t x s} V_{Y,s}||_2 (leaf) or 1/||Ahat_{t,s}||_2 (non-leaf).
     R9: rank k2 = #{sigma > eps}.
     """
@@ -522,18 +529,18 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float) -> InducedBasis:
     RX, A, sig_out, assembled = {}, {}, {}, {}
 
     def compress(t, VX, Vrest_blocks):
-        """Keep range(V_X) exactly, SVD of the remainder."""
+        """Keep the (numerical) range of V_X exactly, SVD of the remainder."""
         rows = VX.shape[0]
-        k1 = min(k, rows)
-        Qx, Rfull = np.linalg.qr(VX, mode="complete")
-        RX[t] = Rfull[:k1, :]
+        Ux, sx, _ = np.linalg.svd(VX, full_matrices=True)          # Ux: rows x rows
+        k1 = int(np.count_nonzero(sx > VX_RTOL * sx[0])) if sx.size and sx[0] > 0 else 0
+        RX[t] = Ux[:, :k1].T @ VX                                  # Q_{X,t}^* V_{X,t} = [R_{X,t}; 0]
         Vrest = np.hstack(Vrest_blocks) if Vrest_blocks else np.zeros((rows, 0))
         assembled[t] = (VX, Vrest)
-        Vtil = (Qx.T @ Vrest)[k1:, :]
+        Vtil = Ux[:, k1:].T @ Vrest
         U, sig = left_svd(Vtil)
         k2 = choose_rank(sig, eps)
         sig_out[t] = sig
-        Qt = np.hstack([Qx[:, :k1], Qx[:, k1:] @ U[:, :k2]])
+        Qt = np.hstack([Ux[:, :k1], Ux[:, k1:] @ U[:, :k2]])
         Q.rank[t] = k1 + k2
         return Qt
 
