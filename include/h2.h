@@ -1,0 +1,198 @@
+/*
+ * h2.h -- C-ABI of an MI355X (gfx950) implementation of adaptive
+ * H^2-matrix multiplication Z <- Z + X Y (S. Boerm, "Adaptive fast
+ * multiplication of H^2-matrices", arXiv 2309.09061).
+ *
+ * The operation is split as in the paper's Introduction into
+ *   phase 1 (h2_mul_intermediate): compressed induced row and column cluster
+ *     bases (Section 4, Figure "induced_basis") with block-relative error
+ *     control (Section 5), and the intermediate product G on the product
+ *     block tree T^XY (Section 6, opening definition);
+ *   phase 2 (h2_recompress): coarsening of G into the prescribed block tree
+ *     T_IK with adaptive nested isometric bases (Section 6, Figures
+ *     "match_column" and "basis").
+ *
+ * Conventions common to every call:
+ *  - Status codes are returned; nothing throws across the ABI.  On error the
+ *    output handles are left untouched (set to NULL) and a thread-local
+ *    message is available from h2_last_error().
+ *  - Every handle owns its device memory.  Callers own the arrays they pass.
+ *  - Device arrays are float64, column-major.  Vectors and dense matrices on
+ *    the device are indexed in CLUSTER ORDER: position p holds the point
+ *    whose original index is perm[p] (perm from h2_tree_build).
+ *  - Calls enqueue work on the context's HIP stream.  Calls that choose
+ *    adaptive ranks (h2_mul_intermediate, h2_recompress) synchronise that
+ *    stream once per tree level to read the ranks back.
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Arguments are validated before any launch; device failures map to
+ *    H2_ERR_DEVICE.
+ */
+#ifndef H2_H
+#define H2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_ARG = 1,          /* invalid argument (NULL handle, bad size, ...) */
+  H2_ERR_SHAPE = 2,        /* operands do not share the cluster trees they must share */
+  H2_ERR_ALLOC = 3,        /* device or host allocation failed */
+  H2_ERR_DEVICE = 4,       /* a HIP call or kernel launch failed */
+  H2_ERR_NOT_REFINED = 5,  /* T^XY does not refine the target block tree T_IK */
+  H2_ERR_UNSUPPORTED = 6,  /* e.g. Z with non-zero blocks, general (non-uniform) trees */
+  H2_ERR_NUMERIC = 7       /* NaN or Inf met where a finite value is required */
+} h2_status;
+
+/* Arithmetic of the bulk products.  Orthogonalisation (QR), the SVDs that
+ * choose ranks and the block norms always run in float64. */
+typedef enum {
+  H2_FP64 = 0,       /* everything in float64 */
+  H2_FP32_BULK = 1   /* bulk products of both phases in float32 (FP32 MFMA) */
+} h2_precision;
+
+/* Kernel functions g(x,y) of the interpolated matrices (Section 2, Example
+ * "Integral operator").  Diagonal entries g(x_i, x_i) of singular kernels are 0. */
+typedef enum {
+  H2_K_LOG = 0,      /* log|x-y|,        diagonal 0 */
+  H2_K_EXPNEG = 1,   /* exp(-|x-y|),     diagonal 1 */
+  H2_K_INV4PI = 2,   /* 1/(4 pi |x-y|),  diagonal 0 (single-layer kernel, Section 7) */
+  H2_K_INV = 3,      /* 1/|x-y|,         diagonal 0 */
+  H2_K_POLY2 = 100   /* (x.y)^2, a degree-2 polynomial reproduced exactly at order >= 3 */
+} h2_kernel;
+
+typedef struct h2_ctx h2_ctx;          /* device, stream, workspace, timers */
+typedef struct h2_tree h2_tree;        /* cluster tree + block tree (standard admissibility) */
+typedef struct h2_matrix h2_matrix;    /* H^2-matrix on a tree's block tree */
+typedef struct h2_product h2_product;  /* phase-1 result: G on T^XY with its bases */
+
+/* Thread-local message of the last failing call (never NULL). */
+const char* h2_last_error(void);
+
+/* Create a context on HIP device `device` using stream `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  device = -1 creates a
+ * host-only context that accepts only h2_tree_build and the tree queries
+ * (symbolic work, no device memory).  *out receives the handle. */
+h2_status h2_ctx_create(int device, void* hip_stream, h2_ctx** out);
+h2_status h2_ctx_destroy(h2_ctx* ctx);
+
+/* Cluster tree (Section 2, Definition "Cluster tree") and block tree
+ * (Definition "Block tree") for n points.
+ *   points    host, n x dim, row-major, float64 (copied);  1 <= dim <= 3
+ *   leaf_size >= 2: clusters are bisected at the median along the longest
+ *             edge of their tight bounding box until every leaf holds at most
+ *             leaf_size points; all leaves lie on one level.
+ *   eta > 0:  standard admissibility max(diam t, diam s) <= eta dist(t, s),
+ *             dist > 0; refinement stops at admissible or leaf x leaf blocks.
+ *   perm_out  optional host int64[n]: perm_out[p] = original index of the
+ *             point at cluster-order position p.
+ * Host-only work; usable with a host-only context. */
+h2_status h2_tree_build(h2_ctx* ctx, int dim, int64_t n, const double* points, int leaf_size,
+                        double eta, h2_tree** out, int64_t* perm_out);
+
+/* Sizes of a tree: out[0] = n, out[1] = dim, out[2] = depth, out[3] = #clusters,
+ * out[4] = #blocks, out[5] = #admissible leaves, out[6] = #inadmissible leaves. */
+h2_status h2_tree_sizes(const h2_tree* tree, int64_t out[7]);
+
+/* Structure of a tree, host arrays sized from h2_tree_sizes (any may be NULL):
+ *   cl_off, cl_size  [#clusters]  index range of each cluster in cluster order
+ *                                 (clusters numbered breadth first, root 0,
+ *                                 children of c are 2c+1 and 2c+2)
+ *   blk_row, blk_col [#blocks]    cluster pair of each block
+ *   blk_type         [#blocks]    0 = subdivided, 1 = admissible leaf, 2 = inadmissible leaf */
+h2_status h2_tree_structure(const h2_tree* tree, int64_t* cl_off, int64_t* cl_size,
+                            int32_t* blk_row, int32_t* blk_col, int8_t* blk_type);
+
+/* H^2-matrix approximating the kernel matrix (g(x_i, x_j)) on tree x tree by
+ * tensor Chebyshev interpolation with `order` points per axis, k = order^dim
+ * (Section 2, Example "Integral operator"): leaf bases l_{t,nu}(x_i),
+ * transfers l_{t,nu}(xi_{t',nu'}), couplings g(xi_t, xi_s); nearfield blocks
+ * hold g(x_i, x_j).  Row and column bases coincide.  1 <= order, k <= 128. */
+h2_status h2_compress_kernel(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order,
+                             h2_matrix** out);
+
+/* Phase 1 for `count` independent products X[i] Y[i] (Section 4, Figure
+ * "induced_basis", for the row basis and, on the adjoint pair (Y*, X*), for
+ * the column basis; Section 5 block scaling; intermediate product G on
+ * T^XY).  X[i] and Y[i] must be built on the same cluster tree.
+ *   eps > = 0: ranks keep the singular values > eps of the block-scaled
+ *              matrices; eps = 0 keeps every non-zero singular value and G
+ *              then represents X Y exactly.
+ * G_out[i] receives a new handle per product. */
+h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
+                              const h2_matrix* const* Y, double eps, h2_precision prec,
+                              h2_product** G_out);
+
+/* A zero H^2-matrix on `tree`'s block tree (the prescribed T_IK). */
+h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix** Z_out);
+
+/* Phase 2 for `count` products (Section 6, Figure "basis"): builds adaptive
+ * isometric nested row and column bases for Z's block tree T_IK from G and
+ * stores Z <- Z + G in them.  Each Z[i] must be zero (h2_zero_like) and its
+ * block tree must be refined by T^XY (H2_ERR_NOT_REFINED otherwise).
+ * Block-relative accuracy eps per admissible block of T_IK. */
+h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix* const* Z,
+                        double eps, h2_precision prec);
+
+/* y <- alpha op(A) x + beta y for nvec column-major device vectors in cluster
+ * order (O(nk) H^2 matrix-vector product: forward transform, couplings,
+ * backward transform, nearfield).  op is 'N' or 'T'.  x and y must not overlap. */
+h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x,
+                    double beta, double* y, int nvec);
+
+/* The same for the intermediate product G. */
+h2_status h2_product_matvec(h2_ctx* ctx, const h2_product* G, char op, double alpha,
+                            const double* x, double beta, double* y, int nvec);
+
+/* Dense n x n copy (cluster order) into device memory `out` with leading
+ * dimension ld >= n.  For tests and measurement; O(n^2) memory. */
+h2_status h2_to_dense(h2_ctx* ctx, const h2_matrix* A, double* out, int64_t ld);
+h2_status h2_product_to_dense(h2_ctx* ctx, const h2_product* G, double* out, int64_t ld);
+
+/* Expanded cluster basis matrix of cluster c (#c x rank, column-major, device
+ * memory `out` with leading dimension ld >= #c) of the row (which = 0) or
+ * column (which = 1) basis; for tests of projectors Q_t Q_t^*.  The basis of a
+ * non-leaf cluster is expanded through the transfer matrices (eq. (transfer)). */
+h2_status h2_matrix_basis(h2_ctx* ctx, const h2_matrix* A, int which, int cluster, double* out, int64_t ld);
+h2_status h2_product_basis(h2_ctx* ctx, const h2_product* G, int which, int cluster, double* out, int64_t ld);
+
+/* Ranks of a basis, host int32[#clusters]:
+ *   which = 0 row basis, 1 column basis (of a matrix, or of G for products). */
+h2_status h2_matrix_ranks(const h2_matrix* A, int which, int32_t* out);
+h2_status h2_product_ranks(const h2_product* G, int which, int32_t* out);
+
+/* Sizes of a product: out[0] = #blocks of T^XY, out[1] = #admissible leaves,
+ * out[2] = #inadmissible leaves, out[3] = terminated triples, out[4] = device
+ * bytes held by G. */
+h2_status h2_product_sizes(const h2_product* G, int64_t out[5]);
+
+/* Step times (milliseconds, stream events) of the last h2_mul_intermediate /
+ * h2_recompress on this context; out[] receives up to n entries in the order
+ *   0 setup, 1 symbolic, 2 phase-1 row, 3 phase-1 col, 4 phase-1 mat (G),
+ *   5 phase-2 row, 6 phase-2 col, 7 phase-2 mat (Z).  Returns the count. */
+int h2_step_times(const h2_ctx* ctx, double* out, int n);
+
+/* Launch timing for measurement.  h2_profile(ctx, 1) makes every kernel
+ * launch of this context record a pair of HIP events on the context stream
+ * (a few microseconds each); h2_kernel_stats() resolves them (synchronising
+ * the stream) and returns, for kernel family `kind` (0 grouped GEMM, 1 TSQR,
+ * 2 Jacobi SVD, 3 construction, 4 other), out[0] = total milliseconds,
+ * out[1] = launches, out[2] = algorithmic flops (2mnk per product term;
+ * Householder 2Nm^2 - 2m^3/3; one Jacobi sweep), out[3] = algorithmic bytes
+ * (operands read once, outputs written once).  reset != 0 clears the counters
+ * after reading. */
+h2_status h2_profile(h2_ctx* ctx, int enable);
+h2_status h2_kernel_stats(h2_ctx* ctx, int kind, double out[4], int reset);
+
+void h2_tree_destroy(h2_tree* tree);
+void h2_matrix_destroy(h2_matrix* A);
+void h2_product_destroy(h2_product* G);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2_H */

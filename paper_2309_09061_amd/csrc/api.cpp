@@ -1,0 +1,326 @@
+// extern "C" entry points of include/h2.h.  Arguments are validated here
+// before any launch; internal errors are exceptions mapped to status codes.
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+
+using namespace h2;
+
+static thread_local std::string g_err = "no error";
+
+template <class F>
+static h2_status guard(F&& f) {
+  try {
+    f();
+    return H2_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return H2_ERR_ALLOC;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return H2_ERR_DEVICE;
+  }
+}
+
+static void need_device(const h2_ctx* ctx) {
+  H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
+  H2_REQUIRE(!ctx->host_only, H2_ERR_ARG, "host-only context: no device work possible");
+  dev_set_device(ctx->device);
+}
+
+static void begin_call(h2_ctx* ctx) {
+  ctx->ws.reset();
+  for (double& v : ctx->step_ms) v = 0.0;
+}
+
+extern "C" {
+
+const char* h2_last_error(void) { return g_err.c_str(); }
+
+h2_status h2_ctx_create(int device, void* hip_stream, h2_ctx** out) {
+  return guard([&] {
+    H2_REQUIRE(out, H2_ERR_ARG, "NULL output");
+    *out = nullptr;
+    H2_REQUIRE(device >= -1, H2_ERR_ARG, "bad device");
+    auto* c = new h2_ctx();
+    c->device = device;
+    c->stream = hip_stream;
+    c->host_only = device < 0;
+    c->ws.ctx = c;
+    if (!c->host_only) {
+      try {
+        dev_set_device(device);
+        c->stage_cap = (size_t)16 << 20;
+        c->stage = (char*)dev_malloc_host(c->stage_cap);
+      } catch (...) {
+        delete c;
+        throw;
+      }
+    }
+    *out = c;
+  });
+}
+
+h2_status h2_ctx_destroy(h2_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    if (!ctx->host_only) {
+      dev_set_device(ctx->device);
+      dev_sync(ctx->stream);
+    }
+    delete ctx;
+  });
+}
+
+h2_status h2_tree_build(h2_ctx* ctx, int dim, int64_t n, const double* points, int leaf_size,
+                        double eta, h2_tree** out, int64_t* perm_out) {
+  return guard([&] {
+    H2_REQUIRE(ctx && out && points, H2_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    H2_REQUIRE(std::isfinite(eta) && eta > 0, H2_ERR_ARG, "eta must be positive");
+    auto* t = new h2_tree();
+    try {
+      t->ct = build_cluster_tree(dim, n, points, leaf_size);
+      t->bt = build_block_tree(*t->ct, *t->ct, eta);
+      t->eta = eta;
+    } catch (...) {
+      delete t;
+      throw;
+    }
+    if (perm_out) std::memcpy(perm_out, t->ct->perm.data(), sizeof(int64_t) * n);
+    *out = t;
+  });
+}
+
+h2_status h2_tree_sizes(const h2_tree* tree, int64_t out[7]) {
+  return guard([&] {
+    H2_REQUIRE(tree && out, H2_ERR_ARG, "NULL argument");
+    out[0] = tree->ct->n;
+    out[1] = tree->ct->dim;
+    out[2] = tree->ct->depth;
+    out[3] = tree->ct->ncl;
+    out[4] = tree->bt->nblocks();
+    out[5] = tree->bt->n_adm;
+    out[6] = tree->bt->n_inadm;
+  });
+}
+
+h2_status h2_tree_structure(const h2_tree* tree, int64_t* cl_off, int64_t* cl_size, int32_t* blk_row,
+                            int32_t* blk_col, int8_t* blk_type) {
+  return guard([&] {
+    H2_REQUIRE(tree, H2_ERR_ARG, "NULL tree");
+    const TreeH& T = *tree->ct;
+    const BlockTreeH& B = *tree->bt;
+    if (cl_off) std::memcpy(cl_off, T.off.data(), sizeof(int64_t) * T.ncl);
+    if (cl_size) std::memcpy(cl_size, T.size.data(), sizeof(int64_t) * T.ncl);
+    if (blk_row) std::memcpy(blk_row, B.t.data(), sizeof(int32_t) * B.nblocks());
+    if (blk_col) std::memcpy(blk_col, B.s.data(), sizeof(int32_t) * B.nblocks());
+    if (blk_type)
+      for (int b = 0; b < B.nblocks(); ++b) blk_type[b] = B.type[b];
+  });
+}
+
+h2_status h2_compress_kernel(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order, h2_matrix** out) {
+  return guard([&] {
+    H2_REQUIRE(out, H2_ERR_ARG, "NULL output");
+    *out = nullptr;
+    H2_REQUIRE(tree, H2_ERR_ARG, "NULL tree");
+    H2_REQUIRE(kernel == H2_K_LOG || kernel == H2_K_EXPNEG || kernel == H2_K_INV4PI || kernel == H2_K_INV ||
+                   kernel == H2_K_POLY2,
+               H2_ERR_ARG, "unknown kernel");
+    need_device(ctx);
+    begin_call(ctx);
+    auto* m = new h2_matrix();
+    try {
+      compress_kernel(ctx, tree, (int)kernel, order, m);
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+  });
+}
+
+h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X, const h2_matrix* const* Y,
+                              double eps, h2_precision prec, h2_product** G_out) {
+  return guard([&] {
+    H2_REQUIRE(G_out && X && Y && count >= 1, H2_ERR_ARG, "bad arguments");
+    for (int i = 0; i < count; ++i) {
+      G_out[i] = nullptr;
+      H2_REQUIRE(X[i] && Y[i], H2_ERR_ARG, "NULL factor");
+    }
+    H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
+    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
+    H2_REQUIRE(prec == H2_FP64, H2_ERR_UNSUPPORTED, "FP32 bulk products are not available yet");
+    need_device(ctx);
+    begin_call(ctx);
+    for (int i = 0; i < count; ++i) {
+      auto* G = new h2_product();
+      try {
+        phase1(ctx, X[i], Y[i], eps, (int)prec, G);
+      } catch (...) {
+        delete G;
+        for (int j = 0; j < i; ++j) {
+          delete G_out[j];
+          G_out[j] = nullptr;
+        }
+        throw;
+      }
+      G_out[i] = G;
+    }
+    steps_collect(ctx);
+  });
+}
+
+h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix** Z_out) {
+  return guard([&] {
+    H2_REQUIRE(Z_out && tree, H2_ERR_ARG, "NULL argument");
+    *Z_out = nullptr;
+    need_device(ctx);
+    auto* m = new h2_matrix();
+    zero_like(ctx, tree, m);
+    *Z_out = m;
+  });
+}
+
+h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix* const* Z, double eps,
+                        h2_precision prec) {
+  return guard([&] {
+    H2_REQUIRE(G && Z && count >= 1, H2_ERR_ARG, "bad arguments");
+    for (int i = 0; i < count; ++i) H2_REQUIRE(G[i] && Z[i], H2_ERR_ARG, "NULL operand");
+    H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
+    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
+    H2_REQUIRE(prec == H2_FP64, H2_ERR_UNSUPPORTED, "FP32 bulk products are not available yet");
+    for (int i = 0; i < count; ++i) H2_REQUIRE(Z[i]->zero, H2_ERR_UNSUPPORTED, "Z must be zero");
+    need_device(ctx);
+    begin_call(ctx);
+    for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);
+    steps_collect(ctx);
+  });
+}
+
+h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x, double beta,
+                    double* y, int nvec) {
+  return guard([&] {
+    H2_REQUIRE(A && x && y && nvec >= 1, H2_ERR_ARG, "bad arguments");
+    H2_REQUIRE(op == 'N' || op == 'T', H2_ERR_ARG, "op must be 'N' or 'T'");
+    need_device(ctx);
+    begin_call(ctx);
+    matvec(ctx, A->c, op == 'T', alpha, x, beta, y, nvec);
+  });
+}
+
+h2_status h2_product_matvec(h2_ctx* ctx, const h2_product* G, char op, double alpha, const double* x,
+                            double beta, double* y, int nvec) {
+  return guard([&] {
+    H2_REQUIRE(G && x && y && nvec >= 1, H2_ERR_ARG, "bad arguments");
+    H2_REQUIRE(op == 'N' || op == 'T', H2_ERR_ARG, "op must be 'N' or 'T'");
+    need_device(ctx);
+    begin_call(ctx);
+    matvec(ctx, G->c, op == 'T', alpha, x, beta, y, nvec);
+  });
+}
+
+h2_status h2_to_dense(h2_ctx* ctx, const h2_matrix* A, double* out, int64_t ld) {
+  return guard([&] {
+    H2_REQUIRE(A && out && ld >= A->c.ct->n, H2_ERR_ARG, "bad arguments");
+    need_device(ctx);
+    begin_call(ctx);
+    to_dense(ctx, A->c, out, ld);
+  });
+}
+
+h2_status h2_product_to_dense(h2_ctx* ctx, const h2_product* G, double* out, int64_t ld) {
+  return guard([&] {
+    H2_REQUIRE(G && out && ld >= G->c.ct->n, H2_ERR_ARG, "bad arguments");
+    need_device(ctx);
+    begin_call(ctx);
+    to_dense(ctx, G->c, out, ld);
+  });
+}
+
+h2_status h2_matrix_basis(h2_ctx* ctx, const h2_matrix* A, int which, int cluster, double* out, int64_t ld) {
+  return guard([&] {
+    H2_REQUIRE(A && out && (which == 0 || which == 1), H2_ERR_ARG, "bad arguments");
+    need_device(ctx);
+    begin_call(ctx);
+    basis_dense(ctx, A->c, which, cluster, out, ld);
+  });
+}
+
+h2_status h2_product_basis(h2_ctx* ctx, const h2_product* G, int which, int cluster, double* out, int64_t ld) {
+  return guard([&] {
+    H2_REQUIRE(G && out && (which == 0 || which == 1), H2_ERR_ARG, "bad arguments");
+    need_device(ctx);
+    begin_call(ctx);
+    basis_dense(ctx, G->c, which, cluster, out, ld);
+  });
+}
+
+h2_status h2_matrix_ranks(const h2_matrix* A, int which, int32_t* out) {
+  return guard([&] {
+    H2_REQUIRE(A && out && (which == 0 || which == 1), H2_ERR_ARG, "bad arguments");
+    const auto& r = which == 0 ? A->c.V.rank : A->c.W.rank;
+    std::memcpy(out, r.data(), sizeof(int32_t) * r.size());
+  });
+}
+
+h2_status h2_product_ranks(const h2_product* G, int which, int32_t* out) {
+  return guard([&] {
+    H2_REQUIRE(G && out && (which == 0 || which == 1), H2_ERR_ARG, "bad arguments");
+    const auto& r = which == 0 ? G->c.V.rank : G->c.W.rank;
+    std::memcpy(out, r.data(), sizeof(int32_t) * r.size());
+  });
+}
+
+h2_status h2_product_sizes(const h2_product* G, int64_t out[5]) {
+  return guard([&] {
+    H2_REQUIRE(G && out, H2_ERR_ARG, "bad arguments");
+    out[0] = G->c.bt->nblocks();
+    out[1] = G->c.bt->n_adm;
+    out[2] = G->c.bt->n_inadm;
+    out[3] = G->n_triples;
+    out[4] = (int64_t)G->mem.total;
+  });
+}
+
+int h2_step_times(const h2_ctx* ctx, double* out, int n) {
+  if (!ctx || !out) return 0;
+  int m = std::min(n, 8);
+  for (int i = 0; i < m; ++i) out[i] = ctx->step_ms[i];
+  return m;
+}
+
+h2_status h2_profile(h2_ctx* ctx, int enable) {
+  return guard([&] {
+    H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
+    ctx->profile = enable != 0;
+  });
+}
+
+h2_status h2_kernel_stats(h2_ctx* ctx, int kind, double out[4], int reset) {
+  return guard([&] {
+    H2_REQUIRE(ctx && out && kind >= 0 && kind < KK_COUNT, H2_ERR_ARG, "bad arguments");
+    if (!ctx->host_only) {
+      dev_set_device(ctx->device);
+      kernel_stats_collect(ctx);
+    }
+    const KernelStat& k = ctx->kstat[kind];
+    out[0] = k.ms;
+    out[1] = (double)k.launches;
+    out[2] = k.flops;
+    out[3] = k.bytes;
+    if (reset)
+      for (auto& s : ctx->kstat) s = KernelStat{};
+  });
+}
+
+void h2_tree_destroy(h2_tree* tree) { delete tree; }
+void h2_matrix_destroy(h2_matrix* A) { delete A; }
+void h2_product_destroy(h2_product* G) { delete G; }
+
+}  // extern "C"

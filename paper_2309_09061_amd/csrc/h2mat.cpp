@@ -1,0 +1,218 @@
+// H^2-matrices on the device: construction by Chebyshev interpolation
+// (Section 2, Example "Integral operator"), zero matrices, the O(nk)
+// matrix-vector product (forward transform, couplings, backward transform,
+// nearfield) and densification for tests.
+#include "internal.h"
+
+namespace h2 {
+
+void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2_matrix* out) {
+  const TreeH& T = *tree->ct;
+  const BlockTreeH& B = *tree->bt;
+  int k = 1;
+  for (int a = 0; a < T.dim; ++a) k *= order;
+  H2_REQUIRE(order >= 1 && k <= 128, H2_ERR_ARG, "order^dim must be in [1, 128]");
+  out->ctx = ctx;
+  out->mem.ctx = ctx;
+  H2Core& C = out->c;
+  C.ct = tree->ct;
+  C.bt = tree->bt;
+  C.V.resize(T.ncl);
+  Arena& A = out->mem;
+  // geometry on the device
+  double* pts = A.get<double>(T.pts.size());
+  double* lo = A.get<double>(T.lo.size());
+  double* hi = A.get<double>(T.hi.size());
+  dev_h2d(pts, T.pts.data(), T.pts.size() * 8, ctx->stream);
+  dev_h2d(lo, T.lo.data(), T.lo.size() * 8, ctx->stream);
+  dev_h2d(hi, T.hi.data(), T.hi.size() * 8, ctx->stream);
+  // leaf bases and transfers
+  std::vector<ChebLeaf> leaves;
+  std::vector<ChebPair> transfers;
+  for (int c = 0; c < T.ncl; ++c) {
+    C.V.rank[c] = k;
+    if (T.leaf(c)) {
+      double* V = A.get<double>((size_t)T.size[c] * k);
+      C.V.leaf[c] = V;
+      C.V.leaf_ld[c] = std::max<int64_t>(T.size[c], 1);
+      leaves.push_back({V, C.V.leaf_ld[c], T.off[c], c, (int32_t)T.size[c]});
+    }
+    if (c > 0) {
+      double* E = A.get<double>((size_t)k * k);
+      C.V.tr[c] = E;
+      C.V.tr_ld[c] = k;
+      transfers.push_back({E, k, c, TreeH::parent(c)});
+    }
+  }
+  // couplings and nearfield
+  C.blk.assign(B.nblocks(), nullptr);
+  std::vector<ChebPair> coup;
+  std::vector<NearBlock> near;
+  for (int b = 0; b < B.nblocks(); ++b) {
+    if (B.type[b] == BT_ADM) {
+      double* S = A.get<double>((size_t)k * k);
+      C.blk[b] = S;
+      coup.push_back({S, k, B.t[b], B.s[b]});
+    } else if (B.type[b] == BT_INADM) {
+      int64_t mt = T.size[B.t[b]], ms = T.size[B.s[b]];
+      double* N = A.get<double>((size_t)mt * ms);
+      C.blk[b] = N;
+      near.push_back({N, std::max<int64_t>(mt, 1), T.off[B.t[b]], T.off[B.s[b]], (int32_t)mt, (int32_t)ms,
+                      B.t[b] == B.s[b] ? 1 : 0, 0});
+    }
+  }
+  C.W = C.V;  // the same interpolation on both sides
+  k_cheb_leaf(upload(ctx, leaves), (int)leaves.size(), pts, lo, hi, T.dim, order, ctx->stream);
+  k_cheb_transfer(upload(ctx, transfers), (int)transfers.size(), lo, hi, T.dim, order, ctx->stream);
+  k_cheb_coupling(upload(ctx, coup), (int)coup.size(), lo, hi, T.dim, order, kernel, ctx->stream);
+  k_nearfield(upload(ctx, near), (int)near.size(), pts, T.dim, kernel, ctx->stream);
+}
+
+void zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix* out) {
+  out->ctx = ctx;
+  out->mem.ctx = ctx;
+  out->zero = true;
+  out->c.ct = tree->ct;
+  out->c.bt = tree->bt;
+  out->c.V.resize(tree->ct->ncl);
+  out->c.W.resize(tree->ct->ncl);
+  out->c.blk.assign(tree->bt->nblocks(), nullptr);
+}
+
+// full cluster basis matrices (#c x rank c, ld #c) for every cluster
+static std::vector<double*> full_basis(h2_ctx* ctx, const TreeH& T, const Basis& V) {
+  std::vector<double*> F(T.ncl, nullptr);
+  for (int c = 0; c < T.ncl; ++c) F[c] = ctx->ws.get<double>((size_t)T.size[c] * std::max(V.rank[c], 1));
+  GemmBatch g;
+  for (int c = T.first(T.depth); c < T.ncl; ++c) {
+    g.out(F[c], T.size[c], (int)T.size[c], V.rank[c]);
+    g.copy(V.leaf[c], V.leaf_ld[c], false, V.rank[c]);
+  }
+  g.run(ctx);
+  for (int l = T.depth - 1; l >= 0; --l) {
+    for (int c = T.first(l); c < T.first(l + 1); ++c)
+      for (int q = 1; q <= 2; ++q) {
+        int ch = 2 * c + q;
+        g.out(F[c] + (T.off[ch] - T.off[c]), T.size[c], (int)T.size[ch], V.rank[c]);
+        g.term(F[ch], T.size[ch], false, V.tr[ch], V.tr_ld[ch], false, V.rank[ch]);
+      }
+    g.run(ctx);
+  }
+  return F;
+}
+
+void basis_dense(h2_ctx* ctx, const H2Core& A, int which, int cluster, double* out, int64_t ld) {
+  const TreeH& T = *A.ct;
+  const Basis& V = which == 0 ? A.V : A.W;
+  H2_REQUIRE(cluster >= 0 && cluster < T.ncl, H2_ERR_ARG, "cluster out of range");
+  H2_REQUIRE(ld >= T.size[cluster], H2_ERR_ARG, "ld too small");
+  auto F = full_basis(ctx, T, V);
+  GemmBatch g;
+  g.out(out, ld, (int)T.size[cluster], V.rank[cluster]);
+  g.copy(F[cluster], T.size[cluster], false, V.rank[cluster]);
+  g.run(ctx);
+}
+
+void to_dense(h2_ctx* ctx, const H2Core& A, double* out, int64_t ld) {
+  const TreeH& T = *A.ct;
+  const BlockTreeH& B = *A.bt;
+  auto Vf = full_basis(ctx, T, A.V);
+  auto Wf = full_basis(ctx, T, A.W);
+  GemmBatch g1, g2;
+  std::vector<double*> tmp(B.nblocks(), nullptr);
+  for (int b = 0; b < B.nblocks(); ++b) {
+    int t = B.t[b], s = B.s[b];
+    double* O = out + T.off[t] + T.off[s] * ld;
+    if (B.type[b] == BT_ADM) {
+      int kt = A.V.rank[t], ks = A.W.rank[s];
+      if (kt == 0 || ks == 0 || !A.blk[b]) {
+        g2.out(O, ld, (int)T.size[t], (int)T.size[s]);  // zero
+        continue;
+      }
+      tmp[b] = ctx->ws.get<double>((size_t)kt * T.size[s]);
+      g1.out(tmp[b], kt, kt, (int)T.size[s]);
+      g1.term(A.blk[b], A.ld_of(b), false, Wf[s], T.size[s], true, ks);
+      g2.out(O, ld, (int)T.size[t], (int)T.size[s]);
+      g2.term(Vf[t], T.size[t], false, tmp[b], kt, false, kt);
+    } else if (B.type[b] == BT_INADM) {
+      g2.out(O, ld, (int)T.size[t], (int)T.size[s]);
+      if (A.blk[b]) g2.copy(A.blk[b], A.ld_of(b), false, (int)T.size[s]);
+    }
+  }
+  g1.run(ctx);
+  g2.run(ctx);
+}
+
+// z = op(A) x (z n x nvec, ld n), then y = alpha z + beta y
+void matvec(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double* x, double beta,
+            double* y, int nvec) {
+  const TreeH& T = *A.ct;
+  View v{&A, trans};
+  const Basis& R = v.rowb();
+  const Basis& Cb = v.colb();
+  int64_t n = T.n;
+  std::vector<double*> xh(T.ncl), yh(T.ncl);
+  for (int c = 0; c < T.ncl; ++c) {
+    xh[c] = ctx->ws.get<double>((size_t)std::max(Cb.rank[c], 1) * nvec);
+    yh[c] = ctx->ws.get<double>((size_t)std::max(R.rank[c], 1) * nvec);
+  }
+  GemmBatch g;
+  // forward transform
+  for (int c = T.first(T.depth); c < T.ncl; ++c) {
+    g.out(xh[c], Cb.rank[c], Cb.rank[c], nvec);
+    g.term(Cb.leaf[c], Cb.leaf_ld[c], true, x + T.off[c], n, false, (int)T.size[c]);
+  }
+  g.run(ctx);
+  for (int l = T.depth - 1; l >= 0; --l) {
+    for (int c = T.first(l); c < T.first(l + 1); ++c) {
+      g.out(xh[c], Cb.rank[c], Cb.rank[c], nvec);
+      for (int q = 1; q <= 2; ++q) {
+        int ch = 2 * c + q;
+        g.term(Cb.tr[ch], Cb.tr_ld[ch], true, xh[ch], Cb.rank[ch], false, Cb.rank[ch]);
+      }
+    }
+    g.run(ctx);
+  }
+  // couplings
+  for (int t = 0; t < T.ncl; ++t) {
+    g.out(yh[t], R.rank[t], R.rank[t], nvec);
+    const int32_t* bl;
+    int cnt;
+    v.row_blocks(t, bl, cnt);
+    for (int q = 0; q < cnt; ++q) {
+      int b = bl[q];
+      if (v.type(b) != BT_ADM || !v.ptr(b)) continue;
+      int s = v.vcol(b);
+      g.term(v.ptr(b), v.ld(b), trans, xh[s], Cb.rank[s], false, Cb.rank[s]);
+    }
+  }
+  g.run(ctx);
+  // backward transform
+  for (int l = 1; l <= T.depth; ++l) {
+    for (int c = T.first(l); c < T.first(l + 1); ++c) {
+      g.out(yh[c], R.rank[c], R.rank[c], nvec, true);
+      g.term(R.tr[c], R.tr_ld[c], false, yh[TreeH::parent(c)], R.rank[TreeH::parent(c)], false,
+             R.rank[TreeH::parent(c)]);
+    }
+    g.run(ctx);
+  }
+  // leaves and nearfield
+  double* z = ctx->ws.get<double>((size_t)n * nvec);
+  for (int t = T.first(T.depth); t < T.ncl; ++t) {
+    g.out(z + T.off[t], n, (int)T.size[t], nvec);
+    g.term(R.leaf[t], R.leaf_ld[t], false, yh[t], R.rank[t], false, R.rank[t]);
+    const int32_t* bl;
+    int cnt;
+    v.row_blocks(t, bl, cnt);
+    for (int q = 0; q < cnt; ++q) {
+      int b = bl[q];
+      if (v.type(b) != BT_INADM || !v.ptr(b)) continue;
+      int s = v.vcol(b);
+      g.term(v.ptr(b), v.ld(b), trans, x + T.off[s], n, false, (int)T.size[s]);
+    }
+  }
+  g.run(ctx);
+  k_axpby(n, nvec, alpha, z, n, beta, y, n, ctx->stream);
+}
+
+}  // namespace h2

@@ -1,0 +1,450 @@
+// Internal declarations of the H^2 multiplication library.
+//
+// Host orchestration (tree.cpp, h2mat.cpp, phase1.cpp, phase2.cpp, api.cpp)
+// is plain C++ over a thin device layer (dev_*) and batched kernel launchers
+// (k_*).  The HIP implementations live in dev_hip.hip and kernels_*.hip.
+#pragma once
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/h2.h"
+
+namespace h2 {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  h2_status code;
+  Error(h2_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] void fail(h2_status c, const std::string& msg);
+#define H2_REQUIRE(cond, code, msg) \
+  do {                              \
+    if (!(cond)) ::h2::fail(code, msg); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device layer (HIP runtime; all copies are asynchronous on `stream`)
+// ---------------------------------------------------------------------------
+void dev_set_device(int device);
+void* dev_malloc(size_t bytes);
+void dev_free(void* p);
+void* dev_malloc_host(size_t bytes);  // pinned
+void dev_free_host(void* p);
+void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);
+void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);
+void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
+void dev_zero(void* dst, size_t bytes, void* stream);
+void dev_sync(void* stream);
+void* dev_event_create();
+void dev_event_destroy(void* ev);
+void dev_event_record(void* ev, void* stream);
+float dev_event_ms(void* a, void* b);  // synchronises on b
+
+// ---------------------------------------------------------------------------
+// kernel descriptors (identical layout on host and device)
+// ---------------------------------------------------------------------------
+// C[m x n] (ldc) = beta*C + sum_terms alpha_eff * op(A) op(B)
+struct GemmOut {
+  void* C;
+  int64_t ldc;
+  int32_t m, n;
+  int32_t t0, t1;  // term range
+  int32_t beta;    // 0: overwrite, 1: accumulate
+  int32_t pad;
+};
+enum : int32_t { GT_TA = 1, GT_TB = 2, GT_BEYE = 4, GT_SCALE_MUL = 8, GT_SCALE_INV = 16 };
+struct GemmTerm {
+  const void* A;
+  const void* B;   // unused when GT_BEYE (B = identity, k == n)
+  const double* scale;  // GT_SCALE_MUL: alpha *= *scale; GT_SCALE_INV: alpha *= (*scale > 0 ? 1 / *scale : 0)
+  int64_t lda, ldb;
+  int32_t k, flags;
+  double alpha;
+};
+// Householder QR (in place; reflectors below the diagonal, tau[min(m,n)]),
+// R (rrows x n, upper part; zero below) copied to R if non-null.
+struct QrProb {
+  double* A;
+  double* tau;
+  double* R;
+  int64_t lda, ldr;
+  int32_t m, n, rrows, pad;
+};
+// C (m x ncols) <- Q^T C (trans = 1) or Q C (trans = 0), Q = H_0 ... H_{r-1}
+struct ApplyProb {
+  const double* V;
+  const double* tau;
+  double* C;
+  int64_t ldv, ldc;
+  int32_t m, nrefl, ncols, trans;
+};
+// R factor of the tall matrix T (N x m): T = A (transA = 0) or T = A^T where A
+// is m x N column-major (transA = 1).  R (min(N,m) x m, ldr) upper, zero below.
+// zero_cols (nullable device int): columns j < *zero_cols of T are read as 0.
+struct TsqrProb {
+  const void* A;
+  double* R;
+  const int32_t* zero_cols;
+  int64_t lda, ldr;
+  int32_t N, m, transA, prec;  // prec 1: A holds float
+};
+// One-sided Jacobi on the m columns of R (p x m, ldr): right singular vectors
+// U (m x m, ldu, columns by descending sigma), sigma[m];
+// rank[0] = #{sigma > max(eps, rtol * sigma_max)}.
+struct JacobiProb {
+  const double* R;
+  double* U;     // may be null (values only)
+  double* sigma;
+  int32_t* rank;
+  int64_t ldr, ldu;
+  int32_t p, m;
+  double eps, rtol;
+};
+
+// dynamic LDS per workgroup of the factorization kernels, in doubles (62.5 KiB;
+// static shared data comes on top).  Working sets larger than this use a
+// global scratch slot per workgroup, which the launch builders allocate.
+constexpr int kLdsDoubles = 8000;
+
+// launchers (descriptor arrays are device pointers)
+void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
+                int prec, void* stream);
+void k_qr(const QrProb* probs, int n, int max_m, int max_n, void* stream);
+void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int max_m, int max_r,
+             void* stream);
+void k_tsqr(const TsqrProb* probs, int n, int max_m, double* scratch, void* stream);
+void k_jacobi(const JacobiProb* probs, int n, int max_m, double* scratch, void* stream);
+size_t tsqr_scratch_doubles(int max_m);
+size_t jacobi_scratch_doubles(int max_m);
+
+// interpolation / kernel evaluation
+struct ChebLeaf {   // V[i, nu] for leaf cluster c
+  double* V;
+  int64_t ldv, off;  // point offset in cluster order
+  int32_t c, size;
+};
+struct ChebPair {   // transfer E_c (c, parent) or coupling S_ts (t, s)
+  double* out;
+  int64_t ld;
+  int32_t a, b;
+};
+struct NearBlock {
+  double* out;
+  int64_t ld, off_t, off_s;
+  int32_t size_t_, size_s, diag, pad;
+};
+void k_cheb_leaf(const ChebLeaf* d, int n, const double* pts, const double* lo, const double* hi,
+                 int dim, int order, void* stream);
+void k_cheb_transfer(const ChebPair* d, int n, const double* lo, const double* hi, int dim,
+                     int order, void* stream);
+void k_cheb_coupling(const ChebPair* d, int n, const double* lo, const double* hi, int dim,
+                     int order, int kernel, void* stream);
+void k_nearfield(const NearBlock* d, int n, const double* pts, int dim, int kernel, void* stream);
+
+// segmented sums of squares: out[i] = sum over items of segment i of ||M||_F^2
+struct SumsqItem {
+  const double* M;
+  int64_t ld;
+  int32_t rows, cols;
+};
+void k_sumsq(const SumsqItem* items, const int32_t* seg_ptr, int nseg, double* out, int mode,
+             void* stream);  // mode 1: out = s > 0 ? 1/sqrt(s) : 0
+// set diagonal: for each item, A[i + i*ld] = 1 for i < count (A must be zeroed)
+struct EyeItem {
+  double* A;
+  int64_t ld;
+  int32_t count, pad;
+};
+void k_eye(const EyeItem* items, int n, void* stream);
+// y (rows x cols, ldy) <- alpha x + beta y (beta = 0 ignores y)
+void k_axpby(int64_t rows, int64_t cols, double alpha, const double* x, int64_t ldx, double beta,
+             double* y, int64_t ldy, void* stream);
+
+// ---------------------------------------------------------------------------
+// host structures
+// ---------------------------------------------------------------------------
+struct TreeH {  // complete binary cluster tree of uniform depth, breadth-first ids
+  int dim = 0, depth = 0, ncl = 0;
+  int64_t n = 0;
+  std::vector<int64_t> off, size, perm;
+  std::vector<double> pts;      // permuted points, n x dim row-major
+  std::vector<double> lo, hi;   // interpolation boxes (widened), ncl x dim
+  std::vector<double> blo, bhi; // tight boxes, ncl x dim
+  static int level(int c) {
+    int l = 0;
+    while ((2 << l) - 1 <= c) ++l;
+    return l;
+  }
+  static int first(int l) { return (1 << l) - 1; }
+  static int parent(int c) { return (c - 1) / 2; }
+  bool leaf(int c) const { return level(c) == depth; }
+  bool same_as(const TreeH& o) const { return n == o.n && depth == o.depth && perm == o.perm; }
+};
+
+enum : int8_t { BT_SPLIT = 0, BT_ADM = 1, BT_INADM = 2 };
+struct BlockTreeH {  // level-aligned block tree; children of a split block are 4 consecutive ids
+  std::vector<int32_t> t, s, child0;
+  std::vector<int8_t> type;
+  std::vector<int32_t> lvl;        // blocks of level l: [lvl[l], lvl[l+1])
+  std::vector<int32_t> row_ptr, row_blk, col_ptr, col_blk;  // CSR by row / column cluster
+  int64_t n_adm = 0, n_inadm = 0;
+  int nblocks() const { return (int)t.size(); }
+  void finalize(int ncl);          // builds CSRs (sorted by the other cluster)
+  int find(int tt, int ss) const;  // block id or -1
+};
+
+struct h2_tree_impl;
+
+// nested cluster basis on the device
+struct Basis {
+  std::vector<int32_t> rank;
+  std::vector<double*> leaf;      // leaf c: #c x rank[c]
+  std::vector<int64_t> leaf_ld;
+  std::vector<double*> tr;        // non-root c: rank[c] x rank[parent]
+  std::vector<int64_t> tr_ld;
+  void resize(int ncl) {
+    rank.assign(ncl, 0);
+    leaf.assign(ncl, nullptr);
+    leaf_ld.assign(ncl, 1);
+    tr.assign(ncl, nullptr);
+    tr_ld.assign(ncl, 1);
+  }
+};
+
+struct H2Core {
+  std::shared_ptr<TreeH> ct;
+  std::shared_ptr<BlockTreeH> bt;
+  Basis V, W;
+  std::vector<double*> blk;  // coupling rank_V[t] x rank_W[s] (ld rank_V[t]) or nearfield #t x #s (ld #t)
+  int64_t ld_of(int b) const {
+    return bt->type[b] == BT_ADM ? (int64_t)std::max(1, V.rank[bt->t[b]]) : ct->size[bt->t[b]];
+  }
+};
+
+}  // namespace h2
+
+// ---------------------------------------------------------------------------
+// context and arenas
+// ---------------------------------------------------------------------------
+struct h2_ctx;
+
+namespace h2 {
+
+struct Arena {
+  h2_ctx* ctx = nullptr;
+  std::vector<std::pair<char*, size_t>> chunks;
+  size_t cur = 0, used = 0, total = 0;
+  void* alloc(size_t bytes);
+  template <class T>
+  T* get(size_t count) { return (T*)alloc(count * sizeof(T)); }
+  void reset() { cur = 0; used = 0; }
+  void release();
+  ~Arena() { release(); }
+};
+
+}  // namespace h2
+
+namespace h2 {
+enum KernelKind { KK_GEMM = 0, KK_TSQR = 1, KK_JACOBI = 2, KK_BUILD = 3, KK_OTHER = 4, KK_COUNT = 5 };
+struct KernelStat {
+  double ms = 0, flops = 0, bytes = 0;
+  int64_t launches = 0;
+};
+struct PendingLaunch {
+  void* a;
+  void* b;
+  int kind;
+  double flops, bytes;
+};
+}  // namespace h2
+
+struct h2_ctx {
+  int device = -1;
+  void* stream = nullptr;
+  bool host_only = true;
+  h2::Arena ws;                        // per-call workspace
+  std::vector<std::pair<char*, size_t>> cache;  // free device chunks
+  char* stage = nullptr;               // pinned staging for descriptor uploads
+  size_t stage_cap = 0, stage_used = 0;
+  std::vector<void*> events;
+  std::vector<int> ev_step;            // step id of each recorded event interval
+  double step_ms[8] = {0};
+  int prec = 0;                        // bulk precision of the running call
+  bool profile = false;                // time every launch with stream events
+  std::vector<void*> ev_pool;          // reusable events for launch timing
+  std::vector<h2::PendingLaunch> pending;
+  h2::KernelStat kstat[h2::KK_COUNT];
+  ~h2_ctx();
+};
+
+struct h2_tree {
+  std::shared_ptr<h2::TreeH> ct;
+  std::shared_ptr<h2::BlockTreeH> bt;
+  double eta = 0;
+};
+
+struct h2_matrix {
+  h2_ctx* ctx = nullptr;
+  h2::H2Core c;
+  h2::Arena mem;
+  bool zero = false;
+};
+
+struct h2_product {
+  h2_ctx* ctx = nullptr;
+  h2::H2Core c;
+  h2::Arena mem;
+  int64_t n_triples = 0;
+};
+
+namespace h2 {
+
+// uploads (pinned staging -> workspace), sync helper resets the staging
+void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes);
+template <class T>
+T* upload(h2_ctx* ctx, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  return (T*)upload_bytes(ctx, v.data(), v.size() * sizeof(T));
+}
+void ctx_sync(h2_ctx* ctx);
+
+// launch timing (when ctx->profile): events around one launch
+struct LaunchTimer {
+  h2_ctx* ctx;
+  void* a = nullptr;
+  int kind;
+  double flops, bytes;
+  LaunchTimer(h2_ctx* c, int k, double f, double b);
+  ~LaunchTimer();
+};
+void kernel_stats_collect(h2_ctx* ctx);
+
+// step timing with stream events
+void step_begin(h2_ctx* ctx, int step);
+void step_end(h2_ctx* ctx, int step);
+void steps_collect(h2_ctx* ctx);
+
+// batched launch builders
+struct GemmBatch {
+  std::vector<GemmOut> outs;
+  std::vector<GemmTerm> terms;
+  int prec = 0;
+  // starts a new output; subsequent term() calls accumulate into it
+  void out(double* C, int64_t ldc, int m, int n, bool accumulate = false);
+  void term(const double* A, int64_t lda, bool tA, const double* B, int64_t ldb, bool tB, int k,
+            double alpha = 1.0, const double* scale = nullptr, int scale_mode = 0);
+  void copy(const double* A, int64_t lda, bool tA, int k, double alpha = 1.0,
+            const double* scale = nullptr, int scale_mode = 0);  // op(A) * I_k
+  void run(h2_ctx* ctx);
+  bool empty() const { return outs.empty(); }
+};
+struct QrBatch {
+  std::vector<QrProb> p;
+  int max_m = 0, max_n = 0;
+  void add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr, int rrows);
+  void run(h2_ctx* ctx);
+};
+struct ApplyBatch {
+  std::vector<ApplyProb> p;
+  int max_m = 0, max_r = 0;
+  void add(const double* V, int64_t ldv, const double* tau, int m, int nrefl, double* C,
+           int64_t ldc, int ncols, bool trans);
+  void run(h2_ctx* ctx);
+};
+struct TsqrBatch {
+  std::vector<TsqrProb> p;
+  int max_m = 0;
+  void add(const void* A, int64_t lda, int N, int m, bool transA, double* R, int64_t ldr,
+           int prec = 0, const int32_t* zero_cols = nullptr);
+  void run(h2_ctx* ctx);
+};
+struct JacobiBatch {
+  std::vector<JacobiProb> p;
+  int max_m = 0;
+  void add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu, double* sigma,
+           int32_t* rank, double eps, double rtol = 0.0);
+  void run(h2_ctx* ctx);
+};
+// sigma_max of many small matrices: tsqr + jacobi (values only); sig[i] = sigma_max
+struct NormBatch {
+  struct Item {
+    const double* A;  // stored rows x cols, column-major
+    int64_t lda;
+    int rows, cols;
+  };
+  std::vector<Item> items;
+  void add(const double* A, int64_t lda, int rows, int cols) { items.push_back({A, lda, rows, cols}); }
+  std::vector<const double*> run(h2_ctx* ctx);  // device pointer to sigma_max of each item
+};
+
+// zeroed device buffer from an arena
+double* zeros(h2_ctx* ctx, Arena& a, size_t count);
+
+// trees
+std::shared_ptr<TreeH> build_cluster_tree(int dim, int64_t n, const double* pts, int leaf_size);
+std::shared_ptr<BlockTreeH> build_block_tree(const TreeH& rt, const TreeH& ct, double eta);
+
+// product block tree with triples
+enum : int8_t { TK_AA = 0, TK_AN = 1, TK_NA = 2, TK_NN = 3, TK_SPLIT = 4 };
+struct Triple {
+  int32_t s, bx, by;  // middle cluster, block of X (view coords), block of Y
+  int8_t kind;
+};
+struct ProductTreeH {
+  std::shared_ptr<BlockTreeH> bt;           // T^XY
+  std::vector<int32_t> tri_ptr;             // per block
+  std::vector<Triple> tri;
+  int64_t n_terminated = 0;
+};
+
+// views of an H^2-matrix or its adjoint
+struct View {
+  const H2Core* m = nullptr;
+  bool T = false;
+  const Basis& rowb() const { return T ? m->W : m->V; }
+  const Basis& colb() const { return T ? m->V : m->W; }
+  const BlockTreeH& bt() const { return *m->bt; }
+  // block ids whose view-row is t (sorted by view-column)
+  void row_blocks(int t, const int32_t*& b, int& cnt) const {
+    const auto& B = *m->bt;
+    if (!T) {
+      b = B.row_blk.data() + B.row_ptr[t];
+      cnt = B.row_ptr[t + 1] - B.row_ptr[t];
+    } else {
+      b = B.col_blk.data() + B.col_ptr[t];
+      cnt = B.col_ptr[t + 1] - B.col_ptr[t];
+    }
+  }
+  int vrow(int b) const { return T ? m->bt->s[b] : m->bt->t[b]; }
+  int vcol(int b) const { return T ? m->bt->t[b] : m->bt->s[b]; }
+  int find(int t, int s) const { return T ? m->bt->find(s, t) : m->bt->find(t, s); }
+  int8_t type(int b) const { return m->bt->type[b]; }
+  const double* ptr(int b) const { return m->blk[b]; }
+  int64_t ld(int b) const { return m->ld_of(b); }
+};
+ProductTreeH build_product_tree(const View& X, const View& Y, int ncl);
+
+// matrices
+void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2_matrix* out);
+void zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix* out);
+void matvec(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double* x, double beta,
+            double* y, int nvec);
+void to_dense(h2_ctx* ctx, const H2Core& A, double* out, int64_t ld);
+void basis_dense(h2_ctx* ctx, const H2Core& A, int which, int cluster, double* out, int64_t ld);
+
+// phases
+void phase1(h2_ctx* ctx, const h2_matrix* X, const h2_matrix* Y, double eps, int prec,
+            h2_product* G);
+void phase2(h2_ctx* ctx, h2_product* G, h2_matrix* Z, double eps, int prec);
+
+}  // namespace h2

@@ -1,0 +1,511 @@
+// Phase 1: compressed induced cluster bases and the intermediate product G.
+//
+// Section 4 of the paper, for the row basis of X Y and (on the adjoint pair
+// Y*, X*) for its column basis:
+//   set-up   basis weights R_{Y,r} (Figure "basis_weights"), cluster basis
+//            products P_{XY,s} = W_{X,s}^* V_{Y,s}, total weights Z_s
+//            (Figure "total_weights") with the block scaling of Section 5;
+//   sweep    Figure "induced_basis" level by level from the leaves: the
+//            range of V_X (or Vhat_X) is kept by a Householder QR, the
+//            remainder is truncated by an SVD at eps, transfer matrices are
+//            cut from Qhat_t, and A_{t,s} = Q_t^* X|_{t x s} V_{Y,s} is kept.
+// Every cluster of a level is processed by one batched launch per step; the
+// ranks chosen on a level are read back once before the next level.
+//
+// G is then formed on the product block tree T^XY: every terminated triple
+// (t,s,r) contributes P_row X|_{ts} Y|_{sr} P_col in the coefficients of the
+// new bases (projection only on a subdivided or inadmissible factor side),
+// contributions are pushed to the leaves of T^XY with the new transfer
+// matrices, and inadmissible leaves are expanded to dense blocks together
+// with the products of two nearfield blocks.
+#include <cmath>
+
+#include "internal.h"
+
+namespace h2 {
+
+struct P1Side {
+  Basis Q;                                   // new isometric nested basis
+  std::vector<int32_t> k1;                   // rank of the kept V_X part
+  std::vector<double*> RXP;                  // [R_{X,t}; 0], k_t x k, ld k_t
+  std::vector<double*> A;                    // A_{t,s} for s in C_t: k_t x (k |C_t|), ld k_t
+  std::vector<int32_t> cpos;                 // per stored block of X': position in C_{t}
+  std::vector<double*> P;                    // P_{XY,s}, k x k
+};
+
+// relative tolerance of the numerical rank of V_X (the kept range)
+static constexpr double kVxRtol = 1e-12;
+
+static int uniform_rank(const Basis& B) {
+  int k = B.rank.empty() ? 0 : B.rank[0];
+  for (int r : B.rank) H2_REQUIRE(r == k, H2_ERR_UNSUPPORTED, "input bases must have one rank");
+  return k;
+}
+
+// One pass of Figure "induced_basis" for the product X Y given as views.
+static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, Arena& keep,
+                         P1Side& out, int step_setup, int step_sweep) {
+  const TreeH& T = *X.m->ct;
+  const int ncl = T.ncl, D = T.depth;
+  const int k = uniform_rank(X.rowb());
+  H2_REQUIRE(uniform_rank(Y.rowb()) == k && uniform_rank(X.colb()) == k && uniform_rank(Y.colb()) == k,
+             H2_ERR_UNSUPPORTED, "X and Y must have the same rank");
+  const Basis& VX = X.rowb();
+  const Basis& WX = X.colb();
+  const Basis& VY = Y.rowb();
+  const Basis& WY = Y.colb();
+  Arena& ws = ctx->ws;
+  GemmBatch g;
+  g.prec = ctx->prec;
+  step_begin(ctx, step_setup);
+
+  // ---- basis weights of W_Y (bottom-up thin QR) ----
+  std::vector<double*> RY(ncl);
+  std::vector<int> lY(ncl);
+  for (int c = 0; c < ncl; ++c) RY[c] = zeros(ctx, ws, (size_t)k * k);
+  {
+    TsqrBatch ts;
+    for (int c = T.first(D); c < ncl; ++c) {
+      lY[c] = (int)std::min<int64_t>(k, T.size[c]);
+      ts.add(WY.leaf[c], WY.leaf_ld[c], (int)T.size[c], k, false, RY[c], k);
+    }
+    ts.run(ctx);
+    for (int l = D - 1; l >= 0; --l) {
+      for (int c = T.first(l); c < T.first(l + 1); ++c) {
+        int c1 = 2 * c + 1, c2 = 2 * c + 2;
+        int rows = lY[c1] + lY[c2];
+        double* Wh = ws.get<double>((size_t)std::max(rows, 1) * k);
+        g.out(Wh, rows, lY[c1], k);
+        g.term(RY[c1], k, false, WY.tr[c1], WY.tr_ld[c1], false, k);
+        g.out(Wh + lY[c1], rows, lY[c2], k);
+        g.term(RY[c2], k, false, WY.tr[c2], WY.tr_ld[c2], false, k);
+        lY[c] = std::min(k, rows);
+        ts.add(Wh, rows, rows, k, false, RY[c], k);
+      }
+      g.run(ctx);
+      ts.run(ctx);
+    }
+  }
+  // ---- cluster basis products P_s = W_{X,s}^* V_{Y,s} ----
+  out.P.assign(ncl, nullptr);
+  for (int c = 0; c < ncl; ++c) out.P[c] = ws.get<double>((size_t)k * k);
+  for (int c = T.first(D); c < ncl; ++c) {
+    g.out(out.P[c], k, k, k);
+    g.term(WX.leaf[c], WX.leaf_ld[c], true, VY.leaf[c], VY.leaf_ld[c], false, (int)T.size[c]);
+  }
+  g.run(ctx);
+  std::vector<double*> PE(ncl, nullptr);  // P_s E_{Y,s}
+  for (int l = D; l >= 1; --l) {
+    for (int c = T.first(l); c < T.first(l + 1); ++c) {
+      PE[c] = ws.get<double>((size_t)k * k);
+      g.out(PE[c], k, k, k);
+      g.term(out.P[c], k, false, VY.tr[c], VY.tr_ld[c], false, k);
+    }
+    g.run(ctx);
+    for (int c = T.first(l - 1); c < T.first(l); ++c) {
+      g.out(out.P[c], k, k, k);
+      for (int q = 1; q <= 2; ++q)
+        g.term(WX.tr[2 * c + q], WX.tr_ld[2 * c + q], true, PE[2 * c + q], k, false, k);
+    }
+    g.run(ctx);
+  }
+  // ---- total weights of (V_Y, Y), top-down, blocks scaled by 1/||S R^*||_2 ----
+  const BlockTreeH& BY = Y.bt();
+  std::vector<double*> M(BY.nblocks(), nullptr);
+  NormBatch nb;
+  std::vector<int> nbi(BY.nblocks(), -1);
+  for (int b = 0; b < BY.nblocks(); ++b) {
+    if (Y.type(b) != BT_ADM) continue;
+    int r = Y.vcol(b);
+    M[b] = ws.get<double>((size_t)k * k);
+    g.out(M[b], std::max(lY[r], 1), lY[r], k);
+    g.term(RY[r], k, false, Y.ptr(b), Y.ld(b), !Y.T, k);  // R_{Y,r} S_{Y,sr}^*
+    nbi[b] = (int)nb.items.size();
+    nb.add(M[b], std::max(lY[r], 1), lY[r], k);
+  }
+  g.run(ctx);
+  std::vector<const double*> sig = nb.run(ctx);
+  std::vector<double*> Z(ncl, nullptr);
+  std::vector<int> zr(ncl, 0);
+  for (int l = 0; l <= D; ++l) {
+    TsqrBatch ts;
+    for (int s = T.first(l); s < T.first(l + 1); ++s) {
+      const int32_t* bl;
+      int cnt;
+      Y.row_blocks(s, bl, cnt);
+      int N = l > 0 ? zr[TreeH::parent(s)] : 0;
+      for (int q = 0; q < cnt; ++q)
+        if (Y.type(bl[q]) == BT_ADM) N += lY[Y.vcol(bl[q])];
+      Z[s] = ws.get<double>((size_t)k * k);
+      zr[s] = std::min(N, k);
+      if (N == 0) continue;
+      double* Gh = ws.get<double>((size_t)N * k);
+      int row = 0;
+      if (l > 0 && zr[TreeH::parent(s)] > 0) {
+        int zp = zr[TreeH::parent(s)];
+        g.out(Gh, N, zp, k);
+        g.term(Z[TreeH::parent(s)], k, false, VY.tr[s], VY.tr_ld[s], true, k);
+        row += zp;
+      }
+      for (int q = 0; q < cnt; ++q) {
+        int b = bl[q];
+        if (Y.type(b) != BT_ADM) continue;
+        int lr = lY[Y.vcol(b)];
+        g.out(Gh + row, N, lr, k);
+        g.copy(M[b], std::max(lr, 1), false, k, 1.0, sig[nbi[b]], 2);
+        row += lr;
+      }
+      ts.add(Gh, N, N, k, false, Z[s], k);
+    }
+    g.run(ctx);
+    ts.run(ctx);
+  }
+  // S_{X,t's'} P_{s'} E_{Y,s'} for admissible blocks of X below the root
+  const BlockTreeH& BX = X.bt();
+  std::vector<double*> SPE(BX.nblocks(), nullptr);
+  for (int b = 0; b < BX.nblocks(); ++b) {
+    if (X.type(b) != BT_ADM || X.vrow(b) == 0) continue;
+    SPE[b] = ws.get<double>((size_t)k * k);
+    g.out(SPE[b], k, k, k);
+    g.term(X.ptr(b), X.ld(b), X.T, PE[X.vcol(b)], k, false, k);
+  }
+  g.run(ctx);
+  step_end(ctx, step_setup);
+
+  // ---- the sweep of Figure "induced_basis" ----
+  step_begin(ctx, step_sweep);
+  out.Q.resize(ncl);
+  out.k1.assign(ncl, 0);
+  out.RXP.assign(ncl, nullptr);
+  out.A.assign(ncl, nullptr);
+  out.cpos.assign(BX.nblocks(), -1);
+  std::vector<std::vector<int32_t>> Cb(ncl);  // blocks (t, s), s in C_t, sorted by s
+  for (int t = 0; t < ncl; ++t) {
+    const int32_t* bl;
+    int cnt;
+    X.row_blocks(t, bl, cnt);
+    for (int q = 0; q < cnt; ++q)
+      if (X.type(bl[q]) != BT_ADM) {
+        out.cpos[bl[q]] = (int32_t)Cb[t].size();
+        Cb[t].push_back(bl[q]);
+      }
+  }
+  for (int l = D; l >= 0; --l) {
+    const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
+    const bool leaf = l == D;
+    std::vector<int> rows(nc), ncols(nc), kk1(nc);
+    std::vector<double*> Bt(nc), Vr(nc), VXw(nc), RX(nc), Rt(nc), U(nc), sg(nc);
+    std::vector<std::vector<int>> offs(nc);
+    // (a) the blocks X|_{t x s} V_{Y,s} (leaf) or Ahat_{t,s} (non-leaf), the V_X part
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i;
+      int m = leaf ? (int)T.size[t] : out.Q.rank[2 * t + 1] + out.Q.rank[2 * t + 2];
+      rows[i] = m;
+      int nC = (int)Cb[t].size();
+      Bt[i] = ws.get<double>((size_t)std::max(m, 1) * k * std::max(nC, 1));
+      VXw[i] = ws.get<double>((size_t)std::max(m, 1) * k);
+      if (leaf) {
+        for (int j = 0; j < nC; ++j) {
+          int b = Cb[t][j], s = X.vcol(b);
+          g.out(Bt[i] + (size_t)j * k * m, m, m, k);
+          g.term(X.ptr(b), X.ld(b), X.T, VY.leaf[s], VY.leaf_ld[s], false, (int)T.size[s]);
+        }
+        g.out(VXw[i], m, m, k);
+        g.copy(VX.leaf[t], VX.leaf_ld[t], false, k);
+      } else {
+        int o = 0;
+        offs[i].clear();
+        for (int q = 1; q <= 2; ++q) {
+          int ch = 2 * t + q;
+          offs[i].push_back(o);
+          g.out(VXw[i] + o, m, out.Q.rank[ch], k);
+          g.term(out.RXP[ch], std::max(out.Q.rank[ch], 1), false, VX.tr[ch], VX.tr_ld[ch], false, k);
+          o += out.Q.rank[ch];
+        }
+        for (int j = 0; j < nC; ++j) {
+          int s = X.vcol(Cb[t][j]);
+          for (int q = 1; q <= 2; ++q) {
+            int ch = 2 * t + q, kc = out.Q.rank[ch];
+            g.out(Bt[i] + (size_t)j * k * m + offs[i][q - 1], m, kc, k);
+            for (int p2 = 1; p2 <= 2; ++p2) {
+              int sc = 2 * s + p2;
+              int bc = X.find(ch, sc);
+              H2_REQUIRE(bc >= 0, H2_ERR_SHAPE, "missing child block");
+              if (X.type(bc) == BT_ADM)
+                g.term(out.RXP[ch], std::max(kc, 1), false, SPE[bc], k, false, k);
+              else
+                g.term(out.A[ch] + (size_t)out.cpos[bc] * k * kc, std::max(kc, 1), false, VY.tr[sc],
+                       VY.tr_ld[sc], false, k);
+            }
+          }
+        }
+      }
+    }
+    g.run(ctx);
+    // (b) block norms (Section 5)
+    NormBatch nrm;
+    std::vector<std::vector<int>> ni(nc);
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i;
+      for (size_t j = 0; j < Cb[t].size(); ++j) {
+        ni[i].push_back((int)nrm.items.size());
+        nrm.add(Bt[i] + j * k * rows[i], std::max(rows[i], 1), rows[i], k);
+      }
+    }
+    std::vector<const double*> ns = nrm.run(ctx);
+    // (c) scaled remainder blocks X V_Y Z_s^* / ||.|| and the SVD of the V_X
+    //     part: U1 (m x m) with the numerical range of V_X in its first k1
+    //     columns (k1 = #{sigma > 1e-12 sigma_max})
+    TsqrBatch ts;
+    JacobiBatch jb;
+    int32_t* rk = ws.get<int32_t>(2 * nc);  // [k1 | k2] per cluster
+    dev_zero(rk, sizeof(int32_t) * 2 * nc, ctx->stream);
+    std::vector<double*> U1(nc), W1(nc);
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, m = rows[i];
+      int nco = 0;
+      for (int b : Cb[t]) nco += zr[X.vcol(b)];
+      ncols[i] = nco;
+      Vr[i] = ws.get<double>((size_t)std::max(m, 1) * std::max(nco, 1));
+      int col = 0;
+      for (size_t j = 0; j < Cb[t].size(); ++j) {
+        int s = X.vcol(Cb[t][j]);
+        if (zr[s] == 0) continue;
+        g.out(Vr[i] + (size_t)col * m, m, m, zr[s]);
+        g.term(Bt[i] + j * k * m, m, false, Z[s], k, true, k, 1.0, ns[ni[i][j]], 2);
+        col += zr[s];
+      }
+      int p1 = std::min(k, m);
+      RX[i] = zeros(ctx, ws, (size_t)m * m);   // R factor of V_X^* (p1 x m)
+      U1[i] = ws.get<double>((size_t)m * m);
+      sg[i] = ws.get<double>(m);
+      ts.add(VXw[i], m, k, m, true, RX[i], m);
+      jb.add(RX[i], m, p1, m, U1[i], m, sg[i], rk + i, 0.0, kVxRtol);
+    }
+    g.run(ctx);
+    ts.run(ctx);
+    jb.run(ctx);
+    // (d) remainder: rows k1.. of U1^* [blocks], SVD on the masked matrix
+    for (int i = 0; i < nc; ++i) {
+      int m = rows[i];
+      W1[i] = ws.get<double>((size_t)m * std::max(ncols[i], 1));
+      if (ncols[i] > 0) {
+        g.out(W1[i], m, m, ncols[i]);
+        g.term(U1[i], m, true, Vr[i], m, false, m);
+      }
+    }
+    g.run(ctx);
+    for (int i = 0; i < nc; ++i) {
+      int m = rows[i];
+      int p = std::min(ncols[i], m);
+      Rt[i] = zeros(ctx, ws, (size_t)m * m);
+      U[i] = ws.get<double>((size_t)m * m);
+      double* sg2 = ws.get<double>(m);
+      ts.add(W1[i], m, ncols[i], m, true, Rt[i], m, 0, rk + i);
+      jb.add(Rt[i], m, p, m, U[i], m, sg2, rk + nc + i, eps);
+    }
+    ts.run(ctx);
+    jb.run(ctx);
+    std::vector<int32_t> kk(2 * nc);
+    dev_d2h(kk.data(), rk, sizeof(int32_t) * 2 * nc, ctx->stream);
+    ctx_sync(ctx);
+    // (e) Q_t = [U1(:, 1:k1), U1 U2(:, 1:k2)], transfers, A_{t,s} = Q_t^* (...), [R_X; 0]
+    std::vector<double*> Qn(nc);
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, m = rows[i];
+      kk1[i] = kk[i];
+      int k2 = kk[nc + i];
+      int kt = kk1[i] + k2;
+      H2_REQUIRE(kt >= 1, H2_ERR_NUMERIC, "phase 1: empty cluster basis");
+      out.Q.rank[t] = kt;
+      out.k1[t] = kk1[i];
+      Qn[i] = keep.get<double>((size_t)m * kt);
+      if (kk1[i] > 0) {
+        g.out(Qn[i], m, m, kk1[i]);
+        g.copy(U1[i], m, false, kk1[i]);
+      }
+      if (k2 > 0) {
+        g.out(Qn[i] + (size_t)kk1[i] * m, m, m, k2);
+        g.term(U1[i], m, false, U[i], m, false, m);
+      }
+    }
+    g.run(ctx);
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, m = rows[i], kt = out.Q.rank[t];
+      if (leaf) {
+        out.Q.leaf[t] = Qn[i];
+        out.Q.leaf_ld[t] = m;
+      } else {
+        for (int q = 1; q <= 2; ++q) {
+          out.Q.tr[2 * t + q] = Qn[i] + offs[i][q - 1];
+          out.Q.tr_ld[2 * t + q] = m;
+        }
+      }
+      int nC = (int)Cb[t].size();
+      out.A[t] = ws.get<double>((size_t)kt * k * std::max(nC, 1));
+      if (nC > 0) {
+        g.out(out.A[t], kt, kt, k * nC);
+        g.term(Qn[i], m, true, Bt[i], m, false, m);
+      }
+      out.RXP[t] = zeros(ctx, ws, (size_t)kt * k);
+      if (kk1[i] > 0) {
+        g.out(out.RXP[t], kt, kk1[i], k);
+        g.term(U1[i], m, true, VXw[i], m, false, m);
+      }
+    }
+    g.run(ctx);
+  }
+  step_end(ctx, step_sweep);
+}
+
+void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, int prec,
+            h2_product* G) {
+  const TreeH& T = *Xm->c.ct;
+  H2_REQUIRE(T.same_as(*Ym->c.ct), H2_ERR_SHAPE, "X and Y must share the cluster tree");
+  ctx->prec = prec;
+  G->ctx = ctx;
+  G->mem.ctx = ctx;
+  View X{&Xm->c, false}, Y{&Ym->c, false};
+  View Yt{&Ym->c, true}, Xt{&Xm->c, true};
+  P1Side row, col;
+  induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2);
+  induced_pass(ctx, Yt, Xt, eps, G->mem, col, 0, 3);
+
+  step_begin(ctx, 1);
+  ProductTreeH PT = build_product_tree(X, Y, T.ncl);
+  step_end(ctx, 1);
+  G->n_triples = PT.n_terminated;
+
+  // ---- forming G on T^XY (top-down, then dense leaves) ----
+  step_begin(ctx, 4);
+  const BlockTreeH& B = *PT.bt;
+  const int k = uniform_rank(Xm->c.V);
+  Arena& ws = ctx->ws;
+  GemmBatch g;
+  g.prec = prec;
+  // P_{XY,s} S_{Y,sr} for admissible blocks of Y
+  const BlockTreeH& BY = *Ym->c.bt;
+  std::vector<double*> PS(BY.nblocks(), nullptr);
+  for (int b = 0; b < BY.nblocks(); ++b) {
+    if (BY.type[b] != BT_ADM) continue;
+    PS[b] = ws.get<double>((size_t)k * k);
+    g.out(PS[b], k, k, k);
+    g.term(row.P[BY.t[b]], k, false, Ym->c.blk[b], Ym->c.ld_of(b), false, k);
+  }
+  g.run(ctx);
+  H2Core& C = G->c;
+  C.ct = Xm->c.ct;
+  C.bt = PT.bt;
+  C.V = row.Q;
+  C.W = col.Q;
+  C.blk.assign(B.nblocks(), nullptr);
+  std::vector<double*> S(B.nblocks(), nullptr);
+  auto Arow = [&](int bx, int kt) { return row.A[X.vrow(bx)] + (size_t)row.cpos[bx] * k * kt; };
+  for (int l = 0; l <= T.depth; ++l) {
+    const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
+    std::vector<double*> TAA(b1 - b0, nullptr), TNA(b1 - b0, nullptr), Pp(b1 - b0, nullptr),
+        Mm(b1 - b0, nullptr);
+    std::vector<int> parent(b1 - b0, -1);
+    if (l > 0)
+      for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
+        if (B.type[pb] == BT_SPLIT)
+          for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - b0] = pb;
+    for (int b = b0; b < b1; ++b) {
+      int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+      bool keep = B.type[b] != BT_SPLIT;
+      S[b] = keep ? G->mem.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1))
+                  : ws.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1));
+      bool aa = false, na = false;
+      for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q) {
+        int8_t kd = PT.tri[q].kind;
+        aa |= kd == TK_AA;
+        na |= kd == TK_NA;
+      }
+      int i = b - b0;
+      if (aa) {
+        TAA[i] = ws.get<double>((size_t)k * k);
+        g.out(TAA[i], k, k, k);
+        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
+          if (PT.tri[q].kind == TK_AA)
+            g.term(Xm->c.blk[PT.tri[q].bx], Xm->c.ld_of(PT.tri[q].bx), false, PS[PT.tri[q].by], k, false, k);
+      }
+      if (na && kt > 0) {
+        TNA[i] = ws.get<double>((size_t)kt * k);
+        g.out(TNA[i], kt, kt, k);
+        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
+          if (PT.tri[q].kind == TK_NA)
+            g.term(Arow(PT.tri[q].bx, kt), kt, false, Ym->c.blk[PT.tri[q].by], Ym->c.ld_of(PT.tri[q].by),
+                   false, k);
+      }
+      if (parent[i] >= 0 && kt > 0) {
+        int pt = B.t[parent[i]], pr = B.s[parent[i]];
+        int kpt = row.Q.rank[pt], kpr = col.Q.rank[pr];
+        Pp[i] = ws.get<double>((size_t)kt * std::max(kpr, 1));
+        g.out(Pp[i], kt, kt, kpr);
+        g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], std::max(kpt, 1), false, kpt);
+      }
+    }
+    g.run(ctx);
+    for (int b = b0; b < b1; ++b) {
+      int i = b - b0, r = B.s[b], kr = col.Q.rank[r];
+      bool an = false;
+      for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q) an |= PT.tri[q].kind == TK_AN;
+      if ((an || TAA[i]) && kr > 0) {
+        Mm[i] = ws.get<double>((size_t)k * kr);
+        g.out(Mm[i], k, k, kr);
+        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
+          if (PT.tri[q].kind == TK_AN) {
+            int by = PT.tri[q].by;  // block (s,r) of Y = block (r,s) of Y^*
+            g.term(Xm->c.blk[PT.tri[q].bx], Xm->c.ld_of(PT.tri[q].bx), false,
+                   col.A[r] + (size_t)col.cpos[by] * k * kr, kr, true, k);
+          }
+        if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
+      }
+    }
+    g.run(ctx);
+    for (int b = b0; b < b1; ++b) {
+      int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+      g.out(S[b], std::max(kt, 1), kt, kr);
+      if (Pp[i]) {
+        int kpr = col.Q.rank[B.s[parent[i]]];
+        g.term(Pp[i], kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
+      }
+      if (TNA[i]) g.term(TNA[i], kt, false, col.RXP[r], std::max(kr, 1), true, k);
+      if (Mm[i]) g.term(row.RXP[t], std::max(kt, 1), false, Mm[i], k, false, k);
+      if (B.type[b] == BT_ADM) C.blk[b] = S[b];
+    }
+    g.run(ctx);
+  }
+  // dense inadmissible leaves: sum of nearfield products plus Q_t S Q^W_r^*
+  {
+    const int l = T.depth;
+    std::vector<double*> QS(B.nblocks(), nullptr);
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (B.type[b] != BT_INADM) continue;
+      int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+      if (kt == 0 || kr == 0) continue;
+      QS[b] = ws.get<double>((size_t)T.size[t] * kr);
+      g.out(QS[b], T.size[t], (int)T.size[t], kr);
+      g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], std::max(kt, 1), false, kt);
+    }
+    g.run(ctx);
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (B.type[b] != BT_INADM) continue;
+      int t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
+      double* Dn = G->mem.get<double>((size_t)T.size[t] * T.size[r]);
+      C.blk[b] = Dn;
+      g.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r]);
+      for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
+        if (PT.tri[q].kind == TK_NN) {
+          int bx = PT.tri[q].bx, by = PT.tri[q].by, s = PT.tri[q].s;
+          g.term(Xm->c.blk[bx], Xm->c.ld_of(bx), false, Ym->c.blk[by], Ym->c.ld_of(by), false,
+                 (int)T.size[s]);
+        }
+      if (QS[b]) g.term(QS[b], T.size[t], false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
+    }
+    g.run(ctx);
+  }
+  step_end(ctx, 4);
+}
+
+}  // namespace h2

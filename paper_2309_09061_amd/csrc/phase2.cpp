@@ -1,0 +1,552 @@
+// Phase 2: coarsening of G (an H^2-matrix on T^XY with isometric bases) into
+// the prescribed block tree T_IK (Section 6, Figures "match_column" and
+// "basis").  For the row basis (and on G* for the column basis):
+//   top-down  product total weights Z_t from [Z_{t+} E_t^*; S_{t,r}^*] over
+//             the admissible leaves of T^XY inside admissible leaves of T_IK
+//             (eq. (Zt_condensation));
+//   bottom-up leaf clusters: C_t = [V_t Z_t^*, G|_{t x r_i}] (eq. (ct_leaf));
+//             non-leaf clusters: Chat_t = [Vhat_t Z_t^*, Ahat_{t,r_i}]
+//             (eq. (ct_nonleaf)), Ahat assembled from the children's
+//             representations on the column tree of (t, r_i) (Definition
+//             "Column tree", Lemma "Column representation", Figure
+//             "match_column"); SVD and rank choice at eps; R_t = Q_t^* V_t
+//             and A_{t,r} = Q_t^* G|_{t x r}.
+// Every block is scaled by omega_b = 1/||G|_b||_F of the admissible leaf b
+// of T_IK containing it.  Z's couplings Q^Z_t^* G|_b Q^ZW_r are accumulated
+// bottom-up over the blocks of T^XY inside b; Z's nearfield copies G.
+#include <cmath>
+#include <functional>
+#include <map>
+
+#include "internal.h"
+
+namespace h2 {
+
+struct ColLeaf {
+  int32_t node;
+  int32_t adm;
+  int32_t width;
+  int32_t off;
+};
+
+struct P2Side {
+  Basis Q;                   // new basis (leaf matrices and transfers)
+  std::vector<double*> R;    // R_t = Q_t^* V_t: kz_t x k_t, ld max(kz_t, 1)
+  std::vector<double*> A;    // per stored G block: A_{t,r} (kz_t x width), ld max(kz_t, 1)
+  std::vector<double*> RS;   // per stored admissible G leaf: R_t S_{t,r}, kz_t x kW_r
+};
+
+// union of two column-tree leaf lists covering the same index range
+static std::vector<ColLeaf> leaf_union(const TreeH& T, const std::vector<ColLeaf>& a,
+                                       const std::vector<ColLeaf>& b) {
+  std::vector<ColLeaf> out;
+  size_t i = 0, j = 0;
+  while (i < a.size() && j < b.size()) {
+    const ColLeaf &x = a[i], &y = b[j];
+    if (x.node == y.node) {
+      out.push_back({x.node, x.adm && y.adm, 0, 0});
+      ++i;
+      ++j;
+    } else if (T.size[x.node] < T.size[y.node]) {  // x lies inside y
+      out.push_back(x);
+      if (T.off[x.node] + T.size[x.node] == T.off[y.node] + T.size[y.node]) ++j;
+      ++i;
+    } else {
+      out.push_back(y);
+      if (T.off[x.node] + T.size[x.node] == T.off[y.node] + T.size[y.node]) ++i;
+      ++j;
+    }
+  }
+  H2_REQUIRE(i == a.size() && j == b.size(), H2_ERR_SHAPE, "column trees do not cover one range");
+  return out;
+}
+
+static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
+                        const BlockTreeH& TIK, const double* omega, double eps, Arena& keep,
+                        P2Side& out, int step) {
+  const TreeH& T = *G.m->ct;
+  const BlockTreeH& B = G.bt();
+  const int ncl = T.ncl, D = T.depth, nb = B.nblocks();
+  const Basis& Vb = G.rowb();
+  const Basis& Wb = G.colb();
+  Arena& ws = ctx->ws;
+  GemmBatch g;
+  g.prec = ctx->prec;
+  step_begin(ctx, step);
+  auto in_adm = [&](int b) { return tag[b] >= 0 && TIK.type[tag[b]] == BT_ADM; };
+  const double* om = omega;  // omega + tag[b] is the scale of block b
+
+  // column trees (leaf lists over the view column) of blocks inside admissible leaves of T_IK
+  std::vector<std::vector<ColLeaf>> ctree(nb);
+  for (int l = D; l >= 0; --l)
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (!in_adm(b)) continue;
+      int r = G.vcol(b), t = G.vrow(b);
+      if (B.type[b] != BT_SPLIT) {
+        ctree[b] = {{r, B.type[b] == BT_ADM ? 1 : 0, 0, 0}};
+      } else {
+        std::vector<ColLeaf> all;
+        for (int qc = 1; qc <= 2; ++qc) {
+          int rc = 2 * r + qc;
+          int c1 = G.find(2 * t + 1, rc), c2 = G.find(2 * t + 2, rc);
+          H2_REQUIRE(c1 >= 0 && c2 >= 0, H2_ERR_SHAPE, "product tree: missing child");
+          auto u = leaf_union(T, ctree[c1], ctree[c2]);
+          all.insert(all.end(), u.begin(), u.end());
+        }
+        ctree[b] = all;
+      }
+      int off = 0;
+      for (auto& L : ctree[b]) {
+        L.width = L.adm ? Wb.rank[L.node] : (int)T.size[L.node];
+        L.off = off;
+        off += L.width;
+      }
+    }
+  auto tree_width = [&](int b) { return ctree[b].empty() ? 0 : ctree[b].back().off + ctree[b].back().width; };
+
+  // ---- product total weights Z_t, top-down ----
+  std::vector<double*> Zt(ncl, nullptr);
+  std::vector<int> zr(ncl, 0);
+  for (int l = 0; l <= D; ++l) {
+    TsqrBatch ts;
+    for (int t = T.first(l); t < T.first(l + 1); ++t) {
+      int kt = Vb.rank[t];
+      int zp = l > 0 ? zr[TreeH::parent(t)] : 0;
+      int N = zp;
+      const int32_t* bl;
+      int cnt;
+      G.row_blocks(t, bl, cnt);
+      for (int q = 0; q < cnt; ++q)
+        if (B.type[bl[q]] == BT_ADM && in_adm(bl[q])) N += Wb.rank[G.vcol(bl[q])];
+      Zt[t] = ws.get<double>((size_t)std::max(kt, 1) * std::max(kt, 1));
+      zr[t] = std::min(N, kt);
+      if (N == 0 || kt == 0) {
+        zr[t] = 0;
+        continue;
+      }
+      double* Gh = ws.get<double>((size_t)N * kt);
+      int row = 0;
+      if (zp > 0) {
+        int kp = Vb.rank[TreeH::parent(t)];
+        g.out(Gh, N, zp, kt);
+        g.term(Zt[TreeH::parent(t)], std::max(kp, 1), false, Vb.tr[t], Vb.tr_ld[t], true, kp);
+        row += zp;
+      }
+      for (int q = 0; q < cnt; ++q) {
+        int b = bl[q];
+        if (B.type[b] != BT_ADM || !in_adm(b)) continue;
+        int kw = Wb.rank[G.vcol(b)];
+        if (kw == 0) continue;
+        g.out(Gh + row, N, kw, kt);
+        g.copy(G.ptr(b), G.ld(b), !G.T, kt, 1.0, om + tag[b], 1);  // omega S_{t,r}^*
+        row += kw;
+      }
+      ts.add(Gh, N, N, kt, false, Zt[t], std::max(kt, 1));
+    }
+    g.run(ctx);
+    ts.run(ctx);
+  }
+
+  // ---- transfer chains of the column basis used by match_column ----
+  // CH(c, a) = F_c F_{parent(c)} ... : W_a restricted to c equals W_c CH(c, a)
+  std::map<int64_t, std::pair<const double*, int64_t>> chain;
+  auto key = [&](int c, int a) { return (int64_t)c * ncl + a; };
+  std::function<void(int, int)> need;
+  std::vector<std::vector<std::pair<int, int>>> by_dist(D + 2);
+  need = [&](int c, int a) {
+    if (chain.count(key(c, a))) return;
+    int p = TreeH::parent(c);
+    if (p == a) {
+      chain[key(c, a)] = {Wb.tr[c], Wb.tr_ld[c]};
+      return;
+    }
+    need(p, a);
+    chain[key(c, a)] = {nullptr, 0};
+    by_dist[TreeH::level(c) - TreeH::level(a)].push_back({c, a});
+  };
+  auto contains = [&](int a, int c) {  // cluster a contains cluster c
+    return T.off[a] <= T.off[c] && T.off[c] + T.size[c] <= T.off[a] + T.size[a] && TreeH::level(a) <= TreeH::level(c);
+  };
+  struct Piece {
+    int blk, tc, src, srcoff, srcld, snode, sadm, tnode, tadm, twidth, toff, roff;
+  };
+  std::vector<std::vector<Piece>> pieces(D + 1);
+  for (int l = 0; l < D; ++l)
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (B.type[b] != BT_SPLIT || !in_adm(b)) continue;
+      int t = G.vrow(b), r = G.vcol(b);
+      for (const ColLeaf& L : ctree[b]) {
+        int rc = contains(2 * r + 1, L.node) ? 2 * r + 1 : 2 * r + 2;
+        for (int qt = 1; qt <= 2; ++qt) {
+          int tc = 2 * t + qt;
+          int c = G.find(tc, rc);
+          const ColLeaf* S = nullptr;
+          for (const ColLeaf& M : ctree[c])
+            if (contains(M.node, L.node)) S = &M;
+          H2_REQUIRE(S, H2_ERR_SHAPE, "match_column: no source leaf");
+          H2_REQUIRE(S->adm || S->node == L.node, H2_ERR_UNSUPPORTED,
+                     "match_column: inadmissible column leaf refined");
+          pieces[l].push_back({b, tc, c, S->off, 0, S->node, S->adm, L.node, L.adm, L.width, L.off, qt});
+          if (S->adm && S->node != L.node) need(L.node, S->node);
+        }
+      }
+    }
+  for (int d = 2; d <= D + 1; ++d) {
+    if (d >= (int)by_dist.size() || by_dist[d].empty()) continue;
+    for (auto [c, a] : by_dist[d]) {
+      int p = TreeH::parent(c);
+      auto pr = chain[key(p, a)];
+      double* M = ws.get<double>((size_t)std::max(Wb.rank[c], 1) * std::max(Wb.rank[a], 1));
+      g.out(M, std::max(Wb.rank[c], 1), Wb.rank[c], Wb.rank[a]);
+      g.term(Wb.tr[c], Wb.tr_ld[c], false, pr.first, pr.second, false, Wb.rank[p]);
+      chain[key(c, a)] = {M, std::max(Wb.rank[c], 1)};
+    }
+    g.run(ctx);
+  }
+  // W_{a} restricted to the leaf c: Q^W_c CH(c, a)
+  std::map<int64_t, std::pair<const double*, int64_t>> wrest;
+  for (int l = 0; l < D; ++l)
+    for (const Piece& P : pieces[l]) {
+      if (!P.sadm || P.tadm) continue;
+      int64_t kk = key(P.tnode, P.snode);
+      if (wrest.count(kk)) continue;
+      if (P.tnode == P.snode) {
+        wrest[kk] = {Wb.leaf[P.tnode], Wb.leaf_ld[P.tnode]};
+        continue;
+      }
+      auto ch = chain[key(P.tnode, P.snode)];
+      double* M = ws.get<double>((size_t)T.size[P.tnode] * std::max(Wb.rank[P.snode], 1));
+      g.out(M, T.size[P.tnode], (int)T.size[P.tnode], Wb.rank[P.snode]);
+      g.term(Wb.leaf[P.tnode], Wb.leaf_ld[P.tnode], false, ch.first, ch.second, false, Wb.rank[P.tnode]);
+      wrest[kk] = {M, T.size[P.tnode]};
+    }
+  g.run(ctx);
+
+  // ---- Figure "basis", bottom-up ----
+  out.Q.resize(ncl);
+  out.R.assign(ncl, nullptr);
+  out.A.assign(nb, nullptr);
+  out.RS.assign(nb, nullptr);
+  for (int l = D; l >= 0; --l) {
+    const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
+    const bool leaf = l == D;
+    std::vector<int> m(nc), ncols(nc);
+    std::vector<double*> Vh(nc, nullptr), C(nc), Rt(nc, nullptr), U(nc, nullptr), sg(nc, nullptr);
+    std::vector<std::vector<int>> cols_of(nc);
+    // Vhat_t = [R_{t'} E_{t'}]
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, kt = Vb.rank[t];
+      if (leaf) {
+        m[i] = (int)T.size[t];
+        continue;
+      }
+      int o = 0;
+      m[i] = out.Q.rank[2 * t + 1] + out.Q.rank[2 * t + 2];
+      Vh[i] = ws.get<double>((size_t)std::max(m[i], 1) * std::max(kt, 1));
+      for (int q = 1; q <= 2; ++q) {
+        int ch = 2 * t + q, kc = out.Q.rank[ch];
+        if (kc > 0) {
+          g.out(Vh[i] + o, m[i], kc, kt);
+          g.term(out.R[ch], kc, false, Vb.tr[ch], Vb.tr_ld[ch], false, Vb.rank[ch]);
+        }
+        o += kc;
+      }
+    }
+    g.run(ctx);
+    // C_t / Chat_t
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, kt = Vb.rank[t];
+      const int32_t* bl;
+      int cnt;
+      G.row_blocks(t, bl, cnt);
+      int nco = zr[t];
+      for (int q = 0; q < cnt; ++q) {
+        int b = bl[q];
+        if (!in_adm(b)) {
+          cols_of[i].push_back(-1);
+        } else if (leaf && B.type[b] == BT_INADM) {
+          cols_of[i].push_back(nco);
+          nco += (int)T.size[G.vcol(b)];
+        } else if (!leaf && B.type[b] == BT_SPLIT) {
+          cols_of[i].push_back(nco);
+          nco += tree_width(b);
+        } else {
+          cols_of[i].push_back(-1);
+        }
+      }
+      ncols[i] = nco;
+      C[i] = ws.get<double>((size_t)std::max(m[i], 1) * std::max(nco, 1));
+      if (m[i] == 0) continue;
+      if (zr[t] > 0) {
+        g.out(C[i], m[i], m[i], zr[t]);
+        if (leaf)
+          g.term(Vb.leaf[t], Vb.leaf_ld[t], false, Zt[t], std::max(kt, 1), true, kt);
+        else
+          g.term(Vh[i], m[i], false, Zt[t], std::max(kt, 1), true, kt);
+      }
+      if (leaf)
+        for (int q = 0; q < cnt; ++q) {
+          int b = bl[q];
+          if (cols_of[i][q] < 0) continue;
+          int r = G.vcol(b);
+          g.out(C[i] + (size_t)cols_of[i][q] * m[i], m[i], m[i], (int)T.size[r]);
+          g.copy(G.ptr(b), G.ld(b), G.T, (int)T.size[r], 1.0, om + tag[b], 1);
+        }
+    }
+    if (!leaf) {
+      // Ahat_{t,r}: the children's representations matched to the column tree of (t,r)
+      for (const Piece& P : pieces[l]) {
+        int t = G.vrow(P.blk), i = t - c0;
+        int kc = out.Q.rank[P.tc];
+        if (kc == 0) continue;
+        int ro = P.roff == 1 ? 0 : out.Q.rank[2 * t + 1];
+        int q;
+        {
+          const int32_t* bl;
+          int cnt;
+          G.row_blocks(t, bl, cnt);
+          for (q = 0; q < cnt && bl[q] != P.blk; ++q) {
+          }
+        }
+        double* dst = C[i] + ro + (size_t)(cols_of[i][q] + P.toff) * m[i];
+        const double* src;
+        int64_t sld = std::max(kc, 1);
+        if (B.type[P.src] == BT_ADM)
+          src = out.RS[P.src];
+        else
+          src = out.A[P.src] + (size_t)P.srcoff * sld;
+        g.out(dst, m[i], kc, P.twidth);
+        const double* sc = om + tag[P.blk];
+        if (!P.sadm) {
+          g.copy(src, sld, false, P.twidth, 1.0, sc, 1);
+        } else if (P.tadm) {
+          if (P.snode == P.tnode)
+            g.copy(src, sld, false, P.twidth, 1.0, sc, 1);
+          else {
+            auto ch = chain[key(P.tnode, P.snode)];
+            g.term(src, sld, false, ch.first, ch.second, true, Wb.rank[P.snode], 1.0, sc, 1);
+          }
+        } else {
+          auto wr = wrest[key(P.tnode, P.snode)];
+          g.term(src, sld, false, wr.first, wr.second, true, Wb.rank[P.snode], 1.0, sc, 1);
+        }
+      }
+    }
+    g.run(ctx);
+    // SVD of C_t: R factor of C_t^*, one-sided Jacobi
+    TsqrBatch ts;
+    JacobiBatch jb;
+    int32_t* rk = ws.get<int32_t>(nc);
+    dev_zero(rk, sizeof(int32_t) * nc, ctx->stream);
+    for (int i = 0; i < nc; ++i) {
+      if (m[i] == 0) continue;
+      int p = std::min(ncols[i], m[i]);
+      Rt[i] = zeros(ctx, ws, (size_t)m[i] * m[i]);
+      U[i] = ws.get<double>((size_t)m[i] * m[i]);
+      sg[i] = ws.get<double>(m[i]);
+      ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
+      jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, eps);
+    }
+    ts.run(ctx);
+    jb.run(ctx);
+    std::vector<int32_t> kz(nc);
+    dev_d2h(kz.data(), rk, sizeof(int32_t) * nc, ctx->stream);
+    ctx_sync(ctx);
+    // new basis, R_t, A_{t,r}
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, kt = Vb.rank[t], k = kz[i];
+      out.Q.rank[t] = k;
+      double* Qn = keep.get<double>((size_t)std::max(m[i], 1) * std::max(k, 1));
+      if (k > 0) {
+        g.out(Qn, m[i], m[i], k);
+        g.copy(U[i], m[i], false, k);
+      }
+      if (leaf) {
+        out.Q.leaf[t] = Qn;
+        out.Q.leaf_ld[t] = std::max(m[i], 1);
+      } else {
+        out.Q.tr[2 * t + 1] = Qn;
+        out.Q.tr[2 * t + 2] = Qn + out.Q.rank[2 * t + 1];
+        out.Q.tr_ld[2 * t + 1] = out.Q.tr_ld[2 * t + 2] = std::max(m[i], 1);
+      }
+      out.R[t] = ws.get<double>((size_t)std::max(k, 1) * std::max(kt, 1));
+    }
+    g.run(ctx);
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, kt = Vb.rank[t], k = out.Q.rank[t];
+      double* Qn = leaf ? out.Q.leaf[t] : out.Q.tr[2 * t + 1];
+      if (k > 0 && kt > 0) {
+        g.out(out.R[t], k, k, kt);
+        if (leaf)
+          g.term(Qn, m[i], true, Vb.leaf[t], Vb.leaf_ld[t], false, m[i]);
+        else
+          g.term(Qn, m[i], true, Vh[i], m[i], false, m[i]);
+      }
+      const int32_t* bl;
+      int cnt;
+      G.row_blocks(t, bl, cnt);
+      for (int q = 0; q < cnt; ++q) {
+        int b = bl[q];
+        if (!in_adm(b)) continue;
+        if (cols_of[i][q] >= 0) {
+          int w = leaf ? (int)T.size[G.vcol(b)] : tree_width(b);
+          out.A[b] = ws.get<double>((size_t)std::max(k, 1) * std::max(w, 1));
+          if (k == 0) continue;
+          g.out(out.A[b], k, k, w);
+          if (leaf)
+            g.term(Qn, m[i], true, G.ptr(b), G.ld(b), G.T, m[i]);  // Q_t^* G|_{t x r}
+          else
+            g.term(Qn, m[i], true, C[i] + (size_t)cols_of[i][q] * m[i], m[i], false, m[i], 1.0,
+                   om + tag[b], 2);
+        }
+      }
+    }
+    g.run(ctx);
+    // R_t S_{t,r} for admissible leaves of this level (used above and for Z)
+    for (int i = 0; i < nc; ++i) {
+      int t = c0 + i, k = out.Q.rank[t], kt = Vb.rank[t];
+      const int32_t* bl;
+      int cnt;
+      G.row_blocks(t, bl, cnt);
+      for (int q = 0; q < cnt; ++q) {
+        int b = bl[q];
+        if (B.type[b] != BT_ADM || !in_adm(b)) continue;
+        int kw = Wb.rank[G.vcol(b)];
+        out.RS[b] = ws.get<double>((size_t)std::max(k, 1) * std::max(kw, 1));
+        if (k == 0 || kw == 0) continue;
+        g.out(out.RS[b], k, k, kw);
+        g.term(out.R[t], k, false, G.ptr(b), G.ld(b), G.T, kt);
+      }
+    }
+    g.run(ctx);
+  }
+  step_end(ctx, step);
+}
+
+void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
+  H2_REQUIRE(Z->zero, H2_ERR_UNSUPPORTED, "Z must be zero (Z <- Z + XY with Z != 0 is not supported)");
+  const TreeH& T = *Gp->c.ct;
+  H2_REQUIRE(T.same_as(*Z->c.ct), H2_ERR_SHAPE, "Z must be built on the cluster tree of X and Y");
+  ctx->prec = prec;
+  const BlockTreeH& B = *Gp->c.bt;
+  const BlockTreeH& TIK = *Z->c.bt;
+  const int nb = B.nblocks();
+  // T_IK leaf containing each block of T^XY (-1: the block is a non-leaf of T_IK)
+  std::vector<int> tag(nb, -1), par(nb, -1);
+  for (int b = 0; b < nb; ++b)
+    if (B.type[b] == BT_SPLIT)
+      for (int q = 0; q < 4; ++q) par[B.child0[b] + q] = b;
+  for (int b = 0; b < nb; ++b) {
+    int f = TIK.find(B.t[b], B.s[b]);
+    if (f >= 0)
+      tag[b] = TIK.type[f] == BT_SPLIT ? -1 : f;
+    else {
+      H2_REQUIRE(par[b] >= 0 && tag[par[b]] >= 0, H2_ERR_NOT_REFINED, "T^XY does not refine T_IK");
+      tag[b] = tag[par[b]];
+    }
+    if (B.type[b] != BT_SPLIT)
+      H2_REQUIRE(tag[b] >= 0, H2_ERR_NOT_REFINED, "T^XY does not refine T_IK");
+  }
+  // omega_b = 1/||G|_b||_F over the leaves of T^XY inside admissible b
+  std::vector<std::vector<SumsqItem>> seg(TIK.nblocks());
+  for (int b = 0; b < nb; ++b) {
+    if (B.type[b] == BT_SPLIT || tag[b] < 0 || TIK.type[tag[b]] != BT_ADM || !Gp->c.blk[b]) continue;
+    int rows = B.type[b] == BT_ADM ? Gp->c.V.rank[B.t[b]] : (int)T.size[B.t[b]];
+    int cols = B.type[b] == BT_ADM ? Gp->c.W.rank[B.s[b]] : (int)T.size[B.s[b]];
+    seg[tag[b]].push_back({Gp->c.blk[b], Gp->c.ld_of(b), rows, cols});
+  }
+  std::vector<SumsqItem> items;
+  std::vector<int32_t> sp{0};
+  for (auto& s : seg) {
+    items.insert(items.end(), s.begin(), s.end());
+    sp.push_back((int32_t)items.size());
+  }
+  double* omega = ctx->ws.get<double>(std::max(TIK.nblocks(), 1));
+  if (items.empty()) items.push_back({nullptr, 1, 0, 0});
+  k_sumsq(upload(ctx, items), upload(ctx, sp), TIK.nblocks(), omega, 1, ctx->stream);
+
+  View Gr{&Gp->c, false}, Gc{&Gp->c, true};
+  P2Side row, col;
+  coarse_pass(ctx, Gr, tag, TIK, omega, eps, Z->mem, row, 5);
+  coarse_pass(ctx, Gc, tag, TIK, omega, eps, Z->mem, col, 6);
+
+  // ---- Z: couplings Q^Z_t^* G|_b Q^ZW_r bottom-up, nearfield copied ----
+  step_begin(ctx, 7);
+  Arena& ws = ctx->ws;
+  GemmBatch g;
+  g.prec = prec;
+  H2Core& Zc = Z->c;
+  Zc.V = row.Q;
+  Zc.W = col.Q;
+  Zc.blk.assign(TIK.nblocks(), nullptr);
+  const Basis &QZ = row.Q, &QZW = col.Q;
+  std::vector<double*> L(nb, nullptr);
+  for (int l = T.depth; l >= 0; --l) {
+    std::vector<double*> T1(nb, nullptr);
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (tag[b] < 0 || TIK.type[tag[b]] != BT_ADM) continue;
+      int t = B.t[b], r = B.s[b], kz = QZ.rank[t], kw = QZW.rank[r];
+      bool top = TIK.find(t, r) == tag[b];
+      L[b] = top ? Z->mem.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1))
+                 : ws.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1));
+      if (B.type[b] == BT_SPLIT)
+        for (int q = 0; q < 4; ++q) {
+          int c = B.child0[b] + q, tc = B.t[c], rc = B.s[c];
+          T1[c] = ws.get<double>((size_t)std::max(QZ.rank[tc], 1) * std::max(kw, 1));
+          if (QZ.rank[tc] == 0 || kw == 0) continue;
+          g.out(T1[c], QZ.rank[tc], QZ.rank[tc], kw);
+          g.term(L[c], std::max(QZ.rank[tc], 1), false, QZW.tr[rc], QZW.tr_ld[rc], false, QZW.rank[rc]);
+        }
+    }
+    g.run(ctx);
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (tag[b] < 0 || TIK.type[tag[b]] != BT_ADM) continue;
+      int t = B.t[b], r = B.s[b], kz = QZ.rank[t], kw = QZW.rank[r];
+      if (kz == 0 || kw == 0) continue;
+      g.out(L[b], kz, kz, kw);
+      if (B.type[b] == BT_ADM) {
+        // R_t S_tr R^W_r^*
+        g.term(row.RS[b], kz, false, col.R[r], kw, true, Gp->c.W.rank[r]);
+      } else if (B.type[b] == BT_INADM) {
+        // (Q^Z_t^* N_tr) Q^ZW_r
+        g.term(row.A[b], kz, false, QZW.leaf[r], QZW.leaf_ld[r], false, (int)T.size[r]);
+      } else {
+        for (int q = 0; q < 4; ++q) {
+          int c = B.child0[b] + q, tc = B.t[c];
+          g.term(QZ.tr[tc], QZ.tr_ld[tc], true, T1[c], std::max(QZ.rank[tc], 1), false, QZ.rank[tc]);
+        }
+      }
+    }
+    g.run(ctx);
+  }
+  for (int zb = 0; zb < TIK.nblocks(); ++zb) {
+    if (TIK.type[zb] == BT_SPLIT) continue;
+    int t = TIK.t[zb], r = TIK.s[zb];
+    int b = B.find(t, r);
+    H2_REQUIRE(b >= 0, H2_ERR_NOT_REFINED, "leaf of T_IK missing from T^XY");
+    if (TIK.type[zb] == BT_ADM) {
+      Zc.blk[zb] = L[b];
+    } else {
+      double* Nz = Z->mem.get<double>((size_t)T.size[t] * T.size[r]);
+      Zc.blk[zb] = Nz;
+      g.out(Nz, T.size[t], (int)T.size[t], (int)T.size[r]);
+      if (B.type[b] == BT_INADM) {
+        g.copy(Gp->c.blk[b], Gp->c.ld_of(b), false, (int)T.size[r]);
+      } else {
+        H2_REQUIRE(B.type[b] == BT_ADM, H2_ERR_NOT_REFINED, "inadmissible leaf of T_IK subdivided in T^XY");
+        int kt = Gp->c.V.rank[t], kr = Gp->c.W.rank[r];
+        double* QS = ws.get<double>((size_t)T.size[t] * std::max(kr, 1));
+        GemmBatch g0;
+        g0.out(QS, T.size[t], (int)T.size[t], kr);
+        g0.term(Gp->c.V.leaf[t], Gp->c.V.leaf_ld[t], false, Gp->c.blk[b], Gp->c.ld_of(b), false, kt);
+        g0.run(ctx);
+        g.term(QS, T.size[t], false, Gp->c.W.leaf[r], Gp->c.W.leaf_ld[r], true, kr);
+      }
+    }
+  }
+  g.run(ctx);
+  Z->zero = false;
+  step_end(ctx, 7);
+}
+
+}  // namespace h2

@@ -1,0 +1,407 @@
+// Runtime: errors, device arenas with a chunk cache, pinned staging of
+// launch descriptors, step timers and the batched launch builders.
+#include <cmath>
+
+#include "internal.h"
+
+namespace h2 {
+
+[[noreturn]] void fail(h2_status c, const std::string& msg) { throw Error(c, msg); }
+
+// ---------------------------------------------------------------------------
+// arenas: bump allocation in device chunks; chunks return to the context cache
+// ---------------------------------------------------------------------------
+static constexpr size_t kChunk = (size_t)64 << 20;
+
+void* Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes == 0) bytes = 256;
+  while (cur < chunks.size()) {
+    if (used + bytes <= chunks[cur].second) {
+      void* p = chunks[cur].first + used;
+      used += bytes;
+      return p;
+    }
+    ++cur;
+    used = 0;
+  }
+  // take the smallest cached chunk that fits, else allocate
+  size_t best = (size_t)-1;
+  int bi = -1;
+  if (ctx)
+    for (size_t i = 0; i < ctx->cache.size(); ++i)
+      if (ctx->cache[i].second >= bytes && ctx->cache[i].second < best) {
+        best = ctx->cache[i].second;
+        bi = (int)i;
+      }
+  std::pair<char*, size_t> ch;
+  if (bi >= 0) {
+    ch = ctx->cache[bi];
+    ctx->cache.erase(ctx->cache.begin() + bi);
+  } else {
+    size_t sz = std::max(bytes, kChunk);
+    ch = {(char*)dev_malloc(sz), sz};
+  }
+  chunks.push_back(ch);
+  cur = chunks.size() - 1;
+  used = bytes;
+  total += ch.second;
+  return ch.first;
+}
+
+void Arena::release() {
+  for (auto& c : chunks) {
+    if (ctx)
+      ctx->cache.push_back(c);
+    else
+      dev_free(c.first);
+  }
+  chunks.clear();
+  cur = used = total = 0;
+}
+
+double* zeros(h2_ctx* ctx, Arena& a, size_t count) {
+  double* p = a.get<double>(count);
+  dev_zero(p, count * sizeof(double), ctx->stream);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// descriptor uploads through pinned staging
+// ---------------------------------------------------------------------------
+void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
+  size_t need = (bytes + 255) & ~(size_t)255;
+  if (ctx->stage_used + need > ctx->stage_cap) {
+    dev_sync(ctx->stream);  // earlier copies out of the staging buffer are done
+    ctx->stage_used = 0;
+    if (need > ctx->stage_cap) {
+      dev_free_host(ctx->stage);
+      ctx->stage_cap = std::max(need, ctx->stage_cap * 2);
+      ctx->stage = (char*)dev_malloc_host(ctx->stage_cap);
+    }
+  }
+  char* h = ctx->stage + ctx->stage_used;
+  ctx->stage_used += need;
+  std::memcpy(h, src, bytes);
+  void* d = ctx->ws.alloc(bytes);
+  dev_h2d(d, h, bytes, ctx->stream);
+  return d;
+}
+
+void ctx_sync(h2_ctx* ctx) {
+  dev_sync(ctx->stream);
+  ctx->stage_used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// step timers
+// ---------------------------------------------------------------------------
+void step_begin(h2_ctx* ctx, int step) {
+  void* e = dev_event_create();
+  dev_event_record(e, ctx->stream);
+  ctx->events.push_back(e);
+  ctx->ev_step.push_back(-1 - step);
+}
+void step_end(h2_ctx* ctx, int step) {
+  void* e = dev_event_create();
+  dev_event_record(e, ctx->stream);
+  ctx->events.push_back(e);
+  ctx->ev_step.push_back(step);
+}
+void steps_collect(h2_ctx* ctx) {
+  for (size_t i = 0; i + 1 < ctx->events.size(); ++i) {
+    int s = ctx->ev_step[i];
+    if (s < 0 && ctx->ev_step[i + 1] == -1 - s)
+      ctx->step_ms[-1 - s] += dev_event_ms(ctx->events[i], ctx->events[i + 1]);
+  }
+  for (void* e : ctx->events) dev_event_destroy(e);
+  ctx->events.clear();
+  ctx->ev_step.clear();
+}
+
+// ---------------------------------------------------------------------------
+// launch timers: one pair of events per launch, resolved at collection
+// ---------------------------------------------------------------------------
+static void* pool_event(h2_ctx* ctx) {
+  if (ctx->ev_pool.empty()) return dev_event_create();
+  void* e = ctx->ev_pool.back();
+  ctx->ev_pool.pop_back();
+  return e;
+}
+
+LaunchTimer::LaunchTimer(h2_ctx* c, int k, double f, double b) : ctx(c), kind(k), flops(f), bytes(b) {
+  if (!ctx->profile) return;
+  a = pool_event(ctx);
+  dev_event_record(a, ctx->stream);
+}
+
+LaunchTimer::~LaunchTimer() {
+  if (!a) return;
+  void* b = pool_event(ctx);
+  dev_event_record(b, ctx->stream);
+  ctx->pending.push_back({a, b, kind, flops, bytes});
+}
+
+void kernel_stats_collect(h2_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    KernelStat& k = ctx->kstat[p.kind];
+    k.ms += dev_event_ms(p.a, p.b);
+    k.launches += 1;
+    k.flops += p.flops;
+    k.bytes += p.bytes;
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// batch builders
+// ---------------------------------------------------------------------------
+void GemmBatch::out(double* C, int64_t ldc, int m, int n, bool accumulate) {
+  GemmOut o{};
+  o.C = C;
+  o.ldc = std::max<int64_t>(ldc, 1);
+  o.m = m;
+  o.n = n;
+  o.t0 = o.t1 = (int32_t)terms.size();
+  o.beta = accumulate ? 1 : 0;
+  outs.push_back(o);
+}
+
+void GemmBatch::term(const double* A, int64_t lda, bool tA, const double* B, int64_t ldb, bool tB,
+                     int k, double alpha, const double* scale, int scale_mode) {
+  GemmTerm t{};
+  t.A = A;
+  t.B = B;
+  t.lda = std::max<int64_t>(lda, 1);
+  t.ldb = std::max<int64_t>(ldb, 1);
+  t.k = k;
+  t.flags = (tA ? GT_TA : 0) | (tB ? GT_TB : 0) |
+            (scale ? (scale_mode == 2 ? GT_SCALE_INV : GT_SCALE_MUL) : 0);
+  t.scale = scale;
+  t.alpha = alpha;
+  if (k <= 0) return;  // empty contraction contributes nothing
+  terms.push_back(t);
+  outs.back().t1 = (int32_t)terms.size();
+}
+
+void GemmBatch::copy(const double* A, int64_t lda, bool tA, int k, double alpha, const double* scale,
+                     int scale_mode) {
+  term(A, lda, tA, nullptr, 1, false, k, alpha, scale, scale_mode);
+  if (k > 0) terms.back().flags |= GT_BEYE;
+}
+
+void GemmBatch::run(h2_ctx* ctx) {
+  std::vector<int32_t> tiles;
+  for (size_t i = 0; i < outs.size(); ++i) {
+    const GemmOut& o = outs[i];
+    if (o.m <= 0 || o.n <= 0) continue;
+    if (o.t0 == o.t1 && o.beta) continue;  // nothing to add
+    for (int j0 = 0; j0 < o.n; j0 += 16)
+      for (int i0 = 0; i0 < o.m; i0 += 16) {
+        tiles.push_back((int32_t)i);
+        tiles.push_back(i0);
+        tiles.push_back(j0);
+      }
+  }
+  if (tiles.empty()) {
+    outs.clear();
+    terms.clear();
+    return;
+  }
+  std::vector<GemmTerm> tt = terms;
+  if (tt.empty()) tt.push_back(GemmTerm{});
+  GemmOut* d_o = upload(ctx, outs);
+  GemmTerm* d_t = upload(ctx, tt);
+  int32_t* d_tiles = upload(ctx, tiles);
+  // algorithmic work: 2 m n k per term; bytes: operands read once, C written
+  double flops = 0, bytes = 0;
+  const double es = prec ? 4.0 : 8.0;
+  for (const GemmOut& o : outs) {
+    if (o.m <= 0 || o.n <= 0) continue;
+    bytes += es * (double)o.m * o.n * (o.beta ? 2 : 1);
+    for (int q = o.t0; q < o.t1; ++q) {
+      const GemmTerm& t = terms[q];
+      flops += (t.flags & GT_BEYE) ? 0.0 : 2.0 * o.m * o.n * t.k;
+      bytes += es * ((double)o.m * t.k + ((t.flags & GT_BEYE) ? 0.0 : (double)t.k * o.n));
+    }
+  }
+  LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
+  k_gemm_sum(d_o, d_t, d_tiles, (int)(tiles.size() / 3), prec, ctx->stream);
+  outs.clear();
+  terms.clear();
+}
+
+void QrBatch::add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr,
+                  int rrows) {
+  if (m <= 0 || n <= 0) return;
+  QrProb q{};
+  q.A = A;
+  q.lda = lda;
+  q.m = m;
+  q.n = n;
+  q.tau = tau;
+  q.R = R;
+  q.ldr = std::max<int64_t>(ldr, 1);
+  q.rrows = rrows;
+  p.push_back(q);
+  max_m = std::max(max_m, m);
+  max_n = std::max(max_n, n);
+}
+void QrBatch::run(h2_ctx* ctx) {
+  if (p.empty()) return;
+  k_qr(upload(ctx, p), (int)p.size(), max_m, max_n, ctx->stream);
+  p.clear();
+  max_m = max_n = 0;
+}
+
+void ApplyBatch::add(const double* V, int64_t ldv, const double* tau, int m, int nrefl, double* C,
+                     int64_t ldc, int ncols, bool trans) {
+  if (m <= 0 || nrefl <= 0 || ncols <= 0) return;
+  ApplyProb a{};
+  a.V = V;
+  a.ldv = ldv;
+  a.tau = tau;
+  a.m = m;
+  a.nrefl = nrefl;
+  a.C = C;
+  a.ldc = ldc;
+  a.ncols = ncols;
+  a.trans = trans ? 1 : 0;
+  p.push_back(a);
+  max_m = std::max(max_m, m);
+  max_r = std::max(max_r, nrefl);
+}
+void ApplyBatch::run(h2_ctx* ctx) {
+  if (p.empty()) return;
+  std::vector<int32_t> work;
+  for (size_t i = 0; i < p.size(); ++i)
+    for (int c = 0; c < p[i].ncols; c += 64) {
+      work.push_back((int32_t)i);
+      work.push_back(c);
+    }
+  k_apply(upload(ctx, p), upload(ctx, work), (int)(work.size() / 2), max_m, max_r, ctx->stream);
+  p.clear();
+  max_m = max_r = 0;
+}
+
+void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, double* R, int64_t ldr,
+                    int prec, const int32_t* zero_cols) {
+  if (m <= 0) return;
+  TsqrProb t{};
+  t.A = A;
+  t.lda = std::max<int64_t>(lda, 1);
+  t.N = N;
+  t.m = m;
+  t.transA = transA ? 1 : 0;
+  t.R = R;
+  t.ldr = std::max<int64_t>(ldr, 1);
+  t.prec = prec;
+  t.zero_cols = zero_cols;
+  p.push_back(t);
+  max_m = std::max(max_m, m);
+}
+void TsqrBatch::run(h2_ctx* ctx) {
+  if (p.empty()) return;
+  size_t slot = tsqr_scratch_doubles(max_m);
+  double* scratch = nullptr;
+  if (slot > (size_t)kLdsDoubles) scratch = ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024));
+  double flops = 0, bytes = 0;
+  for (const TsqrProb& t : p) {  // Householder QR of an N x m matrix: 2 N m^2 - 2 m^3 / 3
+    double N = t.N, m = t.m, r = std::min(N, m);
+    flops += 2.0 * N * m * m - 2.0 * r * r * r / 3.0;
+    bytes += 8.0 * (N * m + r * m);
+  }
+  TsqrProb* d = upload(ctx, p);
+  LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
+  k_tsqr(d, (int)p.size(), max_m, scratch, ctx->stream);
+  p.clear();
+  max_m = 0;
+}
+
+void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu,
+                      double* sigma, int32_t* rank, double eps, double rtol) {
+  JacobiProb j{};
+  j.R = R;
+  j.ldr = std::max<int64_t>(ldr, 1);
+  j.p = p_;
+  j.m = m;
+  j.U = U;
+  j.ldu = std::max<int64_t>(ldu, 1);
+  j.sigma = sigma;
+  j.rank = rank;
+  j.eps = eps;
+  j.rtol = rtol;
+  p.push_back(j);
+  max_m = std::max(max_m, m);
+}
+void JacobiBatch::run(h2_ctx* ctx) {
+  if (p.empty()) return;
+  size_t slot = jacobi_scratch_doubles(std::max(max_m, 1));
+  double* scratch = nullptr;
+  if (slot > (size_t)kLdsDoubles) scratch = ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024));
+  double flops = 0, bytes = 0;
+  for (const JacobiProb& j : p) {  // one sweep of one-sided Jacobi over m columns of length p
+    double m = j.m, pp = j.p;
+    flops += m * (m - 1) / 2 * (6.0 * pp + 6.0 * m);
+    bytes += 8.0 * (pp * m + m * m);
+  }
+  JacobiProb* d = upload(ctx, p);
+  LaunchTimer lt(ctx, KK_JACOBI, flops, bytes);
+  k_jacobi(d, (int)p.size(), max_m, scratch, ctx->stream);
+  p.clear();
+  max_m = 0;
+}
+
+std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
+  // pointer to sigma_max of every item (a zero for empty matrices)
+  size_t n = items.size();
+  std::vector<const double*> out(n);
+  if (n == 0) return out;
+  const double* zero = zeros(ctx, ctx->ws, 1);
+  TsqrBatch ts;
+  JacobiBatch jb;
+  size_t rtot = 0, stot = 0;
+  std::vector<size_t> roff(n), soff(n);
+  for (size_t i = 0; i < n; ++i) {
+    int mn = std::min(items[i].rows, items[i].cols);
+    roff[i] = rtot;
+    soff[i] = stot;
+    rtot += (size_t)mn * mn;
+    stot += mn;
+  }
+  double* R = ctx->ws.get<double>(std::max<size_t>(rtot, 1));
+  double* S = ctx->ws.get<double>(std::max<size_t>(stot, 1));
+  for (size_t i = 0; i < n; ++i) {
+    const Item& it = items[i];
+    int mn = std::min(it.rows, it.cols);
+    if (mn == 0) {
+      out[i] = zero;
+      continue;
+    }
+    // ||A||_2 = ||A^T||_2: factor the tall orientation
+    bool tall = it.rows >= it.cols;
+    ts.add(it.A, it.lda, std::max(it.rows, it.cols), mn, !tall, R + roff[i], mn);
+    jb.add(R + roff[i], mn, mn, mn, nullptr, 1, S + soff[i], nullptr, 0.0);
+    out[i] = S + soff[i];
+  }
+  ts.run(ctx);
+  jb.run(ctx);
+  return out;
+}
+
+}  // namespace h2
+
+h2_ctx::~h2_ctx() {
+  for (auto& p : pending) {
+    h2::dev_event_destroy(p.a);
+    h2::dev_event_destroy(p.b);
+  }
+  for (void* e : ev_pool) h2::dev_event_destroy(e);
+  ws.release();
+  for (auto& c : cache) h2::dev_free(c.first);
+  cache.clear();
+  if (stage) h2::dev_free_host(stage);
+  for (void* e : events) h2::dev_event_destroy(e);
+}

@@ -1,0 +1,276 @@
+// Cluster trees, block trees and the product block tree T^XY (host, integer
+// work).  Section 2: Definitions "Cluster tree" and "Block tree"; Section 6:
+// the product block tree and its admissible / inadmissible leaves.
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+
+namespace h2 {
+
+// Median bisection along the longest edge of the tight bounding box (lowest
+// axis on ties), points ordered by (coordinate, original index); the first
+// floor(m/2) points form child 2c+1.  All branches reach the common depth
+// D = min{D >= 0 : leaf_size 2^D >= n}, so every leaf lies on level D.
+std::shared_ptr<TreeH> build_cluster_tree(int dim, int64_t n, const double* pts, int leaf_size) {
+  H2_REQUIRE(dim >= 1 && dim <= 3, H2_ERR_ARG, "dim must be 1, 2 or 3");
+  H2_REQUIRE(n >= 1, H2_ERR_ARG, "n must be positive");
+  H2_REQUIRE(leaf_size >= 2, H2_ERR_ARG, "leaf_size must be >= 2");
+  for (int64_t i = 0; i < n * dim; ++i)
+    H2_REQUIRE(std::isfinite(pts[i]), H2_ERR_NUMERIC, "non-finite point coordinate");
+  auto T = std::make_shared<TreeH>();
+  T->dim = dim;
+  T->n = n;
+  int depth = 0;
+  while ((int64_t)leaf_size << depth < n) ++depth;
+  H2_REQUIRE(depth <= 24, H2_ERR_ARG, "tree too deep");
+  T->depth = depth;
+  int ncl = (2 << depth) - 1;
+  T->ncl = ncl;
+  T->off.assign(ncl, 0);
+  T->size.assign(ncl, 0);
+  T->blo.assign((size_t)ncl * dim, 0);
+  T->bhi.assign((size_t)ncl * dim, 0);
+  std::vector<int64_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  // every cluster is a contiguous range of idx; children ranges stay contiguous
+  T->off[0] = 0;
+  T->size[0] = n;
+  for (int c = 0; c < ncl; ++c) {
+    int64_t o = T->off[c], m = T->size[c];
+    double* lo = &T->blo[(size_t)c * dim];
+    double* hi = &T->bhi[(size_t)c * dim];
+    for (int a = 0; a < dim; ++a) {
+      lo[a] = INFINITY;
+      hi[a] = -INFINITY;
+    }
+    for (int64_t q = 0; q < m; ++q) {
+      const double* p = pts + idx[o + q] * dim;
+      for (int a = 0; a < dim; ++a) {
+        lo[a] = std::min(lo[a], p[a]);
+        hi[a] = std::max(hi[a], p[a]);
+      }
+    }
+    if (TreeH::level(c) < depth) {
+      int ax = 0;
+      double best = hi[0] - lo[0];
+      for (int a = 1; a < dim; ++a)
+        if (hi[a] - lo[a] > best) {
+          best = hi[a] - lo[a];
+          ax = a;
+        }
+      std::sort(idx.begin() + o, idx.begin() + o + m, [&](int64_t i, int64_t j) {
+        double xi = pts[i * dim + ax], xj = pts[j * dim + ax];
+        return xi < xj || (xi == xj && i < j);
+      });
+      int64_t h = m / 2;
+      T->off[2 * c + 1] = o;
+      T->size[2 * c + 1] = h;
+      T->off[2 * c + 2] = o + h;
+      T->size[2 * c + 2] = m - h;
+    }
+  }
+  T->perm = idx;
+  T->pts.resize((size_t)n * dim);
+  for (int64_t p = 0; p < n; ++p)
+    for (int a = 0; a < dim; ++a) T->pts[(size_t)p * dim + a] = pts[idx[p] * dim + a];
+  // interpolation boxes: edges narrower than 1e-12 diam(root) are widened
+  double d0 = 0;
+  for (int a = 0; a < dim; ++a) {
+    double w = T->bhi[a] - T->blo[a];
+    d0 += w * w;
+  }
+  double floor_w = 1e-12 * std::sqrt(d0);
+  T->lo = T->blo;
+  T->hi = T->bhi;
+  for (int c = 0; c < ncl; ++c)
+    for (int a = 0; a < dim; ++a) {
+      double& l = T->lo[(size_t)c * dim + a];
+      double& h = T->hi[(size_t)c * dim + a];
+      if (h - l < floor_w) {
+        double mid = 0.5 * (l + h);
+        l = mid - 0.5 * floor_w;
+        h = mid + 0.5 * floor_w;
+      }
+    }
+  return T;
+}
+
+static double box_diam(const TreeH& T, int c) {
+  double s = 0;
+  for (int a = 0; a < T.dim; ++a) {
+    double w = T.bhi[(size_t)c * T.dim + a] - T.blo[(size_t)c * T.dim + a];
+    s += w * w;
+  }
+  return std::sqrt(s);
+}
+
+static double box_dist(const TreeH& A, int a, const TreeH& B, int b) {
+  double s = 0;
+  for (int q = 0; q < A.dim; ++q) {
+    double g1 = B.blo[(size_t)b * A.dim + q] - A.bhi[(size_t)a * A.dim + q];
+    double g2 = A.blo[(size_t)a * A.dim + q] - B.bhi[(size_t)b * A.dim + q];
+    double g = std::max(0.0, std::max(g1, g2));
+    s += g * g;
+  }
+  return std::sqrt(s);
+}
+
+void BlockTreeH::finalize(int ncl) {
+  int nb = nblocks();
+  row_ptr.assign(ncl + 1, 0);
+  col_ptr.assign(ncl + 1, 0);
+  n_adm = n_inadm = 0;
+  for (int b = 0; b < nb; ++b) {
+    row_ptr[t[b] + 1]++;
+    col_ptr[s[b] + 1]++;
+    n_adm += type[b] == BT_ADM;
+    n_inadm += type[b] == BT_INADM;
+  }
+  for (int c = 0; c < ncl; ++c) {
+    row_ptr[c + 1] += row_ptr[c];
+    col_ptr[c + 1] += col_ptr[c];
+  }
+  row_blk.assign(nb, 0);
+  col_blk.assign(nb, 0);
+  std::vector<int32_t> rp(row_ptr.begin(), row_ptr.end() - 1), cp(col_ptr.begin(), col_ptr.end() - 1);
+  for (int b = 0; b < nb; ++b) {
+    row_blk[rp[t[b]]++] = b;
+    col_blk[cp[s[b]]++] = b;
+  }
+  for (int c = 0; c < ncl; ++c) {
+    std::sort(row_blk.begin() + row_ptr[c], row_blk.begin() + row_ptr[c + 1],
+              [&](int x, int y) { return s[x] < s[y]; });
+    std::sort(col_blk.begin() + col_ptr[c], col_blk.begin() + col_ptr[c + 1],
+              [&](int x, int y) { return t[x] < t[y]; });
+  }
+}
+
+int BlockTreeH::find(int tt, int ss) const {
+  int lo = row_ptr[tt], hi = row_ptr[tt + 1];
+  while (lo < hi) {
+    int mid = (lo + hi) / 2;
+    int v = s[row_blk[mid]];
+    if (v == ss) return row_blk[mid];
+    if (v < ss)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return -1;
+}
+
+// Standard admissibility: dist(t,s) > 0 and max(diam t, diam s) <= eta dist.
+// Refinement from (root, root) stops at admissible blocks and leaf x leaf.
+std::shared_ptr<BlockTreeH> build_block_tree(const TreeH& rt, const TreeH& ct, double eta) {
+  H2_REQUIRE(rt.depth == ct.depth, H2_ERR_SHAPE, "row and column trees differ in depth");
+  auto B = std::make_shared<BlockTreeH>();
+  B->lvl.push_back(0);
+  B->t.push_back(0);
+  B->s.push_back(0);
+  for (int l = 0; l <= rt.depth; ++l) {
+    int b0 = B->lvl[l], b1 = (int)B->t.size();
+    for (int b = b0; b < b1; ++b) {
+      int tt = B->t[b], ss = B->s[b];
+      double dist = box_dist(rt, tt, ct, ss);
+      bool adm = dist > 0.0 && std::max(box_diam(rt, tt), box_diam(ct, ss)) <= eta * dist;
+      if (adm) {
+        B->type.push_back(BT_ADM);
+        B->child0.push_back(-1);
+      } else if (l == rt.depth) {
+        B->type.push_back(BT_INADM);
+        B->child0.push_back(-1);
+      } else {
+        B->type.push_back(BT_SPLIT);
+        B->child0.push_back((int)B->t.size());
+        for (int a = 1; a <= 2; ++a)
+          for (int c = 1; c <= 2; ++c) {
+            B->t.push_back(2 * tt + a);
+            B->s.push_back(2 * ss + c);
+          }
+      }
+    }
+    B->lvl.push_back(b1);
+  }
+  B->finalize(rt.ncl);
+  return B;
+}
+
+// T^XY: (t,r) is subdivided iff some middle s has (t,s) and (s,r) both
+// subdivided; a leaf is admissible iff every middle s has an admissible
+// factor.  The triples (t,s,r) reaching a block are recorded: terminated
+// ones with their kind (both factors admissible, only (t,s), only (s,r),
+// neither).
+ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
+  ProductTreeH P;
+  auto B = std::make_shared<BlockTreeH>();
+  P.bt = B;
+  std::vector<std::vector<int32_t>> mids_cur{{0}}, mids_next;
+  B->lvl.push_back(0);
+  B->t.push_back(0);
+  B->s.push_back(0);
+  int depth = X.m->ct->depth;
+  P.tri_ptr.push_back(0);
+  for (int l = 0; l <= depth; ++l) {
+    int b0 = B->lvl[l], b1 = (int)B->t.size();
+    mids_next.clear();
+    for (int b = b0; b < b1; ++b) {
+      int tt = B->t[b], rr = B->s[b];
+      const auto& mids = mids_cur[b - b0];
+      std::vector<int32_t> rec;
+      bool nn = false;
+      for (int32_t s : mids) {
+        int bx = X.find(tt, s), by = Y.find(s, rr);
+        H2_REQUIRE(bx >= 0 && by >= 0, H2_ERR_SHAPE, "product tree: missing factor block");
+        int8_t tx = X.type(bx), ty = Y.type(by);
+        if (tx == BT_SPLIT && ty == BT_SPLIT) {
+          rec.push_back(s);
+          continue;
+        }
+        int8_t kind;
+        if (tx == BT_ADM && ty == BT_ADM)
+          kind = TK_AA;
+        else if (tx == BT_ADM)
+          kind = TK_AN;
+        else if (ty == BT_ADM)
+          kind = TK_NA;
+        else {
+          H2_REQUIRE(tx == BT_INADM && ty == BT_INADM, H2_ERR_UNSUPPORTED,
+                     "product tree: non-level-aligned factor blocks");
+          kind = TK_NN;
+          nn = true;
+        }
+        P.tri.push_back({s, bx, by, kind});
+        P.n_terminated++;
+      }
+      P.tri_ptr.push_back((int32_t)P.tri.size());
+      if (!rec.empty()) {
+        H2_REQUIRE(!nn, H2_ERR_UNSUPPORTED, "product tree: dense triple above the leaf level");
+        B->type.push_back(BT_SPLIT);
+        B->child0.push_back((int)B->t.size());
+        for (int a = 1; a <= 2; ++a)
+          for (int c = 1; c <= 2; ++c) {
+            int tc = 2 * tt + a, rc = 2 * rr + c;
+            B->t.push_back(tc);
+            B->s.push_back(rc);
+            std::vector<int32_t> sub;
+            for (int32_t s : rec)
+              for (int q = 1; q <= 2; ++q) {
+                int sc = 2 * s + q;
+                if (X.find(tc, sc) >= 0 && Y.find(sc, rc) >= 0) sub.push_back(sc);
+              }
+            mids_next.push_back(std::move(sub));
+          }
+      } else {
+        B->type.push_back(nn ? BT_INADM : BT_ADM);
+        B->child0.push_back(-1);
+      }
+    }
+    B->lvl.push_back(b1);
+    mids_cur.swap(mids_next);
+  }
+  B->finalize(ncl);
+  return P;
+}
+
+}  // namespace h2

@@ -1,0 +1,285 @@
+"""Python binding of the C-ABI in include/h2.h (argument marshalling only).
+
+Every numerical step runs inside libh2.so (HIP kernels for gfx950).  Device
+memory and streams come from PyTorch: vectors and dense outputs are
+``torch.float64`` CUDA tensors, the context runs on
+``torch.cuda.current_stream()``.  If libh2.so is missing the import fails;
+there is no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2.so")
+
+KERNELS = {"log": 0, "expneg": 1, "inv4pi": 2, "inv": 3, "poly2": 100}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+KERNEL_FAMILIES = ["gemm_sum", "tsqr", "jacobi", "build", "other"]
+STEPS = ["setup", "symbolic", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat"]
+
+_c_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"h2 status {code}: {msg}")
+        self.code = code
+
+
+def _declare(lib):
+    sig = {
+        "h2_last_error": (ctypes.c_char_p, []),
+        "h2_ctx_create": (ctypes.c_int, [ctypes.c_int, _c_p, ctypes.POINTER(_c_p)]),
+        "h2_ctx_destroy": (ctypes.c_int, [_c_p]),
+        "h2_tree_build": (ctypes.c_int, [_c_p, ctypes.c_int, _i64, _c_p, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(_c_p), _c_p]),
+        "h2_tree_sizes": (ctypes.c_int, [_c_p, _c_p]),
+        "h2_tree_structure": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+        "h2_compress_kernel": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_c_p)]),
+        "h2_mul_intermediate": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_double, ctypes.c_int,
+                                               _c_p]),
+        "h2_zero_like": (ctypes.c_int, [_c_p, _c_p, ctypes.POINTER(_c_p)]),
+        "h2_recompress": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_double, ctypes.c_int]),
+        "h2_matvec": (ctypes.c_int, [_c_p, _c_p, ctypes.c_char, ctypes.c_double, _c_p, ctypes.c_double, _c_p,
+                                     ctypes.c_int]),
+        "h2_product_matvec": (ctypes.c_int, [_c_p, _c_p, ctypes.c_char, ctypes.c_double, _c_p, ctypes.c_double,
+                                             _c_p, ctypes.c_int]),
+        "h2_to_dense": (ctypes.c_int, [_c_p, _c_p, _c_p, _i64]),
+        "h2_product_to_dense": (ctypes.c_int, [_c_p, _c_p, _c_p, _i64]),
+        "h2_matrix_basis": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int, _c_p, _i64]),
+        "h2_product_basis": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int, _c_p, _i64]),
+        "h2_matrix_ranks": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p]),
+        "h2_product_ranks": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p]),
+        "h2_product_sizes": (ctypes.c_int, [_c_p, _c_p]),
+        "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int]),
+        "h2_profile": (ctypes.c_int, [_c_p, ctypes.c_int]),
+        "h2_kernel_stats": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int]),
+        "h2_tree_destroy": (None, [_c_p]),
+        "h2_matrix_destroy": (None, [_c_p]),
+        "h2_product_destroy": (None, [_c_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return sig
+
+
+_lib = None
+EXPORTS = None
+
+
+def load(path: str | None = None):
+    """Load libh2.so (raises if it has not been built)."""
+    global _lib, EXPORTS
+    if path is None and _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -m paper_2309_09061_amd.build_lib`")
+    lib = ctypes.CDLL(p)
+    EXPORTS = _declare(lib)
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, st):
+    if st != 0:
+        raise H2Error(st, lib.h2_last_error().decode())
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor, or an integer address."""
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+class Context:
+    """h2_ctx on a HIP device (device=-1: host-only, symbolic calls only)."""
+
+    def __init__(self, device: int = 0, stream=None, lib=None):
+        self.lib = lib or load()
+        self.h = _c_p()
+        if stream is None and device >= 0:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        _check(self.lib, self.lib.h2_ctx_create(device, stream or 0, ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            _check(self.lib, self.lib.h2_ctx_destroy(self.h))
+            self.h = _c_p()
+
+    def profile(self, enable: bool = True):
+        _check(self.lib, self.lib.h2_profile(self.h, 1 if enable else 0))
+
+    def kernel_stats(self, reset: bool = False) -> dict:
+        out = {}
+        for kind, name in enumerate(KERNEL_FAMILIES):
+            v = np.zeros(4)
+            _check(self.lib, self.lib.h2_kernel_stats(self.h, kind, v.ctypes.data, 0))
+            out[name] = {"ms": float(v[0]), "launches": int(v[1]), "flops": float(v[2]), "bytes": float(v[3])}
+        if reset:
+            v = np.zeros(4)
+            _check(self.lib, self.lib.h2_kernel_stats(self.h, 0, v.ctypes.data, 1))
+        return out
+
+    def step_times(self) -> dict:
+        out = np.zeros(8)
+        n = self.lib.h2_step_times(self.h, out.ctypes.data, 8)
+        return {STEPS[i]: float(out[i]) for i in range(n)}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    def __init__(self, ctx: Context, points: np.ndarray, leaf_size: int, eta: float):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim == 1:
+            pts = pts[:, None]
+        self.ctx, self.lib = ctx, ctx.lib
+        self.n, self.dim = pts.shape
+        self.perm = np.zeros(self.n, dtype=np.int64)
+        self.h = _c_p()
+        _check(self.lib, self.lib.h2_tree_build(ctx.h, self.dim, self.n, pts.ctypes.data, leaf_size, eta,
+                                                ctypes.byref(self.h), self.perm.ctypes.data))
+        s = np.zeros(7, dtype=np.int64)
+        _check(self.lib, self.lib.h2_tree_sizes(self.h, s.ctypes.data))
+        self.sizes = dict(zip(["n", "dim", "depth", "nclusters", "nblocks", "nadm", "ninadm"], s.tolist()))
+
+    def structure(self):
+        nc, nb = self.sizes["nclusters"], self.sizes["nblocks"]
+        off = np.zeros(nc, np.int64)
+        size = np.zeros(nc, np.int64)
+        br = np.zeros(nb, np.int32)
+        bc = np.zeros(nb, np.int32)
+        bt = np.zeros(nb, np.int8)
+        _check(self.lib, self.lib.h2_tree_structure(self.h, off.ctypes.data, size.ctypes.data, br.ctypes.data,
+                                                    bc.ctypes.data, bt.ctypes.data))
+        return off, size, br, bc, bt
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.h2_tree_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Matrix:
+    def __init__(self, ctx: Context, tree: Tree, handle):
+        self.ctx, self.lib, self.tree, self.h = ctx, ctx.lib, tree, handle
+
+    @classmethod
+    def kernel(cls, ctx: Context, tree: Tree, kernel: str, order: int):
+        h = _c_p()
+        _check(ctx.lib, ctx.lib.h2_compress_kernel(ctx.h, tree.h, KERNELS[kernel], order, ctypes.byref(h)))
+        return cls(ctx, tree, h)
+
+    @classmethod
+    def zero(cls, ctx: Context, tree: Tree):
+        h = _c_p()
+        _check(ctx.lib, ctx.lib.h2_zero_like(ctx.h, tree.h, ctypes.byref(h)))
+        return cls(ctx, tree, h)
+
+    def matvec(self, x, y, alpha=1.0, beta=0.0, op="N"):
+        nvec = 1 if len(x.shape) == 1 else x.shape[1]
+        _check(self.lib, self.lib.h2_matvec(self.ctx.h, self.h, op.encode(), alpha, _ptr(x), beta, _ptr(y), nvec))
+
+    def to_dense(self, out, ld=None):
+        _check(self.lib, self.lib.h2_to_dense(self.ctx.h, self.h, _ptr(out), ld or self.tree.n))
+
+    def ranks(self, which=0):
+        r = np.zeros(self.tree.sizes["nclusters"], np.int32)
+        _check(self.lib, self.lib.h2_matrix_ranks(self.h, which, r.ctypes.data))
+        return r
+
+    def basis(self, which, cluster, out, ld):
+        _check(self.lib, self.lib.h2_matrix_basis(self.ctx.h, self.h, which, cluster, _ptr(out), ld))
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.h2_matrix_destroy(self.h)
+        except Exception:
+            pass
+
+
+class Product:
+    def __init__(self, ctx, tree, handle):
+        self.ctx, self.lib, self.tree, self.h = ctx, ctx.lib, tree, handle
+
+    def matvec(self, x, y, alpha=1.0, beta=0.0, op="N"):
+        nvec = 1 if len(x.shape) == 1 else x.shape[1]
+        _check(self.lib, self.lib.h2_product_matvec(self.ctx.h, self.h, op.encode(), alpha, _ptr(x), beta,
+                                                    _ptr(y), nvec))
+
+    def to_dense(self, out, ld=None):
+        _check(self.lib, self.lib.h2_product_to_dense(self.ctx.h, self.h, _ptr(out), ld or self.tree.n))
+
+    def ranks(self, which=0):
+        r = np.zeros(self.tree.sizes["nclusters"], np.int32)
+        _check(self.lib, self.lib.h2_product_ranks(self.h, which, r.ctypes.data))
+        return r
+
+    def basis(self, which, cluster, out, ld):
+        _check(self.lib, self.lib.h2_product_basis(self.ctx.h, self.h, which, cluster, _ptr(out), ld))
+
+    def sizes(self):
+        s = np.zeros(5, np.int64)
+        _check(self.lib, self.lib.h2_product_sizes(self.h, s.ctypes.data))
+        return dict(zip(["nblocks", "nadm", "ninadm", "triples", "bytes"], s.tolist()))
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.h2_product_destroy(self.h)
+        except Exception:
+            pass
+
+
+def h2_mul_intermediate(ctx: Context, X: Matrix, Y: Matrix, eps: float, precision: str = "fp64") -> Product:
+    h = _c_p()
+    xs = (_c_p * 1)(X.h)
+    ys = (_c_p * 1)(Y.h)
+    gs = (_c_p * 1)()
+    _check(ctx.lib, ctx.lib.h2_mul_intermediate(ctx.h, 1, ctypes.cast(xs, _c_p), ctypes.cast(ys, _c_p), eps,
+                                                PRECISIONS[precision], ctypes.cast(gs, _c_p)))
+    h = _c_p(gs[0])
+    return Product(ctx, X.tree, h)
+
+
+def h2_recompress(ctx: Context, G: Product, Z: Matrix, eps: float, precision: str = "fp64") -> Matrix:
+    gs = (_c_p * 1)(G.h)
+    zs = (_c_p * 1)(Z.h)
+    _check(ctx.lib, ctx.lib.h2_recompress(ctx.h, 1, ctypes.cast(gs, _c_p), ctypes.cast(zs, _c_p), eps,
+                                          PRECISIONS[precision]))
+    return Z
+
+
+def h2_tree_build(ctx: Context, points, leaf_size: int, eta: float) -> Tree:
+    return Tree(ctx, points, leaf_size, eta)
+
+
+def h2_compress_kernel(ctx: Context, tree: Tree, kernel: str, order: int) -> Matrix:
+    return Matrix.kernel(ctx, tree, kernel, order)
+
+
+def h2_zero_like(ctx: Context, tree: Tree) -> Matrix:
+    return Matrix.zero(ctx, tree)

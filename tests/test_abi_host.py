@@ -1,0 +1,75 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every entry point declared in include/h2.h, and
+its host-only symbolic work (cluster tree, block tree) equals the oracle's
+bit for bit.  Error paths return status codes without touching a device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_2309_09061_amd import h2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = h2.load()
+    header = open(os.path.join(ROOT, "include", "h2.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    declared = set(re.findall(r"\b(h2_[a-z_0-9]+)\s*\(", header))
+    assert len(declared) >= 20
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(h2.EXPORTS) == declared
+
+
+@pytest.mark.parametrize("name,n,dim,leaf,eta,dist,seed", [
+    ("c1", 1024, 1, 16, 1.0, "uniform", 1),
+    ("c2", 16384, 2, 64, 1.0, "uniform", 2),
+    ("sph", 8192, 3, 64, 2.0, "sphere", 3),
+    ("ragged", 1000, 2, 24, 1.5, "uniform", 11),
+])
+def test_tree_matches_oracle_bit_exact(name, n, dim, leaf, eta, dist, seed):
+    pts = W.make_points(seed, n, dim, dist)
+    ctx = h2.Context(device=-1)
+    T = h2.Tree(ctx, pts, leaf, eta)
+    ref = O.ClusterTree(pts, leaf)
+    bt = O.BlockTree(ref, ref, eta)
+    assert np.array_equal(T.perm, ref.perm)
+    off, size, br, bc, btype = T.structure()
+    assert np.array_equal(off, ref.off) and np.array_equal(size, ref.size)
+    tmap = {O.SPLIT: 0, O.ADM: 1, O.INADM: 2}
+    got = {(int(a), int(b)): int(c) for a, b, c in zip(br, bc, btype)}
+    assert got == {k: tmap[v] for k, v in bt.type.items()}
+    assert T.sizes["depth"] == ref.depth and T.sizes["nclusters"] == ref.nclusters
+
+
+def test_error_paths_host_only():
+    lib = h2.load()
+    ctx = h2.Context(device=-1)
+    pts = W.make_points(1, 64, 1, "uniform")
+    with pytest.raises(h2.H2Error) as e:
+        h2.Tree(ctx, pts, 1, 1.0)               # leaf_size < 2
+    assert e.value.code == 1
+    with pytest.raises(h2.H2Error) as e:
+        h2.Tree(ctx, pts, 16, -1.0)             # eta <= 0
+    assert e.value.code == 1
+    bad = pts.copy()
+    bad[3, 0] = np.nan
+    with pytest.raises(h2.H2Error) as e:
+        h2.Tree(ctx, bad, 16, 1.0)
+    assert e.value.code == 7
+    T = h2.Tree(ctx, pts, 16, 1.0)
+    with pytest.raises(h2.H2Error) as e:        # device work on a host-only context
+        h2.Matrix.kernel(ctx, T, "log", 3)
+    assert e.value.code == 1
+    out = ctypes.c_void_p()
+    assert lib.h2_ctx_create(-2, None, ctypes.byref(out)) == 1
+    assert lib.h2_tree_sizes(None, None) == 1
+    assert "NULL" in lib.h2_last_error().decode()

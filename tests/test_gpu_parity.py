@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bar for the FP64 form: identical rank profiles in both phases (rank ties at
+eps are absent from these inputs), relative Frobenius error <= 1e-10 for G
+and Z, and the final error against the exact product X Y below eps.
+Bases are compared through their projectors Q Q^*, which are unique.
+"""
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# name: (n, dim, leaf, order, kernel_x, kernel_y, eta, seed, distribution, eps)
+CASES = {
+    "1d": (256, 1, 16, 4, "log", "log", 1.0, 1, "uniform", 1e-8),
+    "2d": (512, 2, 32, 3, "log", "expneg", 1.0, 2, "uniform", 1e-6),
+    "sph": (512, 3, 32, 3, "inv4pi", "inv4pi", 2.0, 3, "sphere", 1e-4),
+    "ragged": (1000, 2, 24, 3, "log", "expneg", 1.5, 11, "uniform", 1e-6),
+    "c1": (1024, 1, 16, 4, "log", "log", 1.0, 1, "uniform", 1e-8),     # the 1-D workload, full size
+    "2d64": (2048, 2, 64, 4, "log", "expneg", 1.0, 2, "uniform", 1e-6),
+}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def _h2():
+    from paper_2309_09061_amd import h2
+    h2.load()
+    return h2
+
+
+@functools.lru_cache(maxsize=None)
+def ctx():
+    return _h2().Context(0)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name, eps=None):
+    n, d, leaf, order, kx, ky, eta, seed, dist, e = CASES[name]
+    eps = e if eps is None else eps
+    pts = W.make_points(seed, n, d, dist)
+    tree, bt, X, Y = O.build_problem(pts, leaf, eta, order, kx, ky)
+    p1, p2 = O.multiply(X, Y, bt, eps)
+    Xd, Yd = X.dense(), Y.dense()
+    return pts, tree, X, Y, p1, p2, Xd, Yd
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_case(name, eps=None):
+    h2 = _h2()
+    n, d, leaf, order, kx, ky, eta, seed, dist, e = CASES[name]
+    eps = e if eps is None else eps
+    _say(f"[gpu] case={name} n={n} eps={eps}: tree + kernel matrices")
+    pts = W.make_points(seed, n, d, dist)
+    c = ctx()
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order)
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    _say(f"[gpu] case={name}: phase 1")
+    G = h2.h2_mul_intermediate(c, X, Y, eps)
+    _say(f"[gpu] case={name}: phase 2")
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    torch.cuda.synchronize()
+    _say(f"[gpu] case={name}: done")
+    return T, X, Y, G, Z
+
+
+def dense_of(obj, n):
+    out = zeros_colmajor(n, n)
+    obj.to_dense(out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def colmajor(a):
+    """A column-major float64 CUDA tensor with the values of the numpy array a."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).T)).cuda().t()
+
+
+def zeros_colmajor(rows, cols):
+    return torch.zeros((cols, rows), dtype=torch.float64, device="cuda").t()
+
+
+def relF(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_kernel_matrix_and_matvec(name):
+    pts, tree, Xo, Yo, _, _, Xd, Yd = oracle_case(name)
+    T, X, Y, _, _ = gpu_case(name)
+    n = tree.n
+    assert np.array_equal(T.perm, tree.perm)
+    assert relF(dense_of(X, n), Xd) < 1e-13
+    assert relF(dense_of(Y, n), Yd) < 1e-13
+    x = colmajor(W.probe_vectors(5, n, 3))
+    y = zeros_colmajor(n, 3)
+    X.matvec(x, y)
+    yt = zeros_colmajor(n, 3)
+    X.matvec(x, yt, op="T")
+    torch.cuda.synchronize()
+    xr = x.cpu().numpy()
+    assert relF(y.cpu().numpy(), Xd @ xr) < 1e-13
+    assert relF(yt.cpu().numpy(), Xd.T @ xr) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_phase1_parity(name):
+    _, tree, _, _, p1, _, _, _ = oracle_case(name)
+    T, _, _, G, _ = gpu_case(name)
+    nc = tree.nclusters
+    assert list(G.ranks(0)) == [p1.row.Q.rank[c] for c in range(nc)]
+    assert list(G.ranks(1)) == [p1.col.Q.rank[c] for c in range(nc)]
+    assert relF(dense_of(G, tree.n), p1.G.dense()) < 1e-10
+    # projectors of the compressed induced bases at the leaves
+    Qf = p1.row.Q.full()
+    for c in tree.leaves[:16]:
+        k = int(G.ranks(0)[c])
+        m = int(tree.size[c])
+        B = zeros_colmajor(m, k)
+        G.basis(0, c, B, m)
+        torch.cuda.synchronize()
+        Bq = B.cpu().numpy()
+        assert np.abs(Bq.T @ Bq - np.eye(k)).max() < 1e-12
+        assert np.abs(Bq @ Bq.T - Qf[c] @ Qf[c].T).max() < 1e-7
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_phase2_parity(name):
+    _, tree, _, _, _, p2, Xd, Yd = oracle_case(name)
+    eps = CASES[name][-1]
+    _, _, _, _, Z = gpu_case(name)
+    nc = tree.nclusters
+    assert list(Z.ranks(0)) == [p2.row.Q.rank[c] for c in range(nc)]
+    assert list(Z.ranks(1)) == [p2.col.Q.rank[c] for c in range(nc)]
+    Zg = dense_of(Z, tree.n)
+    assert relF(Zg, p2.Z.dense()) < 1e-10
+    XY = Xd @ Yd
+    assert np.linalg.norm(Zg - XY, 2) / np.linalg.norm(XY, 2) <= eps
+
+
+def test_exact_without_truncation():
+    """eps = 0: both phases reproduce X Y to rounding."""
+    _, tree, _, _, _, _, Xd, Yd = oracle_case("2d", 0.0)
+    _, _, _, G, Z = gpu_case("2d", 0.0)
+    XY = Xd @ Yd
+    assert relF(dense_of(G, tree.n), XY) < 1e-12
+    assert relF(dense_of(Z, tree.n), XY) < 1e-12
+
+
+def test_workload_2d_full_size():
+    """The 2-D workload at n = 16384 (the benchmarked configuration):
+    rank profiles and sampled products against the stored oracle results."""
+    gold = json.load(open(os.path.join(HERE, "golden", "c2_oracle.json")))
+    h2 = _h2()
+    w = W.C2
+    _say("[gpu] workload c2 n=16384: build")
+    c = ctx()
+    T = h2.Tree(c, w.points(), w.leaf_size, w.eta)
+    X = h2.Matrix.kernel(c, T, w.kernel_x, w.order)
+    Y = h2.Matrix.kernel(c, T, w.kernel_y, w.order)
+    _say("[gpu] workload c2: phase 1")
+    G = h2.h2_mul_intermediate(c, X, Y, w.eps)
+    _say("[gpu] workload c2: phase 2")
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), w.eps)
+    torch.cuda.synchronize()
+    assert list(G.ranks(0)) == gold["ranks_p1_row"]
+    assert list(G.ranks(1)) == gold["ranks_p1_col"]
+    assert list(Z.ranks(0)) == gold["ranks_p2_row"]
+    assert list(Z.ranks(1)) == gold["ranks_p2_col"]
+    idx = np.array(gold["index"])
+    x = colmajor(W.probe_vectors(gold["probe_seed"], w.n, 2))
+    gx, zx = zeros_colmajor(w.n, 2), zeros_colmajor(w.n, 2)
+    G.matvec(x, gx)
+    Z.matvec(x, zx)
+    torch.cuda.synchronize()
+    for got, key in ((gx, "Gx"), (zx, "Zx")):
+        got = got.cpu().numpy()
+        ref = np.array(gold[key])
+        assert np.abs(got[idx] - ref).max() <= 1e-10 * np.min(gold[key + "_norm"])
+        assert np.allclose(np.linalg.norm(got, axis=0), gold[key + "_norm"], rtol=1e-10)
+    # the product against X (Y x) stays within eps
+    ref = np.array(gold["XYx"])
+    assert np.abs(zx.cpu().numpy()[idx] - ref).max() <= w.eps * np.max(gold["XYx_norm"])
