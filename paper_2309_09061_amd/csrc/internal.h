@@ -71,23 +71,6 @@ struct GemmTerm {
   int32_t k, flags;
   double alpha;
 };
-// Householder QR (in place; reflectors below the diagonal, tau[min(m,n)]),
-// R (rrows x n, upper part; zero below) copied to R if non-null.
-struct QrProb {
-  double* A;
-  double* tau;
-  double* R;
-  int64_t lda, ldr;
-  int32_t m, n, rrows, pad;
-};
-// C (m x ncols) <- Q^T C (trans = 1) or Q C (trans = 0), Q = H_0 ... H_{r-1}
-struct ApplyProb {
-  const double* V;
-  const double* tau;
-  double* C;
-  int64_t ldv, ldc;
-  int32_t m, nrefl, ncols, trans;
-};
 // R factor of the tall matrix T (N x m): T = A (transA = 0) or T = A^T where A
 // is m x N column-major (transA = 1).  R (min(N,m) x m, ldr) upper, zero below.
 // zero_cols (nullable device int): columns j < *zero_cols of T are read as 0.
@@ -119,12 +102,11 @@ constexpr int kLdsDoubles = 8000;
 // launchers (descriptor arrays are device pointers)
 void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
                 int prec, void* stream);
-void k_qr(const QrProb* probs, int n, int max_m, int max_n, void* stream);
-void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int max_m, int max_r,
-             void* stream);
-void k_tsqr(const TsqrProb* probs, int n, int max_m, double* scratch, void* stream);
+// slot: doubles of global scratch per workgroup (0: every problem fits in LDS);
+// scratch must then hold slot * min(n, 1024) doubles
+void k_tsqr(const TsqrProb* probs, int n, size_t slot, double* scratch, void* stream);
 void k_jacobi(const JacobiProb* probs, int n, int max_m, double* scratch, void* stream);
-size_t tsqr_scratch_doubles(int max_m);
+size_t tsqr_need_doubles(int m);  // working set of one TSQR problem with m columns
 size_t jacobi_scratch_doubles(int max_m);
 
 // interpolation / kernel evaluation
@@ -347,19 +329,6 @@ struct GemmBatch {
             const double* scale = nullptr, int scale_mode = 0);  // op(A) * I_k
   void run(h2_ctx* ctx);
   bool empty() const { return outs.empty(); }
-};
-struct QrBatch {
-  std::vector<QrProb> p;
-  int max_m = 0, max_n = 0;
-  void add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr, int rrows);
-  void run(h2_ctx* ctx);
-};
-struct ApplyBatch {
-  std::vector<ApplyProb> p;
-  int max_m = 0, max_r = 0;
-  void add(const double* V, int64_t ldv, const double* tau, int m, int nrefl, double* C,
-           int64_t ldc, int ncols, bool trans);
-  void run(h2_ctx* ctx);
 };
 struct TsqrBatch {
   std::vector<TsqrProb> p;

@@ -3,9 +3,6 @@
 //  gemm_sum  grouped variable-size products C = beta C + sum alpha op(A) op(B)
 //            on FP64 MFMA (v_mfma_f64_16x16x4f64), one wavefront per 16x16
 //            output tile, the terms of one output accumulated in registers
-//  qr        Householder QR of small matrices (reflectors kept, LAPACK
-//            conventions: H = I - tau v v^T, v_j = 1)
-//  apply     C <- Q^T C or Q C with the reflectors of qr
 //  tsqr      R factor of tall (or transposed wide) matrices, streamed in row
 //            chunks through a stacked [R; chunk] Householder QR
 //  jacobi    one-sided (Hestenes) Jacobi SVD with round-robin parallel pair
@@ -82,13 +79,14 @@ __global__ __launch_bounds__(256) void gemm_sum_f64(const GemmOut* __restrict__ 
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a * alpha, b, acc, 0, 0, 0);
     }
   }
-  // accumulator layout: register v of lane (r, q) holds D[4q + v][r]
+  // FP64 accumulator layout (measured on gfx950): register v of lane (r, q)
+  // holds D[4v + q][r]
   double* C = (double*)o.C;
   const int jc = j0 + r;
   if (jc < o.n) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ic = i0 + 4 * q + v;
+      const int ic = i0 + 4 * v + q;
       if (ic < o.m) {
         double* p = C + ic + (int64_t)jc * o.ldc;
         *p = o.beta ? *p + acc[v] : acc[v];
@@ -149,81 +147,14 @@ __device__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau,
   }
 }
 
-__global__ __launch_bounds__(256) void qr_kernel(const QrProb* __restrict__ probs) {
-  extern __shared__ double smem[];
-  __shared__ double red[4];
-  const QrProb P = probs[blockIdx.x];
-  const int m = P.m, n = P.n, tid = threadIdx.x;
-  const bool in_lds = (int64_t)m * n <= kLdsDoubles;
-  double* W = in_lds ? smem : P.A;
-  const int64_t ld = in_lds ? m : P.lda;
-  if (in_lds)
-    for (int64_t e = tid; e < (int64_t)m * n; e += 256) W[e] = P.A[(e % m) + (e / m) * P.lda];
-  __syncthreads();
-  householder_qr(W, ld, m, n, P.tau, red);
-  if (in_lds)
-    for (int64_t e = tid; e < (int64_t)m * n; e += 256) P.A[(e % m) + (e / m) * P.lda] = W[e];
-  if (P.R)
-    for (int64_t e = tid; e < (int64_t)P.rrows * n; e += 256) {
-      const int i = (int)(e % P.rrows), c = (int)(e / P.rrows);
-      P.R[i + c * P.ldr] = (i <= c && i < m) ? W[i + c * ld] : 0.0;
-    }
-}
-
-void k_qr(const QrProb* probs, int n, int max_m, int max_n, void* stream) {
-  if (n <= 0) return;
-  size_t lds = (size_t)max_m * max_n <= (size_t)kLdsDoubles ? (size_t)max_m * max_n * 8 : 0;
-  hipLaunchKernelGGL(qr_kernel, dim3(n), dim3(256), lds, (hipStream_t)stream, probs);
-  HIP_OK(hipGetLastError());
-}
-
-// ---------------------------------------------------------------------------
-// apply reflectors: work item = (problem, first column); 64 columns per item
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict__ probs,
-                                                    const int32_t* __restrict__ work) {
-  extern __shared__ double smem[];
-  __shared__ double tau_s[256];
-  const ApplyProb P = probs[work[2 * blockIdx.x]];
-  const int c0 = work[2 * blockIdx.x + 1];
-  const int m = P.m, r = P.nrefl, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const bool in_lds = (int64_t)m * r <= kLdsDoubles;
-  const double* V = in_lds ? smem : P.V;
-  const int64_t ldv = in_lds ? m : P.ldv;
-  if (in_lds)
-    for (int64_t e = tid; e < (int64_t)m * r; e += 256) smem[e] = P.V[(e % m) + (e / m) * P.ldv];
-  for (int e = tid; e < r; e += 256) tau_s[e] = P.tau[e];
-  __syncthreads();
-  const int cend = min(P.ncols, c0 + 64);
-  for (int c = c0 + wave; c < cend; c += 4) {
-    double* C = P.C + (int64_t)c * P.ldc;
-    for (int s = 0; s < r; ++s) {
-      const int jj = P.trans ? s : r - 1 - s;
-      const double t = tau_s[jj];
-      if (t == 0.0) continue;
-      double d = 0.0;
-      for (int i = jj + lane; i < m; i += 64) d += (i == jj ? 1.0 : V[i + jj * ldv]) * C[i];
-      d = wave_sum(d) * t;
-      for (int i = jj + lane; i < m; i += 64) C[i] -= d * (i == jj ? 1.0 : V[i + jj * ldv]);
-    }
-  }
-}
-
-void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int max_m, int max_r,
-             void* stream) {
-  if (nwork <= 0) return;
-  size_t lds = (size_t)max_m * max_r <= (size_t)kLdsDoubles ? (size_t)max_m * max_r * 8 : 0;
-  hipLaunchKernelGGL(apply_kernel, dim3(nwork), dim3(256), lds, (hipStream_t)stream, probs, work);
-  HIP_OK(hipGetLastError());
-}
-
 // ---------------------------------------------------------------------------
 // TSQR: R of T (N x m), chunks of `ch` rows stacked under the running R
 // ---------------------------------------------------------------------------
+// rows per streamed chunk; the working set (m + chunk) x m is not monotone in
+// m, so LDS-or-scratch is decided per problem with tsqr_need_doubles()
 static __host__ __device__ inline int tsqr_chunk(int m) { return m <= 64 ? 64 : 32; }
-size_t tsqr_scratch_doubles(int max_m) {
-  return (size_t)(max_m + tsqr_chunk(max_m)) * max_m;
-}
+static __host__ __device__ inline size_t tsqr_need(int m) { return (size_t)(m + tsqr_chunk(m)) * m; }
+size_t tsqr_need_doubles(int m) { return tsqr_need(m); }
 
 __global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
                                                    double* __restrict__ scratch, size_t slot) {
@@ -235,7 +166,7 @@ __global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ 
     const int m = P.m, N = P.N;
     const int ch = tsqr_chunk(m);
     const int rows_cap = m + ch;
-    const bool in_lds = (int64_t)rows_cap * m <= kLdsDoubles;
+    const bool in_lds = tsqr_need(m) <= (size_t)kLdsDoubles;
     double* B = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
     const int64_t ld = rows_cap;
     int rowsR = 0;
@@ -278,18 +209,12 @@ __global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ 
   }
 }
 
-void k_tsqr(const TsqrProb* probs, int n, int max_m, double* scratch, void* stream) {
+void k_tsqr(const TsqrProb* probs, int n, size_t slot, double* scratch, void* stream) {
   if (n <= 0) return;
-  const int ch = tsqr_chunk(max_m);
-  const bool lds_ok = (int64_t)(max_m + ch) * max_m <= kLdsDoubles;
-  H2_REQUIRE(lds_ok || scratch, H2_ERR_ARG, "tsqr: global scratch missing");
-  const int grid = lds_ok ? n : std::min(n, 1024);
-  size_t lds = lds_ok ? (size_t)(max_m + ch) * max_m * 8 : 0;
-  // problems with small m use LDS even when the largest does not; give them
-  // the full 64 KiB in that case
-  if (!lds_ok) lds = (size_t)kLdsDoubles * 8;
-  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, probs, n,
-                     scratch, tsqr_scratch_doubles(max_m));
+  H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "tsqr: global scratch missing");
+  const int grid = slot == 0 ? n : std::min(n, 1024);
+  const size_t lds = (size_t)kLdsDoubles * 8;
+  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, probs, n, scratch, slot);
   HIP_OK(hipGetLastError());
 }
 

@@ -233,59 +233,6 @@ void GemmBatch::run(h2_ctx* ctx) {
   terms.clear();
 }
 
-void QrBatch::add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr,
-                  int rrows) {
-  if (m <= 0 || n <= 0) return;
-  QrProb q{};
-  q.A = A;
-  q.lda = lda;
-  q.m = m;
-  q.n = n;
-  q.tau = tau;
-  q.R = R;
-  q.ldr = std::max<int64_t>(ldr, 1);
-  q.rrows = rrows;
-  p.push_back(q);
-  max_m = std::max(max_m, m);
-  max_n = std::max(max_n, n);
-}
-void QrBatch::run(h2_ctx* ctx) {
-  if (p.empty()) return;
-  k_qr(upload(ctx, p), (int)p.size(), max_m, max_n, ctx->stream);
-  p.clear();
-  max_m = max_n = 0;
-}
-
-void ApplyBatch::add(const double* V, int64_t ldv, const double* tau, int m, int nrefl, double* C,
-                     int64_t ldc, int ncols, bool trans) {
-  if (m <= 0 || nrefl <= 0 || ncols <= 0) return;
-  ApplyProb a{};
-  a.V = V;
-  a.ldv = ldv;
-  a.tau = tau;
-  a.m = m;
-  a.nrefl = nrefl;
-  a.C = C;
-  a.ldc = ldc;
-  a.ncols = ncols;
-  a.trans = trans ? 1 : 0;
-  p.push_back(a);
-  max_m = std::max(max_m, m);
-  max_r = std::max(max_r, nrefl);
-}
-void ApplyBatch::run(h2_ctx* ctx) {
-  if (p.empty()) return;
-  std::vector<int32_t> work;
-  for (size_t i = 0; i < p.size(); ++i)
-    for (int c = 0; c < p[i].ncols; c += 64) {
-      work.push_back((int32_t)i);
-      work.push_back(c);
-    }
-  k_apply(upload(ctx, p), upload(ctx, work), (int)(work.size() / 2), max_m, max_r, ctx->stream);
-  p.clear();
-  max_m = max_r = 0;
-}
-
 void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, double* R, int64_t ldr,
                     int prec, const int32_t* zero_cols) {
   if (m <= 0) return;
@@ -304,9 +251,13 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
 }
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  size_t slot = tsqr_scratch_doubles(max_m);
-  double* scratch = nullptr;
-  if (slot > (size_t)kLdsDoubles) scratch = ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024));
+  // scratch slot: the largest working set among problems that exceed LDS
+  size_t slot = 0;
+  for (const TsqrProb& t : p) {
+    size_t need = tsqr_need_doubles(t.m);
+    if (need > (size_t)kLdsDoubles) slot = std::max(slot, need);
+  }
+  double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
   double flops = 0, bytes = 0;
   for (const TsqrProb& t : p) {  // Householder QR of an N x m matrix: 2 N m^2 - 2 m^3 / 3
     double N = t.N, m = t.m, r = std::min(N, m);
@@ -315,7 +266,7 @@ void TsqrBatch::run(h2_ctx* ctx) {
   }
   TsqrProb* d = upload(ctx, p);
   LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
-  k_tsqr(d, (int)p.size(), max_m, scratch, ctx->stream);
+  k_tsqr(d, (int)p.size(), slot, scratch, ctx->stream);
   p.clear();
   max_m = 0;
 }
