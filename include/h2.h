@@ -170,8 +170,9 @@ h2_status h2_product_ranks(const h2_product* G, int which, int32_t* out);
  * bytes held by G. */
 h2_status h2_product_sizes(const h2_product* G, int64_t out[5]);
 
-/* Step times (milliseconds, stream events) of the last h2_mul_intermediate /
- * h2_recompress on this context; out[] receives up to n entries in the order
+/* Step times (milliseconds, stream events) since the last h2_mul_intermediate
+ * on this context (which resets them; h2_recompress adds its steps);
+ * out[] receives up to n entries in the order
  *   0 setup, 1 symbolic, 2 phase-1 row, 3 phase-1 col, 4 phase-1 mat (G),
  *   5 phase-2 row, 6 phase-2 col, 7 phase-2 mat (Z).  Returns the count. */
 int h2_step_times(const h2_ctx* ctx, double* out, int n);

@@ -32,9 +32,10 @@ static void need_device(const h2_ctx* ctx) {
   dev_set_device(ctx->device);
 }
 
-static void begin_call(h2_ctx* ctx) {
+static void begin_call(h2_ctx* ctx, bool reset_steps = false) {
   ctx->ws.reset();
-  for (double& v : ctx->step_ms) v = 0.0;
+  if (reset_steps)
+    for (double& v : ctx->step_ms) v = 0.0;
 }
 
 extern "C" {
@@ -157,7 +158,7 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
     H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
     H2_REQUIRE(prec == H2_FP64, H2_ERR_UNSUPPORTED, "FP32 bulk products are not available yet");
     need_device(ctx);
-    begin_call(ctx);
+    begin_call(ctx, true);
     for (int i = 0; i < count; ++i) {
       auto* G = new h2_product();
       try {

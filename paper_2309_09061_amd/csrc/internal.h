@@ -73,6 +73,23 @@ struct GemmTerm {
 };
 // R factor of the tall matrix T (N x m): T = A (transA = 0) or T = A^T where A
 // is m x N column-major (transA = 1).  R (min(N,m) x m, ldr) upper, zero below.
+// Householder QR (in place; reflectors below the diagonal, tau[min(m,n)]),
+// R (rrows x n, upper part; zero below) copied to R if non-null.
+struct QrProb {
+  double* A;
+  double* tau;
+  double* R;
+  int64_t lda, ldr;
+  int32_t m, n, rrows, pad;
+};
+// C (m x ncols) <- Q^T C (trans = 1) or Q C (trans = 0), Q = H_0 ... H_{r-1}
+struct ApplyProb {
+  const double* V;
+  const double* tau;
+  double* C;
+  int64_t ldv, ldc;
+  int32_t m, nrefl, ncols, trans;
+};
 // zero_cols (nullable device int): columns j < *zero_cols of T are read as 0.
 struct TsqrProb {
   const void* A;
@@ -83,31 +100,42 @@ struct TsqrProb {
 };
 // One-sided Jacobi on the m columns of R (p x m, ldr): right singular vectors
 // U (m x m, ldu, columns by descending sigma), sigma[m];
-// rank[0] = #{sigma > max(eps, rtol * sigma_max)}.
+// rank[0] = #{sigma > max(eps, rtol * sigma_max)}.  Columns j < *skip
+// (nullable device int) are zero and take no part in the rotations.
 struct JacobiProb {
   const double* R;
   double* U;     // may be null (values only)
   double* sigma;
   int32_t* rank;
+  const int32_t* skip;
   int64_t ldr, ldu;
   int32_t p, m;
   double eps, rtol;
 };
-
-// dynamic LDS per workgroup of the factorization kernels, in doubles (62.5 KiB;
-// static shared data comes on top).  Working sets larger than this use a
-// global scratch slot per workgroup, which the launch builders allocate.
-constexpr int kLdsDoubles = 8000;
+// block fill: A[i + j ld] = (i == j ? diag : 0) for i < rows, j < cols
+struct FillItem {
+  double* A;
+  int64_t ld;
+  int32_t rows, cols;
+  double diag;
+};
 
 // launchers (descriptor arrays are device pointers)
 void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
                 int prec, void* stream);
-// slot: doubles of global scratch per workgroup (0: every problem fits in LDS);
-// scratch must then hold slot * min(n, 1024) doubles
-void k_tsqr(const TsqrProb* probs, int n, size_t slot, double* scratch, void* stream);
-void k_jacobi(const JacobiProb* probs, int n, int max_m, double* scratch, void* stream);
-size_t tsqr_need_doubles(int m);  // working set of one TSQR problem with m columns
-size_t jacobi_scratch_doubles(int max_m);
+// Factorization launches: lds_doubles is the dynamic LDS of the launch (a
+// problem whose working set fits it runs in LDS), slot the doubles of global
+// scratch per workgroup for the others (0: none); scratch then holds
+// slot * min(n, 1024) doubles.  lds_limit_doubles() is the device maximum.
+int lds_limit_doubles();
+size_t qr_need_doubles(int m, int n);
+size_t tsqr_need_doubles(int m);
+size_t jacobi_need_doubles(int p, int m);
+void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream);
+void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_doubles, void* stream);
+void k_tsqr(const TsqrProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream);
+void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream);
+void k_fill(const FillItem* items, int n, void* stream);
 
 // interpolation / kernel evaluation
 struct ChebLeaf {   // V[i, nu] for leaf cluster c
@@ -141,13 +169,6 @@ struct SumsqItem {
 };
 void k_sumsq(const SumsqItem* items, const int32_t* seg_ptr, int nseg, double* out, int mode,
              void* stream);  // mode 1: out = s > 0 ? 1/sqrt(s) : 0
-// set diagonal: for each item, A[i + i*ld] = 1 for i < count (A must be zeroed)
-struct EyeItem {
-  double* A;
-  int64_t ld;
-  int32_t count, pad;
-};
-void k_eye(const EyeItem* items, int n, void* stream);
 // y (rows x cols, ldy) <- alpha x + beta y (beta = 0 ignores y)
 void k_axpby(int64_t rows, int64_t cols, double alpha, const double* x, int64_t ldx, double beta,
              double* y, int64_t ldy, void* stream);
@@ -330,6 +351,24 @@ struct GemmBatch {
   void run(h2_ctx* ctx);
   bool empty() const { return outs.empty(); }
 };
+struct QrBatch {
+  std::vector<QrProb> p;
+  void add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr, int rrows);
+  void run(h2_ctx* ctx);
+};
+struct ApplyBatch {
+  std::vector<ApplyProb> p;
+  void add(const double* V, int64_t ldv, const double* tau, int m, int nrefl, double* C,
+           int64_t ldc, int ncols, bool trans);
+  void run(h2_ctx* ctx);
+};
+struct FillBatch {
+  std::vector<FillItem> items;
+  void add(double* A, int64_t ld, int rows, int cols, double diag = 0.0) {
+    if (rows > 0 && cols > 0) items.push_back({A, std::max<int64_t>(ld, 1), rows, cols, diag});
+  }
+  void run(h2_ctx* ctx);
+};
 struct TsqrBatch {
   std::vector<TsqrProb> p;
   int max_m = 0;
@@ -341,7 +380,7 @@ struct JacobiBatch {
   std::vector<JacobiProb> p;
   int max_m = 0;
   void add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu, double* sigma,
-           int32_t* rank, double eps, double rtol = 0.0);
+           int32_t* rank, double eps, double rtol = 0.0, const int32_t* skip = nullptr);
   void run(h2_ctx* ctx);
 };
 // sigma_max of many small matrices: tsqr + jacobi (values only); sig[i] = sigma_max

@@ -198,17 +198,6 @@ void k_sumsq(const SumsqItem* items, const int32_t* seg_ptr, int nseg, double* o
   HIP_OK(hipGetLastError());
 }
 
-__global__ void eye_kernel(const EyeItem* items) {
-  const EyeItem I = items[blockIdx.x];
-  for (int i = threadIdx.x; i < I.count; i += blockDim.x) I.A[i + i * I.ld] = 1.0;
-}
-
-void k_eye(const EyeItem* items, int n, void* stream) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(eye_kernel, dim3(n), dim3(64), 0, (hipStream_t)stream, items);
-  HIP_OK(hipGetLastError());
-}
-
 }  // namespace h2
 
 namespace h2 {

@@ -3,13 +3,19 @@
 //  gemm_sum  grouped variable-size products C = beta C + sum alpha op(A) op(B)
 //            on FP64 MFMA (v_mfma_f64_16x16x4f64), one wavefront per 16x16
 //            output tile, the terms of one output accumulated in registers
+//  qr        Householder QR of small matrices, reflectors kept (LAPACK
+//            conventions: H = I - tau v v^T, v_j = 1), R copied out
+//  apply     C <- Q^T C or Q C with the reflectors of qr
 //  tsqr      R factor of tall (or transposed wide) matrices, streamed in row
 //            chunks through a stacked [R; chunk] Householder QR
 //  jacobi    one-sided (Hestenes) Jacobi SVD with round-robin parallel pair
 //            ordering; singular values and right singular vectors of R
+//  fill      batched block fill (zeros with a constant diagonal)
 //
-// Working sets live in LDS when they fit in 64 KiB and otherwise in a
-// per-workgroup slot of global scratch (generic addressing).
+// Working sets live in LDS (up to the device limit, 160 KiB per workgroup on
+// gfx950) and otherwise in a per-workgroup slot of global scratch.  The host
+// passes the LDS capacity of each launch; a problem uses LDS iff its working
+// set fits that capacity, the same predicate the host used to size it.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -17,7 +23,6 @@
 namespace h2 {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
-
 
 #define HIP_OK(x)                                                              \
   do {                                                                         \
@@ -38,8 +43,7 @@ __device__ inline double block_sum(double v, double* red) {
   __syncthreads();
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  double s = red[0] + red[1] + red[2] + red[3];
-  return s;
+  return red[0] + red[1] + red[2] + red[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -108,7 +112,7 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 // Householder QR of one m x n matrix W (ld) by a 256-thread workgroup
 // ---------------------------------------------------------------------------
 __device__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau, double* red) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x;
   const int kmax = m < n ? m : n;
   for (int jj = 0; jj < kmax; ++jj) {
     double s = 0.0;
@@ -136,11 +140,30 @@ __device__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau,
     }
     __syncthreads();
     if (t != 0.0) {
-      for (int c = jj + 1 + wave; c < n; c += 4) {
+      // trailing update: each of the nt columns is owned by a group of tpc
+      // lanes (a power of two dividing 64) that splits its rows and reduces
+      // with log2(tpc) shuffles
+      const int nt = n - jj - 1;
+      int tpc = 64;
+      while (tpc > 1 && tpc * nt > 256) tpc >>= 1;
+      const int grp = tid / tpc, gl = tid % tpc, ngrp = 256 / tpc;
+      const double* v = W + jj * ld;
+      for (int c0 = 0; c0 < nt; c0 += ngrp) {
+        const int c = jj + 1 + c0 + grp;
+        const bool live = c0 + grp < nt;
         double d = 0.0;
-        for (int i = jj + lane; i < m; i += 64) d += (i == jj ? 1.0 : W[i + jj * ld]) * W[i + c * ld];
-        d = wave_sum(d) * t;
-        for (int i = jj + lane; i < m; i += 64) W[i + c * ld] -= d * (i == jj ? 1.0 : W[i + jj * ld]);
+        if (live) {
+          const double* wc = W + c * ld;
+          if (gl == 0) d = wc[jj];
+          for (int i = jj + 1 + gl; i < m; i += tpc) d += v[i] * wc[i];
+        }
+        for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+        if (live) {
+          d *= t;
+          double* wc = W + c * ld;
+          if (gl == 0) wc[jj] -= d;
+          for (int i = jj + 1 + gl; i < m; i += tpc) wc[i] -= d * v[i];
+        }
       }
     }
     __syncthreads();
@@ -148,16 +171,113 @@ __device__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau,
 }
 
 // ---------------------------------------------------------------------------
+// LDS capacity
+// ---------------------------------------------------------------------------
+__global__ void qr_kernel(const QrProb* __restrict__ probs, int lds_cap);
+__global__ void apply_kernel(const ApplyProb* __restrict__ probs, const int32_t* __restrict__ work, int lds_cap);
+__global__ void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
+                            size_t slot, int lds_cap);
+__global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
+                              size_t slot, int lds_cap);
+
+int lds_limit_doubles() {
+  static int limit = -1;
+  if (limit >= 0) return limit;
+  int dev = 0, maxb = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&maxb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxb = 65536;
+  // 2 KiB stay for static shared data
+  int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
+  const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
+                      (const void*)jacobi_kernel};
+  for (const void* k : ks)
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      bytes = std::min(bytes, 64 * 1024 - 2048);
+    }
+  limit = bytes / 8;
+  return limit;
+}
+
+// ---------------------------------------------------------------------------
+// QR with reflectors
+// ---------------------------------------------------------------------------
+size_t qr_need_doubles(int m, int n) { return (size_t)m * n; }
+
+__global__ __launch_bounds__(256) void qr_kernel(const QrProb* __restrict__ probs, int lds_cap) {
+  extern __shared__ double smem[];
+  __shared__ double red[4];
+  const QrProb P = probs[blockIdx.x];
+  const int m = P.m, n = P.n, tid = threadIdx.x;
+  const bool in_lds = (int64_t)m * n <= lds_cap;
+  double* W = in_lds ? smem : P.A;
+  const int64_t ld = in_lds ? m : P.lda;
+  if (in_lds)
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) W[e] = P.A[(e % m) + (e / m) * P.lda];
+  __syncthreads();
+  householder_qr(W, ld, m, n, P.tau, red);
+  if (in_lds)
+    for (int64_t e = tid; e < (int64_t)m * n; e += 256) P.A[(e % m) + (e / m) * P.lda] = W[e];
+  if (P.R)
+    for (int64_t e = tid; e < (int64_t)P.rrows * n; e += 256) {
+      const int i = (int)(e % P.rrows), c = (int)(e / P.rrows);
+      P.R[i + c * P.ldr] = (i <= c && i < m) ? W[i + c * ld] : 0.0;
+    }
+}
+
+void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(qr_kernel, dim3(n), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream, probs,
+                     lds_doubles);
+  HIP_OK(hipGetLastError());
+}
+
+// work item = (problem, first column); 64 columns per item
+__global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict__ probs,
+                                                    const int32_t* __restrict__ work, int lds_cap) {
+  extern __shared__ double smem[];
+  __shared__ double tau_s[256];
+  const ApplyProb P = probs[work[2 * blockIdx.x]];
+  const int c0 = work[2 * blockIdx.x + 1];
+  const int m = P.m, r = P.nrefl, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const bool in_lds = (int64_t)m * r <= lds_cap;
+  const double* V = in_lds ? smem : P.V;
+  const int64_t ldv = in_lds ? m : P.ldv;
+  if (in_lds)
+    for (int64_t e = tid; e < (int64_t)m * r; e += 256) smem[e] = P.V[(e % m) + (e / m) * P.ldv];
+  for (int e = tid; e < r; e += 256) tau_s[e] = P.tau[e];
+  __syncthreads();
+  const int cend = min(P.ncols, c0 + 64);
+  for (int c = c0 + wave; c < cend; c += 4) {
+    double* C = P.C + (int64_t)c * P.ldc;
+    for (int s = 0; s < r; ++s) {
+      const int jj = P.trans ? s : r - 1 - s;
+      const double t = tau_s[jj];
+      if (t == 0.0) continue;
+      double d = 0.0;
+      for (int i = jj + lane; i < m; i += 64) d += (i == jj ? 1.0 : V[i + jj * ldv]) * C[i];
+      d = wave_sum(d) * t;
+      for (int i = jj + lane; i < m; i += 64) C[i] -= d * (i == jj ? 1.0 : V[i + jj * ldv]);
+    }
+  }
+}
+
+void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_doubles, void* stream) {
+  if (nwork <= 0) return;
+  hipLaunchKernelGGL(apply_kernel, dim3(nwork), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream,
+                     probs, work, lds_doubles);
+  HIP_OK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // TSQR: R of T (N x m), chunks of `ch` rows stacked under the running R
 // ---------------------------------------------------------------------------
-// rows per streamed chunk; the working set (m + chunk) x m is not monotone in
-// m, so LDS-or-scratch is decided per problem with tsqr_need_doubles()
 static __host__ __device__ inline int tsqr_chunk(int m) { return m <= 64 ? 64 : 32; }
 static __host__ __device__ inline size_t tsqr_need(int m) { return (size_t)(m + tsqr_chunk(m)) * m; }
 size_t tsqr_need_doubles(int m) { return tsqr_need(m); }
 
 __global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
-                                                   double* __restrict__ scratch, size_t slot) {
+                                                   double* __restrict__ scratch, size_t slot, int lds_cap) {
   extern __shared__ double smem[];
   __shared__ double red[4];
   const int tid = threadIdx.x;
@@ -166,7 +286,7 @@ __global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ 
     const int m = P.m, N = P.N;
     const int ch = tsqr_chunk(m);
     const int rows_cap = m + ch;
-    const bool in_lds = tsqr_need(m) <= (size_t)kLdsDoubles;
+    const bool in_lds = tsqr_need(m) <= (size_t)lds_cap;
     double* B = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
     const int64_t ld = rows_cap;
     int rowsR = 0;
@@ -209,22 +329,23 @@ __global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ 
   }
 }
 
-void k_tsqr(const TsqrProb* probs, int n, size_t slot, double* scratch, void* stream) {
+void k_tsqr(const TsqrProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream) {
   if (n <= 0) return;
   H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "tsqr: global scratch missing");
   const int grid = slot == 0 ? n : std::min(n, 1024);
-  const size_t lds = (size_t)kLdsDoubles * 8;
-  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, probs, n, scratch, slot);
+  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream, probs,
+                     n, scratch, slot, lds_doubles);
   HIP_OK(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
-// one-sided Jacobi SVD of R (p x m): columns rotated until orthogonal
+// one-sided Jacobi SVD of R (p x m): columns rotated until orthogonal;
+// columns below *skip (all zero) take no part in the rotations
 // ---------------------------------------------------------------------------
-size_t jacobi_scratch_doubles(int max_m) { return (size_t)2 * max_m * max_m + 2 * max_m; }
+size_t jacobi_need_doubles(int p, int m) { return (size_t)p * m + (size_t)m * m + 2 * (size_t)m; }
 
 __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
-                                                     double* __restrict__ scratch, size_t slot) {
+                                                     double* __restrict__ scratch, size_t slot, int lds_cap) {
   extern __shared__ double smem[];
   __shared__ int rotated;
   const int tid = threadIdx.x;
@@ -235,20 +356,23 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
       if (tid == 0 && P.rank) *P.rank = 0;
       continue;
     }
-    const bool in_lds = (int64_t)p * m + (int64_t)m * m + 2 * m <= kLdsDoubles;
+    const bool in_lds = (size_t)p * m + (size_t)m * m + 2 * (size_t)m <= (size_t)lds_cap;
     double* G = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
     double* U = G + (size_t)p * m;
     double* nrm = U + (size_t)m * m;
     for (int e = tid; e < p * m; e += 256) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
     for (int e = tid; e < m * m; e += 256) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
     __syncthreads();
-    const int mm = m + (m & 1);          // players of the round-robin tournament
+    const int s0 = P.skip ? min(max(*P.skip, 0), m) : 0;
+    const int me = m - s0;                // active columns s0..m-1
+    const int mm = me + (me & 1);         // players of the round-robin tournament
     const int npairs = mm / 2;
     const int gsz = npairs >= 64 ? 4 : (npairs >= 32 ? 8 : (npairs >= 16 ? 16 : (npairs >= 8 ? 32 : 64)));
     const int groups = 256 / gsz;
     const int g = tid / gsz, gl = tid % gsz;
-    const double tol = 1e-15;
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    // rotate while |a.b| exceeds the rounding level of a length-p dot product
+    const double tol = fmax(1e-15, 2.2e-16 * p);
+    for (int sweep = 0; sweep < 40 && me > 1; ++sweep) {
       if (tid == 0) rotated = 0;
       __syncthreads();
       for (int rnd = 0; rnd < mm - 1; ++rnd) {
@@ -261,7 +385,9 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
             a = (rnd + pk) % (mm - 1);
             b = (rnd - pk + (mm - 1)) % (mm - 1);
           }
-          const bool live = a < m && b < m;
+          const bool live = a < me && b < me;
+          a += s0;
+          b += s0;
           double al = 0.0, be = 0.0, ga = 0.0;
           if (live) {
             const double* ga_ = G + (size_t)a * p;
@@ -336,15 +462,34 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
   }
 }
 
-void k_jacobi(const JacobiProb* probs, int n, int max_m, double* scratch, void* stream) {
+void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream) {
   if (n <= 0) return;
-  const bool lds_ok = (size_t)2 * max_m * max_m + 2 * max_m <= (size_t)kLdsDoubles;
-  H2_REQUIRE(lds_ok || scratch, H2_ERR_ARG, "jacobi: global scratch missing");
-  const int grid = lds_ok ? n : std::min(n, 1024);
-  const size_t lds = (size_t)kLdsDoubles * 8;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, probs, n,
-                     scratch, jacobi_scratch_doubles(max_m));
+  H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "jacobi: global scratch missing");
+  const int grid = slot == 0 ? n : std::min(n, 1024);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream,
+                     probs, n, scratch, slot, lds_doubles);
   HIP_OK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// batched block fill: A[i + j ld] = (i == j ? diag : 0)
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(const FillItem* __restrict__ items) {
+  const FillItem I = items[blockIdx.y];
+  const int64_t total = (int64_t)I.rows * I.cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % I.rows, j = e / I.rows;
+    I.A[i + j * I.ld] = i == j ? I.diag : 0.0;
+  }
+}
+
+void k_fill(const FillItem* items, int n, void* stream) {
+  if (n <= 0) return;
+  for (int y0 = 0; y0 < n; y0 += 65535) {
+    const int ny = std::min(65535, n - y0);
+    hipLaunchKernelGGL(fill_kernel, dim3(4, ny), dim3(256), 0, (hipStream_t)stream, items + y0);
+    HIP_OK(hipGetLastError());
+  }
 }
 
 }  // namespace h2

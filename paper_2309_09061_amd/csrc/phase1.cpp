@@ -62,7 +62,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
   // ---- basis weights of W_Y (bottom-up thin QR) ----
   std::vector<double*> RY(ncl);
   std::vector<int> lY(ncl);
-  for (int c = 0; c < ncl; ++c) RY[c] = zeros(ctx, ws, (size_t)k * k);
+  for (int c = 0; c < ncl; ++c) RY[c] = ws.get<double>((size_t)k * k);  // rows < lY[c] are written
   {
     TsqrBatch ts;
     for (int c = T.first(D); c < ncl; ++c) {
@@ -194,7 +194,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
     const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
     const bool leaf = l == D;
     std::vector<int> rows(nc), ncols(nc), kk1(nc);
-    std::vector<double*> Bt(nc), Vr(nc), VXw(nc), RX(nc), Rt(nc), U(nc), sg(nc);
+    std::vector<double*> Bt(nc), Vr(nc), VXw(nc), Rt(nc), U(nc), sg(nc);
     std::vector<std::vector<int>> offs(nc);
     // (a) the blocks X|_{t x s} V_{Y,s} (leaf) or Ahat_{t,s} (non-leaf), the V_X part
     for (int i = 0; i < nc; ++i) {
@@ -253,20 +253,22 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       }
     }
     std::vector<const double*> ns = nrm.run(ctx);
-    // (c) scaled remainder blocks X V_Y Z_s^* / ||.|| and the SVD of the V_X
-    //     part: U1 (m x m) with the numerical range of V_X in its first k1
-    //     columns (k1 = #{sigma > 1e-12 sigma_max})
+    // (c) scaled remainder blocks X V_Y Z_s^* / ||.||, and the numerical range
+    //     of V_X: SVD V_X = U S V'^* from the k x k R factor of V_X, then the
+    //     Householder QR of Y = V_X V' (columns by descending sigma), whose
+    //     orthogonal factor Q_X has the dominant k1 directions (k1 =
+    //     #{sigma > 1e-12 sigma_max}) in its first k1 columns
     TsqrBatch ts;
     JacobiBatch jb;
     int32_t* rk = ws.get<int32_t>(2 * nc);  // [k1 | k2] per cluster
     dev_zero(rk, sizeof(int32_t) * 2 * nc, ctx->stream);
-    std::vector<double*> U1(nc), W1(nc);
+    std::vector<double*> Rv(nc), Vp(nc), Yq(nc), tau(nc), RYq(nc);
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, m = rows[i];
       int nco = 0;
       for (int b : Cb[t]) nco += zr[X.vcol(b)];
       ncols[i] = nco;
-      Vr[i] = ws.get<double>((size_t)std::max(m, 1) * std::max(nco, 1));
+      Vr[i] = ws.get<double>((size_t)m * std::max(nco, 1));
       int col = 0;
       for (size_t j = 0; j < Cb[t].size(); ++j) {
         int s = X.vcol(Cb[t][j]);
@@ -276,41 +278,50 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
         col += zr[s];
       }
       int p1 = std::min(k, m);
-      RX[i] = zeros(ctx, ws, (size_t)m * m);   // R factor of V_X^* (p1 x m)
-      U1[i] = ws.get<double>((size_t)m * m);
-      sg[i] = ws.get<double>(m);
-      ts.add(VXw[i], m, k, m, true, RX[i], m);
-      jb.add(RX[i], m, p1, m, U1[i], m, sg[i], rk + i, 0.0, kVxRtol);
+      Rv[i] = ws.get<double>((size_t)k * k);
+      Vp[i] = ws.get<double>((size_t)k * k);
+      sg[i] = ws.get<double>(k);
+      ts.add(VXw[i], m, m, k, false, Rv[i], k);
+      jb.add(Rv[i], k, p1, k, Vp[i], k, sg[i], rk + i, 0.0, kVxRtol);
     }
     g.run(ctx);
     ts.run(ctx);
     jb.run(ctx);
-    // (d) remainder: rows k1.. of U1^* [blocks], SVD on the masked matrix
+    QrBatch qr;
     for (int i = 0; i < nc; ++i) {
       int m = rows[i];
-      W1[i] = ws.get<double>((size_t)m * std::max(ncols[i], 1));
-      if (ncols[i] > 0) {
-        g.out(W1[i], m, m, ncols[i]);
-        g.term(U1[i], m, true, Vr[i], m, false, m);
-      }
+      Yq[i] = ws.get<double>((size_t)m * k);
+      tau[i] = ws.get<double>(k);
+      RYq[i] = ws.get<double>((size_t)k * k);
+      g.out(Yq[i], m, m, k);
+      g.term(VXw[i], m, false, Vp[i], k, false, k);
+      qr.add(Yq[i], m, m, k, tau[i], RYq[i], k, std::min(m, k));
     }
     g.run(ctx);
+    qr.run(ctx);
+    // (d) remainder: Q_X^* [blocks] with the first k1 rows masked, its SVD
+    ApplyBatch ap;
+    for (int i = 0; i < nc; ++i)
+      ap.add(Yq[i], rows[i], tau[i], rows[i], std::min(rows[i], k), Vr[i], rows[i], ncols[i], true);
+    ap.run(ctx);
     for (int i = 0; i < nc; ++i) {
       int m = rows[i];
       int p = std::min(ncols[i], m);
-      Rt[i] = zeros(ctx, ws, (size_t)m * m);
+      Rt[i] = ws.get<double>((size_t)m * m);
       U[i] = ws.get<double>((size_t)m * m);
       double* sg2 = ws.get<double>(m);
-      ts.add(W1[i], m, ncols[i], m, true, Rt[i], m, 0, rk + i);
-      jb.add(Rt[i], m, p, m, U[i], m, sg2, rk + nc + i, eps);
+      ts.add(Vr[i], m, ncols[i], m, true, Rt[i], m, 0, rk + i);
+      jb.add(Rt[i], m, p, m, U[i], m, sg2, rk + nc + i, eps, 0.0, rk + i);
     }
     ts.run(ctx);
     jb.run(ctx);
     std::vector<int32_t> kk(2 * nc);
     dev_d2h(kk.data(), rk, sizeof(int32_t) * 2 * nc, ctx->stream);
     ctx_sync(ctx);
-    // (e) Q_t = [U1(:, 1:k1), U1 U2(:, 1:k2)], transfers, A_{t,s} = Q_t^* (...), [R_X; 0]
+    // (e) Q_t = Q_X [I 0; 0 U2(:, 1:k2)], transfers, A_{t,s} = Q_t^* (...),
+    //     [R_X; 0] with R_X = (R_Y V'^*)(1:k1, :)
     std::vector<double*> Qn(nc);
+    FillBatch fb;
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, m = rows[i];
       kk1[i] = kk[i];
@@ -320,16 +331,20 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       out.Q.rank[t] = kt;
       out.k1[t] = kk1[i];
       Qn[i] = keep.get<double>((size_t)m * kt);
-      if (kk1[i] > 0) {
-        g.out(Qn[i], m, m, kk1[i]);
-        g.copy(U1[i], m, false, kk1[i]);
-      }
+      fb.add(Qn[i], m, m, kt, 1.0);
+    }
+    fb.run(ctx);
+    for (int i = 0; i < nc; ++i) {
+      int m = rows[i], k2 = out.Q.rank[c0 + i] - kk1[i];
       if (k2 > 0) {
         g.out(Qn[i] + (size_t)kk1[i] * m, m, m, k2);
-        g.term(U1[i], m, false, U[i], m, false, m);
+        g.copy(U[i], m, false, k2);
       }
     }
     g.run(ctx);
+    for (int i = 0; i < nc; ++i)
+      ap.add(Yq[i], rows[i], tau[i], rows[i], std::min(rows[i], k), Qn[i], rows[i], out.Q.rank[c0 + i], false);
+    ap.run(ctx);
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, m = rows[i], kt = out.Q.rank[t];
       if (leaf) {
@@ -347,11 +362,10 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
         g.out(out.A[t], kt, kt, k * nC);
         g.term(Qn[i], m, true, Bt[i], m, false, m);
       }
-      out.RXP[t] = zeros(ctx, ws, (size_t)kt * k);
-      if (kk1[i] > 0) {
-        g.out(out.RXP[t], kt, kk1[i], k);
-        g.term(U1[i], m, true, VXw[i], m, false, m);
-      }
+      out.RXP[t] = ws.get<double>((size_t)kt * k);
+      g.out(out.RXP[t], kt, kk1[i], k);
+      g.term(RYq[i], k, false, Vp[i], k, true, k);
+      g.out(out.RXP[t] + kk1[i], kt, kt - kk1[i], k);  // zero rows below R_X
     }
     g.run(ctx);
   }

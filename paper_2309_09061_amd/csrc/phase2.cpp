@@ -341,7 +341,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
     for (int i = 0; i < nc; ++i) {
       if (m[i] == 0) continue;
       int p = std::min(ncols[i], m[i]);
-      Rt[i] = zeros(ctx, ws, (size_t)m[i] * m[i]);
+      Rt[i] = ws.get<double>((size_t)m[i] * m[i]);  // rows < p are written
       U[i] = ws.get<double>((size_t)m[i] * m[i]);
       sg[i] = ws.get<double>(m[i]);
       ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);

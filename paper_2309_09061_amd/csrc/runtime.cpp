@@ -210,11 +210,18 @@ void GemmBatch::run(h2_ctx* ctx) {
     terms.clear();
     return;
   }
-  std::vector<GemmTerm> tt = terms;
-  if (tt.empty()) tt.push_back(GemmTerm{});
-  GemmOut* d_o = upload(ctx, outs);
-  GemmTerm* d_t = upload(ctx, tt);
-  int32_t* d_tiles = upload(ctx, tiles);
+  // one upload for outputs, terms and tiles
+  const size_t so = outs.size() * sizeof(GemmOut), st = std::max<size_t>(terms.size(), 1) * sizeof(GemmTerm);
+  const size_t sti = tiles.size() * sizeof(int32_t);
+  const size_t o_t = (so + 255) & ~(size_t)255, o_ti = o_t + ((st + 255) & ~(size_t)255);
+  std::vector<char> blob(o_ti + sti, 0);
+  std::memcpy(blob.data(), outs.data(), so);
+  if (!terms.empty()) std::memcpy(blob.data() + o_t, terms.data(), terms.size() * sizeof(GemmTerm));
+  std::memcpy(blob.data() + o_ti, tiles.data(), sti);
+  char* dev = (char*)upload_bytes(ctx, blob.data(), blob.size());
+  GemmOut* d_o = (GemmOut*)dev;
+  GemmTerm* d_t = (GemmTerm*)(dev + o_t);
+  int32_t* d_tiles = (int32_t*)(dev + o_ti);
   // algorithmic work: 2 m n k per term; bytes: operands read once, C written
   double flops = 0, bytes = 0;
   const double es = prec ? 4.0 : 8.0;
@@ -233,6 +240,90 @@ void GemmBatch::run(h2_ctx* ctx) {
   terms.clear();
 }
 
+void QrBatch::add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr, int rrows) {
+  if (m <= 0 || n <= 0) return;
+  QrProb q{};
+  q.A = A;
+  q.lda = std::max<int64_t>(lda, 1);
+  q.m = m;
+  q.n = n;
+  q.tau = tau;
+  q.R = R;
+  q.ldr = std::max<int64_t>(ldr, 1);
+  q.rrows = rrows;
+  p.push_back(q);
+}
+
+// dynamic LDS of a launch: the largest working set that fits the device limit
+static int lds_for(size_t largest_fitting) { return (int)std::max<size_t>(largest_fitting, 1); }
+
+void QrBatch::run(h2_ctx* ctx) {
+  if (p.empty()) return;
+  const size_t lim = (size_t)lds_limit_doubles();
+  size_t lds = 0;
+  double flops = 0, bytes = 0;
+  for (const QrProb& q : p) {
+    size_t need = qr_need_doubles(q.m, q.n);
+    if (need <= lim) lds = std::max(lds, need);
+    double m = q.m, n = q.n, r = std::min(m, n);
+    flops += 2.0 * m * n * r - (m + n) * r * r + 2.0 * r * r * r / 3.0;
+    bytes += 16.0 * m * n;
+  }
+  QrProb* d = upload(ctx, p);
+  LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
+  k_qr(d, (int)p.size(), lds_for(lds), ctx->stream);
+  p.clear();
+}
+
+void ApplyBatch::add(const double* V, int64_t ldv, const double* tau, int m, int nrefl, double* C,
+                     int64_t ldc, int ncols, bool trans) {
+  if (m <= 0 || nrefl <= 0 || ncols <= 0) return;
+  ApplyProb a{};
+  a.V = V;
+  a.ldv = std::max<int64_t>(ldv, 1);
+  a.tau = tau;
+  a.m = m;
+  a.nrefl = nrefl;
+  a.C = C;
+  a.ldc = std::max<int64_t>(ldc, 1);
+  a.ncols = ncols;
+  a.trans = trans ? 1 : 0;
+  p.push_back(a);
+}
+
+void ApplyBatch::run(h2_ctx* ctx) {
+  if (p.empty()) return;
+  const size_t lim = (size_t)lds_limit_doubles();
+  size_t lds = 0;
+  std::vector<int32_t> work;
+  double flops = 0, bytes = 0;
+  for (size_t i = 0; i < p.size(); ++i) {
+    size_t need = (size_t)p[i].m * p[i].nrefl;
+    if (need <= lim) lds = std::max(lds, need);
+    for (int c = 0; c < p[i].ncols; c += 64) {
+      work.push_back((int32_t)i);
+      work.push_back(c);
+    }
+    flops += 4.0 * p[i].m * p[i].nrefl * p[i].ncols;
+    bytes += 16.0 * p[i].m * p[i].ncols;
+  }
+  ApplyProb* d = upload(ctx, p);
+  int32_t* w = upload(ctx, work);
+  LaunchTimer lt(ctx, KK_OTHER, flops, bytes);
+  k_apply(d, w, (int)(work.size() / 2), lds_for(lds), ctx->stream);
+  p.clear();
+}
+
+void FillBatch::run(h2_ctx* ctx) {
+  if (items.empty()) return;
+  double bytes = 0;
+  for (const FillItem& f : items) bytes += 8.0 * f.rows * f.cols;
+  FillItem* d = upload(ctx, items);
+  LaunchTimer lt(ctx, KK_OTHER, 0.0, bytes);
+  k_fill(d, (int)items.size(), ctx->stream);
+  items.clear();
+}
+
 void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, double* R, int64_t ldr,
                     int prec, const int32_t* zero_cols) {
   if (m <= 0) return;
@@ -249,13 +340,18 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
   p.push_back(t);
   max_m = std::max(max_m, m);
 }
+
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  // scratch slot: the largest working set among problems that exceed LDS
-  size_t slot = 0;
+  // per problem: LDS if its working set fits the device limit, else a scratch slot
+  const size_t lim = (size_t)lds_limit_doubles();
+  size_t slot = 0, lds = 0;
   for (const TsqrProb& t : p) {
     size_t need = tsqr_need_doubles(t.m);
-    if (need > (size_t)kLdsDoubles) slot = std::max(slot, need);
+    if (need > lim)
+      slot = std::max(slot, need);
+    else
+      lds = std::max(lds, need);
   }
   double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
   double flops = 0, bytes = 0;
@@ -266,13 +362,13 @@ void TsqrBatch::run(h2_ctx* ctx) {
   }
   TsqrProb* d = upload(ctx, p);
   LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
-  k_tsqr(d, (int)p.size(), slot, scratch, ctx->stream);
+  k_tsqr(d, (int)p.size(), lds_for(lds), slot, scratch, ctx->stream);
   p.clear();
   max_m = 0;
 }
 
 void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu,
-                      double* sigma, int32_t* rank, double eps, double rtol) {
+                      double* sigma, int32_t* rank, double eps, double rtol, const int32_t* skip) {
   JacobiProb j{};
   j.R = R;
   j.ldr = std::max<int64_t>(ldr, 1);
@@ -284,23 +380,30 @@ void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, in
   j.rank = rank;
   j.eps = eps;
   j.rtol = rtol;
+  j.skip = skip;
   p.push_back(j);
   max_m = std::max(max_m, m);
 }
+
 void JacobiBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  size_t slot = jacobi_scratch_doubles(std::max(max_m, 1));
-  double* scratch = nullptr;
-  if (slot > (size_t)kLdsDoubles) scratch = ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024));
+  const size_t lim = (size_t)lds_limit_doubles();
+  size_t slot = 0, lds = 0;
   double flops = 0, bytes = 0;
-  for (const JacobiProb& j : p) {  // one sweep of one-sided Jacobi over m columns of length p
-    double m = j.m, pp = j.p;
+  for (const JacobiProb& j : p) {
+    size_t need = jacobi_need_doubles(j.p, j.m);
+    if (need > lim)
+      slot = std::max(slot, need);
+    else
+      lds = std::max(lds, need);
+    double m = j.m, pp = j.p;  // one sweep of one-sided Jacobi over m columns of length p
     flops += m * (m - 1) / 2 * (6.0 * pp + 6.0 * m);
     bytes += 8.0 * (pp * m + m * m);
   }
+  double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
   JacobiProb* d = upload(ctx, p);
   LaunchTimer lt(ctx, KK_JACOBI, flops, bytes);
-  k_jacobi(d, (int)p.size(), max_m, scratch, ctx->stream);
+  k_jacobi(d, (int)p.size(), lds_for(lds), slot, scratch, ctx->stream);
   p.clear();
   max_m = 0;
 }
