@@ -90,18 +90,25 @@ struct ApplyProb {
   int64_t ldv, ldc;
   int32_t m, nrefl, ncols, trans;
 };
-// zero_cols (nullable device int): columns j < *zero_cols of T are read as 0.
+// R factor of T (N x m; T(i, j) = A[i + j lda], or A[j + i lda] if transA),
+// restricted to the columns off..m-1, off = *col_off (nullable device int, 0
+// if null): the top-left corner of R (min(N, m) x m region, zeros elsewhere)
+// holds a factor F with F^T F = T'^T T', T' = T(:, off:): upper triangular
+// (m - off) x (m - off) if N > m - off, else T' itself (N rows).
 struct TsqrProb {
   const void* A;
   double* R;
-  const int32_t* zero_cols;
+  const int32_t* col_off;
   int64_t lda, ldr;
   int32_t N, m, transA, prec;  // prec 1: A holds float
 };
-// One-sided Jacobi on the m columns of R (p x m, ldr): right singular vectors
-// U (m x m, ldu, columns by descending sigma), sigma[m];
-// rank[0] = #{sigma > max(eps, rtol * sigma_max)}.  Columns j < *skip
-// (nullable device int) are zero and take no part in the rotations.
+// One-sided Jacobi SVD of R (p x m, ldr): sigma[m] (descending, zero padded),
+// U (m x m, ldu, nullable) right singular vectors by descending sigma,
+// rank[0] = #{sigma > max(eps, rtol * sigma_max)} (nullable).  s0 = *skip
+// (nullable device int).  mode 0: R's columns < s0 are zero; all m vectors.
+// mode 1: R holds the factor of the columns s0..m-1 only (as written by a
+// TsqrProb with col_off = skip); vectors carry s0 leading zeros and exist for
+// the nonzero singular values only (the other columns of U are zero).
 struct JacobiProb {
   const double* R;
   double* U;     // may be null (values only)
@@ -109,7 +116,7 @@ struct JacobiProb {
   int32_t* rank;
   const int32_t* skip;
   int64_t ldr, ldu;
-  int32_t p, m;
+  int32_t p, m, mode, pad;
   double eps, rtol;
 };
 // block fill: A[i + j ld] = (i == j ? diag : 0) for i < rows, j < cols
@@ -127,13 +134,16 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 // problem whose working set fits it runs in LDS), slot the doubles of global
 // scratch per workgroup for the others (0: none); scratch then holds
 // slot * min(n, 1024) doubles.  lds_limit_doubles() is the device maximum.
+// TSQR sizes its row chunks from the device maximum: a problem runs in LDS
+// iff tsqr_lds_need(m, limit) > 0, and lds_doubles must cover that need.
 int lds_limit_doubles();
 size_t qr_need_doubles(int m, int n);
-size_t tsqr_need_doubles(int m);
-size_t jacobi_need_doubles(int p, int m);
+size_t tsqr_lds_need(int m, int cap);
+size_t tsqr_scratch_need(int m);
+size_t jacobi_need_doubles(int p, int m, int mode);
 void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream);
 void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_doubles, void* stream);
-void k_tsqr(const TsqrProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream);
+void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, double* scratch, void* stream);
 void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream);
 void k_fill(const FillItem* items, int n, void* stream);
 
@@ -373,14 +383,14 @@ struct TsqrBatch {
   std::vector<TsqrProb> p;
   int max_m = 0;
   void add(const void* A, int64_t lda, int N, int m, bool transA, double* R, int64_t ldr,
-           int prec = 0, const int32_t* zero_cols = nullptr);
+           int prec = 0, const int32_t* col_off = nullptr);
   void run(h2_ctx* ctx);
 };
 struct JacobiBatch {
   std::vector<JacobiProb> p;
   int max_m = 0;
   void add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu, double* sigma,
-           int32_t* rank, double eps, double rtol = 0.0, const int32_t* skip = nullptr);
+           int32_t* rank, double eps, double rtol = 0.0, const int32_t* skip = nullptr, int mode = 1);
   void run(h2_ctx* ctx);
 };
 // sigma_max of many small matrices: tsqr + jacobi (values only); sig[i] = sigma_max

@@ -270,79 +270,152 @@ void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_dou
 }
 
 // ---------------------------------------------------------------------------
-// TSQR: R of T (N x m), chunks of `ch` rows stacked under the running R
+// TSQR: R factor of T (N x me), T streamed in chunks of ch rows.  The running
+// R (me x me, upper triangular, zero rows where no data has arrived yet) sits
+// on top of the chunk; column jj of [R; C] is reduced by one Householder
+// reflector whose vector is e_jj on the R part and C(:, jj) / (alpha - beta)
+// on the chunk part, so each step touches row jj of R and the chunk only.
 // ---------------------------------------------------------------------------
-static __host__ __device__ inline int tsqr_chunk(int m) { return m <= 64 ? 64 : 32; }
-static __host__ __device__ inline size_t tsqr_need(int m) { return (size_t)(m + tsqr_chunk(m)) * m; }
-size_t tsqr_need_doubles(int m) { return tsqr_need(m); }
+constexpr int kTsqrThreads = 512;
+constexpr int kTsqrScratchChunk = 64;
 
-__global__ __launch_bounds__(256) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
-                                                   double* __restrict__ scratch, size_t slot, int lds_cap) {
+// chunk rows of an m-column problem held in LDS of `cap` doubles; 0: no fit
+static __host__ __device__ inline int tsqr_lds_chunk(int m, int cap) {
+  const int mm = m > 0 ? m : 1;
+  int c = cap / mm - mm;
+  if (c > 256) c = 256;
+  c &= ~31;
+  return c >= 32 ? c : 0;
+}
+
+size_t tsqr_lds_need(int m, int cap) {
+  const int c = tsqr_lds_chunk(m, cap);
+  return c ? (size_t)(m + c) * m : 0;
+}
+size_t tsqr_scratch_need(int m) { return (size_t)(m + kTsqrScratchChunk) * m; }
+
+__global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
+                                                            double* __restrict__ scratch, size_t slot,
+                                                            int lds_cap) {
   extern __shared__ double smem[];
-  __shared__ double red[4];
-  const int tid = threadIdx.x;
+  __shared__ double red[kTsqrThreads / 64];
+  const int tid = threadIdx.x, wave = tid >> 6;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const TsqrProb P = probs[pi];
     const int m = P.m, N = P.N;
-    const int ch = tsqr_chunk(m);
-    const int rows_cap = m + ch;
-    const bool in_lds = tsqr_need(m) <= (size_t)lds_cap;
+    const int off = P.col_off ? min(max(*P.col_off, 0), m) : 0;
+    const int me = m - off;
+    int ch = tsqr_lds_chunk(m, lds_cap);
+    const bool in_lds = ch > 0;
+    if (!in_lds) ch = kTsqrScratchChunk;
     double* B = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
-    const int64_t ld = rows_cap;
-    int rowsR = 0;
-    const int zc = P.zero_cols ? *P.zero_cols : 0;
+    const int p = min(N, m);
+    if (N <= me) {
+      // T itself is a factor with T^T T = R^T R (N rows): no reduction.  (The
+      // structured step below needs N >= me: with fewer rows its R is not
+      // confined to the first N rows.)
+      for (int e = tid; e < p * m; e += kTsqrThreads) {
+        const int i = e % p, j = e / p;
+        double v = 0.0;
+        if (j < me) {
+          const int64_t src = P.transA ? off + j + (int64_t)i * P.lda : i + (int64_t)(off + j) * P.lda;
+          v = P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src];
+        }
+        P.R[i + (int64_t)j * P.ldr] = v;
+      }
+      continue;  // uniform across the workgroup
+    }
+    const int64_t ld = me + ch;  // rows: R in [0, me), chunk in [me, me + ch)
+    for (int e = tid; e < me * me; e += kTsqrThreads) B[(e % me) + (int64_t)(e / me) * ld] = 0.0;
     for (int q0 = 0; q0 < N; q0 += ch) {
       const int cr = min(ch, N - q0);
-      // load rows q0..q0+cr-1 of T into B[rowsR .. rowsR+cr-1]
-      if (P.transA) {  // T(i, j) = A[j + i*lda], consecutive threads along j
-        for (int e = tid; e < cr * m; e += 256) {
-          const int j = e % m, i = e / m;
-          const int64_t src = j + (int64_t)(q0 + i) * P.lda;
-          B[rowsR + i + (int64_t)j * ld] =
-              j < zc ? 0.0 : (P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src]);
+      double* C = B + me;
+      if (P.transA) {  // T(i, j) = A[j + i lda], consecutive threads along j
+        for (int e = tid; e < cr * me; e += kTsqrThreads) {
+          const int j = e % me, i = e / me;
+          const int64_t src = off + j + (int64_t)(q0 + i) * P.lda;
+          C[i + (int64_t)j * ld] = P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src];
         }
       } else {
-        for (int e = tid; e < cr * m; e += 256) {
+        for (int e = tid; e < cr * me; e += kTsqrThreads) {
           const int i = e % cr, j = e / cr;
-          const int64_t src = (q0 + i) + (int64_t)j * P.lda;
-          B[rowsR + i + (int64_t)j * ld] =
-              j < zc ? 0.0 : (P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src]);
+          const int64_t src = (q0 + i) + (int64_t)(off + j) * P.lda;
+          C[i + (int64_t)j * ld] = P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src];
         }
       }
       __syncthreads();
-      const int rows = rowsR + cr;
-      householder_qr(B, ld, rows, m, nullptr, red);
-      rowsR = min(rows, m);
-      // keep the upper triangle of the top rowsR rows, clear everything below
-      for (int e = tid; e < rows * m; e += 256) {
-        const int i = e % rows, j = e / rows;
-        if (i > j || i >= rowsR) B[i + (int64_t)j * ld] = 0.0;
+      for (int jj = 0; jj < me; ++jj) {
+        const double* cj = C + (int64_t)jj * ld;
+        double s = 0.0;
+        for (int i = tid; i < cr; i += kTsqrThreads) s += cj[i] * cj[i];
+        s = wave_sum(s);
+        if ((tid & 63) == 0) red[wave] = s;
+        __syncthreads();
+        s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kTsqrThreads / 64; ++w) s += red[w];
+        const double alpha = B[jj + (int64_t)jj * ld];
+        if (s > 0.0) {
+          const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+          const double tau = (beta - alpha) / beta;
+          const double scal = 1.0 / (alpha - beta);  // v = [1; scal * C(:, jj)]
+          const int nt = me - jj - 1;
+          int tpc = 64;
+          while (tpc > 1 && tpc * nt > kTsqrThreads) tpc >>= 1;
+          const int grp = tid / tpc, gl = tid % tpc, ngrp = kTsqrThreads / tpc;
+          for (int c0 = 0; c0 < nt; c0 += ngrp) {
+            const int c = jj + 1 + c0 + grp;
+            const bool live = c0 + grp < nt;
+            double d = 0.0;
+            double* cc = C + (int64_t)c * ld;
+            if (live)
+              for (int i = gl; i < cr; i += tpc) d += cj[i] * cc[i];
+            for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+            if (live) {
+              double* rj = B + jj + (int64_t)c * ld;
+              d = tau * (*rj + scal * d);
+              if (gl == 0) *rj -= d;
+              const double f = d * scal;
+              for (int i = gl; i < cr; i += tpc) cc[i] -= f * cj[i];
+            }
+          }
+          if (tid == 0) B[jj + (int64_t)jj * ld] = beta;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
-    const int p = min(N, m);
-    for (int e = tid; e < p * m; e += 256) {
+    for (int e = tid; e < p * m; e += kTsqrThreads) {
       const int i = e % p, j = e / p;
-      P.R[i + (int64_t)j * P.ldr] = (i <= j && i < rowsR) ? B[i + (int64_t)j * ld] : 0.0;
+      P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? B[i + (int64_t)j * ld] : 0.0;
     }
     __syncthreads();
   }
 }
 
-void k_tsqr(const TsqrProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream) {
+void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, double* scratch, void* stream) {
   if (n <= 0) return;
   H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "tsqr: global scratch missing");
   const int grid = slot == 0 ? n : std::min(n, 1024);
-  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream, probs,
-                     n, scratch, slot, lds_doubles);
+  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(kTsqrThreads), lds_doubles * 8, (hipStream_t)stream, probs,
+                     n, scratch, slot, lds_limit_doubles());
   HIP_OK(hipGetLastError());
 }
 
 // ---------------------------------------------------------------------------
-// one-sided Jacobi SVD of R (p x m): columns rotated until orthogonal;
-// columns below *skip (all zero) take no part in the rotations
+// one-sided (Hestenes) Jacobi SVD of R, round-robin parallel ordering.
+//  mode 0: rotate the columns s0..m-1 of R (p x m; columns < s0 are zero) and
+//          accumulate the rotations: U = right singular vectors, all m of them
+//  mode 1: rotate the rows of R' (pe x me, pe = min(p, me), me = m - s0), i.e.
+//          the columns of R'^T; at convergence column j of R'^T V equals
+//          sigma_j v_j with v_j a right singular vector of R', so U needs no
+//          accumulation.  Triangular factors converge in far fewer sweeps
+//          this way.  U(:, pos) = [0 (s0 rows); v_j] for pos < pe, else 0.
+// Singular values = column norms, sorted descending (ties by index).
 // ---------------------------------------------------------------------------
-size_t jacobi_need_doubles(int p, int m) { return (size_t)p * m + (size_t)m * m + 2 * (size_t)m; }
+static __host__ __device__ inline size_t jacobi_need(int p, int m, int mode) {
+  return mode ? (size_t)p * m + 2 * (size_t)m : (size_t)p * m + (size_t)m * m + 2 * (size_t)m;
+}
+size_t jacobi_need_doubles(int p, int m, int mode) { return jacobi_need(p, m, mode); }
 
 __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
                                                      double* __restrict__ scratch, size_t slot, int lds_cap) {
@@ -351,28 +424,41 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
   const int tid = threadIdx.x;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const JacobiProb P = probs[pi];
-    const int m = P.m, p = P.p;
-    if (m == 0) {
-      if (tid == 0 && P.rank) *P.rank = 0;
-      continue;
-    }
-    const bool in_lds = (size_t)p * m + (size_t)m * m + 2 * (size_t)m <= (size_t)lds_cap;
-    double* G = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
-    double* U = G + (size_t)p * m;
-    double* nrm = U + (size_t)m * m;
-    for (int e = tid; e < p * m; e += 256) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
-    for (int e = tid; e < m * m; e += 256) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
-    __syncthreads();
+    const int m = P.m, p = P.p, mode = P.mode;
     const int s0 = P.skip ? min(max(*P.skip, 0), m) : 0;
-    const int me = m - s0;                // active columns s0..m-1
-    const int mm = me + (me & 1);         // players of the round-robin tournament
+    // players: ncol columns of length len in G (len x ncol, column-major)
+    int ncol, len, coff;
+    if (mode) {
+      len = m - s0;
+      ncol = min(p, len);
+      coff = 0;
+    } else {
+      len = p;
+      ncol = m - s0;
+      coff = s0;
+    }
+    const bool in_lds = jacobi_need(p, m, mode) <= (size_t)lds_cap;
+    double* G = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
+    double* U = mode ? nullptr : G + (size_t)p * m;
+    double* nrm = (mode ? G + (size_t)p * m : U + (size_t)m * m);
+    if (mode) {
+      for (int e = tid; e < len * ncol; e += 256) {  // G(i, j) = R'(j, i)
+        const int i = e % len, j = e / len;
+        G[e] = P.R[j + (int64_t)i * P.ldr];
+      }
+    } else {
+      for (int e = tid; e < p * m; e += 256) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
+      for (int e = tid; e < m * m; e += 256) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int mm = ncol + (ncol & 1);  // players of the round-robin tournament
     const int npairs = mm / 2;
     const int gsz = npairs >= 64 ? 4 : (npairs >= 32 ? 8 : (npairs >= 16 ? 16 : (npairs >= 8 ? 32 : 64)));
     const int groups = 256 / gsz;
     const int g = tid / gsz, gl = tid % gsz;
-    // rotate while |a.b| exceeds the rounding level of a length-p dot product
-    const double tol = fmax(1e-15, 2.2e-16 * p);
-    for (int sweep = 0; sweep < 40 && me > 1; ++sweep) {
+    // rotate while |a.b| exceeds the rounding level of a dot product of length len
+    const double tol = fmax(1e-15, 2.2e-16 * len);
+    for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
       if (tid == 0) rotated = 0;
       __syncthreads();
       for (int rnd = 0; rnd < mm - 1; ++rnd) {
@@ -385,22 +471,20 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
             a = (rnd + pk) % (mm - 1);
             b = (rnd - pk + (mm - 1)) % (mm - 1);
           }
-          const bool live = a < me && b < me;
-          a += s0;
-          b += s0;
+          const bool live = a < ncol && b < ncol;
+          a += coff;
+          b += coff;
           double al = 0.0, be = 0.0, ga = 0.0;
-          if (live) {
-            const double* ga_ = G + (size_t)a * p;
-            const double* gb_ = G + (size_t)b * p;
-            for (int i = gl; i < p; i += gsz) {
+          double* ga_ = G + (size_t)a * len;
+          double* gb_ = G + (size_t)b * len;
+          if (live)
+            for (int i = gl; i < len; i += gsz) {
               const double x = ga_[i], y = gb_[i];
               al += x * x;
               be += y * y;
               ga += x * y;
             }
-          }
-          // reduce within the group of gsz lanes (gsz divides 64)
-          for (int o = gsz / 2; o >= 1; o >>= 1) {
+          for (int o = gsz / 2; o >= 1; o >>= 1) {  // gsz divides 64
             al += __shfl_xor(al, o, 64);
             be += __shfl_xor(be, o, 64);
             ga += __shfl_xor(ga, o, 64);
@@ -409,19 +493,19 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
             const double zeta = (be - al) / (2.0 * ga);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-            double* ga_ = G + (size_t)a * p;
-            double* gb_ = G + (size_t)b * p;
-            for (int i = gl; i < p; i += gsz) {
+            for (int i = gl; i < len; i += gsz) {
               const double x = ga_[i], y = gb_[i];
               ga_[i] = c * x - s * y;
               gb_[i] = s * x + c * y;
             }
-            double* ua = U + (size_t)a * m;
-            double* ub = U + (size_t)b * m;
-            for (int i = gl; i < m; i += gsz) {
-              const double x = ua[i], y = ub[i];
-              ua[i] = c * x - s * y;
-              ub[i] = s * x + c * y;
+            if (!mode) {
+              double* ua = U + (size_t)a * m;
+              double* ub = U + (size_t)b * m;
+              for (int i = gl; i < m; i += gsz) {
+                const double x = ua[i], y = ub[i];
+                ua[i] = c * x - s * y;
+                ub[i] = s * x + c * y;
+              }
             }
             if (gl == 0) rotated = 1;
           }
@@ -432,29 +516,45 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
       __syncthreads();
       if (!any) break;
     }
-    // singular values = column norms; order descending (ties by index)
-    for (int c = tid; c < m; c += 256) {
+    // nc columns carry singular values: mode 0 all m (the s0 zero ones too)
+    const int nc = mode ? ncol : m;
+    for (int c = tid; c < nc; c += 256) {
       double s = 0.0;
-      for (int i = 0; i < p; ++i) s += G[i + (size_t)c * p] * G[i + (size_t)c * p];
+      const double* gc = G + (size_t)c * len;
+      for (int i = 0; i < len; ++i) s += gc[i] * gc[i];
       nrm[c] = sqrt(s);
     }
     __syncthreads();
-    for (int c = tid; c < m; c += 256) {
+    for (int c = tid; c < nc; c += 256) {
       const double v = nrm[c];
       int pos = 0;
-      for (int d = 0; d < m; ++d) pos += (nrm[d] > v) || (nrm[d] == v && d < c);
+      for (int d = 0; d < nc; ++d) pos += (nrm[d] > v) || (nrm[d] == v && d < c);
       P.sigma[pos] = v;
+      if (P.U) {
+        double* uo = P.U + (int64_t)pos * P.ldu;
+        if (mode) {
+          const double inv = v > 0.0 ? 1.0 / v : 0.0;
+          const double* gc = G + (size_t)c * len;
+          for (int i = 0; i < s0; ++i) uo[i] = 0.0;
+          for (int i = 0; i < len; ++i) uo[s0 + i] = gc[i] * inv;
+        } else {
+          for (int i = 0; i < m; ++i) uo[i] = U[i + (size_t)c * m];
+        }
+      }
+    }
+    for (int pos = nc + tid; pos < m; pos += 256) {  // mode 1: no vector beyond ncol
+      P.sigma[pos] = 0.0;
       if (P.U)
-        for (int i = 0; i < m; ++i) P.U[i + (int64_t)pos * P.ldu] = U[i + (size_t)c * m];
+        for (int i = 0; i < m; ++i) P.U[i + (int64_t)pos * P.ldu] = 0.0;
     }
     if (P.rank) {
       __syncthreads();
       if (tid == 0) {
         double mx = 0.0;
-        for (int c = 0; c < m; ++c) mx = fmax(mx, nrm[c]);
+        for (int c = 0; c < nc; ++c) mx = fmax(mx, nrm[c]);
         const double thr = fmax(P.eps, P.rtol * mx);
         int k = 0;
-        for (int c = 0; c < m; ++c) k += nrm[c] > thr;
+        for (int c = 0; c < nc; ++c) k += nrm[c] > thr;
         *P.rank = k;
       }
     }

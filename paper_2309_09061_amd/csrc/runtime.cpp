@@ -325,7 +325,7 @@ void FillBatch::run(h2_ctx* ctx) {
 }
 
 void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, double* R, int64_t ldr,
-                    int prec, const int32_t* zero_cols) {
+                    int prec, const int32_t* col_off) {
   if (m <= 0) return;
   TsqrProb t{};
   t.A = A;
@@ -336,20 +336,20 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
   t.R = R;
   t.ldr = std::max<int64_t>(ldr, 1);
   t.prec = prec;
-  t.zero_cols = zero_cols;
+  t.col_off = col_off;
   p.push_back(t);
   max_m = std::max(max_m, m);
 }
 
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  // per problem: LDS if its working set fits the device limit, else a scratch slot
-  const size_t lim = (size_t)lds_limit_doubles();
+  // per problem: LDS (chunk rows sized from the device limit) or a scratch slot
+  const int lim = lds_limit_doubles();
   size_t slot = 0, lds = 0;
   for (const TsqrProb& t : p) {
-    size_t need = tsqr_need_doubles(t.m);
-    if (need > lim)
-      slot = std::max(slot, need);
+    size_t need = tsqr_lds_need(t.m, lim);
+    if (need == 0)
+      slot = std::max(slot, tsqr_scratch_need(t.m));
     else
       lds = std::max(lds, need);
   }
@@ -362,13 +362,13 @@ void TsqrBatch::run(h2_ctx* ctx) {
   }
   TsqrProb* d = upload(ctx, p);
   LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
-  k_tsqr(d, (int)p.size(), lds_for(lds), slot, scratch, ctx->stream);
+  k_tsqr(d, (int)p.size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
   p.clear();
   max_m = 0;
 }
 
 void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu,
-                      double* sigma, int32_t* rank, double eps, double rtol, const int32_t* skip) {
+                      double* sigma, int32_t* rank, double eps, double rtol, const int32_t* skip, int mode) {
   JacobiProb j{};
   j.R = R;
   j.ldr = std::max<int64_t>(ldr, 1);
@@ -381,6 +381,7 @@ void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, in
   j.eps = eps;
   j.rtol = rtol;
   j.skip = skip;
+  j.mode = mode;
   p.push_back(j);
   max_m = std::max(max_m, m);
 }
@@ -391,14 +392,15 @@ void JacobiBatch::run(h2_ctx* ctx) {
   size_t slot = 0, lds = 0;
   double flops = 0, bytes = 0;
   for (const JacobiProb& j : p) {
-    size_t need = jacobi_need_doubles(j.p, j.m);
+    size_t need = jacobi_need_doubles(j.p, j.m, j.mode);
     if (need > lim)
       slot = std::max(slot, need);
     else
       lds = std::max(lds, need);
-    double m = j.m, pp = j.p;  // one sweep of one-sided Jacobi over m columns of length p
-    flops += m * (m - 1) / 2 * (6.0 * pp + 6.0 * m);
-    bytes += 8.0 * (pp * m + m * m);
+    // one sweep over the pairs of players: 3 dot products and a rotation per pair
+    double pl = j.mode ? j.p : j.m, len = j.mode ? j.m : j.p;
+    flops += pl * (pl - 1) / 2 * (6.0 * len + (j.mode ? 0.0 : 6.0 * j.m));
+    bytes += 8.0 * ((double)j.p * j.m + (j.U ? (double)j.m * j.m : 0.0));
   }
   double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
   JacobiProb* d = upload(ctx, p);
