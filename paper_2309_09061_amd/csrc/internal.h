@@ -322,7 +322,11 @@ struct h2_product {
 
 namespace h2 {
 
-// uploads (pinned staging -> workspace), sync helper resets the staging
+// uploads (pinned staging -> workspace), sync helper resets the staging.
+// stage_alloc hands out pinned host space (it may wait for earlier copies),
+// stage_upload enqueues its copy into fresh workspace.
+char* stage_alloc(h2_ctx* ctx, size_t bytes);
+void* stage_upload(h2_ctx* ctx, const char* h, size_t bytes);
 void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes);
 template <class T>
 T* upload(h2_ctx* ctx, const std::vector<T>& v) {

@@ -19,6 +19,8 @@
 // matrices, and inadmissible leaves are expanded to dense blocks together
 // with the products of two nearfield blocks.
 #include <cmath>
+#include <exception>
+#include <thread>
 
 #include "internal.h"
 
@@ -381,13 +383,31 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   G->mem.ctx = ctx;
   View X{&Xm->c, false}, Y{&Ym->c, false};
   View Yt{&Ym->c, true}, Xt{&Xm->c, true};
+  // the product tree T^XY is symbolic (block trees only): built on a host
+  // thread while the two induced-basis passes run
+  ProductTreeH PT;
+  std::exception_ptr sym_err;
+  struct Joiner {
+    std::thread th;
+    ~Joiner() {
+      if (th.joinable()) th.join();
+    }
+  } sym;
+  sym.th = std::thread([&] {
+    try {
+      PT = build_product_tree(X, Y, T.ncl);
+    } catch (...) {
+      sym_err = std::current_exception();
+    }
+  });
   P1Side row, col;
   induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2);
   induced_pass(ctx, Yt, Xt, eps, G->mem, col, 0, 3);
 
-  step_begin(ctx, 1);
-  ProductTreeH PT = build_product_tree(X, Y, T.ncl);
+  step_begin(ctx, 1);  // the part of the symbolic build not hidden by the passes
+  sym.th.join();
   step_end(ctx, 1);
+  if (sym_err) std::rethrow_exception(sym_err);
   G->n_triples = PT.n_terminated;
 
   // ---- forming G on T^XY (top-down, then dense leaves) ----

@@ -69,7 +69,7 @@ double* zeros(h2_ctx* ctx, Arena& a, size_t count) {
 // ---------------------------------------------------------------------------
 // descriptor uploads through pinned staging
 // ---------------------------------------------------------------------------
-void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
+char* stage_alloc(h2_ctx* ctx, size_t bytes) {
   size_t need = (bytes + 255) & ~(size_t)255;
   if (ctx->stage_used + need > ctx->stage_cap) {
     dev_sync(ctx->stream);  // earlier copies out of the staging buffer are done
@@ -82,10 +82,19 @@ void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
   }
   char* h = ctx->stage + ctx->stage_used;
   ctx->stage_used += need;
-  std::memcpy(h, src, bytes);
+  return h;
+}
+
+void* stage_upload(h2_ctx* ctx, const char* h, size_t bytes) {
   void* d = ctx->ws.alloc(bytes);
   dev_h2d(d, h, bytes, ctx->stream);
   return d;
+}
+
+void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
+  char* h = stage_alloc(ctx, bytes);
+  std::memcpy(h, src, bytes);
+  return stage_upload(ctx, h, bytes);
 }
 
 void ctx_sync(h2_ctx* ctx) {
@@ -193,32 +202,37 @@ void GemmBatch::copy(const double* A, int64_t lda, bool tA, int k, double alpha,
 }
 
 void GemmBatch::run(h2_ctx* ctx) {
-  std::vector<int32_t> tiles;
-  for (size_t i = 0; i < outs.size(); ++i) {
-    const GemmOut& o = outs[i];
+  size_t ntiles = 0;
+  for (const GemmOut& o : outs) {
     if (o.m <= 0 || o.n <= 0) continue;
     if (o.t0 == o.t1 && o.beta) continue;  // nothing to add
-    for (int j0 = 0; j0 < o.n; j0 += 16)
-      for (int i0 = 0; i0 < o.m; i0 += 16) {
-        tiles.push_back((int32_t)i);
-        tiles.push_back(i0);
-        tiles.push_back(j0);
-      }
+    ntiles += (size_t)((o.m + 15) / 16) * ((o.n + 15) / 16);
   }
-  if (tiles.empty()) {
+  if (ntiles == 0) {
     outs.clear();
     terms.clear();
     return;
   }
-  // one upload for outputs, terms and tiles
+  // outputs, terms and tiles written straight into pinned staging, one copy
   const size_t so = outs.size() * sizeof(GemmOut), st = std::max<size_t>(terms.size(), 1) * sizeof(GemmTerm);
-  const size_t sti = tiles.size() * sizeof(int32_t);
+  const size_t sti = ntiles * 3 * sizeof(int32_t);
   const size_t o_t = (so + 255) & ~(size_t)255, o_ti = o_t + ((st + 255) & ~(size_t)255);
-  std::vector<char> blob(o_ti + sti, 0);
-  std::memcpy(blob.data(), outs.data(), so);
-  if (!terms.empty()) std::memcpy(blob.data() + o_t, terms.data(), terms.size() * sizeof(GemmTerm));
-  std::memcpy(blob.data() + o_ti, tiles.data(), sti);
-  char* dev = (char*)upload_bytes(ctx, blob.data(), blob.size());
+  char* h = stage_alloc(ctx, o_ti + sti);
+  std::memcpy(h, outs.data(), so);
+  if (!terms.empty()) std::memcpy(h + o_t, terms.data(), terms.size() * sizeof(GemmTerm));
+  int32_t* tl = (int32_t*)(h + o_ti);
+  for (size_t i = 0; i < outs.size(); ++i) {
+    const GemmOut& o = outs[i];
+    if (o.m <= 0 || o.n <= 0) continue;
+    if (o.t0 == o.t1 && o.beta) continue;
+    for (int j0 = 0; j0 < o.n; j0 += 16)
+      for (int i0 = 0; i0 < o.m; i0 += 16) {
+        *tl++ = (int32_t)i;
+        *tl++ = i0;
+        *tl++ = j0;
+      }
+  }
+  char* dev = (char*)stage_upload(ctx, h, o_ti + sti);
   GemmOut* d_o = (GemmOut*)dev;
   GemmTerm* d_t = (GemmTerm*)(dev + o_t);
   int32_t* d_tiles = (int32_t*)(dev + o_ti);
@@ -235,7 +249,7 @@ void GemmBatch::run(h2_ctx* ctx) {
     }
   }
   LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
-  k_gemm_sum(d_o, d_t, d_tiles, (int)(tiles.size() / 3), prec, ctx->stream);
+  k_gemm_sum(d_o, d_t, d_tiles, (int)ntiles, prec, ctx->stream);
   outs.clear();
   terms.clear();
 }
