@@ -101,6 +101,7 @@ struct TsqrProb {
   const int32_t* col_off;
   int64_t lda, ldr;
   int32_t N, m, transA, prec;  // prec 1: A holds float
+  double* work;                 // nullable: flops of the factorization performed
 };
 // One-sided Jacobi SVD of R (p x m, ldr): sigma[m] (descending, zero padded),
 // U (m x m, ldu, nullable) right singular vectors by descending sigma,
@@ -118,6 +119,7 @@ struct JacobiProb {
   int64_t ldr, ldu;
   int32_t p, m, mode, pad;
   double eps, rtol;
+  double* work;  // nullable: flops of the sweeps performed (dots and rotations)
 };
 // block fill: A[i + j ld] = (i == j ? diag : 0) for i < rows, j < cols
 struct FillItem {
@@ -278,6 +280,8 @@ struct PendingLaunch {
   void* b;
   int kind;
   double flops, bytes;
+  const double* work = nullptr;  // pinned host copy of per-problem flops (replaces flops)
+  int nwork = 0;
 };
 }  // namespace h2
 
@@ -295,6 +299,8 @@ struct h2_ctx {
   int prec = 0;                        // bulk precision of the running call
   bool profile = false;                // time every launch with stream events
   std::vector<void*> ev_pool;          // reusable events for launch timing
+  std::vector<std::pair<double*, size_t>> prof_host;  // pinned chunks for per-problem work counts
+  size_t prof_chunk = 0, prof_used = 0;
   std::vector<h2::PendingLaunch> pending;
   h2::KernelStat kstat[h2::KK_COUNT];
   ~h2_ctx();
@@ -341,9 +347,19 @@ struct LaunchTimer {
   void* a = nullptr;
   int kind;
   double flops, bytes;
+  const double* work = nullptr;
+  int nwork = 0;
   LaunchTimer(h2_ctx* c, int k, double f, double b);
   ~LaunchTimer();
 };
+// profiling only: device array of n per-problem work counts, and the pinned
+// host array its values are copied to once the launch is done
+struct WorkCounts {
+  double* dev = nullptr;
+  double* host = nullptr;
+  int n = 0;
+};
+WorkCounts work_counts(h2_ctx* ctx, int n);
 void kernel_stats_collect(h2_ctx* ctx);
 
 // step timing with stream events

@@ -323,6 +323,7 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __re
         }
         P.R[i + (int64_t)j * P.ldr] = v;
       }
+      if (tid == 0 && P.work) *P.work = 0.0;
       continue;  // uniform across the workgroup
     }
     const int64_t ld = me + ch;  // rows: R in [0, me), chunk in [me, me + ch)
@@ -388,6 +389,10 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __re
       const int i = e % p, j = e / p;
       P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? B[i + (int64_t)j * ld] : 0.0;
     }
+    if (tid == 0 && P.work) {  // Householder QR of an N x me matrix
+      const double dn = N, dm = me;
+      *P.work = 2.0 * dn * dm * dm - 2.0 * dm * dm * dm / 3.0;
+    }
     __syncthreads();
   }
 }
@@ -421,10 +426,12 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
                                                      double* __restrict__ scratch, size_t slot, int lds_cap) {
   extern __shared__ double smem[];
   __shared__ int rotated;
+  __shared__ unsigned int nrot;
   const int tid = threadIdx.x;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const JacobiProb P = probs[pi];
     const int m = P.m, p = P.p, mode = P.mode;
+    if (tid == 0) nrot = 0;
     const int s0 = P.skip ? min(max(*P.skip, 0), m) : 0;
     // players: ncol columns of length len in G (len x ncol, column-major)
     int ncol, len, coff;
@@ -458,7 +465,10 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
     const int g = tid / gsz, gl = tid % gsz;
     // rotate while |a.b| exceeds the rounding level of a dot product of length len
     const double tol = fmax(1e-15, 2.2e-16 * len);
+    unsigned int my_rot = 0;
+    int sweeps = 0;
     for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
+      ++sweeps;
       if (tid == 0) rotated = 0;
       __syncthreads();
       for (int rnd = 0; rnd < mm - 1; ++rnd) {
@@ -507,7 +517,10 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
                 ub[i] = s * x + c * y;
               }
             }
-            if (gl == 0) rotated = 1;
+            if (gl == 0) {
+              rotated = 1;
+              ++my_rot;
+            }
           }
         }
         __syncthreads();
@@ -515,6 +528,14 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
       const int any = rotated;
       __syncthreads();
       if (!any) break;
+    }
+    if (P.work) {
+      if (my_rot) atomicAdd(&nrot, my_rot);
+      __syncthreads();
+      if (tid == 0) {  // 3 dot products per pair and sweep, a rotation when applied
+        const double pairs = 0.5 * ncol * (ncol - 1.0);
+        *P.work = sweeps * pairs * 6.0 * len + (double)nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
+      }
     }
     // nc columns carry singular values: mode 0 all m (the s0 zero ones too)
     const int nc = mode ? ncol : m;

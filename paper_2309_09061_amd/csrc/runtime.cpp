@@ -148,7 +148,26 @@ LaunchTimer::~LaunchTimer() {
   if (!a) return;
   void* b = pool_event(ctx);
   dev_event_record(b, ctx->stream);
-  ctx->pending.push_back({a, b, kind, flops, bytes});
+  PendingLaunch p{a, b, kind, flops, bytes};
+  p.work = work;
+  p.nwork = nwork;
+  ctx->pending.push_back(p);
+}
+
+WorkCounts work_counts(h2_ctx* ctx, int n) {
+  WorkCounts w;
+  if (!ctx->profile || n <= 0) return w;
+  w.n = n;
+  w.dev = ctx->ws.get<double>(n);
+  if (ctx->prof_host.empty() || ctx->prof_used + n > ctx->prof_chunk) {
+    size_t cap = std::max<size_t>(n, 1 << 18);
+    ctx->prof_host.push_back({(double*)dev_malloc_host(cap * sizeof(double)), cap});
+    ctx->prof_chunk = cap;
+    ctx->prof_used = 0;
+  }
+  w.host = ctx->prof_host.back().first + ctx->prof_used;
+  ctx->prof_used += n;
+  return w;
 }
 
 void kernel_stats_collect(h2_ctx* ctx) {
@@ -156,12 +175,25 @@ void kernel_stats_collect(h2_ctx* ctx) {
     KernelStat& k = ctx->kstat[p.kind];
     k.ms += dev_event_ms(p.a, p.b);
     k.launches += 1;
-    k.flops += p.flops;
+    if (p.work) {  // the copy of the counts follows the end event on the stream
+      dev_sync(ctx->stream);
+      double f = 0;
+      for (int i = 0; i < p.nwork; ++i) f += p.work[i];
+      k.flops += f;
+    } else {
+      k.flops += p.flops;
+    }
     k.bytes += p.bytes;
     ctx->ev_pool.push_back(p.a);
     ctx->ev_pool.push_back(p.b);
   }
   ctx->pending.clear();
+  // pinned count chunks are reused once nothing refers to them
+  if (ctx->prof_host.size() > 1) {
+    for (size_t i = 0; i + 1 < ctx->prof_host.size(); ++i) dev_free_host(ctx->prof_host[i].first);
+    ctx->prof_host.erase(ctx->prof_host.begin(), ctx->prof_host.end() - 1);
+  }
+  ctx->prof_used = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -374,9 +406,17 @@ void TsqrBatch::run(h2_ctx* ctx) {
     flops += 2.0 * N * m * m - 2.0 * r * r * r / 3.0;
     bytes += 8.0 * (N * m + r * m);
   }
+  WorkCounts wc = work_counts(ctx, (int)p.size());
+  if (wc.dev)
+    for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
   TsqrProb* d = upload(ctx, p);
-  LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
-  k_tsqr(d, (int)p.size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
+  {
+    LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
+    lt.work = wc.host;
+    lt.nwork = wc.n;
+    k_tsqr(d, (int)p.size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
+  }
+  if (wc.dev) dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
   p.clear();
   max_m = 0;
 }
@@ -417,9 +457,17 @@ void JacobiBatch::run(h2_ctx* ctx) {
     bytes += 8.0 * ((double)j.p * j.m + (j.U ? (double)j.m * j.m : 0.0));
   }
   double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
+  WorkCounts wc = work_counts(ctx, (int)p.size());
+  if (wc.dev)
+    for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
   JacobiProb* d = upload(ctx, p);
-  LaunchTimer lt(ctx, KK_JACOBI, flops, bytes);
-  k_jacobi(d, (int)p.size(), lds_for(lds), slot, scratch, ctx->stream);
+  {
+    LaunchTimer lt(ctx, KK_JACOBI, flops, bytes);
+    lt.work = wc.host;
+    lt.nwork = wc.n;
+    k_jacobi(d, (int)p.size(), lds_for(lds), slot, scratch, ctx->stream);
+  }
+  if (wc.dev) dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
   p.clear();
   max_m = 0;
 }
@@ -473,5 +521,6 @@ h2_ctx::~h2_ctx() {
   for (auto& c : cache) h2::dev_free(c.first);
   cache.clear();
   if (stage) h2::dev_free_host(stage);
+  for (auto& c : prof_host) h2::dev_free_host(c.first);
   for (void* e : events) h2::dev_event_destroy(e);
 }
