@@ -108,10 +108,17 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
   HIP_OK(hipGetLastError());
 }
 
+// Dynamic LDS of the factorization kernels.  Each kernel calls its body
+// twice, once on a pointer into this array and once on global scratch, and
+// the bodies are force-inlined: the compiler then sees the address space of
+// every access and emits LDS instructions (ds_read / ds_write, counted
+// separately from global loads) for the LDS copy.
+extern __shared__ double lds_dyn[];
+
 // ---------------------------------------------------------------------------
 // Householder QR of one m x n matrix W (ld) by a 256-thread workgroup
 // ---------------------------------------------------------------------------
-__device__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau, double* red) {
+__device__ __forceinline__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau, double* red) {
   const int tid = threadIdx.x;
   const int kmax = m < n ? m : n;
   for (int jj = 0; jj < kmax; ++jj) {
@@ -151,17 +158,23 @@ __device__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau,
       for (int c0 = 0; c0 < nt; c0 += ngrp) {
         const int c = jj + 1 + c0 + grp;
         const bool live = c0 + grp < nt;
-        double d = 0.0;
+        double d0 = 0.0, d1 = 0.0;
+        double* wc = W + (int64_t)c * ld;
         if (live) {
-          const double* wc = W + c * ld;
-          if (gl == 0) d = wc[jj];
-          for (int i = jj + 1 + gl; i < m; i += tpc) d += v[i] * wc[i];
+          if (gl == 0) d0 = wc[jj];
+          int i = jj + 1 + gl;
+          for (; i + tpc < m; i += 2 * tpc) {
+            d0 += v[i] * wc[i];
+            d1 += v[i + tpc] * wc[i + tpc];
+          }
+          if (i < m) d0 += v[i] * wc[i];
         }
+        double d = d0 + d1;
         for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
         if (live) {
           d *= t;
-          double* wc = W + c * ld;
           if (gl == 0) wc[jj] -= d;
+#pragma unroll 4
           for (int i = jj + 1 + gl; i < m; i += tpc) wc[i] -= d * v[i];
         }
       }
@@ -204,25 +217,28 @@ int lds_limit_doubles() {
 // ---------------------------------------------------------------------------
 size_t qr_need_doubles(int m, int n) { return (size_t)m * n; }
 
+__device__ __forceinline__ void qr_copy_r(const QrProb& P, const double* W, int64_t ld) {
+  for (int64_t e = threadIdx.x; e < (int64_t)P.rrows * P.n; e += 256) {
+    const int i = (int)(e % P.rrows), c = (int)(e / P.rrows);
+    P.R[i + c * P.ldr] = (i <= c && i < P.m) ? W[i + c * ld] : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void qr_kernel(const QrProb* __restrict__ probs, int lds_cap) {
-  extern __shared__ double smem[];
   __shared__ double red[4];
   const QrProb P = probs[blockIdx.x];
   const int m = P.m, n = P.n, tid = threadIdx.x;
-  const bool in_lds = (int64_t)m * n <= lds_cap;
-  double* W = in_lds ? smem : P.A;
-  const int64_t ld = in_lds ? m : P.lda;
-  if (in_lds)
+  if ((int64_t)m * n <= lds_cap) {
+    double* W = lds_dyn;
     for (int64_t e = tid; e < (int64_t)m * n; e += 256) W[e] = P.A[(e % m) + (e / m) * P.lda];
-  __syncthreads();
-  householder_qr(W, ld, m, n, P.tau, red);
-  if (in_lds)
+    __syncthreads();
+    householder_qr(W, m, m, n, P.tau, red);
     for (int64_t e = tid; e < (int64_t)m * n; e += 256) P.A[(e % m) + (e / m) * P.lda] = W[e];
-  if (P.R)
-    for (int64_t e = tid; e < (int64_t)P.rrows * n; e += 256) {
-      const int i = (int)(e % P.rrows), c = (int)(e / P.rrows);
-      P.R[i + c * P.ldr] = (i <= c && i < m) ? W[i + c * ld] : 0.0;
-    }
+    if (P.R) qr_copy_r(P, W, m);
+  } else {
+    householder_qr(P.A, P.lda, m, n, P.tau, red);
+    if (P.R) qr_copy_r(P, P.A, P.lda);
+  }
 }
 
 void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream) {
@@ -232,21 +248,10 @@ void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream) {
   HIP_OK(hipGetLastError());
 }
 
-// work item = (problem, first column); 64 columns per item
-__global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict__ probs,
-                                                    const int32_t* __restrict__ work, int lds_cap) {
-  extern __shared__ double smem[];
-  __shared__ double tau_s[256];
-  const ApplyProb P = probs[work[2 * blockIdx.x]];
-  const int c0 = work[2 * blockIdx.x + 1];
-  const int m = P.m, r = P.nrefl, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const bool in_lds = (int64_t)m * r <= lds_cap;
-  const double* V = in_lds ? smem : P.V;
-  const int64_t ldv = in_lds ? m : P.ldv;
-  if (in_lds)
-    for (int64_t e = tid; e < (int64_t)m * r; e += 256) smem[e] = P.V[(e % m) + (e / m) * P.ldv];
-  for (int e = tid; e < r; e += 256) tau_s[e] = P.tau[e];
-  __syncthreads();
+// C <- Q^T C or Q C for the columns c0 .. c0+63, one wave per column
+__device__ __forceinline__ void apply_cols(const ApplyProb& P, const double* V, int64_t ldv, const double* tau_s,
+                                           int c0) {
+  const int m = P.m, r = P.nrefl, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int cend = min(P.ncols, c0 + 64);
   for (int c = c0 + wave; c < cend; c += 4) {
     double* C = P.C + (int64_t)c * P.ldc;
@@ -254,11 +259,32 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict_
       const int jj = P.trans ? s : r - 1 - s;
       const double t = tau_s[jj];
       if (t == 0.0) continue;
+      const double* v = V + jj * ldv;
       double d = 0.0;
-      for (int i = jj + lane; i < m; i += 64) d += (i == jj ? 1.0 : V[i + jj * ldv]) * C[i];
+#pragma unroll 2
+      for (int i = jj + lane; i < m; i += 64) d += (i == jj ? 1.0 : v[i]) * C[i];
       d = wave_sum(d) * t;
-      for (int i = jj + lane; i < m; i += 64) C[i] -= d * (i == jj ? 1.0 : V[i + jj * ldv]);
+#pragma unroll 2
+      for (int i = jj + lane; i < m; i += 64) C[i] -= d * (i == jj ? 1.0 : v[i]);
     }
+  }
+}
+
+// work item = (problem, first column); 64 columns per item
+__global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict__ probs,
+                                                    const int32_t* __restrict__ work, int lds_cap) {
+  __shared__ double tau_s[256];
+  const ApplyProb P = probs[work[2 * blockIdx.x]];
+  const int c0 = work[2 * blockIdx.x + 1];
+  const int m = P.m, r = P.nrefl, tid = threadIdx.x;
+  for (int e = tid; e < r; e += 256) tau_s[e] = P.tau[e];
+  if ((int64_t)m * r <= lds_cap) {
+    for (int64_t e = tid; e < (int64_t)m * r; e += 256) lds_dyn[e] = P.V[(e % m) + (e / m) * P.ldv];
+    __syncthreads();
+    apply_cols(P, lds_dyn, m, tau_s, c0);
+  } else {
+    __syncthreads();
+    apply_cols(P, P.V, P.ldv, tau_s, c0);
   }
 }
 
@@ -294,104 +320,118 @@ size_t tsqr_lds_need(int m, int cap) {
 }
 size_t tsqr_scratch_need(int m) { return (size_t)(m + kTsqrScratchChunk) * m; }
 
+__device__ __forceinline__ double tsqr_src(const TsqrProb& P, int64_t idx) {
+  return P.prec ? (double)((const float*)P.A)[idx] : ((const double*)P.A)[idx];
+}
+
+// one problem with N > me on the buffer B ((me + ch) x me doubles)
+__device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch, int me, int off, double* red) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int m = P.m, N = P.N;
+  const int64_t ld = me + ch;  // rows: R in [0, me), chunk in [me, me + ch)
+  for (int e = tid; e < me * me; e += kTsqrThreads) B[(e % me) + (int64_t)(e / me) * ld] = 0.0;
+  double* C = B + me;
+  for (int q0 = 0; q0 < N; q0 += ch) {
+    const int cr = min(ch, N - q0);
+    if (P.transA) {  // T(i, j) = A[j + i lda], consecutive threads along j
+      for (int e = tid; e < cr * me; e += kTsqrThreads) {
+        const int j = e % me, i = e / me;
+        C[i + (int64_t)j * ld] = tsqr_src(P, off + j + (int64_t)(q0 + i) * P.lda);
+      }
+    } else {
+      for (int e = tid; e < cr * me; e += kTsqrThreads) {
+        const int i = e % cr, j = e / cr;
+        C[i + (int64_t)j * ld] = tsqr_src(P, (q0 + i) + (int64_t)(off + j) * P.lda);
+      }
+    }
+    __syncthreads();
+    for (int jj = 0; jj < me; ++jj) {
+      const double* cj = C + (int64_t)jj * ld;
+      double s = 0.0;
+      for (int i = tid; i < cr; i += kTsqrThreads) s += cj[i] * cj[i];
+      s = wave_sum(s);
+      if ((tid & 63) == 0) red[wave] = s;
+      __syncthreads();
+      s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kTsqrThreads / 64; ++w) s += red[w];
+      const double alpha = B[jj + (int64_t)jj * ld];
+      if (s > 0.0) {
+        const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        const double tau = (beta - alpha) / beta;
+        const double scal = 1.0 / (alpha - beta);  // v = [1; scal * C(:, jj)]
+        const int nt = me - jj - 1;
+        int tpc = 64;
+        while (tpc > 1 && tpc * nt > kTsqrThreads) tpc >>= 1;
+        const int grp = tid / tpc, gl = tid % tpc, ngrp = kTsqrThreads / tpc;
+        for (int c0 = 0; c0 < nt; c0 += ngrp) {
+          const int c = jj + 1 + c0 + grp;
+          const bool live = c0 + grp < nt;
+          double d0 = 0.0, d1 = 0.0;
+          double* cc = C + (int64_t)c * ld;
+          if (live) {
+            int i = gl;
+            for (; i + tpc < cr; i += 2 * tpc) {
+              d0 += cj[i] * cc[i];
+              d1 += cj[i + tpc] * cc[i + tpc];
+            }
+            if (i < cr) d0 += cj[i] * cc[i];
+          }
+          double d = d0 + d1;
+          for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+          if (live) {
+            double* rj = B + jj + (int64_t)c * ld;
+            d = tau * (*rj + scal * d);
+            if (gl == 0) *rj -= d;
+            const double f = d * scal;
+#pragma unroll 4
+            for (int i = gl; i < cr; i += tpc) cc[i] -= f * cj[i];
+          }
+        }
+        if (tid == 0) B[jj + (int64_t)jj * ld] = beta;
+      }
+      __syncthreads();
+    }
+  }
+  const int p = min(N, m);
+  for (int e = tid; e < p * m; e += kTsqrThreads) {
+    const int i = e % p, j = e / p;
+    P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? B[i + (int64_t)j * ld] : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
                                                             double* __restrict__ scratch, size_t slot,
                                                             int lds_cap) {
-  extern __shared__ double smem[];
   __shared__ double red[kTsqrThreads / 64];
-  const int tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const TsqrProb P = probs[pi];
     const int m = P.m, N = P.N;
     const int off = P.col_off ? min(max(*P.col_off, 0), m) : 0;
     const int me = m - off;
-    int ch = tsqr_lds_chunk(m, lds_cap);
-    const bool in_lds = ch > 0;
-    if (!in_lds) ch = kTsqrScratchChunk;
-    double* B = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
     const int p = min(N, m);
     if (N <= me) {
       // T itself is a factor with T^T T = R^T R (N rows): no reduction.  (The
-      // structured step below needs N >= me: with fewer rows its R is not
-      // confined to the first N rows.)
+      // structured step needs N > me: with fewer rows its R is not confined
+      // to the first N rows.)
       for (int e = tid; e < p * m; e += kTsqrThreads) {
         const int i = e % p, j = e / p;
         double v = 0.0;
-        if (j < me) {
-          const int64_t src = P.transA ? off + j + (int64_t)i * P.lda : i + (int64_t)(off + j) * P.lda;
-          v = P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src];
-        }
+        if (j < me) v = tsqr_src(P, P.transA ? off + j + (int64_t)i * P.lda : i + (int64_t)(off + j) * P.lda);
         P.R[i + (int64_t)j * P.ldr] = v;
       }
       if (tid == 0 && P.work) *P.work = 0.0;
-      continue;  // uniform across the workgroup
-    }
-    const int64_t ld = me + ch;  // rows: R in [0, me), chunk in [me, me + ch)
-    for (int e = tid; e < me * me; e += kTsqrThreads) B[(e % me) + (int64_t)(e / me) * ld] = 0.0;
-    for (int q0 = 0; q0 < N; q0 += ch) {
-      const int cr = min(ch, N - q0);
-      double* C = B + me;
-      if (P.transA) {  // T(i, j) = A[j + i lda], consecutive threads along j
-        for (int e = tid; e < cr * me; e += kTsqrThreads) {
-          const int j = e % me, i = e / me;
-          const int64_t src = off + j + (int64_t)(q0 + i) * P.lda;
-          C[i + (int64_t)j * ld] = P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src];
-        }
-      } else {
-        for (int e = tid; e < cr * me; e += kTsqrThreads) {
-          const int i = e % cr, j = e / cr;
-          const int64_t src = (q0 + i) + (int64_t)(off + j) * P.lda;
-          C[i + (int64_t)j * ld] = P.prec ? (double)((const float*)P.A)[src] : ((const double*)P.A)[src];
-        }
+    } else {
+      const int ch = tsqr_lds_chunk(m, lds_cap);
+      if (ch > 0)
+        tsqr_reduce(P, lds_dyn, ch, me, off, red);
+      else
+        tsqr_reduce(P, scratch + (size_t)blockIdx.x * slot, kTsqrScratchChunk, me, off, red);
+      if (tid == 0 && P.work) {  // Householder QR of an N x me matrix
+        const double dn = N, dm = me;
+        *P.work = 2.0 * dn * dm * dm - 2.0 * dm * dm * dm / 3.0;
       }
-      __syncthreads();
-      for (int jj = 0; jj < me; ++jj) {
-        const double* cj = C + (int64_t)jj * ld;
-        double s = 0.0;
-        for (int i = tid; i < cr; i += kTsqrThreads) s += cj[i] * cj[i];
-        s = wave_sum(s);
-        if ((tid & 63) == 0) red[wave] = s;
-        __syncthreads();
-        s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kTsqrThreads / 64; ++w) s += red[w];
-        const double alpha = B[jj + (int64_t)jj * ld];
-        if (s > 0.0) {
-          const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
-          const double tau = (beta - alpha) / beta;
-          const double scal = 1.0 / (alpha - beta);  // v = [1; scal * C(:, jj)]
-          const int nt = me - jj - 1;
-          int tpc = 64;
-          while (tpc > 1 && tpc * nt > kTsqrThreads) tpc >>= 1;
-          const int grp = tid / tpc, gl = tid % tpc, ngrp = kTsqrThreads / tpc;
-          for (int c0 = 0; c0 < nt; c0 += ngrp) {
-            const int c = jj + 1 + c0 + grp;
-            const bool live = c0 + grp < nt;
-            double d = 0.0;
-            double* cc = C + (int64_t)c * ld;
-            if (live)
-              for (int i = gl; i < cr; i += tpc) d += cj[i] * cc[i];
-            for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-            if (live) {
-              double* rj = B + jj + (int64_t)c * ld;
-              d = tau * (*rj + scal * d);
-              if (gl == 0) *rj -= d;
-              const double f = d * scal;
-              for (int i = gl; i < cr; i += tpc) cc[i] -= f * cj[i];
-            }
-          }
-          if (tid == 0) B[jj + (int64_t)jj * ld] = beta;
-        }
-        __syncthreads();
-      }
-    }
-    for (int e = tid; e < p * m; e += kTsqrThreads) {
-      const int i = e % p, j = e / p;
-      P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? B[i + (int64_t)j * ld] : 0.0;
-    }
-    if (tid == 0 && P.work) {  // Householder QR of an N x me matrix
-      const double dn = N, dm = me;
-      *P.work = 2.0 * dn * dm * dm - 2.0 * dm * dm * dm / 3.0;
     }
     __syncthreads();
   }
@@ -422,163 +462,178 @@ static __host__ __device__ inline size_t jacobi_need(int p, int m, int mode) {
 }
 size_t jacobi_need_doubles(int p, int m, int mode) { return jacobi_need(p, m, mode); }
 
+struct JacobiShared {
+  int rotated;
+  unsigned int nrot;
+};
+
+// one problem on the buffer G (jacobi_need doubles)
+__device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int s0, JacobiShared& sh) {
+  const int tid = threadIdx.x;
+  const int m = P.m, p = P.p, mode = P.mode;
+  // players: ncol columns of length len in G (len x ncol, column-major)
+  int ncol, len, coff;
+  if (mode) {
+    len = m - s0;
+    ncol = min(p, len);
+    coff = 0;
+  } else {
+    len = p;
+    ncol = m - s0;
+    coff = s0;
+  }
+  double* U = mode ? nullptr : G + (size_t)p * m;
+  double* nrm = mode ? G + (size_t)p * m : U + (size_t)m * m;
+  if (mode) {
+    for (int e = tid; e < len * ncol; e += 256) {  // G(i, j) = R'(j, i)
+      const int i = e % len, j = e / len;
+      G[e] = P.R[j + (int64_t)i * P.ldr];
+    }
+  } else {
+    for (int e = tid; e < p * m; e += 256) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
+    for (int e = tid; e < m * m; e += 256) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int mm = ncol + (ncol & 1);  // players of the round-robin tournament
+  const int npairs = mm / 2;
+  // lanes per pair: all pairs of a round at once where possible
+  int gsz = 64;
+  while (gsz > 4 && gsz * npairs > 256) gsz >>= 1;
+  const int groups = 256 / gsz;
+  const int g = tid / gsz, gl = tid % gsz;
+  // rotate while |a.b| exceeds the rounding level of a dot product of length len
+  const double tol = fmax(1e-15, 2.2e-16 * len);
+  unsigned int my_rot = 0;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
+    ++sweeps;
+    if (tid == 0) sh.rotated = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < mm - 1; ++rnd) {
+      for (int pk = g; pk < npairs; pk += groups) {
+        int a, b;
+        if (pk == 0) {
+          a = mm - 1;
+          b = rnd;
+        } else {
+          a = (rnd + pk) % (mm - 1);
+          b = (rnd - pk + (mm - 1)) % (mm - 1);
+        }
+        const bool live = a < ncol && b < ncol;
+        a += coff;
+        b += coff;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        double* ga_ = G + (size_t)a * len;
+        double* gb_ = G + (size_t)b * len;
+        if (live) {
+#pragma unroll 4
+          for (int i = gl; i < len; i += gsz) {
+            const double x = ga_[i], y = gb_[i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+        }
+        for (int o = gsz / 2; o >= 1; o >>= 1) {  // gsz divides 64
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          ga += __shfl_xor(ga, o, 64);
+        }
+        if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll 4
+          for (int i = gl; i < len; i += gsz) {
+            const double x = ga_[i], y = gb_[i];
+            ga_[i] = c * x - s * y;
+            gb_[i] = s * x + c * y;
+          }
+          if (!mode) {
+            double* ua = U + (size_t)a * m;
+            double* ub = U + (size_t)b * m;
+#pragma unroll 4
+            for (int i = gl; i < m; i += gsz) {
+              const double x = ua[i], y = ub[i];
+              ua[i] = c * x - s * y;
+              ub[i] = s * x + c * y;
+            }
+          }
+          if (gl == 0) {
+            sh.rotated = 1;
+            ++my_rot;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int any = sh.rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  if (P.work) {
+    if (my_rot) atomicAdd(&sh.nrot, my_rot);
+    __syncthreads();
+    if (tid == 0) {  // 3 dot products per pair and sweep, a rotation when applied
+      const double pairs = 0.5 * ncol * (ncol - 1.0);
+      *P.work = sweeps * pairs * 6.0 * len + (double)sh.nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
+    }
+  }
+  // nc columns carry singular values: mode 0 all m (the s0 zero ones too)
+  const int nc = mode ? ncol : m;
+  for (int c = tid; c < nc; c += 256) {
+    double s = 0.0;
+    const double* gc = G + (size_t)c * len;
+    for (int i = 0; i < len; ++i) s += gc[i] * gc[i];
+    nrm[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int c = tid; c < nc; c += 256) {
+    const double v = nrm[c];
+    int pos = 0;
+    for (int d = 0; d < nc; ++d) pos += (nrm[d] > v) || (nrm[d] == v && d < c);
+    P.sigma[pos] = v;
+    if (P.U) {
+      double* uo = P.U + (int64_t)pos * P.ldu;
+      if (mode) {
+        const double inv = v > 0.0 ? 1.0 / v : 0.0;
+        const double* gc = G + (size_t)c * len;
+        for (int i = 0; i < s0; ++i) uo[i] = 0.0;
+        for (int i = 0; i < len; ++i) uo[s0 + i] = gc[i] * inv;
+      } else {
+        for (int i = 0; i < m; ++i) uo[i] = U[i + (size_t)c * m];
+      }
+    }
+  }
+  for (int pos = nc + tid; pos < m; pos += 256) {  // mode 1: no vector beyond ncol
+    P.sigma[pos] = 0.0;
+    if (P.U)
+      for (int i = 0; i < m; ++i) P.U[i + (int64_t)pos * P.ldu] = 0.0;
+  }
+  if (P.rank) {
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int c = 0; c < nc; ++c) mx = fmax(mx, nrm[c]);
+      const double thr = fmax(P.eps, P.rtol * mx);
+      int k = 0;
+      for (int c = 0; c < nc; ++c) k += nrm[c] > thr;
+      *P.rank = k;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
                                                      double* __restrict__ scratch, size_t slot, int lds_cap) {
-  extern __shared__ double smem[];
-  __shared__ int rotated;
-  __shared__ unsigned int nrot;
-  const int tid = threadIdx.x;
+  __shared__ JacobiShared sh;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const JacobiProb P = probs[pi];
-    const int m = P.m, p = P.p, mode = P.mode;
-    if (tid == 0) nrot = 0;
-    const int s0 = P.skip ? min(max(*P.skip, 0), m) : 0;
-    // players: ncol columns of length len in G (len x ncol, column-major)
-    int ncol, len, coff;
-    if (mode) {
-      len = m - s0;
-      ncol = min(p, len);
-      coff = 0;
-    } else {
-      len = p;
-      ncol = m - s0;
-      coff = s0;
-    }
-    const bool in_lds = jacobi_need(p, m, mode) <= (size_t)lds_cap;
-    double* G = in_lds ? smem : scratch + (size_t)blockIdx.x * slot;
-    double* U = mode ? nullptr : G + (size_t)p * m;
-    double* nrm = (mode ? G + (size_t)p * m : U + (size_t)m * m);
-    if (mode) {
-      for (int e = tid; e < len * ncol; e += 256) {  // G(i, j) = R'(j, i)
-        const int i = e % len, j = e / len;
-        G[e] = P.R[j + (int64_t)i * P.ldr];
-      }
-    } else {
-      for (int e = tid; e < p * m; e += 256) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
-      for (int e = tid; e < m * m; e += 256) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    const int mm = ncol + (ncol & 1);  // players of the round-robin tournament
-    const int npairs = mm / 2;
-    const int gsz = npairs >= 64 ? 4 : (npairs >= 32 ? 8 : (npairs >= 16 ? 16 : (npairs >= 8 ? 32 : 64)));
-    const int groups = 256 / gsz;
-    const int g = tid / gsz, gl = tid % gsz;
-    // rotate while |a.b| exceeds the rounding level of a dot product of length len
-    const double tol = fmax(1e-15, 2.2e-16 * len);
-    unsigned int my_rot = 0;
-    int sweeps = 0;
-    for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
-      ++sweeps;
-      if (tid == 0) rotated = 0;
-      __syncthreads();
-      for (int rnd = 0; rnd < mm - 1; ++rnd) {
-        for (int pk = g; pk < npairs; pk += groups) {
-          int a, b;
-          if (pk == 0) {
-            a = mm - 1;
-            b = rnd;
-          } else {
-            a = (rnd + pk) % (mm - 1);
-            b = (rnd - pk + (mm - 1)) % (mm - 1);
-          }
-          const bool live = a < ncol && b < ncol;
-          a += coff;
-          b += coff;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          double* ga_ = G + (size_t)a * len;
-          double* gb_ = G + (size_t)b * len;
-          if (live)
-            for (int i = gl; i < len; i += gsz) {
-              const double x = ga_[i], y = gb_[i];
-              al += x * x;
-              be += y * y;
-              ga += x * y;
-            }
-          for (int o = gsz / 2; o >= 1; o >>= 1) {  // gsz divides 64
-            al += __shfl_xor(al, o, 64);
-            be += __shfl_xor(be, o, 64);
-            ga += __shfl_xor(ga, o, 64);
-          }
-          if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-            for (int i = gl; i < len; i += gsz) {
-              const double x = ga_[i], y = gb_[i];
-              ga_[i] = c * x - s * y;
-              gb_[i] = s * x + c * y;
-            }
-            if (!mode) {
-              double* ua = U + (size_t)a * m;
-              double* ub = U + (size_t)b * m;
-              for (int i = gl; i < m; i += gsz) {
-                const double x = ua[i], y = ub[i];
-                ua[i] = c * x - s * y;
-                ub[i] = s * x + c * y;
-              }
-            }
-            if (gl == 0) {
-              rotated = 1;
-              ++my_rot;
-            }
-          }
-        }
-        __syncthreads();
-      }
-      const int any = rotated;
-      __syncthreads();
-      if (!any) break;
-    }
-    if (P.work) {
-      if (my_rot) atomicAdd(&nrot, my_rot);
-      __syncthreads();
-      if (tid == 0) {  // 3 dot products per pair and sweep, a rotation when applied
-        const double pairs = 0.5 * ncol * (ncol - 1.0);
-        *P.work = sweeps * pairs * 6.0 * len + (double)nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
-      }
-    }
-    // nc columns carry singular values: mode 0 all m (the s0 zero ones too)
-    const int nc = mode ? ncol : m;
-    for (int c = tid; c < nc; c += 256) {
-      double s = 0.0;
-      const double* gc = G + (size_t)c * len;
-      for (int i = 0; i < len; ++i) s += gc[i] * gc[i];
-      nrm[c] = sqrt(s);
-    }
-    __syncthreads();
-    for (int c = tid; c < nc; c += 256) {
-      const double v = nrm[c];
-      int pos = 0;
-      for (int d = 0; d < nc; ++d) pos += (nrm[d] > v) || (nrm[d] == v && d < c);
-      P.sigma[pos] = v;
-      if (P.U) {
-        double* uo = P.U + (int64_t)pos * P.ldu;
-        if (mode) {
-          const double inv = v > 0.0 ? 1.0 / v : 0.0;
-          const double* gc = G + (size_t)c * len;
-          for (int i = 0; i < s0; ++i) uo[i] = 0.0;
-          for (int i = 0; i < len; ++i) uo[s0 + i] = gc[i] * inv;
-        } else {
-          for (int i = 0; i < m; ++i) uo[i] = U[i + (size_t)c * m];
-        }
-      }
-    }
-    for (int pos = nc + tid; pos < m; pos += 256) {  // mode 1: no vector beyond ncol
-      P.sigma[pos] = 0.0;
-      if (P.U)
-        for (int i = 0; i < m; ++i) P.U[i + (int64_t)pos * P.ldu] = 0.0;
-    }
-    if (P.rank) {
-      __syncthreads();
-      if (tid == 0) {
-        double mx = 0.0;
-        for (int c = 0; c < nc; ++c) mx = fmax(mx, nrm[c]);
-        const double thr = fmax(P.eps, P.rtol * mx);
-        int k = 0;
-        for (int c = 0; c < nc; ++c) k += nrm[c] > thr;
-        *P.rank = k;
-      }
-    }
+    if (threadIdx.x == 0) sh.nrot = 0;
+    const int s0 = P.skip ? min(max(*P.skip, 0), P.m) : 0;
+    if (jacobi_need(P.p, P.m, P.mode) <= (size_t)lds_cap)
+      jacobi_solve(P, lds_dyn, s0, sh);
+    else
+      jacobi_solve(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
     __syncthreads();
   }
 }
