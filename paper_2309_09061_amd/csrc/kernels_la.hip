@@ -30,11 +30,32 @@ typedef double v4d __attribute__((ext_vector_type(4)));
     if (e_ != hipSuccess) fail(H2_ERR_DEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane sums.  Within a row of 16 lanes DPP moves are used (register
+// to register, no LDS round trip): quad_perm [1,0,3,2] and [2,3,0,1] pair
+// lanes at distance 1 and 2, row_half_mirror (i <-> 7 - i) joins the two
+// quads of each group of 8, row_mirror (i <-> 15 - i) the two halves of each
+// row.  Every lane of a group ends with the same, order-independent sum
+// because each step adds two equal partial sums in either order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over aligned groups of g lanes (g a power of two <= 64, uniform); all
+// lanes of a group must be active
+__device__ __forceinline__ double group_sum(double v, int g) {
+  if (g >= 2) v += dpp_move<0xB1>(v);
+  if (g >= 4) v += dpp_move<0x4E>(v);
+  if (g >= 8) v += dpp_move<0x141>(v);
+  if (g >= 16) v += dpp_move<0x140>(v);
+  if (g >= 32) v += __shfl_xor(v, 16, 64);
+  if (g >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
+
+__device__ inline double wave_sum(double v) { return group_sum(v, 64); }
 
 // block-wide sum for 256 threads (4 waves); `red` has >= 4 doubles
 __device__ inline double block_sum(double v, double* red) {
@@ -169,10 +190,9 @@ __device__ __forceinline__ void householder_qr(double* W, int64_t ld, int m, int
           }
           if (i < m) d0 += v[i] * wc[i];
         }
-        double d = d0 + d1;
-        for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+        const double d_ = group_sum(d0 + d1, tpc);
         if (live) {
-          d *= t;
+          const double d = d_ * t;
           if (gl == 0) wc[jj] -= d;
 #pragma unroll 4
           for (int i = jj + 1 + gl; i < m; i += tpc) wc[i] -= d * v[i];
@@ -377,11 +397,10 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch
             }
             if (i < cr) d0 += cj[i] * cc[i];
           }
-          double d = d0 + d1;
-          for (int o = tpc / 2; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+          const double dsum = group_sum(d0 + d1, tpc);
           if (live) {
             double* rj = B + jj + (int64_t)c * ld;
-            d = tau * (*rj + scal * d);
+            const double d = tau * (*rj + scal * dsum);
             if (gl == 0) *rj -= d;
             const double f = d * scal;
 #pragma unroll 4
@@ -502,7 +521,7 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   const int groups = 256 / gsz;
   const int g = tid / gsz, gl = tid % gsz;
   // rotate while |a.b| exceeds the rounding level of a dot product of length len
-  const double tol = fmax(1e-15, 2.2e-16 * len);
+  const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
   unsigned int my_rot = 0;
   int sweeps = 0;
   for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
@@ -534,12 +553,10 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
             ga += x * y;
           }
         }
-        for (int o = gsz / 2; o >= 1; o >>= 1) {  // gsz divides 64
-          al += __shfl_xor(al, o, 64);
-          be += __shfl_xor(be, o, 64);
-          ga += __shfl_xor(ga, o, 64);
-        }
-        if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+        al = group_sum(al, gsz);
+        be = group_sum(be, gsz);
+        ga = group_sum(ga, gsz);
+        if (live && al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
