@@ -34,6 +34,7 @@ static void need_device(const h2_ctx* ctx) {
 
 static void begin_call(h2_ctx* ctx, bool reset_steps = false) {
   ctx->ws.reset();
+  if (ctx->aux) ctx->aux->ws.reset();  // its earlier work is ordered before ours
   if (reset_steps)
     for (double& v : ctx->step_ms) v = 0.0;
 }
@@ -72,6 +73,7 @@ h2_status h2_ctx_destroy(h2_ctx* ctx) {
     if (!ctx->host_only) {
       dev_set_device(ctx->device);
       dev_sync(ctx->stream);
+      if (ctx->aux) dev_sync(ctx->aux->stream);
     }
     delete ctx;
   });
@@ -174,6 +176,7 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
       G_out[i] = G;
     }
     steps_collect(ctx);
+    aux_collect(ctx);
   });
 }
 
@@ -201,6 +204,7 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     begin_call(ctx);
     for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);
     steps_collect(ctx);
+    aux_collect(ctx);
   });
 }
 

@@ -57,6 +57,20 @@ void dev_zero(void* dst, size_t bytes, void* stream) {
 }
 void dev_sync(void* stream) { HIP_OK(hipStreamSynchronize((hipStream_t)stream)); }
 
+// a second stream for independent passes: default priority, not ordered with
+// the legacy null stream (ordering is explicit through events)
+void* dev_stream_create() {
+  hipStream_t s;
+  HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  return (void*)s;
+}
+void dev_stream_destroy(void* s) {
+  if (s) (void)hipStreamDestroy((hipStream_t)s);
+}
+void dev_stream_wait(void* stream, void* ev) {
+  HIP_OK(hipStreamWaitEvent((hipStream_t)stream, (hipEvent_t)ev, 0));
+}
+
 void* dev_event_create() {
   hipEvent_t e;
   HIP_OK(hipEventCreate(&e));

@@ -13,6 +13,9 @@
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
+#include <exception>
+#include <functional>
+#include <thread>
 #include <vector>
 
 #include "../../include/h2.h"
@@ -45,6 +48,9 @@ void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
 void dev_zero(void* dst, size_t bytes, void* stream);
 void dev_sync(void* stream);
+void* dev_stream_create();
+void dev_stream_destroy(void* s);
+void dev_stream_wait(void* stream, void* ev);
 void* dev_event_create();
 void dev_event_destroy(void* ev);
 void dev_event_record(void* ev, void* stream);
@@ -303,6 +309,10 @@ struct h2_ctx {
   size_t prof_chunk = 0, prof_used = 0;
   std::vector<h2::PendingLaunch> pending;
   h2::KernelStat kstat[h2::KK_COUNT];
+  // second context on the same device (own stream, workspace, staging) for
+  // the column passes, which run concurrently with the row passes
+  h2_ctx* aux = nullptr;
+  bool own_stream = false;
   ~h2_ctx();
 };
 
@@ -316,6 +326,7 @@ struct h2_matrix {
   h2_ctx* ctx = nullptr;
   h2::H2Core c;
   h2::Arena mem;
+  h2::Arena mem_aux;  // results of the column pass (allocated by the auxiliary context)
   bool zero = false;
 };
 
@@ -323,6 +334,7 @@ struct h2_product {
   h2_ctx* ctx = nullptr;
   h2::H2Core c;
   h2::Arena mem;
+  h2::Arena mem_aux;  // results of the column pass (allocated by the auxiliary context)
   int64_t n_triples = 0;
 };
 
@@ -366,6 +378,24 @@ void kernel_stats_collect(h2_ctx* ctx);
 void step_begin(h2_ctx* ctx, int step);
 void step_end(h2_ctx* ctx, int step);
 void steps_collect(h2_ctx* ctx);
+
+void* pool_event(h2_ctx* ctx);
+// the auxiliary context of ctx (created on first use)
+h2_ctx* aux_ctx(h2_ctx* ctx);
+// Runs f(aux) on a host thread, on the auxiliary stream, ordered after the
+// work queued so far on ctx->stream.  join() waits for the thread, makes
+// ctx->stream wait for the auxiliary work, and rethrows its exception.
+struct AuxRun {
+  h2_ctx* ctx;
+  h2_ctx* aux;
+  std::thread th;
+  std::exception_ptr err;
+  AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f);
+  void join();
+  ~AuxRun();
+};
+// step times and launch statistics of the auxiliary context, folded into ctx
+void aux_collect(h2_ctx* ctx);
 
 // batched launch builders
 struct GemmBatch {

@@ -214,21 +214,23 @@ __global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, d
                               size_t slot, int lds_cap);
 
 int lds_limit_doubles() {
-  static int limit = -1;
-  if (limit >= 0) return limit;
-  int dev = 0, maxb = 0;
-  HIP_OK(hipGetDevice(&dev));
-  if (hipDeviceGetAttribute(&maxb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxb = 65536;
-  // 2 KiB stay for static shared data
-  int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
-  const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
-                      (const void*)jacobi_kernel};
-  for (const void* k : ks)
-    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      bytes = std::min(bytes, 64 * 1024 - 2048);
-    }
-  limit = bytes / 8;
+  // computed once (thread-safe static initialisation): the passes run on two
+  // host threads
+  static const int limit = [] {
+    int dev = 0, maxb = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&maxb, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) maxb = 65536;
+    // 2 KiB stay for static shared data
+    int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
+    const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
+                        (const void*)jacobi_kernel};
+    for (const void* k : ks)
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        bytes = std::min(bytes, 64 * 1024 - 2048);
+      }
+    return bytes / 8;
+  }();
   return limit;
 }
 

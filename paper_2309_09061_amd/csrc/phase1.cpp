@@ -400,9 +400,15 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       sym_err = std::current_exception();
     }
   });
+  // row pass (X, Y) here, column pass (Y^*, X^*) concurrently on the
+  // auxiliary context; the two share only read-only inputs
   P1Side row, col;
-  induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2);
-  induced_pass(ctx, Yt, Xt, eps, G->mem, col, 0, 3);
+  G->mem_aux.ctx = aux_ctx(ctx);
+  {
+    AuxRun colrun(ctx, [&](h2_ctx* a) { induced_pass(a, Yt, Xt, eps, G->mem_aux, col, 0, 3); });
+    induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2);
+    colrun.join();
+  }
 
   step_begin(ctx, 1);  // the part of the symbolic build not hidden by the passes
   sym.th.join();

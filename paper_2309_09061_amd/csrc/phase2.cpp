@@ -466,9 +466,15 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
   k_sumsq(upload(ctx, items), upload(ctx, sp), TIK.nblocks(), omega, 1, ctx->stream);
 
   View Gr{&Gp->c, false}, Gc{&Gp->c, true};
+  // row pass on G here, column pass on G^* concurrently on the auxiliary
+  // context; both read G, tag and omega only
   P2Side row, col;
-  coarse_pass(ctx, Gr, tag, TIK, omega, eps, Z->mem, row, 5);
-  coarse_pass(ctx, Gc, tag, TIK, omega, eps, Z->mem, col, 6);
+  Z->mem_aux.ctx = aux_ctx(ctx);
+  {
+    AuxRun colrun(ctx, [&](h2_ctx* a) { coarse_pass(a, Gc, tag, TIK, omega, eps, Z->mem_aux, col, 6); });
+    coarse_pass(ctx, Gr, tag, TIK, omega, eps, Z->mem, row, 5);
+    colrun.join();
+  }
 
   // ---- Z: couplings Q^Z_t^* G|_b Q^ZW_r bottom-up, nearfield copied ----
   step_begin(ctx, 7);

@@ -131,7 +131,7 @@ void steps_collect(h2_ctx* ctx) {
 // ---------------------------------------------------------------------------
 // launch timers: one pair of events per launch, resolved at collection
 // ---------------------------------------------------------------------------
-static void* pool_event(h2_ctx* ctx) {
+void* pool_event(h2_ctx* ctx) {
   if (ctx->ev_pool.empty()) return dev_event_create();
   void* e = ctx->ev_pool.back();
   ctx->ev_pool.pop_back();
@@ -170,7 +170,87 @@ WorkCounts work_counts(h2_ctx* ctx, int n) {
   return w;
 }
 
+// ---------------------------------------------------------------------------
+// auxiliary context: the column passes run on it concurrently with the row
+// passes (own stream, workspace, staging, events; same device)
+// ---------------------------------------------------------------------------
+h2_ctx* aux_ctx(h2_ctx* ctx) {
+  if (!ctx->aux) {
+    auto* a = new h2_ctx();
+    a->device = ctx->device;
+    a->host_only = false;
+    a->ws.ctx = a;
+    try {
+      a->stream = dev_stream_create();
+      a->own_stream = true;
+      a->stage_cap = (size_t)16 << 20;
+      a->stage = (char*)dev_malloc_host(a->stage_cap);
+    } catch (...) {
+      delete a;
+      throw;
+    }
+    ctx->aux = a;
+  }
+  return ctx->aux;
+}
+
+AuxRun::AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f) : ctx(c), aux(aux_ctx(c)) {
+  aux->profile = ctx->profile;
+  aux->prec = ctx->prec;
+  void* e = pool_event(ctx);
+  dev_event_record(e, ctx->stream);
+  dev_stream_wait(aux->stream, e);  // the wait takes the event as recorded now
+  ctx->ev_pool.push_back(e);
+  const int dev = ctx->device;
+  h2_ctx* a = aux;
+  th = std::thread([this, f, dev, a] {
+    try {
+      dev_set_device(dev);  // the current device is per host thread
+      f(a);
+    } catch (...) {
+      err = std::current_exception();
+    }
+  });
+}
+
+void AuxRun::join() {
+  if (th.joinable()) th.join();
+  void* e = pool_event(aux);
+  dev_event_record(e, aux->stream);
+  dev_stream_wait(ctx->stream, e);
+  aux->ev_pool.push_back(e);
+  if (err) {
+    std::exception_ptr x = err;
+    err = nullptr;
+    std::rethrow_exception(x);
+  }
+}
+
+AuxRun::~AuxRun() {
+  if (th.joinable()) th.join();
+}
+
+void aux_collect(h2_ctx* ctx) {
+  h2_ctx* a = ctx->aux;
+  if (!a) return;
+  steps_collect(a);
+  for (int i = 0; i < 8; ++i) {
+    ctx->step_ms[i] += a->step_ms[i];
+    a->step_ms[i] = 0.0;
+  }
+}
+
 void kernel_stats_collect(h2_ctx* ctx) {
+  if (ctx->aux) {
+    kernel_stats_collect(ctx->aux);
+    for (int k = 0; k < KK_COUNT; ++k) {
+      ctx->kstat[k].ms += ctx->aux->kstat[k].ms;
+      ctx->kstat[k].flops += ctx->aux->kstat[k].flops;
+      ctx->kstat[k].bytes += ctx->aux->kstat[k].bytes;
+      ctx->kstat[k].launches += ctx->aux->kstat[k].launches;
+      ctx->aux->kstat[k] = KernelStat{};
+    }
+  }
   for (auto& p : ctx->pending) {
     KernelStat& k = ctx->kstat[p.kind];
     k.ms += dev_event_ms(p.a, p.b);
@@ -512,6 +592,7 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
 }  // namespace h2
 
 h2_ctx::~h2_ctx() {
+  delete aux;
   for (auto& p : pending) {
     h2::dev_event_destroy(p.a);
     h2::dev_event_destroy(p.b);
@@ -523,4 +604,5 @@ h2_ctx::~h2_ctx() {
   if (stage) h2::dev_free_host(stage);
   for (auto& c : prof_host) h2::dev_free_host(c.first);
   for (void* e : events) h2::dev_event_destroy(e);
+  if (own_stream) h2::dev_stream_destroy(stream);
 }

@@ -201,11 +201,31 @@ std::shared_ptr<BlockTreeH> build_block_tree(const TreeH& rt, const TreeH& ct, d
 // factor.  The triples (t,s,r) reaching a block are recorded: terminated
 // ones with their kind (both factors admissible, only (t,s), only (s,r),
 // neither).
+// child (a, c) (a: row child, c: column child, 1 or 2, view coordinates) of
+// the subdivided block b of a view; block trees list the four children of a
+// block row-child-major
+static inline int view_child(const View& V, int b, int a, int c) {
+  const int c0 = V.m->bt->child0[b];
+  return V.T ? c0 + (c - 1) * 2 + (a - 1) : c0 + (a - 1) * 2 + (c - 1);
+}
+
 ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
   ProductTreeH P;
   auto B = std::make_shared<BlockTreeH>();
   P.bt = B;
-  std::vector<std::vector<int32_t>> mids_cur{{0}}, mids_next;
+  // middle triples (s, block of X, block of Y) reaching each block of the
+  // current level, stored flat with offsets; the children of subdivided
+  // factor blocks are found by index (no searches)
+  struct Mid {
+    int32_t s, bx, by;
+  };
+  std::vector<Mid> mids_cur, mids_next, rec;
+  std::vector<int64_t> off_cur{0, 1}, off_next;
+  {
+    const int bx = X.find(0, 0), by = Y.find(0, 0);
+    H2_REQUIRE(bx >= 0 && by >= 0, H2_ERR_SHAPE, "product tree: missing root block");
+    mids_cur.push_back({0, bx, by});
+  }
   B->lvl.push_back(0);
   B->t.push_back(0);
   B->s.push_back(0);
@@ -214,17 +234,16 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
   for (int l = 0; l <= depth; ++l) {
     int b0 = B->lvl[l], b1 = (int)B->t.size();
     mids_next.clear();
+    off_next.assign(1, 0);
     for (int b = b0; b < b1; ++b) {
-      int tt = B->t[b], rr = B->s[b];
-      const auto& mids = mids_cur[b - b0];
-      std::vector<int32_t> rec;
+      const int tt = B->t[b], rr = B->s[b];
+      rec.clear();
       bool nn = false;
-      for (int32_t s : mids) {
-        int bx = X.find(tt, s), by = Y.find(s, rr);
-        H2_REQUIRE(bx >= 0 && by >= 0, H2_ERR_SHAPE, "product tree: missing factor block");
-        int8_t tx = X.type(bx), ty = Y.type(by);
+      for (int64_t q = off_cur[b - b0]; q < off_cur[b - b0 + 1]; ++q) {
+        const Mid& md = mids_cur[q];
+        const int8_t tx = X.type(md.bx), ty = Y.type(md.by);
         if (tx == BT_SPLIT && ty == BT_SPLIT) {
-          rec.push_back(s);
+          rec.push_back(md);
           continue;
         }
         int8_t kind;
@@ -240,7 +259,7 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
           kind = TK_NN;
           nn = true;
         }
-        P.tri.push_back({s, bx, by, kind});
+        P.tri.push_back({md.s, md.bx, md.by, kind});
         P.n_terminated++;
       }
       P.tri_ptr.push_back((int32_t)P.tri.size());
@@ -250,16 +269,12 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
         B->child0.push_back((int)B->t.size());
         for (int a = 1; a <= 2; ++a)
           for (int c = 1; c <= 2; ++c) {
-            int tc = 2 * tt + a, rc = 2 * rr + c;
-            B->t.push_back(tc);
-            B->s.push_back(rc);
-            std::vector<int32_t> sub;
-            for (int32_t s : rec)
-              for (int q = 1; q <= 2; ++q) {
-                int sc = 2 * s + q;
-                if (X.find(tc, sc) >= 0 && Y.find(sc, rc) >= 0) sub.push_back(sc);
-              }
-            mids_next.push_back(std::move(sub));
+            B->t.push_back(2 * tt + a);
+            B->s.push_back(2 * rr + c);
+            for (const Mid& md : rec)
+              for (int q = 1; q <= 2; ++q)
+                mids_next.push_back({2 * md.s + q, view_child(X, md.bx, a, q), view_child(Y, md.by, q, c)});
+            off_next.push_back((int64_t)mids_next.size());
           }
       } else {
         B->type.push_back(nn ? BT_INADM : BT_ADM);
@@ -268,6 +283,7 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
     }
     B->lvl.push_back(b1);
     mids_cur.swap(mids_next);
+    off_cur.swap(off_next);
   }
   B->finalize(ncl);
   return P;
