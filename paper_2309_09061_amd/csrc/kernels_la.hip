@@ -212,6 +212,7 @@ __global__ void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob, doubl
                             size_t slot, int lds_cap);
 __global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
                               size_t slot, int lds_cap);
+__global__ void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob, int per);
 
 int lds_limit_doubles() {
   // computed once (thread-safe static initialisation): the passes run on two
@@ -223,7 +224,7 @@ int lds_limit_doubles() {
     // 2 KiB stay for static shared data
     int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
     const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
-                        (const void*)jacobi_kernel};
+                        (const void*)jacobi_kernel, (const void*)jacobi_small_kernel};
     for (const void* k : ks)
       if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -488,9 +489,24 @@ struct JacobiShared {
   unsigned int nrot;
 };
 
-// one problem on the buffer G (jacobi_need doubles)
+// synchronisation of the NT threads working on one problem: the workgroup
+// (NT = 256) or one wavefront (NT = 64, lanes run in lockstep; the fences
+// keep the compiler from moving LDS accesses across the step boundary)
+template <int NT>
+__device__ __forceinline__ void team_sync() {
+  if (NT == 256) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// one problem on the buffer G (jacobi_need doubles) by NT threads
+template <int NT>
 __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int s0, JacobiShared& sh) {
-  const int tid = threadIdx.x;
+  const int tid = NT == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
   const int m = P.m, p = P.p, mode = P.mode;
   // players: ncol columns of length len in G (len x ncol, column-major)
   int ncol, len, coff;
@@ -506,21 +522,21 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   double* U = mode ? nullptr : G + (size_t)p * m;
   double* nrm = mode ? G + (size_t)p * m : U + (size_t)m * m;
   if (mode) {
-    for (int e = tid; e < len * ncol; e += 256) {  // G(i, j) = R'(j, i)
+    for (int e = tid; e < len * ncol; e += NT) {  // G(i, j) = R'(j, i)
       const int i = e % len, j = e / len;
       G[e] = P.R[j + (int64_t)i * P.ldr];
     }
   } else {
-    for (int e = tid; e < p * m; e += 256) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
-    for (int e = tid; e < m * m; e += 256) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
+    for (int e = tid; e < p * m; e += NT) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
+    for (int e = tid; e < m * m; e += NT) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  team_sync<NT>();
   const int mm = ncol + (ncol & 1);  // players of the round-robin tournament
   const int npairs = mm / 2;
   // lanes per pair: all pairs of a round at once where possible
   int gsz = 64;
-  while (gsz > 4 && gsz * npairs > 256) gsz >>= 1;
-  const int groups = 256 / gsz;
+  while (gsz > 4 && gsz * npairs > NT) gsz >>= 1;
+  const int groups = NT / gsz;
   const int g = tid / gsz, gl = tid % gsz;
   // rotate while |a.b| exceeds the rounding level of a dot product of length len
   const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
@@ -528,8 +544,11 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   int sweeps = 0;
   for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
     ++sweeps;
-    if (tid == 0) sh.rotated = 0;
-    __syncthreads();
+    int rot_here = 0;
+    if (NT == 256) {
+      if (tid == 0) sh.rotated = 0;
+      team_sync<NT>();
+    }
     for (int rnd = 0; rnd < mm - 1; ++rnd) {
       for (int pk = g; pk < npairs; pk += groups) {
         int a, b;
@@ -579,35 +598,48 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
             }
           }
           if (gl == 0) {
-            sh.rotated = 1;
+            rot_here = 1;
             ++my_rot;
           }
         }
       }
-      __syncthreads();
+      team_sync<NT>();
     }
-    const int any = sh.rotated;
-    __syncthreads();
+    int any;
+    if (NT == 256) {
+      if (rot_here) sh.rotated = 1;
+      team_sync<NT>();
+      any = sh.rotated;
+      team_sync<NT>();
+    } else {
+      any = __any(rot_here);
+    }
     if (!any) break;
   }
   if (P.work) {
-    if (my_rot) atomicAdd(&sh.nrot, my_rot);
-    __syncthreads();
+    double nrot;
+    if (NT == 256) {
+      if (my_rot) atomicAdd(&sh.nrot, my_rot);
+      team_sync<NT>();
+      nrot = sh.nrot;
+    } else {
+      nrot = group_sum((double)my_rot, 64);
+    }
     if (tid == 0) {  // 3 dot products per pair and sweep, a rotation when applied
       const double pairs = 0.5 * ncol * (ncol - 1.0);
-      *P.work = sweeps * pairs * 6.0 * len + (double)sh.nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
+      *P.work = sweeps * pairs * 6.0 * len + nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
     }
   }
   // nc columns carry singular values: mode 0 all m (the s0 zero ones too)
   const int nc = mode ? ncol : m;
-  for (int c = tid; c < nc; c += 256) {
+  for (int c = tid; c < nc; c += NT) {
     double s = 0.0;
     const double* gc = G + (size_t)c * len;
     for (int i = 0; i < len; ++i) s += gc[i] * gc[i];
     nrm[c] = sqrt(s);
   }
-  __syncthreads();
-  for (int c = tid; c < nc; c += 256) {
+  team_sync<NT>();
+  for (int c = tid; c < nc; c += NT) {
     const double v = nrm[c];
     int pos = 0;
     for (int d = 0; d < nc; ++d) pos += (nrm[d] > v) || (nrm[d] == v && d < c);
@@ -624,21 +656,18 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
       }
     }
   }
-  for (int pos = nc + tid; pos < m; pos += 256) {  // mode 1: no vector beyond ncol
+  for (int pos = nc + tid; pos < m; pos += NT) {  // mode 1: no vector beyond ncol
     P.sigma[pos] = 0.0;
     if (P.U)
       for (int i = 0; i < m; ++i) P.U[i + (int64_t)pos * P.ldu] = 0.0;
   }
-  if (P.rank) {
-    __syncthreads();
-    if (tid == 0) {
-      double mx = 0.0;
-      for (int c = 0; c < nc; ++c) mx = fmax(mx, nrm[c]);
-      const double thr = fmax(P.eps, P.rtol * mx);
-      int k = 0;
-      for (int c = 0; c < nc; ++c) k += nrm[c] > thr;
-      *P.rank = k;
-    }
+  if (P.rank && tid == 0) {
+    double mx = 0.0;
+    for (int c = 0; c < nc; ++c) mx = fmax(mx, nrm[c]);
+    const double thr = fmax(P.eps, P.rtol * mx);
+    int k = 0;
+    for (int c = 0; c < nc; ++c) k += nrm[c] > thr;
+    *P.rank = k;
   }
 }
 
@@ -650,11 +679,26 @@ __global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restric
     if (threadIdx.x == 0) sh.nrot = 0;
     const int s0 = P.skip ? min(max(*P.skip, 0), P.m) : 0;
     if (jacobi_need(P.p, P.m, P.mode) <= (size_t)lds_cap)
-      jacobi_solve(P, lds_dyn, s0, sh);
+      jacobi_solve<256>(P, lds_dyn, s0, sh);
     else
-      jacobi_solve(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
+      jacobi_solve<256>(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
     __syncthreads();
   }
+}
+
+// small problems (at most kJacobiSmallM columns): one wavefront per problem,
+// four per workgroup, each on its own slice of `per` doubles of LDS
+constexpr int kJacobiSmallM = 32;
+
+__global__ __launch_bounds__(256) void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob,
+                                                           int per) {
+  const int wave = threadIdx.x >> 6;
+  const int pi = blockIdx.x * 4 + wave;
+  if (pi >= nprob) return;  // the whole wavefront leaves; no workgroup barriers below
+  const JacobiProb P = probs[pi];
+  const int s0 = P.skip ? min(max(*P.skip, 0), P.m) : 0;
+  JacobiShared unused;
+  jacobi_solve<64>(P, lds_dyn + (size_t)wave * per, s0, unused);
 }
 
 void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream) {
@@ -663,6 +707,16 @@ void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, doub
   const int grid = slot == 0 ? n : std::min(n, 1024);
   hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream,
                      probs, n, scratch, slot, lds_doubles);
+  HIP_OK(hipGetLastError());
+}
+
+int jacobi_small_max_m() { return kJacobiSmallM; }
+
+void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* stream) {
+  if (n <= 0) return;
+  H2_REQUIRE((size_t)4 * per_doubles <= (size_t)lds_limit_doubles(), H2_ERR_ARG, "jacobi: small problems too large");
+  hipLaunchKernelGGL(jacobi_small_kernel, dim3((n + 3) / 4), dim3(256), (size_t)4 * per_doubles * 8,
+                     (hipStream_t)stream, probs, n, per_doubles);
   HIP_OK(hipGetLastError());
 }
 

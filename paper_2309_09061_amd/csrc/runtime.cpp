@@ -522,32 +522,53 @@ void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, in
 
 void JacobiBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  const size_t lim = (size_t)lds_limit_doubles();
-  size_t slot = 0, lds = 0;
-  double flops = 0, bytes = 0;
-  for (const JacobiProb& j : p) {
-    size_t need = jacobi_need_doubles(j.p, j.m, j.mode);
-    if (need > lim)
-      slot = std::max(slot, need);
-    else
-      lds = std::max(lds, need);
-    // one sweep over the pairs of players: 3 dot products and a rotation per pair
-    double pl = j.mode ? j.p : j.m, len = j.mode ? j.m : j.p;
-    flops += pl * (pl - 1) / 2 * (6.0 * len + (j.mode ? 0.0 : 6.0 * j.m));
-    bytes += 8.0 * ((double)j.p * j.m + (j.U ? (double)j.m * j.m : 0.0));
-  }
-  double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
   WorkCounts wc = work_counts(ctx, (int)p.size());
   if (wc.dev)
     for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
-  JacobiProb* d = upload(ctx, p);
-  {
-    LaunchTimer lt(ctx, KK_JACOBI, flops, bytes);
-    lt.work = wc.host;
-    lt.nwork = wc.n;
-    k_jacobi(d, (int)p.size(), lds_for(lds), slot, scratch, ctx->stream);
+  // small problems: one wavefront each; the rest: one workgroup each
+  const size_t lim = (size_t)lds_limit_doubles();
+  std::vector<JacobiProb> small, large;
+  size_t per = 0, slot = 0, lds = 0;
+  double flops_s = 0, bytes_s = 0, flops_l = 0, bytes_l = 0;
+  for (const JacobiProb& j : p) {
+    const size_t need = jacobi_need_doubles(j.p, j.m, j.mode);
+    // one sweep over the pairs of players: 3 dot products and a rotation per pair
+    const double pl = j.mode ? j.p : j.m, len = j.mode ? j.m : j.p;
+    const double f = pl * (pl - 1) / 2 * (6.0 * len + (j.mode ? 0.0 : 6.0 * j.m));
+    const double by = 8.0 * ((double)j.p * j.m + (j.U ? (double)j.m * j.m : 0.0));
+    if (j.m <= jacobi_small_max_m() && 4 * need <= lim) {
+      small.push_back(j);
+      per = std::max(per, need);
+      flops_s += f;
+      bytes_s += by;
+    } else {
+      large.push_back(j);
+      if (need > lim)
+        slot = std::max(slot, need);
+      else
+        lds = std::max(lds, need);
+      flops_l += f;
+      bytes_l += by;
+    }
   }
-  if (wc.dev) dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
+  if (!small.empty()) {
+    JacobiProb* d = upload(ctx, small);
+    LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_s, bytes_s);
+    k_jacobi_small(d, (int)small.size(), (int)per, ctx->stream);
+  }
+  if (!large.empty()) {
+    double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(large.size(), 1024)) : nullptr;
+    JacobiProb* d = upload(ctx, large);
+    LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_l, bytes_l);
+    k_jacobi(d, (int)large.size(), lds_for(lds), slot, scratch, ctx->stream);
+  }
+  if (wc.dev) {  // counts of both launches, resolved with the second one's timing
+    dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
+    if (!ctx->pending.empty()) {
+      ctx->pending.back().work = wc.host;
+      ctx->pending.back().nwork = wc.n;
+    }
+  }
   p.clear();
   max_m = 0;
 }
