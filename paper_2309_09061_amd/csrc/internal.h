@@ -148,6 +148,11 @@ int lds_limit_doubles();
 size_t qr_need_doubles(int m, int n);
 size_t tsqr_lds_need(int m, int cap);
 size_t tsqr_scratch_need(int m);
+// register-blocked TSQR variants (1..3; 0 = none fits) for problems whose
+// factored width is at most m, and their LDS need in doubles
+int tsqr_rb_variant(int m, int cap);
+size_t tsqr_rb_need(int variant, int m);
+void k_tsqr_rb(int variant, const TsqrProb* probs, int n, size_t lds_doubles, void* stream);
 size_t jacobi_need_doubles(int p, int m, int mode);
 void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream);
 void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_doubles, void* stream);

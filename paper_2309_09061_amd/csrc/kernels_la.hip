@@ -213,6 +213,8 @@ __global__ void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob, doubl
 __global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
                               size_t slot, int lds_cap);
 __global__ void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob, int per);
+template <int G, int CPT, int RPT>
+__global__ void tsqr_rb_kernel(const TsqrProb* __restrict__ probs, int nprob);
 
 int lds_limit_doubles() {
   // computed once (thread-safe static initialisation): the passes run on two
@@ -224,7 +226,9 @@ int lds_limit_doubles() {
     // 2 KiB stay for static shared data
     int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
     const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
-                        (const void*)jacobi_kernel, (const void*)jacobi_small_kernel};
+                        (const void*)jacobi_kernel, (const void*)jacobi_small_kernel,
+                        (const void*)tsqr_rb_kernel<16, 1, 8>, (const void*)tsqr_rb_kernel<8, 1, 16>,
+                        (const void*)tsqr_rb_kernel<8, 2, 8>};
     for (const void* k : ks)
       if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -457,6 +461,193 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __re
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Register-blocked TSQR for m - off <= 128 (one problem per 512-thread
+// workgroup).  Each column of the chunk belongs to a slot of G adjacent lanes
+// that hold its rows in registers (RPT each); a slot holds CPT columns.  Per
+// column jj the owning slot forms the reflector, one barrier publishes it
+// (double-buffered), and every slot updates its own columns in registers: the
+// chunk is read from LDS once per chunk instead of twice per column step.
+// LDS: R (me x me), chunk staging (CH x me), two reflector buffers.
+// ---------------------------------------------------------------------------
+template <int G, int CPT, int RPT>
+struct TsqrRB {
+  static constexpr int kSlots = kTsqrThreads / G;
+  static constexpr int kCH = G * RPT;
+  static __host__ __device__ size_t need(int me) {
+    return (size_t)(me + 1) * me + (size_t)kCH * me + 2 * kCH + 4;
+  }
+};
+using TsqrRB16 = TsqrRB<16, 1, 8>;  // me <= 32
+using TsqrRB64 = TsqrRB<8, 1, 16>;  // me <= 64
+using TsqrRB128 = TsqrRB<8, 2, 8>;  // me <= 128
+
+// Lane rg of a slot holds the chunk rows rg, rg + G, rg + 2G, ...: the G lanes
+// reading one reflector entry each then hit G consecutive doubles (distinct
+// LDS banks).  R is stored with the odd leading dimension me + 1 so that the
+// slots of a wavefront reading row jj of R hit distinct banks as well.
+template <int G, int CPT, int RPT>
+__global__ __launch_bounds__(kTsqrThreads) void tsqr_rb_kernel(const TsqrProb* __restrict__ probs, int nprob) {
+  using K = TsqrRB<G, CPT, RPT>;
+  constexpr int CH = K::kCH, SL = K::kSlots;
+  const int tid = threadIdx.x;
+  const int slot = tid / G, rg = tid % G;
+  for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
+    const TsqrProb P = probs[pi];
+    const int m = P.m, N = P.N;
+    const int off = P.col_off ? min(max(*P.col_off, 0), m) : 0;
+    const int me = m - off;
+    const int p = min(N, m);
+    if (N <= me) {  // T itself is a factor (see tsqr_kernel)
+      for (int e = tid; e < p * m; e += kTsqrThreads) {
+        const int i = e % p, j = e / p;
+        double v = 0.0;
+        if (j < me) v = tsqr_src(P, P.transA ? off + j + (int64_t)i * P.lda : i + (int64_t)(off + j) * P.lda);
+        P.R[i + (int64_t)j * P.ldr] = v;
+      }
+      if (tid == 0 && P.work) *P.work = 0.0;
+      __syncthreads();
+      continue;
+    }
+    const int ldr = me + 1;
+    double* R = lds_dyn;          // me x me, column-major, ld me + 1
+    double* S = R + ldr * me;     // CH x me staging, ld CH
+    double* vb = S + CH * me;     // 2 x CH reflector buffers (by chunk row)
+    double* sc = vb + 2 * CH;     // tau per buffer
+    for (int e = tid; e < ldr * me; e += kTsqrThreads) R[e] = 0.0;
+    for (int q0 = 0; q0 < N; q0 += CH) {
+      const int cr = min(CH, N - q0);
+      if (P.transA) {  // T(i, j) = A[j + i lda]: consecutive threads along j
+        for (int e = tid; e < CH * me; e += kTsqrThreads) {
+          const int j = e % me, i = e / me;
+          S[i + j * CH] = i < cr ? tsqr_src(P, off + j + (int64_t)(q0 + i) * P.lda) : 0.0;
+        }
+      } else {
+        for (int e = tid; e < CH * me; e += kTsqrThreads) {
+          const int i = e % CH, j = e / CH;
+          S[i + j * CH] = i < cr ? tsqr_src(P, (q0 + i) + (int64_t)(off + j) * P.lda) : 0.0;
+        }
+      }
+      __syncthreads();
+      double C[CPT][RPT];
+#pragma unroll
+      for (int cc = 0; cc < CPT; ++cc) {
+        const int col = slot + SL * cc;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) C[cc][k] = col < me ? S[rg + G * k + col * CH] : 0.0;
+      }
+      for (int jj = 0; jj < me; ++jj) {
+        const int buf = jj & 1;
+        const int os = jj % SL, oc = jj / SL;
+        // row jj of R for this slot's columns: final before step jj (prefetch)
+        double rv[CPT];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+          const int col = slot + SL * cc;
+          rv[cc] = (col > jj && col < me) ? R[jj + col * ldr] : 0.0;
+        }
+        if (slot == os) {
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int k = 0; k < RPT; k += 2) {
+            const double x0 = (CPT == 1 || oc == 0) ? C[0][k] : C[CPT - 1][k];
+            s0 += x0 * x0;
+            if (k + 1 < RPT) {
+              const double x1 = (CPT == 1 || oc == 0) ? C[0][k + 1] : C[CPT - 1][k + 1];
+              s1 += x1 * x1;
+            }
+          }
+          const double s = group_sum(s0 + s1, G);
+          const double alpha = R[jj + jj * ldr];
+          double tau = 0.0, scal = 0.0;
+          if (s > 0.0) {
+            const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+            if (rg == 0) R[jj + jj * ldr] = beta;
+          }
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) {
+            const double x = (CPT == 1 || oc == 0) ? C[0][k] : C[CPT - 1][k];
+            vb[buf * CH + rg + G * k] = x * scal;
+          }
+          if (rg == 0) sc[buf] = tau;
+        }
+        __syncthreads();
+        const double tau = sc[buf];
+        double v[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) v[k] = vb[buf * CH + rg + G * k];
+        if (tau != 0.0) {
+#pragma unroll
+          for (int cc = 0; cc < CPT; ++cc) {
+            const int col = slot + SL * cc;
+            if (col > jj && col < me) {  // uniform within the slot's G lanes
+              double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+              for (int k = 0; k < RPT; k += 2) {
+                d0 += v[k] * C[cc][k];
+                if (k + 1 < RPT) d1 += v[k + 1] * C[cc][k + 1];
+              }
+              const double d = group_sum(d0 + d1, G);
+              const double dd = tau * (rv[cc] + d);
+              if (rg == 0) R[jj + col * ldr] = rv[cc] - dd;
+#pragma unroll
+              for (int k = 0; k < RPT; ++k) C[cc][k] -= dd * v[k];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < p * m; e += kTsqrThreads) {
+      const int i = e % p, j = e / p;
+      P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? R[i + j * ldr] : 0.0;
+    }
+    if (tid == 0 && P.work) {  // Householder QR of an N x me matrix
+      const double dn = N, dm = me;
+      *P.work = 2.0 * dn * dm * dm - 2.0 * dm * dm * dm / 3.0;
+    }
+    __syncthreads();
+  }
+}
+
+int tsqr_rb_variant(int m, int cap) {
+  if (m <= 32 && TsqrRB16::need(m) <= (size_t)cap) return 1;
+  if (m <= 64 && TsqrRB64::need(m) <= (size_t)cap) return 2;
+  if (m <= 128 && TsqrRB128::need(m) <= (size_t)cap) return 3;
+  return 0;
+}
+
+size_t tsqr_rb_need(int variant, int m) {
+  switch (variant) {
+    case 1: return TsqrRB16::need(m);
+    case 2: return TsqrRB64::need(m);
+    case 3: return TsqrRB128::need(m);
+  }
+  return 0;
+}
+
+void k_tsqr_rb(int variant, const TsqrProb* probs, int n, size_t lds_doubles, void* stream) {
+  if (n <= 0) return;
+  H2_REQUIRE(lds_doubles <= (size_t)lds_limit_doubles(), H2_ERR_ARG, "tsqr: LDS request over the limit");
+  const size_t bytes = lds_doubles * 8;
+  switch (variant) {
+    case 1:
+      hipLaunchKernelGGL((tsqr_rb_kernel<16, 1, 8>), dim3(n), dim3(kTsqrThreads), bytes, (hipStream_t)stream, probs, n);
+      break;
+    case 2:
+      hipLaunchKernelGGL((tsqr_rb_kernel<8, 1, 16>), dim3(n), dim3(kTsqrThreads), bytes, (hipStream_t)stream, probs, n);
+      break;
+    case 3:
+      hipLaunchKernelGGL((tsqr_rb_kernel<8, 2, 8>), dim3(n), dim3(kTsqrThreads), bytes, (hipStream_t)stream, probs, n);
+      break;
+    default:
+      fail(H2_ERR_ARG, "tsqr: unknown variant");
+  }
+  HIP_OK(hipGetLastError());
 }
 
 void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, double* scratch, void* stream) {

@@ -469,34 +469,52 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
 
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  // per problem: LDS (chunk rows sized from the device limit) or a scratch slot
-  const int lim = lds_limit_doubles();
-  size_t slot = 0, lds = 0;
-  for (const TsqrProb& t : p) {
-    size_t need = tsqr_lds_need(t.m, lim);
-    if (need == 0)
-      slot = std::max(slot, tsqr_scratch_need(t.m));
-    else
-      lds = std::max(lds, need);
-  }
-  double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(p.size(), 1024)) : nullptr;
-  double flops = 0, bytes = 0;
-  for (const TsqrProb& t : p) {  // Householder QR of an N x m matrix: 2 N m^2 - 2 m^3 / 3
-    double N = t.N, m = t.m, r = std::min(N, m);
-    flops += 2.0 * N * m * m - 2.0 * r * r * r / 3.0;
-    bytes += 8.0 * (N * m + r * m);
-  }
   WorkCounts wc = work_counts(ctx, (int)p.size());
   if (wc.dev)
     for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
-  TsqrProb* d = upload(ctx, p);
-  {
-    LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
-    lt.work = wc.host;
-    lt.nwork = wc.n;
-    k_tsqr(d, (int)p.size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
+  // per problem: a register-blocked variant sized by m (the widest factored
+  // width), else the streaming kernel in LDS, else in a global scratch slot
+  const int lim = lds_limit_doubles();
+  std::vector<TsqrProb> rb[4];
+  size_t rb_need[4] = {0, 0, 0, 0};
+  double rb_flops[4] = {0, 0, 0, 0}, rb_bytes[4] = {0, 0, 0, 0};
+  size_t slot = 0, lds = 0;
+  for (const TsqrProb& t : p) {
+    double N = t.N, m = t.m, r = std::min(N, m);
+    const double f = 2.0 * N * m * m - 2.0 * r * r * r / 3.0, by = 8.0 * (N * m + r * m);
+    const int v = tsqr_rb_variant(t.m, lim);
+    rb[v].push_back(t);
+    rb_flops[v] += f;
+    rb_bytes[v] += by;
+    if (v) {
+      rb_need[v] = std::max(rb_need[v], tsqr_rb_need(v, t.m));
+    } else {
+      size_t need = tsqr_lds_need(t.m, lim);
+      if (need == 0)
+        slot = std::max(slot, tsqr_scratch_need(t.m));
+      else
+        lds = std::max(lds, need);
+    }
   }
-  if (wc.dev) dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
+  for (int v = 1; v <= 3; ++v) {
+    if (rb[v].empty()) continue;
+    TsqrProb* d = upload(ctx, rb[v]);
+    LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[v], rb_bytes[v]);
+    k_tsqr_rb(v, d, (int)rb[v].size(), rb_need[v], ctx->stream);
+  }
+  if (!rb[0].empty()) {
+    double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(rb[0].size(), 1024)) : nullptr;
+    TsqrProb* d = upload(ctx, rb[0]);
+    LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[0], rb_bytes[0]);
+    k_tsqr(d, (int)rb[0].size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
+  }
+  if (wc.dev) {  // counts of all launches, resolved with the last one's timing
+    dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
+    if (!ctx->pending.empty()) {
+      ctx->pending.back().work = wc.host;
+      ctx->pending.back().nwork = wc.n;
+    }
+  }
   p.clear();
   max_m = 0;
 }
