@@ -670,8 +670,19 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
 //          this way.  U(:, pos) = [0 (s0 rows); v_j] for pos < pe, else 0.
 // Singular values = column norms, sorted descending (ties by index).
 // ---------------------------------------------------------------------------
+// Column stride of the rotated matrix: lanes of a group read gsz consecutive
+// doubles of one column and the groups of a round read consecutive columns,
+// so a stride congruent to gsz modulo 32 doubles makes the groups of a
+// wavefront tile the LDS banks.  At most 31 doubles of padding per column.
+static __host__ __device__ inline int jacobi_ld(int len, int gsz) {
+  return len + (((gsz - len) % 32) + 32) % 32;
+}
 static __host__ __device__ inline size_t jacobi_need(int p, int m, int mode) {
-  return mode ? (size_t)p * m + 2 * (size_t)m : (size_t)p * m + (size_t)m * m + 2 * (size_t)m;
+  // players x padded length, column norms; mode 0 adds the m x m rotations
+  // (mode 1: ncol <= p columns of stride <= m + 31; mode 0: m columns of
+  // stride <= p + 31 and m rotation columns of stride <= m + 31)
+  const size_t mp = (size_t)m + 31, pp = (size_t)p + 31;
+  return mode ? mp * (size_t)p + 2 * (size_t)m : pp * (size_t)m + mp * (size_t)m + 2 * (size_t)m;
 }
 size_t jacobi_need_doubles(int p, int m, int mode) { return jacobi_need(p, m, mode); }
 
@@ -694,44 +705,81 @@ __device__ __forceinline__ void team_sync() {
   }
 }
 
-// one problem on the buffer G (jacobi_need doubles) by NT threads
-template <int NT>
-__device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int s0, JacobiShared& sh) {
-  const int tid = NT == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
-  const int m = P.m, p = P.p, mode = P.mode;
-  // players: ncol columns of length len in G (len x ncol, column-major)
-  int ncol, len, coff;
-  if (mode) {
-    len = m - s0;
-    ncol = min(p, len);
-    coff = 0;
-  } else {
-    len = p;
-    ncol = m - s0;
-    coff = s0;
+// One pair of players: the three dot products over the group's gsz lanes and,
+// if the pair is not yet orthogonal, the rotation.  EPL > 0: each lane keeps
+// its (at most EPL) elements of both columns in registers between the dot
+// products and the rotation; EPL = 0: loop form for any length.
+template <int EPL>
+__device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua, double* ub, int len, int m,
+                                            bool live, int gsz, int gl, double tol2) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+  double x[EPL > 0 ? EPL : 1], y[EPL > 0 ? EPL : 1];
+  if (EPL > 0) {
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+      const int i = gl + k * gsz;
+      const bool in = live && i < len;
+      x[k] = in ? ga_[i] : 0.0;
+      y[k] = in ? gb_[i] : 0.0;
+      al += x[k] * x[k];
+      be += y[k] * y[k];
+      ga += x[k] * y[k];
+    }
+  } else if (live) {
+#pragma unroll 4
+    for (int i = gl; i < len; i += gsz) {
+      const double xv = ga_[i], yv = gb_[i];
+      al += xv * xv;
+      be += yv * yv;
+      ga += xv * yv;
+    }
   }
-  double* U = mode ? nullptr : G + (size_t)p * m;
-  double* nrm = mode ? G + (size_t)p * m : U + (size_t)m * m;
-  if (mode) {
-    for (int e = tid; e < len * ncol; e += NT) {  // G(i, j) = R'(j, i)
-      const int i = e % len, j = e / len;
-      G[e] = P.R[j + (int64_t)i * P.ldr];
+  al = group_sum(al, gsz);
+  be = group_sum(be, gsz);
+  ga = group_sum(ga, gsz);
+  if (!(live && al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+  if (EPL > 0) {
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
+      const int i = gl + k * gsz;
+      if (i < len) {
+        ga_[i] = c * x[k] - s * y[k];
+        gb_[i] = s * x[k] + c * y[k];
+      }
     }
   } else {
-    for (int e = tid; e < p * m; e += NT) G[e] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
-    for (int e = tid; e < m * m; e += NT) U[e] = (e % m) == (e / m) ? 1.0 : 0.0;
+#pragma unroll 4
+    for (int i = gl; i < len; i += gsz) {
+      const double xv = ga_[i], yv = gb_[i];
+      ga_[i] = c * xv - s * yv;
+      gb_[i] = s * xv + c * yv;
+    }
   }
-  team_sync<NT>();
-  const int mm = ncol + (ncol & 1);  // players of the round-robin tournament
+  if (ua) {
+#pragma unroll 4
+    for (int i = gl; i < m; i += gsz) {
+      const double xv = ua[i], yv = ub[i];
+      ua[i] = c * xv - s * yv;
+      ub[i] = s * xv + c * yv;
+    }
+  }
+  return true;
+}
+
+// the sweeps over the round-robin tournament of ncol players (columns of G,
+// stride ld); returns the number of sweeps, counts this thread's rotations
+template <int NT, int EPL>
+__device__ __forceinline__ int jacobi_sweeps(double* G, int ld, double* U, int ldu, int m, int ncol, int len,
+                                             int coff, int gsz, double tol2, unsigned int& my_rot,
+                                             JacobiShared& sh) {
+  const int tid = NT == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  const int mm = ncol + (ncol & 1);
   const int npairs = mm / 2;
-  // lanes per pair: all pairs of a round at once where possible
-  int gsz = 64;
-  while (gsz > 4 && gsz * npairs > NT) gsz >>= 1;
   const int groups = NT / gsz;
   const int g = tid / gsz, gl = tid % gsz;
-  // rotate while |a.b| exceeds the rounding level of a dot product of length len
-  const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
-  unsigned int my_rot = 0;
   int sweeps = 0;
   for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
     ++sweeps;
@@ -753,45 +801,12 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
         const bool live = a < ncol && b < ncol;
         a += coff;
         b += coff;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        double* ga_ = G + (size_t)a * len;
-        double* gb_ = G + (size_t)b * len;
-        if (live) {
-#pragma unroll 4
-          for (int i = gl; i < len; i += gsz) {
-            const double x = ga_[i], y = gb_[i];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
-          }
-        }
-        al = group_sum(al, gsz);
-        be = group_sum(be, gsz);
-        ga = group_sum(ga, gsz);
-        if (live && al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-#pragma unroll 4
-          for (int i = gl; i < len; i += gsz) {
-            const double x = ga_[i], y = gb_[i];
-            ga_[i] = c * x - s * y;
-            gb_[i] = s * x + c * y;
-          }
-          if (!mode) {
-            double* ua = U + (size_t)a * m;
-            double* ub = U + (size_t)b * m;
-#pragma unroll 4
-            for (int i = gl; i < m; i += gsz) {
-              const double x = ua[i], y = ub[i];
-              ua[i] = c * x - s * y;
-              ub[i] = s * x + c * y;
-            }
-          }
-          if (gl == 0) {
-            rot_here = 1;
-            ++my_rot;
-          }
+        double* ua = U ? U + (size_t)a * ldu : nullptr;
+        double* ub = U ? U + (size_t)b * ldu : nullptr;
+        if (jacobi_pair<EPL>(G + (size_t)a * ld, G + (size_t)b * ld, ua, ub, len, m, live, gsz, gl, tol2) &&
+            gl == 0) {
+          rot_here = 1;
+          ++my_rot;
         }
       }
       team_sync<NT>();
@@ -807,6 +822,61 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
     }
     if (!any) break;
   }
+  return sweeps;
+}
+
+// one problem on the buffer G (jacobi_need doubles) by NT threads
+template <int NT>
+__device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int s0, JacobiShared& sh) {
+  const int tid = NT == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  const int m = P.m, p = P.p, mode = P.mode;
+  // players: ncol columns of length len in G (stride ld)
+  int ncol, len, coff;
+  if (mode) {
+    len = m - s0;
+    ncol = min(p, len);
+    coff = 0;
+  } else {
+    len = p;
+    ncol = m - s0;
+    coff = s0;
+  }
+  const int mm = ncol + (ncol & 1);
+  const int npairs = mm / 2;
+  // lanes per pair: all pairs of a round at once where possible
+  int gsz = 64;
+  while (gsz > 4 && gsz * npairs > NT) gsz >>= 1;
+  const int ld = jacobi_ld(len, gsz);
+  const int ldu = jacobi_ld(m, gsz);
+  // G holds the columns 0..(mode ? ncol : m)-1 (mode 0 stores the zero ones too)
+  const int gcols = mode ? ncol : m;
+  double* U = mode ? nullptr : G + (size_t)ld * gcols;
+  double* nrm = mode ? G + (size_t)ld * gcols : U + (size_t)ldu * m;
+  if (mode) {
+    for (int e = tid; e < len * ncol; e += NT) {  // G(i, j) = R'(j, i)
+      const int i = e % len, j = e / len;
+      G[i + (size_t)j * ld] = P.R[j + (int64_t)i * P.ldr];
+    }
+  } else {
+    for (int e = tid; e < p * m; e += NT) G[(e % p) + (size_t)(e / p) * ld] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
+    for (int e = tid; e < m * m; e += NT) U[(e % m) + (size_t)(e / m) * ldu] = (e % m) == (e / m) ? 1.0 : 0.0;
+  }
+  team_sync<NT>();
+  // rotate while |a.b| exceeds the rounding level of a dot product of length len
+  const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
+  unsigned int my_rot = 0;
+  const int epl = (len + gsz - 1) / gsz;
+  int sweeps;
+  if (epl <= 4)
+    sweeps = jacobi_sweeps<NT, 4>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
+  else if (epl <= 8)
+    sweeps = jacobi_sweeps<NT, 8>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
+  else if (epl <= 16)
+    sweeps = jacobi_sweeps<NT, 16>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
+  else if (epl <= 32)
+    sweeps = jacobi_sweeps<NT, 32>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
+  else
+    sweeps = jacobi_sweeps<NT, 0>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
   if (P.work) {
     double nrot;
     if (NT == 256) {
@@ -825,7 +895,7 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   const int nc = mode ? ncol : m;
   for (int c = tid; c < nc; c += NT) {
     double s = 0.0;
-    const double* gc = G + (size_t)c * len;
+    const double* gc = G + (size_t)c * ld;
     for (int i = 0; i < len; ++i) s += gc[i] * gc[i];
     nrm[c] = sqrt(s);
   }
@@ -839,11 +909,11 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
       double* uo = P.U + (int64_t)pos * P.ldu;
       if (mode) {
         const double inv = v > 0.0 ? 1.0 / v : 0.0;
-        const double* gc = G + (size_t)c * len;
+        const double* gc = G + (size_t)c * ld;
         for (int i = 0; i < s0; ++i) uo[i] = 0.0;
         for (int i = 0; i < len; ++i) uo[s0 + i] = gc[i] * inv;
       } else {
-        for (int i = 0; i < m; ++i) uo[i] = U[i + (size_t)c * m];
+        for (int i = 0; i < m; ++i) uo[i] = U[i + (size_t)c * ldu];
       }
     }
   }
