@@ -160,6 +160,7 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
 // problems with m <= jacobi_small_max_m(): one wavefront each, per_doubles of
 // LDS each (4 per workgroup)
 int jacobi_small_max_m();
+int jacobi_max_len();
 void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* stream);
 void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream);
 void k_fill(const FillItem* items, int n, void* stream);

@@ -670,21 +670,38 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
 //          this way.  U(:, pos) = [0 (s0 rows); v_j] for pos < pe, else 0.
 // Singular values = column norms, sorted descending (ties by index).
 // ---------------------------------------------------------------------------
-// Column stride of the rotated matrix: lanes of a group read gsz consecutive
-// doubles of one column and the groups of a round read consecutive columns,
-// so a stride congruent to gsz modulo 32 doubles makes the groups of a
-// wavefront tile the LDS banks.  At most 31 doubles of padding per column.
+static __host__ __device__ inline int pow2ceil(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+// lanes per pair for nt threads: all pairs of a round at once where possible
+static __host__ __device__ inline int jacobi_gsz(int npairs, int nt) {
+  int g = 64;
+  while (g > 4 && g * npairs > nt) g >>= 1;
+  return g;
+}
+// Column stride of the rotated matrix.  Rows len .. L-1 (L = max(gsz,
+// pow2ceil(len))) are kept zero, so each lane's EPL = L / gsz elements are
+// loaded without per-element predicates.  The extra shift by gsz (for gsz <
+// 32) makes the lane groups of a wavefront, which read consecutive columns,
+// fall on different LDS banks.
 static __host__ __device__ inline int jacobi_ld(int len, int gsz) {
-  return len + (((gsz - len) % 32) + 32) % 32;
+  const int L = max(gsz, pow2ceil(len));
+  return L + (gsz < 32 ? gsz : 0);
+}
+static __host__ __device__ inline size_t jacobi_ld_max(int len) {
+  return (size_t)max(64, pow2ceil(len)) + 16;
 }
 static __host__ __device__ inline size_t jacobi_need(int p, int m, int mode) {
-  // players x padded length, column norms; mode 0 adds the m x m rotations
-  // (mode 1: ncol <= p columns of stride <= m + 31; mode 0: m columns of
-  // stride <= p + 31 and m rotation columns of stride <= m + 31)
-  const size_t mp = (size_t)m + 31, pp = (size_t)p + 31;
-  return mode ? mp * (size_t)p + 2 * (size_t)m : pp * (size_t)m + mp * (size_t)m + 2 * (size_t)m;
+  // mode 1: ncol <= p columns of length <= m; mode 0: m columns of length p
+  // and the m x m rotations; column norms
+  return mode ? jacobi_ld_max(m) * (size_t)p + 2 * (size_t)m
+              : jacobi_ld_max(p) * (size_t)m + jacobi_ld_max(m) * (size_t)m + 2 * (size_t)m;
 }
 size_t jacobi_need_doubles(int p, int m, int mode) { return jacobi_need(p, m, mode); }
+// longest column the kernels take (8 elements per lane of a 64-lane group)
+int jacobi_max_len() { return 512; }
 
 struct JacobiShared {
   int rotated;
@@ -692,11 +709,11 @@ struct JacobiShared {
 };
 
 // synchronisation of the NT threads working on one problem: the workgroup
-// (NT = 256) or one wavefront (NT = 64, lanes run in lockstep; the fences
+// (NT = 1024) or one wavefront (NT = 64, lanes run in lockstep; the fences
 // keep the compiler from moving LDS accesses across the step boundary)
 template <int NT>
 __device__ __forceinline__ void team_sync() {
-  if (NT == 256) {
+  if (NT > 64) {
     __syncthreads();
   } else {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -706,32 +723,25 @@ __device__ __forceinline__ void team_sync() {
 }
 
 // One pair of players: the three dot products over the group's gsz lanes and,
-// if the pair is not yet orthogonal, the rotation.  EPL > 0: each lane keeps
-// its (at most EPL) elements of both columns in registers between the dot
-// products and the rotation; EPL = 0: loop form for any length.
+// if the pair is not yet orthogonal, the rotation.  The EPL elements of each
+// lane (rows gl + k gsz, zero-padded) stay in registers between the dot
+// products and the rotation.  The branch on `live` is uniform per group.
 template <int EPL>
-__device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua, double* ub, int len, int m,
+__device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua, double* ub, int ldu_m,
                                             bool live, int gsz, int gl, double tol2) {
   double al = 0.0, be = 0.0, ga = 0.0;
-  double x[EPL > 0 ? EPL : 1], y[EPL > 0 ? EPL : 1];
-  if (EPL > 0) {
+  double x[EPL], y[EPL];
+  if (live) {
 #pragma unroll
     for (int k = 0; k < EPL; ++k) {
-      const int i = gl + k * gsz;
-      const bool in = live && i < len;
-      x[k] = in ? ga_[i] : 0.0;
-      y[k] = in ? gb_[i] : 0.0;
+      x[k] = ga_[gl + k * gsz];
+      y[k] = gb_[gl + k * gsz];
+    }
+#pragma unroll
+    for (int k = 0; k < EPL; ++k) {
       al += x[k] * x[k];
       be += y[k] * y[k];
       ga += x[k] * y[k];
-    }
-  } else if (live) {
-#pragma unroll 4
-    for (int i = gl; i < len; i += gsz) {
-      const double xv = ga_[i], yv = gb_[i];
-      al += xv * xv;
-      be += yv * yv;
-      ga += xv * yv;
     }
   }
   al = group_sum(al, gsz);
@@ -741,26 +751,14 @@ __device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-  if (EPL > 0) {
 #pragma unroll
-    for (int k = 0; k < EPL; ++k) {
-      const int i = gl + k * gsz;
-      if (i < len) {
-        ga_[i] = c * x[k] - s * y[k];
-        gb_[i] = s * x[k] + c * y[k];
-      }
-    }
-  } else {
-#pragma unroll 4
-    for (int i = gl; i < len; i += gsz) {
-      const double xv = ga_[i], yv = gb_[i];
-      ga_[i] = c * xv - s * yv;
-      gb_[i] = s * xv + c * yv;
-    }
+  for (int k = 0; k < EPL; ++k) {
+    ga_[gl + k * gsz] = c * x[k] - s * y[k];
+    gb_[gl + k * gsz] = s * x[k] + c * y[k];
   }
   if (ua) {
 #pragma unroll 4
-    for (int i = gl; i < m; i += gsz) {
+    for (int i = gl; i < ldu_m; i += gsz) {
       const double xv = ua[i], yv = ub[i];
       ua[i] = c * xv - s * yv;
       ub[i] = s * xv + c * yv;
@@ -772,39 +770,39 @@ __device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua
 // the sweeps over the round-robin tournament of ncol players (columns of G,
 // stride ld); returns the number of sweeps, counts this thread's rotations
 template <int NT, int EPL>
-__device__ __forceinline__ int jacobi_sweeps(double* G, int ld, double* U, int ldu, int m, int ncol, int len,
-                                             int coff, int gsz, double tol2, unsigned int& my_rot,
-                                             JacobiShared& sh) {
-  const int tid = NT == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+__device__ __forceinline__ int jacobi_sweeps(double* G, int ld, double* U, int ldu, int m, int ncol, int coff,
+                                             int gsz, double tol2, unsigned int& my_rot, JacobiShared& sh) {
+  const int tid = NT > 64 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
   const int mm = ncol + (ncol & 1);
-  const int npairs = mm / 2;
+  const int npairs = mm / 2, nr = mm - 1;
   const int groups = NT / gsz;
   const int g = tid / gsz, gl = tid % gsz;
   int sweeps = 0;
-  for (int sweep = 0; sweep < 40 && ncol > 1 && len > 0; ++sweep) {
+  for (int sweep = 0; sweep < 40 && ncol > 1; ++sweep) {
     ++sweeps;
     int rot_here = 0;
-    if (NT == 256) {
+    if (NT > 64) {
       if (tid == 0) sh.rotated = 0;
       team_sync<NT>();
     }
-    for (int rnd = 0; rnd < mm - 1; ++rnd) {
+    for (int rnd = 0; rnd < nr; ++rnd) {
       for (int pk = g; pk < npairs; pk += groups) {
         int a, b;
         if (pk == 0) {
-          a = mm - 1;
+          a = nr;
           b = rnd;
         } else {
-          a = (rnd + pk) % (mm - 1);
-          b = (rnd - pk + (mm - 1)) % (mm - 1);
+          a = rnd + pk;
+          if (a >= nr) a -= nr;
+          b = rnd - pk;
+          if (b < 0) b += nr;
         }
         const bool live = a < ncol && b < ncol;
         a += coff;
         b += coff;
         double* ua = U ? U + (size_t)a * ldu : nullptr;
         double* ub = U ? U + (size_t)b * ldu : nullptr;
-        if (jacobi_pair<EPL>(G + (size_t)a * ld, G + (size_t)b * ld, ua, ub, len, m, live, gsz, gl, tol2) &&
-            gl == 0) {
+        if (jacobi_pair<EPL>(G + (size_t)a * ld, G + (size_t)b * ld, ua, ub, m, live, gsz, gl, tol2) && gl == 0) {
           rot_here = 1;
           ++my_rot;
         }
@@ -812,7 +810,7 @@ __device__ __forceinline__ int jacobi_sweeps(double* G, int ld, double* U, int l
       team_sync<NT>();
     }
     int any;
-    if (NT == 256) {
+    if (NT > 64) {
       if (rot_here) sh.rotated = 1;
       team_sync<NT>();
       any = sh.rotated;
@@ -828,9 +826,9 @@ __device__ __forceinline__ int jacobi_sweeps(double* G, int ld, double* U, int l
 // one problem on the buffer G (jacobi_need doubles) by NT threads
 template <int NT>
 __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int s0, JacobiShared& sh) {
-  const int tid = NT == 256 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+  const int tid = NT > 64 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
   const int m = P.m, p = P.p, mode = P.mode;
-  // players: ncol columns of length len in G (stride ld)
+  // players: ncol columns of length len in G (stride ld, zero-padded rows)
   int ncol, len, coff;
   if (mode) {
     len = m - s0;
@@ -841,45 +839,46 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
     ncol = m - s0;
     coff = s0;
   }
-  const int mm = ncol + (ncol & 1);
-  const int npairs = mm / 2;
-  // lanes per pair: all pairs of a round at once where possible
-  int gsz = 64;
-  while (gsz > 4 && gsz * npairs > NT) gsz >>= 1;
+  const int npairs = (ncol + (ncol & 1)) / 2;
+  // at most 8 elements per lane (register budget of 1024-thread groups): long
+  // columns take wider lane groups, which then take several pairs in turn
+  int gsz = jacobi_gsz(npairs, NT);
+  while (gsz < 64 && max(gsz, pow2ceil(len)) > 8 * gsz) gsz *= 2;
   const int ld = jacobi_ld(len, gsz);
   const int ldu = jacobi_ld(m, gsz);
+  const int epl = (ld - (gsz < 32 ? gsz : 0)) / gsz;  // L / gsz, a power of two
   // G holds the columns 0..(mode ? ncol : m)-1 (mode 0 stores the zero ones too)
   const int gcols = mode ? ncol : m;
   double* U = mode ? nullptr : G + (size_t)ld * gcols;
   double* nrm = mode ? G + (size_t)ld * gcols : U + (size_t)ldu * m;
   if (mode) {
-    for (int e = tid; e < len * ncol; e += NT) {  // G(i, j) = R'(j, i)
-      const int i = e % len, j = e / len;
-      G[i + (size_t)j * ld] = P.R[j + (int64_t)i * P.ldr];
+    for (int e = tid; e < ld * ncol; e += NT) {  // G(i, j) = R'(j, i), rows >= len zero
+      const int i = e % ld, j = e / ld;
+      G[e] = i < len ? P.R[j + (int64_t)i * P.ldr] : 0.0;
     }
   } else {
-    for (int e = tid; e < p * m; e += NT) G[(e % p) + (size_t)(e / p) * ld] = P.R[(e % p) + (int64_t)(e / p) * P.ldr];
-    for (int e = tid; e < m * m; e += NT) U[(e % m) + (size_t)(e / m) * ldu] = (e % m) == (e / m) ? 1.0 : 0.0;
+    for (int e = tid; e < ld * m; e += NT) {
+      const int i = e % ld, j = e / ld;
+      G[e] = i < p ? P.R[i + (int64_t)j * P.ldr] : 0.0;
+    }
+    for (int e = tid; e < ldu * m; e += NT) U[e] = (e % ldu) == (e / ldu) ? 1.0 : 0.0;
   }
   team_sync<NT>();
   // rotate while |a.b| exceeds the rounding level of a dot product of length len
   const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
   unsigned int my_rot = 0;
-  const int epl = (len + gsz - 1) / gsz;
-  int sweeps;
-  if (epl <= 4)
-    sweeps = jacobi_sweeps<NT, 4>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
-  else if (epl <= 8)
-    sweeps = jacobi_sweeps<NT, 8>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
-  else if (epl <= 16)
-    sweeps = jacobi_sweeps<NT, 16>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
-  else if (epl <= 32)
-    sweeps = jacobi_sweeps<NT, 32>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
-  else
-    sweeps = jacobi_sweeps<NT, 0>(G, ld, U, ldu, m, ncol, len, coff, gsz, tol2, my_rot, sh);
+  int sweeps = 0;
+  if (len > 0) {
+    switch (epl) {
+      case 1: sweeps = jacobi_sweeps<NT, 1>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
+      case 2: sweeps = jacobi_sweeps<NT, 2>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
+      case 4: sweeps = jacobi_sweeps<NT, 4>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
+      default: sweeps = jacobi_sweeps<NT, 8>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
+    }
+  }
   if (P.work) {
     double nrot;
-    if (NT == 256) {
+    if (NT > 64) {
       if (my_rot) atomicAdd(&sh.nrot, my_rot);
       team_sync<NT>();
       nrot = sh.nrot;
@@ -932,17 +931,20 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   }
 }
 
-__global__ __launch_bounds__(256) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
-                                                     double* __restrict__ scratch, size_t slot, int lds_cap) {
+constexpr int kJacobiThreads = 1024;
+
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
+                                                                double* __restrict__ scratch, size_t slot,
+                                                                int lds_cap) {
   __shared__ JacobiShared sh;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const JacobiProb P = probs[pi];
     if (threadIdx.x == 0) sh.nrot = 0;
     const int s0 = P.skip ? min(max(*P.skip, 0), P.m) : 0;
     if (jacobi_need(P.p, P.m, P.mode) <= (size_t)lds_cap)
-      jacobi_solve<256>(P, lds_dyn, s0, sh);
+      jacobi_solve<kJacobiThreads>(P, lds_dyn, s0, sh);
     else
-      jacobi_solve<256>(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
+      jacobi_solve<kJacobiThreads>(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
     __syncthreads();
   }
 }
@@ -966,8 +968,8 @@ void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, doub
   if (n <= 0) return;
   H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "jacobi: global scratch missing");
   const int grid = slot == 0 ? n : std::min(n, 1024);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream,
-                     probs, n, scratch, slot, lds_doubles);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(kJacobiThreads), (size_t)lds_doubles * 8,
+                     (hipStream_t)stream, probs, n, scratch, slot, lds_doubles);
   HIP_OK(hipGetLastError());
 }
 

@@ -521,6 +521,8 @@ void TsqrBatch::run(h2_ctx* ctx) {
 
 void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu,
                       double* sigma, int32_t* rank, double eps, double rtol, const int32_t* skip, int mode) {
+  H2_REQUIRE(m <= jacobi_max_len() && p_ <= jacobi_max_len(), H2_ERR_UNSUPPORTED,
+             "jacobi: matrix larger than the kernels take");
   JacobiProb j{};
   j.R = R;
   j.ldr = std::max<int64_t>(ldr, 1);
