@@ -87,12 +87,13 @@ def main():
     ctx.kernel_stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps = {}
+    steps, hsteps = {}, {}
     for i in range(args.steps):
         G, Z = step()
-        st = ctx.step_times()
-        for k, v in st.items():
+        for k, v in ctx.step_times().items():
             steps[k] = steps.get(k, 0.0) + v
+        for k, v in ctx.step_times(host=True).items():
+            hsteps[k] = hsteps.get(k, 0.0) + v
         if i < args.steps - 1:
             del G, Z
     torch.cuda.synchronize()
@@ -130,6 +131,7 @@ def main():
         "mfma_util_step": mfma_util,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in ks.items()},
         "step_ms": {k: v / args.steps for k, v in steps.items()},
+        "host_step_ms": {k: v / args.steps for k, v in hsteps.items()},
         "ranks": ranks, "product_tree": sizes,
     }
     if not args.no_cpu_baseline:

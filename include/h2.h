@@ -170,11 +170,14 @@ h2_status h2_product_ranks(const h2_product* G, int which, int32_t* out);
  * bytes held by G. */
 h2_status h2_product_sizes(const h2_product* G, int64_t out[5]);
 
-/* Step times (milliseconds, stream events) since the last h2_mul_intermediate
- * on this context (which resets them; h2_recompress adds its steps);
- * out[] receives up to n entries in the order
+/* Step times (milliseconds) since the last h2_mul_intermediate on this
+ * context (which resets them; h2_recompress adds its steps); out[] receives
+ * up to n entries: out[0..7] device time between stream events around each
+ * step, out[8..15] host wall time spent issuing it, in the order
  *   0 setup, 1 symbolic, 2 phase-1 row, 3 phase-1 col, 4 phase-1 mat (G),
- *   5 phase-2 row, 6 phase-2 col, 7 phase-2 mat (Z).  Returns the count. */
+ *   5 phase-2 row, 6 phase-2 col, 7 phase-2 mat (Z).
+ * The column passes run on a second stream concurrently with the row passes,
+ * so steps 2/3 and 5/6 overlap in time.  Returns the count. */
 int h2_step_times(const h2_ctx* ctx, double* out, int n);
 
 /* Launch timing for measurement.  h2_profile(ctx, 1) makes every kernel
@@ -183,7 +186,8 @@ int h2_step_times(const h2_ctx* ctx, double* out, int n);
  * the stream) and returns, for kernel family `kind` (0 grouped GEMM, 1 TSQR,
  * 2 Jacobi SVD, 3 construction, 4 other), out[0] = total milliseconds,
  * out[1] = launches, out[2] = algorithmic flops (2mnk per product term;
- * Householder 2Nm^2 - 2m^3/3; one Jacobi sweep), out[3] = algorithmic bytes
+ * Householder 2Nm^2 - 2m^3/3; for Jacobi, three dot products per pair and
+ * sweep performed plus each rotation applied), out[3] = algorithmic bytes
  * (operands read once, outputs written once).  reset != 0 clears the counters
  * after reading. */
 h2_status h2_profile(h2_ctx* ctx, int enable);

@@ -35,8 +35,10 @@ static void need_device(const h2_ctx* ctx) {
 static void begin_call(h2_ctx* ctx, bool reset_steps = false) {
   ctx->ws.reset();
   if (ctx->aux) ctx->aux->ws.reset();  // its earlier work is ordered before ours
-  if (reset_steps)
+  if (reset_steps) {
     for (double& v : ctx->step_ms) v = 0.0;
+    for (double& v : ctx->host_ms) v = 0.0;
+  }
 }
 
 extern "C" {
@@ -295,8 +297,8 @@ h2_status h2_product_sizes(const h2_product* G, int64_t out[5]) {
 
 int h2_step_times(const h2_ctx* ctx, double* out, int n) {
   if (!ctx || !out) return 0;
-  int m = std::min(n, 8);
-  for (int i = 0; i < m; ++i) out[i] = ctx->step_ms[i];
+  int m = std::min(n, 16);
+  for (int i = 0; i < m; ++i) out[i] = i < 8 ? ctx->step_ms[i] : ctx->host_ms[i - 8];
   return m;
 }
 

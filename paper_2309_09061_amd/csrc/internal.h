@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <chrono>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -77,6 +78,26 @@ struct GemmTerm {
   int32_t k, flags;
   double alpha;
 };
+// Grouped products driven by the product-tree triples: output o (one block of
+// T^XY) = beta C + sum over the triples q in [q0, q1) whose kind equals
+// F.kind of op(F.A[bx_q]) op(F.B[by_q]); the operand tables are indexed by
+// the factor blocks of the triple, the inner dimension is F.k or F.ks[s_q].
+struct TriOut {
+  double* C;
+  int64_t ldc;
+  int32_t m, n;
+  int32_t q0, q1;
+  int32_t beta, pad;
+};
+struct TriFamily {
+  const int32_t* tri;          // 4 ints per triple: s, bx, by, kind
+  const double* const* A;      // by block of X (view)
+  const int64_t* lda;
+  const double* const* B;      // by block of Y (view)
+  const int64_t* ldb;
+  const int32_t* ks;           // inner dimension per middle cluster; null: k
+  int32_t k, kind, tA, tB;
+};
 // R factor of the tall matrix T (N x m): T = A (transA = 0) or T = A^T where A
 // is m x N column-major (transA = 1).  R (min(N,m) x m, ldr) upper, zero below.
 // Householder QR (in place; reflectors below the diagonal, tau[min(m,n)]),
@@ -138,6 +159,7 @@ struct FillItem {
 // launchers (descriptor arrays are device pointers)
 void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
                 int prec, void* stream);
+void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, void* stream);
 // Factorization launches: lds_doubles is the dynamic LDS of the launch (a
 // problem whose working set fits it runs in LDS), slot the doubles of global
 // scratch per workgroup for the others (0: none); scratch then holds
@@ -312,6 +334,8 @@ struct h2_ctx {
   std::vector<void*> events;
   std::vector<int> ev_step;            // step id of each recorded event interval
   double step_ms[8] = {0};
+  double host_ms[8] = {0};             // host wall time between step_begin and step_end
+  std::chrono::steady_clock::time_point host_t0[8];
   int prec = 0;                        // bulk precision of the running call
   bool profile = false;                // time every launch with stream events
   std::vector<void*> ev_pool;          // reusable events for launch timing
@@ -421,6 +445,13 @@ struct GemmBatch {
   void run(h2_ctx* ctx);
   bool empty() const { return outs.empty(); }
 };
+// outputs of one triple family (one launch)
+struct TriBatch {
+  std::vector<TriOut> outs;
+  TriFamily fam{};
+  void out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate = false);
+  void run(h2_ctx* ctx, double flops);
+};
 struct QrBatch {
   std::vector<QrProb> p;
   void add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr, int rrows);
@@ -476,12 +507,13 @@ std::shared_ptr<BlockTreeH> build_block_tree(const TreeH& rt, const TreeH& ct, d
 enum : int8_t { TK_AA = 0, TK_AN = 1, TK_NA = 2, TK_NN = 3, TK_SPLIT = 4 };
 struct Triple {
   int32_t s, bx, by;  // middle cluster, block of X (view coords), block of Y
-  int8_t kind;
+  int32_t kind;       // laid out as the 4 ints a TriFamily reads
 };
 struct ProductTreeH {
   std::shared_ptr<BlockTreeH> bt;           // T^XY
   std::vector<int32_t> tri_ptr;             // per block
   std::vector<Triple> tri;
+  std::vector<int32_t> kind_cnt;            // 4 per block: triples of each kind
   int64_t n_terminated = 0;
 };
 

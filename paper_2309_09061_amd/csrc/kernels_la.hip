@@ -137,6 +137,62 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 extern __shared__ double lds_dyn[];
 
 // ---------------------------------------------------------------------------
+// grouped products over product-tree triples (FP64 MFMA): one wavefront per
+// 16 x 16 output tile; each tile scans its block's triples and accumulates the
+// ones of the launch's kind
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gemm_tri_f64(const TriOut* __restrict__ outs,
+                                                    const int32_t* __restrict__ tiles, int ntiles,
+                                                    const TriFamily F) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tix = blockIdx.x * 4 + wave;
+  if (tix >= ntiles) return;
+  const int oi = tiles[3 * tix], i0 = tiles[3 * tix + 1], j0 = tiles[3 * tix + 2];
+  const TriOut o = outs[oi];
+  const int r = lane & 15, q = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  const int i = i0 + r, j = j0 + r;
+  const bool ia = i < o.m, jb = j < o.n;
+  for (int t = o.q0; t < o.q1; ++t) {
+    const int4 tr = reinterpret_cast<const int4*>(F.tri)[t];
+    if (tr.w != F.kind) continue;
+    const double* A = F.A[tr.y];
+    const double* B = F.B[tr.z];
+    const int64_t lda = F.lda[tr.y], ldb = F.ldb[tr.z];
+    const int k = F.ks ? F.ks[tr.x] : F.k;
+    const int64_t sa_i = F.tA ? lda : 1, sa_l = F.tA ? 1 : lda;
+    const int64_t sb_l = F.tB ? ldb : 1, sb_j = F.tB ? 1 : ldb;
+    for (int l0 = 0; l0 < k; l0 += 4) {
+      const int l = l0 + q;
+      double a = 0.0, b = 0.0;
+      if (ia && l < k) a = A[(int64_t)i * sa_i + (int64_t)l * sa_l];
+      if (jb && l < k) b = B[(int64_t)l * sb_l + (int64_t)j * sb_j];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+  }
+  // FP64 accumulator layout: register v of lane (r, q) holds D[4v + q][r]
+  double* C = o.C;
+  const int jc = j0 + r;
+  if (jc < o.n) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ic = i0 + 4 * v + q;
+      if (ic < o.m) {
+        double* p = C + ic + (int64_t)jc * o.ldc;
+        *p = o.beta ? *p + acc[v] : acc[v];
+      }
+    }
+  }
+}
+
+void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, void* stream) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(gemm_tri_f64, dim3((ntiles + 3) / 4), dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles,
+                     fam);
+  HIP_OK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // Householder QR of one m x n matrix W (ld) by a 256-thread workgroup
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau, double* red) {

@@ -440,7 +440,60 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   C.W = col.Q;
   C.blk.assign(B.nblocks(), nullptr);
   std::vector<double*> S(B.nblocks(), nullptr);
-  auto Arow = [&](int bx, int kt) { return row.A[X.vrow(bx)] + (size_t)row.cpos[bx] * k * kt; };
+
+  // Operand tables for the triple-driven products, indexed by the factor
+  // blocks of a triple (one upload each per call): X's and Y's blocks, the
+  // products P S_Y of admissible blocks of Y, the row pass's A_{t,s} of the
+  // blocks of X and the column pass's A^c of the blocks of Y.
+  const BlockTreeH& BX = *Xm->c.bt;
+  const int nbx = BX.nblocks(), nby = BY.nblocks();
+  std::vector<const double*> tX(nbx), tY(nby), tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
+  std::vector<int64_t> lX(nbx), lY(nby), lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
+  for (int b = 0; b < nbx; ++b) {
+    tX[b] = Xm->c.blk[b];
+    lX[b] = Xm->c.ld_of(b);
+    if (BX.type[b] != BT_ADM && row.cpos[b] >= 0) {
+      const int kt = row.Q.rank[X.vrow(b)];
+      tAr[b] = row.A[X.vrow(b)] + (size_t)row.cpos[b] * k * kt;
+      lAr[b] = std::max(kt, 1);
+    }
+  }
+  for (int b = 0; b < nby; ++b) {
+    tY[b] = Ym->c.blk[b];
+    lY[b] = Ym->c.ld_of(b);
+    tPS[b] = PS[b];
+    if (BY.type[b] != BT_ADM && col.cpos[b] >= 0) {
+      const int r = BY.s[b], kr = col.Q.rank[r];
+      tAc[b] = col.A[r] + (size_t)col.cpos[b] * k * kr;
+      lAc[b] = std::max(kr, 1);
+    }
+  }
+  const int32_t* d_tri = (const int32_t*)upload(ctx, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
+  std::vector<int32_t> sizes(T.ncl);
+  for (int c = 0; c < T.ncl; ++c) sizes[c] = (int32_t)T.size[c];
+  const int32_t* d_size = upload(ctx, sizes);
+  auto fam = [&](const std::vector<const double*>& A, const std::vector<int64_t>& la,
+                 const std::vector<const double*>& Bt, const std::vector<int64_t>& lb, int kind, bool tB,
+                 const int32_t* ks) {
+    TriFamily f{};
+    f.tri = d_tri;
+    f.A = upload(ctx, A);
+    f.lda = upload(ctx, la);
+    f.B = upload(ctx, Bt);
+    f.ldb = upload(ctx, lb);
+    f.ks = ks;
+    f.k = k;
+    f.kind = kind;
+    f.tA = 0;
+    f.tB = tB ? 1 : 0;
+    return f;
+  };
+  const TriFamily fAA = fam(tX, lX, tPS, lPS, TK_AA, false, nullptr);  // S_X (P S_Y)
+  const TriFamily fNA = fam(tAr, lAr, tY, lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
+  const TriFamily fAN = fam(tX, lX, tAc, lAc, TK_AN, true, nullptr);   // S_X A^c_{r,s}^*
+  const TriFamily fNN = fam(tX, lX, tY, lY, TK_NN, false, d_size);     // N_X N_Y
+  auto cnt = [&](int b, int kind) { return PT.kind_cnt[4 * (size_t)b + kind]; };
+
   for (int l = 0; l <= T.depth; ++l) {
     const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
     std::vector<double*> TAA(b1 - b0, nullptr), TNA(b1 - b0, nullptr), Pp(b1 - b0, nullptr),
@@ -450,32 +503,26 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
         if (B.type[pb] == BT_SPLIT)
           for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - b0] = pb;
+    TriBatch taa, tna, tan_;
+    taa.fam = fAA;
+    tna.fam = fNA;
+    tan_.fam = fAN;
+    double f_aa = 0, f_na = 0, f_an = 0;
     for (int b = b0; b < b1; ++b) {
       int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
       bool keep = B.type[b] != BT_SPLIT;
       S[b] = keep ? G->mem.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1))
                   : ws.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1));
-      bool aa = false, na = false;
-      for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q) {
-        int8_t kd = PT.tri[q].kind;
-        aa |= kd == TK_AA;
-        na |= kd == TK_NA;
-      }
       int i = b - b0;
-      if (aa) {
+      if (cnt(b, TK_AA)) {
         TAA[i] = ws.get<double>((size_t)k * k);
-        g.out(TAA[i], k, k, k);
-        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
-          if (PT.tri[q].kind == TK_AA)
-            g.term(Xm->c.blk[PT.tri[q].bx], Xm->c.ld_of(PT.tri[q].bx), false, PS[PT.tri[q].by], k, false, k);
+        taa.out(TAA[i], k, k, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
+        f_aa += 2.0 * k * k * k * cnt(b, TK_AA);
       }
-      if (na && kt > 0) {
+      if (cnt(b, TK_NA) && kt > 0) {
         TNA[i] = ws.get<double>((size_t)kt * k);
-        g.out(TNA[i], kt, kt, k);
-        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
-          if (PT.tri[q].kind == TK_NA)
-            g.term(Arow(PT.tri[q].bx, kt), kt, false, Ym->c.blk[PT.tri[q].by], Ym->c.ld_of(PT.tri[q].by),
-                   false, k);
+        tna.out(TNA[i], kt, kt, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
+        f_na += 2.0 * kt * k * k * cnt(b, TK_NA);
       }
       if (parent[i] >= 0 && kt > 0) {
         int pt = B.t[parent[i]], pr = B.s[parent[i]];
@@ -485,24 +532,23 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
         g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], std::max(kpt, 1), false, kpt);
       }
     }
+    taa.run(ctx, f_aa);
+    tna.run(ctx, f_na);
     g.run(ctx);
     for (int b = b0; b < b1; ++b) {
       int i = b - b0, r = B.s[b], kr = col.Q.rank[r];
-      bool an = false;
-      for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q) an |= PT.tri[q].kind == TK_AN;
-      if ((an || TAA[i]) && kr > 0) {
+      if ((cnt(b, TK_AN) || TAA[i]) && kr > 0) {
         Mm[i] = ws.get<double>((size_t)k * kr);
         g.out(Mm[i], k, k, kr);
-        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
-          if (PT.tri[q].kind == TK_AN) {
-            int by = PT.tri[q].by;  // block (s,r) of Y = block (r,s) of Y^*
-            g.term(Xm->c.blk[PT.tri[q].bx], Xm->c.ld_of(PT.tri[q].bx), false,
-                   col.A[r] + (size_t)col.cpos[by] * k * kr, kr, true, k);
-          }
         if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
+        if (cnt(b, TK_AN)) {
+          tan_.out(Mm[i], k, k, kr, PT.tri_ptr[b], PT.tri_ptr[b + 1], TAA[i] != nullptr);
+          f_an += 2.0 * k * k * kr * cnt(b, TK_AN);
+        }
       }
     }
-    g.run(ctx);
+    g.run(ctx);  // TAA R^c^* first (overwrites), then the AN triples accumulate
+    tan_.run(ctx, f_an);
     for (int b = b0; b < b1; ++b) {
       int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
       g.out(S[b], std::max(kt, 1), kt, kr);
@@ -529,21 +575,24 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], std::max(kt, 1), false, kt);
     }
     g.run(ctx);
+    TriBatch tnn;
+    tnn.fam = fNN;
+    double f_nn = 0;
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (B.type[b] != BT_INADM) continue;
       int t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
       double* Dn = G->mem.get<double>((size_t)T.size[t] * T.size[r]);
       C.blk[b] = Dn;
       g.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r]);
-      for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
-        if (PT.tri[q].kind == TK_NN) {
-          int bx = PT.tri[q].bx, by = PT.tri[q].by, s = PT.tri[q].s;
-          g.term(Xm->c.blk[bx], Xm->c.ld_of(bx), false, Ym->c.blk[by], Ym->c.ld_of(by), false,
-                 (int)T.size[s]);
-        }
       if (QS[b]) g.term(QS[b], T.size[t], false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
+      if (cnt(b, TK_NN)) {
+        tnn.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r], PT.tri_ptr[b], PT.tri_ptr[b + 1], true);
+        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
+          if (PT.tri[q].kind == TK_NN) f_nn += 2.0 * T.size[t] * T.size[r] * T.size[PT.tri[q].s];
+      }
     }
-    g.run(ctx);
+    g.run(ctx);  // Q S Q^W^* (overwrites; zero when no expanded part), then the dense triples
+    tnn.run(ctx, f_nn);
   }
   step_end(ctx, 4);
 }

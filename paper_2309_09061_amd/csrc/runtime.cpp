@@ -106,12 +106,15 @@ void ctx_sync(h2_ctx* ctx) {
 // step timers
 // ---------------------------------------------------------------------------
 void step_begin(h2_ctx* ctx, int step) {
+  ctx->host_t0[step] = std::chrono::steady_clock::now();
   void* e = dev_event_create();
   dev_event_record(e, ctx->stream);
   ctx->events.push_back(e);
   ctx->ev_step.push_back(-1 - step);
 }
 void step_end(h2_ctx* ctx, int step) {
+  ctx->host_ms[step] +=
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ctx->host_t0[step]).count();
   void* e = dev_event_create();
   dev_event_record(e, ctx->stream);
   ctx->events.push_back(e);
@@ -236,7 +239,9 @@ void aux_collect(h2_ctx* ctx) {
   steps_collect(a);
   for (int i = 0; i < 8; ++i) {
     ctx->step_ms[i] += a->step_ms[i];
+    ctx->host_ms[i] += a->host_ms[i];
     a->step_ms[i] = 0.0;
+    a->host_ms[i] = 0.0;
   }
 }
 
@@ -364,6 +369,42 @@ void GemmBatch::run(h2_ctx* ctx) {
   k_gemm_sum(d_o, d_t, d_tiles, (int)ntiles, prec, ctx->stream);
   outs.clear();
   terms.clear();
+}
+
+void TriBatch::out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate) {
+  if (m <= 0 || n <= 0) return;
+  TriOut o{};
+  o.C = C;
+  o.ldc = std::max<int64_t>(ldc, 1);
+  o.m = m;
+  o.n = n;
+  o.q0 = q0;
+  o.q1 = q1;
+  o.beta = accumulate ? 1 : 0;
+  outs.push_back(o);
+}
+
+void TriBatch::run(h2_ctx* ctx, double flops) {
+  if (outs.empty()) return;
+  size_t ntiles = 0;
+  for (const TriOut& o : outs) ntiles += (size_t)((o.m + 15) / 16) * ((o.n + 15) / 16);
+  const size_t so = outs.size() * sizeof(TriOut), o_t = (so + 255) & ~(size_t)255;
+  char* h = stage_alloc(ctx, o_t + ntiles * 3 * sizeof(int32_t));
+  std::memcpy(h, outs.data(), so);
+  int32_t* tl = (int32_t*)(h + o_t);
+  for (size_t i = 0; i < outs.size(); ++i)
+    for (int j0 = 0; j0 < outs[i].n; j0 += 16)
+      for (int i0 = 0; i0 < outs[i].m; i0 += 16) {
+        *tl++ = (int32_t)i;
+        *tl++ = i0;
+        *tl++ = j0;
+      }
+  char* dev = (char*)stage_upload(ctx, h, o_t + ntiles * 3 * sizeof(int32_t));
+  double bytes = 0;
+  for (const TriOut& o : outs) bytes += 8.0 * o.m * o.n * (o.beta ? 2 : 1);
+  LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
+  k_gemm_tri((TriOut*)dev, (int32_t*)(dev + o_t), (int)ntiles, fam, ctx->stream);
+  outs.clear();
 }
 
 void QrBatch::add(double* A, int64_t lda, int m, int n, double* tau, double* R, int64_t ldr, int rrows) {

@@ -235,6 +235,7 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
     int b0 = B->lvl[l], b1 = (int)B->t.size();
     mids_next.clear();
     off_next.assign(1, 0);
+    P.kind_cnt.resize(4 * (size_t)b1, 0);
     for (int b = b0; b < b1; ++b) {
       const int tt = B->t[b], rr = B->s[b];
       rec.clear();
@@ -259,7 +260,8 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
           kind = TK_NN;
           nn = true;
         }
-        P.tri.push_back({md.s, md.bx, md.by, kind});
+        P.tri.push_back({md.s, md.bx, md.by, (int32_t)kind});
+        P.kind_cnt[4 * (size_t)b + kind]++;
         P.n_terminated++;
       }
       P.tri_ptr.push_back((int32_t)P.tri.size());

@@ -136,10 +136,12 @@ class Context:
             _check(self.lib, self.lib.h2_kernel_stats(self.h, 0, v.ctypes.data, 1))
         return out
 
-    def step_times(self) -> dict:
-        out = np.zeros(8)
-        n = self.lib.h2_step_times(self.h, out.ctypes.data, 8)
-        return {STEPS[i]: float(out[i]) for i in range(n)}
+    def step_times(self, host: bool = False) -> dict:
+        """Device time per step (ms); host=True: host issue time per step."""
+        out = np.zeros(16)
+        n = self.lib.h2_step_times(self.h, out.ctypes.data, 16)
+        off = 8 if host else 0
+        return {STEPS[i]: float(out[off + i]) for i in range(min(8, n - off))}
 
     def __del__(self):
         try:
