@@ -160,6 +160,8 @@ struct FillItem {
 void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
                 int prec, void* stream);
 void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, void* stream);
+// one workgroup per output of at most 64 x 64 (untransposed operands)
+void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, void* stream);
 // Factorization launches: lds_doubles is the dynamic LDS of the launch (a
 // problem whose working set fits it runs in LDS), slot the doubles of global
 // scratch per workgroup for the others (0: none); scratch then holds
@@ -449,6 +451,7 @@ struct GemmBatch {
 struct TriBatch {
   std::vector<TriOut> outs;
   TriFamily fam{};
+  bool block = false;  // outputs <= 64 x 64: one workgroup per output
   void out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate = false);
   void run(h2_ctx* ctx, double flops);
 };

@@ -185,6 +185,88 @@ __global__ __launch_bounds__(256) void gemm_tri_f64(const TriOut* __restrict__ o
   }
 }
 
+// ---------------------------------------------------------------------------
+// Block form of the triple products for outputs up to 64 x 64 (the dense
+// leaf blocks): one workgroup per output, operands staged through LDS in
+// k-chunks of 16 (A as loaded, B transposed so that both MFMA operands are
+// read along consecutive lanes), each wavefront owning a 32 x 32 quadrant
+// (2 x 2 tiles of 16 x 16).  Global loads run along columns (coalesced).
+// ---------------------------------------------------------------------------
+constexpr int kTriKC = 16;        // k-chunk
+constexpr int kTriLdA = 64 + 1;   // LDS stride of the A chunk (odd: spreads banks)
+constexpr int kTriLdB = kTriKC + 1;
+
+__global__ __launch_bounds__(256) void gemm_tri_block_f64(const TriOut* __restrict__ outs, const TriFamily F) {
+  __shared__ double As[kTriKC * kTriLdA];  // A(i, l) at i + l * kTriLdA
+  __shared__ double Bs[64 * kTriLdB];      // B(l, j) at l + j * kTriLdB
+  const TriOut o = outs[blockIdx.x];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;  // quadrant of this wavefront
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int t = o.q0; t < o.q1; ++t) {
+    const int4 tr = reinterpret_cast<const int4*>(F.tri)[t];
+    if (tr.w != F.kind) continue;  // uniform across the workgroup
+    const double* A = F.A[tr.y];
+    const double* B = F.B[tr.z];
+    const int64_t lda = F.lda[tr.y], ldb = F.ldb[tr.z];
+    const int k = F.ks ? F.ks[tr.x] : F.k;
+    for (int l0 = 0; l0 < k; l0 += kTriKC) {
+      __syncthreads();  // previous chunk consumed
+      // A chunk: 64 x 16, consecutive threads along i
+      for (int e = tid; e < 64 * kTriKC; e += 256) {
+        const int i = e & 63, l = e >> 6;
+        As[i + l * kTriLdA] = (i < o.m && l0 + l < k) ? A[i + (int64_t)(l0 + l) * lda] : 0.0;
+      }
+      // B chunk: 16 x 64, consecutive threads along l (down a column)
+      for (int e = tid; e < 64 * kTriKC; e += 256) {
+        const int l = e & (kTriKC - 1), j = e / kTriKC;
+        Bs[l + j * kTriLdB] = (j < o.n && l0 + l < k) ? B[(l0 + l) + (int64_t)j * ldb] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ls = 0; ls < kTriKC; ls += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = As[(wi + 16 * a + r) + (ls + q) * kTriLdA];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = Bs[(ls + q) + (wj + 16 * b + r) * kTriLdB];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  }
+  // FP64 accumulator layout: register v of lane (r, q) holds D[4v + q][r]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int jc = wj + 16 * b + r;
+      if (jc >= o.n) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ic = wi + 16 * a + 4 * v + q;
+        if (ic < o.m) {
+          double* p = o.C + ic + (int64_t)jc * o.ldc;
+          *p = o.beta ? *p + acc[a][b][v] : acc[a][b][v];
+        }
+      }
+    }
+}
+
+void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, void* stream) {
+  if (nouts <= 0) return;
+  H2_REQUIRE(!fam.tA && !fam.tB, H2_ERR_ARG, "gemm_tri_block: untransposed operands only");
+  hipLaunchKernelGGL(gemm_tri_block_f64, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
+  HIP_OK(hipGetLastError());
+}
+
 void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, void* stream) {
   if (ntiles <= 0) return;
   hipLaunchKernelGGL(gemm_tri_f64, dim3((ntiles + 3) / 4), dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles,

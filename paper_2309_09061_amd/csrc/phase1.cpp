@@ -577,6 +577,10 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     g.run(ctx);
     TriBatch tnn;
     tnn.fam = fNN;
+    int64_t leaf_max = 0;
+    for (int c = 0; c < T.ncl; ++c)
+      if (T.leaf(c)) leaf_max = std::max(leaf_max, T.size[c]);
+    tnn.block = leaf_max <= 64;
     double f_nn = 0;
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (B.type[b] != BT_INADM) continue;

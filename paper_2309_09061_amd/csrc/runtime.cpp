@@ -386,6 +386,16 @@ void TriBatch::out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool ac
 
 void TriBatch::run(h2_ctx* ctx, double flops) {
   if (outs.empty()) return;
+  if (block) {
+    for (const TriOut& o : outs) H2_REQUIRE(o.m <= 64 && o.n <= 64, H2_ERR_ARG, "triple block product: output over 64 x 64");
+    double bytes = 0;
+    for (const TriOut& o : outs) bytes += 8.0 * o.m * o.n * (o.beta ? 2 : 1);
+    TriOut* d = upload(ctx, outs);
+    LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
+    k_gemm_tri_block(d, (int)outs.size(), fam, ctx->stream);
+    outs.clear();
+    return;
+  }
   size_t ntiles = 0;
   for (const TriOut& o : outs) ntiles += (size_t)((o.m + 15) / 16) * ((o.n + 15) / 16);
   const size_t so = outs.size() * sizeof(TriOut), o_t = (so + 255) & ~(size_t)255;
