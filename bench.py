@@ -6,7 +6,7 @@ unit square, X = log|x-y|, Y = exp(-|x-y|), leaf 64, eta 1, Chebyshev order
 on T^XY) and phase 2 (h2_recompress into Z's block tree).  Inputs (tree,
 X, Y) are resident on the GPU before timing.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|fp64|fp32]
 """
 from __future__ import annotations
 
@@ -48,12 +48,52 @@ def cpu_baseline(seconds_budget: float = 30.0):
                       f"scaled by n={w.n}/{n_s} (linear complexity)"}
 
 
+def run_form(ctx, T, X, Y, w, precision, steps, warmup):
+    """Warm-up, then `steps` timed steps of the hot path in one precision."""
+    import torch
+
+    from paper_2309_09061_amd import h2
+
+    def step():
+        G = h2.h2_mul_intermediate(ctx, X, Y, w.eps, precision)
+        Z = h2.h2_recompress(ctx, G, h2.Matrix.zero(ctx, T), w.eps, precision)
+        return G, Z
+
+    for i in range(warmup):
+        G, Z = step()
+        torch.cuda.synchronize()
+        print(f"[{precision}] warmup step {i + 1}/{warmup} done", file=sys.stderr, flush=True)
+        del G, Z
+    ctx.profile(True)
+    ctx.kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev, host = {}, {}
+    for i in range(steps):
+        G, Z = step()
+        for k, v in ctx.step_times().items():
+            dev[k] = dev.get(k, 0.0) + v
+        for k, v in ctx.step_times(host=True).items():
+            host[k] = host.get(k, 0.0) + v
+        if i < steps - 1:
+            del G, Z
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ks = ctx.kernel_stats()
+    ctx.profile(False)
+    print(f"[{precision}] {steps} timed steps done", file=sys.stderr, flush=True)
+    return {"ms": (t1 - t0) / steps * 1e3, "dev": {k: v / steps for k, v in dev.items()},
+            "host": {k: v / steps for k, v in host.items()}, "ks": ks, "G": G, "Z": Z}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"],
+                    help="fp64: the float64 form; fp32: bulk products in float32; both: "
+                         "the float64 form as the headline value, the mixed form beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -61,6 +101,7 @@ def main():
               "(the multi-GPU layout is a design note, not a run)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import workloads as W
@@ -73,67 +114,59 @@ def main():
     Y = h2.Matrix.kernel(ctx, T, w.kernel_y, w.order)
     torch.cuda.synchronize()
 
-    def step():
-        G = h2.h2_mul_intermediate(ctx, X, Y, w.eps, args.precision)
-        Z = h2.h2_recompress(ctx, G, h2.Matrix.zero(ctx, T), w.eps, args.precision)
-        return G, Z
-
-    for i in range(args.warmup):
-        G, Z = step()
-        torch.cuda.synchronize()
-        print(f"warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-        del G, Z
-    ctx.profile(True)
-    ctx.kernel_stats(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps, hsteps = {}, {}
-    for i in range(args.steps):
-        G, Z = step()
-        for k, v in ctx.step_times().items():
-            steps[k] = steps.get(k, 0.0) + v
-        for k, v in ctx.step_times(host=True).items():
-            hsteps[k] = hsteps.get(k, 0.0) + v
-        if i < args.steps - 1:
-            del G, Z
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ks = ctx.kernel_stats()
-    ctx.profile(False)
-    ms = (t1 - t0) / args.steps * 1e3
+    main_prec = "fp32" if args.precision == "fp32" else "fp64"
+    r = run_form(ctx, T, X, Y, w, main_prec, args.steps, args.warmup)
+    G, Z, ks, ms = r["G"], r["Z"], r["ks"], r["ms"]
     ranks = {"p1_row_max": int(G.ranks(0).max()), "p2_row_max": int(Z.ranks(0).max()),
              "p2_row_mean": float(Z.ranks(0).mean())}
     sizes = G.sizes()
 
     dom = max(ks, key=lambda k: ks[k]["ms"])
     d = ks[dom]
+    mfma_peak = PEAK["fp64_mfma" if main_prec == "fp64" else "fp32_mfma"]
     if dom == "gemm_sum":
-        bound, peak = "mfma", PEAK["fp64_mfma" if args.precision == "fp64" else "fp32_mfma"]
+        bound, peak = "mfma", mfma_peak
     else:
         bound, peak = "alu", PEAK["fp64_vector"]
     achieved = d["flops"] / (d["ms"] * 1e-3) if d["ms"] > 0 else 0.0
     gemm = ks["gemm_sum"]
-    mfma_util = gemm["flops"] / (args.steps * ms * 1e-3) / PEAK["fp64_mfma"]
+    mfma_util = gemm["flops"] / (ms * 1e-3) / mfma_peak
 
     out = {
         "metric": "H^2 product time (s) and MFMA util at eps; mixed vs FP64 on one MI355X",
         "value": ms * 1e-3, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-bulk/f64",
+        "dtype": "f64" if main_prec == "fp64" else "f32-bulk/f64",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "dim": w.dim, "leaf": w.leaf_size, "eta": w.eta,
                    "order": w.order, "rank": w.rank, "kernel_x": w.kernel_x, "kernel_y": w.kernel_y,
-                   "eps": w.eps, "precision": args.precision},
+                   "eps": w.eps, "precision": main_prec},
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "avg_launch_ms": d["ms"] / max(d["launches"], 1),
                      "flops_per_launch": d["flops"] / max(d["launches"], 1)},
         "mfma_util_step": mfma_util,
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in ks.items()},
-        "step_ms": {k: v / args.steps for k, v in steps.items()},
-        "host_step_ms": {k: v / args.steps for k, v in hsteps.items()},
+        "step_ms": r["dev"],
+        "host_step_ms": r["host"],
         "ranks": ranks, "product_tree": sizes,
     }
+    if args.precision == "both":
+        m = run_form(ctx, T, X, Y, w, "fp32", args.steps, args.warmup)
+        # distance of the mixed Z to the float64 Z on seeded probe vectors
+        x = torch.from_numpy(np.ascontiguousarray(W.probe_vectors(7, w.n, 2).T)).cuda().t()
+        z64 = torch.zeros((2, w.n), dtype=torch.float64, device="cuda").t()
+        z32 = torch.zeros((2, w.n), dtype=torch.float64, device="cuda").t()
+        Z.matvec(x, z64)
+        m["Z"].matvec(x, z32)
+        torch.cuda.synchronize()
+        diff = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
+        mg = m["ks"]["gemm_sum"]
+        out["mixed"] = {"precision": "fp32 bulk products, fp64 factorizations", "ms_per_step": m["ms"],
+                        "speedup_vs_fp64": ms / m["ms"], "rel_diff_Zx_vs_fp64": diff,
+                        "gemm_ms_per_step": mg["ms"] / args.steps,
+                        "mfma_util_step": mg["flops"] / (m["ms"] * 1e-3) / PEAK["fp32_mfma"],
+                        "step_ms": m["dev"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -49,7 +49,11 @@ typedef enum {
 } h2_status;
 
 /* Arithmetic of the bulk products.  Orthogonalisation (QR), the SVDs that
- * choose ranks and the block norms always run in float64. */
+ * choose ranks and the block norms always run in float64, and all stored
+ * matrices are float64.  H2_FP32_BULK rounds the operands of every grouped
+ * product to float32 and accumulates in float32 (FP32 MFMA); its results
+ * differ from the float64 form by about 1e-7 relative, so it is accepted
+ * only for eps >= 1e-6 (H2_ERR_ARG otherwise). */
 typedef enum {
   H2_FP64 = 0,       /* everything in float64 */
   H2_FP32_BULK = 1   /* bulk products of both phases in float32 (FP32 MFMA) */

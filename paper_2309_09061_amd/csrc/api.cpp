@@ -32,6 +32,10 @@ static void need_device(const h2_ctx* ctx) {
   dev_set_device(ctx->device);
 }
 
+// FP32 rounding of the bulk products (about 6e-8 relative, with growth over
+// the levels) stays within the 2 eps bar of the mixed form only above this
+static constexpr double kFp32BulkMinEps = 1e-6;
+
 static void begin_call(h2_ctx* ctx, bool reset_steps = false) {
   ctx->ws.reset();
   if (ctx->aux) ctx->aux->ws.reset();  // its earlier work is ordered before ours
@@ -160,7 +164,8 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
     }
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
     H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
-    H2_REQUIRE(prec == H2_FP64, H2_ERR_UNSUPPORTED, "FP32 bulk products are not available yet");
+    H2_REQUIRE(prec != H2_FP32_BULK || eps >= kFp32BulkMinEps, H2_ERR_ARG,
+               "FP32 bulk products need eps >= 1e-6 (FP32 rounding would exceed 2 eps)");
     need_device(ctx);
     begin_call(ctx, true);
     for (int i = 0; i < count; ++i) {
@@ -200,7 +205,8 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     for (int i = 0; i < count; ++i) H2_REQUIRE(G[i] && Z[i], H2_ERR_ARG, "NULL operand");
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
     H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
-    H2_REQUIRE(prec == H2_FP64, H2_ERR_UNSUPPORTED, "FP32 bulk products are not available yet");
+    H2_REQUIRE(prec != H2_FP32_BULK || eps >= kFp32BulkMinEps, H2_ERR_ARG,
+               "FP32 bulk products need eps >= 1e-6 (FP32 rounding would exceed 2 eps)");
     for (int i = 0; i < count; ++i) H2_REQUIRE(Z[i]->zero, H2_ERR_UNSUPPORTED, "Z must be zero");
     need_device(ctx);
     begin_call(ctx);

@@ -159,9 +159,11 @@ struct FillItem {
 // launchers (descriptor arrays are device pointers)
 void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
                 int prec, void* stream);
-void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, void* stream);
+// prec 1: the products run on FP32 MFMA (operands rounded to FP32, FP32
+// accumulation, FP64 storage); 0: FP64 MFMA
+void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, int prec, void* stream);
 // one workgroup per output of at most 64 x 64 (untransposed operands)
-void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, void* stream);
+void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, int prec, void* stream);
 // Factorization launches: lds_doubles is the dynamic LDS of the launch (a
 // problem whose working set fits it runs in LDS), slot the doubles of global
 // scratch per workgroup for the others (0: none); scratch then holds
@@ -452,6 +454,7 @@ struct TriBatch {
   std::vector<TriOut> outs;
   TriFamily fam{};
   bool block = false;  // outputs <= 64 x 64: one workgroup per output
+  int prec = 0;
   void out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate = false);
   void run(h2_ctx* ctx, double flops);
 };

@@ -18,6 +18,8 @@
 // set fits that capacity, the same predicate the host used to size it.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace h2 {
@@ -70,16 +72,40 @@ __device__ inline double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 // grouped GEMM on FP64 MFMA
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_sum_f64(const GemmOut* __restrict__ outs,
-                                                    const GemmTerm* __restrict__ terms,
-                                                    const int32_t* __restrict__ tiles, int ntiles) {
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One MFMA step of a 16 x 16 x 4 product; the FP32 form (bulk products of
+// the mixed precision) rounds the FP64 operands to FP32 and accumulates in
+// FP32.  Accumulator layouts (measured on gfx950): FP64 register v of lane
+// (r, q) holds D[4v + q][r]; FP32 register v holds D[4q + v][r].
+template <bool F32>
+struct Mfma16 {
+  typedef typename std::conditional<F32, v4f, v4d>::type acc_t;
+  static __device__ __forceinline__ acc_t zero() {
+    acc_t z = {0, 0, 0, 0};
+    return z;
+  }
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    if constexpr (F32)
+      return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int v, int q) { return F32 ? 4 * q + v : 4 * v + q; }
+};
+
+template <bool F32>
+__global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict__ outs,
+                                                       const GemmTerm* __restrict__ terms,
+                                                       const int32_t* __restrict__ tiles, int ntiles) {
+  using M = Mfma16<F32>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tix = blockIdx.x * 4 + wave;
   if (tix >= ntiles) return;
   const int oi = tiles[3 * tix], i0 = tiles[3 * tix + 1], j0 = tiles[3 * tix + 2];
   const GemmOut o = outs[oi];
   const int r = lane & 15, q = lane >> 4;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  typename M::acc_t acc = M::zero();
   const int i = i0 + r, j = j0 + r;
   const bool ia = i < o.m, jb = j < o.n;
   for (int ti = o.t0; ti < o.t1; ++ti) {
@@ -101,20 +127,18 @@ __global__ __launch_bounds__(256) void gemm_sum_f64(const GemmOut* __restrict__ 
       double a = 0.0, b = 0.0;
       if (ia && l < T.k) a = A[(int64_t)i * sa_i + (int64_t)l * sa_l];
       if (jb && l < T.k) b = eye ? (l == j ? 1.0 : 0.0) : B[(int64_t)l * sb_l + (int64_t)j * sb_j];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a * alpha, b, acc, 0, 0, 0);
+      acc = M::step(a * alpha, b, acc);
     }
   }
-  // FP64 accumulator layout (measured on gfx950): register v of lane (r, q)
-  // holds D[4v + q][r]
   double* C = (double*)o.C;
   const int jc = j0 + r;
   if (jc < o.n) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ic = i0 + 4 * v + q;
+      const int ic = i0 + M::row(v, q);
       if (ic < o.m) {
         double* p = C + ic + (int64_t)jc * o.ldc;
-        *p = o.beta ? *p + acc[v] : acc[v];
+        *p = o.beta ? *p + (double)acc[v] : (double)acc[v];
       }
     }
   }
@@ -123,9 +147,11 @@ __global__ __launch_bounds__(256) void gemm_sum_f64(const GemmOut* __restrict__ 
 void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
                 int prec, void* stream) {
   if (ntiles <= 0) return;
-  (void)prec;
   dim3 grid((ntiles + 3) / 4);
-  hipLaunchKernelGGL(gemm_sum_f64, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
+  if (prec)
+    hipLaunchKernelGGL(gemm_sum_kernel<true>, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
+  else
+    hipLaunchKernelGGL(gemm_sum_kernel<false>, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
   HIP_OK(hipGetLastError());
 }
 
@@ -137,20 +163,22 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 extern __shared__ double lds_dyn[];
 
 // ---------------------------------------------------------------------------
-// grouped products over product-tree triples (FP64 MFMA): one wavefront per
+// grouped products over product-tree triples (MFMA): one wavefront per
 // 16 x 16 output tile; each tile scans its block's triples and accumulates the
 // ones of the launch's kind
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gemm_tri_f64(const TriOut* __restrict__ outs,
-                                                    const int32_t* __restrict__ tiles, int ntiles,
-                                                    const TriFamily F) {
+template <bool F32>
+__global__ __launch_bounds__(256) void gemm_tri_kernel(const TriOut* __restrict__ outs,
+                                                       const int32_t* __restrict__ tiles, int ntiles,
+                                                       const TriFamily F) {
+  using M = Mfma16<F32>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tix = blockIdx.x * 4 + wave;
   if (tix >= ntiles) return;
   const int oi = tiles[3 * tix], i0 = tiles[3 * tix + 1], j0 = tiles[3 * tix + 2];
   const TriOut o = outs[oi];
   const int r = lane & 15, q = lane >> 4;
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  typename M::acc_t acc = M::zero();
   const int i = i0 + r, j = j0 + r;
   const bool ia = i < o.m, jb = j < o.n;
   for (int t = o.q0; t < o.q1; ++t) {
@@ -167,19 +195,18 @@ __global__ __launch_bounds__(256) void gemm_tri_f64(const TriOut* __restrict__ o
       double a = 0.0, b = 0.0;
       if (ia && l < k) a = A[(int64_t)i * sa_i + (int64_t)l * sa_l];
       if (jb && l < k) b = B[(int64_t)l * sb_l + (int64_t)j * sb_j];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      acc = M::step(a, b, acc);
     }
   }
-  // FP64 accumulator layout: register v of lane (r, q) holds D[4v + q][r]
   double* C = o.C;
   const int jc = j0 + r;
   if (jc < o.n) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int ic = i0 + 4 * v + q;
+      const int ic = i0 + M::row(v, q);
       if (ic < o.m) {
         double* p = C + ic + (int64_t)jc * o.ldc;
-        *p = o.beta ? *p + acc[v] : acc[v];
+        *p = o.beta ? *p + (double)acc[v] : (double)acc[v];
       }
     }
   }
@@ -196,18 +223,20 @@ constexpr int kTriKC = 16;        // k-chunk
 constexpr int kTriLdA = 64 + 1;   // LDS stride of the A chunk (odd: spreads banks)
 constexpr int kTriLdB = kTriKC + 1;
 
-__global__ __launch_bounds__(256) void gemm_tri_block_f64(const TriOut* __restrict__ outs, const TriFamily F) {
+template <bool F32>
+__global__ __launch_bounds__(256) void gemm_tri_block_kernel(const TriOut* __restrict__ outs, const TriFamily F) {
+  using M = Mfma16<F32>;
   __shared__ double As[kTriKC * kTriLdA];  // A(i, l) at i + l * kTriLdA
   __shared__ double Bs[64 * kTriLdB];      // B(l, j) at l + j * kTriLdB
   const TriOut o = outs[blockIdx.x];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int r = lane & 15, q = lane >> 4;
   const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;  // quadrant of this wavefront
-  v4d acc[2][2];
+  typename M::acc_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = M::zero();
   for (int t = o.q0; t < o.q1; ++t) {
     const int4 tr = reinterpret_cast<const int4*>(F.tri)[t];
     if (tr.w != F.kind) continue;  // uniform across the workgroup
@@ -238,11 +267,10 @@ __global__ __launch_bounds__(256) void gemm_tri_block_f64(const TriOut* __restri
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b) acc[a][b] = M::step(av[a], bv[b], acc[a][b]);
       }
     }
   }
-  // FP64 accumulator layout: register v of lane (r, q) holds D[4v + q][r]
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -251,26 +279,32 @@ __global__ __launch_bounds__(256) void gemm_tri_block_f64(const TriOut* __restri
       if (jc >= o.n) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int ic = wi + 16 * a + 4 * v + q;
+        const int ic = wi + 16 * a + M::row(v, q);
         if (ic < o.m) {
           double* p = o.C + ic + (int64_t)jc * o.ldc;
-          *p = o.beta ? *p + acc[a][b][v] : acc[a][b][v];
+          *p = o.beta ? *p + (double)acc[a][b][v] : (double)acc[a][b][v];
         }
       }
     }
 }
 
-void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, void* stream) {
+void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, int prec, void* stream) {
   if (nouts <= 0) return;
   H2_REQUIRE(!fam.tA && !fam.tB, H2_ERR_ARG, "gemm_tri_block: untransposed operands only");
-  hipLaunchKernelGGL(gemm_tri_block_f64, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
+  if (prec)
+    hipLaunchKernelGGL(gemm_tri_block_kernel<true>, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
+  else
+    hipLaunchKernelGGL(gemm_tri_block_kernel<false>, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
   HIP_OK(hipGetLastError());
 }
 
-void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, void* stream) {
+void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, int prec, void* stream) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(gemm_tri_f64, dim3((ntiles + 3) / 4), dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles,
-                     fam);
+  dim3 grid((ntiles + 3) / 4);
+  if (prec)
+    hipLaunchKernelGGL(gemm_tri_kernel<true>, grid, dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles, fam);
+  else
+    hipLaunchKernelGGL(gemm_tri_kernel<false>, grid, dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles, fam);
   HIP_OK(hipGetLastError());
 }
 

@@ -507,6 +507,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     taa.fam = fAA;
     tna.fam = fNA;
     tan_.fam = fAN;
+    taa.prec = tna.prec = tan_.prec = prec;
     double f_aa = 0, f_na = 0, f_an = 0;
     for (int b = b0; b < b1; ++b) {
       int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
@@ -577,6 +578,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     g.run(ctx);
     TriBatch tnn;
     tnn.fam = fNN;
+    tnn.prec = prec;
     int64_t leaf_max = 0;
     for (int c = 0; c < T.ncl; ++c)
       if (T.leaf(c)) leaf_max = std::max(leaf_max, T.size[c]);

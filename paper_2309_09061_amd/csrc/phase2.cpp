@@ -543,6 +543,7 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
         int kt = Gp->c.V.rank[t], kr = Gp->c.W.rank[r];
         double* QS = ws.get<double>((size_t)T.size[t] * std::max(kr, 1));
         GemmBatch g0;
+        g0.prec = prec;
         g0.out(QS, T.size[t], (int)T.size[t], kr);
         g0.term(Gp->c.V.leaf[t], Gp->c.V.leaf_ld[t], false, Gp->c.blk[b], Gp->c.ld_of(b), false, kt);
         g0.run(ctx);

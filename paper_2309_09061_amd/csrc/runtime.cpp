@@ -392,7 +392,7 @@ void TriBatch::run(h2_ctx* ctx, double flops) {
     for (const TriOut& o : outs) bytes += 8.0 * o.m * o.n * (o.beta ? 2 : 1);
     TriOut* d = upload(ctx, outs);
     LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
-    k_gemm_tri_block(d, (int)outs.size(), fam, ctx->stream);
+    k_gemm_tri_block(d, (int)outs.size(), fam, prec, ctx->stream);
     outs.clear();
     return;
   }
@@ -413,7 +413,7 @@ void TriBatch::run(h2_ctx* ctx, double flops) {
   double bytes = 0;
   for (const TriOut& o : outs) bytes += 8.0 * o.m * o.n * (o.beta ? 2 : 1);
   LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
-  k_gemm_tri((TriOut*)dev, (int32_t*)(dev + o_t), (int)ntiles, fam, ctx->stream);
+  k_gemm_tri((TriOut*)dev, (int32_t*)(dev + o_t), (int)ntiles, fam, prec, ctx->stream);
   outs.clear();
 }
 

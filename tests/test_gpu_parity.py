@@ -196,3 +196,48 @@ def test_workload_2d_full_size():
     # the product against X (Y x) stays within eps
     ref = np.array(gold["XYx"])
     assert np.abs(zx.cpu().numpy()[idx] - ref).max() <= w.eps * np.max(gold["XYx_norm"])
+
+
+# ---------------------------------------------------------------------------
+# mixed form: bulk products on FP32 MFMA, factorizations and ranks in FP64.
+# Bar: relative Frobenius distance to the FP64 oracle <= 2 eps for G and Z
+# (ranks may differ where FP32 rounding moves a singular value across eps),
+# and Z stays within eps of X Y.
+MIXED = ["2d", "ragged", "2d64", "sph"]
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_case_mixed(name):
+    h2 = _h2()
+    n, d, leaf, order, kx, ky, eta, seed, dist, eps = CASES[name]
+    _say(f"[gpu] case={name} n={n} eps={eps}: mixed form")
+    pts = W.make_points(seed, n, d, dist)
+    c = ctx()
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order)
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    G = h2.h2_mul_intermediate(c, X, Y, eps, "fp32")
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps, "fp32")
+    torch.cuda.synchronize()
+    return G, Z
+
+
+@pytest.mark.parametrize("name", MIXED)
+def test_mixed_parity(name):
+    _, tree, _, _, p1, p2, Xd, Yd = oracle_case(name)
+    eps = CASES[name][-1]
+    G, Z = gpu_case_mixed(name)
+    assert relF(dense_of(G, tree.n), p1.G.dense()) <= 2 * eps
+    Zg = dense_of(Z, tree.n)
+    assert relF(Zg, p2.Z.dense()) <= 2 * eps
+    XY = Xd @ Yd
+    assert np.linalg.norm(Zg - XY, 2) / np.linalg.norm(XY, 2) <= eps
+
+
+def test_mixed_rejects_small_eps():
+    h2 = _h2()
+    c = ctx()
+    T = h2.Tree(c, W.make_points(1, 256, 1, "uniform"), 16, 1.0)
+    X = h2.Matrix.kernel(c, T, "log", 4)
+    with pytest.raises(h2.H2Error):
+        h2.h2_mul_intermediate(c, X, X, 1e-8, "fp32")
