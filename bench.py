@@ -48,6 +48,48 @@ def cpu_baseline(seconds_budget: float = 30.0):
                       f"scaled by n={w.n}/{n_s} (linear complexity)"}
 
 
+FAMILY_KERNELS = {"gemm_sum": ("gemm_sum_kernel", "gemm_tri_kernel", "gemm_tri_block_kernel"),
+                  "tsqr": ("tsqr_rb_kernel", "tsqr_kernel"),
+                  "jacobi": ("jacobi_kernel", "jacobi_small_kernel")}
+
+
+def measured_traffic(family: str, precision: str):
+    """HBM bytes per launch of a kernel family from the committed counter
+    summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary is
+    missing or the kernels changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"traffic_2d_n16384_{precision}.md")
+    src = os.path.join(ROOT, "paper_2309_09061_amd", "csrc", "kernels_la.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernels source sha256: ([0-9a-f]{64})", text)
+    if not m or m.group(1) != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    launches = total = 0.0
+    for row in re.finditer(r"^\| ([^|]+) \| (\d+) \| ([0-9.]+) \| ([0-9.]+) \|$", text, re.M):
+        name = row.group(1).split("<")[0].strip()
+        if name in FAMILY_KERNELS.get(family, ()):
+            n = float(row.group(2))
+            launches += n
+            total += n * (float(row.group(3)) + float(row.group(4))) * 2**20
+    return total / launches if launches else None
+
+
+def copy_calibration():
+    """A plain device copy of 2^25 float64 (256 MiB read, 256 MiB written):
+    the counters FETCH_SIZE / WRITE_SIZE of this copy against its known bytes
+    give the scale applied to the counters of the library kernels."""
+    import torch
+    a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {a.numel() * 8} bytes", flush=True)
+
+
 def run_form(ctx, T, X, Y, w, precision, steps, warmup):
     """Warm-up, then `steps` timed steps of the hot path in one precision."""
     import torch
@@ -95,7 +137,12 @@ def main():
                     help="fp64: the float64 form; fp32: bulk products in float32; both: "
                          "the float64 form as the headline value, the mixed form beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB on the GPU (the reference for the HBM traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is a design note, not a run)", file=sys.stderr)
@@ -142,7 +189,7 @@ def main():
                    "order": w.order, "rank": w.rank, "kernel_x": w.kernel_x, "kernel_y": w.kernel_y,
                    "eps": w.eps, "precision": main_prec},
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom, main_prec),
                      "avg_launch_ms": d["ms"] / max(d["launches"], 1),
                      "flops_per_launch": d["flops"] / max(d["launches"], 1)},
         "mfma_util_step": mfma_util,
