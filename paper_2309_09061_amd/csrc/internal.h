@@ -188,7 +188,11 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
 int jacobi_small_max_m();
 int jacobi_max_len();
 void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* stream);
-void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream);
+// medium problems (m <= jacobi_mid_max_m()) take 256-thread workgroups,
+// larger ones 1024 (wide)
+int jacobi_mid_max_m();
+void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, bool wide,
+              void* stream);
 void k_fill(const FillItem* items, int n, void* stream);
 
 // interpolation / kernel evaluation

@@ -382,6 +382,7 @@ __global__ void qr_kernel(const QrProb* __restrict__ probs, int lds_cap);
 __global__ void apply_kernel(const ApplyProb* __restrict__ probs, const int32_t* __restrict__ work, int lds_cap);
 __global__ void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
                             size_t slot, int lds_cap);
+template <int NT>
 __global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
                               size_t slot, int lds_cap);
 __global__ void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob, int per);
@@ -398,7 +399,8 @@ int lds_limit_doubles() {
     // 2 KiB stay for static shared data
     int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
     const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
-                        (const void*)jacobi_kernel, (const void*)jacobi_small_kernel,
+                        (const void*)jacobi_kernel<256>, (const void*)jacobi_kernel<1024>,
+                        (const void*)jacobi_small_kernel,
                         (const void*)tsqr_rb_kernel<16, 1, 8>, (const void*)tsqr_rb_kernel<8, 1, 16>,
                         (const void*)tsqr_rb_kernel<8, 2, 8>};
     for (const void* k : ks)
@@ -920,9 +922,13 @@ __device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua
   be = group_sum(be, gsz);
   ga = group_sum(ga, gsz);
   if (!(live && al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+  // tangent of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0
+  // with zeta = d / q: t = sign(d) q / (|d| + sqrt(d^2 + q^2))
+  const double d = be - al, qq = 2.0 * ga;
+  const double rr = sqrt(d * d + qq * qq);
+  if (!(rr > 0.0)) return false;
+  const double t = (d >= 0.0 ? qq : -qq) / (fabs(d) + rr);
+  const double c = rsqrt(1.0 + t * t), s = c * t;
 #pragma unroll
   for (int k = 0; k < EPL; ++k) {
     ga_[gl + k * gsz] = c * x[k] - s * y[k];
@@ -1103,20 +1109,24 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   }
 }
 
-constexpr int kJacobiThreads = 1024;
+// Medium problems (m <= kJacobiMidM) take 256 threads, larger ones 1024: a
+// round is a chain of dependent LDS loads, cross-lane sums and the rotation;
+// wider groups shorten the per-lane work of long columns but lengthen the
+// cross-lane sums (measured: 256 threads win at m = 64, 1024 at m ~ 100).
+constexpr int kJacobiMidM = 64;
 
-__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
-                                                                double* __restrict__ scratch, size_t slot,
-                                                                int lds_cap) {
+template <int NT>
+__global__ __launch_bounds__(NT) void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob,
+                                                    double* __restrict__ scratch, size_t slot, int lds_cap) {
   __shared__ JacobiShared sh;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const JacobiProb P = probs[pi];
     if (threadIdx.x == 0) sh.nrot = 0;
     const int s0 = P.skip ? min(max(*P.skip, 0), P.m) : 0;
     if (jacobi_need(P.p, P.m, P.mode) <= (size_t)lds_cap)
-      jacobi_solve<kJacobiThreads>(P, lds_dyn, s0, sh);
+      jacobi_solve<NT>(P, lds_dyn, s0, sh);
     else
-      jacobi_solve<kJacobiThreads>(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
+      jacobi_solve<NT>(P, scratch + (size_t)blockIdx.x * slot, s0, sh);
     __syncthreads();
   }
 }
@@ -1136,12 +1146,19 @@ __global__ __launch_bounds__(256) void jacobi_small_kernel(const JacobiProb* __r
   jacobi_solve<64>(P, lds_dyn + (size_t)wave * per, s0, unused);
 }
 
-void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, void* stream) {
+int jacobi_mid_max_m() { return kJacobiMidM; }
+
+void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, bool wide,
+              void* stream) {
   if (n <= 0) return;
   H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "jacobi: global scratch missing");
   const int grid = slot == 0 ? n : std::min(n, 1024);
-  hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(kJacobiThreads), (size_t)lds_doubles * 8,
-                     (hipStream_t)stream, probs, n, scratch, slot, lds_doubles);
+  if (wide)
+    hipLaunchKernelGGL(jacobi_kernel<1024>, dim3(grid), dim3(1024), (size_t)lds_doubles * 8, (hipStream_t)stream,
+                       probs, n, scratch, slot, lds_doubles);
+  else
+    hipLaunchKernelGGL(jacobi_kernel<256>, dim3(grid), dim3(256), (size_t)lds_doubles * 8, (hipStream_t)stream,
+                       probs, n, scratch, slot, lds_doubles);
   HIP_OK(hipGetLastError());
 }
 

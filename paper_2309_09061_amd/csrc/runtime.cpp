@@ -627,11 +627,26 @@ void JacobiBatch::run(h2_ctx* ctx) {
     LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_s, bytes_s);
     k_jacobi_small(d, (int)small.size(), (int)per, ctx->stream);
   }
-  if (!large.empty()) {
-    double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(large.size(), 1024)) : nullptr;
-    JacobiProb* d = upload(ctx, large);
-    LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_l, bytes_l);
-    k_jacobi(d, (int)large.size(), lds_for(lds), slot, scratch, ctx->stream);
+  // the rest: medium problems on 256-thread groups, large ones on 1024
+  std::vector<JacobiProb> grp[2];
+  size_t gslot[2] = {0, 0}, glds[2] = {0, 0};
+  for (const JacobiProb& j : large) {
+    const int w = std::max(j.m, j.p) > jacobi_mid_max_m() ? 1 : 0;
+    grp[w].push_back(j);
+    const size_t need = jacobi_need_doubles(j.p, j.m, j.mode);
+    if (need > lim)
+      gslot[w] = std::max(gslot[w], need);
+    else
+      glds[w] = std::max(glds[w], need);
+  }
+  (void)slot;
+  (void)lds;
+  for (int w = 0; w < 2; ++w) {
+    if (grp[w].empty()) continue;
+    double* scratch = gslot[w] ? ctx->ws.get<double>(gslot[w] * std::min<size_t>(grp[w].size(), 1024)) : nullptr;
+    JacobiProb* d = upload(ctx, grp[w]);
+    LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_l * grp[w].size() / large.size(), bytes_l * grp[w].size() / large.size());
+    k_jacobi(d, (int)grp[w].size(), lds_for(glds[w]), gslot[w], scratch, w == 1, ctx->stream);
   }
   if (wc.dev) {  // counts of both launches, resolved with the second one's timing
     dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
