@@ -1,9 +1,9 @@
-"""Write the oracle's results on the 2-D workload (n = 16384) to c2_oracle.json.
+"""Write the oracle's results on a full-size workload to <workload>_oracle.json.
 
 Calls only oracle/ and workloads.py.  Stored: the rank profiles of both
 phases, and the products G x, Z x and X (Y x) for two seeded Gaussian probe
 vectors sampled at 512 seeded positions (cluster order), plus their full
-norms.  Run: python tests/golden/make_c2_golden.py
+norms.  Run: python tests/golden/make_golden.py c2   (or c3)
 """
 import json
 import os
@@ -18,14 +18,18 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle as O  # noqa: E402
 import workloads as W  # noqa: E402
 
+NAMES = {"c2": W.C2, "c3": W.C3}
 
-def main():
-    w = W.C2
+
+def main(key: str):
+    w = NAMES[key]
     pts = w.points()
     t0 = time.time()
     tree, bt, X, Y = O.build_problem(pts, w.leaf_size, w.eta, w.order, w.kernel_x, w.kernel_y)
+    print(f"[{key}] problem built ({time.time() - t0:.1f}s)", flush=True)
     p1, p2 = O.multiply(X, Y, bt, w.eps)
     elapsed = time.time() - t0
+    print(f"[{key}] oracle done ({elapsed:.1f}s)", flush=True)
     x = W.probe_vectors(101, w.n, 2)
     idx = np.sort(np.random.default_rng(102).choice(w.n, 512, replace=False))
     gx, zx, xyx = p1.G.matvec(x), p2.Z.matvec(x), X.matvec(Y.matvec(x))
@@ -42,10 +46,10 @@ def main():
         "XYx_norm": np.linalg.norm(xyx, axis=0).tolist(),
         "txy_adm": len(p1.G.S), "txy_inadm": len(p1.G.N),
     }
-    with open(os.path.join(HERE, "c2_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, f"{key}_oracle.json"), "w") as f:
         json.dump(out, f)
-    print(f"wrote c2_oracle.json (oracle {elapsed:.1f}s)")
+    print(f"wrote {key}_oracle.json (oracle {elapsed:.1f}s)")
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "c2")
