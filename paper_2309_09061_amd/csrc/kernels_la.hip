@@ -119,14 +119,24 @@ __global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict
     }
     const double* A = (const double*)T.A;
     const double* B = (const double*)T.B;
-    const bool tA = T.flags & GT_TA, tB = T.flags & GT_TB, eye = T.flags & GT_BEYE;
+    const bool tA = T.flags & GT_TA, tB = T.flags & GT_TB;
     const int64_t sa_i = tA ? T.lda : 1, sa_l = tA ? 1 : T.lda;
+    if (T.flags & GT_BEYE) {
+      // op(A) times the identity: the tile's own entries of op(A), added in
+      // the accumulator layout (no products, no re-reads across the tile)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ia_ = i0 + M::row(v, q), jc = j0 + r;
+        if (ia_ < o.m && jc < o.n && jc < T.k) acc[v] += alpha * A[(int64_t)ia_ * sa_i + (int64_t)jc * sa_l];
+      }
+      continue;
+    }
     const int64_t sb_l = tB ? T.ldb : 1, sb_j = tB ? 1 : T.ldb;
     for (int l0 = 0; l0 < T.k; l0 += 4) {
       const int l = l0 + q;
       double a = 0.0, b = 0.0;
       if (ia && l < T.k) a = A[(int64_t)i * sa_i + (int64_t)l * sa_l];
-      if (jb && l < T.k) b = eye ? (l == j ? 1.0 : 0.0) : B[(int64_t)l * sb_l + (int64_t)j * sb_j];
+      if (jb && l < T.k) b = B[(int64_t)l * sb_l + (int64_t)j * sb_j];
       acc = M::step(a * alpha, b, acc);
     }
   }
