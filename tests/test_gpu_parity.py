@@ -162,20 +162,25 @@ def test_exact_without_truncation():
     assert relF(dense_of(Z, tree.n), XY) < 1e-12
 
 
-def test_workload_2d_full_size():
-    """The 2-D workload at n = 16384 (the benchmarked configuration):
-    rank profiles and sampled products against the stored oracle results."""
-    gold = json.load(open(os.path.join(HERE, "golden", "c2_oracle.json")))
+FULL = {"c2": W.C2, "c3": W.C3}
+
+
+@pytest.mark.parametrize("key", list(FULL))
+def test_workload_full_size(key):
+    """The 2-D workload at n = 16384 (the benchmarked configuration) and the
+    sphere workload at n = 131072: rank profiles and sampled products against
+    the stored oracle results."""
+    gold = json.load(open(os.path.join(HERE, "golden", f"{key}_oracle.json")))
     h2 = _h2()
-    w = W.C2
-    _say("[gpu] workload c2 n=16384: build")
+    w = FULL[key]
+    _say(f"[gpu] workload {key} n={w.n}: build")
     c = ctx()
     T = h2.Tree(c, w.points(), w.leaf_size, w.eta)
     X = h2.Matrix.kernel(c, T, w.kernel_x, w.order)
-    Y = h2.Matrix.kernel(c, T, w.kernel_y, w.order)
-    _say("[gpu] workload c2: phase 1")
+    Y = X if w.kernel_y == w.kernel_x else h2.Matrix.kernel(c, T, w.kernel_y, w.order)
+    _say(f"[gpu] workload {key}: phase 1")
     G = h2.h2_mul_intermediate(c, X, Y, w.eps)
-    _say("[gpu] workload c2: phase 2")
+    _say(f"[gpu] workload {key}: phase 2")
     Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), w.eps)
     torch.cuda.synchronize()
     assert list(G.ranks(0)) == gold["ranks_p1_row"]
@@ -188,14 +193,22 @@ def test_workload_2d_full_size():
     G.matvec(x, gx)
     Z.matvec(x, zx)
     torch.cuda.synchronize()
-    for got, key in ((gx, "Gx"), (zx, "Zx")):
+    for got, k in ((gx, "Gx"), (zx, "Zx")):
         got = got.cpu().numpy()
-        ref = np.array(gold[key])
-        assert np.abs(got[idx] - ref).max() <= 1e-10 * np.min(gold[key + "_norm"])
-        assert np.allclose(np.linalg.norm(got, axis=0), gold[key + "_norm"], rtol=1e-10)
+        ref = np.array(gold[k])
+        assert np.abs(got[idx] - ref).max() <= 1e-10 * np.min(gold[k + "_norm"])
+        assert np.allclose(np.linalg.norm(got, axis=0), gold[k + "_norm"], rtol=1e-10)
     # the product against X (Y x) stays within eps
     ref = np.array(gold["XYx"])
     assert np.abs(zx.cpu().numpy()[idx] - ref).max() <= w.eps * np.max(gold["XYx_norm"])
+    # mixed form on the same inputs: within 2 eps of the oracle's Z x
+    Gm = h2.h2_mul_intermediate(c, X, Y, w.eps, "fp32")
+    Zm = h2.h2_recompress(c, Gm, h2.Matrix.zero(c, T), w.eps, "fp32")
+    zm = zeros_colmajor(w.n, 2)
+    Zm.matvec(x, zm)
+    torch.cuda.synchronize()
+    zm = zm.cpu().numpy()
+    assert np.abs(zm[idx] - np.array(gold["Zx"])).max() <= 2 * w.eps * np.min(gold["Zx_norm"])
 
 
 # ---------------------------------------------------------------------------
