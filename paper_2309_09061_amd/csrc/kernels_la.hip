@@ -859,10 +859,11 @@ static __host__ __device__ inline int pow2ceil(int x) {
   while (p < x) p <<= 1;
   return p;
 }
-// lanes per pair for nt threads: all pairs of a round at once where possible
-static __host__ __device__ inline int jacobi_gsz(int npairs, int nt) {
+// lanes per pair for nt threads (at least gmin): all pairs of a round at
+// once where possible
+static __host__ __device__ inline int jacobi_gsz(int npairs, int nt, int gmin) {
   int g = 64;
-  while (g > 4 && g * npairs > nt) g >>= 1;
+  while (g > gmin && g * npairs > nt) g >>= 1;
   return g;
 }
 // Column stride of the rotated matrix.  Rows len .. L-1 (L = max(gsz,
@@ -1030,8 +1031,11 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   const int npairs = (ncol + (ncol & 1)) / 2;
   // at most 8 elements per lane (register budget of 1024-thread groups): long
   // columns take wider lane groups, which then take several pairs in turn
-  int gsz = jacobi_gsz(npairs, NT);
-  while (gsz < 64 && max(gsz, pow2ceil(len)) > 8 * gsz) gsz *= 2;
+  // a wavefront alone on a problem (NT = 64) takes every pair of a round at
+  // once (down to one lane per pair) and up to 32 elements per lane
+  constexpr int kEplCap = NT == 64 ? 32 : 8;
+  int gsz = jacobi_gsz(npairs, NT, NT == 64 ? 1 : 4);
+  while (gsz < 64 && max(gsz, pow2ceil(len)) > kEplCap * gsz) gsz *= 2;
   const int ld = jacobi_ld(len, gsz);
   const int ldu = jacobi_ld(m, gsz);
   const int epl = (ld - (gsz < 32 ? gsz : 0)) / gsz;  // L / gsz, a power of two
@@ -1061,7 +1065,15 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
       case 1: sweeps = jacobi_sweeps<NT, 1>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
       case 2: sweeps = jacobi_sweeps<NT, 2>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
       case 4: sweeps = jacobi_sweeps<NT, 4>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
-      default: sweeps = jacobi_sweeps<NT, 8>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
+      case 8: sweeps = jacobi_sweeps<NT, 8>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh); break;
+      default:
+        if constexpr (NT == 64) {
+          if (epl == 16)
+            sweeps = jacobi_sweeps<NT, 16>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh);
+          else
+            sweeps = jacobi_sweeps<NT, 32>(G, ld, U, ldu, m, ncol, coff, gsz, tol2, my_rot, sh);
+        }
+        break;
     }
   }
   if (P.work) {
@@ -1141,14 +1153,15 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const JacobiProb* __restrict
   }
 }
 
-// small problems (at most kJacobiSmallM columns): one wavefront per problem,
-// four per workgroup, each on its own slice of `per` doubles of LDS
+// small problems (at most kJacobiSmallM columns): one wavefront
+// per problem, blockDim.x / 64 per workgroup, each on its own slice of `per`
+// doubles of LDS.  No workgroup barriers: a round is one wavefront's work.
 constexpr int kJacobiSmallM = 32;
 
 __global__ __launch_bounds__(256) void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob,
                                                            int per) {
   const int wave = threadIdx.x >> 6;
-  const int pi = blockIdx.x * 4 + wave;
+  const int pi = blockIdx.x * (blockDim.x >> 6) + wave;
   if (pi >= nprob) return;  // the whole wavefront leaves; no workgroup barriers below
   const JacobiProb P = probs[pi];
   const int s0 = P.skip ? min(max(*P.skip, 0), P.m) : 0;
@@ -1176,8 +1189,12 @@ int jacobi_small_max_m() { return kJacobiSmallM; }
 
 void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* stream) {
   if (n <= 0) return;
-  H2_REQUIRE((size_t)4 * per_doubles <= (size_t)lds_limit_doubles(), H2_ERR_ARG, "jacobi: small problems too large");
-  hipLaunchKernelGGL(jacobi_small_kernel, dim3((n + 3) / 4), dim3(256), (size_t)4 * per_doubles * 8,
+  // several problems per workgroup only when there are enough of them to
+  // fill every compute unit; otherwise each problem gets a compute unit alone
+  int wpb = std::min(4, lds_limit_doubles() / std::max(per_doubles, 1));
+  if (n < 4 * 256) wpb = std::min(wpb, 1);
+  H2_REQUIRE(wpb >= 1, H2_ERR_ARG, "jacobi: small problems too large");
+  hipLaunchKernelGGL(jacobi_small_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), (size_t)wpb * per_doubles * 8,
                      (hipStream_t)stream, probs, n, per_doubles);
   HIP_OK(hipGetLastError());
 }

@@ -607,7 +607,7 @@ void JacobiBatch::run(h2_ctx* ctx) {
     const double pl = j.mode ? j.p : j.m, len = j.mode ? j.m : j.p;
     const double f = pl * (pl - 1) / 2 * (6.0 * len + (j.mode ? 0.0 : 6.0 * j.m));
     const double by = 8.0 * ((double)j.p * j.m + (j.U ? (double)j.m * j.m : 0.0));
-    if (j.m <= jacobi_small_max_m() && 4 * need <= lim) {
+    if (j.m <= jacobi_small_max_m() && j.p <= jacobi_small_max_m() && need <= lim) {
       small.push_back(j);
       per = std::max(per, need);
       flops_s += f;
