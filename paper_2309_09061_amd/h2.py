@@ -256,21 +256,33 @@ class Product:
             pass
 
 
-def h2_mul_intermediate(ctx: Context, X: Matrix, Y: Matrix, eps: float, precision: str = "fp64") -> Product:
-    h = _c_p()
-    xs = (_c_p * 1)(X.h)
-    ys = (_c_p * 1)(Y.h)
-    gs = (_c_p * 1)()
-    _check(ctx.lib, ctx.lib.h2_mul_intermediate(ctx.h, 1, ctypes.cast(xs, _c_p), ctypes.cast(ys, _c_p), eps,
+def h2_mul_intermediate(ctx: Context, X, Y, eps: float, precision: str = "fp64"):
+    """Phase 1 for one product (X, Y matrices) or for independent products in
+    one call (X, Y equal-length lists); returns a Product or a list of them."""
+    single = not isinstance(X, (list, tuple))
+    xs_l, ys_l = ([X], [Y]) if single else (list(X), list(Y))
+    if len(xs_l) != len(ys_l) or not xs_l:
+        raise ValueError("X and Y must have the same, non-zero length")
+    n = len(xs_l)
+    xs = (_c_p * n)(*[x.h for x in xs_l])
+    ys = (_c_p * n)(*[y.h for y in ys_l])
+    gs = (_c_p * n)()
+    _check(ctx.lib, ctx.lib.h2_mul_intermediate(ctx.h, n, ctypes.cast(xs, _c_p), ctypes.cast(ys, _c_p), eps,
                                                 PRECISIONS[precision], ctypes.cast(gs, _c_p)))
-    h = _c_p(gs[0])
-    return Product(ctx, X.tree, h)
+    out = [Product(ctx, x.tree, _c_p(gs[i])) for i, x in enumerate(xs_l)]
+    return out[0] if single else out
 
 
-def h2_recompress(ctx: Context, G: Product, Z: Matrix, eps: float, precision: str = "fp64") -> Matrix:
-    gs = (_c_p * 1)(G.h)
-    zs = (_c_p * 1)(Z.h)
-    _check(ctx.lib, ctx.lib.h2_recompress(ctx.h, 1, ctypes.cast(gs, _c_p), ctypes.cast(zs, _c_p), eps,
+def h2_recompress(ctx: Context, G, Z, eps: float, precision: str = "fp64"):
+    """Phase 2 for one product or for lists of products and zero targets."""
+    single = not isinstance(G, (list, tuple))
+    g_l, z_l = ([G], [Z]) if single else (list(G), list(Z))
+    if len(g_l) != len(z_l) or not g_l:
+        raise ValueError("G and Z must have the same, non-zero length")
+    n = len(g_l)
+    gs = (_c_p * n)(*[g.h for g in g_l])
+    zs = (_c_p * n)(*[z.h for z in z_l])
+    _check(ctx.lib, ctx.lib.h2_recompress(ctx.h, n, ctypes.cast(gs, _c_p), ctypes.cast(zs, _c_p), eps,
                                           PRECISIONS[precision]))
     return Z
 

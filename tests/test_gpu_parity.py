@@ -254,3 +254,47 @@ def test_mixed_rejects_small_eps():
     X = h2.Matrix.kernel(c, T, "log", 4)
     with pytest.raises(h2.H2Error):
         h2.h2_mul_intermediate(c, X, X, 1e-8, "fp32")
+
+
+def test_batched_products():
+    """Several independent products of different sizes and orders in one
+    call of each phase (the batched workload's interface), each against its
+    own oracle result."""
+    h2 = _h2()
+    c = ctx()
+    specs = [(700, 3, 1), (1500, 4, 2), (300, 3, 3)]  # (n, order, seed), 2-D, log kernel, leaf 64
+    eps = 1e-6
+    Ts, Xs, refs = [], [], []
+    for n, order, seed in specs:
+        pts = W.make_points(4000 + seed, n, 2, "uniform")
+        T = h2.Tree(c, pts, 64, 1.0)
+        Ts.append(T)
+        Xs.append(h2.Matrix.kernel(c, T, "log", order))
+        _, bt, Xo, _ = O.build_problem(pts, 64, 1.0, order, "log", "log")
+        p1, p2 = O.multiply(Xo, Xo, bt, eps)
+        refs.append((p1, p2))
+    _say(f"[gpu] batched: {len(specs)} products")
+    Gs = h2.h2_mul_intermediate(c, Xs, Xs, eps)
+    Zs = h2.h2_recompress(c, Gs, [h2.Matrix.zero(c, T) for T in Ts], eps)
+    torch.cuda.synchronize()
+    for (n, _, _), G, Z, (p1, p2) in zip(specs, Gs, Zs, refs):
+        assert relF(dense_of(G, n), p1.G.dense()) < 1e-10
+        assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
+
+
+def test_single_leaf_tree():
+    """Degenerate tree: fewer points than the leaf size, one cluster, one
+    inadmissible block; the product is the dense product."""
+    h2 = _h2()
+    c = ctx()
+    n = 40
+    pts = W.make_points(9, n, 2, "uniform")
+    T = h2.Tree(c, pts, 64, 1.0)
+    X = h2.Matrix.kernel(c, T, "log", 3)
+    Y = h2.Matrix.kernel(c, T, "expneg", 3)
+    G = h2.h2_mul_intermediate(c, X, Y, 1e-6)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
+    torch.cuda.synchronize()
+    XY = dense_of(X, n) @ dense_of(Y, n)
+    assert relF(dense_of(G, n), XY) < 1e-13
+    assert relF(dense_of(Z, n), XY) < 1e-13
