@@ -174,27 +174,32 @@ h2_status h2_product_ranks(const h2_product* G, int which, int32_t* out);
  * bytes held by G. */
 h2_status h2_product_sizes(const h2_product* G, int64_t out[5]);
 
-/* Step times (milliseconds) since the last h2_mul_intermediate on this
- * context (which resets them; h2_recompress adds its steps); out[] receives
- * up to n entries: out[0..7] device time between stream events around each
- * step, out[8..15] host wall time spent issuing it, in the order
+/* Step times (milliseconds) summed over the calls on this context since the
+ * last read with reset != 0; out[] receives up to n entries: out[0..7]
+ * device time between stream events around each step, out[8..15] host wall
+ * time spent issuing it, in the order
  *   0 setup, 1 symbolic, 2 phase-1 row, 3 phase-1 col, 4 phase-1 mat (G),
  *   5 phase-2 row, 6 phase-2 col, 7 phase-2 mat (Z).
  * The column passes run on a second stream concurrently with the row passes,
- * so steps 2/3 and 5/6 overlap in time.  Returns the count. */
-int h2_step_times(const h2_ctx* ctx, double* out, int n);
+ * so steps 2/3 and 5/6 overlap in time.  The calls themselves do not wait for
+ * their events; this function does (it synchronises with the streams).
+ * Returns the count (0 on a NULL argument or a device error). */
+int h2_step_times(h2_ctx* ctx, double* out, int n, int reset);
 
-/* Launch timing for measurement.  h2_profile(ctx, 1) makes every kernel
- * launch of this context record a pair of HIP events on the context stream
- * (a few microseconds each); h2_kernel_stats() resolves them (synchronising
- * the stream) and returns, for kernel family `kind` (0 grouped GEMM, 1 TSQR,
- * 2 Jacobi SVD, 3 construction, 4 other), out[0] = total milliseconds,
- * out[1] = launches, out[2] = algorithmic flops (2mnk per product term;
- * Householder 2Nm^2 - 2m^3/3; for Jacobi, three dot products per pair and
- * sweep performed plus each rotation applied), out[3] = algorithmic bytes
+/* Launch timing for measurement.  h2_profile(ctx, families) makes every
+ * kernel launch of a family whose bit is set in `families` (bit k for family
+ * k: 0 grouped GEMM, 1 TSQR, 2 Jacobi SVD, 3 construction, 4 other;
+ * H2_PROFILE_ALL sets them all, 0 turns timing off) record a pair of HIP
+ * events on the context stream (a few microseconds of host time each);
+ * h2_kernel_stats() resolves them (synchronising the stream) and returns,
+ * for family `kind`, out[0] = total milliseconds, out[1] = launches,
+ * out[2] = algorithmic flops (2mnk per product term; Householder
+ * 2Nm^2 - 2m^3/3; for Jacobi, three dot products per pair and sweep
+ * performed plus each rotation applied), out[3] = algorithmic bytes
  * (operands read once, outputs written once).  reset != 0 clears the counters
- * after reading. */
-h2_status h2_profile(h2_ctx* ctx, int enable);
+ * after reading.  Families whose bit is clear report zeros. */
+#define H2_PROFILE_ALL 0x1F
+h2_status h2_profile(h2_ctx* ctx, int families);
 h2_status h2_kernel_stats(h2_ctx* ctx, int kind, double out[4], int reset);
 
 void h2_tree_destroy(h2_tree* tree);

@@ -36,13 +36,13 @@ static void need_device(const h2_ctx* ctx) {
 // the levels) stays within the 2 eps bar of the mixed form only above this
 static constexpr double kFp32BulkMinEps = 1e-6;
 
-static void begin_call(h2_ctx* ctx, bool reset_steps = false) {
+// The workspace of the previous call is reused at once: every later launch
+// is ordered after the earlier ones on the context stream, and the auxiliary
+// stream's work of a call is ordered after the context stream's work queued
+// before it.
+static void begin_call(h2_ctx* ctx) {
   ctx->ws.reset();
-  if (ctx->aux) ctx->aux->ws.reset();  // its earlier work is ordered before ours
-  if (reset_steps) {
-    for (double& v : ctx->step_ms) v = 0.0;
-    for (double& v : ctx->host_ms) v = 0.0;
-  }
+  if (ctx->aux) ctx->aux->ws.reset();
 }
 
 extern "C" {
@@ -64,6 +64,7 @@ h2_status h2_ctx_create(int device, void* hip_stream, h2_ctx** out) {
         dev_set_device(device);
         c->stage_cap = (size_t)16 << 20;
         c->stage = (char*)dev_malloc_host(c->stage_cap);
+        c->stage_dev = (char*)dev_host_view(c->stage);
       } catch (...) {
         delete c;
         throw;
@@ -167,7 +168,7 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
     H2_REQUIRE(prec != H2_FP32_BULK || eps >= kFp32BulkMinEps, H2_ERR_ARG,
                "FP32 bulk products need eps >= 1e-6 (FP32 rounding would exceed 2 eps)");
     need_device(ctx);
-    begin_call(ctx, true);
+    begin_call(ctx);
     for (int i = 0; i < count; ++i) {
       auto* G = new h2_product();
       try {
@@ -182,8 +183,6 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
       }
       G_out[i] = G;
     }
-    steps_collect(ctx);
-    aux_collect(ctx);
   });
 }
 
@@ -211,8 +210,6 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     need_device(ctx);
     begin_call(ctx);
     for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);
-    steps_collect(ctx);
-    aux_collect(ctx);
   });
 }
 
@@ -301,17 +298,30 @@ h2_status h2_product_sizes(const h2_product* G, int64_t out[5]) {
   });
 }
 
-int h2_step_times(const h2_ctx* ctx, double* out, int n) {
+int h2_step_times(h2_ctx* ctx, double* out, int n, int reset) {
   if (!ctx || !out) return 0;
+  if (!ctx->host_only) {
+    try {
+      dev_set_device(ctx->device);
+      steps_collect(ctx);
+      aux_collect(ctx);
+    } catch (...) {
+      return 0;
+    }
+  }
   int m = std::min(n, 16);
   for (int i = 0; i < m; ++i) out[i] = i < 8 ? ctx->step_ms[i] : ctx->host_ms[i - 8];
+  if (reset) {
+    for (double& v : ctx->step_ms) v = 0.0;
+    for (double& v : ctx->host_ms) v = 0.0;
+  }
   return m;
 }
 
-h2_status h2_profile(h2_ctx* ctx, int enable) {
+h2_status h2_profile(h2_ctx* ctx, int families) {
   return guard([&] {
     H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
-    ctx->profile = enable != 0;
+    ctx->profile = families & ((1 << h2::KK_COUNT) - 1);
   });
 }
 

@@ -29,9 +29,11 @@ void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// Pinned, mapped into the device address space and coherent: kernels read it
+// directly (dev_pull), seeing what the host wrote before the launch.
 void* dev_malloc_host(size_t bytes) {
   void* p = nullptr;
-  hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+  hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     fail(H2_ERR_ALLOC, "hipHostMalloc failed");
@@ -41,6 +43,33 @@ void* dev_malloc_host(size_t bytes) {
 
 void dev_free_host(void* p) {
   if (p) (void)hipHostFree(p);
+}
+
+void* dev_host_view(void* host) {
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, host, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return d;
+}
+
+// A plain copy kernel reading the device view of pinned host memory: the
+// upload is an ordinary launch on the stream, with no runtime copy path (which
+// may wait for the stream before returning).  Both ends are padded to 256
+// bytes, so whole 16-byte words are copied.
+__global__ void pull_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+void dev_pull(void* dst, const void* src_view, size_t bytes, void* stream) {
+  const size_t n = (bytes + 15) / 16;
+  if (n == 0) return;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(pull_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (uint4*)dst,
+                     (const uint4*)src_view, n);
+  HIP_OK(hipGetLastError());
 }
 
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream) {

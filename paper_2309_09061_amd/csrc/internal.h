@@ -42,8 +42,12 @@ struct Error : std::runtime_error {
 void dev_set_device(int device);
 void* dev_malloc(size_t bytes);
 void dev_free(void* p);
-void* dev_malloc_host(size_t bytes);  // pinned
+void* dev_malloc_host(size_t bytes);  // pinned, mapped, coherent
 void dev_free_host(void* p);
+void* dev_host_view(void* host);      // device address of pinned host memory, or nullptr
+// copy from pinned host memory (its device view) with a kernel on `stream`;
+// both buffers hold bytes rounded up to 256
+void dev_pull(void* dst, const void* src_view, size_t bytes, void* stream);
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
@@ -338,6 +342,7 @@ struct h2_ctx {
   h2::Arena ws;                        // per-call workspace
   std::vector<std::pair<char*, size_t>> cache;  // free device chunks
   char* stage = nullptr;               // pinned staging for descriptor uploads
+  char* stage_dev = nullptr;           // its device view (nullptr: runtime copies)
   size_t stage_cap = 0, stage_used = 0;
   std::vector<void*> events;
   std::vector<int> ev_step;            // step id of each recorded event interval
@@ -345,7 +350,7 @@ struct h2_ctx {
   double host_ms[8] = {0};             // host wall time between step_begin and step_end
   std::chrono::steady_clock::time_point host_t0[8];
   int prec = 0;                        // bulk precision of the running call
-  bool profile = false;                // time every launch with stream events
+  int profile = 0;                     // bit k: time the launches of kernel family k
   std::vector<void*> ev_pool;          // reusable events for launch timing
   std::vector<std::pair<double*, size_t>> prof_host;  // pinned chunks for per-problem work counts
   size_t prof_chunk = 0, prof_used = 0;
@@ -395,7 +400,7 @@ T* upload(h2_ctx* ctx, const std::vector<T>& v) {
 }
 void ctx_sync(h2_ctx* ctx);
 
-// launch timing (when ctx->profile): events around one launch
+// launch timing (when bit `kind` of ctx->profile is set): events around one launch
 struct LaunchTimer {
   h2_ctx* ctx;
   void* a = nullptr;
@@ -413,7 +418,7 @@ struct WorkCounts {
   double* host = nullptr;
   int n = 0;
 };
-WorkCounts work_counts(h2_ctx* ctx, int n);
+WorkCounts work_counts(h2_ctx* ctx, int n, int kind);
 void kernel_stats_collect(h2_ctx* ctx);
 
 // step timing with stream events

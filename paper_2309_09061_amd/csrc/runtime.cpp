@@ -76,8 +76,10 @@ char* stage_alloc(h2_ctx* ctx, size_t bytes) {
     ctx->stage_used = 0;
     if (need > ctx->stage_cap) {
       dev_free_host(ctx->stage);
+      ctx->stage = ctx->stage_dev = nullptr;
       ctx->stage_cap = std::max(need, ctx->stage_cap * 2);
       ctx->stage = (char*)dev_malloc_host(ctx->stage_cap);
+      ctx->stage_dev = (char*)dev_host_view(ctx->stage);
     }
   }
   char* h = ctx->stage + ctx->stage_used;
@@ -87,7 +89,10 @@ char* stage_alloc(h2_ctx* ctx, size_t bytes) {
 
 void* stage_upload(h2_ctx* ctx, const char* h, size_t bytes) {
   void* d = ctx->ws.alloc(bytes);
-  dev_h2d(d, h, bytes, ctx->stream);
+  if (ctx->stage_dev)
+    dev_pull(d, ctx->stage_dev + (h - ctx->stage), bytes, ctx->stream);
+  else
+    dev_h2d(d, h, bytes, ctx->stream);
   return d;
 }
 
@@ -106,8 +111,11 @@ void ctx_sync(h2_ctx* ctx) {
 // step timers
 // ---------------------------------------------------------------------------
 void step_begin(h2_ctx* ctx, int step) {
+  // the intervals are resolved when they are read; a long run of calls
+  // without a read resolves them here (this waits for the stream)
+  if (ctx->events.size() > 4096) steps_collect(ctx);
   ctx->host_t0[step] = std::chrono::steady_clock::now();
-  void* e = dev_event_create();
+  void* e = pool_event(ctx);
   dev_event_record(e, ctx->stream);
   ctx->events.push_back(e);
   ctx->ev_step.push_back(-1 - step);
@@ -115,7 +123,7 @@ void step_begin(h2_ctx* ctx, int step) {
 void step_end(h2_ctx* ctx, int step) {
   ctx->host_ms[step] +=
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ctx->host_t0[step]).count();
-  void* e = dev_event_create();
+  void* e = pool_event(ctx);
   dev_event_record(e, ctx->stream);
   ctx->events.push_back(e);
   ctx->ev_step.push_back(step);
@@ -126,7 +134,7 @@ void steps_collect(h2_ctx* ctx) {
     if (s < 0 && ctx->ev_step[i + 1] == -1 - s)
       ctx->step_ms[-1 - s] += dev_event_ms(ctx->events[i], ctx->events[i + 1]);
   }
-  for (void* e : ctx->events) dev_event_destroy(e);
+  for (void* e : ctx->events) ctx->ev_pool.push_back(e);
   ctx->events.clear();
   ctx->ev_step.clear();
 }
@@ -142,7 +150,7 @@ void* pool_event(h2_ctx* ctx) {
 }
 
 LaunchTimer::LaunchTimer(h2_ctx* c, int k, double f, double b) : ctx(c), kind(k), flops(f), bytes(b) {
-  if (!ctx->profile) return;
+  if (!((ctx->profile >> kind) & 1)) return;
   a = pool_event(ctx);
   dev_event_record(a, ctx->stream);
 }
@@ -157,9 +165,9 @@ LaunchTimer::~LaunchTimer() {
   ctx->pending.push_back(p);
 }
 
-WorkCounts work_counts(h2_ctx* ctx, int n) {
+WorkCounts work_counts(h2_ctx* ctx, int n, int kind) {
   WorkCounts w;
-  if (!ctx->profile || n <= 0) return w;
+  if (!((ctx->profile >> kind) & 1) || n <= 0) return w;
   w.n = n;
   w.dev = ctx->ws.get<double>(n);
   if (ctx->prof_host.empty() || ctx->prof_used + n > ctx->prof_chunk) {
@@ -188,6 +196,7 @@ h2_ctx* aux_ctx(h2_ctx* ctx) {
       a->own_stream = true;
       a->stage_cap = (size_t)16 << 20;
       a->stage = (char*)dev_malloc_host(a->stage_cap);
+      a->stage_dev = (char*)dev_host_view(a->stage);
     } catch (...) {
       delete a;
       throw;
@@ -520,7 +529,7 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
 
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  WorkCounts wc = work_counts(ctx, (int)p.size());
+  WorkCounts wc = work_counts(ctx, (int)p.size(), KK_TSQR);
   if (wc.dev)
     for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
   // per problem: a register-blocked variant sized by m (the widest factored
@@ -593,7 +602,7 @@ void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, in
 
 void JacobiBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  WorkCounts wc = work_counts(ctx, (int)p.size());
+  WorkCounts wc = work_counts(ctx, (int)p.size(), KK_JACOBI);
   if (wc.dev)
     for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
   // small problems: one wavefront each; the rest: one workgroup each

@@ -57,7 +57,7 @@ def _declare(lib):
         "h2_matrix_ranks": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p]),
         "h2_product_ranks": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p]),
         "h2_product_sizes": (ctypes.c_int, [_c_p, _c_p]),
-        "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int]),
+        "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int]),
         "h2_profile": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_kernel_stats": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int]),
         "h2_tree_destroy": (None, [_c_p]),
@@ -122,8 +122,15 @@ class Context:
             _check(self.lib, self.lib.h2_ctx_destroy(self.h))
             self.h = _c_p()
 
-    def profile(self, enable: bool = True):
-        _check(self.lib, self.lib.h2_profile(self.h, 1 if enable else 0))
+    def profile(self, enable: bool = True, families=None):
+        """Time kernel launches with HIP events: every family when `families`
+        is None, else only the named ones (names of KERNEL_FAMILIES)."""
+        mask = 0
+        if enable:
+            fams = KERNEL_FAMILIES if families is None else families
+            for f in fams:
+                mask |= 1 << KERNEL_FAMILIES.index(f)
+        _check(self.lib, self.lib.h2_profile(self.h, mask))
 
     def kernel_stats(self, reset: bool = False) -> dict:
         out = {}
@@ -136,10 +143,11 @@ class Context:
             _check(self.lib, self.lib.h2_kernel_stats(self.h, 0, v.ctypes.data, 1))
         return out
 
-    def step_times(self, host: bool = False) -> dict:
-        """Device time per step (ms); host=True: host issue time per step."""
+    def step_times(self, host: bool = False, reset: bool = False) -> dict:
+        """Device time per step (ms) summed since the last reset; host=True:
+        host issue time per step.  Waits for the context's streams."""
         out = np.zeros(16)
-        n = self.lib.h2_step_times(self.h, out.ctypes.data, 16)
+        n = self.lib.h2_step_times(self.h, out.ctypes.data, 16, 1 if reset else 0)
         off = 8 if host else 0
         return {STEPS[i]: float(out[off + i]) for i in range(min(8, n - off))}
 
