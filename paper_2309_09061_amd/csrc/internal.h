@@ -398,6 +398,15 @@ T* upload(h2_ctx* ctx, const std::vector<T>& v) {
   if (v.empty()) return nullptr;
   return (T*)upload_bytes(ctx, v.data(), v.size() * sizeof(T));
 }
+// the same for a table read only by the launch issued next (small tables are
+// read from the staging itself; see stage_launch)
+void* stage_launch(h2_ctx* ctx, const char* h, size_t bytes);
+void* upload_launch_bytes(h2_ctx* ctx, const void* src, size_t bytes);
+template <class T>
+T* upload_launch(h2_ctx* ctx, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  return (T*)upload_launch_bytes(ctx, v.data(), v.size() * sizeof(T));
+}
 void ctx_sync(h2_ctx* ctx);
 
 // launch timing (when bit `kind` of ctx->profile is set): events around one launch

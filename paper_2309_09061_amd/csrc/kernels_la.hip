@@ -879,9 +879,10 @@ static __host__ __device__ inline size_t jacobi_ld_max(int len) {
   return (size_t)max(64, pow2ceil(len)) + 16;
 }
 static __host__ __device__ inline size_t jacobi_need(int p, int m, int mode) {
-  // mode 1: ncol <= p columns of length <= m; mode 0: m columns of length p
-  // and the m x m rotations; column norms
-  return mode ? jacobi_ld_max(m) * (size_t)p + 2 * (size_t)m
+  // mode 1: ncol <= p columns of length <= m, column norms, and the pivoted
+  // QR's permutation, remaining norms and reflector; mode 0: m columns of
+  // length p and the m x m rotations; column norms
+  return mode ? jacobi_ld_max(m) * (size_t)p + 5 * (size_t)m
               : jacobi_ld_max(p) * (size_t)m + jacobi_ld_max(m) * (size_t)m + 2 * (size_t)m;
 }
 size_t jacobi_need_doubles(int p, int m, int mode) { return jacobi_need(p, m, mode); }
@@ -891,6 +892,8 @@ int jacobi_max_len() { return 512; }
 struct JacobiShared {
   int rotated;
   unsigned int nrot;
+  int piv;
+  double tau, beta;
 };
 
 // synchronisation of the NT threads working on one problem: the workgroup
@@ -1012,6 +1015,128 @@ __device__ __forceinline__ int jacobi_sweeps(double* G, int ld, double* U, int l
   return sweeps;
 }
 
+// Preconditioner of the row-rotating mode (one-sided Jacobi after a QR with
+// column pivoting, as proposed by Drmac and Veselic): Householder QR of
+// B = G^T (ncol x len, B(j, c) = G[c + j ld]) with the pivot of step s taken
+// over the coordinates c >= s by largest remaining norm (first index on ties;
+// the norms are downdated, which only steers the choice).  Afterwards player j
+// (column j of G) is row j of the trapezoidal factor, zero in the coordinates
+// before j, and perm[c] is the original coordinate now stored at c.  The
+// players change by an orthogonal map, which the row-rotating mode never
+// needs; the permutation is undone when the vectors are written.  On the
+// graded factor the sweeps roughly halve.
+constexpr int kJacobiQrcpMinCols = 16;
+
+template <int NT>
+__device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol, int32_t* perm, double* cn,
+                                            double* v, JacobiShared& sh) {
+  static_assert(NT >= 256, "the pivoted QR takes a whole workgroup");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int c = tid; c < len; c += NT) {
+    perm[c] = c;
+    double q = 0.0;
+    for (int j = 0; j < ncol; ++j) {
+      const double x = G[c + (size_t)j * ld];
+      q += x * x;
+    }
+    cn[c] = q;
+  }
+  __syncthreads();
+  // GS lanes per coordinate in the reflector application (aligned groups)
+  constexpr int GS = NT >= 1024 ? 8 : 2;
+  const int grp = tid / GS, gl = tid % GS, ngrp = NT / GS;
+  for (int s = 0; s < ncol; ++s) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = len;
+      for (int c = s + lane; c < len; c += 64) {
+        const double x = cn[c];
+        if (x > best) {
+          best = x;
+          bi = c;
+        }
+      }
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) sh.piv = bi;
+    }
+    __syncthreads();
+    const int pv = sh.piv;
+    if (pv != s && pv < len) {  // swap coordinates s and pv of every player
+      for (int j = tid; j < ncol; j += NT) {
+        const double a = G[s + (size_t)j * ld];
+        G[s + (size_t)j * ld] = G[pv + (size_t)j * ld];
+        G[pv + (size_t)j * ld] = a;
+      }
+      if (tid == 0) {
+        const int32_t t = perm[s];
+        perm[s] = perm[pv];
+        perm[pv] = t;
+        const double q = cn[s];
+        cn[s] = cn[pv];
+        cn[pv] = q;
+      }
+    }
+    __syncthreads();
+    if (s == ncol - 1) break;  // the last player has nothing below it
+    if (wave == 0) {  // reflector of (B(s, s), ..., B(ncol - 1, s))
+      double q = 0.0;
+      for (int j = s + 1 + lane; j < ncol; j += 64) {
+        const double x = G[s + (size_t)j * ld];
+        q += x * x;
+      }
+      q = group_sum(q, 64);
+      const double al = G[s + (size_t)s * ld];
+      double tau = 0.0, beta = al, sc = 0.0;
+      if (q > 0.0) {
+        const double nr = sqrt(al * al + q);
+        beta = al >= 0.0 ? -nr : nr;
+        tau = (beta - al) / beta;
+        sc = 1.0 / (al - beta);
+      }
+      for (int j = s + 1 + lane; j < ncol; j += 64) v[j] = G[s + (size_t)j * ld] * sc;
+      if (lane == 0) {
+        v[s] = 1.0;
+        sh.tau = tau;
+        sh.beta = beta;
+      }
+    }
+    __syncthreads();
+    const double tau = sh.tau;
+    // coordinate s becomes (beta, 0, ..., 0) over the players s..ncol-1
+    for (int j = s + tid; j < ncol; j += NT) G[s + (size_t)j * ld] = j == s ? sh.beta : 0.0;
+    // the other coordinates c > s: B(:, c) -= tau v (v^T B(:, c)); then the
+    // remaining norm loses the new B(s, c)^2
+    for (int c0 = s + 1; c0 < len; c0 += ngrp) {
+      const int c = c0 + grp;
+      const bool act = c < len;  // uniform per group
+      double w = 0.0, gcs = 0.0;
+      if (act) {
+        gcs = G[c + (size_t)s * ld];
+        if (tau != 0.0)
+          for (int j = s + gl; j < ncol; j += GS) w += v[j] * G[c + (size_t)j * ld];
+      }
+      w = group_sum(w, GS);
+      if (act) {
+        const double tw = tau * w;
+        if (tau != 0.0)
+          for (int j = s + gl; j < ncol; j += GS) G[c + (size_t)j * ld] -= tw * v[j];
+        if (gl == 0) {
+          const double ncs = gcs - tw;
+          cn[c] = fmax(cn[c] - ncs * ncs, 0.0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // one problem on the buffer G (jacobi_need doubles) by NT threads
 template <int NT>
 __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int s0, JacobiShared& sh) {
@@ -1043,6 +1168,9 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   const int gcols = mode ? ncol : m;
   double* U = mode ? nullptr : G + (size_t)ld * gcols;
   double* nrm = mode ? G + (size_t)ld * gcols : U + (size_t)ldu * m;
+  // mode 1 with the pivoted QR first (whole workgroups, enough players)
+  const bool qrcp = NT > 64 && mode && ncol >= kJacobiQrcpMinCols;
+  int32_t* perm = (int32_t*)(nrm + m);
   if (mode) {
     for (int e = tid; e < ld * ncol; e += NT) {  // G(i, j) = R'(j, i), rows >= len zero
       const int i = e % ld, j = e / ld;
@@ -1056,6 +1184,8 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
     for (int e = tid; e < ldu * m; e += NT) U[e] = (e % ldu) == (e / ldu) ? 1.0 : 0.0;
   }
   team_sync<NT>();
+  if constexpr (NT > 64)
+    if (qrcp) jacobi_qrcp<NT>(G, ld, len, ncol, perm, nrm + 2 * m, nrm + 3 * m, sh);
   // rotate while |a.b| exceeds the rounding level of a dot product of length len
   const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
   unsigned int my_rot = 0;
@@ -1087,7 +1217,10 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
     }
     if (tid == 0) {  // 3 dot products per pair and sweep, a rotation when applied
       const double pairs = 0.5 * ncol * (ncol - 1.0);
-      *P.work = sweeps * pairs * 6.0 * len + nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
+      double f = sweeps * pairs * 6.0 * len + nrot * (6.0 * len + (mode ? 0.0 : 6.0 * m));
+      if (qrcp)  // reflector applications: 4 (ncol - s) (len - s - 1) per step
+        for (int q = 0; q + 1 < ncol; ++q) f += 4.0 * (ncol - q) * (len - q - 1.0);
+      *P.work = f;
     }
   }
   // nc columns carry singular values: mode 0 all m (the s0 zero ones too)
@@ -1110,7 +1243,10 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
         const double inv = v > 0.0 ? 1.0 / v : 0.0;
         const double* gc = G + (size_t)c * ld;
         for (int i = 0; i < s0; ++i) uo[i] = 0.0;
-        for (int i = 0; i < len; ++i) uo[s0 + i] = gc[i] * inv;
+        if (qrcp)
+          for (int i = 0; i < len; ++i) uo[s0 + perm[i]] = gc[i] * inv;
+        else
+          for (int i = 0; i < len; ++i) uo[s0 + i] = gc[i] * inv;
       } else {
         for (int i = 0; i < m; ++i) uo[i] = U[i + (size_t)c * ldu];
       }

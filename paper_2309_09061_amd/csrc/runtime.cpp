@@ -96,6 +96,22 @@ void* stage_upload(h2_ctx* ctx, const char* h, size_t bytes) {
   return d;
 }
 
+// Descriptor tables read only by the launch that follows: a small table is
+// read by the kernel straight from the mapped staging (no copy launch); the
+// staging is reused only after the stream has been synchronised, which the
+// launch precedes.  Larger tables are copied into the workspace.
+static constexpr size_t kStageViewMax = (size_t)32 << 10;
+void* stage_launch(h2_ctx* ctx, const char* h, size_t bytes) {
+  if (ctx->stage_dev && bytes <= kStageViewMax) return ctx->stage_dev + (h - ctx->stage);
+  return stage_upload(ctx, h, bytes);
+}
+
+void* upload_launch_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
+  char* h = stage_alloc(ctx, bytes);
+  std::memcpy(h, src, bytes);
+  return stage_launch(ctx, h, bytes);
+}
+
 void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
   char* h = stage_alloc(ctx, bytes);
   std::memcpy(h, src, bytes);
@@ -358,7 +374,7 @@ void GemmBatch::run(h2_ctx* ctx) {
         *tl++ = j0;
       }
   }
-  char* dev = (char*)stage_upload(ctx, h, o_ti + sti);
+  char* dev = (char*)stage_launch(ctx, h, o_ti + sti);
   GemmOut* d_o = (GemmOut*)dev;
   GemmTerm* d_t = (GemmTerm*)(dev + o_t);
   int32_t* d_tiles = (int32_t*)(dev + o_ti);
@@ -399,7 +415,7 @@ void TriBatch::run(h2_ctx* ctx, double flops) {
     for (const TriOut& o : outs) H2_REQUIRE(o.m <= 64 && o.n <= 64, H2_ERR_ARG, "triple block product: output over 64 x 64");
     double bytes = 0;
     for (const TriOut& o : outs) bytes += 8.0 * o.m * o.n * (o.beta ? 2 : 1);
-    TriOut* d = upload(ctx, outs);
+    TriOut* d = upload_launch(ctx, outs);
     LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
     k_gemm_tri_block(d, (int)outs.size(), fam, prec, ctx->stream);
     outs.clear();
@@ -418,7 +434,7 @@ void TriBatch::run(h2_ctx* ctx, double flops) {
         *tl++ = i0;
         *tl++ = j0;
       }
-  char* dev = (char*)stage_upload(ctx, h, o_t + ntiles * 3 * sizeof(int32_t));
+  char* dev = (char*)stage_launch(ctx, h, o_t + ntiles * 3 * sizeof(int32_t));
   double bytes = 0;
   for (const TriOut& o : outs) bytes += 8.0 * o.m * o.n * (o.beta ? 2 : 1);
   LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
@@ -455,7 +471,7 @@ void QrBatch::run(h2_ctx* ctx) {
     flops += 2.0 * m * n * r - (m + n) * r * r + 2.0 * r * r * r / 3.0;
     bytes += 16.0 * m * n;
   }
-  QrProb* d = upload(ctx, p);
+  QrProb* d = upload_launch(ctx, p);
   LaunchTimer lt(ctx, KK_TSQR, flops, bytes);
   k_qr(d, (int)p.size(), lds_for(lds), ctx->stream);
   p.clear();
@@ -493,8 +509,15 @@ void ApplyBatch::run(h2_ctx* ctx) {
     flops += 4.0 * p[i].m * p[i].nrefl * p[i].ncols;
     bytes += 16.0 * p[i].m * p[i].ncols;
   }
-  ApplyProb* d = upload(ctx, p);
-  int32_t* w = upload(ctx, work);
+  // one staging region for both tables (the launch reads them together)
+  const size_t sp = p.size() * sizeof(ApplyProb), o_w = (sp + 255) & ~(size_t)255;
+  const size_t sw = work.size() * sizeof(int32_t);
+  char* h = stage_alloc(ctx, o_w + sw);
+  std::memcpy(h, p.data(), sp);
+  std::memcpy(h + o_w, work.data(), sw);
+  char* dev = (char*)stage_launch(ctx, h, o_w + sw);
+  ApplyProb* d = (ApplyProb*)dev;
+  int32_t* w = (int32_t*)(dev + o_w);
   LaunchTimer lt(ctx, KK_OTHER, flops, bytes);
   k_apply(d, w, (int)(work.size() / 2), lds_for(lds), ctx->stream);
   p.clear();
@@ -504,7 +527,7 @@ void FillBatch::run(h2_ctx* ctx) {
   if (items.empty()) return;
   double bytes = 0;
   for (const FillItem& f : items) bytes += 8.0 * f.rows * f.cols;
-  FillItem* d = upload(ctx, items);
+  FillItem* d = upload_launch(ctx, items);
   LaunchTimer lt(ctx, KK_OTHER, 0.0, bytes);
   k_fill(d, (int)items.size(), ctx->stream);
   items.clear();
@@ -558,13 +581,13 @@ void TsqrBatch::run(h2_ctx* ctx) {
   }
   for (int v = 1; v <= 3; ++v) {
     if (rb[v].empty()) continue;
-    TsqrProb* d = upload(ctx, rb[v]);
+    TsqrProb* d = upload_launch(ctx, rb[v]);
     LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[v], rb_bytes[v]);
     k_tsqr_rb(v, d, (int)rb[v].size(), rb_need[v], ctx->stream);
   }
   if (!rb[0].empty()) {
     double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(rb[0].size(), 1024)) : nullptr;
-    TsqrProb* d = upload(ctx, rb[0]);
+    TsqrProb* d = upload_launch(ctx, rb[0]);
     LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[0], rb_bytes[0]);
     k_tsqr(d, (int)rb[0].size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
   }
@@ -632,7 +655,7 @@ void JacobiBatch::run(h2_ctx* ctx) {
     }
   }
   if (!small.empty()) {
-    JacobiProb* d = upload(ctx, small);
+    JacobiProb* d = upload_launch(ctx, small);
     LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_s, bytes_s);
     k_jacobi_small(d, (int)small.size(), (int)per, ctx->stream);
   }
@@ -653,7 +676,7 @@ void JacobiBatch::run(h2_ctx* ctx) {
   for (int w = 0; w < 2; ++w) {
     if (grp[w].empty()) continue;
     double* scratch = gslot[w] ? ctx->ws.get<double>(gslot[w] * std::min<size_t>(grp[w].size(), 1024)) : nullptr;
-    JacobiProb* d = upload(ctx, grp[w]);
+    JacobiProb* d = upload_launch(ctx, grp[w]);
     LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_l * grp[w].size() / large.size(), bytes_l * grp[w].size() / large.size());
     k_jacobi(d, (int)grp[w].size(), lds_for(glds[w]), gslot[w], scratch, w == 1, ctx->stream);
   }
