@@ -1030,8 +1030,9 @@ constexpr int kJacobiQrcpMinCols = 16;
 template <int NT>
 __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol, int32_t* perm, double* cn,
                                             double* v, JacobiShared& sh) {
-  static_assert(NT >= 256, "the pivoted QR takes a whole workgroup");
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // NT = 64: one wavefront computes every uniform value itself; larger teams
+  // let wavefront 0 compute them and publish them through `sh`
+  const int tid = NT > 64 ? (int)threadIdx.x : (int)(threadIdx.x & 63), lane = tid & 63, wave = tid >> 6;
   for (int c = tid; c < len; c += NT) {
     perm[c] = c;
     double q = 0.0;
@@ -1041,12 +1042,13 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
     }
     cn[c] = q;
   }
-  __syncthreads();
+  team_sync<NT>();
   // GS lanes per coordinate in the reflector application (aligned groups)
   constexpr int GS = NT >= 1024 ? 8 : 2;
   const int grp = tid / GS, gl = tid % GS, ngrp = NT / GS;
   for (int s = 0; s < ncol; ++s) {
-    if (wave == 0) {
+    int pv = len;
+    if (NT == 64 || wave == 0) {
       double best = -1.0;
       int bi = len;
       for (int c = s + lane; c < len; c += 64) {
@@ -1056,7 +1058,7 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
           bi = c;
         }
       }
-      for (int o = 32; o >= 1; o >>= 1) {
+      for (int o = 32; o >= 1; o >>= 1) {  // the same winner on every lane
         const double ob = __shfl_xor(best, o, 64);
         const int oi = __shfl_xor(bi, o, 64);
         if (ob > best || (ob == best && oi < bi)) {
@@ -1064,10 +1066,13 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
           bi = oi;
         }
       }
-      if (lane == 0) sh.piv = bi;
+      pv = bi;
+      if (NT > 64 && lane == 0) sh.piv = bi;
     }
-    __syncthreads();
-    const int pv = sh.piv;
+    if (NT > 64) {
+      __syncthreads();
+      pv = sh.piv;
+    }
     if (pv != s && pv < len) {  // swap coordinates s and pv of every player
       for (int j = tid; j < ncol; j += NT) {
         const double a = G[s + (size_t)j * ld];
@@ -1083,9 +1088,10 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
         cn[pv] = q;
       }
     }
-    __syncthreads();
+    team_sync<NT>();
     if (s == ncol - 1) break;  // the last player has nothing below it
-    if (wave == 0) {  // reflector of (B(s, s), ..., B(ncol - 1, s))
+    double tau = 0.0, beta = 0.0;
+    if (NT == 64 || wave == 0) {  // reflector of (B(s, s), ..., B(ncol - 1, s))
       double q = 0.0;
       for (int j = s + 1 + lane; j < ncol; j += 64) {
         const double x = G[s + (size_t)j * ld];
@@ -1093,7 +1099,8 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
       }
       q = group_sum(q, 64);
       const double al = G[s + (size_t)s * ld];
-      double tau = 0.0, beta = al, sc = 0.0;
+      double sc = 0.0;
+      beta = al;
       if (q > 0.0) {
         const double nr = sqrt(al * al + q);
         beta = al >= 0.0 ? -nr : nr;
@@ -1103,14 +1110,19 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
       for (int j = s + 1 + lane; j < ncol; j += 64) v[j] = G[s + (size_t)j * ld] * sc;
       if (lane == 0) {
         v[s] = 1.0;
-        sh.tau = tau;
-        sh.beta = beta;
+        if (NT > 64) {
+          sh.tau = tau;
+          sh.beta = beta;
+        }
       }
     }
-    __syncthreads();
-    const double tau = sh.tau;
+    team_sync<NT>();
+    if (NT > 64) {
+      tau = sh.tau;
+      beta = sh.beta;
+    }
     // coordinate s becomes (beta, 0, ..., 0) over the players s..ncol-1
-    for (int j = s + tid; j < ncol; j += NT) G[s + (size_t)j * ld] = j == s ? sh.beta : 0.0;
+    for (int j = s + tid; j < ncol; j += NT) G[s + (size_t)j * ld] = j == s ? beta : 0.0;
     // the other coordinates c > s: B(:, c) -= tau v (v^T B(:, c)); then the
     // remaining norm loses the new B(s, c)^2
     for (int c0 = s + 1; c0 < len; c0 += ngrp) {
@@ -1133,7 +1145,7 @@ __device__ __forceinline__ void jacobi_qrcp(double* G, int ld, int len, int ncol
         }
       }
     }
-    __syncthreads();
+    team_sync<NT>();
   }
 }
 
@@ -1168,8 +1180,8 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
   const int gcols = mode ? ncol : m;
   double* U = mode ? nullptr : G + (size_t)ld * gcols;
   double* nrm = mode ? G + (size_t)ld * gcols : U + (size_t)ldu * m;
-  // mode 1 with the pivoted QR first (whole workgroups, enough players)
-  const bool qrcp = NT > 64 && mode && ncol >= kJacobiQrcpMinCols;
+  // mode 1 with the pivoted QR first (enough players)
+  const bool qrcp = mode && ncol >= kJacobiQrcpMinCols;
   int32_t* perm = (int32_t*)(nrm + m);
   if (mode) {
     for (int e = tid; e < ld * ncol; e += NT) {  // G(i, j) = R'(j, i), rows >= len zero
@@ -1184,8 +1196,7 @@ __device__ __forceinline__ void jacobi_solve(const JacobiProb& P, double* G, int
     for (int e = tid; e < ldu * m; e += NT) U[e] = (e % ldu) == (e / ldu) ? 1.0 : 0.0;
   }
   team_sync<NT>();
-  if constexpr (NT > 64)
-    if (qrcp) jacobi_qrcp<NT>(G, ld, len, ncol, perm, nrm + 2 * m, nrm + 3 * m, sh);
+  if (qrcp) jacobi_qrcp<NT>(G, ld, len, ncol, perm, nrm + 2 * m, nrm + 3 * m, sh);
   // rotate while |a.b| exceeds the rounding level of a dot product of length len
   const double tol = fmax(1e-15, 2.2e-16 * len), tol2 = tol * tol;
   unsigned int my_rot = 0;

@@ -673,6 +673,15 @@ void JacobiBatch::run(h2_ctx* ctx) {
   }
   (void)slot;
   (void)lds;
+  // a few medium problems beside wide ones join the wide launch: two launches
+  // on the stream would run one after the other, each leaving most of the
+  // device idle
+  if (!grp[0].empty() && !grp[1].empty() && grp[0].size() < 128) {
+    grp[1].insert(grp[1].end(), grp[0].begin(), grp[0].end());
+    grp[0].clear();
+    gslot[1] = std::max(gslot[1], gslot[0]);
+    glds[1] = std::max(glds[1], glds[0]);
+  }
   for (int w = 0; w < 2; ++w) {
     if (grp[w].empty()) continue;
     double* scratch = gslot[w] ? ctx->ws.get<double>(gslot[w] * std::min<size_t>(grp[w].size(), 1024)) : nullptr;
