@@ -182,6 +182,7 @@ size_t tsqr_scratch_need(int m);
 // factored width is at most m, and their LDS need in doubles
 int tsqr_rb_variant(int m, int cap);
 size_t tsqr_rb_need(int variant, int m);
+int tsqr_rb_chunk(int variant);  // rows factored per step sequence
 void k_tsqr_rb(int variant, const TsqrProb* probs, int n, size_t lds_doubles, void* stream);
 size_t jacobi_need_doubles(int p, int m, int mode);
 void k_qr(const QrProb* probs, int n, int lds_doubles, void* stream);

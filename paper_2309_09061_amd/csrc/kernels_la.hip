@@ -652,17 +652,17 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __re
 // workgroup).  Each column of the chunk belongs to a slot of G adjacent lanes
 // that hold its rows in registers (RPT each); a slot holds CPT columns.  Per
 // column jj the owning slot forms the reflector, one barrier publishes it
-// (double-buffered), and every slot updates its own columns in registers: the
-// chunk is read from LDS once per chunk instead of twice per column step.
-// LDS: R (me x me), chunk staging (CH x me), two reflector buffers.
+// (double-buffered), and every slot updates its own columns in registers.
+// The chunk is loaded from global memory straight into the registers (the G
+// lanes of a slot read G consecutive rows of a column, or of a row for the
+// transposed input); LDS holds only R (me x me) and two reflector buffers,
+// so several workgroups share a compute unit.
 // ---------------------------------------------------------------------------
 template <int G, int CPT, int RPT>
 struct TsqrRB {
   static constexpr int kSlots = kTsqrThreads / G;
   static constexpr int kCH = G * RPT;
-  static __host__ __device__ size_t need(int me) {
-    return (size_t)(me + 1) * me + (size_t)kCH * me + 2 * kCH + 4;
-  }
+  static __host__ __device__ size_t need(int me) { return (size_t)(me + 1) * me + 2 * kCH + 4; }
 };
 using TsqrRB16 = TsqrRB<16, 1, 8>;  // me <= 32
 using TsqrRB64 = TsqrRB<8, 1, 16>;  // me <= 64
@@ -697,30 +697,25 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_rb_kernel(const TsqrProb* _
     }
     const int ldr = me + 1;
     double* R = lds_dyn;          // me x me, column-major, ld me + 1
-    double* S = R + ldr * me;     // CH x me staging, ld CH
-    double* vb = S + CH * me;     // 2 x CH reflector buffers (by chunk row)
+    double* vb = R + ldr * me;    // 2 x CH reflector buffers (by chunk row)
     double* sc = vb + 2 * CH;     // tau per buffer
     for (int e = tid; e < ldr * me; e += kTsqrThreads) R[e] = 0.0;
+    __syncthreads();
     for (int q0 = 0; q0 < N; q0 += CH) {
       const int cr = min(CH, N - q0);
-      if (P.transA) {  // T(i, j) = A[j + i lda]: consecutive threads along j
-        for (int e = tid; e < CH * me; e += kTsqrThreads) {
-          const int j = e % me, i = e / me;
-          S[i + j * CH] = i < cr ? tsqr_src(P, off + j + (int64_t)(q0 + i) * P.lda) : 0.0;
-        }
-      } else {
-        for (int e = tid; e < CH * me; e += kTsqrThreads) {
-          const int i = e % CH, j = e / CH;
-          S[i + j * CH] = i < cr ? tsqr_src(P, (q0 + i) + (int64_t)(off + j) * P.lda) : 0.0;
-        }
-      }
-      __syncthreads();
+      // rows rg + G k of the slot's columns (T(i, j) = A[j + i lda] when transposed)
       double C[CPT][RPT];
 #pragma unroll
       for (int cc = 0; cc < CPT; ++cc) {
         const int col = slot + SL * cc;
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) C[cc][k] = col < me ? S[rg + G * k + col * CH] : 0.0;
+        for (int k = 0; k < RPT; ++k) {
+          const int i = rg + G * k;
+          double x = 0.0;
+          if (col < me && i < cr)
+            x = tsqr_src(P, P.transA ? off + col + (int64_t)(q0 + i) * P.lda : (q0 + i) + (int64_t)(off + col) * P.lda);
+          C[cc][k] = x;
+        }
       }
       for (int jj = 0; jj < me; ++jj) {
         const int buf = jj & 1;
@@ -802,6 +797,15 @@ int tsqr_rb_variant(int m, int cap) {
   if (m <= 32 && TsqrRB16::need(m) <= (size_t)cap) return 1;
   if (m <= 64 && TsqrRB64::need(m) <= (size_t)cap) return 2;
   if (m <= 128 && TsqrRB128::need(m) <= (size_t)cap) return 3;
+  return 0;
+}
+
+int tsqr_rb_chunk(int variant) {
+  switch (variant) {
+    case 1: return TsqrRB16::kCH;
+    case 2: return TsqrRB64::kCH;
+    case 3: return TsqrRB128::kCH;
+  }
   return 0;
 }
 

@@ -552,45 +552,95 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
 
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
-  WorkCounts wc = work_counts(ctx, (int)p.size(), KK_TSQR);
-  if (wc.dev)
-    for (size_t i = 0; i < p.size(); ++i) p[i].work = wc.dev + i;
   // per problem: a register-blocked variant sized by m (the widest factored
-  // width), else the streaming kernel in LDS, else in a global scratch slot
+  // width), else the streaming kernel in LDS, else in a global scratch slot.
+  // When the batch leaves most of the device idle, tall problems of the
+  // register-blocked variants are cut into row segments factored by separate
+  // workgroups, and a second launch factors each stack of segment factors (a
+  // two-level TSQR tree; R agrees with the one-level result up to the signs
+  // of its rows).
   const int lim = lds_limit_doubles();
-  std::vector<TsqrProb> rb[4];
-  size_t rb_need[4] = {0, 0, 0, 0};
-  double rb_flops[4] = {0, 0, 0, 0}, rb_bytes[4] = {0, 0, 0, 0};
-  size_t slot = 0, lds = 0;
+  constexpr size_t kFillGroups = 1024;  // four workgroups per compute unit
+  const size_t want = p.size() < kFillGroups ? kFillGroups / p.size() : 1;
+  std::vector<std::pair<int, TsqrProb>> first, second;
   for (const TsqrProb& t : p) {
-    double N = t.N, m = t.m, r = std::min(N, m);
-    const double f = 2.0 * N * m * m - 2.0 * r * r * r / 3.0, by = 8.0 * (N * m + r * m);
     const int v = tsqr_rb_variant(t.m, lim);
-    rb[v].push_back(t);
-    rb_flops[v] += f;
-    rb_bytes[v] += by;
-    if (v) {
-      rb_need[v] = std::max(rb_need[v], tsqr_rb_need(v, t.m));
-    } else {
-      size_t need = tsqr_lds_need(t.m, lim);
-      if (need == 0)
-        slot = std::max(slot, tsqr_scratch_need(t.m));
-      else
-        lds = std::max(lds, need);
+    int parts = 1;
+    if (v && want > 1) {
+      const int64_t seg_min = std::max<int64_t>(2 * tsqr_rb_chunk(v), t.m + 1);
+      parts = (int)std::min<int64_t>({(int64_t)want, t.N / seg_min, 16});
     }
+    if (parts < 2) {
+      first.push_back({v, t});
+      continue;
+    }
+    const int64_t seg = (t.N + parts - 1) / parts;
+    parts = (int)((t.N + seg - 1) / seg);
+    const int64_t ld_stack = (int64_t)parts * t.m;
+    double* stack = ctx->ws.get<double>((size_t)ld_stack * t.m);
+    const size_t es = t.prec ? sizeof(float) : sizeof(double);
+    for (int q = 0; q < parts; ++q) {
+      const int64_t r0 = q * seg, r1 = std::min<int64_t>(t.N, r0 + seg);
+      TsqrProb u = t;
+      u.A = (const char*)t.A + (size_t)(t.transA ? r0 * t.lda : r0) * es;
+      u.N = (int32_t)(r1 - r0);
+      u.R = stack + (size_t)q * t.m;
+      u.ldr = ld_stack;
+      first.push_back({v, u});
+    }
+    TsqrProb w{};
+    w.A = stack;
+    w.lda = ld_stack;
+    w.N = (int32_t)ld_stack;
+    w.m = t.m;
+    w.transA = 0;
+    w.prec = 0;
+    w.col_off = nullptr;
+    w.R = t.R;
+    w.ldr = t.ldr;
+    second.push_back({v, w});
   }
-  for (int v = 1; v <= 3; ++v) {
-    if (rb[v].empty()) continue;
-    TsqrProb* d = upload_launch(ctx, rb[v]);
-    LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[v], rb_bytes[v]);
-    k_tsqr_rb(v, d, (int)rb[v].size(), rb_need[v], ctx->stream);
+  WorkCounts wc = work_counts(ctx, (int)(first.size() + second.size()), KK_TSQR);
+  if (wc.dev) {
+    size_t i = 0;
+    for (auto& e : first) e.second.work = wc.dev + i++;
+    for (auto& e : second) e.second.work = wc.dev + i++;
   }
-  if (!rb[0].empty()) {
-    double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(rb[0].size(), 1024)) : nullptr;
-    TsqrProb* d = upload_launch(ctx, rb[0]);
-    LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[0], rb_bytes[0]);
-    k_tsqr(d, (int)rb[0].size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
-  }
+  auto launch = [&](const std::vector<std::pair<int, TsqrProb>>& list) {
+    std::vector<TsqrProb> rb[4];
+    size_t rb_need[4] = {0, 0, 0, 0};
+    double rb_flops[4] = {0, 0, 0, 0}, rb_bytes[4] = {0, 0, 0, 0};
+    size_t slot = 0, lds = 0;
+    for (const auto& [v, t] : list) {
+      double N = t.N, m = t.m, r = std::min(N, m);
+      rb[v].push_back(t);
+      rb_flops[v] += 2.0 * N * m * m - 2.0 * r * r * r / 3.0;
+      rb_bytes[v] += 8.0 * (N * m + r * m);
+      if (v) {
+        rb_need[v] = std::max(rb_need[v], tsqr_rb_need(v, t.m));
+      } else {
+        size_t need = tsqr_lds_need(t.m, lim);
+        if (need == 0)
+          slot = std::max(slot, tsqr_scratch_need(t.m));
+        else
+          lds = std::max(lds, need);
+      }
+    }
+    for (int v = 1; v <= 3; ++v) {
+      if (rb[v].empty()) continue;
+      TsqrProb* d = upload_launch(ctx, rb[v]);
+      LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[v], rb_bytes[v]);
+      k_tsqr_rb(v, d, (int)rb[v].size(), rb_need[v], ctx->stream);
+    }
+    if (!rb[0].empty()) {
+      double* scratch = slot ? ctx->ws.get<double>(slot * std::min<size_t>(rb[0].size(), 1024)) : nullptr;
+      TsqrProb* d = upload_launch(ctx, rb[0]);
+      LaunchTimer lt(ctx, KK_TSQR, wc.dev ? 0.0 : rb_flops[0], rb_bytes[0]);
+      k_tsqr(d, (int)rb[0].size(), std::max<size_t>(lds, 1), slot, scratch, ctx->stream);
+    }
+  };
+  launch(first);
+  launch(second);
   if (wc.dev) {  // counts of all launches, resolved with the last one's timing
     dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);
     if (!ctx->pending.empty()) {
