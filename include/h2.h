@@ -178,7 +178,8 @@ h2_status h2_product_sizes(const h2_product* G, int64_t out[5]);
  * last read with reset != 0; out[] receives up to n entries: out[0..7]
  * device time between stream events around each step, out[8..15] host wall
  * time spent issuing it, in the order
- *   0 setup, 1 symbolic, 2 phase-1 row, 3 phase-1 col, 4 phase-1 mat (G),
+ *   0 setup, 1 product tree and nearfield products (a third stream,
+ *   overlapping steps 2/3), 2 phase-1 row, 3 phase-1 col, 4 phase-1 mat (G),
  *   5 phase-2 row, 6 phase-2 col, 7 phase-2 mat (Z).
  * The column passes run on a second stream concurrently with the row passes,
  * so steps 2/3 and 5/6 overlap in time.  The calls themselves do not wait for

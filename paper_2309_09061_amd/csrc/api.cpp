@@ -41,8 +41,7 @@ static constexpr double kFp32BulkMinEps = 1e-6;
 // stream's work of a call is ordered after the context stream's work queued
 // before it.
 static void begin_call(h2_ctx* ctx) {
-  ctx->ws.reset();
-  if (ctx->aux) ctx->aux->ws.reset();
+  for (h2_ctx* c = ctx; c; c = c->aux) c->ws.reset();
 }
 
 extern "C" {
@@ -79,8 +78,7 @@ h2_status h2_ctx_destroy(h2_ctx* ctx) {
     if (!ctx) return;
     if (!ctx->host_only) {
       dev_set_device(ctx->device);
-      dev_sync(ctx->stream);
-      if (ctx->aux) dev_sync(ctx->aux->stream);
+      for (h2_ctx* c = ctx; c; c = c->aux) dev_sync(c->stream);
     }
     delete ctx;
   });
@@ -294,7 +292,7 @@ h2_status h2_product_sizes(const h2_product* G, int64_t out[5]) {
     out[1] = G->c.bt->n_adm;
     out[2] = G->c.bt->n_inadm;
     out[3] = G->n_triples;
-    out[4] = (int64_t)G->mem.total;
+    out[4] = (int64_t)(G->mem.total + G->mem_aux.total + G->mem_nf.total);
   });
 }
 

@@ -383,6 +383,7 @@ struct h2_product {
   h2::H2Core c;
   h2::Arena mem;
   h2::Arena mem_aux;  // results of the column pass (allocated by the auxiliary context)
+  h2::Arena mem_nf;   // dense leaf blocks (allocated by the second auxiliary context)
   int64_t n_triples = 0;
 };
 
@@ -437,7 +438,8 @@ void step_end(h2_ctx* ctx, int step);
 void steps_collect(h2_ctx* ctx);
 
 void* pool_event(h2_ctx* ctx);
-// the auxiliary context of ctx (created on first use)
+// the auxiliary context of ctx (created on first use); the auxiliary
+// context's own one, aux_ctx(aux_ctx(ctx)), is a third stream
 h2_ctx* aux_ctx(h2_ctx* ctx);
 // Runs f(aux) on a host thread, on the auxiliary stream, ordered after the
 // work queued so far on ctx->stream.  join() waits for the thread, makes
@@ -448,6 +450,7 @@ struct AuxRun {
   std::thread th;
   std::exception_ptr err;
   AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f);
+  AuxRun(h2_ctx* c, h2_ctx* a, std::function<void(h2_ctx*)> f);  // on a given auxiliary context
   void join();
   ~AuxRun();
 };

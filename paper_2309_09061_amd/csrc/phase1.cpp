@@ -19,6 +19,9 @@
 // matrices, and inadmissible leaves are expanded to dense blocks together
 // with the products of two nearfield blocks.
 #include <cmath>
+
+#include <algorithm>
+#include <array>
 #include <exception>
 #include <thread>
 
@@ -383,22 +386,105 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   G->mem.ctx = ctx;
   View X{&Xm->c, false}, Y{&Ym->c, false};
   View Yt{&Ym->c, true}, Xt{&Xm->c, true};
-  // the product tree T^XY is symbolic (block trees only): built on a host
-  // thread while the two induced-basis passes run
+  const BlockTreeH& BX = *Xm->c.bt;
+  const BlockTreeH& BY = *Ym->c.bt;
+  const int nbx = BX.nblocks(), nby = BY.nblocks();
+  // operand tables of the factor blocks of a triple: X's and Y's blocks
+  std::vector<const double*> tX(nbx), tY(nby);
+  std::vector<int64_t> lX(nbx), lY(nby);
+  for (int b = 0; b < nbx; ++b) {
+    tX[b] = Xm->c.blk[b];
+    lX[b] = Xm->c.ld_of(b);
+  }
+  for (int b = 0; b < nby; ++b) {
+    tY[b] = Ym->c.blk[b];
+    lY[b] = Ym->c.ld_of(b);
+  }
+  // The dense leaf blocks of T^XY start with the sum of their nearfield-
+  // times-nearfield triples and the product tree T^XY is symbolic (block
+  // trees only); neither needs a basis, so both are done on a second
+  // auxiliary context (host thread and stream) while the two induced-basis
+  // passes run.  The dense blocks are the leaf pairs (t, r) joined by a
+  // nearfield block (t, s) of X and (s, r) of Y (a block of T^XY is dense
+  // exactly when such a triple ends in it); their products are launched
+  // before the product tree is built.  The projected part Q_t S Q^W_r^* is
+  // added at the end.
   ProductTreeH PT;
   std::exception_ptr sym_err;
   struct Joiner {
     std::thread th;
-    ~Joiner() {
+    void join() {
       if (th.joinable()) th.join();
     }
+    ~Joiner() { join(); }
   } sym;
-  sym.th = std::thread([&] {
+  sym.th = std::thread([&] {  // host work only
     try {
       PT = build_product_tree(X, Y, T.ncl);
     } catch (...) {
       sym_err = std::current_exception();
     }
+  });
+  const int32_t* d_tri = nullptr;
+  std::vector<std::vector<std::pair<int, double*>>> dn_of(T.ncl);  // leaf t: (r, block) by r
+  h2_ctx* nf_ctx = aux_ctx(aux_ctx(ctx));
+  G->mem_nf.ctx = nf_ctx;
+  AuxRun nfrun(ctx, nf_ctx, [&](h2_ctx* a) {
+    step_begin(a, 1);
+    std::vector<int32_t> sizes(T.ncl);
+    int64_t leaf_max = 0;
+    for (int c = 0; c < T.ncl; ++c) {
+      sizes[c] = (int32_t)T.size[c];
+      if (T.leaf(c)) leaf_max = std::max(leaf_max, T.size[c]);
+    }
+    TriBatch tnn;
+    tnn.prec = prec;
+    tnn.block = leaf_max <= 64;
+    std::vector<Triple> nn;
+    std::vector<std::array<int32_t, 4>> row;  // (r, s, bx, by) of one leaf t
+    double f_nn = 0;
+    for (int t = T.first(T.depth); t < T.ncl; ++t) {
+      row.clear();
+      const int32_t* bl;
+      int cnt;
+      X.row_blocks(t, bl, cnt);
+      for (int q = 0; q < cnt; ++q) {
+        if (X.type(bl[q]) != BT_INADM) continue;
+        const int sm = X.vcol(bl[q]);
+        const int32_t* bl2;
+        int cnt2;
+        Y.row_blocks(sm, bl2, cnt2);
+        for (int q2 = 0; q2 < cnt2; ++q2)
+          if (Y.type(bl2[q2]) == BT_INADM) row.push_back({Y.vcol(bl2[q2]), sm, bl[q], bl2[q2]});
+      }
+      std::sort(row.begin(), row.end());
+      for (size_t i = 0; i < row.size();) {
+        const int r = row[i][0];
+        const int q0 = (int)nn.size();
+        for (; i < row.size() && row[i][0] == r; ++i) {
+          nn.push_back({row[i][1], row[i][2], row[i][3], TK_NN});
+          f_nn += 2.0 * T.size[t] * T.size[r] * T.size[row[i][1]];
+        }
+        double* D = G->mem_nf.get<double>((size_t)T.size[t] * T.size[r]);
+        dn_of[t].push_back({r, D});
+        tnn.out(D, T.size[t], (int)T.size[t], (int)T.size[r], q0, (int)nn.size(), false);
+      }
+    }
+    TriFamily fNN{};  // N_X N_Y over the leaf size of the middle cluster
+    fNN.tri = (const int32_t*)upload(a, nn.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : nn);
+    fNN.A = upload(a, tX);
+    fNN.lda = upload(a, lX);
+    fNN.B = upload(a, tY);
+    fNN.ldb = upload(a, lY);
+    fNN.ks = upload(a, sizes);
+    fNN.k = uniform_rank(Xm->c.V);
+    fNN.kind = TK_NN;
+    tnn.fam = fNN;
+    tnn.run(a, f_nn);
+    sym.join();
+    if (sym_err) std::rethrow_exception(sym_err);
+    d_tri = (const int32_t*)upload(a, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
+    step_end(a, 1);
   });
   // row pass (X, Y) here, column pass (Y^*, X^*) concurrently on the
   // auxiliary context; the two share only read-only inputs
@@ -409,11 +495,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2);
     colrun.join();
   }
-
-  step_begin(ctx, 1);  // the part of the symbolic build not hidden by the passes
-  sym.th.join();
-  step_end(ctx, 1);
-  if (sym_err) std::rethrow_exception(sym_err);
+  nfrun.join();
   G->n_triples = PT.n_terminated;
 
   // ---- forming G on T^XY (top-down, then dense leaves) ----
@@ -424,7 +506,6 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   GemmBatch g;
   g.prec = prec;
   // P_{XY,s} S_{Y,sr} for admissible blocks of Y
-  const BlockTreeH& BY = *Ym->c.bt;
   std::vector<double*> PS(BY.nblocks(), nullptr);
   for (int b = 0; b < BY.nblocks(); ++b) {
     if (BY.type[b] != BT_ADM) continue;
@@ -445,13 +526,9 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   // blocks of a triple (one upload each per call): X's and Y's blocks, the
   // products P S_Y of admissible blocks of Y, the row pass's A_{t,s} of the
   // blocks of X and the column pass's A^c of the blocks of Y.
-  const BlockTreeH& BX = *Xm->c.bt;
-  const int nbx = BX.nblocks(), nby = BY.nblocks();
-  std::vector<const double*> tX(nbx), tY(nby), tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
-  std::vector<int64_t> lX(nbx), lY(nby), lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
+  std::vector<const double*> tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
+  std::vector<int64_t> lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
   for (int b = 0; b < nbx; ++b) {
-    tX[b] = Xm->c.blk[b];
-    lX[b] = Xm->c.ld_of(b);
     if (BX.type[b] != BT_ADM && row.cpos[b] >= 0) {
       const int kt = row.Q.rank[X.vrow(b)];
       tAr[b] = row.A[X.vrow(b)] + (size_t)row.cpos[b] * k * kt;
@@ -459,8 +536,6 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     }
   }
   for (int b = 0; b < nby; ++b) {
-    tY[b] = Ym->c.blk[b];
-    lY[b] = Ym->c.ld_of(b);
     tPS[b] = PS[b];
     if (BY.type[b] != BT_ADM && col.cpos[b] >= 0) {
       const int r = BY.s[b], kr = col.Q.rank[r];
@@ -468,10 +543,6 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       lAc[b] = std::max(kr, 1);
     }
   }
-  const int32_t* d_tri = (const int32_t*)upload(ctx, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
-  std::vector<int32_t> sizes(T.ncl);
-  for (int c = 0; c < T.ncl; ++c) sizes[c] = (int32_t)T.size[c];
-  const int32_t* d_size = upload(ctx, sizes);
   auto fam = [&](const std::vector<const double*>& A, const std::vector<int64_t>& la,
                  const std::vector<const double*>& Bt, const std::vector<int64_t>& lb, int kind, bool tB,
                  const int32_t* ks) {
@@ -491,7 +562,6 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   const TriFamily fAA = fam(tX, lX, tPS, lPS, TK_AA, false, nullptr);  // S_X (P S_Y)
   const TriFamily fNA = fam(tAr, lAr, tY, lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
   const TriFamily fAN = fam(tX, lX, tAc, lAc, TK_AN, true, nullptr);   // S_X A^c_{r,s}^*
-  const TriFamily fNN = fam(tX, lX, tY, lY, TK_NN, false, d_size);     // N_X N_Y
   auto cnt = [&](int b, int kind) { return PT.kind_cnt[4 * (size_t)b + kind]; };
 
   for (int l = 0; l <= T.depth; ++l) {
@@ -563,7 +633,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     }
     g.run(ctx);
   }
-  // dense inadmissible leaves: sum of nearfield products plus Q_t S Q^W_r^*
+  // dense inadmissible leaves: the nearfield products (already there) plus Q_t S Q^W_r^*
   {
     const int l = T.depth;
     std::vector<double*> QS(B.nblocks(), nullptr);
@@ -576,29 +646,19 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], std::max(kt, 1), false, kt);
     }
     g.run(ctx);
-    TriBatch tnn;
-    tnn.fam = fNN;
-    tnn.prec = prec;
-    int64_t leaf_max = 0;
-    for (int c = 0; c < T.ncl; ++c)
-      if (T.leaf(c)) leaf_max = std::max(leaf_max, T.size[c]);
-    tnn.block = leaf_max <= 64;
-    double f_nn = 0;
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (B.type[b] != BT_INADM) continue;
       int t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
-      double* Dn = G->mem.get<double>((size_t)T.size[t] * T.size[r]);
+      const auto& dl = dn_of[t];
+      auto it = std::lower_bound(dl.begin(), dl.end(), std::make_pair(r, (double*)nullptr));
+      H2_REQUIRE(it != dl.end() && it->first == r, H2_ERR_SHAPE, "dense leaf of T^XY without nearfield triple");
+      double* Dn = it->second;
       C.blk[b] = Dn;
-      g.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r]);
-      if (QS[b]) g.term(QS[b], T.size[t], false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
-      if (cnt(b, TK_NN)) {
-        tnn.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r], PT.tri_ptr[b], PT.tri_ptr[b + 1], true);
-        for (int q = PT.tri_ptr[b]; q < PT.tri_ptr[b + 1]; ++q)
-          if (PT.tri[q].kind == TK_NN) f_nn += 2.0 * T.size[t] * T.size[r] * T.size[PT.tri[q].s];
-      }
+      if (!QS[b]) continue;
+      g.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r], true);
+      g.term(QS[b], T.size[t], false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
     }
-    g.run(ctx);  // Q S Q^W^* (overwrites; zero when no expanded part), then the dense triples
-    tnn.run(ctx, f_nn);
+    g.run(ctx);
   }
   step_end(ctx, 4);
 }

@@ -74,10 +74,13 @@ char* stage_alloc(h2_ctx* ctx, size_t bytes) {
   if (ctx->stage_used + need > ctx->stage_cap) {
     dev_sync(ctx->stream);  // earlier copies out of the staging buffer are done
     ctx->stage_used = 0;
-    if (need > ctx->stage_cap) {
+    // a call that fills the staging waits here: the buffer grows (up to
+    // 1 GiB) so that later calls of the same size do not
+    constexpr size_t kStageMax = (size_t)1 << 30;
+    if (need > ctx->stage_cap || ctx->stage_cap < kStageMax) {
       dev_free_host(ctx->stage);
       ctx->stage = ctx->stage_dev = nullptr;
-      ctx->stage_cap = std::max(need, ctx->stage_cap * 2);
+      ctx->stage_cap = std::max(need, std::min(ctx->stage_cap * 2, kStageMax));
       ctx->stage = (char*)dev_malloc_host(ctx->stage_cap);
       ctx->stage_dev = (char*)dev_host_view(ctx->stage);
     }
@@ -222,7 +225,9 @@ h2_ctx* aux_ctx(h2_ctx* ctx) {
   return ctx->aux;
 }
 
-AuxRun::AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f) : ctx(c), aux(aux_ctx(c)) {
+AuxRun::AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f) : AuxRun(c, aux_ctx(c), std::move(f)) {}
+
+AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), aux(a_) {
   aux->profile = ctx->profile;
   aux->prec = ctx->prec;
   void* e = pool_event(ctx);
@@ -261,6 +266,7 @@ AuxRun::~AuxRun() {
 void aux_collect(h2_ctx* ctx) {
   h2_ctx* a = ctx->aux;
   if (!a) return;
+  aux_collect(a);  // the auxiliary context's own one first
   steps_collect(a);
   for (int i = 0; i < 8; ++i) {
     ctx->step_ms[i] += a->step_ms[i];

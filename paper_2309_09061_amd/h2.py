@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libh2.so")
 KERNELS = {"log": 0, "expneg": 1, "inv4pi": 2, "inv": 3, "poly2": 100}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 KERNEL_FAMILIES = ["gemm_sum", "tsqr", "jacobi", "build", "other"]
-STEPS = ["setup", "symbolic", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat"]
+STEPS = ["setup", "nearfield", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat"]
 
 _c_p = ctypes.c_void_p
 _i64 = ctypes.c_int64
