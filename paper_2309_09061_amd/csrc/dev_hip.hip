@@ -111,6 +111,7 @@ void dev_event_destroy(void* ev) {
 void dev_event_record(void* ev, void* stream) {
   HIP_OK(hipEventRecord((hipEvent_t)ev, (hipStream_t)stream));
 }
+void dev_event_sync(void* ev) { HIP_OK(hipEventSynchronize((hipEvent_t)ev)); }
 float dev_event_ms(void* a, void* b) {
   HIP_OK(hipEventSynchronize((hipEvent_t)b));
   float ms = 0;

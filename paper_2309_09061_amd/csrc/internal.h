@@ -60,6 +60,7 @@ void* dev_event_create();
 void dev_event_destroy(void* ev);
 void dev_event_record(void* ev, void* stream);
 float dev_event_ms(void* a, void* b);  // synchronises on b
+void dev_event_sync(void* ev);
 
 // ---------------------------------------------------------------------------
 // kernel descriptors (identical layout on host and device)
@@ -360,6 +361,7 @@ struct h2_ctx {
   // second context on the same device (own stream, workspace, staging) for
   // the column passes, which run concurrently with the row passes
   h2_ctx* aux = nullptr;
+  void* drain = nullptr;  // auxiliary contexts: end of the last run's work on the stream
   bool own_stream = false;
   ~h2_ctx();
 };

@@ -22,7 +22,9 @@
 
 #include <algorithm>
 #include <array>
+#include <condition_variable>
 #include <exception>
+#include <mutex>
 #include <thread>
 
 #include "internal.h"
@@ -38,6 +40,50 @@ struct P1Side {
   std::vector<double*> P;                    // P_{XY,s}, k x k
 };
 
+// Completion of the levels of the two induced-basis passes (both run from
+// the leaves up), for the parts of G that need the bases of one level only.
+// A pass records an event on its stream after a level and publishes the
+// level; a waiter orders its own stream after both events.
+struct LevelSignal {
+  std::mutex mu;
+  std::condition_variable cv;
+  int low[2];                // lowest level finished by each pass (depth + 1: none yet)
+  bool stop = false;         // set when a pass ends early (an error)
+  std::vector<void*> ev[2];  // per pass and level
+  explicit LevelSignal(int depth) {
+    for (int s = 0; s < 2; ++s) {
+      low[s] = depth + 1;
+      ev[s].assign(depth + 1, nullptr);
+      for (auto& e : ev[s]) e = dev_event_create();
+    }
+  }
+  ~LevelSignal() {
+    for (auto& v : ev)
+      for (void* e : v) dev_event_destroy(e);
+  }
+  void done(int side, int l, void* stream) {
+    dev_event_record(ev[side][l], stream);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      low[side] = l;
+    }
+    cv.notify_all();
+  }
+  // true once both passes have finished level l; false if stopped before
+  bool wait(int l) {
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return (low[0] <= l && low[1] <= l) || stop; });
+    return low[0] <= l && low[1] <= l;
+  }
+  void abort() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+  }
+};
+
 // relative tolerance of the numerical rank of V_X (the kept range)
 static constexpr double kVxRtol = 1e-12;
 
@@ -49,7 +95,7 @@ static int uniform_rank(const Basis& B) {
 
 // One pass of Figure "induced_basis" for the product X Y given as views.
 static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, Arena& keep,
-                         P1Side& out, int step_setup, int step_sweep) {
+                         P1Side& out, int step_setup, int step_sweep, LevelSignal* lsig, int side) {
   const TreeH& T = *X.m->ct;
   const int ncl = T.ncl, D = T.depth;
   const int k = uniform_rank(X.rowb());
@@ -373,6 +419,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       g.out(out.RXP[t] + kk1[i], kt, kt - kk1[i], k);  // zero rows below R_X
     }
     g.run(ctx);
+    if (lsig) lsig->done(side, l, ctx->stream);
   }
   step_end(ctx, step_sweep);
 }
@@ -407,8 +454,11 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   // passes run.  The dense blocks are the leaf pairs (t, r) joined by a
   // nearfield block (t, s) of X and (s, r) of Y (a block of T^XY is dense
   // exactly when such a triple ends in it); their products are launched
-  // before the product tree is built.  The projected part Q_t S Q^W_r^* is
-  // added at the end.
+  // before the product tree is built (on a host thread of its own).  The
+  // same context then forms the part of G that needs the bases of one level
+  // only, level by level as the passes finish them.  The parents' share of
+  // S and the projected part Q_t S Q^W_r^* of the dense blocks are added
+  // after the passes.
   ProductTreeH PT;
   std::exception_ptr sym_err;
   struct Joiner {
@@ -425,10 +475,14 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       sym_err = std::current_exception();
     }
   });
-  const int32_t* d_tri = nullptr;
   std::vector<std::vector<std::pair<int, double*>>> dn_of(T.ncl);  // leaf t: (r, block) by r
   h2_ctx* nf_ctx = aux_ctx(aux_ctx(ctx));
   G->mem_nf.ctx = nf_ctx;
+  const int k = uniform_rank(Xm->c.V);
+  P1Side row, col;
+  LevelSignal sig(T.depth);
+  // S (kt x kr) of every block of T^XY, in the coefficients of the new bases
+  std::vector<double*> S;
   AuxRun nfrun(ctx, nf_ctx, [&](h2_ctx* a) {
     step_begin(a, 1);
     std::vector<int32_t> sizes(T.ncl);
@@ -441,10 +495,10 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     tnn.prec = prec;
     tnn.block = leaf_max <= 64;
     std::vector<Triple> nn;
-    std::vector<std::array<int32_t, 4>> row;  // (r, s, bx, by) of one leaf t
+    std::vector<std::array<int32_t, 4>> rowl;  // (r, s, bx, by) of one leaf t
     double f_nn = 0;
     for (int t = T.first(T.depth); t < T.ncl; ++t) {
-      row.clear();
+      rowl.clear();
       const int32_t* bl;
       int cnt;
       X.row_blocks(t, bl, cnt);
@@ -455,184 +509,198 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
         int cnt2;
         Y.row_blocks(sm, bl2, cnt2);
         for (int q2 = 0; q2 < cnt2; ++q2)
-          if (Y.type(bl2[q2]) == BT_INADM) row.push_back({Y.vcol(bl2[q2]), sm, bl[q], bl2[q2]});
+          if (Y.type(bl2[q2]) == BT_INADM) rowl.push_back({Y.vcol(bl2[q2]), sm, bl[q], bl2[q2]});
       }
-      std::sort(row.begin(), row.end());
-      for (size_t i = 0; i < row.size();) {
-        const int r = row[i][0];
+      std::sort(rowl.begin(), rowl.end());
+      for (size_t i = 0; i < rowl.size();) {
+        const int r = rowl[i][0];
         const int q0 = (int)nn.size();
-        for (; i < row.size() && row[i][0] == r; ++i) {
-          nn.push_back({row[i][1], row[i][2], row[i][3], TK_NN});
-          f_nn += 2.0 * T.size[t] * T.size[r] * T.size[row[i][1]];
+        for (; i < rowl.size() && rowl[i][0] == r; ++i) {
+          nn.push_back({rowl[i][1], rowl[i][2], rowl[i][3], TK_NN});
+          f_nn += 2.0 * T.size[t] * T.size[r] * T.size[rowl[i][1]];
         }
         double* D = G->mem_nf.get<double>((size_t)T.size[t] * T.size[r]);
         dn_of[t].push_back({r, D});
         tnn.out(D, T.size[t], (int)T.size[t], (int)T.size[r], q0, (int)nn.size(), false);
       }
     }
-    TriFamily fNN{};  // N_X N_Y over the leaf size of the middle cluster
-    fNN.tri = (const int32_t*)upload(a, nn.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : nn);
-    fNN.A = upload(a, tX);
-    fNN.lda = upload(a, lX);
-    fNN.B = upload(a, tY);
-    fNN.ldb = upload(a, lY);
-    fNN.ks = upload(a, sizes);
-    fNN.k = uniform_rank(Xm->c.V);
-    fNN.kind = TK_NN;
-    tnn.fam = fNN;
+    // operand tables indexed by the factor blocks of a triple
+    const double* const* d_tX = upload(a, tX);
+    const int64_t* d_lX = upload(a, lX);
+    const double* const* d_tY = upload(a, tY);
+    const int64_t* d_lY = upload(a, lY);
+    auto family = [&](const int32_t* tri, const double* const* A, const int64_t* la, const double* const* Bt,
+                      const int64_t* lb, int kind, bool tB, const int32_t* ks) {
+      TriFamily f{};
+      f.tri = tri;
+      f.A = A;
+      f.lda = la;
+      f.B = Bt;
+      f.ldb = lb;
+      f.ks = ks;
+      f.k = k;
+      f.kind = kind;
+      f.tA = 0;
+      f.tB = tB ? 1 : 0;
+      return f;
+    };
+    // N_X N_Y over the leaf size of the middle cluster
+    tnn.fam = family((const int32_t*)upload(a, nn.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : nn), d_tX, d_lX,
+                     d_tY, d_lY, TK_NN, false, upload(a, sizes));
     tnn.run(a, f_nn);
     sym.join();
     if (sym_err) std::rethrow_exception(sym_err);
-    d_tri = (const int32_t*)upload(a, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
+    const int32_t* d_tri = (const int32_t*)upload(a, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
     step_end(a, 1);
+
+    // ---- G, the part of each level that needs the bases of that level only ----
+    // Sloc_b = TNA_b R^c_r^* + R_t Mm_b with TNA_b the sum of A_{t,s} S_Y over
+    // the NA triples and Mm_b = (sum of S_X P S_Y over AA triples) R^c_r^* +
+    // sum of S_X A^c^* over AN triples; it is formed for each level of T^XY as
+    // soon as both passes have finished that level.  The projections of the
+    // parents' S are added top-down once the passes are done.
+    step_begin(a, 4);
+    const BlockTreeH& B = *PT.bt;
+    Arena& ws = a->ws;
+    GemmBatch g;
+    g.prec = prec;
+    S.assign(B.nblocks(), nullptr);
+    auto cnt = [&](int b, int kind) { return PT.kind_cnt[4 * (size_t)b + kind]; };
+    std::vector<const double*> tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
+    std::vector<int64_t> lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
+    TriFamily fAA{};
+    for (int l = T.depth; l >= 0; --l) {
+      H2_REQUIRE(sig.wait(l), H2_ERR_DEVICE, "phase 1: a basis pass stopped early");
+      dev_stream_wait(a->stream, sig.ev[0][l]);
+      dev_stream_wait(a->stream, sig.ev[1][l]);
+      if (l == T.depth) {  // P_{XY,s} S_{Y,sr} for admissible blocks of Y (P from the row set-up)
+        for (int b = 0; b < nby; ++b) {
+          if (BY.type[b] != BT_ADM) continue;
+          double* ps = ws.get<double>((size_t)k * k);
+          tPS[b] = ps;
+          g.out(ps, k, k, k);
+          g.term(row.P[BY.t[b]], k, false, Ym->c.blk[b], Ym->c.ld_of(b), false, k);
+        }
+        g.run(a);
+        fAA = family(d_tri, d_tX, d_lX, upload(a, tPS), upload(a, lPS), TK_AA, false, nullptr);  // S_X (P S_Y)
+      }
+      // A_{t,s} of the blocks of X and A^c of the blocks of Y on this level
+      for (int b = BX.lvl[l]; b < BX.lvl[l + 1]; ++b)
+        if (BX.type[b] != BT_ADM && row.cpos[b] >= 0) {
+          const int kt = row.Q.rank[X.vrow(b)];
+          tAr[b] = row.A[X.vrow(b)] + (size_t)row.cpos[b] * k * kt;
+          lAr[b] = std::max(kt, 1);
+        }
+      for (int b = BY.lvl[l]; b < BY.lvl[l + 1]; ++b)
+        if (BY.type[b] != BT_ADM && col.cpos[b] >= 0) {
+          const int r = BY.s[b], kr = col.Q.rank[r];
+          tAc[b] = col.A[r] + (size_t)col.cpos[b] * k * kr;
+          lAc[b] = std::max(kr, 1);
+        }
+      const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
+      TriBatch taa, tna, tan_;
+      taa.fam = fAA;
+      tna.fam = family(d_tri, upload(a, tAr), upload(a, lAr), d_tY, d_lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
+      tan_.fam = family(d_tri, d_tX, d_lX, upload(a, tAc), upload(a, lAc), TK_AN, true, nullptr);  // S_X A^c^*
+      taa.prec = tna.prec = tan_.prec = prec;
+      std::vector<double*> TAA(b1 - b0, nullptr), TNA(b1 - b0, nullptr), Mm(b1 - b0, nullptr);
+      double f_aa = 0, f_na = 0, f_an = 0;
+      for (int b = b0; b < b1; ++b) {
+        const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+        S[b] = G->mem_nf.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1));
+        if (cnt(b, TK_AA)) {
+          TAA[i] = ws.get<double>((size_t)k * k);
+          taa.out(TAA[i], k, k, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
+          f_aa += 2.0 * k * k * k * cnt(b, TK_AA);
+        }
+        if (cnt(b, TK_NA) && kt > 0) {
+          TNA[i] = ws.get<double>((size_t)kt * k);
+          tna.out(TNA[i], kt, kt, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
+          f_na += 2.0 * kt * k * k * cnt(b, TK_NA);
+        }
+      }
+      taa.run(a, f_aa);
+      tna.run(a, f_na);
+      for (int b = b0; b < b1; ++b) {
+        const int i = b - b0, r = B.s[b], kr = col.Q.rank[r];
+        if ((cnt(b, TK_AN) || TAA[i]) && kr > 0) {
+          Mm[i] = ws.get<double>((size_t)k * kr);
+          g.out(Mm[i], k, k, kr);
+          if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
+          if (cnt(b, TK_AN)) {
+            tan_.out(Mm[i], k, k, kr, PT.tri_ptr[b], PT.tri_ptr[b + 1], TAA[i] != nullptr);
+            f_an += 2.0 * k * k * kr * cnt(b, TK_AN);
+          }
+        }
+      }
+      g.run(a);  // TAA R^c^* first (overwrites), then the AN triples accumulate
+      tan_.run(a, f_an);
+      for (int b = b0; b < b1; ++b) {
+        const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+        g.out(S[b], std::max(kt, 1), kt, kr);  // zero without terms
+        if (TNA[i]) g.term(TNA[i], kt, false, col.RXP[r], std::max(kr, 1), true, k);
+        if (Mm[i]) g.term(row.RXP[t], std::max(kt, 1), false, Mm[i], k, false, k);
+      }
+      g.run(a);
+    }
+    step_end(a, 4);
   });
   // row pass (X, Y) here, column pass (Y^*, X^*) concurrently on the
   // auxiliary context; the two share only read-only inputs
-  P1Side row, col;
+  struct StopOnExit {
+    LevelSignal& s;
+    ~StopOnExit() { s.abort(); }
+  } stop_on_exit{sig};
   G->mem_aux.ctx = aux_ctx(ctx);
   {
-    AuxRun colrun(ctx, [&](h2_ctx* a) { induced_pass(a, Yt, Xt, eps, G->mem_aux, col, 0, 3); });
-    induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2);
+    AuxRun colrun(ctx, [&](h2_ctx* a) { induced_pass(a, Yt, Xt, eps, G->mem_aux, col, 0, 3, &sig, 1); });
+    induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2, &sig, 0);
     colrun.join();
   }
   nfrun.join();
   G->n_triples = PT.n_terminated;
 
-  // ---- forming G on T^XY (top-down, then dense leaves) ----
+  // ---- G: the parents' S projected onto each block, top-down ----
   step_begin(ctx, 4);
   const BlockTreeH& B = *PT.bt;
-  const int k = uniform_rank(Xm->c.V);
   Arena& ws = ctx->ws;
   GemmBatch g;
   g.prec = prec;
-  // P_{XY,s} S_{Y,sr} for admissible blocks of Y
-  std::vector<double*> PS(BY.nblocks(), nullptr);
-  for (int b = 0; b < BY.nblocks(); ++b) {
-    if (BY.type[b] != BT_ADM) continue;
-    PS[b] = ws.get<double>((size_t)k * k);
-    g.out(PS[b], k, k, k);
-    g.term(row.P[BY.t[b]], k, false, Ym->c.blk[b], Ym->c.ld_of(b), false, k);
-  }
-  g.run(ctx);
   H2Core& C = G->c;
   C.ct = Xm->c.ct;
   C.bt = PT.bt;
   C.V = row.Q;
   C.W = col.Q;
   C.blk.assign(B.nblocks(), nullptr);
-  std::vector<double*> S(B.nblocks(), nullptr);
-
-  // Operand tables for the triple-driven products, indexed by the factor
-  // blocks of a triple (one upload each per call): X's and Y's blocks, the
-  // products P S_Y of admissible blocks of Y, the row pass's A_{t,s} of the
-  // blocks of X and the column pass's A^c of the blocks of Y.
-  std::vector<const double*> tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
-  std::vector<int64_t> lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
-  for (int b = 0; b < nbx; ++b) {
-    if (BX.type[b] != BT_ADM && row.cpos[b] >= 0) {
-      const int kt = row.Q.rank[X.vrow(b)];
-      tAr[b] = row.A[X.vrow(b)] + (size_t)row.cpos[b] * k * kt;
-      lAr[b] = std::max(kt, 1);
-    }
-  }
-  for (int b = 0; b < nby; ++b) {
-    tPS[b] = PS[b];
-    if (BY.type[b] != BT_ADM && col.cpos[b] >= 0) {
-      const int r = BY.s[b], kr = col.Q.rank[r];
-      tAc[b] = col.A[r] + (size_t)col.cpos[b] * k * kr;
-      lAc[b] = std::max(kr, 1);
-    }
-  }
-  auto fam = [&](const std::vector<const double*>& A, const std::vector<int64_t>& la,
-                 const std::vector<const double*>& Bt, const std::vector<int64_t>& lb, int kind, bool tB,
-                 const int32_t* ks) {
-    TriFamily f{};
-    f.tri = d_tri;
-    f.A = upload(ctx, A);
-    f.lda = upload(ctx, la);
-    f.B = upload(ctx, Bt);
-    f.ldb = upload(ctx, lb);
-    f.ks = ks;
-    f.k = k;
-    f.kind = kind;
-    f.tA = 0;
-    f.tB = tB ? 1 : 0;
-    return f;
-  };
-  const TriFamily fAA = fam(tX, lX, tPS, lPS, TK_AA, false, nullptr);  // S_X (P S_Y)
-  const TriFamily fNA = fam(tAr, lAr, tY, lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
-  const TriFamily fAN = fam(tX, lX, tAc, lAc, TK_AN, true, nullptr);   // S_X A^c_{r,s}^*
-  auto cnt = [&](int b, int kind) { return PT.kind_cnt[4 * (size_t)b + kind]; };
-
-  for (int l = 0; l <= T.depth; ++l) {
+  for (int l = 1; l <= T.depth; ++l) {
     const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
-    std::vector<double*> TAA(b1 - b0, nullptr), TNA(b1 - b0, nullptr), Pp(b1 - b0, nullptr),
-        Mm(b1 - b0, nullptr);
     std::vector<int> parent(b1 - b0, -1);
-    if (l > 0)
-      for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
-        if (B.type[pb] == BT_SPLIT)
-          for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - b0] = pb;
-    TriBatch taa, tna, tan_;
-    taa.fam = fAA;
-    tna.fam = fNA;
-    tan_.fam = fAN;
-    taa.prec = tna.prec = tan_.prec = prec;
-    double f_aa = 0, f_na = 0, f_an = 0;
-    for (int b = b0; b < b1; ++b) {
-      int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      bool keep = B.type[b] != BT_SPLIT;
-      S[b] = keep ? G->mem.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1))
-                  : ws.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1));
-      int i = b - b0;
-      if (cnt(b, TK_AA)) {
-        TAA[i] = ws.get<double>((size_t)k * k);
-        taa.out(TAA[i], k, k, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
-        f_aa += 2.0 * k * k * k * cnt(b, TK_AA);
-      }
-      if (cnt(b, TK_NA) && kt > 0) {
-        TNA[i] = ws.get<double>((size_t)kt * k);
-        tna.out(TNA[i], kt, kt, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
-        f_na += 2.0 * kt * k * k * cnt(b, TK_NA);
-      }
-      if (parent[i] >= 0 && kt > 0) {
-        int pt = B.t[parent[i]], pr = B.s[parent[i]];
-        int kpt = row.Q.rank[pt], kpr = col.Q.rank[pr];
-        Pp[i] = ws.get<double>((size_t)kt * std::max(kpr, 1));
-        g.out(Pp[i], kt, kt, kpr);
-        g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], std::max(kpt, 1), false, kpt);
-      }
+    for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
+      if (B.type[pb] == BT_SPLIT)
+        for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - b0] = pb;
+    std::vector<double*> Pp(b1 - b0, nullptr);
+    for (int b = b0; b < b1; ++b) {  // Pp = E_t S_parent (transfer of the new row basis)
+      const int i = b - b0, t = B.t[b], kt = row.Q.rank[t];
+      if (parent[i] < 0 || kt == 0) continue;
+      const int pt = B.t[parent[i]], pr = B.s[parent[i]];
+      const int kpt = row.Q.rank[pt], kpr = col.Q.rank[pr];
+      if (kpt == 0 || kpr == 0) continue;
+      Pp[i] = ws.get<double>((size_t)kt * kpr);
+      g.out(Pp[i], kt, kt, kpr);
+      g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], kpt, false, kpt);
     }
-    taa.run(ctx, f_aa);
-    tna.run(ctx, f_na);
     g.run(ctx);
-    for (int b = b0; b < b1; ++b) {
-      int i = b - b0, r = B.s[b], kr = col.Q.rank[r];
-      if ((cnt(b, TK_AN) || TAA[i]) && kr > 0) {
-        Mm[i] = ws.get<double>((size_t)k * kr);
-        g.out(Mm[i], k, k, kr);
-        if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
-        if (cnt(b, TK_AN)) {
-          tan_.out(Mm[i], k, k, kr, PT.tri_ptr[b], PT.tri_ptr[b + 1], TAA[i] != nullptr);
-          f_an += 2.0 * k * k * kr * cnt(b, TK_AN);
-        }
-      }
-    }
-    g.run(ctx);  // TAA R^c^* first (overwrites), then the AN triples accumulate
-    tan_.run(ctx, f_an);
-    for (int b = b0; b < b1; ++b) {
-      int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      g.out(S[b], std::max(kt, 1), kt, kr);
-      if (Pp[i]) {
-        int kpr = col.Q.rank[B.s[parent[i]]];
-        g.term(Pp[i], kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
-      }
-      if (TNA[i]) g.term(TNA[i], kt, false, col.RXP[r], std::max(kr, 1), true, k);
-      if (Mm[i]) g.term(row.RXP[t], std::max(kt, 1), false, Mm[i], k, false, k);
-      if (B.type[b] == BT_ADM) C.blk[b] = S[b];
+    for (int b = b0; b < b1; ++b) {  // S_b += Pp F_r^*
+      const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+      if (!Pp[i] || kr == 0) continue;
+      const int kpr = col.Q.rank[B.s[parent[i]]];
+      g.out(S[b], kt, kt, kr, true);
+      g.term(Pp[i], kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
     }
     g.run(ctx);
   }
+  for (int b = 0; b < B.nblocks(); ++b)
+    if (B.type[b] == BT_ADM) C.blk[b] = S[b];
   // dense inadmissible leaves: the nearfield products (already there) plus Q_t S Q^W_r^*
   {
     const int l = T.depth;

@@ -230,6 +230,13 @@ AuxRun::AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f) : AuxRun(c, aux_ctx(c)
 AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), aux(a_) {
   aux->profile = ctx->profile;
   aux->prec = ctx->prec;
+  // the staging of the previous run is free once that run's work is done
+  // (usually long ago): wait for its end event, not for the stream, which is
+  // about to wait for ctx's queue
+  if (aux->drain) {
+    dev_event_sync(aux->drain);
+    aux->stage_used = 0;
+  }
   void* e = pool_event(ctx);
   dev_event_record(e, ctx->stream);
   dev_stream_wait(aux->stream, e);  // the wait takes the event as recorded now
@@ -248,10 +255,9 @@ AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), 
 
 void AuxRun::join() {
   if (th.joinable()) th.join();
-  void* e = pool_event(aux);
-  dev_event_record(e, aux->stream);
-  dev_stream_wait(ctx->stream, e);
-  aux->ev_pool.push_back(e);
+  if (!aux->drain) aux->drain = dev_event_create();
+  dev_event_record(aux->drain, aux->stream);
+  dev_stream_wait(ctx->stream, aux->drain);
   if (err) {
     std::exception_ptr x = err;
     err = nullptr;
@@ -802,6 +808,7 @@ h2_ctx::~h2_ctx() {
     h2::dev_event_destroy(p.b);
   }
   for (void* e : ev_pool) h2::dev_event_destroy(e);
+  h2::dev_event_destroy(drain);
   ws.release();
   for (auto& c : cache) h2::dev_free(c.first);
   cache.clear();
