@@ -76,34 +76,6 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   auto in_adm = [&](int b) { return tag[b] >= 0 && TIK.type[tag[b]] == BT_ADM; };
   const double* om = omega;  // omega + tag[b] is the scale of block b
 
-  // column trees (leaf lists over the view column) of blocks inside admissible leaves of T_IK
-  std::vector<std::vector<ColLeaf>> ctree(nb);
-  for (int l = D; l >= 0; --l)
-    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
-      if (!in_adm(b)) continue;
-      int r = G.vcol(b), t = G.vrow(b);
-      if (B.type[b] != BT_SPLIT) {
-        ctree[b] = {{r, B.type[b] == BT_ADM ? 1 : 0, 0, 0}};
-      } else {
-        std::vector<ColLeaf> all;
-        for (int qc = 1; qc <= 2; ++qc) {
-          int rc = 2 * r + qc;
-          int c1 = G.find(2 * t + 1, rc), c2 = G.find(2 * t + 2, rc);
-          H2_REQUIRE(c1 >= 0 && c2 >= 0, H2_ERR_SHAPE, "product tree: missing child");
-          auto u = leaf_union(T, ctree[c1], ctree[c2]);
-          all.insert(all.end(), u.begin(), u.end());
-        }
-        ctree[b] = all;
-      }
-      int off = 0;
-      for (auto& L : ctree[b]) {
-        L.width = L.adm ? Wb.rank[L.node] : (int)T.size[L.node];
-        L.off = off;
-        off += L.width;
-      }
-    }
-  auto tree_width = [&](int b) { return ctree[b].empty() ? 0 : ctree[b].back().off + ctree[b].back().width; };
-
   // ---- product total weights Z_t, top-down ----
   std::vector<double*> Zt(ncl, nullptr);
   std::vector<int> zr(ncl, 0);
@@ -146,6 +118,35 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
     g.run(ctx);
     ts.run(ctx);
   }
+
+  // column trees (leaf lists over the view column) of blocks inside
+  // admissible leaves of T_IK (host work, while the device forms Z_t)
+  std::vector<std::vector<ColLeaf>> ctree(nb);
+  for (int l = D; l >= 0; --l)
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (!in_adm(b)) continue;
+      int r = G.vcol(b), t = G.vrow(b);
+      if (B.type[b] != BT_SPLIT) {
+        ctree[b] = {{r, B.type[b] == BT_ADM ? 1 : 0, 0, 0}};
+      } else {
+        std::vector<ColLeaf> all;
+        for (int qc = 1; qc <= 2; ++qc) {
+          int rc = 2 * r + qc;
+          int c1 = G.find(2 * t + 1, rc), c2 = G.find(2 * t + 2, rc);
+          H2_REQUIRE(c1 >= 0 && c2 >= 0, H2_ERR_SHAPE, "product tree: missing child");
+          auto u = leaf_union(T, ctree[c1], ctree[c2]);
+          all.insert(all.end(), u.begin(), u.end());
+        }
+        ctree[b] = all;
+      }
+      int off = 0;
+      for (auto& L : ctree[b]) {
+        L.width = L.adm ? Wb.rank[L.node] : (int)T.size[L.node];
+        L.off = off;
+        off += L.width;
+      }
+    }
+  auto tree_width = [&](int b) { return ctree[b].empty() ? 0 : ctree[b].back().off + ctree[b].back().width; };
 
   // ---- transfer chains of the column basis used by match_column ----
   // CH(c, a) = F_c F_{parent(c)} ... : W_a restricted to c equals W_c CH(c, a)
@@ -431,38 +432,53 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
   const BlockTreeH& B = *Gp->c.bt;
   const BlockTreeH& TIK = *Z->c.bt;
   const int nb = B.nblocks();
-  // T_IK leaf containing each block of T^XY (-1: the block is a non-leaf of T_IK)
-  std::vector<int> tag(nb, -1), par(nb, -1);
-  for (int b = 0; b < nb; ++b)
-    if (B.type[b] == BT_SPLIT)
-      for (int q = 0; q < 4; ++q) par[B.child0[b] + q] = b;
-  for (int b = 0; b < nb; ++b) {
-    int f = TIK.find(B.t[b], B.s[b]);
-    if (f >= 0)
-      tag[b] = TIK.type[f] == BT_SPLIT ? -1 : f;
-    else {
-      H2_REQUIRE(par[b] >= 0 && tag[par[b]] >= 0, H2_ERR_NOT_REFINED, "T^XY does not refine T_IK");
-      tag[b] = tag[par[b]];
-    }
-    if (B.type[b] != BT_SPLIT)
+  // T_IK leaf containing each block of T^XY (-1: the block is a non-leaf of
+  // T_IK), by one pass from the root: same[b] is the block of T_IK equal to
+  // b (-1 below a leaf of T_IK); the four children of a subdivided block
+  // are matched among the four children of its T_IK block
+  std::vector<int> tag(nb, -1), same(nb, -1);
+  same[0] = TIK.find(B.t[0], B.s[0]);
+  H2_REQUIRE(same[0] >= 0, H2_ERR_NOT_REFINED, "T^XY does not refine T_IK");
+  for (int b = 0; b < nb; ++b) {  // parents before children
+    const int f = same[b];
+    if (f >= 0) tag[b] = TIK.type[f] == BT_SPLIT ? -1 : f;
+    if (B.type[b] != BT_SPLIT) {
       H2_REQUIRE(tag[b] >= 0, H2_ERR_NOT_REFINED, "T^XY does not refine T_IK");
+      continue;
+    }
+    for (int q = 0; q < 4; ++q) {
+      const int c = B.child0[b] + q;
+      if (f >= 0 && TIK.type[f] == BT_SPLIT) {
+        for (int qq = 0; qq < 4; ++qq) {
+          const int cc = TIK.child0[f] + qq;
+          if (TIK.t[cc] == B.t[c] && TIK.s[cc] == B.s[c]) same[c] = cc;
+        }
+        H2_REQUIRE(same[c] >= 0, H2_ERR_NOT_REFINED, "T^XY does not refine T_IK");
+      } else {
+        tag[c] = tag[b];
+      }
+    }
   }
-  // omega_b = 1/||G|_b||_F over the leaves of T^XY inside admissible b
-  std::vector<std::vector<SumsqItem>> seg(TIK.nblocks());
-  for (int b = 0; b < nb; ++b) {
-    if (B.type[b] == BT_SPLIT || tag[b] < 0 || TIK.type[tag[b]] != BT_ADM || !Gp->c.blk[b]) continue;
-    int rows = B.type[b] == BT_ADM ? Gp->c.V.rank[B.t[b]] : (int)T.size[B.t[b]];
-    int cols = B.type[b] == BT_ADM ? Gp->c.W.rank[B.s[b]] : (int)T.size[B.s[b]];
-    seg[tag[b]].push_back({Gp->c.blk[b], Gp->c.ld_of(b), rows, cols});
-  }
-  std::vector<SumsqItem> items;
-  std::vector<int32_t> sp{0};
-  for (auto& s : seg) {
-    items.insert(items.end(), s.begin(), s.end());
-    sp.push_back((int32_t)items.size());
+  // omega_b = 1/||G|_b||_F over the leaves of T^XY inside admissible b:
+  // the leaves grouped by their T_IK block (counting sort, in block order)
+  auto in_sum = [&](int b) {
+    return B.type[b] != BT_SPLIT && tag[b] >= 0 && TIK.type[tag[b]] == BT_ADM && Gp->c.blk[b];
+  };
+  std::vector<int32_t> sp(TIK.nblocks() + 1, 0);
+  for (int b = 0; b < nb; ++b)
+    if (in_sum(b)) ++sp[tag[b] + 1];
+  for (int i = 0; i < TIK.nblocks(); ++i) sp[i + 1] += sp[i];
+  std::vector<SumsqItem> items(std::max(sp.back(), 1), SumsqItem{nullptr, 1, 0, 0});
+  {
+    std::vector<int32_t> pos(sp.begin(), sp.end() - 1);
+    for (int b = 0; b < nb; ++b) {
+      if (!in_sum(b)) continue;
+      int rows = B.type[b] == BT_ADM ? Gp->c.V.rank[B.t[b]] : (int)T.size[B.t[b]];
+      int cols = B.type[b] == BT_ADM ? Gp->c.W.rank[B.s[b]] : (int)T.size[B.s[b]];
+      items[pos[tag[b]]++] = {Gp->c.blk[b], Gp->c.ld_of(b), rows, cols};
+    }
   }
   double* omega = ctx->ws.get<double>(std::max(TIK.nblocks(), 1));
-  if (items.empty()) items.push_back({nullptr, 1, 0, 0});
   k_sumsq(upload(ctx, items), upload(ctx, sp), TIK.nblocks(), omega, 1, ctx->stream);
 
   View Gr{&Gp->c, false}, Gc{&Gp->c, true};
@@ -492,7 +508,7 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (tag[b] < 0 || TIK.type[tag[b]] != BT_ADM) continue;
       int t = B.t[b], r = B.s[b], kz = QZ.rank[t], kw = QZW.rank[r];
-      bool top = TIK.find(t, r) == tag[b];
+      bool top = same[b] >= 0 && same[b] == tag[b];  // b is the T_IK leaf itself
       L[b] = top ? Z->mem.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1))
                  : ws.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1));
       if (B.type[b] == BT_SPLIT)
@@ -525,10 +541,13 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
     }
     g.run(ctx);
   }
+  std::vector<int> of_tik(TIK.nblocks(), -1);  // the block of T^XY equal to a T_IK block
+  for (int b = 0; b < nb; ++b)
+    if (same[b] >= 0) of_tik[same[b]] = b;
   for (int zb = 0; zb < TIK.nblocks(); ++zb) {
     if (TIK.type[zb] == BT_SPLIT) continue;
     int t = TIK.t[zb], r = TIK.s[zb];
-    int b = B.find(t, r);
+    int b = of_tik[zb];
     H2_REQUIRE(b >= 0, H2_ERR_NOT_REFINED, "leaf of T_IK missing from T^XY");
     if (TIK.type[zb] == BT_ADM) {
       Zc.blk[zb] = L[b];
