@@ -83,6 +83,20 @@ struct GemmTerm {
   int32_t k, flags;
   double alpha;
 };
+// Chained small products C (m x n) = beta C + op(A) B op(D), all dimensions
+// at most 64: op(A) is A (m x p, lda) or A^T (A stored p x m); op(D) is D^T
+// (D stored n x q, ldd) or D (stored q x n); B is p x q (ldb).  One workgroup
+// per item; the middle product op(A) B stays in LDS.
+struct Chain3 {
+  double* C;
+  const double* A;
+  const double* B;
+  const double* D;
+  int64_t ldc, lda, ldb, ldd;
+  int32_t m, n, p, q;
+  int32_t tA, dT, beta, pad;
+};
+constexpr int kChain3Max = 64;
 // Grouped products driven by the product-tree triples: output o (one block of
 // T^XY) = beta C + sum over the triples q in [q0, q1) whose kind equals
 // F.kind of op(F.A[bx_q]) op(F.B[by_q]); the operand tables are indexed by
@@ -169,6 +183,7 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, int prec, void* stream);
 // one workgroup per output of at most 64 x 64 (untransposed operands)
 void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, int prec, void* stream);
+void k_chain3(const Chain3* items, int n, void* stream);
 // Factorization launches: lds_doubles is the dynamic LDS of the launch (a
 // problem whose working set fits it runs in LDS), slot the doubles of global
 // scratch per workgroup for the others (0: none); scratch then holds
@@ -472,6 +487,17 @@ struct GemmBatch {
             const double* scale = nullptr, int scale_mode = 0);  // op(A) * I_k
   void run(h2_ctx* ctx);
   bool empty() const { return outs.empty(); }
+};
+// chained products C = beta C + op(A) B op(D) (one launch)
+struct Chain3Batch {
+  std::vector<Chain3> items;
+  // false when a dimension exceeds kChain3Max (the caller then uses GemmBatch)
+  static bool fits(int m, int n, int p, int q) {
+    return m <= kChain3Max && n <= kChain3Max && p <= kChain3Max && q <= kChain3Max;
+  }
+  void add(double* C, int64_t ldc, int m, int n, const double* A, int64_t lda, bool tA, int p,
+           const double* B, int64_t ldb, int q, const double* D, int64_t ldd, bool dT, bool accumulate);
+  void run(h2_ctx* ctx);
 };
 // outputs of one triple family (one launch)
 struct TriBatch {

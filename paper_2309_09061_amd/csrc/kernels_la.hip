@@ -165,6 +165,63 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
   HIP_OK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// chained small products C = beta C + op(A) B op(D) (FP64 MFMA): one
+// workgroup (4 wavefronts) per item; the 16 x 16 tiles of T = op(A) B are
+// formed into LDS, then those of C from T and op(D)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void chain3_kernel(const Chain3* __restrict__ items) {
+  __shared__ double Ts[kChain3Max * kChain3Max];  // T(i, l) at i + 64 l
+  using M = Mfma16<false>;
+  const Chain3 it = items[blockIdx.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, q4 = lane >> 4;
+  const int mt = (it.m + 15) / 16, qt = (it.q + 15) / 16, nt = (it.n + 15) / 16;
+  for (int tile = wave; tile < mt * qt; tile += 4) {
+    const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
+    const int i = i0 + r, j = j0 + r;
+    typename M::acc_t acc = M::zero();
+    for (int l0 = 0; l0 < it.p; l0 += 4) {
+      const int l = l0 + q4;
+      double a = 0.0, b = 0.0;
+      if (i < it.m && l < it.p) a = it.tA ? it.A[l + (int64_t)i * it.lda] : it.A[i + (int64_t)l * it.lda];
+      if (j < it.q && l < it.p) b = it.B[l + (int64_t)j * it.ldb];
+      acc = M::step(a, b, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ts[i0 + M::row(v, q4) + (j0 + r) * kChain3Max] = acc[v];
+  }
+  __syncthreads();
+  for (int tile = wave; tile < mt * nt; tile += 4) {
+    const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
+    const int i = i0 + r, j = j0 + r;
+    typename M::acc_t acc = M::zero();
+    for (int l0 = 0; l0 < it.q; l0 += 4) {
+      const int l = l0 + q4;
+      double a = 0.0, b = 0.0;
+      if (i < it.m && l < it.q) a = Ts[i + l * kChain3Max];
+      if (j < it.n && l < it.q) b = it.dT ? it.D[j + (int64_t)l * it.ldd] : it.D[l + (int64_t)j * it.ldd];
+      acc = M::step(a, b, acc);
+    }
+    if (j < it.n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ic = i0 + M::row(v, q4);
+        if (ic < it.m) {
+          double* c = it.C + ic + (int64_t)j * it.ldc;
+          *c = it.beta ? *c + acc[v] : acc[v];
+        }
+      }
+    }
+  }
+}
+
+void k_chain3(const Chain3* items, int n, void* stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(chain3_kernel, dim3(n), dim3(256), 0, (hipStream_t)stream, items);
+  HIP_OK(hipGetLastError());
+}
+
 // Dynamic LDS of the factorization kernels.  Each kernel calls its body
 // twice, once on a pointer into this array and once on global scratch, and
 // the bodies are force-inlined: the compiler then sees the address space of

@@ -672,30 +672,40 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   C.V = row.Q;
   C.W = col.Q;
   C.blk.assign(B.nblocks(), nullptr);
+  // S_b += E_t S_parent F_r^* level by level (E, F: transfers of the new
+  // bases); one fused launch per level, two grouped products where a rank
+  // exceeds the fused kernel's 64
+  Chain3Batch ch;
   for (int l = 1; l <= T.depth; ++l) {
     const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
     std::vector<int> parent(b1 - b0, -1);
     for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
       if (B.type[pb] == BT_SPLIT)
         for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - b0] = pb;
-    std::vector<double*> Pp(b1 - b0, nullptr);
-    for (int b = b0; b < b1; ++b) {  // Pp = E_t S_parent (transfer of the new row basis)
-      const int i = b - b0, t = B.t[b], kt = row.Q.rank[t];
-      if (parent[i] < 0 || kt == 0) continue;
+    std::vector<std::pair<int, double*>> wide;  // (block, E_t S_parent) of the two-step path
+    for (int b = b0; b < b1; ++b) {
+      const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+      if (parent[i] < 0 || kt == 0 || kr == 0) continue;
       const int pt = B.t[parent[i]], pr = B.s[parent[i]];
       const int kpt = row.Q.rank[pt], kpr = col.Q.rank[pr];
       if (kpt == 0 || kpr == 0) continue;
-      Pp[i] = ws.get<double>((size_t)kt * kpr);
-      g.out(Pp[i], kt, kt, kpr);
+      if (Chain3Batch::fits(kt, kr, kpt, kpr)) {
+        ch.add(S[b], kt, kt, kr, row.Q.tr[t], row.Q.tr_ld[t], false, kpt, S[parent[i]], kpt, kpr, col.Q.tr[r],
+               col.Q.tr_ld[r], true, true);
+        continue;
+      }
+      double* Pp = ws.get<double>((size_t)kt * kpr);
+      g.out(Pp, kt, kt, kpr);
       g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], kpt, false, kpt);
+      wide.push_back({b, Pp});
     }
+    ch.run(ctx);
     g.run(ctx);
-    for (int b = b0; b < b1; ++b) {  // S_b += Pp F_r^*
-      const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      if (!Pp[i] || kr == 0) continue;
-      const int kpr = col.Q.rank[B.s[parent[i]]];
+    for (auto [b, Pp] : wide) {
+      const int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+      const int kpr = col.Q.rank[B.s[parent[b - b0]]];
       g.out(S[b], kt, kt, kr, true);
-      g.term(Pp[i], kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
+      g.term(Pp, kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
     }
     g.run(ctx);
   }
@@ -704,27 +714,35 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   // dense inadmissible leaves: the nearfield products (already there) plus Q_t S Q^W_r^*
   {
     const int l = T.depth;
-    std::vector<double*> QS(B.nblocks(), nullptr);
+    std::vector<std::pair<int, double*>> wide;  // (block, Q_t S) of the two-step path
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (B.type[b] != BT_INADM) continue;
       int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      if (kt == 0 || kr == 0) continue;
-      QS[b] = ws.get<double>((size_t)T.size[t] * kr);
-      g.out(QS[b], T.size[t], (int)T.size[t], kr);
-      g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], std::max(kt, 1), false, kt);
-    }
-    g.run(ctx);
-    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
-      if (B.type[b] != BT_INADM) continue;
-      int t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
       const auto& dl = dn_of[t];
       auto it = std::lower_bound(dl.begin(), dl.end(), std::make_pair(r, (double*)nullptr));
       H2_REQUIRE(it != dl.end() && it->first == r, H2_ERR_SHAPE, "dense leaf of T^XY without nearfield triple");
       double* Dn = it->second;
       C.blk[b] = Dn;
-      if (!QS[b]) continue;
-      g.out(Dn, T.size[t], (int)T.size[t], (int)T.size[r], true);
-      g.term(QS[b], T.size[t], false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
+      if (kt == 0 || kr == 0) continue;
+      const int mt = (int)T.size[t], nr = (int)T.size[r];
+      if (Chain3Batch::fits(mt, nr, kt, kr)) {
+        ch.add(Dn, mt, mt, nr, row.Q.leaf[t], row.Q.leaf_ld[t], false, kt, S[b], kt, kr, col.Q.leaf[r],
+               col.Q.leaf_ld[r], true, true);
+        continue;
+      }
+      double* QS = ws.get<double>((size_t)mt * kr);
+      g.out(QS, mt, mt, kr);
+      g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], kt, false, kt);
+      wide.push_back({b, QS});
+    }
+    ch.run(ctx);
+    g.run(ctx);
+    for (auto [b, QS] : wide) {
+      const int t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
+      const int mt = (int)T.size[t], nr = (int)T.size[r];
+      double* Dn = C.blk[b];
+      g.out(Dn, mt, mt, nr, true);
+      g.term(QS, mt, false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
     }
     g.run(ctx);
   }

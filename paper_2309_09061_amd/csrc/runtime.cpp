@@ -408,6 +408,44 @@ void GemmBatch::run(h2_ctx* ctx) {
   terms.clear();
 }
 
+void Chain3Batch::add(double* C, int64_t ldc, int m, int n, const double* A, int64_t lda, bool tA, int p,
+                      const double* B, int64_t ldb, int q, const double* D, int64_t ldd, bool dT,
+                      bool accumulate) {
+  H2_REQUIRE(fits(m, n, p, q), H2_ERR_ARG, "chained product: dimension over 64");
+  if (m <= 0 || n <= 0) return;
+  if ((p <= 0 || q <= 0) && accumulate) return;  // adds nothing
+  Chain3 c{};
+  c.C = C;
+  c.ldc = std::max<int64_t>(ldc, 1);
+  c.m = m;
+  c.n = n;
+  c.A = A;
+  c.lda = std::max<int64_t>(lda, 1);
+  c.tA = tA ? 1 : 0;
+  c.p = std::max(p, 0);
+  c.B = B;
+  c.ldb = std::max<int64_t>(ldb, 1);
+  c.q = std::max(q, 0);
+  c.D = D;
+  c.ldd = std::max<int64_t>(ldd, 1);
+  c.dT = dT ? 1 : 0;
+  c.beta = accumulate ? 1 : 0;
+  items.push_back(c);
+}
+
+void Chain3Batch::run(h2_ctx* ctx) {
+  if (items.empty()) return;
+  double flops = 0, bytes = 0;
+  for (const Chain3& c : items) {
+    flops += 2.0 * c.m * c.p * c.q + 2.0 * c.m * c.q * c.n;
+    bytes += 8.0 * ((double)c.m * c.p + (double)c.p * c.q + (double)c.n * c.q + (double)c.m * c.n * (c.beta ? 2 : 1));
+  }
+  Chain3* d = upload_launch(ctx, items);
+  LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
+  k_chain3(d, (int)items.size(), ctx->stream);
+  items.clear();
+}
+
 void TriBatch::out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate) {
   if (m <= 0 || n <= 0) return;
   TriOut o{};
