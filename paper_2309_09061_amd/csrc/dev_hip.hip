@@ -63,6 +63,20 @@ __global__ void pull_kernel(uint4* __restrict__ dst, const uint4* __restrict__ s
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// The reverse direction for a few values: a kernel writes them into the
+// device view of pinned host memory (visible to the host after the stream
+// is synchronised).
+__global__ void push_i32_kernel(int32_t* __restrict__ dst_view, const int32_t* __restrict__ src, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst_view[i] = src[i];
+}
+
+void dev_push_i32(int32_t* dst_view, const int32_t* src, int n, void* stream) {
+  if (n <= 0) return;
+  const int blocks = std::min((n + 255) / 256, 64);
+  hipLaunchKernelGGL(push_i32_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, dst_view, src, n);
+  HIP_OK(hipGetLastError());
+}
+
 void dev_pull(void* dst, const void* src_view, size_t bytes, void* stream) {
   const size_t n = (bytes + 15) / 16;
   if (n == 0) return;

@@ -48,6 +48,8 @@ void* dev_host_view(void* host);      // device address of pinned host memory, o
 // copy from pinned host memory (its device view) with a kernel on `stream`;
 // both buffers hold bytes rounded up to 256
 void dev_pull(void* dst, const void* src_view, size_t bytes, void* stream);
+// n ints from device memory into the device view of pinned host memory (a kernel)
+void dev_push_i32(int32_t* dst_view, const int32_t* src, int n, void* stream);
 void dev_h2d(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2d(void* dst, const void* src, size_t bytes, void* stream);
@@ -426,6 +428,9 @@ T* upload_launch(h2_ctx* ctx, const std::vector<T>& v) {
   if (v.empty()) return nullptr;
   return (T*)upload_launch_bytes(ctx, v.data(), v.size() * sizeof(T));
 }
+// asynchronous copy of n device ints into pinned staging; the host pointer
+// holds them after the next ctx_sync and until the next staging allocation
+const int32_t* read_back(h2_ctx* ctx, const int32_t* dev, int n);
 void ctx_sync(h2_ctx* ctx);
 
 // launch timing (when bit `kind` of ctx->profile is set): events around one launch

@@ -366,9 +366,9 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
     }
     ts.run(ctx);
     jb.run(ctx);
-    std::vector<int32_t> kk(2 * nc);
-    dev_d2h(kk.data(), rk, sizeof(int32_t) * 2 * nc, ctx->stream);
+    const int32_t* kkh = read_back(ctx, rk, 2 * nc);
     ctx_sync(ctx);
+    const std::vector<int32_t> kk(kkh, kkh + 2 * nc);
     // (e) Q_t = Q_X [I 0; 0 U2(:, 1:k2)], transfers, A_{t,s} = Q_t^* (...),
     //     [R_X; 0] with R_X = (R_Y V'^*)(1:k1, :)
     std::vector<double*> Qn(nc);

@@ -119,109 +119,113 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
     ts.run(ctx);
   }
 
-  // column trees (leaf lists over the view column) of blocks inside
-  // admissible leaves of T_IK (host work, while the device forms Z_t)
+  // Column trees (leaf lists over the view column) of blocks inside
+  // admissible leaves of T_IK, the transfer chains of the column basis used
+  // by match_column and W_a restricted to leaves: host work and a few small
+  // products, done while the device factorizes the leaf level
   std::vector<std::vector<ColLeaf>> ctree(nb);
-  for (int l = D; l >= 0; --l)
-    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
-      if (!in_adm(b)) continue;
-      int r = G.vcol(b), t = G.vrow(b);
-      if (B.type[b] != BT_SPLIT) {
-        ctree[b] = {{r, B.type[b] == BT_ADM ? 1 : 0, 0, 0}};
-      } else {
-        std::vector<ColLeaf> all;
-        for (int qc = 1; qc <= 2; ++qc) {
-          int rc = 2 * r + qc;
-          int c1 = G.find(2 * t + 1, rc), c2 = G.find(2 * t + 2, rc);
-          H2_REQUIRE(c1 >= 0 && c2 >= 0, H2_ERR_SHAPE, "product tree: missing child");
-          auto u = leaf_union(T, ctree[c1], ctree[c2]);
-          all.insert(all.end(), u.begin(), u.end());
-        }
-        ctree[b] = all;
-      }
-      int off = 0;
-      for (auto& L : ctree[b]) {
-        L.width = L.adm ? Wb.rank[L.node] : (int)T.size[L.node];
-        L.off = off;
-        off += L.width;
-      }
-    }
   auto tree_width = [&](int b) { return ctree[b].empty() ? 0 : ctree[b].back().off + ctree[b].back().width; };
-
-  // ---- transfer chains of the column basis used by match_column ----
-  // CH(c, a) = F_c F_{parent(c)} ... : W_a restricted to c equals W_c CH(c, a)
   std::map<int64_t, std::pair<const double*, int64_t>> chain;
   auto key = [&](int c, int a) { return (int64_t)c * ncl + a; };
   std::function<void(int, int)> need;
   std::vector<std::vector<std::pair<int, int>>> by_dist(D + 2);
-  need = [&](int c, int a) {
-    if (chain.count(key(c, a))) return;
-    int p = TreeH::parent(c);
-    if (p == a) {
-      chain[key(c, a)] = {Wb.tr[c], Wb.tr_ld[c]};
-      return;
-    }
-    need(p, a);
-    chain[key(c, a)] = {nullptr, 0};
-    by_dist[TreeH::level(c) - TreeH::level(a)].push_back({c, a});
-  };
-  auto contains = [&](int a, int c) {  // cluster a contains cluster c
-    return T.off[a] <= T.off[c] && T.off[c] + T.size[c] <= T.off[a] + T.size[a] && TreeH::level(a) <= TreeH::level(c);
-  };
   struct Piece {
     int blk, tc, src, srcoff, srcld, snode, sadm, tnode, tadm, twidth, toff, roff;
   };
   std::vector<std::vector<Piece>> pieces(D + 1);
-  for (int l = 0; l < D; ++l)
-    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
-      if (B.type[b] != BT_SPLIT || !in_adm(b)) continue;
-      int t = G.vrow(b), r = G.vcol(b);
-      for (const ColLeaf& L : ctree[b]) {
-        int rc = contains(2 * r + 1, L.node) ? 2 * r + 1 : 2 * r + 2;
-        for (int qt = 1; qt <= 2; ++qt) {
-          int tc = 2 * t + qt;
-          int c = G.find(tc, rc);
-          const ColLeaf* S = nullptr;
-          for (const ColLeaf& M : ctree[c])
-            if (contains(M.node, L.node)) S = &M;
-          H2_REQUIRE(S, H2_ERR_SHAPE, "match_column: no source leaf");
-          H2_REQUIRE(S->adm || S->node == L.node, H2_ERR_UNSUPPORTED,
-                     "match_column: inadmissible column leaf refined");
-          pieces[l].push_back({b, tc, c, S->off, 0, S->node, S->adm, L.node, L.adm, L.width, L.off, qt});
-          if (S->adm && S->node != L.node) need(L.node, S->node);
+  std::map<int64_t, std::pair<const double*, int64_t>> wrest;
+  auto build_columns = [&]() {
+    for (int l = D; l >= 0; --l)
+      for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+        if (!in_adm(b)) continue;
+        int r = G.vcol(b), t = G.vrow(b);
+        if (B.type[b] != BT_SPLIT) {
+          ctree[b] = {{r, B.type[b] == BT_ADM ? 1 : 0, 0, 0}};
+        } else {
+          std::vector<ColLeaf> all;
+          for (int qc = 1; qc <= 2; ++qc) {
+            int rc = 2 * r + qc;
+            int c1 = G.find(2 * t + 1, rc), c2 = G.find(2 * t + 2, rc);
+            H2_REQUIRE(c1 >= 0 && c2 >= 0, H2_ERR_SHAPE, "product tree: missing child");
+            auto u = leaf_union(T, ctree[c1], ctree[c2]);
+            all.insert(all.end(), u.begin(), u.end());
+          }
+          ctree[b] = all;
+        }
+        int off = 0;
+        for (auto& L : ctree[b]) {
+          L.width = L.adm ? Wb.rank[L.node] : (int)T.size[L.node];
+          L.off = off;
+          off += L.width;
         }
       }
-    }
-  for (int d = 2; d <= D + 1; ++d) {
-    if (d >= (int)by_dist.size() || by_dist[d].empty()) continue;
-    for (auto [c, a] : by_dist[d]) {
+
+    // ---- transfer chains of the column basis used by match_column ----
+    // CH(c, a) = F_c F_{parent(c)} ... : W_a restricted to c equals W_c CH(c, a)
+    need = [&](int c, int a) {
+      if (chain.count(key(c, a))) return;
       int p = TreeH::parent(c);
-      auto pr = chain[key(p, a)];
-      double* M = ws.get<double>((size_t)std::max(Wb.rank[c], 1) * std::max(Wb.rank[a], 1));
-      g.out(M, std::max(Wb.rank[c], 1), Wb.rank[c], Wb.rank[a]);
-      g.term(Wb.tr[c], Wb.tr_ld[c], false, pr.first, pr.second, false, Wb.rank[p]);
-      chain[key(c, a)] = {M, std::max(Wb.rank[c], 1)};
-    }
-    g.run(ctx);
-  }
-  // W_{a} restricted to the leaf c: Q^W_c CH(c, a)
-  std::map<int64_t, std::pair<const double*, int64_t>> wrest;
-  for (int l = 0; l < D; ++l)
-    for (const Piece& P : pieces[l]) {
-      if (!P.sadm || P.tadm) continue;
-      int64_t kk = key(P.tnode, P.snode);
-      if (wrest.count(kk)) continue;
-      if (P.tnode == P.snode) {
-        wrest[kk] = {Wb.leaf[P.tnode], Wb.leaf_ld[P.tnode]};
-        continue;
+      if (p == a) {
+        chain[key(c, a)] = {Wb.tr[c], Wb.tr_ld[c]};
+        return;
       }
-      auto ch = chain[key(P.tnode, P.snode)];
-      double* M = ws.get<double>((size_t)T.size[P.tnode] * std::max(Wb.rank[P.snode], 1));
-      g.out(M, T.size[P.tnode], (int)T.size[P.tnode], Wb.rank[P.snode]);
-      g.term(Wb.leaf[P.tnode], Wb.leaf_ld[P.tnode], false, ch.first, ch.second, false, Wb.rank[P.tnode]);
-      wrest[kk] = {M, T.size[P.tnode]};
+      need(p, a);
+      chain[key(c, a)] = {nullptr, 0};
+      by_dist[TreeH::level(c) - TreeH::level(a)].push_back({c, a});
+    };
+    auto contains = [&](int a, int c) {  // cluster a contains cluster c
+      return T.off[a] <= T.off[c] && T.off[c] + T.size[c] <= T.off[a] + T.size[a] && TreeH::level(a) <= TreeH::level(c);
+    };
+    for (int l = 0; l < D; ++l)
+      for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+        if (B.type[b] != BT_SPLIT || !in_adm(b)) continue;
+        int t = G.vrow(b), r = G.vcol(b);
+        for (const ColLeaf& L : ctree[b]) {
+          int rc = contains(2 * r + 1, L.node) ? 2 * r + 1 : 2 * r + 2;
+          for (int qt = 1; qt <= 2; ++qt) {
+            int tc = 2 * t + qt;
+            int c = G.find(tc, rc);
+            const ColLeaf* S = nullptr;
+            for (const ColLeaf& M : ctree[c])
+              if (contains(M.node, L.node)) S = &M;
+            H2_REQUIRE(S, H2_ERR_SHAPE, "match_column: no source leaf");
+            H2_REQUIRE(S->adm || S->node == L.node, H2_ERR_UNSUPPORTED,
+                       "match_column: inadmissible column leaf refined");
+            pieces[l].push_back({b, tc, c, S->off, 0, S->node, S->adm, L.node, L.adm, L.width, L.off, qt});
+            if (S->adm && S->node != L.node) need(L.node, S->node);
+          }
+        }
+      }
+    for (int d = 2; d <= D + 1; ++d) {
+      if (d >= (int)by_dist.size() || by_dist[d].empty()) continue;
+      for (auto [c, a] : by_dist[d]) {
+        int p = TreeH::parent(c);
+        auto pr = chain[key(p, a)];
+        double* M = ws.get<double>((size_t)std::max(Wb.rank[c], 1) * std::max(Wb.rank[a], 1));
+        g.out(M, std::max(Wb.rank[c], 1), Wb.rank[c], Wb.rank[a]);
+        g.term(Wb.tr[c], Wb.tr_ld[c], false, pr.first, pr.second, false, Wb.rank[p]);
+        chain[key(c, a)] = {M, std::max(Wb.rank[c], 1)};
+      }
+      g.run(ctx);
     }
-  g.run(ctx);
+    // W_{a} restricted to the leaf c: Q^W_c CH(c, a)
+    for (int l = 0; l < D; ++l)
+      for (const Piece& P : pieces[l]) {
+        if (!P.sadm || P.tadm) continue;
+        int64_t kk = key(P.tnode, P.snode);
+        if (wrest.count(kk)) continue;
+        if (P.tnode == P.snode) {
+          wrest[kk] = {Wb.leaf[P.tnode], Wb.leaf_ld[P.tnode]};
+          continue;
+        }
+        auto ch = chain[key(P.tnode, P.snode)];
+        double* M = ws.get<double>((size_t)T.size[P.tnode] * std::max(Wb.rank[P.snode], 1));
+        g.out(M, T.size[P.tnode], (int)T.size[P.tnode], Wb.rank[P.snode]);
+        g.term(Wb.leaf[P.tnode], Wb.leaf_ld[P.tnode], false, ch.first, ch.second, false, Wb.rank[P.tnode]);
+        wrest[kk] = {M, T.size[P.tnode]};
+      }
+    g.run(ctx);
+  };
 
   // ---- Figure "basis", bottom-up ----
   out.Q.resize(ncl);
@@ -350,9 +354,10 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
     }
     ts.run(ctx);
     jb.run(ctx);
-    std::vector<int32_t> kz(nc);
-    dev_d2h(kz.data(), rk, sizeof(int32_t) * nc, ctx->stream);
+    const int32_t* kzh = read_back(ctx, rk, nc);
+    if (leaf) build_columns();
     ctx_sync(ctx);
+    const std::vector<int32_t> kz(kzh, kzh + nc);
     // new basis, R_t, A_{t,r}
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, kt = Vb.rank[t], k = kz[i];

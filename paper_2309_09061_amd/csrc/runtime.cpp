@@ -121,6 +121,15 @@ void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes) {
   return stage_upload(ctx, h, bytes);
 }
 
+const int32_t* read_back(h2_ctx* ctx, const int32_t* dev, int n) {
+  int32_t* h = (int32_t*)stage_alloc(ctx, sizeof(int32_t) * std::max(n, 1));
+  if (ctx->stage_dev)
+    dev_push_i32((int32_t*)(ctx->stage_dev + ((char*)h - ctx->stage)), dev, n, ctx->stream);
+  else
+    dev_d2h(h, dev, sizeof(int32_t) * n, ctx->stream);
+  return h;
+}
+
 void ctx_sync(h2_ctx* ctx) {
   dev_sync(ctx->stream);
   ctx->stage_used = 0;
