@@ -538,6 +538,68 @@ __device__ __forceinline__ void apply_cols(const ApplyProb& P, const double* V, 
   }
 }
 
+// The same with each column held in registers (EPL = ceil(m / 64) elements
+// per lane) across all reflectors: one read and one write of C per column.
+template <int EPL>
+__device__ __forceinline__ void apply_cols_reg(const ApplyProb& P, const double* V, int64_t ldv,
+                                               const double* tau_s, int c0) {
+  const int m = P.m, r = P.nrefl, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cend = min(P.ncols, c0 + 64);
+  for (int c = c0 + wave; c < cend; c += 4) {
+    double* C = P.C + (int64_t)c * P.ldc;
+    double x[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int i = lane + 64 * e;
+      x[e] = i < m ? C[i] : 0.0;
+    }
+    for (int s = 0; s < r; ++s) {
+      const int jj = P.trans ? s : r - 1 - s;
+      const double t = tau_s[jj];
+      if (t == 0.0) continue;
+      const double* v = V + jj * ldv;
+      double ve[EPL];
+      double d = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int i = lane + 64 * e;
+        ve[e] = (i < jj || i >= m) ? 0.0 : (i == jj ? 1.0 : v[i]);
+        d += ve[e] * x[e];
+      }
+      d = wave_sum(d) * t;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) x[e] -= d * ve[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const int i = lane + 64 * e;
+      if (i < m) C[i] = x[e];
+    }
+  }
+}
+
+template <int EPL>
+__device__ __forceinline__ void apply_dispatch(const ApplyProb& P, const double* V, int64_t ldv,
+                                               const double* tau_s, int c0) {
+  if constexpr (EPL == 0)
+    apply_cols(P, V, ldv, tau_s, c0);
+  else
+    apply_cols_reg<EPL>(P, V, ldv, tau_s, c0);
+}
+
+template <int EPL>
+__device__ __forceinline__ void apply_body(const ApplyProb& P, int c0, int lds_cap, const double* tau_s) {
+  const int m = P.m, r = P.nrefl;
+  if ((int64_t)m * r <= lds_cap) {
+    for (int64_t e = threadIdx.x; e < (int64_t)m * r; e += 256) lds_dyn[e] = P.V[(e % m) + (e / m) * P.ldv];
+    __syncthreads();
+    apply_dispatch<EPL>(P, lds_dyn, m, tau_s, c0);
+  } else {
+    __syncthreads();
+    apply_dispatch<EPL>(P, P.V, P.ldv, tau_s, c0);
+  }
+}
+
 // work item = (problem, first column); 64 columns per item
 __global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict__ probs,
                                                     const int32_t* __restrict__ work, int lds_cap) {
@@ -546,14 +608,16 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyProb* __restrict_
   const int c0 = work[2 * blockIdx.x + 1];
   const int m = P.m, r = P.nrefl, tid = threadIdx.x;
   for (int e = tid; e < r; e += 256) tau_s[e] = P.tau[e];
-  if ((int64_t)m * r <= lds_cap) {
-    for (int64_t e = tid; e < (int64_t)m * r; e += 256) lds_dyn[e] = P.V[(e % m) + (e / m) * P.ldv];
-    __syncthreads();
-    apply_cols(P, lds_dyn, m, tau_s, c0);
-  } else {
-    __syncthreads();
-    apply_cols(P, P.V, P.ldv, tau_s, c0);
-  }
+  if (m <= 64)
+    apply_body<1>(P, c0, lds_cap, tau_s);
+  else if (m <= 128)
+    apply_body<2>(P, c0, lds_cap, tau_s);
+  else if (m <= 256)
+    apply_body<4>(P, c0, lds_cap, tau_s);
+  else if (m <= 512)
+    apply_body<8>(P, c0, lds_cap, tau_s);
+  else
+    apply_body<0>(P, c0, lds_cap, tau_s);
 }
 
 void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_doubles, void* stream) {
