@@ -547,10 +547,15 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     // N_X N_Y over the leaf size of the middle cluster
     tnn.fam = family((const int32_t*)upload(a, nn.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : nn), d_tX, d_lX,
                      d_tY, d_lY, TK_NN, false, upload(a, sizes));
-    tnn.run(a, f_nn);
     sym.join();
     if (sym_err) std::rethrow_exception(sym_err);
     const int32_t* d_tri = (const int32_t*)upload(a, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
+    // The dense products fill the whole device; launched while the passes
+    // still factorize the wide lower levels they would hold those launches
+    // back.  They start once both passes are three levels from the leaves,
+    // where the passes' launches leave most compute units idle.
+    H2_REQUIRE(sig.wait(std::max(0, T.depth - 3)), H2_ERR_DEVICE, "phase 1: a basis pass stopped early");
+    tnn.run(a, f_nn);
     step_end(a, 1);
 
     // ---- G, the part of each level that needs the bases of that level only ----
