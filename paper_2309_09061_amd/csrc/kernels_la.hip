@@ -1061,13 +1061,19 @@ __device__ __forceinline__ bool jacobi_pair(double* ga_, double* gb_, double* ua
   be = group_sum(be, gsz);
   ga = group_sum(ga, gsz);
   if (!(live && al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be))) return false;
-  // tangent of the rotation angle, the smaller root of t^2 + 2 zeta t - 1 = 0
-  // with zeta = d / q: t = sign(d) q / (|d| + sqrt(d^2 + q^2))
+  // The rotation by the smaller angle theta, tan(2 theta) = q / d with
+  // d = beta - alpha, q = 2 gamma (tan theta = sign(d) q / (|d| + sqrt(d^2 +
+  // q^2))), from the half-angle formulas with two reciprocal square roots and
+  // no division: cos 2theta = |d| / r, sin 2theta = sign(d) q / r with
+  // r = sqrt(d^2 + q^2), c^2 = (1 + cos 2theta) / 2 >= 1/2 and
+  // s = sin 2theta / (2 c).  This shortens the dependent chain of each round.
   const double d = be - al, qq = 2.0 * ga;
-  const double rr = sqrt(d * d + qq * qq);
-  if (!(rr > 0.0)) return false;
-  const double t = (d >= 0.0 ? qq : -qq) / (fabs(d) + rr);
-  const double c = rsqrt(1.0 + t * t), s = c * t;
+  const double r2 = d * d + qq * qq;
+  if (!(r2 > 0.0)) return false;
+  const double ir = rsqrt(r2);
+  const double h = 0.5 + 0.5 * (fabs(d) * ir);  // c^2
+  const double ic = rsqrt(h);                    // 1 / c
+  const double c = h * ic, s = 0.5 * ((d >= 0.0 ? qq : -qq) * ir) * ic;
 #pragma unroll
   for (int k = 0; k < EPL; ++k) {
     ga_[gl + k * gsz] = c * x[k] - s * y[k];
