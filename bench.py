@@ -48,7 +48,7 @@ def cpu_baseline(seconds_budget: float = 30.0):
                       f"scaled by n={w.n}/{n_s} (linear complexity)"}
 
 
-FAMILY_KERNELS = {"gemm_sum": ("gemm_sum_kernel", "gemm_tri_kernel", "gemm_tri_block_kernel"),
+FAMILY_KERNELS = {"gemm_sum": ("gemm_sum_kernel", "gemm_tri_kernel", "gemm_tri_block_kernel", "chain3_kernel"),
                   "tsqr": ("tsqr_rb_kernel", "tsqr_kernel"),
                   "jacobi": ("jacobi_kernel", "jacobi_small_kernel")}
 

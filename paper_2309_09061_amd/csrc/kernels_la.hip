@@ -173,21 +173,31 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 __global__ __launch_bounds__(256) void chain3_kernel(const Chain3* __restrict__ items) {
   __shared__ double Ts[kChain3Max * kChain3Max];  // T(i, l) at i + 64 l
   using M = Mfma16<false>;
+  constexpr int KS = kChain3Max / 4;  // MFMA k-steps at most
   const Chain3 it = items[blockIdx.x];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, q4 = lane >> 4;
   const int mt = (it.m + 15) / 16, qt = (it.q + 15) / 16, nt = (it.n + 15) / 16;
+  // each wavefront loads all operand fragments of a tile before its MFMA
+  // steps, so the global loads of a tile overlap instead of forming a chain
   for (int tile = wave; tile < mt * qt; tile += 4) {
     const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
     const int i = i0 + r, j = j0 + r;
-    typename M::acc_t acc = M::zero();
-    for (int l0 = 0; l0 < it.p; l0 += 4) {
-      const int l = l0 + q4;
-      double a = 0.0, b = 0.0;
-      if (i < it.m && l < it.p) a = it.tA ? it.A[l + (int64_t)i * it.lda] : it.A[i + (int64_t)l * it.lda];
-      if (j < it.q && l < it.p) b = it.B[l + (int64_t)j * it.ldb];
-      acc = M::step(a, b, acc);
+    double a[KS], b[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int l = 4 * ks + q4;
+      a[ks] = 0.0;
+      b[ks] = 0.0;
+      if (l < it.p) {
+        if (i < it.m) a[ks] = it.tA ? it.A[l + (int64_t)i * it.lda] : it.A[i + (int64_t)l * it.lda];
+        if (j < it.q) b[ks] = it.B[l + (int64_t)j * it.ldb];
+      }
     }
+    typename M::acc_t acc = M::zero();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      if (4 * ks < it.p) acc = M::step(a[ks], b[ks], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) Ts[i0 + M::row(v, q4) + (j0 + r) * kChain3Max] = acc[v];
   }
@@ -195,14 +205,21 @@ __global__ __launch_bounds__(256) void chain3_kernel(const Chain3* __restrict__ 
   for (int tile = wave; tile < mt * nt; tile += 4) {
     const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
     const int i = i0 + r, j = j0 + r;
-    typename M::acc_t acc = M::zero();
-    for (int l0 = 0; l0 < it.q; l0 += 4) {
-      const int l = l0 + q4;
-      double a = 0.0, b = 0.0;
-      if (i < it.m && l < it.q) a = Ts[i + l * kChain3Max];
-      if (j < it.n && l < it.q) b = it.dT ? it.D[j + (int64_t)l * it.ldd] : it.D[l + (int64_t)j * it.ldd];
-      acc = M::step(a, b, acc);
+    double a[KS], b[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int l = 4 * ks + q4;
+      a[ks] = 0.0;
+      b[ks] = 0.0;
+      if (l < it.q) {
+        if (i < it.m) a[ks] = Ts[i + l * kChain3Max];
+        if (j < it.n) b[ks] = it.dT ? it.D[j + (int64_t)l * it.ldd] : it.D[l + (int64_t)j * it.ldd];
+      }
     }
+    typename M::acc_t acc = M::zero();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      if (4 * ks < it.q) acc = M::step(a[ks], b[ks], acc);
     if (j < it.n) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
