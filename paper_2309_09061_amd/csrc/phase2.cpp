@@ -14,9 +14,11 @@
 // Every block is scaled by omega_b = 1/||G|_b||_F of the admissible leaf b
 // of T_IK containing it.  Z's couplings Q^Z_t^* G|_b Q^ZW_r are accumulated
 // bottom-up over the blocks of T^XY inside b; Z's nearfield copies G.
+#include <algorithm>
 #include <cmath>
 #include <functional>
 #include <map>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -125,15 +127,16 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   // products, done while the device factorizes the leaf level
   std::vector<std::vector<ColLeaf>> ctree(nb);
   auto tree_width = [&](int b) { return ctree[b].empty() ? 0 : ctree[b].back().off + ctree[b].back().width; };
-  std::map<int64_t, std::pair<const double*, int64_t>> chain;
+  std::unordered_map<int64_t, std::pair<const double*, int64_t>> chain;
   auto key = [&](int c, int a) { return (int64_t)c * ncl + a; };
   std::function<void(int, int)> need;
   std::vector<std::vector<std::pair<int, int>>> by_dist(D + 2);
   struct Piece {
     int blk, tc, src, srcoff, srcld, snode, sadm, tnode, tadm, twidth, toff, roff;
+    int rowpos;  // position of blk in the block list of its row
   };
   std::vector<std::vector<Piece>> pieces(D + 1);
-  std::map<int64_t, std::pair<const double*, int64_t>> wrest;
+  std::unordered_map<int64_t, std::pair<const double*, int64_t>> wrest;
   auto build_columns = [&]() {
     for (int l = D; l >= 0; --l)
       for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
@@ -150,7 +153,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
             auto u = leaf_union(T, ctree[c1], ctree[c2]);
             all.insert(all.end(), u.begin(), u.end());
           }
-          ctree[b] = all;
+          ctree[b] = std::move(all);
         }
         int off = 0;
         for (auto& L : ctree[b]) {
@@ -180,18 +183,34 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
         if (B.type[b] != BT_SPLIT || !in_adm(b)) continue;
         int t = G.vrow(b), r = G.vcol(b);
+        int rowpos = 0;
+        {
+          const int32_t* bl;
+          int cnt;
+          G.row_blocks(t, bl, cnt);
+          while (rowpos < cnt && bl[rowpos] != b) ++rowpos;
+        }
         for (const ColLeaf& L : ctree[b]) {
           int rc = contains(2 * r + 1, L.node) ? 2 * r + 1 : 2 * r + 2;
           for (int qt = 1; qt <= 2; ++qt) {
             int tc = 2 * t + qt;
             int c = G.find(tc, rc);
+            // the last leaf of c's column tree containing L; the list is
+            // ordered by position, so no leaf after the last one starting at
+            // or before L can contain it (the backward scan only moves past
+            // empty clusters)
+            const std::vector<ColLeaf>& cl = ctree[c];
+            auto it = std::upper_bound(cl.begin(), cl.end(), T.off[L.node],
+                                       [&](int64_t o, const ColLeaf& M) { return o < T.off[M.node]; });
             const ColLeaf* S = nullptr;
-            for (const ColLeaf& M : ctree[c])
-              if (contains(M.node, L.node)) S = &M;
+            while (it != cl.begin() && !S) {
+              --it;
+              if (contains(it->node, L.node)) S = &*it;
+            }
             H2_REQUIRE(S, H2_ERR_SHAPE, "match_column: no source leaf");
             H2_REQUIRE(S->adm || S->node == L.node, H2_ERR_UNSUPPORTED,
                        "match_column: inadmissible column leaf refined");
-            pieces[l].push_back({b, tc, c, S->off, 0, S->node, S->adm, L.node, L.adm, L.width, L.off, qt});
+            pieces[l].push_back({b, tc, c, S->off, 0, S->node, S->adm, L.node, L.adm, L.width, L.off, qt, rowpos});
             if (S->adm && S->node != L.node) need(L.node, S->node);
           }
         }
@@ -305,15 +324,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         int kc = out.Q.rank[P.tc];
         if (kc == 0) continue;
         int ro = P.roff == 1 ? 0 : out.Q.rank[2 * t + 1];
-        int q;
-        {
-          const int32_t* bl;
-          int cnt;
-          G.row_blocks(t, bl, cnt);
-          for (q = 0; q < cnt && bl[q] != P.blk; ++q) {
-          }
-        }
-        double* dst = C[i] + ro + (size_t)(cols_of[i][q] + P.toff) * m[i];
+        double* dst = C[i] + ro + (size_t)(cols_of[i][P.rowpos] + P.toff) * m[i];
         const double* src;
         int64_t sld = std::max(kc, 1);
         if (B.type[P.src] == BT_ADM)
