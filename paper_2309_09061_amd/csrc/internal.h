@@ -169,6 +169,14 @@ struct JacobiProb {
   double eps, rtol;
   double* work;  // nullable: flops of the sweeps performed (dots and rotations)
 };
+// Spectral norm of a small matrix: out[0] = ||A||_2 for A (rows x cols,
+// column-major, lda), g = min(rows, cols) <= norm2_max_dim().
+struct Norm2Prob {
+  const double* A;
+  int64_t lda;
+  int32_t rows, cols;
+  double* out;
+};
 // block fill: A[i + j ld] = (i == j ? diag : 0) for i < rows, j < cols
 struct FillItem {
   double* A;
@@ -211,6 +219,11 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
 int jacobi_small_max_m();
 int jacobi_max_len();
 void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* stream);
+// spectral norms: one wavefront per problem, per_doubles = norm2_need_doubles
+// of the largest g of the launch
+int norm2_max_dim();
+size_t norm2_need_doubles(int g);
+void k_norm2(const Norm2Prob* probs, int n, int per_doubles, void* stream);
 // medium problems (m <= jacobi_mid_max_m()) take 256-thread workgroups,
 // larger ones 1024 (wide)
 int jacobi_mid_max_m();

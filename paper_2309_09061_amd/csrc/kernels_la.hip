@@ -18,6 +18,7 @@
 // set fits that capacity, the same predicate the host used to size it.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <type_traits>
 
 #include "internal.h"
@@ -470,6 +471,7 @@ template <int NT>
 __global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
                               size_t slot, int lds_cap);
 __global__ void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob, int per);
+__global__ void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per);
 template <int G, int CPT, int RPT>
 __global__ void tsqr_rb_kernel(const TsqrProb* __restrict__ probs, int nprob);
 
@@ -484,7 +486,7 @@ int lds_limit_doubles() {
     int bytes = std::max(std::min(maxb, 160 * 1024) - 2048, 32 * 1024);
     const void* ks[] = {(const void*)qr_kernel, (const void*)apply_kernel, (const void*)tsqr_kernel,
                         (const void*)jacobi_kernel<256>, (const void*)jacobi_kernel<1024>,
-                        (const void*)jacobi_small_kernel,
+                        (const void*)jacobi_small_kernel, (const void*)norm2_kernel,
                         (const void*)tsqr_rb_kernel<16, 1, 8>, (const void*)tsqr_rb_kernel<8, 1, 16>,
                         (const void*)tsqr_rb_kernel<8, 2, 8>};
     for (const void* k : ks)
@@ -1490,6 +1492,196 @@ void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* strea
   if (n < 4 * 256) wpb = std::min(wpb, 1);
   H2_REQUIRE(wpb >= 1, H2_ERR_ARG, "jacobi: small problems too large");
   hipLaunchKernelGGL(jacobi_small_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), (size_t)wpb * per_doubles * 8,
+                     (hipStream_t)stream, probs, n, per_doubles);
+  HIP_OK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Spectral norms of small matrices, one wavefront per matrix.  With g =
+// min(rows, cols) <= 64: the g x g Gram matrix (A^T A or A A^T) is formed in
+// LDS, scaled to a unit largest diagonal entry; g steps of Lanczos with full
+// reorthogonalisation (classical Gram-Schmidt, twice) reduce it to a
+// tridiagonal T with the same spectrum up to rounding; the largest eigenvalue
+// of T is then bracketed by Sturm counts at 64 shifts per step (one per lane)
+// until the bracket is a few ulps wide.  ||A||_2 = sqrt(lambda_max).  The
+// Gram matrix squares the singular values, which costs nothing in the
+// relative accuracy of the largest one.
+// LDS per problem: Gram g^2 | Lanczos vectors by rows and by columns (2 g^2;
+// the sample staging of the Gram step, 64 g, shares this space) | w, h, and
+// the diagonal and off-diagonal of T (g each).
+// ---------------------------------------------------------------------------
+constexpr int kNorm2MaxG = 64;
+int norm2_max_dim() { return kNorm2MaxG; }
+static __host__ __device__ inline size_t norm2_need(int g) {
+  return (size_t)g * g + (size_t)max(2 * g * g, 64 * g) + 4 * (size_t)g;
+}
+size_t norm2_need_doubles(int g) { return norm2_need(g); }
+
+__global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int pi = blockIdx.x * (blockDim.x >> 6) + wave;
+  if (pi >= nprob) return;  // whole wavefront; no workgroup barriers below
+  const Norm2Prob P = probs[pi];
+  const bool tall = P.cols <= P.rows;
+  const int g = tall ? P.cols : P.rows, ns = tall ? P.rows : P.cols;
+  if (g <= 0) {
+    if (lane == 0) *P.out = 0.0;
+    return;
+  }
+  // the entries are scaled by a power of two (exact) that brings the largest
+  // to [1/2, 1), so the Gram matrix neither overflows nor underflows
+  double amax = 0.0;
+  for (int j = 0; j < P.cols; ++j)
+    for (int i = lane; i < P.rows; i += 64) amax = fmax(amax, fabs(P.A[i + (int64_t)j * P.lda]));
+  for (int o = 1; o < 64; o <<= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
+  if (!(amax > 0.0) || !(amax <= DBL_MAX)) {  // zero, or not finite: passed through
+    if (lane == 0) *P.out = amax;
+    return;
+  }
+  int ex;
+  (void)frexp(amax, &ex);
+  const double sc = ldexp(1.0, -ex);
+  double* Gm = lds_dyn + (size_t)wave * per;
+  double* Qr = Gm + g * g;  // Qr[t g + i]: component i of Lanczos vector t
+  double* Qt = Qr + g * g;  // Qt[i g + t]: the same, transposed
+  double* X = Qr;           // staging of 64 samples (rows, or columns) x g
+  double* Wv = Gm + g * g + max(2 * g * g, 64 * g);
+  double* Hv = Wv + g;
+  double* Ta = Hv + g;
+  double* Tb = Ta + g;
+
+  // ---- Gram matrix, upper triangle accumulated over chunks of 64 samples ----
+  for (int e = lane; e < g * g; e += 64) Gm[e] = 0.0;
+  for (int s0 = 0; s0 < ns; s0 += 64) {
+    const int cnt = min(64, ns - s0);
+    team_sync<64>();  // the previous chunk's reads are done
+    if (tall) {
+      for (int e = lane; e < 64 * g; e += 64) {
+        const int sm = e & 63, f = e >> 6;
+        if (sm < cnt) X[sm * g + f] = sc * P.A[(s0 + sm) + (int64_t)f * P.lda];
+      }
+    } else {
+      for (int e = lane; e < cnt * g; e += 64) X[e] = sc * P.A[(e % g) + (int64_t)(s0 + e / g) * P.lda];
+    }
+    team_sync<64>();
+    for (int e = lane; e < g * g; e += 64) {
+      const int f1 = e % g, f2 = e / g;
+      if (f1 > f2) continue;
+      double acc = 0.0;
+      for (int sm = 0; sm < cnt; ++sm) acc += X[sm * g + f1] * X[sm * g + f2];
+      Gm[e] += acc;
+    }
+  }
+  team_sync<64>();
+  // the largest diagonal entry bounds every entry (positive semidefinite);
+  // the Gram matrix is divided by it, which puts lambda_max in [1, g]
+  double dmax = 0.0;
+  for (int i = lane; i < g; i += 64) dmax = fmax(dmax, Gm[i + i * g]);
+  for (int o = 1; o < 64; o <<= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+  const double inv = 1.0 / dmax;  // dmax >= 1/4: some entry of A is at least 1/2 after scaling
+  for (int e = lane; e < g * g; e += 64) {  // lower triangle from the upper, all scaled
+    const int f1 = e % g, f2 = e / g;
+    if (f1 > f2) Gm[e] = Gm[f2 + f1 * g] * inv;
+  }
+  team_sync<64>();
+  for (int e = lane; e < g * g; e += 64) {
+    const int f1 = e % g, f2 = e / g;
+    if (f1 <= f2) Gm[e] *= inv;
+  }
+  team_sync<64>();
+
+  // ---- Lanczos: T = Q^T Gm Q, fixed start vector with unequal entries ----
+  double q = 0.0;
+  if (lane < g) {
+    const double u = (double)lane * 0.6180339887498949;
+    q = 1.0 + (u - floor(u));
+  }
+  q *= rsqrt(wave_sum(q * q));
+  double qp = 0.0, bprev = 0.0;
+  int nt = g;
+  for (int j = 0; j < g; ++j) {
+    if (lane < g) {
+      Qr[j * g + lane] = q;
+      Qt[lane * g + j] = q;
+    }
+    team_sync<64>();
+    double w = 0.0;
+    if (lane < g)
+      for (int k = 0; k < g; ++k) w += Gm[k * g + lane] * Qr[j * g + k];  // Gm symmetric: column access
+    const double al = wave_sum(w * q);
+    w -= al * q + bprev * qp;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (lane < g) Wv[lane] = w;
+      team_sync<64>();
+      if (lane <= j) {
+        double h = 0.0;
+        for (int i = 0; i < g; ++i) h += Wv[i] * Qt[i * g + lane];
+        Hv[lane] = h;
+      }
+      team_sync<64>();
+      if (lane < g)
+        for (int t = 0; t <= j; ++t) w -= Hv[t] * Qr[t * g + lane];
+      team_sync<64>();
+    }
+    const double bt = sqrt(wave_sum(w * w));
+    if (lane == 0) {
+      Ta[j] = al;
+      Tb[j] = bt;
+    }
+    // an invariant subspace (or the whole space) is reached; a residual at
+    // the rounding level moves the eigenvalues by no more than itself
+    if (j + 1 == g || !(bt > 0x1p-60)) {
+      nt = j + 1;
+      break;
+    }
+    qp = q;
+    q = w / bt;
+    bprev = bt;
+  }
+  team_sync<64>();
+
+  // ---- lambda_max(T) by multisection with Sturm counts ----
+  double lo = Ta[0], hi = -1.0, bmax2 = 0.0;
+  for (int i = 0; i < nt; ++i) {
+    const double bl = i > 0 ? fabs(Tb[i - 1]) : 0.0, br = i + 1 < nt ? fabs(Tb[i]) : 0.0;
+    lo = fmax(lo, Ta[i]);            // a diagonal entry of T is a Rayleigh quotient
+    hi = fmax(hi, Ta[i] + bl + br);  // Gershgorin
+    bmax2 = fmax(bmax2, br * br);
+  }
+  hi = fmax(hi, lo);
+  const double pivmin = 0x1p-1000 * fmax(1.0, bmax2);
+  for (int it = 0; it < 24 && hi - lo > 0x1p-51 * hi; ++it) {
+    const double wd = hi - lo;
+    const double x = lo + wd * ((double)(lane + 1) * (1.0 / 65.0));
+    int neg = 0;  // eigenvalues of T below x: negative pivots of T - x I
+    double d = Ta[0] - x;
+    if (fabs(d) < pivmin) d = -pivmin;
+    neg += d < 0.0;
+    for (int i = 1; i < nt; ++i) {
+      d = (Ta[i] - x) - Tb[i - 1] * Tb[i - 1] / d;
+      if (fabs(d) < pivmin) d = -pivmin;
+      neg += d < 0.0;
+    }
+    const unsigned long long above = __ballot(neg == nt);  // x above every eigenvalue
+    if (above) {
+      const int f = __ffsll(above) - 1;
+      const double nhi = lo + wd * ((double)(f + 1) * (1.0 / 65.0));
+      const double nlo = f > 0 ? lo + wd * ((double)f * (1.0 / 65.0)) : lo;
+      lo = nlo;
+      hi = nhi;
+    } else {
+      lo = lo + wd * (64.0 / 65.0);
+    }
+  }
+  if (lane == 0) *P.out = ldexp(sqrt(0.5 * (lo + hi) * dmax), ex);
+}
+
+void k_norm2(const Norm2Prob* probs, int n, int per_doubles, void* stream) {
+  if (n <= 0) return;
+  int wpb = std::min(4, lds_limit_doubles() / std::max(per_doubles, 1));
+  if (n < 4 * 256) wpb = std::min(wpb, 1);
+  H2_REQUIRE(wpb >= 1, H2_ERR_ARG, "norm2: problems too large");
+  hipLaunchKernelGGL(norm2_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), (size_t)wpb * per_doubles * 8,
                      (hipStream_t)stream, probs, n, per_doubles);
   HIP_OK(hipGetLastError());
 }

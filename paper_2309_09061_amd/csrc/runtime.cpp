@@ -828,6 +828,11 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
   }
   double* R = ctx->ws.get<double>(std::max<size_t>(rtot, 1));
   double* S = ctx->ws.get<double>(std::max<size_t>(stot, 1));
+  // g = min(rows, cols) <= norm2_max_dim(): the Gram / Lanczos kernel;
+  // larger ones: R factor and the singular values of R
+  std::vector<Norm2Prob> np;
+  int gmax = 0;
+  double nflops = 0, nbytes = 0;
   for (size_t i = 0; i < n; ++i) {
     const Item& it = items[i];
     int mn = std::min(it.rows, it.cols);
@@ -835,11 +840,26 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
       out[i] = zero;
       continue;
     }
+    if (mn <= norm2_max_dim()) {
+      np.push_back({it.A, std::max<int64_t>(it.lda, 1), it.rows, it.cols, S + soff[i]});
+      out[i] = S + soff[i];
+      gmax = std::max(gmax, mn);
+      // Gram (upper triangle), Lanczos with two reorthogonalisations
+      const double g = mn, s = std::max(it.rows, it.cols);
+      nflops += s * g * (g + 1) + g * (2 * g * g + 4 * g * (g + 1));
+      nbytes += 8.0 * it.rows * it.cols;
+      continue;
+    }
     // ||A||_2 = ||A^T||_2: factor the tall orientation
     bool tall = it.rows >= it.cols;
     ts.add(it.A, it.lda, std::max(it.rows, it.cols), mn, !tall, R + roff[i], mn);
     jb.add(R + roff[i], mn, mn, mn, nullptr, 1, S + soff[i], nullptr, 0.0);
     out[i] = S + soff[i];
+  }
+  if (!np.empty()) {
+    Norm2Prob* d = upload_launch(ctx, np);
+    LaunchTimer lt(ctx, KK_OTHER, nflops, nbytes);
+    k_norm2(d, (int)np.size(), (int)norm2_need_doubles(gmax), ctx->stream);
   }
   ts.run(ctx);
   jb.run(ctx);
