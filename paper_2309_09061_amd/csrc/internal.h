@@ -11,12 +11,14 @@
 #include <cstdint>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
 #include <exception>
 #include <functional>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/h2.h"
@@ -427,8 +429,8 @@ namespace h2 {
 char* stage_alloc(h2_ctx* ctx, size_t bytes);
 void* stage_upload(h2_ctx* ctx, const char* h, size_t bytes);
 void* upload_bytes(h2_ctx* ctx, const void* src, size_t bytes);
-template <class T>
-T* upload(h2_ctx* ctx, const std::vector<T>& v) {
+template <class T, class A>
+T* upload(h2_ctx* ctx, const std::vector<T, A>& v) {
   if (v.empty()) return nullptr;
   return (T*)upload_bytes(ctx, v.data(), v.size() * sizeof(T));
 }
@@ -583,10 +585,29 @@ struct Triple {
   int32_t s, bx, by;  // middle cluster, block of X (view coords), block of Y
   int32_t kind;       // laid out as the 4 ints a TriFamily reads
 };
+// allocator whose resize leaves plain data uninitialised (large host tables
+// written in parallel right after they are sized: their pages are first
+// touched by the threads that fill them)
+template <class T>
+struct DefaultInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = DefaultInit<U>;
+  };
+  using std::allocator<T>::allocator;
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
 struct ProductTreeH {
   std::shared_ptr<BlockTreeH> bt;           // T^XY
   std::vector<int32_t> tri_ptr;             // per block
-  std::vector<Triple> tri;
+  std::vector<Triple, DefaultInit<Triple>> tri;
   std::vector<int32_t> kind_cnt;            // 4 per block: triples of each kind
   int64_t n_terminated = 0;
 };

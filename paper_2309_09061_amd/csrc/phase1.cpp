@@ -549,7 +549,8 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
                      d_tY, d_lY, TK_NN, false, upload(a, sizes));
     sym.join();
     if (sym_err) std::rethrow_exception(sym_err);
-    const int32_t* d_tri = (const int32_t*)upload(a, PT.tri.empty() ? std::vector<Triple>{{0, 0, 0, -1}} : PT.tri);
+    const int32_t* d_tri = PT.tri.empty() ? (const int32_t*)upload(a, std::vector<Triple>{{0, 0, 0, -1}})
+                                          : (const int32_t*)upload(a, PT.tri);
     // The dense products fill the whole device; launched while the passes
     // still factorize the wide lower levels they would hold those launches
     // back.  They start once both passes are three levels from the leaves,

@@ -1,8 +1,11 @@
 // Cluster trees, block trees and the product block tree T^XY (host, integer
 // work).  Section 2: Definitions "Cluster tree" and "Block tree"; Section 6:
 // the product block tree and its admissible / inadmissible leaves.
+#include <algorithm>
 #include <cmath>
+#include <exception>
 #include <numeric>
+#include <thread>
 
 #include "internal.h"
 
@@ -204,22 +207,67 @@ std::shared_ptr<BlockTreeH> build_block_tree(const TreeH& rt, const TreeH& ct, d
 // child (a, c) (a: row child, c: column child, 1 or 2, view coordinates) of
 // the subdivided block b of a view; block trees list the four children of a
 // block row-child-major
-static inline int view_child(const View& V, int b, int a, int c) {
-  const int c0 = V.m->bt->child0[b];
-  return V.T ? c0 + (c - 1) * 2 + (a - 1) : c0 + (a - 1) * 2 + (c - 1);
+static inline int view_child(const int32_t* child0, bool transposed, int b, int a, int c) {
+  const int c0 = child0[b];
+  return transposed ? c0 + (c - 1) * 2 + (a - 1) : c0 + (a - 1) * 2 + (c - 1);
 }
 
+// f(i0, i1) over [0, n) in contiguous parts on up to `threads` host threads,
+// split so that the parts hold about equal shares of the weights given by
+// the prefix sums w (w[0] = 0, w[n] = total); the first exception is rethrown
+template <typename F>
+static void parallel_parts(int n, const std::vector<int64_t>& w, int threads, F f) {
+  if (threads <= 1 || n < 2 * threads) {
+    f(0, n);
+    return;
+  }
+  std::vector<int> cut(threads + 1, n);
+  cut[0] = 0;
+  for (int p = 1; p < threads; ++p) {
+    const int64_t target = w[n] * p / threads;
+    cut[p] = (int)(std::lower_bound(w.begin(), w.begin() + n + 1, target) - w.begin());
+    cut[p] = std::max(cut[p], cut[p - 1]);
+  }
+  std::vector<std::exception_ptr> err(threads);
+  std::vector<std::thread> th;
+  for (int p = 1; p < threads; ++p)
+    th.emplace_back([&, p] {
+      try {
+        f(cut[p], cut[p + 1]);
+      } catch (...) {
+        err[p] = std::current_exception();
+      }
+    });
+  try {
+    f(cut[0], cut[1]);
+  } catch (...) {
+    err[0] = std::current_exception();
+  }
+  for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+
+// Level by level: the middle triples (s, block of X, block of Y) reaching each
+// block of the level (stored flat with offsets) are first counted per block
+// (terminated ones, by kind, and subdivided ones), then, with the offsets
+// from prefix sums, each block writes its terminated triples, its children
+// and their middle triples in place.  Blocks are independent, so both sweeps
+// run on several host threads for the wide levels; the result is the same
+// as a sequential build.
 ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
   ProductTreeH P;
   auto B = std::make_shared<BlockTreeH>();
   P.bt = B;
-  // middle triples (s, block of X, block of Y) reaching each block of the
-  // current level, stored flat with offsets; the children of subdivided
-  // factor blocks are found by index (no searches)
   struct Mid {
     int32_t s, bx, by;
   };
-  std::vector<Mid> mids_cur, mids_next, rec;
+  const int8_t* tyX = X.m->bt->type.data();
+  const int8_t* tyY = Y.m->bt->type.data();
+  const int32_t* chX = X.m->bt->child0.data();
+  const int32_t* chY = Y.m->bt->child0.data();
+  const bool trX = X.T, trY = Y.T;
+  std::vector<Mid, DefaultInit<Mid>> mids_cur, mids_next;
   std::vector<int64_t> off_cur{0, 1}, off_next;
   {
     const int bx = X.find(0, 0), by = Y.find(0, 0);
@@ -229,60 +277,109 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
   B->lvl.push_back(0);
   B->t.push_back(0);
   B->s.push_back(0);
-  int depth = X.m->ct->depth;
+  const int depth = X.m->ct->depth;
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   P.tri_ptr.push_back(0);
   for (int l = 0; l <= depth; ++l) {
-    int b0 = B->lvl[l], b1 = (int)B->t.size();
-    mids_next.clear();
-    off_next.assign(1, 0);
-    P.kind_cnt.resize(4 * (size_t)b1, 0);
-    for (int b = b0; b < b1; ++b) {
-      const int tt = B->t[b], rr = B->s[b];
-      rec.clear();
-      bool nn = false;
-      for (int64_t q = off_cur[b - b0]; q < off_cur[b - b0 + 1]; ++q) {
-        const Mid& md = mids_cur[q];
-        const int8_t tx = X.type(md.bx), ty = Y.type(md.by);
-        if (tx == BT_SPLIT && ty == BT_SPLIT) {
-          rec.push_back(md);
-          continue;
-        }
-        int8_t kind;
-        if (tx == BT_ADM && ty == BT_ADM)
-          kind = TK_AA;
-        else if (tx == BT_ADM)
-          kind = TK_AN;
-        else if (ty == BT_ADM)
-          kind = TK_NA;
-        else {
-          H2_REQUIRE(tx == BT_INADM && ty == BT_INADM, H2_ERR_UNSUPPORTED,
-                     "product tree: non-level-aligned factor blocks");
-          kind = TK_NN;
-          nn = true;
-        }
-        P.tri.push_back({md.s, md.bx, md.by, (int32_t)kind});
-        P.kind_cnt[4 * (size_t)b + kind]++;
-        P.n_terminated++;
-      }
-      P.tri_ptr.push_back((int32_t)P.tri.size());
-      if (!rec.empty()) {
-        H2_REQUIRE(!nn, H2_ERR_UNSUPPORTED, "product tree: dense triple above the leaf level");
-        B->type.push_back(BT_SPLIT);
-        B->child0.push_back((int)B->t.size());
-        for (int a = 1; a <= 2; ++a)
-          for (int c = 1; c <= 2; ++c) {
-            B->t.push_back(2 * tt + a);
-            B->s.push_back(2 * rr + c);
-            for (const Mid& md : rec)
-              for (int q = 1; q <= 2; ++q)
-                mids_next.push_back({2 * md.s + q, view_child(X, md.bx, a, q), view_child(Y, md.by, q, c)});
-            off_next.push_back((int64_t)mids_next.size());
+    const int b0 = B->lvl[l], b1 = (int)B->t.size(), nb = b1 - b0;
+    const int threads = mids_cur.size() >= 65536 ? std::min(8, hw) : 1;
+    // ---- counts per block: terminated triples and subdivided middles ----
+    std::vector<int64_t> nterm(nb + 1, 0), nrec(nb + 1, 0);
+    parallel_parts(nb, off_cur, threads, [&](int i0, int i1) {
+      for (int i = i0; i < i1; ++i) {
+        int64_t t = 0, r = 0;
+        bool nn = false;
+        for (int64_t q = off_cur[i]; q < off_cur[i + 1]; ++q) {
+          const int8_t tx = tyX[mids_cur[q].bx], ty = tyY[mids_cur[q].by];
+          if (tx == BT_SPLIT && ty == BT_SPLIT) {
+            ++r;
+            continue;
           }
-      } else {
-        B->type.push_back(nn ? BT_INADM : BT_ADM);
-        B->child0.push_back(-1);
+          if (tx != BT_ADM && ty != BT_ADM) {
+            H2_REQUIRE(tx == BT_INADM && ty == BT_INADM, H2_ERR_UNSUPPORTED,
+                       "product tree: non-level-aligned factor blocks");
+            nn = true;
+          }
+          ++t;
+        }
+        H2_REQUIRE(!(nn && r > 0), H2_ERR_UNSUPPORTED, "product tree: dense triple above the leaf level");
+        nterm[i] = t;
+        nrec[i] = r;
       }
+    });
+    // ---- offsets ----
+    std::vector<int64_t> tri_off(nb + 1), kid_off(nb + 1), mid_off(nb + 1);
+    tri_off[0] = kid_off[0] = mid_off[0] = 0;
+    for (int i = 0; i < nb; ++i) {
+      tri_off[i + 1] = tri_off[i] + nterm[i];
+      kid_off[i + 1] = kid_off[i] + (nrec[i] ? 4 : 0);
+      mid_off[i + 1] = mid_off[i] + 8 * nrec[i];
     }
+    const size_t tri0 = P.tri.size();
+    const int nkids = (int)kid_off[nb];
+    P.tri.resize(tri0 + tri_off[nb]);
+    P.tri_ptr.resize((size_t)b1 + 1);
+    P.kind_cnt.resize(4 * (size_t)b1, 0);
+    B->type.resize(b1);
+    B->child0.resize(b1);
+    B->t.resize((size_t)b1 + nkids);
+    B->s.resize((size_t)b1 + nkids);
+    mids_next.resize(mid_off[nb]);
+    off_next.assign((size_t)nkids + 1, 0);
+    // ---- fill ----
+    parallel_parts(nb, off_cur, threads, [&](int i0, int i1) {
+      for (int i = i0; i < i1; ++i) {
+        const int b = b0 + i, tt = B->t[b], rr = B->s[b];
+        int64_t tp = tri0 + tri_off[i], r = 0;
+        bool nn = false;
+        const int64_t nr = nrec[i];
+        const int kid = b1 + (int)kid_off[i];
+        for (int64_t q = off_cur[i]; q < off_cur[i + 1]; ++q) {
+          const Mid md = mids_cur[q];
+          const int8_t tx = tyX[md.bx], ty = tyY[md.by];
+          if (tx == BT_SPLIT && ty == BT_SPLIT) {
+            for (int a = 1; a <= 2; ++a)
+              for (int c = 1; c <= 2; ++c) {
+                const int k = (a - 1) * 2 + (c - 1);
+                Mid* dst = &mids_next[mid_off[i] + (int64_t)k * 2 * nr + 2 * r];
+                for (int qq = 1; qq <= 2; ++qq)
+                  dst[qq - 1] = {2 * md.s + qq, view_child(chX, trX, md.bx, a, qq), view_child(chY, trY, md.by, qq, c)};
+              }
+            ++r;
+            continue;
+          }
+          int8_t kind;
+          if (tx == BT_ADM && ty == BT_ADM)
+            kind = TK_AA;
+          else if (tx == BT_ADM)
+            kind = TK_AN;
+          else if (ty == BT_ADM)
+            kind = TK_NA;
+          else {
+            kind = TK_NN;
+            nn = true;
+          }
+          P.tri[tp++] = {md.s, md.bx, md.by, (int32_t)kind};
+          P.kind_cnt[4 * (size_t)b + kind]++;
+        }
+        P.tri_ptr[b + 1] = (int32_t)tp;
+        if (nr) {
+          B->type[b] = BT_SPLIT;
+          B->child0[b] = kid;
+          for (int a = 1; a <= 2; ++a)
+            for (int c = 1; c <= 2; ++c) {
+              const int k = (a - 1) * 2 + (c - 1);
+              B->t[kid + k] = 2 * tt + a;
+              B->s[kid + k] = 2 * rr + c;
+              off_next[kid - b1 + k + 1] = mid_off[i] + (int64_t)(k + 1) * 2 * nr;
+            }
+        } else {
+          B->type[b] = nn ? BT_INADM : BT_ADM;
+          B->child0[b] = -1;
+        }
+      }
+    });
+    P.n_terminated += tri_off[nb];
     B->lvl.push_back(b1);
     mids_cur.swap(mids_next);
     off_cur.swap(off_next);
