@@ -38,29 +38,37 @@ struct P2Side {
   std::vector<double*> RS;   // per stored admissible G leaf: R_t S_{t,r}, kz_t x kW_r
 };
 
-// union of two column-tree leaf lists covering the same index range
-static std::vector<ColLeaf> leaf_union(const TreeH& T, const std::vector<ColLeaf>& a,
-                                       const std::vector<ColLeaf>& b) {
-  std::vector<ColLeaf> out;
-  size_t i = 0, j = 0;
-  while (i < a.size() && j < b.size()) {
-    const ColLeaf &x = a[i], &y = b[j];
+// Column trees of all blocks in one array (per pass): the leaves of block b
+// are leaves[beg[b] .. beg[b] + len[b]), ordered by position.
+struct ColTrees {
+  std::vector<ColLeaf> leaves;
+  std::vector<int64_t> beg;
+  std::vector<int32_t> len;
+};
+
+// appends the union of the leaf lists of blocks c1 and c2 (which cover the
+// same index range) to the array
+static void leaf_union_into(const TreeH& T, ColTrees& C, int c1, int c2) {
+  const int64_t a = C.beg[c1], b = C.beg[c2];
+  const int na = C.len[c1], nb = C.len[c2];
+  int i = 0, j = 0;
+  while (i < na && j < nb) {
+    const ColLeaf x = C.leaves[a + i], y = C.leaves[b + j];
     if (x.node == y.node) {
-      out.push_back({x.node, x.adm && y.adm, 0, 0});
+      C.leaves.push_back({x.node, x.adm && y.adm, 0, 0});
       ++i;
       ++j;
     } else if (T.size[x.node] < T.size[y.node]) {  // x lies inside y
-      out.push_back(x);
+      C.leaves.push_back(x);
       if (T.off[x.node] + T.size[x.node] == T.off[y.node] + T.size[y.node]) ++j;
       ++i;
     } else {
-      out.push_back(y);
+      C.leaves.push_back(y);
       if (T.off[x.node] + T.size[x.node] == T.off[y.node] + T.size[y.node]) ++i;
       ++j;
     }
   }
-  H2_REQUIRE(i == a.size() && j == b.size(), H2_ERR_SHAPE, "column trees do not cover one range");
-  return out;
+  H2_REQUIRE(i == na && j == nb, H2_ERR_SHAPE, "column trees do not cover one range");
 }
 
 static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
@@ -125,8 +133,14 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   // admissible leaves of T_IK, the transfer chains of the column basis used
   // by match_column and W_a restricted to leaves: host work and a few small
   // products, done while the device factorizes the leaf level
-  std::vector<std::vector<ColLeaf>> ctree(nb);
-  auto tree_width = [&](int b) { return ctree[b].empty() ? 0 : ctree[b].back().off + ctree[b].back().width; };
+  ColTrees ct;
+  ct.beg.assign(nb, 0);
+  ct.len.assign(nb, 0);
+  auto tree_width = [&](int b) {
+    if (ct.len[b] == 0) return 0;
+    const ColLeaf& e = ct.leaves[ct.beg[b] + ct.len[b] - 1];
+    return e.off + e.width;
+  };
   std::unordered_map<int64_t, std::pair<const double*, int64_t>> chain;
   auto key = [&](int c, int a) { return (int64_t)c * ncl + a; };
   std::function<void(int, int)> need;
@@ -142,21 +156,21 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
         if (!in_adm(b)) continue;
         int r = G.vcol(b), t = G.vrow(b);
+        ct.beg[b] = (int64_t)ct.leaves.size();
         if (B.type[b] != BT_SPLIT) {
-          ctree[b] = {{r, B.type[b] == BT_ADM ? 1 : 0, 0, 0}};
+          ct.leaves.push_back({r, B.type[b] == BT_ADM ? 1 : 0, 0, 0});
         } else {
-          std::vector<ColLeaf> all;
           for (int qc = 1; qc <= 2; ++qc) {
             int rc = 2 * r + qc;
             int c1 = G.find(2 * t + 1, rc), c2 = G.find(2 * t + 2, rc);
             H2_REQUIRE(c1 >= 0 && c2 >= 0, H2_ERR_SHAPE, "product tree: missing child");
-            auto u = leaf_union(T, ctree[c1], ctree[c2]);
-            all.insert(all.end(), u.begin(), u.end());
+            leaf_union_into(T, ct, c1, c2);
           }
-          ctree[b] = std::move(all);
         }
+        ct.len[b] = (int32_t)((int64_t)ct.leaves.size() - ct.beg[b]);
         int off = 0;
-        for (auto& L : ctree[b]) {
+        for (int64_t e = ct.beg[b]; e < ct.beg[b] + ct.len[b]; ++e) {
+          ColLeaf& L = ct.leaves[e];
           L.width = L.adm ? Wb.rank[L.node] : (int)T.size[L.node];
           L.off = off;
           off += L.width;
@@ -190,7 +204,8 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
           G.row_blocks(t, bl, cnt);
           while (rowpos < cnt && bl[rowpos] != b) ++rowpos;
         }
-        for (const ColLeaf& L : ctree[b]) {
+        for (int64_t e = ct.beg[b]; e < ct.beg[b] + ct.len[b]; ++e) {
+          const ColLeaf& L = ct.leaves[e];
           int rc = contains(2 * r + 1, L.node) ? 2 * r + 1 : 2 * r + 2;
           for (int qt = 1; qt <= 2; ++qt) {
             int tc = 2 * t + qt;
@@ -199,13 +214,14 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
             // ordered by position, so no leaf after the last one starting at
             // or before L can contain it (the backward scan only moves past
             // empty clusters)
-            const std::vector<ColLeaf>& cl = ctree[c];
-            auto it = std::upper_bound(cl.begin(), cl.end(), T.off[L.node],
-                                       [&](int64_t o, const ColLeaf& M) { return o < T.off[M.node]; });
+            const ColLeaf* c_beg = ct.leaves.data() + ct.beg[c];
+            const ColLeaf* c_end = c_beg + ct.len[c];
+            const ColLeaf* it = std::upper_bound(c_beg, c_end, T.off[L.node],
+                                                 [&](int64_t o, const ColLeaf& M) { return o < T.off[M.node]; });
             const ColLeaf* S = nullptr;
-            while (it != cl.begin() && !S) {
+            while (it != c_beg && !S) {
               --it;
-              if (contains(it->node, L.node)) S = &*it;
+              if (contains(it->node, L.node)) S = it;
             }
             H2_REQUIRE(S, H2_ERR_SHAPE, "match_column: no source leaf");
             H2_REQUIRE(S->adm || S->node == L.node, H2_ERR_UNSUPPORTED,
