@@ -59,6 +59,17 @@ typedef enum {
   H2_FP32_BULK = 1   /* bulk products of both phases in float32 (FP32 MFMA) */
 } h2_precision;
 
+/* Truncation rule of the rank-choosing SVDs of both phases (Section 5 error
+ * control).  H2_RANK_ABS is the paper's: keep the singular values > eps of
+ * the block-scaled matrix.  H2_RANK_REL_FROB is a variant: keep the fewest
+ * leading singular values whose discarded tail has Frobenius norm at most
+ * eps times the Frobenius norm of the whole scaled matrix (in phase 1, of its
+ * part outside the kept range of V_X). */
+typedef enum {
+  H2_RANK_ABS = 0,
+  H2_RANK_REL_FROB = 1
+} h2_rank_rule;
+
 /* Kernel functions g(x,y) of the interpolated matrices (Section 2, Example
  * "Integral operator").  Diagonal entries g(x_i, x_i) of singular kernels are 0. */
 typedef enum {
@@ -186,6 +197,11 @@ h2_status h2_product_sizes(const h2_product* G, int64_t out[5]);
  * their events; this function does (it synchronises with the streams).
  * Returns the count (0 on a NULL argument or a device error). */
 int h2_step_times(h2_ctx* ctx, double* out, int n, int reset);
+
+/* Sets the truncation rule (h2_rank_rule) of the later h2_mul_intermediate and
+ * h2_recompress calls on ctx; the default is H2_RANK_ABS.  H2_ERR_ARG for an
+ * unknown rule or a NULL context. */
+h2_status h2_set_rank_rule(h2_ctx* ctx, int rule);
 
 /* Launch timing for measurement.  h2_profile(ctx, families) makes every
  * kernel launch of a family whose bit is set in `families` (bit k for family

@@ -12,7 +12,7 @@ Everything is float64 numpy.  Library QR / SVD / matmul serve as single steps;
 the loops over clusters and blocks follow the recursive procedures of the
 paper (basis weights, total weights, induced basis, build basis, match
 column) in the paper's order and notation.  Where the paper is silent the
-reading used is named in the docstring (R1..R20, listed in the design doc).
+reading used is named in the docstring (readings R1..R21).
 
 Conventions: clusters are numbered breadth-first (root 0); all matrices are
 indexed in cluster order (the permuted order of the points).  A cluster basis
@@ -413,9 +413,26 @@ def left_svd(M: np.ndarray):
     return U, sig
 
 
-def choose_rank(sig: np.ndarray, eps: float) -> int:
-    """R9: keep the singular values strictly above eps (on the scaled matrix)."""
-    return int(np.count_nonzero(sig > eps))
+RANK_ABS, RANK_REL_FROB = "abs", "relF"
+
+
+def choose_rank(sig: np.ndarray, eps: float, rule: str = RANK_ABS) -> int:
+    """Rank of a truncated SVD with singular values sig (descending).
+
+    R9 (rule "abs", the paper's): keep the singular values strictly above eps
+    on the scaled matrix.
+    R21 (rule "relF", a variant): the smallest k whose discarded tail has
+    Frobenius norm at most eps times the Frobenius norm of the whole matrix,
+    i.e. keep sigma_i while sqrt(sum_{j >= i} sigma_j^2) > eps ||sigma||_2.
+    """
+    if rule == RANK_ABS:
+        return int(np.count_nonzero(sig > eps))
+    if rule != RANK_REL_FROB:
+        raise ValueError(f"unknown rank rule {rule!r}")
+    if sig.size == 0:
+        return 0
+    tail = np.sqrt(np.cumsum((sig * sig)[::-1])[::-1])  # tail[i] = ||sig[i:]||_2
+    return int(np.count_nonzero(tail > eps * tail[0]))
 
 
 # ----------------------------------------------------------------------------
@@ -505,7 +522,7 @@ def _pad_rows(M: np.ndarray, rows: int) -> np.ndarray:
     return out
 
 
-def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float) -> InducedBasis:
+def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) -> InducedBasis:
     """Compressed induced row basis of the product X Y.
 
     R18: Q_{X,t} is a full orthogonal factor whose first k1 columns span the
@@ -538,7 +555,7 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float) -> InducedBasis:
         assembled[t] = (VX, Vrest)
         Vtil = Ux[:, k1:].T @ Vrest
         U, sig = left_svd(Vtil)
-        k2 = choose_rank(sig, eps)
+        k2 = choose_rank(sig, eps, rule)
         sig_out[t] = sig
         Qt = np.hstack([Ux[:, :k1], Ux[:, k1:] @ U[:, :k2]])
         Q.rank[t] = k1 + k2
@@ -691,9 +708,9 @@ def form_product(X: H2Matrix, Y: H2Matrix, rowb: InducedBasis, colb: InducedBasi
 
 
 class Phase1:
-    def __init__(self, X, Y, eps):
-        self.row = induced_basis(X, Y, eps)
-        self.col = induced_basis(Y.transposed(), X.transposed(), eps)
+    def __init__(self, X, Y, eps, rule=RANK_ABS):
+        self.row = induced_basis(X, Y, eps, rule)
+        self.col = induced_basis(Y.transposed(), X.transposed(), eps, rule)
         self.PT = ProductTree(X, Y)
         self.G = form_product(X, Y, self.row, self.col, self.PT)
 
@@ -832,7 +849,7 @@ class CoarseBasis:
         self.Z, self.C = Z, C           # product total weights, condensed C_t / Chat_t
 
 
-def build_basis(G: H2Matrix, TIK: BlockTree, eps: float) -> CoarseBasis:
+def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -> CoarseBasis:
     """Figure "basis": adaptive isometric nested row basis for the coarse
     block tree T_IK, with the product total weights Z_t of
     eq. (Zt_condensation), leaf matrices C_t (eq. (ct_leaf)) and non-leaf
@@ -883,7 +900,7 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float) -> CoarseBasis:
                 cols.append(omega[tag[(t, r)]] * G.N[(t, r)])
             Cm[t] = np.hstack(cols)
             U, sig = left_svd(Cm[t])
-            kz = choose_rank(sig, eps)
+            kz = choose_rank(sig, eps, rule)
             sig_out[t] = sig
             Qt = U[:, :kz]
             Q.leaf[t] = Qt
@@ -921,7 +938,7 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float) -> CoarseBasis:
             cols.append(omega[tag[(t, r)]] * np.hstack([M for _, _, M in Ahat[r]]))
         Cm[t] = np.hstack(cols)
         U, sig = left_svd(Cm[t])
-        kz = choose_rank(sig, eps)
+        kz = choose_rank(sig, eps, rule)
         sig_out[t] = sig
         Qhat = U[:, :kz]
         Q.rank[t] = kz
@@ -975,16 +992,18 @@ def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasi
 
 
 class Phase2:
-    def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float):
-        self.row = build_basis(G, TIK, eps)
-        self.col = build_basis(G.transposed(), TIK.transposed(), eps)
+    def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS):
+        self.row = build_basis(G, TIK, eps, rule)
+        self.col = build_basis(G.transposed(), TIK.transposed(), eps, rule)
         self.Z = form_coarse(G, TIK, self.row, self.col)
 
 
-def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float = None):
-    """Both phases: returns (Phase1, Phase2); Z = phase2.Z approximates X Y."""
-    p1 = Phase1(X, Y, eps1)
-    p2 = Phase2(p1.G, TIK, eps1 if eps2 is None else eps2)
+def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float = None, rule: str = RANK_ABS):
+    """Both phases: returns (Phase1, Phase2); Z = phase2.Z approximates X Y.
+    rule: the truncation rule of both phases (R9 "abs", or the variant R21
+    "relF")."""
+    p1 = Phase1(X, Y, eps1, rule)
+    p2 = Phase2(p1.G, TIK, eps1 if eps2 is None else eps2, rule)
     return p1, p2
 
 

@@ -316,6 +316,14 @@ int h2_step_times(h2_ctx* ctx, double* out, int n, int reset) {
   return m;
 }
 
+h2_status h2_set_rank_rule(h2_ctx* ctx, int rule) {
+  return guard([&] {
+    H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
+    H2_REQUIRE(rule == H2_RANK_ABS || rule == H2_RANK_REL_FROB, H2_ERR_ARG, "unknown rank rule");
+    ctx->rank_rule = rule;
+  });
+}
+
 h2_status h2_profile(h2_ctx* ctx, int families) {
   return guard([&] {
     H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");

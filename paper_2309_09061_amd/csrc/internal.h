@@ -167,7 +167,7 @@ struct JacobiProb {
   int32_t* rank;
   const int32_t* skip;
   int64_t ldr, ldu;
-  int32_t p, m, mode, pad;
+  int32_t p, m, mode, rule;  // rule: 0 keep sigma > max(eps, rtol sigma_max); 1 relative-Frobenius tail <= eps
   double eps, rtol;
   double* work;  // nullable: flops of the sweeps performed (dots and rotations)
 };
@@ -221,6 +221,9 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
 int jacobi_small_max_m();
 int jacobi_max_len();
 void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* stream);
+// replaces the rank written by a Jacobi launch with the relative-Frobenius
+// rank of the singular values it wrote (problems with rule 1)
+void k_rank_relf(const JacobiProb* probs, int n, void* stream);
 // spectral norms: one wavefront per problem, per_doubles = norm2_need_doubles
 // of the largest g of the launch
 int norm2_max_dim();
@@ -384,6 +387,7 @@ struct h2_ctx {
   double host_ms[8] = {0};             // host wall time between step_begin and step_end
   std::chrono::steady_clock::time_point host_t0[8];
   int prec = 0;                        // bulk precision of the running call
+  int rank_rule = 0;                   // h2_rank_rule of the truncating SVDs
   int profile = 0;                     // bit k: time the launches of kernel family k
   std::vector<void*> ev_pool;          // reusable events for launch timing
   std::vector<std::pair<double*, size_t>> prof_host;  // pinned chunks for per-problem work counts
@@ -557,7 +561,8 @@ struct JacobiBatch {
   std::vector<JacobiProb> p;
   int max_m = 0;
   void add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu, double* sigma,
-           int32_t* rank, double eps, double rtol = 0.0, const int32_t* skip = nullptr, int mode = 1);
+           int32_t* rank, double eps, double rtol = 0.0, const int32_t* skip = nullptr, int mode = 1,
+           int rule = 0);
   void run(h2_ctx* ctx);
 };
 // sigma_max of many small matrices: tsqr + jacobi (values only); sig[i] = sigma_max

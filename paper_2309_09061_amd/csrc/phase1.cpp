@@ -362,7 +362,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       U[i] = ws.get<double>((size_t)m * m);
       double* sg2 = ws.get<double>(m);
       ts.add(Vr[i], m, ncols[i], m, true, Rt[i], m, 0, rk + i);
-      jb.add(Rt[i], m, p, m, U[i], m, sg2, rk + nc + i, eps, 0.0, rk + i);
+      jb.add(Rt[i], m, p, m, U[i], m, sg2, rk + nc + i, eps, 0.0, rk + i, 1, ctx->rank_rule);
     }
     ts.run(ctx);
     jb.run(ctx);

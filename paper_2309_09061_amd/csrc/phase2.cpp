@@ -377,7 +377,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       U[i] = ws.get<double>((size_t)m[i] * m[i]);
       sg[i] = ws.get<double>(m[i]);
       ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
-      jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, eps);
+      jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, eps, 0.0, nullptr, 1, ctx->rank_rule);
     }
     ts.run(ctx);
     jb.run(ctx);

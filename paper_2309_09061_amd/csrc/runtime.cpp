@@ -239,6 +239,7 @@ AuxRun::AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f) : AuxRun(c, aux_ctx(c)
 AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), aux(a_) {
   aux->profile = ctx->profile;
   aux->prec = ctx->prec;
+  aux->rank_rule = ctx->rank_rule;
   // the staging of the previous run is free once that run's work is done
   // (usually long ago): wait for its end event, not for the stream, which is
   // about to wait for ctx's queue
@@ -712,7 +713,8 @@ void TsqrBatch::run(h2_ctx* ctx) {
 }
 
 void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, int64_t ldu,
-                      double* sigma, int32_t* rank, double eps, double rtol, const int32_t* skip, int mode) {
+                      double* sigma, int32_t* rank, double eps, double rtol, const int32_t* skip, int mode,
+                      int rule) {
   H2_REQUIRE(m <= jacobi_max_len() && p_ <= jacobi_max_len(), H2_ERR_UNSUPPORTED,
              "jacobi: matrix larger than the kernels take");
   JacobiProb j{};
@@ -728,6 +730,7 @@ void JacobiBatch::add(const double* R, int64_t ldr, int p_, int m, double* U, in
   j.rtol = rtol;
   j.skip = skip;
   j.mode = mode;
+  j.rule = rule;
   p.push_back(j);
   max_m = std::max(max_m, m);
 }
@@ -797,6 +800,16 @@ void JacobiBatch::run(h2_ctx* ctx) {
     JacobiProb* d = upload_launch(ctx, grp[w]);
     LaunchTimer lt(ctx, KK_JACOBI, wc.dev ? 0.0 : flops_l * grp[w].size() / large.size(), bytes_l * grp[w].size() / large.size());
     k_jacobi(d, (int)grp[w].size(), lds_for(glds[w]), gslot[w], scratch, w == 1, ctx->stream);
+  }
+  {  // relative-Frobenius ranks, from the singular values just written
+    std::vector<JacobiProb> rel;
+    for (const JacobiProb& j : p)
+      if (j.rule == 1 && j.rank) rel.push_back(j);
+    if (!rel.empty()) {
+      JacobiProb* d = upload_launch(ctx, rel);
+      LaunchTimer lt(ctx, KK_OTHER, 0.0, 8.0 * rel.size());
+      k_rank_relf(d, (int)rel.size(), ctx->stream);
+    }
   }
   if (wc.dev) {  // counts of both launches, resolved with the second one's timing
     dev_d2h(wc.host, wc.dev, sizeof(double) * wc.n, ctx->stream);

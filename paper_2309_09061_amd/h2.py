@@ -58,6 +58,7 @@ def _declare(lib):
         "h2_product_ranks": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p]),
         "h2_product_sizes": (ctypes.c_int, [_c_p, _c_p]),
         "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int]),
+        "h2_set_rank_rule": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_profile": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_kernel_stats": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int]),
         "h2_tree_destroy": (None, [_c_p]),
@@ -73,6 +74,7 @@ def _declare(lib):
 
 _lib = None
 EXPORTS = None
+RANK_RULES = {"abs": 0, "relF": 1}
 
 
 def load(path: str | None = None):
@@ -121,6 +123,12 @@ class Context:
         if self.h:
             _check(self.lib, self.lib.h2_ctx_destroy(self.h))
             self.h = _c_p()
+
+    def set_rank_rule(self, rule: str):
+        """Truncation rule of the rank-choosing SVDs: "abs" (singular values
+        above eps of the scaled matrices) or "relF" (relative-Frobenius tail
+        at most eps)."""
+        _check(self.lib, self.lib.h2_set_rank_rule(self.h, RANK_RULES[rule]))
 
     def profile(self, enable: bool = True, families=None):
         """Time kernel launches with HIP events: every family when `families`

@@ -73,3 +73,13 @@ def test_error_paths_host_only():
     assert lib.h2_ctx_create(-2, None, ctypes.byref(out)) == 1
     assert lib.h2_tree_sizes(None, None) == 1
     assert "NULL" in lib.h2_last_error().decode()
+
+
+def test_rank_rule_setting_host_only():
+    lib = h2.load()
+    ctx = h2.Context(device=-1)
+    ctx.set_rank_rule("relF")
+    ctx.set_rank_rule("abs")
+    assert lib.h2_set_rank_rule(ctx.h, 2) == 1          # unknown rule
+    assert lib.h2_set_rank_rule(ctx.h, -1) == 1
+    assert lib.h2_set_rank_rule(None, 0) == 1           # NULL context

@@ -282,6 +282,34 @@ def test_batched_products():
         assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
 
 
+@pytest.mark.parametrize("name", ["1d", "2d", "ragged"])
+def test_rel_frobenius_rank_rule(name):
+    """The relative-Frobenius truncation variant (h2_set_rank_rule) against
+    the oracle under the same rule: identical rank profiles in both phases and
+    the FP64 bar for G and Z."""
+    h2 = _h2()
+    n, d, leaf, order, kx, ky, eta, seed, dist, eps = CASES[name]
+    pts, tree, X, Y, _, _, _, _ = oracle_case(name)
+    bt = O.BlockTree(tree, tree, eta)
+    p1, p2 = O.multiply(X, Y, bt, eps, rule=O.RANK_REL_FROB)
+    c = h2.Context(0)
+    c.set_rank_rule("relF")
+    _say(f"[gpu] rank rule relF: case={name} n={n} eps={eps}")
+    T = h2.Tree(c, pts, leaf, eta)
+    Xg = h2.Matrix.kernel(c, T, kx, order)
+    Yg = Xg if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    G = h2.h2_mul_intermediate(c, Xg, Yg, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    torch.cuda.synchronize()
+    nc = tree.nclusters
+    assert list(G.ranks(0)) == [p1.row.Q.rank[t] for t in range(nc)]
+    assert list(G.ranks(1)) == [p1.col.Q.rank[t] for t in range(nc)]
+    assert list(Z.ranks(0)) == [p2.row.Q.rank[t] for t in range(nc)]
+    assert list(Z.ranks(1)) == [p2.col.Q.rank[t] for t in range(nc)]
+    assert relF(dense_of(G, n), p1.G.dense()) < 1e-10
+    assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
+
+
 def test_single_leaf_tree():
     """Degenerate tree: fewer points than the leaf size, one cluster, one
     inadmissible block; the product is the dense product."""

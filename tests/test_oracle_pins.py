@@ -472,3 +472,63 @@ def test_symmetric_product_bases_coincide():
     p1, p2 = product("1d", 1e-6)
     assert p1.row.Q.rank == p1.col.Q.rank
     assert p2.row.Q.rank == p2.col.Q.rank
+
+
+# --------------------------------------------------------------------------
+# R21 (variant of R9): relative-Frobenius truncation
+# --------------------------------------------------------------------------
+def test_rel_frobenius_rank_rule_brute_force():
+    """The rank is the smallest k whose discarded tail has Frobenius norm at
+    most eps times that of all singular values (brute force over k)."""
+    rng = np.random.default_rng(21)
+    for _ in range(300):
+        n = int(rng.integers(0, 9))
+        sig = np.sort(rng.random(n) * 10.0 ** rng.integers(-4, 3, n))[::-1]
+        eps = 10.0 ** rng.uniform(-5, 0)
+        total = np.sqrt(np.sum(sig ** 2))
+        ok = [k for k in range(n + 1) if np.sqrt(np.sum(sig[k:] ** 2)) <= eps * total]
+        assert O.choose_rank(sig, eps, O.RANK_REL_FROB) == min(ok)
+    assert O.choose_rank(np.zeros(3), 0.1, O.RANK_REL_FROB) == 0
+    assert O.choose_rank(np.array([4.0, 3.0]), 0.6, O.RANK_REL_FROB) == 1  # tail 3 = 0.6 * 5: discarded
+
+
+def _stacked_transfers(Q, tree, t):
+    return np.vstack([Q.transfer[ch] for ch in tree.children[t]])
+
+
+@pytest.mark.parametrize("name", ["1d", "2d"])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_rel_frobenius_truncation_of_each_cluster(name, eps):
+    """Phase 2 under R21: each condensed matrix C_t (Chat_t) keeps all but at
+    most eps of its Frobenius norm in the span of the new basis, checked from
+    the matrices themselves (projection residual), and phase 1's remainder
+    likewise after the kept range of V_X."""
+    _, tree, bt, X, Y = problem(name)
+    p1, p2 = O.multiply(X, Y, bt, eps, rule=O.RANK_REL_FROB)
+    for side in (p2.row, p2.col):
+        for t, C in side.C.items():
+            if C.size == 0:
+                continue
+            Q = side.Q.leaf[t] if tree.is_leaf(t) else (
+                _stacked_transfers(side.Q, tree, t) if side.Q.rank[t] else np.zeros((C.shape[0], 0)))
+            res = C - Q @ (Q.T @ C)
+            assert np.linalg.norm(res) <= eps * np.linalg.norm(C) * (1 + 1e-10) + 1e-14 * np.linalg.norm(C)
+    Qf = p1.row.Q.full()
+    for t, (VX, Vrest) in p1.row.assembled.items():
+        if Vrest.size == 0:
+            continue
+        Q = Qf[t] if tree.is_leaf(t) else _stacked_transfers(p1.row.Q, tree, t)
+        Ux, sx, _ = np.linalg.svd(VX, full_matrices=True)
+        k1 = int(np.count_nonzero(sx > OH.VX_RTOL * sx[0])) if sx.size and sx[0] > 0 else 0
+        rem = Vrest - Ux[:, :k1] @ (Ux[:, :k1].T @ Vrest)       # remainder outside range V_X
+        res = Vrest - Q @ (Q.T @ Vrest)
+        assert np.linalg.norm(res) <= eps * np.linalg.norm(rem) * (1 + 1e-10) + 1e-13 * np.linalg.norm(Vrest)
+
+
+@pytest.mark.parametrize("name", ["1d", "2d"])
+def test_rel_frobenius_exact_without_truncation(name):
+    _, _, bt, X, Y = problem(name)
+    _, _, XY = dense(name)
+    p1, p2 = O.multiply(X, Y, bt, 0.0, rule=O.RANK_REL_FROB)
+    assert relF(p1.G.dense(), XY) < 1e-12
+    assert relF(p2.Z.dense(), XY) < 1e-12
