@@ -282,7 +282,9 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl) {
   P.tri_ptr.push_back(0);
   for (int l = 0; l <= depth; ++l) {
     const int b0 = B->lvl[l], b1 = (int)B->t.size(), nb = b1 - b0;
-    const int threads = mids_cur.size() >= 65536 ? std::min(8, hw) : 1;
+    // two workers: more compete with the passes' host threads (measured: no
+    // faster with four or eight)
+    const int threads = mids_cur.size() >= 65536 ? std::min(2, hw) : 1;
     // ---- counts per block: terminated triples and subdivided middles ----
     std::vector<int64_t> nterm(nb + 1, 0), nrec(nb + 1, 0);
     parallel_parts(nb, off_cur, threads, [&](int i0, int i1) {
