@@ -333,7 +333,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       Vp[i] = ws.get<double>((size_t)k * k);
       sg[i] = ws.get<double>(k);
       ts.add(VXw[i], m, m, k, false, Rv[i], k);
-      jb.add(Rv[i], k, p1, k, Vp[i], k, sg[i], rk + i, 0.0, kVxRtol, nullptr, 0);
+      jb.add(Rv[i], k, p1, k, Vp[i], k, sg[i], rk + i, 0.0, kVxRtol, nullptr, 1);
     }
     g.run(ctx);
     ts.run(ctx);
