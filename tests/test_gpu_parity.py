@@ -211,6 +211,49 @@ def test_workload_full_size(key):
     assert np.abs(zm[idx] - np.array(gold["Zx"])).max() <= 2 * w.eps * np.min(gold["Zx_norm"])
 
 
+def test_workload_batched_full_size():
+    """The batched workload at full size: 64 independent 2-D products (n from
+    2048 to 32768, orders 3 to 5) in one call of each phase; per instance the
+    rank profiles of both phases (digest and per-level sums) and Z x at
+    sampled positions against the stored oracle results."""
+    import hashlib
+    path = os.path.join(HERE, "golden", "c4_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle results missing (tests/golden/make_golden.py c4 writes them)")
+    gold = json.load(open(path))
+    h2 = _h2()
+    c = ctx()
+    inst = W.batched_instances()
+    assert len(inst) == len(gold["instances"])
+    Ts, Xs = [], []
+    for w, pts in inst:
+        T = h2.Tree(c, pts, w.leaf_size, w.eta)
+        Ts.append(T)
+        Xs.append(h2.Matrix.kernel(c, T, w.kernel_x, w.order))
+    _say(f"[gpu] batched workload: {len(inst)} products, n total {sum(w.n for w, _ in inst)}")
+    Gs = h2.h2_mul_intermediate(c, Xs, Xs, inst[0][0].eps)
+    Zs = h2.h2_recompress(c, Gs, [h2.Matrix.zero(c, T) for T in Ts], inst[0][0].eps)
+    torch.cuda.synchronize()
+    for (w, _), G, Z, g in zip(inst, Gs, Zs, gold["instances"]):
+        assert g["n"] == w.n and g["order"] == w.order
+        prof = [G.ranks(0), G.ranks(1), Z.ranks(0), Z.ranks(1)]
+        lev = np.floor(np.log2(np.arange(len(prof[0])) + 1)).astype(int)
+        sums = [[int(np.asarray(p)[lev == l].sum()) for l in range(lev.max() + 1)] for p in prof]
+        assert sums == g["level_sums"], w.name
+        hsh = hashlib.sha256()
+        for p in prof:
+            hsh.update(np.asarray(p, dtype=np.int32).tobytes())
+        assert hsh.hexdigest() == g["rank_digest"], w.name
+        x = colmajor(W.probe_vectors(g["probe_seed"], w.n, 2))
+        zx = zeros_colmajor(w.n, 2)
+        Z.matvec(x, zx)
+        torch.cuda.synchronize()
+        zx = zx.cpu().numpy()
+        idx = np.array(g["index"])
+        assert np.abs(zx[idx] - np.array(g["Zx"])).max() <= 1e-10 * np.min(g["Zx_norm"]), w.name
+        assert np.allclose(np.linalg.norm(zx, axis=0), g["Zx_norm"], rtol=1e-10), w.name
+
+
 # ---------------------------------------------------------------------------
 # mixed form: bulk products on FP32 MFMA, factorizations and ranks in FP64.
 # Bar: relative Frobenius distance to the FP64 oracle <= 2 eps for G and Z
