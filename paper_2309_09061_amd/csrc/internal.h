@@ -225,10 +225,10 @@ void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* strea
 // rank of the singular values it wrote (problems with rule 1)
 void k_rank_relf(const JacobiProb* probs, int n, void* stream);
 // spectral norms: one wavefront per problem, per_doubles = norm2_need_doubles
-// of the largest g of the launch
+// of the largest g of the launch and the staging chunk (16, 32 or 64 samples)
 int norm2_max_dim();
-size_t norm2_need_doubles(int g);
-void k_norm2(const Norm2Prob* probs, int n, int per_doubles, void* stream);
+size_t norm2_need_doubles(int g, int chunk);
+void k_norm2(const Norm2Prob* probs, int n, int per_doubles, int chunk, void* stream);
 // medium problems (m <= jacobi_mid_max_m()) take 256-thread workgroups,
 // larger ones 1024 (wide)
 int jacobi_mid_max_m();

@@ -471,7 +471,7 @@ template <int NT>
 __global__ void jacobi_kernel(const JacobiProb* __restrict__ probs, int nprob, double* __restrict__ scratch,
                               size_t slot, int lds_cap);
 __global__ void jacobi_small_kernel(const JacobiProb* __restrict__ probs, int nprob, int per);
-__global__ void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per);
+__global__ void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per, int cshift);
 template <int G, int CPT, int RPT>
 __global__ void tsqr_rb_kernel(const TsqrProb* __restrict__ probs, int nprob);
 
@@ -1507,17 +1507,21 @@ void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* strea
 // Gram matrix squares the singular values, which costs nothing in the
 // relative accuracy of the largest one.
 // LDS per problem: Gram g^2 | Lanczos vectors by rows and by columns (2 g^2;
-// the sample staging of the Gram step, 64 g, shares this space) | w, h, and
-// the diagonal and off-diagonal of T (g each).
+// the sample staging of the Gram step, chunk x g, shares this space) | w, h,
+// and the diagonal and off-diagonal of T (g each).  The chunk (16, 32 or 64
+// samples) is the smallest that holds the longest side of the launch's
+// blocks, up to 64: short blocks then leave room for more wavefronts.
 // ---------------------------------------------------------------------------
 constexpr int kNorm2MaxG = 64;
 int norm2_max_dim() { return kNorm2MaxG; }
-static __host__ __device__ inline size_t norm2_need(int g) {
-  return (size_t)g * g + (size_t)max(2 * g * g, 64 * g) + 4 * (size_t)g;
+static __host__ __device__ inline size_t norm2_need(int g, int chunk) {
+  return (size_t)g * g + (size_t)max(2 * g * g, chunk * g) + 4 * (size_t)g;
 }
-size_t norm2_need_doubles(int g) { return norm2_need(g); }
+size_t norm2_need_doubles(int g, int chunk) { return norm2_need(g, chunk); }
 
-__global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per) {
+__global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per,
+                                                     int cshift) {
+  const int chunk = 1 << cshift;  // samples staged per step (16, 32 or 64)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int pi = blockIdx.x * (blockDim.x >> 6) + wave;
   if (pi >= nprob) return;  // whole wavefront; no workgroup barriers below
@@ -1544,20 +1548,20 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   double* Gm = lds_dyn + (size_t)wave * per;
   double* Qr = Gm + g * g;  // Qr[t g + i]: component i of Lanczos vector t
   double* Qt = Qr + g * g;  // Qt[i g + t]: the same, transposed
-  double* X = Qr;           // staging of 64 samples (rows, or columns) x g
-  double* Wv = Gm + g * g + max(2 * g * g, 64 * g);
+  double* X = Qr;           // staging of `chunk` samples (rows, or columns) x g
+  double* Wv = Gm + g * g + max(2 * g * g, chunk * g);
   double* Hv = Wv + g;
   double* Ta = Hv + g;
   double* Tb = Ta + g;
 
-  // ---- Gram matrix, upper triangle accumulated over chunks of 64 samples ----
+  // ---- Gram matrix, upper triangle accumulated over chunks of samples ----
   for (int e = lane; e < g * g; e += 64) Gm[e] = 0.0;
-  for (int s0 = 0; s0 < ns; s0 += 64) {
-    const int cnt = min(64, ns - s0);
+  for (int s0 = 0; s0 < ns; s0 += chunk) {
+    const int cnt = min(chunk, ns - s0);
     team_sync<64>();  // the previous chunk's reads are done
     if (tall) {
-      for (int e = lane; e < 64 * g; e += 64) {
-        const int sm = e & 63, f = e >> 6;
+      for (int e = lane; e < chunk * g; e += 64) {
+        const int sm = e & (chunk - 1), f = e >> cshift;
         if (sm < cnt) X[sm * g + f] = sc * P.A[(s0 + sm) + (int64_t)f * P.lda];
       }
     } else {
@@ -1676,13 +1680,15 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   if (lane == 0) *P.out = ldexp(sqrt(0.5 * (lo + hi) * dmax), ex);
 }
 
-void k_norm2(const Norm2Prob* probs, int n, int per_doubles, void* stream) {
+void k_norm2(const Norm2Prob* probs, int n, int per_doubles, int chunk, void* stream) {
   if (n <= 0) return;
+  H2_REQUIRE(chunk == 16 || chunk == 32 || chunk == 64, H2_ERR_ARG, "norm2: chunk must be 16, 32 or 64");
   int wpb = std::min(4, lds_limit_doubles() / std::max(per_doubles, 1));
   if (n < 4 * 256) wpb = std::min(wpb, 1);
   H2_REQUIRE(wpb >= 1, H2_ERR_ARG, "norm2: problems too large");
+  const int cshift = chunk == 16 ? 4 : chunk == 32 ? 5 : 6;
   hipLaunchKernelGGL(norm2_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), (size_t)wpb * per_doubles * 8,
-                     (hipStream_t)stream, probs, n, per_doubles);
+                     (hipStream_t)stream, probs, n, per_doubles, cshift);
   HIP_OK(hipGetLastError());
 }
 

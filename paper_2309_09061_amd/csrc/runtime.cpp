@@ -872,7 +872,10 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
   if (!np.empty()) {
     Norm2Prob* d = upload_launch(ctx, np);
     LaunchTimer lt(ctx, KK_OTHER, nflops, nbytes);
-    k_norm2(d, (int)np.size(), (int)norm2_need_doubles(gmax), ctx->stream);
+    int ns_max = 0;
+    for (const Norm2Prob& q : np) ns_max = std::max(ns_max, std::max(q.rows, q.cols));
+    const int chunk = ns_max <= 16 ? 16 : ns_max <= 32 ? 32 : 64;
+    k_norm2(d, (int)np.size(), (int)norm2_need_doubles(gmax, chunk), chunk, ctx->stream);
   }
   ts.run(ctx);
   jb.run(ctx);
