@@ -135,8 +135,9 @@ h2_status h2_compress_kernel(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel,
  * the column basis; Section 5 block scaling; intermediate product G on
  * T^XY).  X[i] and Y[i] must be built on the same cluster tree.
  *   eps > = 0: ranks keep the singular values > eps of the block-scaled
- *              matrices; eps = 0 keeps every non-zero singular value and G
- *              then represents X Y exactly.
+ *              matrices (the default rule; h2_set_rank_rule selects the
+ *              relative-Frobenius variant); eps = 0 keeps every non-zero
+ *              singular value and G then represents X Y exactly.
  * G_out[i] receives a new handle per product. */
 h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
                               const h2_matrix* const* Y, double eps, h2_precision prec,
@@ -149,7 +150,8 @@ h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix** Z_out);
  * isometric nested row and column bases for Z's block tree T_IK from G and
  * stores Z <- Z + G in them.  Each Z[i] must be zero (h2_zero_like) and its
  * block tree must be refined by T^XY (H2_ERR_NOT_REFINED otherwise).
- * Block-relative accuracy eps per admissible block of T_IK. */
+ * Block-relative accuracy eps per admissible block of T_IK (truncation rule
+ * as set by h2_set_rank_rule). */
 h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix* const* Z,
                         double eps, h2_precision prec);
 
