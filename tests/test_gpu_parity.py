@@ -153,10 +153,11 @@ def test_phase2_parity(name):
     assert np.linalg.norm(Zg - XY, 2) / np.linalg.norm(XY, 2) <= eps
 
 
-def test_exact_without_truncation():
+@pytest.mark.parametrize("name", ["2d", "sph", "ragged", "1d"])
+def test_exact_without_truncation(name):
     """eps = 0: both phases reproduce X Y to rounding."""
-    _, tree, _, _, _, _, Xd, Yd = oracle_case("2d", 0.0)
-    _, _, _, G, Z = gpu_case("2d", 0.0)
+    _, tree, _, _, _, _, Xd, Yd = oracle_case(name, 0.0)
+    _, _, _, G, Z = gpu_case(name, 0.0)
     XY = Xd @ Yd
     assert relF(dense_of(G, tree.n), XY) < 1e-12
     assert relF(dense_of(Z, tree.n), XY) < 1e-12
