@@ -370,3 +370,22 @@ def test_single_leaf_tree():
     XY = dense_of(X, n) @ dense_of(Y, n)
     assert relF(dense_of(G, n), XY) < 1e-13
     assert relF(dense_of(Z, n), XY) < 1e-13
+
+
+def test_recompress_rejects_nonzero_target():
+    """R16: Z <- Z + G is supported for Z = 0 only; a Z that already holds a
+    result is refused with H2_ERR_UNSUPPORTED, and the refused call leaves
+    the context usable."""
+    h2 = _h2()
+    c = ctx()
+    pts = W.make_points(12, 300, 2, "uniform")
+    T = h2.Tree(c, pts, 32, 1.0)
+    X = h2.Matrix.kernel(c, T, "log", 3)
+    G = h2.h2_mul_intermediate(c, X, X, 1e-6)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
+    with pytest.raises(h2.H2Error) as e:
+        h2.h2_recompress(c, G, Z, 1e-6)
+    assert e.value.code == 6
+    Z2 = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
+    torch.cuda.synchronize()
+    assert relF(dense_of(Z2, 300), dense_of(Z, 300)) < 1e-14
