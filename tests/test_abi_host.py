@@ -65,6 +65,12 @@ def test_error_paths_host_only():
     with pytest.raises(h2.H2Error) as e:
         h2.Tree(ctx, bad, 16, 1.0)
     assert e.value.code == 7
+    with pytest.raises(h2.H2Error) as e:        # empty point set
+        h2.Tree(ctx, np.zeros((0, 2)), 16, 1.0)
+    assert e.value.code == 1 and "n must be positive" in str(e.value)
+    with pytest.raises(h2.H2Error) as e:        # dimension outside 1..3
+        h2.Tree(ctx, np.zeros((8, 4)), 16, 1.0)
+    assert e.value.code == 1 and "dim" in str(e.value)
     T = h2.Tree(ctx, pts, 16, 1.0)
     with pytest.raises(h2.H2Error) as e:        # device work on a host-only context
         h2.Matrix.kernel(ctx, T, "log", 3)
