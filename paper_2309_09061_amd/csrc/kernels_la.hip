@@ -322,38 +322,75 @@ __global__ __launch_bounds__(256) void gemm_tri_block_kernel(const TriOut* __res
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = M::zero();
-  for (int t = o.q0; t < o.q1; ++t) {
-    const int4 tr = reinterpret_cast<const int4*>(F.tri)[t];
-    if (tr.w != F.kind) continue;  // uniform across the workgroup
-    const double* A = F.A[tr.y];
-    const double* B = F.B[tr.z];
-    const int64_t lda = F.lda[tr.y], ldb = F.ldb[tr.z];
-    const int k = F.ks ? F.ks[tr.x] : F.k;
-    for (int l0 = 0; l0 < k; l0 += kTriKC) {
-      __syncthreads();  // previous chunk consumed
-      // A chunk: 64 x 16, consecutive threads along i
-      for (int e = tid; e < 64 * kTriKC; e += 256) {
-        const int i = e & 63, l = e >> 6;
-        As[i + l * kTriLdA] = (i < o.m && l0 + l < k) ? A[i + (int64_t)(l0 + l) * lda] : 0.0;
-      }
-      // B chunk: 16 x 64, consecutive threads along l (down a column)
-      for (int e = tid; e < 64 * kTriKC; e += 256) {
-        const int l = e & (kTriKC - 1), j = e / kTriKC;
-        Bs[l + j * kTriLdB] = (j < o.n && l0 + l < k) ? B[(l0 + l) + (int64_t)j * ldb] : 0.0;
-      }
-      __syncthreads();
+  // The output's (triple, chunk) sequence, software-pipelined: each thread
+  // holds its share of the next chunk of A and B in registers, loaded while
+  // the MFMA steps consume the current chunk from LDS.
+  const int4* tri = reinterpret_cast<const int4*>(F.tri);
+  auto next_triple = [&](int t) {  // first triple of this family at or after t (uniform)
+    while (t < o.q1 && tri[t].w != F.kind) ++t;
+    return t;
+  };
+  constexpr int kPer = 64 * kTriKC / 256;  // elements of each operand chunk per thread
+  const double* A = nullptr;
+  const double* B = nullptr;
+  int64_t lda = 0, ldb = 0;
+  int k = 0;
+  auto bind = [&](int t) {
+    const int4 tr = tri[t];
+    A = F.A[tr.y];
+    B = F.B[tr.z];
+    lda = F.lda[tr.y];
+    ldb = F.ldb[tr.z];
+    k = F.ks ? F.ks[tr.x] : F.k;
+  };
+  double ra[kPer], rb[kPer];
+  // operands live in device memory: global loads (counted on vmcnt only)
+  // stay in flight past the LDS reads of the MFMA steps, flat loads would not
+  using gdouble = const __attribute__((address_space(1))) double;
+  auto fetch = [&](int l0) {
+    gdouble* Ag = (gdouble*)A;
+    gdouble* Bg = (gdouble*)B;
 #pragma unroll
-      for (int ls = 0; ls < kTriKC; ls += 4) {
-        double av[2], bv[2];
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int i = e & 63, la = e >> 6;                // A chunk: consecutive threads along i
+      ra[u] = (i < o.m && l0 + la < k) ? Ag[i + (int64_t)(l0 + la) * lda] : 0.0;
+      const int lb = e & (kTriKC - 1), j = e / kTriKC;  // B chunk: consecutive threads down a column
+      rb[u] = (j < o.n && l0 + lb < k) ? Bg[(l0 + lb) + (int64_t)j * ldb] : 0.0;
+    }
+  };
+  int t = next_triple(o.q0), l0 = 0;
+  if (t < o.q1) {
+    bind(t);
+    fetch(0);
+  }
+  while (t < o.q1) {
+    __syncthreads();  // previous chunk consumed
 #pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = As[(wi + 16 * a + r) + (ls + q) * kTriLdA];
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      As[(e & 63) + (e >> 6) * kTriLdA] = ra[u];
+      Bs[(e & (kTriKC - 1)) + (e / kTriKC) * kTriLdB] = rb[u];
+    }
+    __syncthreads();
+    l0 += kTriKC;
+    if (l0 >= k) {
+      t = next_triple(t + 1);
+      l0 = 0;
+      if (t < o.q1) bind(t);
+    }
+    if (t < o.q1) fetch(l0);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Bs[(ls + q) + (wj + 16 * b + r) * kTriLdB];
+    for (int ls = 0; ls < kTriKC; ls += 4) {
+      double av[2], bv[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 2; ++a) av[a] = As[(wi + 16 * a + r) + (ls + q) * kTriLdA];
 #pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = M::step(av[a], bv[b], acc[a][b]);
-      }
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[(ls + q) + (wj + 16 * b + r) * kTriLdB];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = M::step(av[a], bv[b], acc[a][b]);
     }
   }
 #pragma unroll
