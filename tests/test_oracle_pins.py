@@ -130,6 +130,44 @@ def test_kernel_entries_and_diagonal():
     assert np.all(np.diag(Xd) == 0.0) and np.all(np.diag(Yd) == 1.0)
 
 
+def _raw_kernel(kind, pts):
+    """The kernel matrix written from its definition on the raw points in
+    input order (Section 7, single-layer kernel 1/(4 pi |x-y|); 1/|x-y| of the
+    volume workload), zero diagonal (R5)."""
+    d = pts[:, None, :] - pts[None, :, :]
+    r = np.sqrt((d * d).sum(axis=-1))
+    with np.errstate(divide="ignore"):
+        K = 1.0 / r if kind == "inv" else 1.0 / (4.0 * np.pi * r)
+    np.fill_diagonal(K, 0.0)
+    return K
+
+
+@pytest.mark.parametrize("kind,dist,seed", [("inv4pi", "sphere", 3), ("inv", "uniform", 5)])
+def test_singular_kernel_entries_from_raw_points(kind, dist, seed):
+    """The singular kernels of the sphere and cube workloads against the raw
+    kernel matrix: nearfield entries exactly, the interpolated far field
+    within the interpolation error, which shrinks with the order (so a wrong
+    constant, power or diagonal in the oracle's kernel fails here)."""
+    pts = W.make_points(seed, 512, 3, dist)
+    tree = O.ClusterTree(pts, 32)
+    bt = O.BlockTree(tree, tree, 2.0)
+    Kc = _raw_kernel(kind, pts)[np.ix_(tree.perm, tree.perm)]
+    errs = []
+    for order in (3, 5):
+        X = O.kernel_h2(tree, bt, kind, order)
+        Xd = X.dense()
+        for (t, s) in X.N:
+            blk = Kc[tree.rng(t), tree.rng(s)]
+            assert np.array_equal(Xd[tree.rng(t), tree.rng(s)], blk)
+        assert np.all(np.diag(Xd) == 0.0)
+        for (t, s) in X.S:
+            blk = Kc[tree.rng(t), tree.rng(s)]
+            assert np.abs(Xd[tree.rng(t), tree.rng(s)] - blk).max() <= 0.1 * np.abs(blk).max()
+        errs.append(relF(Xd, Kc))
+    assert errs[0] < 2e-3
+    assert errs[1] < errs[0] / 5
+
+
 # --------------------------------------------------------------------------
 # P3-P5: set-up quantities (basis weights, basis products, total weights)
 # --------------------------------------------------------------------------
@@ -193,6 +231,31 @@ def test_phase1_basis_isometric_and_keeps_VX(name, eps):
             res = VX[t] - Q @ (Q.T @ VX[t])
             # the numerical range (relative tolerance 1e-12) is kept exactly
             assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(VX[t])
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "2d64"])
+@pytest.mark.parametrize("eps", [0.0, 1e-6])
+def test_phase1_kept_range_is_thin_householder_factor(name, eps):
+    """Where V_{X,t} has full numerical rank (the 1-D and 2-D cases), the
+    kept part of Q_t reduces to the paper's literal construction (Section 4,
+    leaf case): k1 = min(k, rows of V_{X,t}) on every cluster, and the first
+    k1 columns of Q_t span the range of the thin Householder factor of
+    V_{X,t} (the 2-D and 1-D inputs have no numerical rank deficiency)."""
+    _, tree, _, X, _ = problem(name)
+    p1, _ = product(name, eps)
+    k = X.V.rank[0]
+    for side in (p1.row, p1.col):
+        for t in range(tree.nclusters):
+            VX = side.assembled[t][0]
+            k1 = side.RX[t].shape[0]
+            assert k1 == min(k, VX.shape[0]), (t, k1, VX.shape)
+            if tree.is_leaf(t):
+                Qt = side.Q.leaf[t]
+            else:
+                Qt = np.vstack([side.Q.transfer[ch] for ch in tree.children[t]])
+            Qh, _ = np.linalg.qr(VX)               # thin Householder factor
+            P1 = Qt[:, :k1] @ Qt[:, :k1].T
+            assert np.abs(P1 - Qh @ Qh.T).max() < 1e-12
 
 
 @pytest.mark.parametrize("name", CASES)
