@@ -1,12 +1,29 @@
 """Benchmark of the adaptive H^2 product Z = X Y on one MI355X.
 
-One step is the whole hot path on the 2-D workload (n = 16384 points in the
-unit square, X = log|x-y|, Y = exp(-|x-y|), leaf 64, eta 1, Chebyshev order
-4 -> k = 16, eps = 1e-6): phase 1 (h2_mul_intermediate: induced bases and G
-on T^XY) and phase 2 (h2_recompress into Z's block tree).  Inputs (tree,
-X, Y) are resident on the GPU before timing.  Prints one JSON line.
+One step is the whole hot path on one workload: phase 1 (h2_mul_intermediate:
+induced bases and the intermediate product G on T^XY) and phase 2
+(h2_recompress into Z's block tree), with the inputs (tree, X, Y) resident on
+the GPU before timing.  The headline workload is the sphere workload: n =
+131072 points on the unit sphere, single-layer kernel 1/(4 pi |x-y|), X = Y,
+leaf 64, eta 2, Chebyshev order 3 (k = 27), eps = 1e-4; the 2-D workload
+(n = 16384, log / exp(-r), k = 16, eps = 1e-6) is reported beside it.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|fp64|fp32]
+For each workload and form (FP64, and the mixed form with bulk products in
+reduced precision):
+  - `steps` uninstrumented steps after `warmup` give the time per step (the
+    headline value and the mixed form's speed-up);
+  - two further steps with HIP events around every launch give the time per
+    kernel family and the dominant family;
+  - `steps` further steps with events around the dominant family's launches
+    only give its average launch duration, measured on the stream it runs on;
+    the roofline's numerator is the oracle's algorithmic work for that
+    family's kind per step (stored with the oracle's results);
+  - the results are checked against the stored oracle results (relative
+    Frobenius distance of G and Z over 32 seeded probes, two-sided sketch)
+    and against X Y (relative spectral error by power iteration).
+Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2]
 """
 from __future__ import annotations
 
@@ -20,46 +37,62 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published peaks
-PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "fp64_vector": 78.6e12, "hbm": 8.0e12}
-
-
-def cpu_baseline(seconds_budget: float = 30.0):
-    """The FP64 oracle on a bounded sample of the same workload: the same recipe
-    (seeded points, kernels, leaf size, order, eps) at n = 4096, extrapolated
-    linearly to n = 16384 (the method's cost is O(n))."""
-    import numpy as np
-
-    import oracle as O
-    import workloads as W
-    w = W.C2
-    n_s = 4096
-    pts = W.make_points(w.seed, n_s, w.dim, w.distribution)
-    tree, bt, X, Y = O.build_problem(pts, w.leaf_size, w.eta, w.order, w.kernel_x, w.kernel_y)
-    t0 = time.perf_counter()
-    O.multiply(X, Y, bt, w.eps)
-    dt = time.perf_counter() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = 1
-    return {"value": dt * w.n / n_s, "unit": "s", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle phase 1 + phase 2 on the same recipe at n={n_s} ({dt:.2f} s), "
-                      f"scaled by n={w.n}/{n_s} (linear complexity)"}
-
-
+PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "fp64_vector": 78.6e12,
+        "hbm": 8.0e12}
+# kernel family of the library -> kind of algorithmic work in the oracle's ledger
+FAMILY_KIND = {"gemm_sum": ("gemm",), "tsqr": ("qr",), "jacobi": ("svd",), "other": ("norm", "sumsq")}
 FAMILY_KERNELS = {"gemm_sum": ("gemm_sum_kernel", "gemm_tri_kernel", "gemm_tri_block_kernel", "chain3_kernel"),
                   "tsqr": ("tsqr_rb_kernel", "tsqr_kernel"),
                   "jacobi": ("jacobi_kernel", "jacobi_small_kernel")}
+STEP_NAMES = ("setup", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat")
 
 
-def measured_traffic(family: str, precision: str):
+def _threads_used():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, gold):
+    """The FP64 oracle, as it stands, on two bounded samples of the same
+    workload recipe (the same seeded generator, kernel, leaf size, eta, order
+    and eps with fewer points): t(n) = a n^b is fitted through the two timings
+    and evaluated at the workload's n.  The oracle's time on the identical
+    full-size input, measured when its stored results were written, is
+    reported beside the estimate."""
+    import oracle as O
+    import workloads as W
+    samples = {"c3": (8192, 16384), "c2": (4096, 8192)}[w.name[:2]]
+    times = []
+    for n_s in samples:
+        pts = W.make_points(w.seed, n_s, w.dim, w.distribution)
+        tree, bt, X, Y = O.build_problem(pts, w.leaf_size, w.eta, w.order, w.kernel_x, w.kernel_y)
+        t0 = time.perf_counter()
+        O.multiply(X, Y, bt, w.eps)
+        times.append(time.perf_counter() - t0)
+        print(f"[cpu] oracle at n={n_s}: {times[-1]:.1f} s", file=sys.stderr, flush=True)
+    import math
+    b = math.log(times[1] / times[0]) / math.log(samples[1] / samples[0])
+    est = times[1] * (w.n / samples[1]) ** b
+    full = ""
+    if gold:
+        full = (f"; the oracle on the identical n={w.n} input took {gold['oracle_seconds']:.0f} s "
+                f"with {gold.get('oracle_threads')} threads on the host that wrote its stored results")
+    return {"value": est, "unit": "s", "cores": int(_threads_used()), "kind": "oracle",
+            "sample": f"oracle phases 1 + 2 on the same recipe at n={samples[0]} ({times[0]:.1f} s) and "
+                      f"n={samples[1]} ({times[1]:.1f} s); t = a n^b fitted (b = {b:.2f}) and evaluated at "
+                      f"n={w.n}{full}"}
+
+
+def measured_traffic(workload: str, family: str, precision: str):
     """HBM bytes per launch of a kernel family from the committed counter
     summary (calibrated FETCH_SIZE + WRITE_SIZE), or None when the summary is
     missing or the kernels changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"traffic_2d_n16384_{precision}.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.md")
     src = os.path.join(ROOT, "paper_2309_09061_amd", "csrc", "kernels_la.hip")
     if not os.path.exists(path):
         return None
@@ -90,43 +123,155 @@ def copy_calibration():
     print(f"copied {a.numel() * 8} bytes", flush=True)
 
 
-def run_form(ctx, T, X, Y, w, precision, steps, warmup, families=None):
-    """Warm-up, then `steps` timed steps of the hot path in one precision;
-    launches of the kernel families named in `families` (all when None) are
-    timed with HIP events inside the timed region."""
-    import torch
+class Problem:
+    def __init__(self, w):
+        import torch
 
-    from paper_2309_09061_amd import h2
+        from paper_2309_09061_amd import h2
+        self.w = w
+        self.ctx = h2.Context(0)
+        self.T = h2.Tree(self.ctx, w.points(), w.leaf_size, w.eta)
+        self.X = h2.Matrix.kernel(self.ctx, self.T, w.kernel_x, w.order)
+        self.Y = self.X if w.kernel_y == w.kernel_x else h2.Matrix.kernel(self.ctx, self.T, w.kernel_y, w.order)
+        torch.cuda.synchronize()
 
-    def step():
-        G = h2.h2_mul_intermediate(ctx, X, Y, w.eps, precision)
-        Z = h2.h2_recompress(ctx, G, h2.Matrix.zero(ctx, T), w.eps, precision)
+    def step(self, precision):
+        from paper_2309_09061_amd import h2
+        G = h2.h2_mul_intermediate(self.ctx, self.X, self.Y, self.w.eps, precision)
+        Z = h2.h2_recompress(self.ctx, G, h2.Matrix.zero(self.ctx, self.T), self.w.eps, precision)
         return G, Z
 
-    for i in range(warmup):
-        G, Z = step()
-        torch.cuda.synchronize()
-        print(f"[{precision}] warmup step {i + 1}/{warmup} done", file=sys.stderr, flush=True)
-        del G, Z
-    ctx.profile(True, families)
+
+def run_steps(P, precision, steps, families=None, label=""):
+    """`steps` steps, synchronised before and after; launches of the named
+    kernel families (none when families is None) carry HIP events."""
+    import torch
+    ctx = P.ctx
+    if families:
+        ctx.profile(True, families)
     ctx.kernel_stats(reset=True)
     ctx.step_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    G = Z = None
     for i in range(steps):
-        G, Z = step()
-        if i < steps - 1:
-            del G, Z
+        del G, Z
+        G, Z = P.step(precision)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dev = ctx.step_times()
     host = ctx.step_times(host=True, reset=True)
-    ks = ctx.kernel_stats()
+    ks = ctx.kernel_stats(reset=True)
     ctx.profile(False)
-    print(f"[{precision}] {steps} timed steps done ({'all' if families is None else ','.join(families)} "
-          f"kernel families timed)", file=sys.stderr, flush=True)
+    print(f"[{P.w.name[:2]} {precision}] {steps} {label} steps done", file=sys.stderr, flush=True)
     return {"ms": (t1 - t0) / steps * 1e3, "dev": {k: v / steps for k, v in dev.items()},
-            "host": {k: v / steps for k, v in host.items()}, "ks": ks, "G": G, "Z": Z, "steps": steps}
+            "host": {k: v / steps for k, v in host.items()}, "ks": ks, "G": G, "Z": Z}
+
+
+def power_eps2(P, Z, seed=104, steps=20):
+    """||Z - X Y||_2 / ||X Y||_2, each norm by power iteration on A^T A from
+    the same seeded vector, all products through h2_matvec."""
+    import torch
+
+    import workloads as W
+    n = P.w.n
+
+    def mv(A, v, op="N"):
+        out = torch.zeros((1, n), dtype=torch.float64, device="cuda").t()
+        A.matvec(v, out, op=op)
+        return out
+
+    def norm2(apply, applyT):
+        v = torch.from_numpy(W.probe_vectors(seed, n, 1).T.copy()).cuda().t()
+        v /= torch.linalg.norm(v)
+        lam = 0.0
+        for _ in range(steps):
+            w = applyT(apply(v))
+            lam = float(torch.linalg.norm(w))
+            if lam == 0.0:
+                return 0.0
+            v = w / lam
+        return lam ** 0.5
+    X, Y = P.X, P.Y
+    e = norm2(lambda v: mv(Z, v) - mv(X, mv(Y, v)), lambda v: mv(Z, v, "T") - mv(Y, mv(X, v, "T"), "T"))
+    r = norm2(lambda v: mv(X, mv(Y, v)), lambda v: mv(Y, mv(X, v, "T"), "T"))
+    return e / r
+
+
+def oracle_distance(P, M, gold, key):
+    """Relative Frobenius distance of M (G or Z) to the oracle's, over all n
+    entries of 32 seeded probes (two-sided sketch stored with the oracle's
+    results); None without stored results."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    if not gold:
+        return None
+    n = P.w.n
+    om = torch.from_numpy(np.ascontiguousarray(W.probe_vectors(gold["probe_seed"], n, gold["nprobe"]).T)).cuda().t()
+    out = torch.zeros((gold["nprobe"], n), dtype=torch.float64, device="cuda").t()
+    M.matvec(om, out)
+    torch.cuda.synchronize()
+    sk = W.probe_vectors(gold["sketch_seed"], n, gold["nprobe"]).T @ out.cpu().numpy()
+    ref = np.array(gold["sketch_" + key])
+    return float(np.linalg.norm(sk - ref) / np.linalg.norm(ref))
+
+
+def measure_form(P, precision, steps, warmup, gold, peak_bulk):
+    """Time, breakdown, roofline and errors of one form on one workload."""
+    import torch
+    for i in range(warmup):
+        G, Z = P.step(precision)
+        torch.cuda.synchronize()
+        del G, Z
+    print(f"[{P.w.name[:2]} {precision}] {warmup} warm-up steps done", file=sys.stderr, flush=True)
+    plain = run_steps(P, precision, steps, None, "uninstrumented")
+    nb = 2
+    br = run_steps(P, precision, nb, ["gemm_sum", "tsqr", "jacobi", "build", "other"], "all-launch-timed")
+    fam_ms = {k: v["ms"] / nb for k, v in br["ks"].items()}
+    dom = max(fam_ms, key=fam_ms.get)
+    del br
+    rr = run_steps(P, precision, steps, [dom], f"{dom}-timed")
+    d = rr["ks"][dom]
+    led = (gold or {}).get("ledger", {})
+    kind_flops = sum(led.get(s, {}).get(k, 0.0) for s in STEP_NAMES for k in FAMILY_KIND.get(dom, ()))
+    avg_launch_s = d["ms"] * 1e-3 / max(d["launches"], 1)
+    launches_per_step = d["launches"] / steps
+    fam_s_per_step = d["ms"] * 1e-3 / steps
+    if dom == "gemm_sum":
+        bound, peak = "mfma", peak_bulk
+    else:
+        bound, peak = "alu", PEAK["fp64_vector"]
+    achieved = kind_flops / fam_s_per_step if fam_s_per_step > 0 else 0.0
+    gemm_flops = sum(led.get(s, {}).get("gemm", 0.0) for s in STEP_NAMES)
+    G, Z = plain["G"], plain["Z"]
+    res = {
+        "ms_per_step": plain["ms"],
+        "step_ms": plain["dev"], "host_step_ms": plain["host"],
+        "kernel_ms_per_step": fam_ms,
+        "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(P.w.name[:2], dom, "fp64" if precision == "fp64" else "mixed"),
+                     "avg_launch_ms": avg_launch_s * 1e3, "launches_per_step": launches_per_step,
+                     "flops_per_launch": kind_flops / max(launches_per_step, 1e-30),
+                     "flops_source": f"oracle work ledger, kind {'+'.join(FAMILY_KIND.get(dom, ()))}"},
+        "mfma_util_step": gemm_flops / (plain["ms"] * 1e-3) / peak_bulk,
+        "error": {"G_relF_vs_oracle": oracle_distance(P, G, gold, "G"),
+                  "Z_relF_vs_oracle": oracle_distance(P, Z, gold, "Z"),
+                  "Z_eps2_vs_XY": power_eps2(P, Z),
+                  "oracle_eps2_vs_XY": (gold or {}).get("eps2_Z")},
+        "ranks": {"p1_row_max": int(G.ranks(0).max()), "p2_row_max": int(Z.ranks(0).max()),
+                  "p2_row_mean": float(Z.ranks(0).mean())},
+        "product_tree": G.sizes(),
+    }
+    del rr
+    return res
+
+
+def load_gold(w):
+    path = os.path.join(ROOT, "tests", "golden", f"{w.name[:2]}_oracle.json")
+    return json.load(open(path)) if os.path.exists(path) else None
 
 
 def main():
@@ -134,12 +279,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="both", choices=["both", "fp64", "fp32"],
-                    help="fp64: the float64 form; fp32: bulk products in float32; both: "
-                         "the float64 form as the headline value, the mixed form beside it")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2"],
+                    help="headline workload (the other one is reported beside it)")
+    ap.add_argument("--no-side", action="store_true", help="skip the second workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB on the GPU (the reference for the HBM traffic counters) and exit")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run only this many FP64 steps of the headline workload (for profilers) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -149,82 +296,65 @@ def main():
               "(the multi-GPU layout is a design note, not a run)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import workloads as W
-    from paper_2309_09061_amd import h2
+    main_w = W.C3 if args.workload == "c3" else W.C2
+    side_w = W.C2 if args.workload == "c3" else W.C3
+    mixed_prec = "fp32"
+    mixed_name = "fp32 bulk products (FP32 MFMA), fp64 factorizations, ranks and norms"
 
-    w = W.C2
-    ctx = h2.Context(0)
-    T = h2.Tree(ctx, w.points(), w.leaf_size, w.eta)
-    X = h2.Matrix.kernel(ctx, T, w.kernel_x, w.order)
-    Y = h2.Matrix.kernel(ctx, T, w.kernel_y, w.order)
+    if args.profile_steps:
+        P = Problem(main_w)
+        for i in range(args.profile_steps):
+            G, Z = P.step("fp64")
+            torch.cuda.synchronize()
+            print(f"[profile] step {i + 1}/{args.profile_steps} done", flush=True)
+            del G, Z
+        return
+
+    gold = load_gold(main_w)
+    P = Problem(main_w)
+    f64 = measure_form(P, "fp64", args.steps, args.warmup, gold, PEAK["fp64_mfma"])
+    mix = measure_form(P, mixed_prec, args.steps, args.warmup, gold, PEAK["fp32_mfma"])
+    del P
     torch.cuda.synchronize()
-
-    main_prec = "fp32" if args.precision == "fp32" else "fp64"
-    # breakdown run: every launch timed (the events add host time per launch),
-    # giving the per-family kernel time and the dominant family
-    nb = max(2, min(args.steps, 3))
-    br = run_form(ctx, T, X, Y, w, main_prec, nb, args.warmup)
-    bks = br["ks"]
-    dom = max(bks, key=lambda k: bks[k]["ms"])
-    del br
-    # headline run: only the dominant family's launches carry events
-    r = run_form(ctx, T, X, Y, w, main_prec, args.steps, 1, families=[dom])
-    G, Z, ks, ms = r["G"], r["Z"], r["ks"], r["ms"]
-    ranks = {"p1_row_max": int(G.ranks(0).max()), "p2_row_max": int(Z.ranks(0).max()),
-             "p2_row_mean": float(Z.ranks(0).mean())}
-    sizes = G.sizes()
-
-    d = ks[dom]
-    mfma_peak = PEAK["fp64_mfma" if main_prec == "fp64" else "fp32_mfma"]
-    if dom == "gemm_sum":
-        bound, peak = "mfma", mfma_peak
-    else:
-        bound, peak = "alu", PEAK["fp64_vector"]
-    achieved = d["flops"] / (d["ms"] * 1e-3) if d["ms"] > 0 else 0.0
-    gemm = bks["gemm_sum"]
-    mfma_util = gemm["flops"] / nb / (ms * 1e-3) / mfma_peak
-
+    w = main_w
     out = {
         "metric": "H^2 product time (s) and MFMA util at eps; mixed vs FP64 on one MI355X",
-        "value": ms * 1e-3, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if main_prec == "fp64" else "f32-bulk/f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "dim": w.dim, "leaf": w.leaf_size, "eta": w.eta,
-                   "order": w.order, "rank": w.rank, "kernel_x": w.kernel_x, "kernel_y": w.kernel_y,
-                   "eps": w.eps, "precision": main_prec},
-        "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom, main_prec),
-                     "avg_launch_ms": d["ms"] / max(d["launches"], 1),
-                     "flops_per_launch": d["flops"] / max(d["launches"], 1)},
-        "mfma_util_step": mfma_util,
-        "kernel_ms_per_step": {k: v["ms"] / nb for k, v in bks.items()},
-        "kernel_ms_per_step_note": f"from {nb} further steps with every launch timed",
-        "step_ms": r["dev"],
-        "host_step_ms": r["host"],
-        "ranks": ranks, "product_tree": sizes,
+        "value": f64["ms_per_step"] * 1e-3, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f64["ms_per_step"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "dim": w.dim, "points": w.distribution, "leaf": w.leaf_size,
+                   "eta": w.eta, "order": w.order, "rank": w.rank, "kernel_x": w.kernel_x,
+                   "kernel_y": w.kernel_y, "eps": w.eps, "precision": "fp64"},
+        "roofline": f64["roofline"],
+        "mfma_util_step": f64["mfma_util_step"],
+        "kernel_ms_per_step": f64["kernel_ms_per_step"],
+        "kernel_ms_per_step_note": "from 2 further steps with every launch timed",
+        "step_ms": f64["step_ms"], "host_step_ms": f64["host_step_ms"],
+        "error": f64["error"], "ranks": f64["ranks"], "product_tree": f64["product_tree"],
+        "mixed": {"precision": mixed_name, "ms_per_step": mix["ms_per_step"],
+                  "speedup_vs_fp64": f64["ms_per_step"] / mix["ms_per_step"],
+                  "error": mix["error"], "roofline": mix["roofline"],
+                  "kernel_ms_per_step": mix["kernel_ms_per_step"], "step_ms": mix["step_ms"],
+                  "mfma_util_step": mix["mfma_util_step"]},
+        "oracle_work_per_step": {s: v for s, v in (gold or {}).get("ledger", {}).items()},
     }
-    if args.precision == "both":
-        m = run_form(ctx, T, X, Y, w, "fp32", args.steps, args.warmup, families=["gemm_sum"])
-        # distance of the mixed Z to the float64 Z on seeded probe vectors
-        x = torch.from_numpy(np.ascontiguousarray(W.probe_vectors(7, w.n, 2).T)).cuda().t()
-        z64 = torch.zeros((2, w.n), dtype=torch.float64, device="cuda").t()
-        z32 = torch.zeros((2, w.n), dtype=torch.float64, device="cuda").t()
-        Z.matvec(x, z64)
-        m["Z"].matvec(x, z32)
-        torch.cuda.synchronize()
-        diff = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
-        mg = m["ks"]["gemm_sum"]
-        out["mixed"] = {"precision": "fp32 bulk products, fp64 factorizations", "ms_per_step": m["ms"],
-                        "speedup_vs_fp64": ms / m["ms"], "rel_diff_Zx_vs_fp64": diff,
-                        "gemm_ms_per_step": mg["ms"] / m["steps"],
-                        "mfma_util_step": mg["flops"] / m["steps"] / (m["ms"] * 1e-3) / PEAK["fp32_mfma"],
-                        "step_ms": m["dev"]}
+    if not args.no_side:
+        gs = load_gold(side_w)
+        Q = Problem(side_w)
+        s64 = measure_form(Q, "fp64", args.steps, args.warmup, gs, PEAK["fp64_mfma"])
+        smx = measure_form(Q, "fp32", args.steps, args.warmup, gs, PEAK["fp32_mfma"])
+        out["side"] = {"workload": side_w.name, "n": side_w.n, "eps": side_w.eps,
+                       "fp64": {"ms_per_step": s64["ms_per_step"], "roofline": s64["roofline"],
+                                "kernel_ms_per_step": s64["kernel_ms_per_step"], "error": s64["error"]},
+                       "mixed": {"precision": "fp32 bulk products", "ms_per_step": smx["ms_per_step"],
+                                 "speedup_vs_fp64": s64["ms_per_step"] / smx["ms_per_step"],
+                                 "error": smx["error"]}}
+        del Q
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(main_w, gold)
     print(json.dumps(out), flush=True)
 
 

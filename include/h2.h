@@ -88,11 +88,33 @@ typedef struct h2_product h2_product;  /* phase-1 result: G on T^XY with its bas
 /* Thread-local message of the last failing call (never NULL). */
 const char* h2_last_error(void);
 
+/* Device allocator of a context: alloc returns `bytes` of device memory on
+ * the context's device (aligned to at least 256 bytes) or NULL; free
+ * releases such a pointer.  `user` is passed through unchanged.  The library
+ * asks for large chunks (64 MiB or more), keeps them in a per-context cache
+ * across calls, and hands them back to free only when the context is
+ * destroyed, after every stream of the context has finished.  The callbacks
+ * are called from the calling thread and, concurrently, from the library's
+ * worker threads (one per auxiliary stream of the context): they must be
+ * thread-safe. */
+typedef void* (*h2_alloc_fn)(size_t bytes, void* user);
+typedef void (*h2_free_fn)(void* p, void* user);
+
 /* Create a context on HIP device `device` using stream `hip_stream`
- * (a hipStream_t; NULL = the default stream).  device = -1 creates a
- * host-only context that accepts only h2_tree_build and the tree queries
- * (symbolic work, no device memory).  *out receives the handle. */
-h2_status h2_ctx_create(int device, void* hip_stream, h2_ctx** out);
+ * (a hipStream_t; NULL = the default stream) and device memory from
+ * alloc_fn / free_fn (both NULL: hipMalloc / hipFree; giving one of the two
+ * is H2_ERR_ARG).  A NULL from alloc_fn makes the call that needed the
+ * memory fail with H2_ERR_ALLOC.  device = -1 creates a host-only context
+ * that accepts only h2_tree_build and the tree queries (symbolic work, no
+ * device memory).  *out receives the handle. */
+h2_status h2_ctx_create(int device, void* hip_stream, h2_alloc_fn alloc_fn, h2_free_fn free_fn, void* user,
+                        h2_ctx** out);
+/* Waits for the context's streams and releases the caller's hold on it.
+ * Matrices and products whose device memory came from the context keep it
+ * (its chunk cache, streams and allocator) until the last of them is
+ * destroyed, in any order and from any thread; no new call may use the
+ * context afterwards.  Handles may be destroyed at any time, also from inside
+ * an allocator callback: their memory goes back to the context's cache. */
 h2_status h2_ctx_destroy(h2_ctx* ctx);
 
 /* Cluster tree (Section 2, Definition "Cluster tree") and block tree
@@ -143,8 +165,14 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
                               const h2_matrix* const* Y, double eps, h2_precision prec,
                               h2_product** G_out);
 
-/* A zero H^2-matrix on `tree`'s block tree (the prescribed T_IK). */
-h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix** Z_out);
+/* A zero H^2-matrix Z on `tree`'s cluster tree whose block tree, the
+ * prescribed T_IK of phase 2, uses the standard admissibility condition with
+ * parameter eta_Z (Section 2, Definition "Block tree"); eta_Z <= 0 takes the
+ * tree's own block tree (its eta).  Phase 2 needs T^XY to refine T_IK
+ * (Section 6 assumes it; H2_ERR_NOT_REFINED otherwise): a larger eta_Z gives
+ * a coarser T_IK, which T^XY refines; a much smaller one may not be.
+ * NaN eta_Z is H2_ERR_ARG.  Host work only (no device memory). */
+h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix** Z_out);
 
 /* Phase 2 for `count` products (Section 6, Figure "basis"): builds adaptive
  * isometric nested row and column bases for Z's block tree T_IK from G and
@@ -182,6 +210,49 @@ h2_status h2_product_basis(h2_ctx* ctx, const h2_product* G, int which, int clus
 h2_status h2_matrix_ranks(const h2_matrix* A, int which, int32_t* out);
 h2_status h2_product_ranks(const h2_product* G, int which, int32_t* out);
 
+/* Kinds of handles for h2_stats and h2_export. */
+typedef enum { H2_HANDLE_TREE = 0, H2_HANDLE_MATRIX = 1, H2_HANDLE_PRODUCT = 2 } h2_handle_kind;
+
+#define H2_STATS_MAX_LEVELS 32
+/* Sizes and rank profile of a handle.  Block counts refer to the handle's
+ * block tree (T_IJ of a tree or matrix, T^XY of a product G).  Rank fields
+ * are [0] row basis, [1] column basis, per tree level from the root (levels
+ * beyond H2_STATS_MAX_LEVELS - 1 are not reported); zero for trees. */
+typedef struct {
+  int64_t n, dim, depth, nclusters;
+  int64_t nblocks, nadm, ninadm;
+  int64_t triples;            /* products: terminated triples of T^XY; else 0 */
+  int64_t device_bytes;       /* device memory held by the handle */
+  int64_t coupling_entries;   /* stored entries of the coupling matrices */
+  int64_t nearfield_entries;  /* stored entries of the nearfield blocks */
+  int32_t rank_max[2];
+  double rank_mean[2];
+  int32_t level_rank_max[2][H2_STATS_MAX_LEVELS];
+  double level_rank_mean[2][H2_STATS_MAX_LEVELS];
+} h2_stats_t;
+
+/* Fills *out for `handle` of kind h2_handle_kind.  Host data only (no device
+ * work).  H2_ERR_ARG for a NULL argument or an unknown kind. */
+h2_status h2_stats(const void* handle, int kind, h2_stats_t* out);
+
+/* Writes every array of `handle` into an uncompressed NumPy .npz archive at
+ * `path` (debugging and checkpoints; not timed).  Members, all 1-D unless
+ * noted, in cluster order:
+ *   kind; perm, cl_off, cl_size (int64, per cluster); points (n x dim,
+ *   float64, cluster order); blk_row, blk_col (int32), blk_type (int8:
+ *   0 subdivided, 1 admissible, 2 inadmissible) per block;
+ * and for matrices and products, per basis tag in {row, col}:
+ *   rank_<tag> (int32 per cluster); <tag>_leaf (float64) holding each leaf
+ *   basis (#c x rank, column-major) at <tag>_leaf_off[c] .. [c + 1];
+ *   <tag>_transfer holding each transfer E_c (rank c x rank parent,
+ *   column-major; eq. (transfer)) at <tag>_transfer_off[c] .. [c + 1];
+ *   blk_data with each block (coupling rank_row[t] x rank_col[s], or
+ *   nearfield #t x #s, column-major; none for subdivided blocks) at
+ *   blk_off[b] .. [b + 1].
+ * Synchronises the context stream.  H2_ERR_ARG if the file cannot be
+ * written or the archive would exceed 4 GiB. */
+h2_status h2_export(h2_ctx* ctx, const void* handle, int kind, const char* path);
+
 /* Sizes of a product: out[0] = #blocks of T^XY, out[1] = #admissible leaves,
  * out[2] = #inadmissible leaves, out[3] = terminated triples, out[4] = device
  * bytes held by G. */
@@ -204,6 +275,15 @@ int h2_step_times(h2_ctx* ctx, double* out, int n, int reset);
  * h2_recompress calls on ctx; the default is H2_RANK_ABS.  H2_ERR_ARG for an
  * unknown rule or a NULL context. */
 h2_status h2_set_rank_rule(h2_ctx* ctx, int rule);
+
+/* Test hook for the error paths: the `launches`-th batched kernel launch that
+ * the context's own host thread issues from now on (0 = the next one) fails
+ * with H2_ERR_DEVICE before it is launched, as a host-side failure in the
+ * middle of a call would; work already issued on any stream of the context
+ * completes normally.  launches < 0 turns the hook off.  After the failing
+ * call returns, the context and its handles remain usable.  H2_ERR_ARG for a
+ * NULL context. */
+h2_status h2_debug_fail_after(h2_ctx* ctx, int launches);
 
 /* Launch timing for measurement.  h2_profile(ctx, families) makes every
  * kernel launch of a family whose bit is set in `families` (bit k for family

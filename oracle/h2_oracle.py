@@ -29,6 +29,76 @@ VX_RTOL = 1e-12
 
 
 # ----------------------------------------------------------------------------
+# Work ledger: algorithmic floating-point operations per step and kind,
+# counted at every dense operation of the method (not of the checks):
+#   gemm   2 m n k for each product of an m x k and a k x n matrix;
+#   qr     Householder QR of an m x n matrix, 2 n^2 (m - n/3) for m >= n and
+#          2 m^2 (n - m/3) otherwise; forming an explicit m x m orthogonal
+#          factor from p reflectors adds 4 (m^2 p - m p^2 + p^3/3);
+#   svd    an SVD is counted as the QR of the matrix (kind qr) followed by
+#          the SVD of its p x p triangular factor, p = min(m, n): 12 p^3 for
+#          the singular values with one set of singular vectors (Golub-Reinsch
+#          counts, Golub and Van Loan, "Matrix Computations", 4th ed.,
+#          Section 8.6);
+#   norm   a spectral norm, the same with values only: 8 p^3 / 3 after the QR;
+#   sumsq  2 per entry of a sum of squares.
+# Steps: setup, p1_row, p1_col, p1_mat, p2_row, p2_col, p2_mat.
+# ----------------------------------------------------------------------------
+_LEDGER = None
+_STAGE = ["other"]
+
+
+class counting:
+    """``with counting() as ledger:`` collects {(step, kind): flops} of the
+    oracle calls made inside the block."""
+
+    def __enter__(self):
+        global _LEDGER
+        self.prev = _LEDGER
+        _LEDGER = {}
+        self.ledger = _LEDGER
+        return self.ledger
+
+    def __exit__(self, *exc):
+        global _LEDGER
+        _LEDGER = self.prev
+        return False
+
+
+class _stage:
+    def __init__(self, name):
+        self.name = name
+
+    def __enter__(self):
+        _STAGE.append(self.name)
+
+    def __exit__(self, *exc):
+        _STAGE.pop()
+        return False
+
+
+def _count(kind: str, flops: float):
+    if _LEDGER is not None:
+        key = (_STAGE[-1], kind)
+        _LEDGER[key] = _LEDGER.get(key, 0.0) + float(flops)
+
+
+def _qr_flops(m: int, n: int) -> float:
+    if m >= n:
+        return 2.0 * n * n * (m - n / 3.0)
+    return 2.0 * m * m * (n - m / 3.0)
+
+
+def mul(*factors: np.ndarray) -> np.ndarray:
+    """Product of the factors from left to right, counted in the ledger."""
+    out = factors[0]
+    for f in factors[1:]:
+        _count("gemm", 2.0 * out.shape[0] * out.shape[1] * f.shape[1])
+        out = out @ f
+    return out
+
+
+# ----------------------------------------------------------------------------
 # Cluster tree (Section 2, Definition "Cluster tree"; readings R1, R2)
 # ----------------------------------------------------------------------------
 class ClusterTree:
@@ -396,12 +466,16 @@ def qr_r(M: np.ndarray) -> np.ndarray:
     """R factor of a thin Householder QR, min(rows, cols) x cols."""
     if M.shape[0] == 0:
         return np.zeros((0, M.shape[1]))
+    _count("qr", _qr_flops(*M.shape))
     return np.linalg.qr(M, mode="r")
 
 
 def norm2(M: np.ndarray) -> float:
     if M.size == 0:
         return 0.0
+    p = min(M.shape)
+    _count("qr", _qr_flops(*M.shape))
+    _count("norm", 8.0 * p ** 3 / 3.0)
     return float(np.linalg.norm(M, 2))
 
 
@@ -409,6 +483,8 @@ def left_svd(M: np.ndarray):
     """Left singular vectors and singular values (descending)."""
     if M.shape[0] == 0 or M.shape[1] == 0:
         return np.zeros((M.shape[0], 0)), np.zeros(0)
+    _count("qr", _qr_flops(*M.shape))
+    _count("svd", 12.0 * min(M.shape) ** 3)
     U, sig, _ = np.linalg.svd(M, full_matrices=False)
     return U, sig
 
@@ -453,7 +529,7 @@ def basis_weights(W: ClusterBasis) -> dict:
         else:
             for ch in tr.children[r]:
                 rec(ch)
-            R[r] = qr_r(np.vstack([R[ch] @ W.transfer[ch] for ch in tr.children[r]]))
+            R[r] = qr_r(np.vstack([mul(R[ch], W.transfer[ch]) for ch in tr.children[r]]))
 
     rec(0)
     return R
@@ -465,9 +541,9 @@ def cluster_basis_products(WX: ClusterBasis, VY: ClusterBasis) -> dict:
     P = {}
     for s in range(tr.nclusters - 1, -1, -1):
         if tr.is_leaf(s):
-            P[s] = WX.leaf[s].T @ VY.leaf[s]
+            P[s] = mul(WX.leaf[s].T, VY.leaf[s])
         else:
-            P[s] = sum(WX.transfer[ch].T @ P[ch] @ VY.transfer[ch] for ch in tr.children[s])
+            P[s] = sum(mul(WX.transfer[ch].T, P[ch], VY.transfer[ch]) for ch in tr.children[s])
     return P
 
 
@@ -487,9 +563,9 @@ def total_weights(Y: H2Matrix, RY: dict) -> dict:
     def rec(s, Zp):
         blocks = []
         if Zp is not None:
-            blocks.append(Zp @ Y.V.transfer[s].T)
+            blocks.append(mul(Zp, Y.V.transfer[s].T))
         for r in row.get(s, []):
-            M = RY[r] @ Y.S[(s, r)].T
+            M = mul(RY[r], Y.S[(s, r)].T)
             w = norm2(M)
             if w > 0.0:
                 blocks.append(M / w)
@@ -538,9 +614,10 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
     if any(rt.level[c] != rt.depth for c in rt.leaves):
         raise ValueError("oracle expects uniform-depth cluster trees (R1)")
     k = X.V.rank[0]
-    RY = basis_weights(Y.W)
-    P = cluster_basis_products(X.W, Y.V)
-    Z = total_weights(Y, RY)
+    with _stage("setup"):
+        RY = basis_weights(Y.W)
+        P = cluster_basis_products(X.W, Y.V)
+        Z = total_weights(Y, RY)
     Cmap = X.bt.row_map((INADM, SPLIT))
     Q = ClusterBasis(rt)
     RX, A, sig_out, assembled = {}, {}, {}, {}
@@ -548,16 +625,19 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
     def compress(t, VX, Vrest_blocks):
         """Keep the (numerical) range of V_X exactly, SVD of the remainder."""
         rows = VX.shape[0]
+        pv = min(VX.shape)
+        _count("qr", _qr_flops(*VX.shape) + 4.0 * (rows * rows * pv - rows * pv * pv + pv ** 3 / 3.0))
+        _count("svd", 12.0 * pv ** 3)
         Ux, sx, _ = np.linalg.svd(VX, full_matrices=True)          # Ux: rows x rows
         k1 = int(np.count_nonzero(sx > VX_RTOL * sx[0])) if sx.size and sx[0] > 0 else 0
-        RX[t] = Ux[:, :k1].T @ VX                                  # Q_{X,t}^* V_{X,t} = [R_{X,t}; 0]
+        RX[t] = mul(Ux[:, :k1].T, VX)                              # Q_{X,t}^* V_{X,t} = [R_{X,t}; 0]
         Vrest = np.hstack(Vrest_blocks) if Vrest_blocks else np.zeros((rows, 0))
         assembled[t] = (VX, Vrest)
-        Vtil = Ux[:, k1:].T @ Vrest
+        Vtil = mul(Ux[:, k1:].T, Vrest)
         U, sig = left_svd(Vtil)
         k2 = choose_rank(sig, eps, rule)
         sig_out[t] = sig
-        Qt = np.hstack([Ux[:, :k1], Ux[:, k1:] @ U[:, :k2]])
+        Qt = np.hstack([Ux[:, :k1], mul(Ux[:, k1:], U[:, :k2])])
         Q.rank[t] = k1 + k2
         return Qt
 
@@ -567,14 +647,14 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
             blocks = []
             for s in Cmap.get(t, []):
                 assert X.bt.type[(t, s)] == INADM
-                B[s] = X.N[(t, s)] @ Y.V.leaf[s]          # X|_{t x s} V_{Y,s}
+                B[s] = mul(X.N[(t, s)], Y.V.leaf[s])     # X|_{t x s} V_{Y,s}
                 w = norm2(B[s])
                 if w > 0.0 and Z[s].shape[0] > 0:
-                    blocks.append(B[s] @ Z[s].T / w)
+                    blocks.append(mul(B[s], Z[s].T) / w)
             Qt = compress(t, X.V.leaf[t], blocks)
             Q.leaf[t] = Qt
             for s in B:
-                A[(t, s)] = Qt.T @ B[s]
+                A[(t, s)] = mul(Qt.T, B[s])
             return
         kids = rt.children[t]
         for ch in kids:
@@ -586,7 +666,7 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
         rows = o
         VXhat = np.zeros((rows, k))
         for ch in kids:
-            VXhat[offs[ch]:offs[ch] + RX[ch].shape[0]] = RX[ch] @ X.V.transfer[ch]
+            VXhat[offs[ch]:offs[ch] + RX[ch].shape[0]] = mul(RX[ch], X.V.transfer[ch])
         Ahat, blocks = {}, []
         for s in Cmap.get(t, []):
             M = np.zeros((rows, k))
@@ -594,22 +674,24 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
                 for sc in Y.V.tree.children[s]:
                     ty = X.bt.type[(ch, sc)]
                     if ty == ADM:        # A_{t',s'} = [R_{X,t'} S_{X,t's'} P_{XY,s'}; 0]
-                        At = _pad_rows(RX[ch] @ X.S[(ch, sc)] @ P[sc], Q.rank[ch])
+                        At = _pad_rows(mul(RX[ch], X.S[(ch, sc)], P[sc]), Q.rank[ch])
                     else:
                         At = A[(ch, sc)]
-                    M[offs[ch]:offs[ch] + Q.rank[ch]] += At @ Y.V.transfer[sc]
+                    M[offs[ch]:offs[ch] + Q.rank[ch]] += mul(At, Y.V.transfer[sc])
             Ahat[s] = M
             w = norm2(M)
             if w > 0.0 and Z[s].shape[0] > 0:
-                blocks.append(M @ Z[s].T / w)
+                blocks.append(mul(M, Z[s].T) / w)
         Qhat = compress(t, VXhat, blocks)
         for ch in kids:
             Q.transfer[ch] = Qhat[offs[ch]:offs[ch] + Q.rank[ch], :]
         for s in Ahat:
-            A[(t, s)] = Qhat.T @ Ahat[s]
+            A[(t, s)] = mul(Qhat.T, Ahat[s])
 
     rec(0)
-    return InducedBasis(Q, RX, A, sig_out, assembled)
+    out = InducedBasis(Q, RX, A, sig_out, assembled)
+    out.P = P
+    return out
 
 
 # ----------------------------------------------------------------------------
@@ -671,7 +753,7 @@ def form_product(X: H2Matrix, Y: H2Matrix, rowb: InducedBasis, colb: InducedBasi
     block and pushed to the leaves of T^XY through the transfer matrices."""
     Q, QW = rowb.Q, colb.Q
     k = X.V.rank[0]
-    P = cluster_basis_products(X.W, Y.V)
+    P = rowb.P                          # P_{XY,s} of the row pass's set-up
     RXp = {t: _pad_rows(rowb.RX[t], Q.rank[t]) for t in rowb.RX}          # [R_{X,t}; 0]
     Rcp = {r: _pad_rows(colb.RX[r], QW.rank[r]) for r in colb.RX}         # [R^c_{Y,r}; 0]
     acc, S, N = {}, {}, {}
@@ -685,34 +767,37 @@ def form_product(X: H2Matrix, Y: H2Matrix, rowb: InducedBasis, colb: InducedBasi
         M = np.zeros((Q.rank[t], QW.rank[r]))
         if (t, r) in parent:
             tp, rp = parent[(t, r)]
-            M += Q.transfer[t] @ acc[(tp, rp)] @ QW.transfer[r].T
+            M += mul(Q.transfer[t], acc[(tp, rp)], QW.transfer[r].T)
         dense = None
         for s, kd in PT.triples[(t, r)]:
             if kd == "NA":
-                M += rowb.A[(t, s)] @ Y.S[(s, r)] @ Rcp[r].T
+                M += mul(rowb.A[(t, s)], Y.S[(s, r)], Rcp[r].T)
             elif kd == "AN":
-                M += RXp[t] @ X.S[(t, s)] @ colb.A[(r, s)].T
+                M += mul(RXp[t], X.S[(t, s)], colb.A[(r, s)].T)
             elif kd == "AA":
-                M += RXp[t] @ X.S[(t, s)] @ P[s] @ Y.S[(s, r)] @ Rcp[r].T
+                M += mul(RXp[t], X.S[(t, s)], P[s], Y.S[(s, r)], Rcp[r].T)
             else:
-                d = X.N[(t, s)] @ Y.N[(s, r)]
+                d = mul(X.N[(t, s)], Y.N[(s, r)])
                 dense = d if dense is None else dense + d
         acc[(t, r)] = M
         ty = PT.type[(t, r)]
         if ty == ADM:
             S[(t, r)] = M
         elif ty == INADM:
-            Nm = Q.leaf[t] @ M @ QW.leaf[r].T
+            Nm = mul(Q.leaf[t], M, QW.leaf[r].T)
             N[(t, r)] = Nm + dense if dense is not None else Nm
     return H2Matrix(Q, QW, PT.bt, S, N)
 
 
 class Phase1:
     def __init__(self, X, Y, eps, rule=RANK_ABS):
-        self.row = induced_basis(X, Y, eps, rule)
-        self.col = induced_basis(Y.transposed(), X.transposed(), eps, rule)
-        self.PT = ProductTree(X, Y)
-        self.G = form_product(X, Y, self.row, self.col, self.PT)
+        with _stage("p1_row"):
+            self.row = induced_basis(X, Y, eps, rule)
+        with _stage("p1_col"):
+            self.col = induced_basis(Y.transposed(), X.transposed(), eps, rule)
+        with _stage("p1_mat"):
+            self.PT = ProductTree(X, Y)
+            self.G = form_product(X, Y, self.row, self.col, self.PT)
 
 
 # ----------------------------------------------------------------------------
@@ -755,6 +840,7 @@ def block_norms(G: H2Matrix, TIK: BlockTree, tag) -> dict:
     for b, m in list(G.S.items()) + list(G.N.items()):
         tb = tag[b]
         if tb is not None and TIK.type[tb] == ADM:
+            _count("sumsq", 2.0 * m.size)
             sq[tb] = sq.get(tb, 0.0) + float(np.sum(m * m))
     return {b: (1.0 / np.sqrt(v) if v > 0 else 0.0) for b, v in sq.items()}
 
@@ -831,11 +917,11 @@ def match_column(rep: dict, target: ColumnTree, W: ClusterBasis) -> dict:
             if not adm:
                 raise ValueError("inadmissible column leaf refined by the target")
             for rc in target.kids[r]:
-                visit(rc, True, M @ W.transfer[rc].T)
+                visit(rc, True, mul(M, W.transfer[rc].T))
         else:
             tadm = target.adm[r]
             if adm and not tadm:
-                M = M @ W.leaf[r].T
+                M = mul(M, W.leaf[r].T)
             out[r] = (tadm, M)
 
     for r, (adm, M) in rep.items():
@@ -880,21 +966,21 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
     def rep_of_child(tc, rc):
         ty = G.bt.type[(tc, rc)]
         if ty == ADM:
-            return {rc: (True, R[tc] @ G.S[(tc, rc)])}
+            return {rc: (True, mul(R[tc], G.S[(tc, rc)]))}
         return A[(tc, rc)]
 
     def rec(t, Zp):
         # total weights of the product (top-down part of the recursion)
         blocks = []
         if Zp is not None:
-            blocks.append(Zp @ G.V.transfer[t].T)
+            blocks.append(mul(Zp, G.V.transfer[t].T))
         for r in rowXY.get(t, []):
             if G.bt.type[(t, r)] == ADM and in_adm((t, r)):
                 blocks.append(omega[tag[(t, r)]] * G.S[(t, r)].T)
         Zt = qr_r(np.vstack(blocks)) if blocks else np.zeros((0, G.V.rank[t]))
         Z[t] = Zt
         if rt.is_leaf(t):
-            cols = [G.V.leaf[t] @ Zt.T]
+            cols = [mul(G.V.leaf[t], Zt.T)]
             inad = [r for r in rowXY.get(t, []) if G.bt.type[(t, r)] == INADM and in_adm((t, r))]
             for r in inad:
                 cols.append(omega[tag[(t, r)]] * G.N[(t, r)])
@@ -905,9 +991,9 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
             Qt = U[:, :kz]
             Q.leaf[t] = Qt
             Q.rank[t] = kz
-            R[t] = Qt.T @ G.V.leaf[t]
+            R[t] = mul(Qt.T, G.V.leaf[t])
             for r in inad:
-                A[(t, r)] = {r: (False, Qt.T @ G.N[(t, r)])}
+                A[(t, r)] = {r: (False, mul(Qt.T, G.N[(t, r)]))}
             return
         kids = rt.children[t]
         for ch in kids:
@@ -919,8 +1005,8 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
         rows = o
         Vhat = np.zeros((rows, G.V.rank[t]))
         for ch in kids:
-            Vhat[offs[ch]:offs[ch] + Q.rank[ch]] = R[ch] @ G.V.transfer[ch]
-        cols = [Vhat @ Zt.T]
+            Vhat[offs[ch]:offs[ch] + Q.rank[ch]] = mul(R[ch], G.V.transfer[ch])
+        cols = [mul(Vhat, Zt.T)]
         split = [r for r in rowXY.get(t, []) if G.bt.type[(t, r)] == SPLIT and in_adm((t, r))]
         Ahat = {}
         for r in split:
@@ -944,9 +1030,9 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
         Q.rank[t] = kz
         for ch in kids:
             Q.transfer[ch] = Qhat[offs[ch]:offs[ch] + Q.rank[ch], :]
-        R[t] = Qhat.T @ Vhat
+        R[t] = mul(Qhat.T, Vhat)
         for r in split:
-            A[(t, r)] = {lf: (adm, Qhat.T @ M) for lf, adm, M in Ahat[r]}
+            A[(t, r)] = {lf: (adm, mul(Qhat.T, M)) for lf, adm, M in Ahat[r]}
 
     rec(0, None)
     return CoarseBasis(Q, R, A, sig_out, omega, tag, Z, Cm)
@@ -969,11 +1055,11 @@ def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasi
         t, r = b
         ty = G.bt.type[b]
         if ty == ADM:
-            L[b] = rowc.R[t] @ G.S[b] @ colc.R[r].T
+            L[b] = mul(rowc.R[t], G.S[b], colc.R[r].T)
         elif ty == INADM:
-            L[b] = QZ.leaf[t].T @ G.N[b] @ QZW.leaf[r]
+            L[b] = mul(QZ.leaf[t].T, G.N[b], QZW.leaf[r])
         else:
-            L[b] = sum(QZ.transfer[tc].T @ L[(tc, rc)] @ QZW.transfer[rc]
+            L[b] = sum(mul(QZ.transfer[tc].T, L[(tc, rc)], QZW.transfer[rc])
                        for (tc, rc) in G.bt.children[b])
     S, N = {}, {}
     Gf = None
@@ -985,7 +1071,7 @@ def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasi
             if gt == INADM:
                 N[b] = G.N[b]
             elif gt == ADM:
-                N[b] = G.V.leaf[b[0]] @ G.S[b] @ G.W.leaf[b[1]].T
+                N[b] = mul(G.V.leaf[b[0]], G.S[b], G.W.leaf[b[1]].T)
             else:
                 raise ValueError("inadmissible leaf of T_IK not a leaf of T^XY")
     return H2Matrix(QZ, QZW, TIK, S, N)
@@ -993,9 +1079,12 @@ def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasi
 
 class Phase2:
     def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS):
-        self.row = build_basis(G, TIK, eps, rule)
-        self.col = build_basis(G.transposed(), TIK.transposed(), eps, rule)
-        self.Z = form_coarse(G, TIK, self.row, self.col)
+        with _stage("p2_row"):
+            self.row = build_basis(G, TIK, eps, rule)
+        with _stage("p2_col"):
+            self.col = build_basis(G.transposed(), TIK.transposed(), eps, rule)
+        with _stage("p2_mat"):
+            self.Z = form_coarse(G, TIK, self.row, self.col)
 
 
 def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float = None, rule: str = RANK_ABS):

@@ -48,16 +48,22 @@ extern "C" {
 
 const char* h2_last_error(void) { return g_err.c_str(); }
 
-h2_status h2_ctx_create(int device, void* hip_stream, h2_ctx** out) {
+h2_status h2_ctx_create(int device, void* hip_stream, h2_alloc_fn alloc_fn, h2_free_fn free_fn, void* user,
+                        h2_ctx** out) {
   return guard([&] {
     H2_REQUIRE(out, H2_ERR_ARG, "NULL output");
     *out = nullptr;
     H2_REQUIRE(device >= -1, H2_ERR_ARG, "bad device");
+    H2_REQUIRE((alloc_fn == nullptr) == (free_fn == nullptr), H2_ERR_ARG,
+               "give both allocator callbacks or neither");
     auto* c = new h2_ctx();
     c->device = device;
     c->stream = hip_stream;
     c->host_only = device < 0;
     c->ws.ctx = c;
+    c->alloc_fn = alloc_fn;
+    c->free_fn = free_fn;
+    c->alloc_user = user;
     if (!c->host_only) {
       try {
         dev_set_device(device);
@@ -76,11 +82,14 @@ h2_status h2_ctx_create(int device, void* hip_stream, h2_ctx** out) {
 h2_status h2_ctx_destroy(h2_ctx* ctx) {
   return guard([&] {
     if (!ctx) return;
+    H2_REQUIRE(!ctx->root, H2_ERR_ARG, "not a context created by h2_ctx_create");
     if (!ctx->host_only) {
       dev_set_device(ctx->device);
       for (h2_ctx* c = ctx; c; c = c->aux) dev_sync(c->stream);
     }
-    delete ctx;
+    // handles still holding memory of the context keep it until the last
+    // of them is destroyed
+    ctx_unref(ctx);
   });
 }
 
@@ -184,14 +193,39 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
   });
 }
 
-h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix** Z_out) {
+h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix** Z_out) {
   return guard([&] {
     H2_REQUIRE(Z_out && tree, H2_ERR_ARG, "NULL argument");
     *Z_out = nullptr;
+    H2_REQUIRE(!std::isnan(eta_Z) && !std::isinf(eta_Z), H2_ERR_ARG, "eta_Z must be finite");
     need_device(ctx);
     auto* m = new h2_matrix();
-    zero_like(ctx, tree, m);
+    try {
+      zero_like(ctx, tree, eta_Z, m);
+    } catch (...) {
+      delete m;
+      throw;
+    }
     *Z_out = m;
+  });
+}
+
+h2_status h2_stats(const void* handle, int kind, h2_stats_t* out) {
+  return guard([&] {
+    H2_REQUIRE(handle && out, H2_ERR_ARG, "NULL argument");
+    H2_REQUIRE(kind == H2_HANDLE_TREE || kind == H2_HANDLE_MATRIX || kind == H2_HANDLE_PRODUCT, H2_ERR_ARG,
+               "unknown handle kind");
+    handle_stats(handle, kind, out);
+  });
+}
+
+h2_status h2_export(h2_ctx* ctx, const void* handle, int kind, const char* path) {
+  return guard([&] {
+    H2_REQUIRE(handle && path, H2_ERR_ARG, "NULL argument");
+    H2_REQUIRE(kind == H2_HANDLE_TREE || kind == H2_HANDLE_MATRIX || kind == H2_HANDLE_PRODUCT, H2_ERR_ARG,
+               "unknown handle kind");
+    if (kind != H2_HANDLE_TREE) need_device(ctx);
+    export_handle(ctx, handle, kind, path);
   });
 }
 
@@ -321,6 +355,13 @@ h2_status h2_set_rank_rule(h2_ctx* ctx, int rule) {
     H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
     H2_REQUIRE(rule == H2_RANK_ABS || rule == H2_RANK_REL_FROB, H2_ERR_ARG, "unknown rank rule");
     ctx->rank_rule = rule;
+  });
+}
+
+h2_status h2_debug_fail_after(h2_ctx* ctx, int launches) {
+  return guard([&] {
+    H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
+    ctx->fail_after = launches < 0 ? -1 : launches;
   });
 }
 

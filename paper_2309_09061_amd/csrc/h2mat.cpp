@@ -13,7 +13,7 @@ void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2
   for (int a = 0; a < T.dim; ++a) k *= order;
   H2_REQUIRE(order >= 1 && k <= 128, H2_ERR_ARG, "order^dim must be in [1, 128]");
   out->ctx = ctx;
-  out->mem.ctx = ctx;
+  out->mem.bind(ctx);
   H2Core& C = out->c;
   C.ct = tree->ct;
   C.bt = tree->bt;
@@ -68,12 +68,12 @@ void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2
   k_nearfield(upload(ctx, near), (int)near.size(), pts, T.dim, kernel, ctx->stream);
 }
 
-void zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix* out) {
+void zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix* out) {
   out->ctx = ctx;
-  out->mem.ctx = ctx;
+  out->mem.bind(ctx);
   out->zero = true;
   out->c.ct = tree->ct;
-  out->c.bt = tree->bt;
+  out->c.bt = eta_Z > 0 && eta_Z != tree->eta ? build_block_tree(*tree->ct, *tree->ct, eta_Z) : tree->bt;
   out->c.V.resize(tree->ct->ncl);
   out->c.W.resize(tree->ct->ncl);
   out->c.blk.assign(tree->bt->nblocks(), nullptr);

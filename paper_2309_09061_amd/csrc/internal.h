@@ -15,8 +15,10 @@
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
+#include <atomic>
 #include <exception>
 #include <functional>
+#include <mutex>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -344,14 +346,18 @@ namespace h2 {
 
 struct Arena {
   h2_ctx* ctx = nullptr;
+  h2_ctx* owner = nullptr;  // root context referenced by a handle's arena (bind)
   std::vector<std::pair<char*, size_t>> chunks;
   size_t cur = 0, used = 0, total = 0;
   void* alloc(size_t bytes);
   template <class T>
   T* get(size_t count) { return (T*)alloc(count * sizeof(T)); }
   void reset() { cur = 0; used = 0; }
-  void release();
-  ~Arena() { release(); }
+  // the arena of a handle: memory from c, whose root context stays alive
+  // (h2_ctx_destroy is deferred) until the arena is gone
+  void bind(h2_ctx* c);
+  void release();  // chunks go back to the context (its returned list)
+  ~Arena();
 };
 
 }  // namespace h2
@@ -377,7 +383,15 @@ struct h2_ctx {
   void* stream = nullptr;
   bool host_only = true;
   h2::Arena ws;                        // per-call workspace
-  std::vector<std::pair<char*, size_t>> cache;  // free device chunks
+  std::vector<std::pair<char*, size_t>> cache;  // free device chunks (touched by the context's own thread)
+  // chunks handed back by destroyed handles, from any thread (also from
+  // inside an allocator callback): merged into `cache` before it is searched
+  std::mutex ret_mu;
+  std::vector<std::pair<char*, size_t>> returned;
+  h2_ctx* root = nullptr;              // auxiliary contexts: the context they belong to
+  // references on a root context: the caller's (dropped by h2_ctx_destroy)
+  // plus one per handle arena holding its memory; the last drop deletes it
+  std::atomic<int> refs{1};
   char* stage = nullptr;               // pinned staging for descriptor uploads
   char* stage_dev = nullptr;           // its device view (nullptr: runtime copies)
   size_t stage_cap = 0, stage_used = 0;
@@ -389,6 +403,10 @@ struct h2_ctx {
   int prec = 0;                        // bulk precision of the running call
   int rank_rule = 0;                   // h2_rank_rule of the truncating SVDs
   int profile = 0;                     // bit k: time the launches of kernel family k
+  int fail_after = -1;                 // test hook: launches left before an injected failure (-1: off)
+  h2_alloc_fn alloc_fn = nullptr;      // caller's device allocator (nullptr: hipMalloc / hipFree)
+  h2_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
   std::vector<void*> ev_pool;          // reusable events for launch timing
   std::vector<std::pair<double*, size_t>> prof_host;  // pinned chunks for per-problem work counts
   size_t prof_chunk = 0, prof_used = 0;
@@ -490,6 +508,7 @@ struct AuxRun {
   h2_ctx* aux;
   std::thread th;
   std::exception_ptr err;
+  bool joined = false;
   AuxRun(h2_ctx* c, std::function<void(h2_ctx*)> f);
   AuxRun(h2_ctx* c, h2_ctx* a, std::function<void(h2_ctx*)> f);  // on a given auxiliary context
   void join();
@@ -577,6 +596,14 @@ struct NormBatch {
   std::vector<const double*> run(h2_ctx* ctx);  // device pointer to sigma_max of each item
 };
 
+// drops a reference on a root context; the last one deletes it
+void ctx_unref(h2_ctx* root);
+
+// device memory of a context: the caller's allocator callbacks when given,
+// else the HIP runtime
+void* ctx_malloc(h2_ctx* ctx, size_t bytes);
+void ctx_free(h2_ctx* ctx, void* p);
+
 // zeroed device buffer from an arena
 double* zeros(h2_ctx* ctx, Arena& a, size_t count);
 
@@ -646,11 +673,15 @@ ProductTreeH build_product_tree(const View& X, const View& Y, int ncl);
 
 // matrices
 void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2_matrix* out);
-void zero_like(h2_ctx* ctx, const h2_tree* tree, h2_matrix* out);
+void zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix* out);
 void matvec(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double* x, double beta,
             double* y, int nvec);
 void to_dense(h2_ctx* ctx, const H2Core& A, double* out, int64_t ld);
 void basis_dense(h2_ctx* ctx, const H2Core& A, int which, int cluster, double* out, int64_t ld);
+
+// h2_stats / h2_export
+void handle_stats(const void* handle, int kind, h2_stats_t* out);
+void export_handle(h2_ctx* ctx, const void* handle, int kind, const std::string& path);
 
 // phases
 void phase1(h2_ctx* ctx, const h2_matrix* X, const h2_matrix* Y, double eps, int prec,

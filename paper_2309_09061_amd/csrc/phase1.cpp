@@ -430,7 +430,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   H2_REQUIRE(T.same_as(*Ym->c.ct), H2_ERR_SHAPE, "X and Y must share the cluster tree");
   ctx->prec = prec;
   G->ctx = ctx;
-  G->mem.ctx = ctx;
+  G->mem.bind(ctx);
   View X{&Xm->c, false}, Y{&Ym->c, false};
   View Yt{&Ym->c, true}, Xt{&Xm->c, true};
   const BlockTreeH& BX = *Xm->c.bt;
@@ -477,7 +477,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   });
   std::vector<std::vector<std::pair<int, double*>>> dn_of(T.ncl);  // leaf t: (r, block) by r
   h2_ctx* nf_ctx = aux_ctx(aux_ctx(ctx));
-  G->mem_nf.ctx = nf_ctx;
+  G->mem_nf.bind(nf_ctx);
   const int k = uniform_rank(Xm->c.V);
   P1Side row, col;
   LevelSignal sig(T.depth);
@@ -657,7 +657,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     LevelSignal& s;
     ~StopOnExit() { s.abort(); }
   } stop_on_exit{sig};
-  G->mem_aux.ctx = aux_ctx(ctx);
+  G->mem_aux.bind(aux_ctx(ctx));
   {
     AuxRun colrun(ctx, [&](h2_ctx* a) { induced_pass(a, Yt, Xt, eps, G->mem_aux, col, 0, 3, &sig, 1); });
     induced_pass(ctx, X, Y, eps, G->mem, row, 0, 2, &sig, 0);

@@ -517,7 +517,7 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
   // row pass on G here, column pass on G^* concurrently on the auxiliary
   // context; both read G, tag and omega only
   P2Side row, col;
-  Z->mem_aux.ctx = aux_ctx(ctx);
+  Z->mem_aux.bind(aux_ctx(ctx));
   {
     AuxRun colrun(ctx, [&](h2_ctx* a) { coarse_pass(a, Gc, tag, TIK, omega, eps, Z->mem_aux, col, 6); });
     coarse_pass(ctx, Gr, tag, TIK, omega, eps, Z->mem, row, 5);

@@ -13,6 +13,23 @@ namespace h2 {
 // ---------------------------------------------------------------------------
 static constexpr size_t kChunk = (size_t)64 << 20;
 
+void* ctx_malloc(h2_ctx* ctx, size_t bytes) {
+  if (ctx && ctx->alloc_fn) {
+    void* p = ctx->alloc_fn(bytes, ctx->alloc_user);
+    H2_REQUIRE(p, H2_ERR_ALLOC, "the allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  return dev_malloc(bytes);
+}
+
+void ctx_free(h2_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx && ctx->free_fn)
+    ctx->free_fn(p, ctx->alloc_user);
+  else
+    dev_free(p);
+}
+
 void* Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
   if (bytes == 0) bytes = 256;
@@ -26,6 +43,11 @@ void* Arena::alloc(size_t bytes) {
     used = 0;
   }
   // take the smallest cached chunk that fits, else allocate
+  if (ctx) {
+    std::lock_guard<std::mutex> lock(ctx->ret_mu);
+    for (auto& c : ctx->returned) ctx->cache.push_back(c);
+    ctx->returned.clear();
+  }
   size_t best = (size_t)-1;
   int bi = -1;
   if (ctx)
@@ -40,7 +62,7 @@ void* Arena::alloc(size_t bytes) {
     ctx->cache.erase(ctx->cache.begin() + bi);
   } else {
     size_t sz = std::max(bytes, kChunk);
-    ch = {(char*)dev_malloc(sz), sz};
+    ch = {(char*)ctx_malloc(ctx, sz), sz};
   }
   chunks.push_back(ch);
   cur = chunks.size() - 1;
@@ -50,14 +72,35 @@ void* Arena::alloc(size_t bytes) {
 }
 
 void Arena::release() {
-  for (auto& c : chunks) {
-    if (ctx)
-      ctx->cache.push_back(c);
-    else
-      dev_free(c.first);
+  if (ctx) {
+    std::lock_guard<std::mutex> lock(ctx->ret_mu);
+    for (auto& c : chunks) ctx->returned.push_back(c);
+  } else {
+    for (auto& c : chunks) dev_free(c.first);
   }
   chunks.clear();
   cur = used = total = 0;
+}
+
+static h2_ctx* root_of(h2_ctx* c) { return c->root ? c->root : c; }
+
+void Arena::bind(h2_ctx* c) {
+  if (ctx == c) return;
+  H2_REQUIRE(chunks.empty(), H2_ERR_ARG, "a handle's memory cannot move to another context");
+  h2_ctx* o = root_of(c);
+  o->refs.fetch_add(1);
+  if (owner) ctx_unref(owner);
+  ctx = c;
+  owner = o;
+}
+
+Arena::~Arena() {
+  release();
+  if (owner) ctx_unref(owner);
+}
+
+void ctx_unref(h2_ctx* root) {
+  if (root->refs.fetch_sub(1) == 1) delete root;
 }
 
 double* zeros(h2_ctx* ctx, Arena& a, size_t count) {
@@ -178,6 +221,7 @@ void* pool_event(h2_ctx* ctx) {
 }
 
 LaunchTimer::LaunchTimer(h2_ctx* c, int k, double f, double b) : ctx(c), kind(k), flops(f), bytes(b) {
+  if (ctx->fail_after >= 0 && ctx->fail_after-- == 0) fail(H2_ERR_DEVICE, "injected failure before a launch");
   if (!((ctx->profile >> kind) & 1)) return;
   a = pool_event(ctx);
   dev_event_record(a, ctx->stream);
@@ -219,6 +263,10 @@ h2_ctx* aux_ctx(h2_ctx* ctx) {
     a->device = ctx->device;
     a->host_only = false;
     a->ws.ctx = a;
+    a->root = root_of(ctx);
+    a->alloc_fn = ctx->alloc_fn;
+    a->free_fn = ctx->free_fn;
+    a->alloc_user = ctx->alloc_user;
     try {
       a->stream = dev_stream_create();
       a->own_stream = true;
@@ -264,6 +312,7 @@ AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), 
 }
 
 void AuxRun::join() {
+  joined = true;
   if (th.joinable()) th.join();
   if (!aux->drain) aux->drain = dev_event_create();
   dev_event_record(aux->drain, aux->stream);
@@ -275,8 +324,21 @@ void AuxRun::join() {
   }
 }
 
+// Error path (join() not reached because the owning thread threw): the
+// auxiliary thread has issued work that may still run on the device, reading
+// workspace and staging that the next call on these contexts reuses.  Order
+// the context stream after it and wait for it before the exception leaves.
 AuxRun::~AuxRun() {
   if (th.joinable()) th.join();
+  if (joined) return;
+  try {
+    if (!aux->drain) aux->drain = dev_event_create();
+    dev_event_record(aux->drain, aux->stream);
+    dev_stream_wait(ctx->stream, aux->drain);
+    dev_sync(aux->stream);
+    aux->stage_used = 0;
+  } catch (...) {
+  }
 }
 
 void aux_collect(h2_ctx* ctx) {
@@ -893,7 +955,9 @@ h2_ctx::~h2_ctx() {
   for (void* e : ev_pool) h2::dev_event_destroy(e);
   h2::dev_event_destroy(drain);
   ws.release();
-  for (auto& c : cache) h2::dev_free(c.first);
+  for (auto& c : returned) h2::ctx_free(this, c.first);
+  returned.clear();
+  for (auto& c : cache) h2::ctx_free(this, c.first);
   cache.clear();
   if (stage) h2::dev_free_host(stage);
   for (auto& c : prof_host) h2::dev_free_host(c.first);

@@ -26,6 +26,68 @@ _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def torch_allocator(device: int, stream: int):
+    """Allocator callbacks backed by PyTorch's caching allocator on `device`
+    and `stream` (what a Context uses by default)."""
+    import torch
+
+    def _alloc(nbytes, _user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:
+            return None  # NULL: the library reports H2_ERR_ALLOC
+
+    def _free(ptr, _user):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
+MAX_LEVELS = 32
+HANDLE_KINDS = {"tree": 0, "matrix": 1, "product": 2}
+
+
+class Stats(ctypes.Structure):
+    """h2_stats_t of include/h2.h."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("n", "dim", "depth", "nclusters", "nblocks", "nadm", "ninadm",
+                                               "triples", "device_bytes", "coupling_entries",
+                                               "nearfield_entries")] + [
+        ("rank_max", ctypes.c_int32 * 2), ("rank_mean", ctypes.c_double * 2),
+        ("level_rank_max", (ctypes.c_int32 * MAX_LEVELS) * 2),
+        ("level_rank_mean", (ctypes.c_double * MAX_LEVELS) * 2)]
+
+    def as_dict(self) -> dict:
+        out = {f: getattr(self, f) for f, _ in self._fields_[:11]}
+        depth = int(self.depth)
+        out["rank_max"] = list(self.rank_max)
+        out["rank_mean"] = list(self.rank_mean)
+        out["level_rank_max"] = [list(self.level_rank_max[w])[:depth + 1] for w in range(2)]
+        out["level_rank_mean"] = [list(self.level_rank_mean[w])[:depth + 1] for w in range(2)]
+        return out
+
+
+def stats(obj) -> dict:
+    """h2_stats of a Tree, Matrix or Product."""
+    kind = {"Tree": 0, "Matrix": 1, "Product": 2}[type(obj).__name__]
+    st = Stats()
+    lib = obj.lib
+    _check(lib, lib.h2_stats(obj.h, kind, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def export(ctx, obj, path: str):
+    """h2_export of a Tree, Matrix or Product into an .npz archive at path."""
+    kind = {"Tree": 0, "Matrix": 1, "Product": 2}[type(obj).__name__]
+    lib = obj.lib
+    _check(lib, lib.h2_export(ctx.h if ctx is not None else None, obj.h, kind, os.fsencode(path)))
+
+
 class H2Error(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"h2 status {code}: {msg}")
@@ -35,7 +97,7 @@ class H2Error(RuntimeError):
 def _declare(lib):
     sig = {
         "h2_last_error": (ctypes.c_char_p, []),
-        "h2_ctx_create": (ctypes.c_int, [ctypes.c_int, _c_p, ctypes.POINTER(_c_p)]),
+        "h2_ctx_create": (ctypes.c_int, [ctypes.c_int, _c_p, ALLOC_FN, FREE_FN, _c_p, ctypes.POINTER(_c_p)]),
         "h2_ctx_destroy": (ctypes.c_int, [_c_p]),
         "h2_tree_build": (ctypes.c_int, [_c_p, ctypes.c_int, _i64, _c_p, ctypes.c_int, ctypes.c_double,
                                          ctypes.POINTER(_c_p), _c_p]),
@@ -44,7 +106,9 @@ def _declare(lib):
         "h2_compress_kernel": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_c_p)]),
         "h2_mul_intermediate": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_double, ctypes.c_int,
                                                _c_p]),
-        "h2_zero_like": (ctypes.c_int, [_c_p, _c_p, ctypes.POINTER(_c_p)]),
+        "h2_zero_like": (ctypes.c_int, [_c_p, _c_p, ctypes.c_double, ctypes.POINTER(_c_p)]),
+        "h2_stats": (ctypes.c_int, [_c_p, ctypes.c_int, ctypes.POINTER(Stats)]),
+        "h2_export": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_char_p]),
         "h2_recompress": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_double, ctypes.c_int]),
         "h2_matvec": (ctypes.c_int, [_c_p, _c_p, ctypes.c_char, ctypes.c_double, _c_p, ctypes.c_double, _c_p,
                                      ctypes.c_int]),
@@ -59,6 +123,7 @@ def _declare(lib):
         "h2_product_sizes": (ctypes.c_int, [_c_p, _c_p]),
         "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int]),
         "h2_set_rank_rule": (ctypes.c_int, [_c_p, ctypes.c_int]),
+        "h2_debug_fail_after": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_profile": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_kernel_stats": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int]),
         "h2_tree_destroy": (None, [_c_p]),
@@ -111,13 +176,23 @@ def _ptr(x):
 class Context:
     """h2_ctx on a HIP device (device=-1: host-only, symbolic calls only)."""
 
-    def __init__(self, device: int = 0, stream=None, lib=None):
+    def __init__(self, device: int = 0, stream=None, lib=None, allocator="torch"):
+        """allocator: "torch" (PyTorch's caching allocator on the context's
+        stream), None (the library's own hipMalloc), or a pair of
+        (ALLOC_FN, FREE_FN) callbacks."""
         self.lib = lib or load()
         self.h = _c_p()
         if stream is None and device >= 0:
             import torch
             stream = torch.cuda.current_stream(device).cuda_stream
-        _check(self.lib, self.lib.h2_ctx_create(device, stream or 0, ctypes.byref(self.h)))
+        if device < 0 or allocator is None:
+            self._cb = (ALLOC_FN(), FREE_FN())
+        elif allocator == "torch":
+            self._cb = torch_allocator(device, stream or 0)
+        else:
+            self._cb = tuple(allocator)
+        _check(self.lib, self.lib.h2_ctx_create(device, stream or 0, self._cb[0], self._cb[1], None,
+                                                ctypes.byref(self.h)))
 
     def close(self):
         if self.h:
@@ -129,6 +204,11 @@ class Context:
         above eps of the scaled matrices) or "relF" (relative-Frobenius tail
         at most eps)."""
         _check(self.lib, self.lib.h2_set_rank_rule(self.h, RANK_RULES[rule]))
+
+    def fail_after(self, launches: int):
+        """Test hook: the launches-th batched launch issued by this context's
+        own host thread fails before it starts (-1 turns it off)."""
+        _check(self.lib, self.lib.h2_debug_fail_after(self.h, launches))
 
     def profile(self, enable: bool = True, families=None):
         """Time kernel launches with HIP events: every family when `families`
@@ -211,9 +291,11 @@ class Matrix:
         return cls(ctx, tree, h)
 
     @classmethod
-    def zero(cls, ctx: Context, tree: Tree):
+    def zero(cls, ctx: Context, tree: Tree, eta: float = 0.0):
+        """Z = 0 on the tree's block tree, or on the block tree of
+        admissibility parameter eta when eta > 0."""
         h = _c_p()
-        _check(ctx.lib, ctx.lib.h2_zero_like(ctx.h, tree.h, ctypes.byref(h)))
+        _check(ctx.lib, ctx.lib.h2_zero_like(ctx.h, tree.h, eta, ctypes.byref(h)))
         return cls(ctx, tree, h)
 
     def matvec(self, x, y, alpha=1.0, beta=0.0, op="N"):
@@ -311,5 +393,5 @@ def h2_compress_kernel(ctx: Context, tree: Tree, kernel: str, order: int) -> Mat
     return Matrix.kernel(ctx, tree, kernel, order)
 
 
-def h2_zero_like(ctx: Context, tree: Tree) -> Matrix:
-    return Matrix.zero(ctx, tree)
+def h2_zero_like(ctx: Context, tree: Tree, eta: float = 0.0) -> Matrix:
+    return Matrix.zero(ctx, tree, eta)

@@ -76,7 +76,7 @@ def test_error_paths_host_only():
         h2.Matrix.kernel(ctx, T, "log", 3)
     assert e.value.code == 1
     out = ctypes.c_void_p()
-    assert lib.h2_ctx_create(-2, None, ctypes.byref(out)) == 1
+    assert lib.h2_ctx_create(-2, None, h2.ALLOC_FN(), h2.FREE_FN(), None, ctypes.byref(out)) == 1
     assert lib.h2_tree_sizes(None, None) == 1
     assert "NULL" in lib.h2_last_error().decode()
 
@@ -89,3 +89,40 @@ def test_rank_rule_setting_host_only():
     assert lib.h2_set_rank_rule(ctx.h, 2) == 1          # unknown rule
     assert lib.h2_set_rank_rule(ctx.h, -1) == 1
     assert lib.h2_set_rank_rule(None, 0) == 1           # NULL context
+
+
+def test_stats_and_export_of_a_tree(tmp_path):
+    """h2_stats and h2_export on a tree (host data only)."""
+    lib = h2.load()
+    ctx = h2.Context(device=-1)
+    pts = W.make_points(5, 700, 2, "uniform")
+    T = h2.Tree(ctx, pts, 24, 1.5)
+    st = h2.stats(T)
+    for k in ("n", "dim", "depth", "nclusters", "nblocks", "nadm", "ninadm"):
+        assert st[k] == T.sizes[k], k
+    assert st["rank_max"] == [0, 0] and st["device_bytes"] == 0
+    path = str(tmp_path / "tree.npz")
+    h2.export(ctx, T, path)
+    d = np.load(path)  # numpy's own reader, no pickles
+    off, size, br, bc, bt = T.structure()
+    assert int(d["kind"][0]) == 0
+    assert np.array_equal(d["perm"], T.perm)
+    assert np.array_equal(d["cl_off"], off) and np.array_equal(d["cl_size"], size)
+    assert np.array_equal(d["blk_row"], br) and np.array_equal(d["blk_col"], bc)
+    assert np.array_equal(d["blk_type"], bt)
+    assert np.array_equal(d["points"], pts[T.perm])        # points in cluster order
+    # argument errors
+    st_c = h2.Stats()
+    assert lib.h2_stats(T.h, 7, ctypes.byref(st_c)) == 1
+    assert lib.h2_stats(None, 0, ctypes.byref(st_c)) == 1
+    assert lib.h2_export(ctx.h, T.h, 0, None) == 1
+    assert lib.h2_export(ctx.h, T.h, 0, b"/nonexistent-dir/x.npz") == 1
+
+
+def test_ctx_create_needs_both_allocator_callbacks():
+    lib = h2.load()
+    out = ctypes.c_void_p()
+    alloc = h2.ALLOC_FN(lambda n, u: None)
+    assert lib.h2_ctx_create(-1, None, alloc, h2.FREE_FN(), None, ctypes.byref(out)) == 1
+    assert "both allocator callbacks" in lib.h2_last_error().decode()
+    assert not out.value

@@ -1,0 +1,233 @@
+"""The C-ABI boundary on the GPU: caller-supplied allocators, a target block
+tree T_IK other than the inputs' (h2_zero_like with eta_Z) including the
+refinement failure, h2_stats, and h2_export read back by numpy."""
+import ctypes
+import functools
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def _h2():
+    from paper_2309_09061_amd import h2
+    h2.load()
+    return h2
+
+
+def zeros_colmajor(rows, cols):
+    return torch.zeros((cols, rows), dtype=torch.float64, device="cuda").t()
+
+
+def dense_of(obj, n):
+    out = zeros_colmajor(n, n)
+    obj.to_dense(out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def relF(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _problem(c, n, dim, leaf, order, kx, ky, eta, seed):
+    h2 = _h2()
+    pts = W.make_points(seed, n, dim, "uniform")
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order)
+    Y = X if kx == ky else h2.Matrix.kernel(c, T, ky, order)
+    return pts, T, X, Y
+
+
+@pytest.mark.parametrize("eta_z", [2.0, 0.5])
+def test_target_block_tree_other_than_inputs(eta_z):
+    """Phase 2 into Z = 0 on T_IK(eta_Z) != T_IJ(eta): ranks and Z equal the
+    oracle run with the same T_IK (Section 6, prescribed block tree)."""
+    h2 = _h2()
+    n, leaf, order, eta, eps = 2048, 16, 3, 1.0, 1e-6
+    c = h2.Context(0)
+    pts, T, X, Y = _problem(c, n, 2, leaf, order, "log", "expneg", eta, 31)
+    _say(f"[gpu] target tree eta_Z={eta_z}")
+    G = h2.h2_mul_intermediate(c, X, Y, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T, eta_z), eps)
+    torch.cuda.synchronize()
+    tree, bt, Xo, Yo = O.build_problem(pts, leaf, eta, order, "log", "expneg")
+    TIK = O.BlockTree(tree, tree, eta_z)
+    p1, p2 = O.multiply(Xo, Yo, TIK, eps)
+    st = h2.stats(Z)
+    assert st["nadm"] == sum(1 for v in TIK.type.values() if v == O.ADM)
+    assert st["ninadm"] == sum(1 for v in TIK.type.values() if v == O.INADM)
+    nc = tree.nclusters
+    assert list(Z.ranks(0)) == [p2.row.Q.rank[t] for t in range(nc)]
+    assert list(Z.ranks(1)) == [p2.col.Q.rank[t] for t in range(nc)]
+    Zg = dense_of(Z, n)
+    assert relF(Zg, p2.Z.dense()) < 1e-10
+    XY = Xo.dense() @ Yo.dense()
+    assert np.linalg.norm(Zg - XY, 2) / np.linalg.norm(XY, 2) <= eps
+
+
+def test_target_block_tree_not_refined():
+    """A T_IK finer than T^XY (eta_Z = 0.25 against eta = 1 at depth 7):
+    H2_ERR_NOT_REFINED, as the oracle's refinement check also fails, and the
+    context and Z stay usable."""
+    h2 = _h2()
+    n, leaf, order, eta, eps = 2048, 16, 3, 1.0, 1e-6
+    c = h2.Context(0)
+    pts, T, X, _ = _problem(c, n, 2, leaf, order, "log", "log", eta, 2)
+    tree, bt, Xo, _ = O.build_problem(pts, leaf, eta, order, "log", "log")
+    G_o = O.H2Matrix(Xo.V, Xo.W, O.ProductTree(Xo, Xo).bt, {}, {})
+    with pytest.raises(ValueError):
+        O.h2_oracle.tag_blocks(G_o, O.BlockTree(tree, tree, 0.25))
+    G = h2.h2_mul_intermediate(c, X, X, eps)
+    Zf = h2.Matrix.zero(c, T, 0.25)
+    with pytest.raises(h2.H2Error) as e:
+        h2.h2_recompress(c, G, Zf, eps)
+    assert e.value.code == 5
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    torch.cuda.synchronize()
+    assert h2.stats(Z)["rank_max"][0] > 0
+
+
+def test_torch_allocator_callbacks_carry_all_device_memory():
+    """Every device allocation of a context goes through its callbacks (here
+    PyTorch's caching allocator, counted), and all of it is handed back when
+    the context is destroyed."""
+    h2 = _h2()
+    stream = torch.cuda.current_stream(0).cuda_stream
+    live, count = {}, [0, 0]
+
+    def _alloc(nbytes, _u):
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), 0, stream)
+        live[p] = nbytes
+        count[0] += 1
+        return p
+
+    def _free(p, _u):
+        live.pop(p)
+        count[1] += 1
+        torch.cuda.caching_allocator_delete(p)
+    cbs = (h2.ALLOC_FN(_alloc), h2.FREE_FN(_free))
+    c = h2.Context(0, allocator=cbs)
+    pts, T, X, Y = _problem(c, 1500, 2, 32, 3, "log", "expneg", 1.0, 41)
+    G = h2.h2_mul_intermediate(c, X, Y, 1e-6)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
+    torch.cuda.synchronize()
+    tree, bt, Xo, Yo = O.build_problem(pts, 32, 1.0, 3, "log", "expneg")
+    _, p2 = O.multiply(Xo, Yo, bt, 1e-6)
+    assert relF(dense_of(Z, 1500), p2.Z.dense()) < 1e-10
+    assert count[0] > 0 and sum(live.values()) >= h2.stats(Z)["device_bytes"]
+    del G, Z, X, Y, T
+    c.close()
+    assert count[1] == count[0] and not live
+
+
+def test_allocator_returning_null():
+    """An allocator that returns NULL makes the call that needs memory fail
+    with H2_ERR_ALLOC (no device fault, nothing launched on bad memory)."""
+    h2 = _h2()
+    cbs = (h2.ALLOC_FN(lambda n, u: None), h2.FREE_FN(lambda p, u: None))
+    c = h2.Context(0, allocator=cbs)
+    T = h2.Tree(c, W.make_points(3, 800, 2, "uniform"), 32, 1.0)
+    with pytest.raises(h2.H2Error) as e:
+        h2.Matrix.kernel(c, T, "log", 3)
+    assert e.value.code == 3 and "NULL" in str(e.value)
+
+
+def _dense_from_export(path):
+    """The represented matrix rebuilt from an h2_export archive (cluster
+    order): nested bases expanded through the transfers, couplings and
+    nearfield blocks placed by the block tree."""
+    d = np.load(path)
+    off, size = d["cl_off"], d["cl_size"]
+    ncl = off.size
+    depth = int(np.log2(ncl + 1)) - 1
+    n = int(d["perm"].size)
+
+    def basis(tag):
+        rank, L, Lo = d["rank_" + tag], d[tag + "_leaf"], d[tag + "_leaf_off"]
+        E, Eo = d[tag + "_transfer"], d[tag + "_transfer_off"]
+        full = {}
+        for c in range(ncl - 1, -1, -1):
+            if int(np.floor(np.log2(c + 1))) == depth:
+                full[c] = L[Lo[c]:Lo[c + 1]].reshape((size[c], rank[c]), order="F")
+            else:
+                full[c] = np.vstack([full[ch] @ E[Eo[ch]:Eo[ch + 1]].reshape((rank[ch], rank[c]), order="F")
+                                     for ch in (2 * c + 1, 2 * c + 2)])
+        return full, rank
+    (V, kr), (Wb, kc) = basis("row"), basis("col")
+    A = np.zeros((n, n))
+    data, bo = d["blk_data"], d["blk_off"]
+    for b, (t, s, ty) in enumerate(zip(d["blk_row"], d["blk_col"], d["blk_type"])):
+        blk = data[bo[b]:bo[b + 1]]
+        rt, rs = slice(off[t], off[t] + size[t]), slice(off[s], off[s] + size[s])
+        if ty == 1:
+            A[rt, rs] = V[t] @ blk.reshape((kr[t], kc[s]), order="F") @ Wb[s].T
+        elif ty == 2:
+            A[rt, rs] = blk.reshape((size[t], size[s]), order="F")
+    return A
+
+
+def test_stats_and_export(tmp_path):
+    """h2_stats against the ranks and block counts; h2_export of X, G and Z
+    read back with numpy and rebuilt into the same dense matrices as
+    h2_to_dense."""
+    h2 = _h2()
+    c = h2.Context(0)
+    n = 1200
+    pts, T, X, Y = _problem(c, n, 2, 32, 3, "log", "expneg", 1.0, 51)
+    G = h2.h2_mul_intermediate(c, X, Y, 1e-6)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
+    torch.cuda.synchronize()
+    for obj in (X, G, Z):
+        st = h2.stats(obj)
+        r0, r1 = obj.ranks(0), obj.ranks(1)
+        assert st["rank_max"] == [int(r0.max()), int(r1.max())]
+        assert abs(st["rank_mean"][0] - r0.mean()) < 1e-12
+        lev = np.floor(np.log2(np.arange(r0.size) + 1)).astype(int)
+        assert st["level_rank_max"][0] == [int(r0[lev == l].max()) for l in range(lev.max() + 1)]
+        assert st["device_bytes"] > 0 and st["n"] == n
+        path = str(tmp_path / f"{type(obj).__name__}.npz")
+        h2.export(c, obj, path)
+        A = _dense_from_export(path)
+        ref = dense_of(obj, n)
+        assert np.abs(A - ref).max() <= 1e-13 * np.abs(ref).max()
+    gs = h2.stats(G)
+    assert gs["triples"] == G.sizes()["triples"] and gs["nblocks"] == G.sizes()["nblocks"]
+
+
+def test_handles_outlive_their_context():
+    """Destroying the context before its matrices and products (the order a
+    garbage collector may pick) keeps the context's memory until the last
+    handle is destroyed; then all of it is handed back."""
+    h2 = _h2()
+    stream = torch.cuda.current_stream(0).cuda_stream
+    count = [0, 0]
+
+    def _alloc(nbytes, _u):
+        count[0] += 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), 0, stream)
+
+    def _free(p, _u):
+        count[1] += 1
+        torch.cuda.caching_allocator_delete(p)
+    cbs = (h2.ALLOC_FN(_alloc), h2.FREE_FN(_free))
+    c = h2.Context(0, allocator=cbs)
+    _, T, X, Y = _problem(c, 900, 2, 32, 3, "log", "expneg", 1.0, 61)
+    G = h2.h2_mul_intermediate(c, X, Y, 1e-6)
+    torch.cuda.synchronize()
+    c.close()
+    assert count[0] > 0 and count[1] == 0
+    del G
+    del X, Y
+    assert count[1] == count[0]

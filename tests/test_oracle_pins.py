@@ -595,3 +595,52 @@ def test_rel_frobenius_exact_without_truncation(name):
     p1, p2 = O.multiply(X, Y, bt, 0.0, rule=O.RANK_REL_FROB)
     assert relF(p1.G.dense(), XY) < 1e-12
     assert relF(p2.Z.dense(), XY) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P11: the work ledger (algorithmic flop counts per step) against the
+# method's linear complexity (Section 6, closing complexity estimate; the
+# bounded run time per degree of freedom of Section 7) and against a
+# brute-force count of its dominant term
+# --------------------------------------------------------------------------
+def _ledger_of(n, dim, leaf, order, kx, ky, eps, seed, eta=1.0):
+    pts = W.make_points(seed, n, dim, "uniform")
+    tree, bt, X, Y = O.build_problem(pts, leaf, eta, order, kx, ky)
+    with O.counting() as led:
+        O.multiply(X, Y, bt, eps)
+    return tree, bt, led
+
+
+def test_work_ledger_linear_complexity_1d():
+    """Work per degree of freedom stays bounded as n grows (O(n k^2) total)."""
+    per = []
+    for n in (1024, 2048, 4096, 8192, 16384):
+        _, _, led = _ledger_of(n, 1, 16, 4, "log", "log", 1e-8, 1)
+        per.append(sum(led.values()) / n)
+    assert max(per) / min(per) < 1.15, per
+    assert max(per[2:]) / min(per[2:]) < 1.03, per
+
+
+def test_work_ledger_steps_and_dense_triples():
+    """Every step is counted, and the G formation's products include the
+    dense nearfield-times-nearfield products 2 #t #s #r of every leaf triple
+    (t, s, r) whose two factor blocks are inadmissible leaves (enumerated by
+    brute force from the block tree), plus at most the small coupling
+    products of the remaining triples and blocks."""
+    tree, bt, led = _ledger_of(1024, 2, 32, 3, "log", "expneg", 1e-6, 2)
+    steps = {s for s, _ in led}
+    assert {"setup", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat"} <= steps
+    for st in ("p1_row", "p1_col", "p2_row", "p2_col"):
+        assert led[(st, "svd")] > 0 and led[(st, "qr")] > 0 and led[(st, "gemm")] > 0
+    inad = [(t, s) for (t, s), ty in bt.type.items() if ty == O.INADM]
+    by_row = {}
+    for t, s in inad:
+        by_row.setdefault(t, []).append(s)
+    dense = 0.0
+    for t, s in inad:
+        for r in by_row.get(s, []):
+            dense += 2.0 * tree.size[t] * tree.size[s] * tree.size[r]
+    k = 9
+    nblocks = len(bt.type)
+    small = 2.0 * (2 * k) ** 3 * 5 * (nblocks ** 2)   # generous bound on the rest
+    assert dense <= led[("p1_mat", "gemm")] <= dense + small
