@@ -106,7 +106,8 @@ typedef void (*h2_free_fn)(void* p, void* user);
  * is H2_ERR_ARG).  A NULL from alloc_fn makes the call that needed the
  * memory fail with H2_ERR_ALLOC.  device = -1 creates a host-only context
  * that accepts only h2_tree_build and the tree queries (symbolic work, no
- * device memory).  *out receives the handle. */
+ * device memory).  *out receives the handle.  The context also makes the
+ * device's fixed scratch of h2_matvec_noalloc addressable. */
 h2_status h2_ctx_create(int device, void* hip_stream, h2_alloc_fn alloc_fn, h2_free_fn free_fn, void* user,
                         h2_ctx** out);
 /* Waits for the context's streams and releases the caller's hold on it.
@@ -188,6 +189,26 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
  * backward transform, nearfield).  op is 'N' or 'T'.  x and y must not overlap. */
 h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x,
                     double beta, double* y, int nvec);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as h2_matvec, through the same kernels, with every device buffer
+ * beyond x and y taken from a fixed array of 64 MiB per device that the
+ * library holds until the process ends (its address is resolved when a
+ * context is created on the device).  Nothing is allocated: no hipMalloc,
+ * hipFree, pinned-memory or event creation; descriptor tables go through the
+ * context's existing pinned staging, which is reused but never grown.
+ * The coefficient vectors need sum over clusters of (row rank + column rank)
+ * x nvec doubles plus n x nvec for the result, each rounded up to 256 bytes;
+ * with 8 MiB kept for descriptor tables this must fit in the 64 MiB, else
+ * H2_ERR_ARG before anything is launched (as is a descriptor table larger
+ * than the staging, before its launch and before y is written).
+ * Every call on a device shares that device's array and overwrites what the
+ * last call left there; calls that overlap in time on one device (several
+ * contexts or host threads, different streams) race and must be serialised
+ * by the caller.  Arguments and errors otherwise as h2_matvec. */
+h2_status h2_matvec_noalloc(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x,
+                            double beta, double* y, int nvec);
 
 /* The same for the intermediate product G. */
 h2_status h2_product_matvec(h2_ctx* ctx, const h2_product* G, char op, double alpha,

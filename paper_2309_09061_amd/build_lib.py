@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libh2.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "runtime.cpp", "tree.cpp", "h2mat.cpp", "phase1.cpp", "phase2.cpp", "export.cpp",
-           "dev_hip.hip", "kernels_la.hip", "kernels_cheb.hip", "kernels_rank.hip"]
+           "dev_hip.hip", "kernels_la.hip", "kernels_cheb.hip", "kernels_rank.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

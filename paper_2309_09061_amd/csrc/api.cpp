@@ -70,6 +70,7 @@ h2_status h2_ctx_create(int device, void* hip_stream, h2_alloc_fn alloc_fn, h2_f
         c->stage_cap = (size_t)16 << 20;
         c->stage = (char*)dev_malloc_host(c->stage_cap);
         c->stage_dev = (char*)dev_host_view(c->stage);
+        c->scratch_dev = noalloc_scratch_resolve(device);
       } catch (...) {
         delete c;
         throw;
@@ -253,6 +254,17 @@ h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, cons
     need_device(ctx);
     begin_call(ctx);
     matvec(ctx, A->c, op == 'T', alpha, x, beta, y, nvec);
+  });
+}
+
+h2_status h2_matvec_noalloc(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x,
+                            double beta, double* y, int nvec) {
+  return guard([&] {
+    H2_REQUIRE(A && x && y && nvec >= 1, H2_ERR_ARG, "bad arguments");
+    H2_REQUIRE(op == 'N' || op == 'T', H2_ERR_ARG, "op must be 'N' or 'T'");
+    need_device(ctx);
+    begin_call(ctx);
+    matvec_noalloc(ctx, A->c, op == 'T', alpha, x, beta, y, nvec);
   });
 }
 

@@ -349,6 +349,10 @@ struct Arena {
   h2_ctx* owner = nullptr;  // root context referenced by a handle's arena (bind)
   std::vector<std::pair<char*, size_t>> chunks;
   size_t cur = 0, used = 0, total = 0;
+  // fixed region (device scratch of the entry point that allocates nothing):
+  // when set, alloc() bumps inside it and fails once it is exhausted
+  char* fixed = nullptr;
+  size_t fixed_cap = 0, fixed_used = 0;
   void* alloc(size_t bytes);
   template <class T>
   T* get(size_t count) { return (T*)alloc(count * sizeof(T)); }
@@ -407,6 +411,8 @@ struct h2_ctx {
   h2_alloc_fn alloc_fn = nullptr;      // caller's device allocator (nullptr: hipMalloc / hipFree)
   h2_free_fn free_fn = nullptr;
   void* alloc_user = nullptr;
+  char* scratch_dev = nullptr;         // device address of the fixed scratch on this device
+  bool no_alloc = false;               // inside an entry point that allocates nothing
   std::vector<void*> ev_pool;          // reusable events for launch timing
   std::vector<std::pair<double*, size_t>> prof_host;  // pinned chunks for per-problem work counts
   size_t prof_chunk = 0, prof_used = 0;
@@ -678,6 +684,15 @@ void matvec(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double
             double* y, int nvec);
 void to_dense(h2_ctx* ctx, const H2Core& A, double* out, int64_t ld);
 void basis_dense(h2_ctx* ctx, const H2Core& A, int which, int cluster, double* out, int64_t ld);
+
+// the entry point that allocates nothing: a fixed device array of this size
+// per device (coefficient vectors, result staging and large descriptor
+// tables of one call); kNoAllocTableReserve of it is kept for the tables
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr size_t kNoAllocTableReserve = (size_t)8 << 20;
+char* noalloc_scratch_resolve(int device);
+void matvec_noalloc(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double* x, double beta,
+                    double* y, int nvec);
 
 // h2_stats / h2_export
 void handle_stats(const void* handle, int kind, h2_stats_t* out);

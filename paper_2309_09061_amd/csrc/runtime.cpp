@@ -33,6 +33,13 @@ void ctx_free(h2_ctx* ctx, void* p) {
 void* Arena::alloc(size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
   if (bytes == 0) bytes = 256;
+  if (fixed) {
+    H2_REQUIRE(fixed_used + bytes <= fixed_cap, H2_ERR_ARG,
+               "the call needs more than the fixed scratch of " + std::to_string(fixed_cap) + " bytes");
+    void* p = fixed + fixed_used;
+    fixed_used += bytes;
+    return p;
+  }
   while (cur < chunks.size()) {
     if (used + bytes <= chunks[cur].second) {
       void* p = chunks[cur].first + used;
@@ -117,6 +124,13 @@ char* stage_alloc(h2_ctx* ctx, size_t bytes) {
   if (ctx->stage_used + need > ctx->stage_cap) {
     dev_sync(ctx->stream);  // earlier copies out of the staging buffer are done
     ctx->stage_used = 0;
+    if (ctx->no_alloc) {  // the staging is reused as it is, never reallocated
+      H2_REQUIRE(need <= ctx->stage_cap, H2_ERR_ARG,
+                 "a descriptor table exceeds the context's staging (" + std::to_string(ctx->stage_cap) + " bytes)");
+      char* h = ctx->stage;
+      ctx->stage_used = need;
+      return h;
+    }
     // a call that fills the staging waits here: the buffer grows (up to
     // 1 GiB) so that later calls of the same size do not
     constexpr size_t kStageMax = (size_t)1 << 30;
@@ -222,7 +236,7 @@ void* pool_event(h2_ctx* ctx) {
 
 LaunchTimer::LaunchTimer(h2_ctx* c, int k, double f, double b) : ctx(c), kind(k), flops(f), bytes(b) {
   if (ctx->fail_after >= 0 && ctx->fail_after-- == 0) fail(H2_ERR_DEVICE, "injected failure before a launch");
-  if (!((ctx->profile >> kind) & 1)) return;
+  if (!((ctx->profile >> kind) & 1) || ctx->no_alloc) return;  // events are not created there
   a = pool_event(ctx);
   dev_event_record(a, ctx->stream);
 }
@@ -239,7 +253,7 @@ LaunchTimer::~LaunchTimer() {
 
 WorkCounts work_counts(h2_ctx* ctx, int n, int kind) {
   WorkCounts w;
-  if (!((ctx->profile >> kind) & 1) || n <= 0) return w;
+  if (!((ctx->profile >> kind) & 1) || n <= 0 || ctx->no_alloc) return w;
   w.n = n;
   w.dev = ctx->ws.get<double>(n);
   if (ctx->prof_host.empty() || ctx->prof_used + n > ctx->prof_chunk) {
@@ -267,6 +281,7 @@ h2_ctx* aux_ctx(h2_ctx* ctx) {
     a->alloc_fn = ctx->alloc_fn;
     a->free_fn = ctx->free_fn;
     a->alloc_user = ctx->alloc_user;
+    a->scratch_dev = ctx->scratch_dev;
     try {
       a->stream = dev_stream_create();
       a->own_stream = true;

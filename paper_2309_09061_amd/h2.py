@@ -112,6 +112,8 @@ def _declare(lib):
         "h2_recompress": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_double, ctypes.c_int]),
         "h2_matvec": (ctypes.c_int, [_c_p, _c_p, ctypes.c_char, ctypes.c_double, _c_p, ctypes.c_double, _c_p,
                                      ctypes.c_int]),
+        "h2_matvec_noalloc": (ctypes.c_int, [_c_p, _c_p, ctypes.c_char, ctypes.c_double, _c_p, ctypes.c_double,
+                                             _c_p, ctypes.c_int]),
         "h2_product_matvec": (ctypes.c_int, [_c_p, _c_p, ctypes.c_char, ctypes.c_double, _c_p, ctypes.c_double,
                                              _c_p, ctypes.c_int]),
         "h2_to_dense": (ctypes.c_int, [_c_p, _c_p, _c_p, _i64]),
@@ -301,6 +303,12 @@ class Matrix:
     def matvec(self, x, y, alpha=1.0, beta=0.0, op="N"):
         nvec = 1 if len(x.shape) == 1 else x.shape[1]
         _check(self.lib, self.lib.h2_matvec(self.ctx.h, self.h, op.encode(), alpha, _ptr(x), beta, _ptr(y), nvec))
+
+    def matvec_noalloc(self, x, y, alpha=1.0, beta=0.0, op="N"):
+        """The same product without any device allocation (fixed scratch)."""
+        nvec = 1 if len(x.shape) == 1 else x.shape[1]
+        _check(self.lib, self.lib.h2_matvec_noalloc(self.ctx.h, self.h, op.encode(), alpha, _ptr(x), beta,
+                                                    _ptr(y), nvec))
 
     def to_dense(self, out, ld=None):
         _check(self.lib, self.lib.h2_to_dense(self.ctx.h, self.h, _ptr(out), ld or self.tree.n))
