@@ -286,7 +286,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB on the GPU (the reference for the HBM traffic counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="run only this many FP64 steps of the headline workload (for profilers) and exit")
+                    help="run only this many steps of the headline workload (for profilers) and exit")
+    ap.add_argument("--profile-precision", default="fp64", choices=["fp64", "fp32"],
+                    help="form of the --profile-steps run")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -307,7 +309,7 @@ def main():
     if args.profile_steps:
         P = Problem(main_w)
         for i in range(args.profile_steps):
-            G, Z = P.step("fp64")
+            G, Z = P.step(args.profile_precision)
             torch.cuda.synchronize()
             print(f"[profile] step {i + 1}/{args.profile_steps} done", flush=True)
             del G, Z
