@@ -48,15 +48,25 @@ typedef enum {
   H2_ERR_NUMERIC = 7       /* NaN or Inf met where a finite value is required */
 } h2_status;
 
-/* Arithmetic of the bulk products.  Orthogonalisation (QR), the SVDs that
- * choose ranks and the block norms always run in float64, and all stored
- * matrices are float64.  H2_FP32_BULK rounds the operands of every grouped
- * product to float32 and accumulates in float32 (FP32 MFMA); its results
- * differ from the float64 form by about 1e-7 relative, so it is accepted
- * only for eps >= 1e-6 (H2_ERR_ARG otherwise). */
+/* Arithmetic of the bulk products (the grouped products of both phases;
+ * Section 5's error control bounds what they may add).  Orthogonalisation
+ * (QR), the SVDs that choose ranks and the block norms always run in
+ * float64, and all stored matrices are float64.
+ *   H2_FP32_BULK   operands rounded to float32, float32 accumulation (FP32
+ *                  MFMA): about 1e-7 relative, accepted for eps >= 1e-6;
+ *   H2_BF16X2_BULK each operand split into a bfloat16 head and a bfloat16
+ *                  tail (a = a_h + a_l), products a_h b_h + a_h b_l + a_l b_h
+ *                  on BF16 MFMA with float32 accumulation: about 2^-16
+ *                  relative, accepted for eps >= 1e-4;
+ *   H2_BF16_BULK   plain bfloat16 operands (a_h b_h only, 2^-9 rounding),
+ *                  accepted for eps >= 1e-4 but not expected to meet the
+ *                  2 eps bar there: offered to measure that it does not.
+ * Smaller eps are H2_ERR_ARG. */
 typedef enum {
-  H2_FP64 = 0,       /* everything in float64 */
-  H2_FP32_BULK = 1   /* bulk products of both phases in float32 (FP32 MFMA) */
+  H2_FP64 = 0,         /* everything in float64 */
+  H2_FP32_BULK = 1,    /* bulk products in float32 (FP32 MFMA) */
+  H2_BF16X2_BULK = 2,  /* bulk products in split bfloat16 (BF16 MFMA, three products) */
+  H2_BF16_BULK = 3     /* bulk products in plain bfloat16 (BF16 MFMA) */
 } h2_precision;
 
 /* Truncation rule of the rank-choosing SVDs of both phases (Section 5 error

@@ -32,9 +32,16 @@ static void need_device(const h2_ctx* ctx) {
   dev_set_device(ctx->device);
 }
 
-// FP32 rounding of the bulk products (about 6e-8 relative, with growth over
-// the levels) stays within the 2 eps bar of the mixed form only above this
-static constexpr double kFp32BulkMinEps = 1e-6;
+// Smallest eps of each bulk precision: FP32 rounding (about 6e-8 relative,
+// with growth over the levels) stays within the 2 eps bar only above 1e-6,
+// the split bfloat16 products (about 2^-16 = 1.5e-5 relative) above 1e-4
+static void check_precision(int prec, double eps) {
+  H2_REQUIRE(prec >= H2_FP64 && prec <= H2_BF16_BULK, H2_ERR_ARG, "unknown precision");
+  H2_REQUIRE(prec != H2_FP32_BULK || eps >= 1e-6, H2_ERR_ARG,
+             "FP32 bulk products need eps >= 1e-6 (FP32 rounding would exceed 2 eps)");
+  H2_REQUIRE(prec < H2_BF16X2_BULK || eps >= 1e-4, H2_ERR_ARG,
+             "bfloat16 bulk products need eps >= 1e-4 (their rounding would exceed 2 eps)");
+}
 
 // The workspace of the previous call is reused at once: every later launch
 // is ordered after the earlier ones on the context stream, and the auxiliary
@@ -172,9 +179,7 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
       H2_REQUIRE(X[i] && Y[i], H2_ERR_ARG, "NULL factor");
     }
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
-    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
-    H2_REQUIRE(prec != H2_FP32_BULK || eps >= kFp32BulkMinEps, H2_ERR_ARG,
-               "FP32 bulk products need eps >= 1e-6 (FP32 rounding would exceed 2 eps)");
+    check_precision((int)prec, eps);
     need_device(ctx);
     begin_call(ctx);
     for (int i = 0; i < count; ++i) {
@@ -236,9 +241,7 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     H2_REQUIRE(G && Z && count >= 1, H2_ERR_ARG, "bad arguments");
     for (int i = 0; i < count; ++i) H2_REQUIRE(G[i] && Z[i], H2_ERR_ARG, "NULL operand");
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
-    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32_BULK, H2_ERR_ARG, "unknown precision");
-    H2_REQUIRE(prec != H2_FP32_BULK || eps >= kFp32BulkMinEps, H2_ERR_ARG,
-               "FP32 bulk products need eps >= 1e-6 (FP32 rounding would exceed 2 eps)");
+    check_precision((int)prec, eps);
     for (int i = 0; i < count; ++i) H2_REQUIRE(Z[i]->zero, H2_ERR_UNSUPPORTED, "Z must be zero");
     need_device(ctx);
     begin_call(ctx);

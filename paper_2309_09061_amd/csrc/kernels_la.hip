@@ -75,31 +75,71 @@ __device__ inline double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// One MFMA step of a 16 x 16 x 4 product; the FP32 form (bulk products of
-// the mixed precision) rounds the FP64 operands to FP32 and accumulates in
-// FP32.  Accumulator layouts (measured on gfx950): FP64 register v of lane
-// (r, q) holds D[4v + q][r]; FP32 register v holds D[4q + v][r].
-template <bool F32>
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// bfloat16 of a float by round-to-nearest-even (finite values), as its bits
+__device__ __forceinline__ short bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(short h) { return __uint_as_float((uint32_t)(uint16_t)h << 16); }
+
+// MFMA steps of a 16 x 16 product in the arithmetic of the bulk products:
+//   P = 0  FP64 (v_mfma_f64_16x16x4f64), one k per lane and step;
+//   P = 1  FP32: operands rounded to FP32, FP32 accumulation (16x16x4f32);
+//   P = 2  BF16 hi/lo: each operand a = a_h + a_l with a_h = bf16(a) and
+//          a_l = bf16(a - a_h), and a b ~ a_h b_h + a_h b_l + a_l b_h, three
+//          v_mfma_f32_16x16x16_bf16 with FP32 accumulation (about 2^-16
+//          relative per product);
+//   P = 3  plain BF16: a_h b_h only (about 2^-8 relative).
+// A step consumes KG values of k: lane (r, q) holds EPL = KG / 4 of them,
+// k = l0 + kof(u, q) for u < EPL (any bijection onto the chunk gives the same
+// sum; the BF16 instruction takes four consecutive k per lane).
+// Accumulator layouts (measured on gfx950): FP64 register v of lane (r, q)
+// holds D[4v + q][r]; FP32 register v holds D[4q + v][r].
+template <int P>
 struct Mfma16 {
-  typedef typename std::conditional<F32, v4f, v4d>::type acc_t;
+  static constexpr int KG = P >= 2 ? 16 : 4;
+  static constexpr int EPL = KG / 4;
+  typedef typename std::conditional<P == 0, v4d, v4f>::type acc_t;
   static __device__ __forceinline__ acc_t zero() {
     acc_t z = {0, 0, 0, 0};
     return z;
   }
-  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
-    if constexpr (F32)
-      return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
-    else
-      return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  static __device__ __forceinline__ int kof(int u, int q) { return P >= 2 ? 4 * q + u : q; }
+  static __device__ __forceinline__ acc_t step(const double* a, const double* b, acc_t c) {
+    if constexpr (P == 0) {
+      return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+    } else if constexpr (P == 1) {
+      return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[0], (float)b[0], c, 0, 0, 0);
+    } else {
+      v4s ah, bh, al, bl;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ah[u] = bf16_bits((float)a[u]);
+        bh[u] = bf16_bits((float)b[u]);
+        if constexpr (P == 2) {
+          al[u] = bf16_bits((float)(a[u] - (double)bf16_float(ah[u])));
+          bl[u] = bf16_bits((float)(b[u] - (double)bf16_float(bh[u])));
+        }
+      }
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+      if constexpr (P == 2) {
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+      }
+      return c;
+    }
   }
-  static __device__ __forceinline__ int row(int v, int q) { return F32 ? 4 * q + v : 4 * v + q; }
+  static __device__ __forceinline__ int row(int v, int q) { return P ? 4 * q + v : 4 * v + q; }
 };
 
-template <bool F32>
+template <int P>
 __global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict__ outs,
                                                        const GemmTerm* __restrict__ terms,
                                                        const int32_t* __restrict__ tiles, int ntiles) {
-  using M = Mfma16<F32>;
+  using M = Mfma16<P>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tix = blockIdx.x * 4 + wave;
   if (tix >= ntiles) return;
@@ -133,12 +173,15 @@ __global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict
       continue;
     }
     const int64_t sb_l = tB ? T.ldb : 1, sb_j = tB ? 1 : T.ldb;
-    for (int l0 = 0; l0 < T.k; l0 += 4) {
-      const int l = l0 + q;
-      double a = 0.0, b = 0.0;
-      if (ia && l < T.k) a = A[(int64_t)i * sa_i + (int64_t)l * sa_l];
-      if (jb && l < T.k) b = B[(int64_t)l * sb_l + (int64_t)j * sb_j];
-      acc = M::step(a * alpha, b, acc);
+    for (int l0 = 0; l0 < T.k; l0 += M::KG) {
+      double a[M::EPL], b[M::EPL];
+#pragma unroll
+      for (int u = 0; u < M::EPL; ++u) {
+        const int l = l0 + M::kof(u, q);
+        a[u] = (ia && l < T.k) ? A[(int64_t)i * sa_i + (int64_t)l * sa_l] * alpha : 0.0;
+        b[u] = (jb && l < T.k) ? B[(int64_t)l * sb_l + (int64_t)j * sb_j] : 0.0;
+      }
+      acc = M::step(a, b, acc);
     }
   }
   double* C = (double*)o.C;
@@ -159,10 +202,9 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
                 int prec, void* stream) {
   if (ntiles <= 0) return;
   dim3 grid((ntiles + 3) / 4);
-  if (prec)
-    hipLaunchKernelGGL(gemm_sum_kernel<true>, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
-  else
-    hipLaunchKernelGGL(gemm_sum_kernel<false>, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
+  auto k = prec == 1 ? gemm_sum_kernel<1> : prec == 2 ? gemm_sum_kernel<2> : prec == 3 ? gemm_sum_kernel<3>
+                                                                                      : gemm_sum_kernel<0>;
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
   HIP_OK(hipGetLastError());
 }
 
@@ -173,7 +215,7 @@ void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void chain3_kernel(const Chain3* __restrict__ items) {
   __shared__ double Ts[kChain3Max * kChain3Max];  // T(i, l) at i + 64 l
-  using M = Mfma16<false>;
+  using M = Mfma16<0>;
   constexpr int KS = kChain3Max / 4;  // MFMA k-steps at most
   const Chain3 it = items[blockIdx.x];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -198,7 +240,7 @@ __global__ __launch_bounds__(256) void chain3_kernel(const Chain3* __restrict__ 
     typename M::acc_t acc = M::zero();
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      if (4 * ks < it.p) acc = M::step(a[ks], b[ks], acc);
+      if (4 * ks < it.p) acc = M::step(&a[ks], &b[ks], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) Ts[i0 + M::row(v, q4) + (j0 + r) * kChain3Max] = acc[v];
   }
@@ -220,7 +262,7 @@ __global__ __launch_bounds__(256) void chain3_kernel(const Chain3* __restrict__ 
     typename M::acc_t acc = M::zero();
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      if (4 * ks < it.q) acc = M::step(a[ks], b[ks], acc);
+      if (4 * ks < it.q) acc = M::step(&a[ks], &b[ks], acc);
     if (j < it.n) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -252,11 +294,11 @@ extern __shared__ double lds_dyn[];
 // 16 x 16 output tile; each tile scans its block's triples and accumulates the
 // ones of the launch's kind
 // ---------------------------------------------------------------------------
-template <bool F32>
+template <int P>
 __global__ __launch_bounds__(256) void gemm_tri_kernel(const TriOut* __restrict__ outs,
                                                        const int32_t* __restrict__ tiles, int ntiles,
                                                        const TriFamily F) {
-  using M = Mfma16<F32>;
+  using M = Mfma16<P>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tix = blockIdx.x * 4 + wave;
   if (tix >= ntiles) return;
@@ -275,11 +317,14 @@ __global__ __launch_bounds__(256) void gemm_tri_kernel(const TriOut* __restrict_
     const int k = F.ks ? F.ks[tr.x] : F.k;
     const int64_t sa_i = F.tA ? lda : 1, sa_l = F.tA ? 1 : lda;
     const int64_t sb_l = F.tB ? ldb : 1, sb_j = F.tB ? 1 : ldb;
-    for (int l0 = 0; l0 < k; l0 += 4) {
-      const int l = l0 + q;
-      double a = 0.0, b = 0.0;
-      if (ia && l < k) a = A[(int64_t)i * sa_i + (int64_t)l * sa_l];
-      if (jb && l < k) b = B[(int64_t)l * sb_l + (int64_t)j * sb_j];
+    for (int l0 = 0; l0 < k; l0 += M::KG) {
+      double a[M::EPL], b[M::EPL];
+#pragma unroll
+      for (int u = 0; u < M::EPL; ++u) {
+        const int l = l0 + M::kof(u, q);
+        a[u] = (ia && l < k) ? A[(int64_t)i * sa_i + (int64_t)l * sa_l] : 0.0;
+        b[u] = (jb && l < k) ? B[(int64_t)l * sb_l + (int64_t)j * sb_j] : 0.0;
+      }
       acc = M::step(a, b, acc);
     }
   }
@@ -308,9 +353,9 @@ constexpr int kTriKC = 16;        // k-chunk
 constexpr int kTriLdA = 64 + 1;   // LDS stride of the A chunk (odd: spreads banks)
 constexpr int kTriLdB = kTriKC + 1;
 
-template <bool F32>
+template <int P>
 __global__ __launch_bounds__(256) void gemm_tri_block_kernel(const TriOut* __restrict__ outs, const TriFamily F) {
-  using M = Mfma16<F32>;
+  using M = Mfma16<P>;
   __shared__ double As[kTriKC * kTriLdA];  // A(i, l) at i + l * kTriLdA
   __shared__ double Bs[64 * kTriLdB];      // B(l, j) at l + j * kTriLdB
   const TriOut o = outs[blockIdx.x];
@@ -381,12 +426,16 @@ __global__ __launch_bounds__(256) void gemm_tri_block_kernel(const TriOut* __res
     }
     if (t < o.q1) fetch(l0);
 #pragma unroll
-    for (int ls = 0; ls < kTriKC; ls += 4) {
-      double av[2], bv[2];
+    for (int ls = 0; ls < kTriKC; ls += M::KG) {
+      double av[2][M::EPL], bv[2][M::EPL];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[(wi + 16 * a + r) + (ls + q) * kTriLdA];
+      for (int u = 0; u < M::EPL; ++u) {
+        const int l = ls + M::kof(u, q);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[(ls + q) + (wj + 16 * b + r) * kTriLdB];
+        for (int a = 0; a < 2; ++a) av[a][u] = As[(wi + 16 * a + r) + l * kTriLdA];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b][u] = Bs[l + (wj + 16 * b + r) * kTriLdB];
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -413,20 +462,20 @@ __global__ __launch_bounds__(256) void gemm_tri_block_kernel(const TriOut* __res
 void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, int prec, void* stream) {
   if (nouts <= 0) return;
   H2_REQUIRE(!fam.tA && !fam.tB, H2_ERR_ARG, "gemm_tri_block: untransposed operands only");
-  if (prec)
-    hipLaunchKernelGGL(gemm_tri_block_kernel<true>, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
-  else
-    hipLaunchKernelGGL(gemm_tri_block_kernel<false>, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
+  auto k = prec == 1   ? gemm_tri_block_kernel<1>
+           : prec == 2 ? gemm_tri_block_kernel<2>
+           : prec == 3 ? gemm_tri_block_kernel<3>
+                       : gemm_tri_block_kernel<0>;
+  hipLaunchKernelGGL(k, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, fam);
   HIP_OK(hipGetLastError());
 }
 
 void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, int prec, void* stream) {
   if (ntiles <= 0) return;
   dim3 grid((ntiles + 3) / 4);
-  if (prec)
-    hipLaunchKernelGGL(gemm_tri_kernel<true>, grid, dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles, fam);
-  else
-    hipLaunchKernelGGL(gemm_tri_kernel<false>, grid, dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles, fam);
+  auto k = prec == 1 ? gemm_tri_kernel<1> : prec == 2 ? gemm_tri_kernel<2> : prec == 3 ? gemm_tri_kernel<3>
+                                                                                      : gemm_tri_kernel<0>;
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, (hipStream_t)stream, outs, tiles, ntiles, fam);
   HIP_OK(hipGetLastError());
 }
 

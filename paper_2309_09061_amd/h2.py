@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2.so")
 
 KERNELS = {"log": 0, "expneg": 1, "inv4pi": 2, "inv": 3, "poly2": 100}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16": 3}
 KERNEL_FAMILIES = ["gemm_sum", "tsqr", "jacobi", "build", "other"]
 STEPS = ["setup", "nearfield", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat"]
 
