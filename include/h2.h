@@ -87,6 +87,9 @@ typedef enum {
   H2_K_EXPNEG = 1,   /* exp(-|x-y|),     diagonal 1 */
   H2_K_INV4PI = 2,   /* 1/(4 pi |x-y|),  diagonal 0 (single-layer kernel, Section 7) */
   H2_K_INV = 3,      /* 1/|x-y|,         diagonal 0 */
+  H2_K_DLP = 4,      /* <n(x), x-y> / (4 pi |x-y|^3), diagonal 0: the double-layer kernel of
+                        Section 7, with the unit normal n(x) at the row point (needs
+                        h2_compress_kernel_normals); not symmetric */
   H2_K_POLY2 = 100   /* (x.y)^2, a degree-2 polynomial reproduced exactly at order >= 3 */
 } h2_kernel;
 
@@ -162,6 +165,22 @@ h2_status h2_tree_structure(const h2_tree* tree, int64_t* cl_off, int64_t* cl_si
  * hold g(x_i, x_j).  Row and column bases coincide.  1 <= order, k <= 128. */
 h2_status h2_compress_kernel(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order,
                              h2_matrix** out);
+
+/* The same with unit normals at the points (host, n x dim, row-major, in the
+ * input point order of h2_tree_build; copied), for kernels that use them:
+ * H2_K_DLP, the double-layer kernel <n(x), x-y>/(4 pi |x-y|^3) (Section 7).
+ * With gamma(x, y) = 1/(4 pi |x-y|) that kernel is -<n(x), grad_x gamma>,
+ * so gamma is interpolated in both variables and the row side is
+ * differentiated: row leaf bases -<n(x_i), grad l_{t,nu}(x_i)>, column leaf
+ * bases l_{s,mu}(y_j), transfers as for plain interpolation (both bases),
+ * couplings gamma(xi_{t,nu}, xi_{s,mu}), nearfield entries from the kernel.
+ * The interpolation boxes of this kernel are the bounding cubes of the
+ * cluster boxes (a cluster on one face of a surface has a flat box, on
+ * which a derivative across the face would be determined by rounding).
+ * Other kernels ignore the normals.  NULL normals: H2_ERR_ARG; non-finite
+ * normals: H2_ERR_NUMERIC. */
+h2_status h2_compress_kernel_normals(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order,
+                                     const double* normals, h2_matrix** out);
 
 /* Phase 1 for `count` independent products X[i] Y[i] (Section 4, Figure
  * "induced_basis", for the row basis and, on the adjoint pair (Y*, X*), for

@@ -26,6 +26,12 @@ ADM, INADM, SPLIT = "A", "I", "N"
 
 # Relative tolerance of the numerical rank of V_{X,t} (reading R18).
 VX_RTOL = 1e-12
+# Section 5 scaling (reading R8): a block whose spectral norm is at most
+# BLOCK_RTOL times the largest block norm of its level (same pass, same kind
+# of block) is zero up to rounding and is dropped like a block of norm 0.
+BLOCK_RTOL = 1e-12
+# blocks dropped by that rule (not by an exact zero norm) since import
+DROPPED = [0]
 
 
 # ----------------------------------------------------------------------------
@@ -336,13 +342,17 @@ class H2Matrix:
 # Construction by Chebyshev interpolation (Section 2, Example "Integral
 # operator"; readings R4, R5)
 # ----------------------------------------------------------------------------
-def kernel_eval(kind: str, x: np.ndarray, y: np.ndarray, same_index=None) -> np.ndarray:
+def kernel_eval(kind: str, x: np.ndarray, y: np.ndarray, same_index=None, nx: np.ndarray = None) -> np.ndarray:
     """g(x_i, y_j) for point arrays x (p x d), y (q x d).  R5: entries with
-    i == j (same_index given as the diagonal offset) use the diagonal rule."""
+    i == j (same_index given as the diagonal offset) use the diagonal rule.
+    The double-layer kernel "dlp" of Section 7, <n(x), x - y> / (4 pi |x - y|^3),
+    takes the unit normals nx (p x d) at the points x."""
     diff = x[:, None, :] - y[None, :, :]
     r = np.sqrt(np.sum(diff * diff, axis=2))
     with np.errstate(divide="ignore", invalid="ignore"):
-        if kind == "log":
+        if kind == "dlp":
+            g, dg = np.sum(nx[:, None, :] * diff, axis=2) / (4.0 * np.pi * r ** 3), 0.0
+        elif kind == "log":
             g, dg = np.log(r), 0.0
         elif kind == "expneg":
             g, dg = np.exp(-r), 1.0
@@ -377,6 +387,23 @@ def lagrange(nodes: np.ndarray, x: np.ndarray) -> np.ndarray:
     return L
 
 
+def lagrange_derivative(nodes: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """D[i, j] = l_j'(x_i), written without division by x - xi:
+    l_j'(x) = sum_{q != j} 1/(xi_j - xi_q) prod_{r != j, q} (x - xi_r)/(xi_j - xi_r)."""
+    m = len(nodes)
+    D = np.zeros((len(x), m))
+    for j in range(m):
+        for q in range(m):
+            if q == j:
+                continue
+            term = np.full(len(x), 1.0 / (nodes[j] - nodes[q]))
+            for r_ in range(m):
+                if r_ != j and r_ != q:
+                    term *= (x - nodes[r_]) / (nodes[j] - nodes[r_])
+            D[:, j] += term
+    return D
+
+
 def _axis_boxes(tree: ClusterTree, c: int):
     """R4: box edges narrower than 1e-12 * root diameter are widened."""
     floor = 1e-12 * tree.diam(0)
@@ -389,6 +416,17 @@ def _axis_boxes(tree: ClusterTree, c: int):
     return lo, hi
 
 
+def _cube_boxes(tree: ClusterTree, c: int):
+    """R22: interpolation box of the double-layer bases, the bounding cube of
+    the cluster's (R4-widened) box: same center, every edge as long as the
+    longest.  A cluster on one face of the cube surface has a flat box, on
+    which derivatives across the face would be determined by rounding."""
+    lo, hi = _axis_boxes(tree, c)
+    half = 0.5 * float(np.max(hi - lo))
+    mid = 0.5 * (lo + hi)
+    return mid - half, mid + half
+
+
 def _multi_indices(m: int, d: int) -> np.ndarray:
     """Tensor multi-indices, axis 0 fastest: nu = nu_0 + m nu_1 + m^2 nu_2."""
     k = m ** d
@@ -396,16 +434,16 @@ def _multi_indices(m: int, d: int) -> np.ndarray:
     return np.stack([(lin // (m ** a)) % m for a in range(d)], axis=1)
 
 
-def interpolation_points(tree: ClusterTree, c: int, m: int) -> np.ndarray:
-    lo, hi = _axis_boxes(tree, c)
+def interpolation_points(tree: ClusterTree, c: int, m: int, boxes=_axis_boxes) -> np.ndarray:
+    lo, hi = boxes(tree, c)
     mi = _multi_indices(m, tree.dim)
     nodes = [cheb_nodes(lo[a], hi[a], m) for a in range(tree.dim)]
     return np.stack([nodes[a][mi[:, a]] for a in range(tree.dim)], axis=1)
 
 
-def _tensor_lagrange(tree: ClusterTree, c: int, m: int, x: np.ndarray) -> np.ndarray:
+def _tensor_lagrange(tree: ClusterTree, c: int, m: int, x: np.ndarray, boxes=_axis_boxes) -> np.ndarray:
     """Tensor Lagrange polynomials of cluster c evaluated at points x (p x d)."""
-    lo, hi = _axis_boxes(tree, c)
+    lo, hi = boxes(tree, c)
     mi = _multi_indices(m, tree.dim)
     out = np.ones((x.shape[0], m ** tree.dim))
     for a in range(tree.dim):
@@ -414,16 +452,50 @@ def _tensor_lagrange(tree: ClusterTree, c: int, m: int, x: np.ndarray) -> np.nda
     return out
 
 
-def interpolation_basis(tree: ClusterTree, m: int) -> ClusterBasis:
+def _tensor_normal_derivative(tree: ClusterTree, c: int, m: int, x: np.ndarray, nx: np.ndarray,
+                              boxes=_axis_boxes) -> np.ndarray:
+    """-<n(x_i), grad l_{c,nu}(x_i)> for points x (p x d) with normals nx."""
+    lo, hi = boxes(tree, c)
+    mi = _multi_indices(m, tree.dim)
+    L, D = [], []
+    for a in range(tree.dim):
+        nodes = cheb_nodes(lo[a], hi[a], m)
+        L.append(lagrange(nodes, x[:, a])[:, mi[:, a]])
+        D.append(lagrange_derivative(nodes, x[:, a])[:, mi[:, a]])
+    out = np.zeros((x.shape[0], m ** tree.dim))
+    for d in range(tree.dim):
+        term = D[d].copy()
+        for a in range(tree.dim):
+            if a != d:
+                term *= L[a]
+        out -= nx[:, d:d + 1] * term
+    return out
+
+
+def interpolation_basis(tree: ClusterTree, m: int, boxes=_axis_boxes) -> ClusterBasis:
     """Leaf V_t[i,nu] = l_{t,nu}(x_i); transfer E_{t'}[nu',nu] = l_{t,nu}(xi_{t',nu'})."""
     cb = ClusterBasis(tree)
     k = m ** tree.dim
     for c in range(tree.nclusters):
         cb.rank[c] = k
         if tree.is_leaf(c):
-            cb.leaf[c] = _tensor_lagrange(tree, c, m, tree.points[tree.rng(c)])
+            cb.leaf[c] = _tensor_lagrange(tree, c, m, tree.points[tree.rng(c)], boxes)
         if c > 0:
-            cb.transfer[c] = _tensor_lagrange(tree, tree.parent[c], m, interpolation_points(tree, c, m))
+            cb.transfer[c] = _tensor_lagrange(tree, tree.parent[c], m, interpolation_points(tree, c, m, boxes),
+                                              boxes)
+    return cb
+
+
+def normal_derivative_basis(tree: ClusterTree, m: int, normals: np.ndarray) -> ClusterBasis:
+    """Row basis of the double-layer kernel: with gamma(x, y) = 1/(4 pi |x - y|),
+    <n(x), x - y>/(4 pi |x - y|^3) = -<n(x), grad_x gamma(x, y)>, so the
+    interpolant of gamma gives leaf V_t[i,nu] = -<n(x_i), grad l_{t,nu}(x_i)>;
+    transfers as for the interpolation basis (the gradient of a nested
+    polynomial is nested), on the R22 boxes.  normals: cluster order."""
+    cb = interpolation_basis(tree, m, _cube_boxes)
+    for c in tree.leaves:
+        r = tree.rng(c)
+        cb.leaf[c] = _tensor_normal_derivative(tree, c, m, tree.points[r], normals[r], _cube_boxes)
     return cb
 
 
@@ -440,6 +512,27 @@ def kernel_h2(tree: ClusterTree, bt: BlockTree, kind: str, m: int, basis: Cluste
             N[(t, s)] = kernel_eval(kind, tree.points[tree.rng(t)], tree.points[tree.rng(s)],
                                     same_index=True if t == s else None)
     return H2Matrix(V, V, bt, S, N)
+
+
+def dlp_h2(tree: ClusterTree, bt: BlockTree, m: int, normals: np.ndarray) -> H2Matrix:
+    """The double-layer kernel matrix of Section 7 (<n(x_i), x_i - x_j> /
+    (4 pi |x_i - x_j|^3), diagonal 0; normals in the input point order):
+    row basis normal_derivative_basis, column basis the interpolation basis,
+    both on the R22 boxes; S_ts[nu,mu] = gamma(xi_{t,nu}, xi_{s,mu}); exact
+    nearfield.  Not symmetric: row and column bases differ."""
+    nrm = np.asarray(normals, dtype=np.float64)[tree.perm]
+    V = normal_derivative_basis(tree, m, nrm)
+    Wb = interpolation_basis(tree, m, _cube_boxes)
+    ip = {c: interpolation_points(tree, c, m, _cube_boxes) for c in range(tree.nclusters)}
+    S, N = {}, {}
+    for (t, s), ty in bt.type.items():
+        if ty == ADM:
+            S[(t, s)] = kernel_eval("inv4pi", ip[t], ip[s])
+        elif ty == INADM:
+            rt, rs = tree.rng(t), tree.rng(s)
+            N[(t, s)] = kernel_eval("dlp", tree.points[rt], tree.points[rs], same_index=True if t == s else None,
+                                    nx=nrm[rt])
+    return H2Matrix(V, Wb, bt, S, N)
 
 
 def identity_h2(tree: ClusterTree, bt: BlockTree, m: int) -> H2Matrix:
@@ -551,30 +644,31 @@ def total_weights(Y: H2Matrix, RY: dict) -> dict:
     """Figure "total_weights": Z_s = R factor of
     [Z_{s+} E_{Y,s}^*; R_{Y,r} S_{Y,sr}^* (r in row(s))], top-down.
 
-    Section 5 / R8: block r is scaled by 1/||S_{Y,sr} R_{Y,r}^*||_2 (blocks of
-    norm zero are dropped).  R7: parent block first, then row(s) in
-    increasing cluster id.
+    Section 5 / R8: block r is scaled by 1/||S_{Y,sr} R_{Y,r}^*||_2; blocks of
+    norm zero, or at most BLOCK_RTOL times the largest of the level, are
+    dropped.  R7: parent block first, then row(s) in increasing cluster id.
+    The recursion is taken level by level from the root (the clusters of a
+    level are independent).
     """
     tr = Y.V.tree
-    k = Y.V.rank[0]
     row = Y.bt.row_map((ADM,))
     Z = {}
-
-    def rec(s, Zp):
-        blocks = []
-        if Zp is not None:
-            blocks.append(mul(Zp, Y.V.transfer[s].T))
-        for r in row.get(s, []):
-            M = mul(RY[r], Y.S[(s, r)].T)
-            w = norm2(M)
-            if w > 0.0:
-                blocks.append(M / w)
-        G = np.vstack(blocks) if blocks else np.zeros((0, Y.V.rank[s]))
-        Z[s] = qr_r(G)
-        for ch in tr.children[s]:
-            rec(ch, Z[s])
-
-    rec(0, None)
+    for lev in range(tr.depth + 1):
+        cls = list(tr.clusters_at(lev))
+        M = {(s, r): mul(RY[r], Y.S[(s, r)].T) for s in cls for r in row.get(s, [])}
+        w = {b: norm2(m) for b, m in M.items()}
+        floor = BLOCK_RTOL * max(w.values(), default=0.0)
+        for s in cls:
+            blocks = []
+            if lev > 0:
+                blocks.append(mul(Z[tr.parent[s]], Y.V.transfer[s].T))
+            for r in row.get(s, []):
+                if w[(s, r)] > floor:
+                    blocks.append(M[(s, r)] / w[(s, r)])
+                elif w[(s, r)] > 0.0:
+                    DROPPED[0] += 1
+            G = np.vstack(blocks) if blocks else np.zeros((0, Y.V.rank[s]))
+            Z[s] = qr_r(G)
     return Z
 
 
@@ -607,8 +701,13 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
     whenever V_{X,t} has full numerical rank, and Q_{X,t} is taken from the
     SVD of V_{X,t} so that the kept range is unique; the remainder has
     (rows - k1) rows.  R8: the block of s is scaled by
-    1/||X|_{t x s} V_{Y,s}||_2 (leaf) or 1/||Ahat_{t,s}||_2 (non-leaf).
-    R9: rank k2 = #{sigma > eps}.
+    1/||X|_{t x s} V_{Y,s}||_2 (leaf) or 1/||Ahat_{t,s}||_2 (non-leaf);
+    blocks of norm zero, or at most BLOCK_RTOL times the largest block norm
+    of the level, are dropped (zero up to rounding: for the double-layer
+    kernel the blocks of two clusters on one face of the cube).
+    R9: rank k2 = #{sigma > eps}.  The recursion of Figure "induced_basis"
+    is taken level by level from the leaves (the clusters of a level are
+    independent), so that each level's largest block norm is known.
     """
     rt = X.V.tree
     if any(rt.level[c] != rt.depth for c in rt.leaves):
@@ -641,24 +740,16 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
         Q.rank[t] = k1 + k2
         return Qt
 
-    def rec(t):
+    def level_blocks(t):
+        """The blocks of t (leaf: X|_{t x s} V_{Y,s}; else Ahat_{t,s}), and
+        for a non-leaf the stacked V_X part and the children's row offsets."""
         if rt.is_leaf(t):
             B = {}
-            blocks = []
             for s in Cmap.get(t, []):
                 assert X.bt.type[(t, s)] == INADM
-                B[s] = mul(X.N[(t, s)], Y.V.leaf[s])     # X|_{t x s} V_{Y,s}
-                w = norm2(B[s])
-                if w > 0.0 and Z[s].shape[0] > 0:
-                    blocks.append(mul(B[s], Z[s].T) / w)
-            Qt = compress(t, X.V.leaf[t], blocks)
-            Q.leaf[t] = Qt
-            for s in B:
-                A[(t, s)] = mul(Qt.T, B[s])
-            return
+                B[s] = mul(X.N[(t, s)], Y.V.leaf[s])      # X|_{t x s} V_{Y,s}
+            return B, X.V.leaf[t], None
         kids = rt.children[t]
-        for ch in kids:
-            rec(ch)
         offs, o = {}, 0
         for ch in kids:
             offs[ch] = o
@@ -667,7 +758,7 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
         VXhat = np.zeros((rows, k))
         for ch in kids:
             VXhat[offs[ch]:offs[ch] + RX[ch].shape[0]] = mul(RX[ch], X.V.transfer[ch])
-        Ahat, blocks = {}, []
+        Ahat = {}
         for s in Cmap.get(t, []):
             M = np.zeros((rows, k))
             for ch in kids:
@@ -679,16 +770,30 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
                         At = A[(ch, sc)]
                     M[offs[ch]:offs[ch] + Q.rank[ch]] += mul(At, Y.V.transfer[sc])
             Ahat[s] = M
-            w = norm2(M)
-            if w > 0.0 and Z[s].shape[0] > 0:
-                blocks.append(mul(M, Z[s].T) / w)
-        Qhat = compress(t, VXhat, blocks)
-        for ch in kids:
-            Q.transfer[ch] = Qhat[offs[ch]:offs[ch] + Q.rank[ch], :]
-        for s in Ahat:
-            A[(t, s)] = mul(Qhat.T, Ahat[s])
+        return Ahat, VXhat, offs
 
-    rec(0)
+    for lev in range(rt.depth, -1, -1):
+        cls = list(rt.clusters_at(lev))
+        parts = {t: level_blocks(t) for t in cls}
+        w = {(t, s): norm2(M) for t in cls for s, M in parts[t][0].items()}
+        floor = BLOCK_RTOL * max(w.values(), default=0.0)
+        for t in cls:
+            Bs, VX, offs = parts[t]
+            blocks = []
+            for s, M in Bs.items():
+                if w[(t, s)] > floor and Z[s].shape[0] > 0:
+                    blocks.append(mul(M, Z[s].T) / w[(t, s)])
+                elif 0.0 < w[(t, s)] <= floor:
+                    DROPPED[0] += 1
+            Qt = compress(t, VX, blocks)
+            if offs is None:
+                Q.leaf[t] = Qt
+            else:
+                for ch in rt.children[t]:
+                    Q.transfer[ch] = Qt[offs[ch]:offs[ch] + Q.rank[ch], :]
+            for s, M in Bs.items():
+                A[(t, s)] = mul(Qt.T, M)
+
     out = InducedBasis(Q, RX, A, sig_out, assembled)
     out.P = P
     return out
@@ -1096,11 +1201,15 @@ def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float 
     return p1, p2
 
 
-def build_problem(points, leaf_size, eta, order, kx, ky):
-    """Tree, block tree (T_IJ = T_JK = T_IK) and the H^2-matrices X, Y."""
+def build_problem(points, leaf_size, eta, order, kx, ky, normals=None):
+    """Tree, block tree (T_IJ = T_JK = T_IK) and the H^2-matrices X, Y
+    (kernel "dlp" needs the normals at the points, input order)."""
     tree = ClusterTree(points, leaf_size)
     bt = BlockTree(tree, tree, eta)
-    V = interpolation_basis(tree, order)
-    X = kernel_h2(tree, bt, kx, order, V)
-    Y = X if ky == kx else kernel_h2(tree, bt, ky, order, V)
+    V = interpolation_basis(tree, order) if "dlp" not in (kx, ky) or kx != ky else None
+
+    def make(kind):
+        return dlp_h2(tree, bt, order, normals) if kind == "dlp" else kernel_h2(tree, bt, kind, order, V)
+    X = make(kx)
+    Y = X if ky == kx else make(ky)
     return tree, bt, X, Y

@@ -149,25 +149,42 @@ h2_status h2_tree_structure(const h2_tree* tree, int64_t* cl_off, int64_t* cl_si
   });
 }
 
-h2_status h2_compress_kernel(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order, h2_matrix** out) {
+static h2_status compress_any(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order, const double* normals,
+                              h2_matrix** out) {
   return guard([&] {
     H2_REQUIRE(out, H2_ERR_ARG, "NULL output");
     *out = nullptr;
     H2_REQUIRE(tree, H2_ERR_ARG, "NULL tree");
     H2_REQUIRE(kernel == H2_K_LOG || kernel == H2_K_EXPNEG || kernel == H2_K_INV4PI || kernel == H2_K_INV ||
-                   kernel == H2_K_POLY2,
+                   kernel == H2_K_DLP || kernel == H2_K_POLY2,
                H2_ERR_ARG, "unknown kernel");
+    H2_REQUIRE(kernel != H2_K_DLP || normals, H2_ERR_ARG,
+               "the double-layer kernel needs normals (h2_compress_kernel_normals)");
     need_device(ctx);
     begin_call(ctx);
     auto* m = new h2_matrix();
     try {
-      compress_kernel(ctx, tree, (int)kernel, order, m);
+      compress_kernel(ctx, tree, (int)kernel, order, normals, m);
     } catch (...) {
       delete m;
       throw;
     }
     *out = m;
   });
+}
+
+h2_status h2_compress_kernel(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order, h2_matrix** out) {
+  return compress_any(ctx, tree, kernel, order, nullptr, out);
+}
+
+h2_status h2_compress_kernel_normals(h2_ctx* ctx, const h2_tree* tree, h2_kernel kernel, int order,
+                                     const double* normals, h2_matrix** out) {
+  if (!normals) {
+    g_err = "NULL normals";
+    if (out) *out = nullptr;
+    return H2_ERR_ARG;
+  }
+  return compress_any(ctx, tree, kernel, order, normals, out);
 }
 
 h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X, const h2_matrix* const* Y,

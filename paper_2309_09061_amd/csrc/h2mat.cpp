@@ -2,16 +2,21 @@
 // (Section 2, Example "Integral operator"), zero matrices, the O(nk)
 // matrix-vector product (forward transform, couplings, backward transform,
 // nearfield) and densification for tests.
+#include <cmath>
+
 #include "internal.h"
 
 namespace h2 {
 
-void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2_matrix* out) {
+void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, const double* normals,
+                     h2_matrix* out) {
   const TreeH& T = *tree->ct;
   const BlockTreeH& B = *tree->bt;
   int k = 1;
   for (int a = 0; a < T.dim; ++a) k *= order;
   H2_REQUIRE(order >= 1 && k <= 128, H2_ERR_ARG, "order^dim must be in [1, 128]");
+  const bool dlp = kernel == H2_K_DLP;
+  H2_REQUIRE(!dlp || normals, H2_ERR_ARG, "the double-layer kernel needs the normals at the points");
   out->ctx = ctx;
   out->mem.bind(ctx);
   H2Core& C = out->c;
@@ -19,16 +24,50 @@ void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2
   C.bt = tree->bt;
   C.V.resize(T.ncl);
   Arena& A = out->mem;
-  // geometry on the device
+  // Interpolation boxes: the (widened) cluster boxes; for the double-layer
+  // kernel their bounding cubes (same center, every edge the longest one),
+  // since a cluster on one face of a surface has a flat box on which the
+  // derivative across the face would be determined by rounding
+  std::vector<double> blo = T.lo, bhi = T.hi;
+  if (dlp)
+    for (int c = 0; c < T.ncl; ++c) {
+      double* l = &blo[(size_t)c * T.dim];
+      double* h = &bhi[(size_t)c * T.dim];
+      double edge = 0.0;
+      for (int a = 0; a < T.dim; ++a) edge = std::max(edge, h[a] - l[a]);
+      const double half = 0.5 * edge;
+      for (int a = 0; a < T.dim; ++a) {
+        const double mid = 0.5 * (l[a] + h[a]);
+        l[a] = mid - half;
+        h[a] = mid + half;
+      }
+    }
+  // geometry on the device (points and normals in cluster order)
   double* pts = A.get<double>(T.pts.size());
-  double* lo = A.get<double>(T.lo.size());
-  double* hi = A.get<double>(T.hi.size());
+  double* lo = A.get<double>(blo.size());
+  double* hi = A.get<double>(bhi.size());
   dev_h2d(pts, T.pts.data(), T.pts.size() * 8, ctx->stream);
-  dev_h2d(lo, T.lo.data(), T.lo.size() * 8, ctx->stream);
-  dev_h2d(hi, T.hi.data(), T.hi.size() * 8, ctx->stream);
-  // leaf bases and transfers
-  std::vector<ChebLeaf> leaves;
+  dev_h2d(lo, blo.data(), blo.size() * 8, ctx->stream);
+  dev_h2d(hi, bhi.data(), bhi.size() * 8, ctx->stream);
+  double* nrm = nullptr;
+  if (dlp) {
+    std::vector<double> nc((size_t)T.n * T.dim);
+    for (int64_t p = 0; p < T.n; ++p)
+      for (int a = 0; a < T.dim; ++a) {
+        const double v = normals[T.perm[p] * T.dim + a];
+        H2_REQUIRE(std::isfinite(v), H2_ERR_NUMERIC, "non-finite normal");
+        nc[(size_t)p * T.dim + a] = v;
+      }
+    nrm = A.get<double>(nc.size());
+    dev_h2d(nrm, nc.data(), nc.size() * 8, ctx->stream);
+    dev_sync(ctx->stream);  // nc is a host temporary
+  }
+  // leaf bases and transfers (the column basis of the double-layer kernel
+  // has plain interpolation leaves and the row basis's transfers)
+  std::vector<ChebLeaf> leaves, wleaves;
   std::vector<ChebPair> transfers;
+  Basis Wb;
+  if (dlp) Wb.resize(T.ncl);
   for (int c = 0; c < T.ncl; ++c) {
     C.V.rank[c] = k;
     if (T.leaf(c)) {
@@ -36,6 +75,12 @@ void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2
       C.V.leaf[c] = V;
       C.V.leaf_ld[c] = std::max<int64_t>(T.size[c], 1);
       leaves.push_back({V, C.V.leaf_ld[c], T.off[c], c, (int32_t)T.size[c]});
+      if (dlp) {
+        double* Wl = A.get<double>((size_t)T.size[c] * k);
+        Wb.leaf[c] = Wl;
+        Wb.leaf_ld[c] = C.V.leaf_ld[c];
+        wleaves.push_back({Wl, Wb.leaf_ld[c], T.off[c], c, (int32_t)T.size[c]});
+      }
     }
     if (c > 0) {
       double* E = A.get<double>((size_t)k * k);
@@ -61,11 +106,25 @@ void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2
                       B.t[b] == B.s[b] ? 1 : 0, 0});
     }
   }
-  C.W = C.V;  // the same interpolation on both sides
-  k_cheb_leaf(upload(ctx, leaves), (int)leaves.size(), pts, lo, hi, T.dim, order, ctx->stream);
+  if (dlp) {
+    // <n(x), x - y>/(4 pi |x - y|^3) = -<n(x), grad_x gamma(x, y)> with
+    // gamma = 1/(4 pi |x - y|): interpolate gamma, differentiate the row side
+    for (int c = 0; c < T.ncl; ++c) {
+      Wb.rank[c] = k;
+      Wb.tr[c] = C.V.tr[c];
+      Wb.tr_ld[c] = C.V.tr_ld[c];
+    }
+    C.W = Wb;
+    k_cheb_leaf_dn(upload(ctx, leaves), (int)leaves.size(), pts, nrm, lo, hi, T.dim, order, ctx->stream);
+    k_cheb_leaf(upload(ctx, wleaves), (int)wleaves.size(), pts, lo, hi, T.dim, order, ctx->stream);
+  } else {
+    C.W = C.V;  // the same interpolation on both sides
+    k_cheb_leaf(upload(ctx, leaves), (int)leaves.size(), pts, lo, hi, T.dim, order, ctx->stream);
+  }
   k_cheb_transfer(upload(ctx, transfers), (int)transfers.size(), lo, hi, T.dim, order, ctx->stream);
-  k_cheb_coupling(upload(ctx, coup), (int)coup.size(), lo, hi, T.dim, order, kernel, ctx->stream);
-  k_nearfield(upload(ctx, near), (int)near.size(), pts, T.dim, kernel, ctx->stream);
+  k_cheb_coupling(upload(ctx, coup), (int)coup.size(), lo, hi, T.dim, order, dlp ? H2_K_INV4PI : kernel,
+                  ctx->stream);
+  k_nearfield(upload(ctx, near), (int)near.size(), pts, nrm, T.dim, kernel, ctx->stream);
 }
 
 void zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix* out) {

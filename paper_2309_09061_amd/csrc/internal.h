@@ -237,6 +237,9 @@ int jacobi_mid_max_m();
 void k_jacobi(const JacobiProb* probs, int n, int lds_doubles, size_t slot, double* scratch, bool wide,
               void* stream);
 void k_fill(const FillItem* items, int n, void* stream);
+// groups g of values *vals[i], i in [gptr[g], gptr[g+1]): values at most
+// rtol times the group's largest become 0
+void k_drop_small(double* const* vals, const int32_t* gptr, int ngroups, double rtol, void* stream);
 
 // interpolation / kernel evaluation
 struct ChebLeaf {   // V[i, nu] for leaf cluster c
@@ -260,7 +263,12 @@ void k_cheb_transfer(const ChebPair* d, int n, const double* lo, const double* h
                      int order, void* stream);
 void k_cheb_coupling(const ChebPair* d, int n, const double* lo, const double* hi, int dim,
                      int order, int kernel, void* stream);
-void k_nearfield(const NearBlock* d, int n, const double* pts, int dim, int kernel, void* stream);
+// leaves of the double-layer row basis: -<n(x_i), grad l_{c,nu}(x_i)>
+void k_cheb_leaf_dn(const ChebLeaf* d, int n, const double* pts, const double* nrm, const double* lo,
+                    const double* hi, int dim, int order, void* stream);
+// nrm: unit normals at the points (cluster order), read for H2_K_DLP only
+void k_nearfield(const NearBlock* d, int n, const double* pts, const double* nrm, int dim, int kernel,
+                 void* stream);
 
 // segmented sums of squares: out[i] = sum over items of segment i of ||M||_F^2
 struct SumsqItem {
@@ -598,9 +606,20 @@ struct NormBatch {
     int rows, cols;
   };
   std::vector<Item> items;
-  void add(const double* A, int64_t lda, int rows, int cols) { items.push_back({A, lda, rows, cols}); }
+  // drop rule of the Section 5 scaling: sigma_max of an item at most
+  // drop_rtol times the largest of its group is set to 0 (the block is then
+  // dropped); group[i] numbers the groups from 0 in item order (empty: off)
+  double drop_rtol = 0.0;
+  std::vector<int32_t> group;
+  void add(const double* A, int64_t lda, int rows, int cols, int grp = -1) {
+    items.push_back({A, lda, rows, cols});
+    if (grp >= 0) group.push_back(grp);
+  }
   std::vector<const double*> run(h2_ctx* ctx);  // device pointer to sigma_max of each item
 };
+// a block whose spectral norm is at most this fraction of the largest block
+// norm of its level (same pass and kind) is zero up to rounding
+constexpr double kBlockRtol = 1e-12;
 
 // drops a reference on a root context; the last one deletes it
 void ctx_unref(h2_ctx* root);
@@ -678,7 +697,9 @@ struct View {
 ProductTreeH build_product_tree(const View& X, const View& Y, int ncl);
 
 // matrices
-void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, h2_matrix* out);
+// normals: host n x dim in the input point order (H2_K_DLP only; else null)
+void compress_kernel(h2_ctx* ctx, const h2_tree* tree, int kernel, int order, const double* normals,
+                     h2_matrix* out);
 void zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix* out);
 void matvec(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double* x, double beta,
             double* y, int nvec);

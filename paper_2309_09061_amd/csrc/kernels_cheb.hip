@@ -32,6 +32,43 @@ __device__ inline double lagrange1(double lo, double hi, int order, int j, doubl
   return v;
 }
 
+// derivative of Lagrange polynomial j at x, without division by x - xi:
+// l_j'(x) = sum_{q != j} 1/(xi_j - xi_q) prod_{r != j, q} (x - xi_r)/(xi_j - xi_r)
+__device__ inline double lagrange1_d(double lo, double hi, int order, int j, double x) {
+  const double xj = cheb_node(lo, hi, order, j);
+  double s = 0.0;
+  for (int q = 0; q < order; ++q) {
+    if (q == j) continue;
+    const double xq = cheb_node(lo, hi, order, q);
+    double term = 1.0 / (xj - xq);
+    for (int r = 0; r < order; ++r)
+      if (r != j && r != q) {
+        const double xr = cheb_node(lo, hi, order, r);
+        term *= (x - xr) / (xj - xr);
+      }
+    s += term;
+  }
+  return s;
+}
+
+// -<n, grad l_{c,nu}(x)>: the row basis of the double-layer kernel
+__device__ inline double lagrange_t_dn(const double* lo, const double* hi, int c, int dim, int order, int nu,
+                                       const double* x, const double* n) {
+  int ja[3];
+  for (int a = 0; a < dim; ++a) {
+    ja[a] = nu % order;
+    nu /= order;
+  }
+  double out = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    double term = lagrange1_d(lo[c * dim + d], hi[c * dim + d], order, ja[d], x[d]);
+    for (int a = 0; a < dim; ++a)
+      if (a != d) term *= lagrange1(lo[c * dim + a], hi[c * dim + a], order, ja[a], x[a]);
+    out -= n[d] * term;
+  }
+  return out;
+}
+
 // tensor Lagrange polynomial nu of cluster c at point x (dim coordinates)
 __device__ inline double lagrange_t(const double* lo, const double* hi, int c, int dim, int order,
                                     int nu, const double* x) {
@@ -73,6 +110,18 @@ __device__ inline double kernel_g(int kernel, const double* x, const double* y, 
   }
 }
 
+// <n(x), x - y> / (4 pi |x - y|^3), the double-layer kernel
+__device__ inline double kernel_dlp(const double* x, const double* y, const double* nx, int dim) {
+  double s = 0.0, p = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    const double d = x[a] - y[a];
+    s += d * d;
+    p += nx[a] * d;
+  }
+  const double r = sqrt(s);
+  return p / (4.0 * M_PI * r * r * r);
+}
+
 __device__ inline double kernel_diag(int kernel, const double* x, int dim) {
   switch (kernel) {
     case H2_K_EXPNEG: return 1.0;
@@ -91,6 +140,20 @@ __global__ void cheb_leaf_kernel(const ChebLeaf* d, const double* pts, const dou
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e % L.size), nu = (int)(e / L.size);
     L.V[i + nu * L.ldv] = lagrange_t(lo, hi, L.c, dim, order, nu, pts + (L.off + i) * dim);
+  }
+}
+
+__global__ void cheb_leaf_dn_kernel(const ChebLeaf* d, const double* pts, const double* nrm, const double* lo,
+                                    const double* hi, int dim, int order) {
+  const ChebLeaf L = d[blockIdx.y];
+  int k = 1;
+  for (int a = 0; a < dim; ++a) k *= order;
+  const int64_t total = (int64_t)L.size * k;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % L.size), nu = (int)(e / L.size);
+    L.V[i + nu * L.ldv] =
+        lagrange_t_dn(lo, hi, L.c, dim, order, nu, pts + (L.off + i) * dim, nrm + (L.off + i) * dim);
   }
 }
 
@@ -121,7 +184,7 @@ __global__ void cheb_coupling_kernel(const ChebPair* d, const double* lo, const 
   }
 }
 
-__global__ void nearfield_kernel(const NearBlock* d, const double* pts, int dim, int kernel) {
+__global__ void nearfield_kernel(const NearBlock* d, const double* pts, const double* nrm, int dim, int kernel) {
   const NearBlock B = d[blockIdx.y];
   const int64_t total = (int64_t)B.size_t_ * B.size_s;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -129,7 +192,14 @@ __global__ void nearfield_kernel(const NearBlock* d, const double* pts, int dim,
     const int i = (int)(e % B.size_t_), j = (int)(e / B.size_t_);
     const double* x = pts + (B.off_t + i) * dim;
     const double* y = pts + (B.off_s + j) * dim;
-    B.out[i + j * B.ld] = (B.diag && i == j) ? kernel_diag(kernel, x, dim) : kernel_g(kernel, x, y, dim);
+    double v;
+    if (B.diag && i == j)
+      v = kernel_diag(kernel, x, dim);
+    else if (kernel == H2_K_DLP)
+      v = kernel_dlp(x, y, nrm + (B.off_t + i) * dim, dim);
+    else
+      v = kernel_g(kernel, x, y, dim);
+    B.out[i + j * B.ld] = v;
   }
 }
 
@@ -137,6 +207,14 @@ void k_cheb_leaf(const ChebLeaf* d, int n, const double* pts, const double* lo, 
                  int dim, int order, void* stream) {
   if (n <= 0) return;
   hipLaunchKernelGGL(cheb_leaf_kernel, dim3(8, n), dim3(256), 0, (hipStream_t)stream, d, pts, lo, hi,
+                     dim, order);
+  HIP_OK(hipGetLastError());
+}
+
+void k_cheb_leaf_dn(const ChebLeaf* d, int n, const double* pts, const double* nrm, const double* lo,
+                    const double* hi, int dim, int order, void* stream) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(cheb_leaf_dn_kernel, dim3(8, n), dim3(256), 0, (hipStream_t)stream, d, pts, nrm, lo, hi,
                      dim, order);
   HIP_OK(hipGetLastError());
 }
@@ -157,9 +235,10 @@ void k_cheb_coupling(const ChebPair* d, int n, const double* lo, const double* h
   HIP_OK(hipGetLastError());
 }
 
-void k_nearfield(const NearBlock* d, int n, const double* pts, int dim, int kernel, void* stream) {
+void k_nearfield(const NearBlock* d, int n, const double* pts, const double* nrm, int dim, int kernel,
+                 void* stream) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(nearfield_kernel, dim3(8, n), dim3(256), 0, (hipStream_t)stream, d, pts, dim,
+  hipLaunchKernelGGL(nearfield_kernel, dim3(8, n), dim3(256), 0, (hipStream_t)stream, d, pts, nrm, dim,
                      kernel);
   HIP_OK(hipGetLastError());
 }
@@ -188,6 +267,29 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const SumsqItem* items, cons
     const double t = red[0] + red[1] + red[2] + red[3];
     out[sg] = mode == 1 ? (t > 0.0 ? 1.0 / sqrt(t) : 0.0) : t;
   }
+}
+
+// one workgroup per group: the group's largest value, then the values at
+// most rtol times it set to 0 (every read precedes every write)
+__global__ __launch_bounds__(256) void drop_small_kernel(double* const* vals, const int32_t* gptr, double rtol) {
+  __shared__ double red[4];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int i0 = gptr[g], i1 = gptr[g + 1];
+  double m = 0.0;
+  for (int i = i0 + tid; i < i1; i += 256) m = fmax(m, *vals[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = m;
+  __syncthreads();
+  const double floor = rtol * fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  for (int i = i0 + tid; i < i1; i += 256)
+    if (*vals[i] <= floor) *vals[i] = 0.0;
+}
+
+void k_drop_small(double* const* vals, const int32_t* gptr, int ngroups, double rtol, void* stream) {
+  if (ngroups <= 0) return;
+  hipLaunchKernelGGL(drop_small_kernel, dim3(ngroups), dim3(256), 0, (hipStream_t)stream, vals, gptr, rtol);
+  HIP_OK(hipGetLastError());
 }
 
 void k_sumsq(const SumsqItem* items, const int32_t* seg_ptr, int nseg, double* out, int mode,

@@ -164,7 +164,9 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
   const BlockTreeH& BY = Y.bt();
   std::vector<double*> M(BY.nblocks(), nullptr);
   NormBatch nb;
+  nb.drop_rtol = kBlockRtol;  // per level of the block tree (blocks are stored level by level)
   std::vector<int> nbi(BY.nblocks(), -1);
+  int cur_lvl = -1, gid = -1;
   for (int b = 0; b < BY.nblocks(); ++b) {
     if (Y.type(b) != BT_ADM) continue;
     int r = Y.vcol(b);
@@ -172,7 +174,12 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
     g.out(M[b], std::max(lY[r], 1), lY[r], k);
     g.term(RY[r], k, false, Y.ptr(b), Y.ld(b), !Y.T, k);  // R_{Y,r} S_{Y,sr}^*
     nbi[b] = (int)nb.items.size();
-    nb.add(M[b], std::max(lY[r], 1), lY[r], k);
+    const int lv = TreeH::level(Y.vrow(b));
+    if (lv != cur_lvl) {
+      cur_lvl = lv;
+      ++gid;
+    }
+    nb.add(M[b], std::max(lY[r], 1), lY[r], k, gid);
   }
   g.run(ctx);
   std::vector<const double*> sig = nb.run(ctx);
@@ -293,14 +300,16 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       }
     }
     g.run(ctx);
-    // (b) block norms (Section 5)
+    // (b) block norms (Section 5); blocks at most kBlockRtol of the level's
+    //     largest are zero up to rounding and are dropped
     NormBatch nrm;
+    nrm.drop_rtol = kBlockRtol;
     std::vector<std::vector<int>> ni(nc);
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i;
       for (size_t j = 0; j < Cb[t].size(); ++j) {
         ni[i].push_back((int)nrm.items.size());
-        nrm.add(Bt[i] + j * k * rows[i], std::max(rows[i], 1), rows[i], k);
+        nrm.add(Bt[i] + j * k * rows[i], std::max(rows[i], 1), rows[i], k, 0);
       }
     }
     std::vector<const double*> ns = nrm.run(ctx);

@@ -956,6 +956,19 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
   }
   ts.run(ctx);
   jb.run(ctx);
+  if (!group.empty() && drop_rtol > 0.0) {
+    H2_REQUIRE(group.size() == n, H2_ERR_ARG, "NormBatch: a group for every item or none");
+    std::vector<int32_t> gptr(1, 0);
+    for (size_t i = 0; i < n; ++i) {
+      H2_REQUIRE(group[i] == (int32_t)gptr.size() - 1 || group[i] == (int32_t)gptr.size(), H2_ERR_ARG,
+                 "NormBatch: groups must be numbered in item order");
+      if (group[i] == (int32_t)gptr.size()) gptr.push_back((int32_t)i);
+    }
+    gptr.push_back((int32_t)n);
+    std::vector<double*> vals(n);
+    for (size_t i = 0; i < n; ++i) vals[i] = const_cast<double*>(out[i]);
+    k_drop_small(upload_launch(ctx, vals), upload_launch(ctx, gptr), (int)gptr.size() - 1, drop_rtol, ctx->stream);
+  }
   return out;
 }
 

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2.so")
 
-KERNELS = {"log": 0, "expneg": 1, "inv4pi": 2, "inv": 3, "poly2": 100}
+KERNELS = {"log": 0, "expneg": 1, "inv4pi": 2, "inv": 3, "dlp": 4, "poly2": 100}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "bf16": 3}
 KERNEL_FAMILIES = ["gemm_sum", "tsqr", "jacobi", "build", "other"]
 STEPS = ["setup", "nearfield", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat"]
@@ -104,6 +104,8 @@ def _declare(lib):
         "h2_tree_sizes": (ctypes.c_int, [_c_p, _c_p]),
         "h2_tree_structure": (ctypes.c_int, [_c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
         "h2_compress_kernel": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_c_p)]),
+        "h2_compress_kernel_normals": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int, _c_p,
+                                                      ctypes.POINTER(_c_p)]),
         "h2_mul_intermediate": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, _c_p, ctypes.c_double, ctypes.c_int,
                                                _c_p]),
         "h2_zero_like": (ctypes.c_int, [_c_p, _c_p, ctypes.c_double, ctypes.POINTER(_c_p)]),
@@ -287,9 +289,18 @@ class Matrix:
         self.ctx, self.lib, self.tree, self.h = ctx, ctx.lib, tree, handle
 
     @classmethod
-    def kernel(cls, ctx: Context, tree: Tree, kernel: str, order: int):
+    def kernel(cls, ctx: Context, tree: Tree, kernel: str, order: int, normals=None):
+        """Chebyshev H^2 approximation of a kernel matrix; normals (n x dim,
+        input point order) for the double-layer kernel "dlp"."""
         h = _c_p()
-        _check(ctx.lib, ctx.lib.h2_compress_kernel(ctx.h, tree.h, KERNELS[kernel], order, ctypes.byref(h)))
+        if normals is None:
+            _check(ctx.lib, ctx.lib.h2_compress_kernel(ctx.h, tree.h, KERNELS[kernel], order, ctypes.byref(h)))
+        else:
+            nrm = np.ascontiguousarray(normals, dtype=np.float64)
+            if nrm.shape != (tree.n, tree.dim):
+                raise ValueError("normals must be n x dim")
+            _check(ctx.lib, ctx.lib.h2_compress_kernel_normals(ctx.h, tree.h, KERNELS[kernel], order,
+                                                               nrm.ctypes.data, ctypes.byref(h)))
         return cls(ctx, tree, h)
 
     @classmethod

@@ -1,9 +1,9 @@
 """Write the oracle's results on a full-size workload to <workload>_oracle.json.
 
 Calls only oracle/ and workloads.py.  Run:
-    python tests/golden/make_golden.py c2      (or c3, or c4)
+    python tests/golden/make_golden.py c2      (or c3, dlp, or c4)
 
-For the single-product workloads (c2, c3) the file holds
+For the single-product workloads (c2, c3, dlp) the file holds
   - the rank profiles of both phases (row and column bases);
   - a two-sided randomized sketch of G, Z and X Y:  Psi^T M Omega with
     Omega = probe_vectors(101, n, 32) and Psi = probe_vectors(103, n, 32)
@@ -36,7 +36,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle as O  # noqa: E402
 import workloads as W  # noqa: E402
 
-NAMES = {"c2": W.C2, "c3": W.C3}
+NAMES = {"c2": W.C2, "c3": W.C3, "dlp": W.C6}
 PROBE_SEED, SKETCH_SEED, INDEX_SEED, POWER_SEED = 101, 103, 102, 104
 NPROBE = 32
 POWER_STEPS = 20
@@ -73,7 +73,8 @@ def main(key: str):
     w = NAMES[key]
     pts = w.points()
     t0 = time.time()
-    tree, bt, X, Y = O.build_problem(pts, w.leaf_size, w.eta, w.order, w.kernel_x, w.kernel_y)
+    tree, bt, X, Y = O.build_problem(pts, w.leaf_size, w.eta, w.order, w.kernel_x, w.kernel_y,
+                                     normals=w.normals())
     t1 = time.time()
     print(f"[{key}] problem built ({t1 - t0:.1f}s)", flush=True)
     with O.counting() as led:

@@ -29,7 +29,13 @@ CASES = {
     "ragged": (1000, 2, 24, 3, "log", "expneg", 1.5, 11, "uniform", 1e-6),
     "c1": (1024, 1, 16, 4, "log", "log", 1.0, 1, "uniform", 1e-8),     # the 1-D workload, full size
     "2d64": (2048, 2, 64, 4, "log", "expneg", 1.0, 2, "uniform", 1e-6),
+    # the double-layer kernel on the surface of [-1, 1]^3 (not symmetric)
+    "dlp": (1536, 3, 32, 3, "dlp", "dlp", 2.0, 6, "cube_surface", 1e-4),
 }
+
+
+def normals_of(pts, dist):
+    return W.cube_surface_normals(pts) if dist == "cube_surface" else None
 
 
 def _say(*a):
@@ -53,7 +59,7 @@ def oracle_case(name, eps=None):
     n, d, leaf, order, kx, ky, eta, seed, dist, e = CASES[name]
     eps = e if eps is None else eps
     pts = W.make_points(seed, n, d, dist)
-    tree, bt, X, Y = O.build_problem(pts, leaf, eta, order, kx, ky)
+    tree, bt, X, Y = O.build_problem(pts, leaf, eta, order, kx, ky, normals=normals_of(pts, dist))
     p1, p2 = O.multiply(X, Y, bt, eps)
     Xd, Yd = X.dense(), Y.dense()
     return pts, tree, X, Y, p1, p2, Xd, Yd
@@ -68,8 +74,8 @@ def gpu_case(name, eps=None):
     pts = W.make_points(seed, n, d, dist)
     c = ctx()
     T = h2.Tree(c, pts, leaf, eta)
-    X = h2.Matrix.kernel(c, T, kx, order)
-    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    X = h2.Matrix.kernel(c, T, kx, order, normals_of(pts, dist))
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order, normals_of(pts, dist))
     _say(f"[gpu] case={name}: phase 1")
     G = h2.h2_mul_intermediate(c, X, Y, eps)
     _say(f"[gpu] case={name}: phase 2")
@@ -166,7 +172,7 @@ def test_phase2_parity(name):
         check_leaf_projectors(Z, tree, which, basis.full())
 
 
-@pytest.mark.parametrize("name", ["2d", "sph", "ragged", "1d"])
+@pytest.mark.parametrize("name", ["2d", "sph", "ragged", "1d", "dlp"])
 def test_exact_without_truncation(name):
     """eps = 0: both phases reproduce X Y to rounding."""
     _, tree, _, _, _, _, Xd, Yd = oracle_case(name, 0.0)
@@ -343,7 +349,7 @@ def test_workload_batched_full_size():
 # Bar: relative Frobenius distance to the FP64 oracle <= 2 eps for G and Z
 # (ranks may differ where FP32 rounding moves a singular value across eps),
 # and Z stays within eps of X Y.
-MIXED = ["2d", "ragged", "2d64", "sph"]
+MIXED = ["2d", "ragged", "2d64", "sph", "dlp"]
 
 
 @functools.lru_cache(maxsize=None)
@@ -354,8 +360,8 @@ def gpu_case_mixed(name):
     pts = W.make_points(seed, n, d, dist)
     c = ctx()
     T = h2.Tree(c, pts, leaf, eta)
-    X = h2.Matrix.kernel(c, T, kx, order)
-    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    X = h2.Matrix.kernel(c, T, kx, order, normals_of(pts, dist))
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order, normals_of(pts, dist))
     G = h2.h2_mul_intermediate(c, X, Y, eps, "fp32")
     Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps, "fp32")
     torch.cuda.synchronize()
@@ -391,7 +397,7 @@ def test_mixed_rejects_small_eps():
 
 # BF16 hi/lo bulk products: the same bar (2 eps) at eps = 1e-4, the sphere
 # workload's tolerance
-MIXED_BF16 = ["sph", "2d64", "ragged"]
+MIXED_BF16 = ["sph", "2d64", "ragged", "dlp"]
 
 
 @pytest.mark.parametrize("name", MIXED_BF16)
@@ -401,9 +407,10 @@ def test_bf16x2_parity(name):
     h2 = _h2()
     n, d, leaf, order, kx, ky, eta, seed, dist, _ = CASES[name]
     c = ctx()
-    T = h2.Tree(c, W.make_points(seed, n, d, dist), leaf, eta)
-    X = h2.Matrix.kernel(c, T, kx, order)
-    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    pts = W.make_points(seed, n, d, dist)
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order, normals_of(pts, dist))
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order, normals_of(pts, dist))
     _say(f"[gpu] case={name} bf16x2 eps={eps}")
     G = h2.h2_mul_intermediate(c, X, Y, eps, "bf16x2")
     Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps, "bf16x2")

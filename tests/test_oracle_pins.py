@@ -5,6 +5,7 @@ oracle itself: definitions evaluated densely, Gram identities of the
 condensation steps, exactness of the method without truncation, scaling
 invariance of the block-relative error control and special cases.
 """
+import functools
 import itertools
 
 import numpy as np
@@ -644,3 +645,127 @@ def test_work_ledger_steps_and_dense_triples():
     nblocks = len(bt.type)
     small = 2.0 * (2 * k) ** 3 * 5 * (nblocks ** 2)   # generous bound on the rest
     assert dense <= led[("p1_mat", "gemm")] <= dense + small
+
+
+# --------------------------------------------------------------------------
+# The double-layer kernel of Section 7 (<n(x), x - y> / (4 pi |x - y|^3) on
+# the surface of [-1, 1]^3): derivative interpolation basis, raw entries,
+# convergence, and the product of a non-symmetric matrix with itself
+# --------------------------------------------------------------------------
+def test_lagrange_derivative_reproduces_polynomial_derivatives():
+    rng = np.random.default_rng(5)
+    for m in (2, 3, 4, 5):
+        a, b = sorted(rng.uniform(-3, 3, 2))
+        nodes = OH.cheb_nodes(a, b, m)
+        x = np.concatenate([rng.uniform(a - 1, b + 1, 40), nodes])   # nodes included
+        coef = rng.standard_normal(m)                                 # degree m - 1
+        p = np.polynomial.polynomial.polyval(nodes, coef)
+        dp = np.polynomial.polynomial.polyval(x, np.polynomial.polynomial.polyder(coef))
+        got = OH.lagrange_derivative(nodes, x) @ p
+        assert np.abs(got - dp).max() <= 1e-11 * max(1.0, np.abs(dp).max())
+
+
+@functools.lru_cache(maxsize=None)
+def _dlp_problem(n=1536, order=3, leaf=32, seed=6):
+    pts = W.make_points(seed, n, 3, "cube_surface")
+    nrm = W.cube_surface_normals(pts)
+    tree, bt, X, _ = O.build_problem(pts, leaf, 2.0, order, "dlp", "dlp", normals=nrm)
+    return pts, nrm, tree, bt, X
+
+
+def test_cube_surface_points_and_normals():
+    pts = W.make_points(6, 3000, 3, "cube_surface")
+    nrm = W.cube_surface_normals(pts)
+    assert np.all(np.abs(pts) <= 1.0) and np.allclose(np.max(np.abs(pts), axis=1), 1.0, rtol=0, atol=0)
+    assert np.allclose(np.linalg.norm(nrm, axis=1), 1.0)
+    # each normal is the outward axis of the face the point lies on
+    assert np.all(np.sum(nrm * pts, axis=1) == 1.0)
+
+
+def test_dlp_entries_from_raw_points():
+    """Nearfield entries equal <n(x_i), x_i - x_j>/(4 pi |x_i - x_j|^3) from the
+    raw points and normals (0 on the diagonal and, exactly, for two points of
+    the same face); the far field converges as the order grows."""
+    pts, nrm, tree, bt, X = _dlp_problem()
+    Xd = X.dense()
+    P, Nr = pts[tree.perm], nrm[tree.perm]
+    raw = np.zeros_like(Xd)
+    for i in range(tree.n):
+        d = P[i] - P
+        r = np.linalg.norm(d, axis=1)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            raw[i] = (d @ Nr[i]) / (4.0 * np.pi * r ** 3)
+        raw[i, i] = 0.0
+    near = np.zeros(Xd.shape, dtype=bool)
+    for (t, s), ty in bt.type.items():
+        if ty == O.INADM:
+            near[tree.rng(t), tree.rng(s)] = True
+    assert np.abs(Xd[near] - raw[near]).max() <= 1e-15 * np.abs(raw[near]).max()
+    same_face = (Nr @ Nr.T) == 1.0
+    assert np.all(Xd[near & same_face] == 0.0)
+    errs = []
+    for order in (2, 3, 4):
+        Xo = _dlp_problem(order=order)[4].dense()
+        errs.append(np.linalg.norm((Xo - raw)[~near]) / np.linalg.norm(raw[~near]))
+    # interpolation error of the far field falls by more than 2 per order
+    assert errs[0] > 2 * errs[1] and errs[1] > 2 * errs[2], errs
+
+
+def test_dlp_row_basis_nested():
+    """The normal-derivative row basis is nested: expanding the transfers
+    gives the derivative basis of the parent evaluated on the child's points."""
+    pts, nrm, tree, bt, X = _dlp_problem(n=600, leaf=16)
+    Vf = X.V.full()
+    Nr = nrm[tree.perm]
+    for c in range(1, tree.nclusters):
+        if tree.is_leaf(c):
+            continue
+        r = tree.rng(c)
+        direct = OH._tensor_normal_derivative(tree, c, 3, tree.points[r], Nr[r], OH._cube_boxes)
+        assert np.abs(Vf[c] - direct).max() <= 1e-11 * np.abs(direct).max()
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-4])
+def test_dlp_product_error_and_adjoint_passes(eps):
+    """X X for the non-symmetric double-layer matrix: exact without
+    truncation, within eps otherwise; the column pass of X Y equals the row
+    pass of Y^* X^* (same ranks), and row and column ranks differ."""
+    pts, nrm, tree, bt, X = _dlp_problem()
+    Xd = X.dense()
+    XY = Xd @ Xd
+    p1, p2 = O.multiply(X, X, bt, eps)
+    Zd = p2.Z.dense()
+    if eps == 0.0:
+        assert relF(p1.G.dense(), XY) <= 1e-12 and relF(Zd, XY) <= 1e-12
+        return
+    assert rel2(Zd, XY) <= eps
+    Xt = X.transposed()
+    q1 = O.Phase1(Xt, Xt, eps)
+    nc = tree.nclusters
+    assert [p1.col.Q.rank[c] for c in range(nc)] == [q1.row.Q.rank[c] for c in range(nc)]
+    assert [p1.row.Q.rank[c] for c in range(nc)] != [p1.col.Q.rank[c] for c in range(nc)]
+
+
+def test_block_scaling_ignores_rounding_level_blocks():
+    """Section 5 scaling with reading R8: blocks of the double-layer product
+    that vanish in exact arithmetic (two clusters on one face) come out of
+    the interpolated couplings at the rounding level; scaled to unit norm
+    they would decide ranks by rounding noise.  Dropping blocks at most
+    BLOCK_RTOL of their level's largest makes the rank profiles invariant
+    under a perturbation of X at 1e-14; without the rule they are not."""
+    pts, nrm, tree, bt, X = _dlp_problem()
+    rng = np.random.default_rng(1)
+    Xp = O.H2Matrix(X.V, X.W, X.bt, {b: m * (1 + 1e-14 * rng.standard_normal(m.shape)) for b, m in X.S.items()},
+                    {b: m * (1 + 1e-14 * rng.standard_normal(m.shape)) for b, m in X.N.items()})
+
+    def moved():
+        a, b = O.Phase1(X, X, 1e-4), O.Phase1(Xp, Xp, 1e-4)
+        return sum(a.row.Q.rank[c] != b.row.Q.rank[c] or a.col.Q.rank[c] != b.col.Q.rank[c]
+                   for c in range(tree.nclusters))
+    assert moved() == 0
+    saved = OH.BLOCK_RTOL
+    try:
+        OH.BLOCK_RTOL = 0.0
+        assert moved() > 0
+    finally:
+        OH.BLOCK_RTOL = saved

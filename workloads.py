@@ -24,6 +24,7 @@ KERNELS = {
     "expneg": 1,    # exp(-|x-y|), diagonal 1
     "inv4pi": 2,    # 1/(4 pi |x-y|), diagonal 0 (single-layer kernel, Section 7)
     "inv": 3,       # 1/|x-y|, diagonal 0
+    "dlp": 4,       # <n(x), x-y> / (4 pi |x-y|^3), diagonal 0 (double-layer kernel, Section 7)
     "poly2": 100,   # (x.y)^2: a polynomial of degree 2, reproduced exactly by order >= 3
 }
 
@@ -50,6 +51,13 @@ class Workload:
     def points(self) -> np.ndarray:
         return make_points(self.seed, self.n, self.dim, self.distribution)
 
+    def normals(self):
+        """Unit normals at the points (input order) where the points lie on a
+        surface with a kernel that uses them; else None."""
+        if self.distribution == "cube_surface":
+            return cube_surface_normals(self.points())
+        return None
+
 
 def make_points(seed: int, n: int, dim: int, distribution: str) -> np.ndarray:
     """n x dim float64 points, row-major, from numpy's default_rng(seed)."""
@@ -59,7 +67,26 @@ def make_points(seed: int, n: int, dim: int, distribution: str) -> np.ndarray:
     if distribution == "sphere":
         g = rng.standard_normal((n, dim))
         return np.ascontiguousarray(g / np.linalg.norm(g, axis=1, keepdims=True))
+    if distribution == "cube_surface":
+        # uniform on the surface of [-1, 1]^3: a face (axis, sign) per point,
+        # uniform coordinates in (-1, 1) on the other two axes
+        if dim != 3:
+            raise ValueError("cube_surface points are 3-D")
+        face = rng.integers(0, 6, n)
+        pts = rng.uniform(-1.0, 1.0, (n, 3))
+        ax, sign = face // 2, np.where(face % 2 == 0, -1.0, 1.0)
+        pts[np.arange(n), ax] = sign
+        return np.ascontiguousarray(pts)
     raise ValueError(f"unknown distribution {distribution!r}")
+
+
+def cube_surface_normals(points: np.ndarray) -> np.ndarray:
+    """Outward unit normals of points on the surface of [-1, 1]^3 (input
+    order): the axis whose coordinate is exactly -1 or 1, with its sign."""
+    ax = np.argmax(np.abs(points), axis=1)
+    nrm = np.zeros_like(points)
+    nrm[np.arange(points.shape[0]), ax] = np.sign(points[np.arange(points.shape[0]), ax])
+    return nrm
 
 
 # The five workloads.  "c1" is the small case the oracle finishes in seconds;
@@ -73,7 +100,13 @@ C3 = Workload("c3_sphere_slp_n131072", 3, 131072, 3, "sphere", 64, 2.0, 3, "inv4
 C5 = Workload("c5_cube_inv_n1048576", 5, 1 << 20, 3, "uniform", 128, 2.0, 4, "inv", "inv", 1e-5,
               "unit cube volume, X = Y")
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C5)}
+# The double-layer workload of the paper's second experiment (Section 7):
+# the surface of [-1, 1]^3 with the double-layer kernel (not symmetric),
+# n = 110592, one of the paper's sizes for it; X = Y.
+C6 = Workload("dlp_cube_n110592", 60, 110592, 3, "cube_surface", 64, 2.0, 3, "dlp", "dlp", 1e-4,
+              "cube surface, double-layer kernel, X = Y (not symmetric)")
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C5, C6)}
 
 
 def batched_instances(count: int = 64):
