@@ -206,10 +206,18 @@ h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix
 
 /* Phase 2 for `count` products (Section 6, Figure "basis"): builds adaptive
  * isometric nested row and column bases for Z's block tree T_IK from G and
- * stores Z <- Z + G in them.  Each Z[i] must be zero (h2_zero_like) and its
- * block tree must be refined by T^XY (H2_ERR_NOT_REFINED otherwise).
- * Block-relative accuracy eps per admissible block of T_IK (truncation rule
- * as set by h2_set_rank_rule). */
+ * stores Z <- Z + G in them.  Z[i]'s block tree must be refined by T^XY
+ * (H2_ERR_NOT_REFINED otherwise).  Block-relative accuracy eps per
+ * admissible block of T_IK, relative to G's block (truncation rule as set by
+ * h2_set_rank_rule).
+ * Z[i] may be zero (h2_zero_like) or hold a matrix on the same cluster tree
+ * (a previous result, a kernel matrix, any basis ranks): Z <- Z + X Y, the
+ * general operation of the paper's Introduction.  The ranges of Z's row and
+ * column bases are then kept exactly (as phase 1 keeps range(V_X), Section 4
+ * leaf case): the new bases start with an orthonormal basis of them
+ * (numerical rank at 1e-12 relative) and add the truncated part of G outside
+ * them, so the old Z is represented exactly and only G is compressed.  Z's
+ * memory is replaced at the end of the call; on an error Z is unchanged. */
 h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix* const* Z,
                         double eps, h2_precision prec);
 

@@ -1035,12 +1035,14 @@ def match_column(rep: dict, target: ColumnTree, W: ClusterBasis) -> dict:
 
 
 class CoarseBasis:
-    def __init__(self, Q, R, A, sigmas, omega, tag, Z, C):
+    def __init__(self, Q, R, A, sigmas, omega, tag, Z, C, RZ=None):
         self.Q, self.R, self.A, self.sigmas, self.omega, self.tag = Q, R, A, sigmas, omega, tag
         self.Z, self.C = Z, C           # product total weights, condensed C_t / Chat_t
+        self.RZ = RZ                    # Z <- Z + X Y: Q_t^* V^Z_t, the old basis in the new one
 
 
-def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -> CoarseBasis:
+def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS,
+                Vold: ClusterBasis = None) -> CoarseBasis:
     """Figure "basis": adaptive isometric nested row basis for the coarse
     block tree T_IK, with the product total weights Z_t of
     eq. (Zt_condensation), leaf matrices C_t (eq. (ct_leaf)) and non-leaf
@@ -1050,6 +1052,15 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
     enter Z_t.  R12: "admissible ancestor in T_IK" includes the block itself.
     R10: every block lying in b of T_IK is scaled by omega_b.  R9: rank
     #{sigma > eps}.  R_t = Q_t^* V_t is the basis change from G's row basis.
+
+    Z <- Z + X Y with Z != 0 (reading R16): Vold is the row basis of the
+    old Z on T_IK.  Its range is kept exactly, as phase 1 keeps range(V_X)
+    (Section 4, leaf case): at every cluster the new basis is an orthonormal
+    basis of that range (numerical rank, VX_RTOL) followed by the truncated
+    SVD of the part of C_t (or Chat_t) outside it; at a non-leaf the old
+    basis enters through Vhat^Z_t = [RZ_{t'} E^Z_{t'}] with RZ_{t'} =
+    Q_{t'}^* V^Z_{t'}.  The old Z is then represented exactly and only G is
+    compressed, with G's block weights.
     """
     rt, ct = G.V.tree, G.W.tree
     tag = tag_blocks(G, TIK)
@@ -1066,7 +1077,29 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
     for v in rowXY.values():
         v.sort()
     Q = ClusterBasis(rt)
-    R, A, sig_out, Z, Cm = {}, {}, {}, {}, {}
+    R, A, sig_out, Z, Cm, RZ = {}, {}, {}, {}, {}, {}
+
+    def truncate(t, C, VZ):
+        """Orthonormal basis of C_t truncated at eps; with VZ the exact range
+        of VZ followed by the truncated part of C_t outside it."""
+        if VZ is None:
+            U, sig = left_svd(C)
+            kz = choose_rank(sig, eps, rule)
+            sig_out[t] = sig
+            return U[:, :kz]
+        rows = VZ.shape[0]
+        pv = min(VZ.shape)
+        _count("qr", _qr_flops(*VZ.shape) + 4.0 * (rows * rows * pv - rows * pv * pv + pv ** 3 / 3.0))
+        _count("svd", 12.0 * pv ** 3)
+        if VZ.shape[1] == 0:
+            Ux, sx = np.eye(rows), np.zeros(0)
+        else:
+            Ux, sx, _ = np.linalg.svd(VZ, full_matrices=True)
+        k1 = int(np.count_nonzero(sx > VX_RTOL * sx[0])) if sx.size and sx[0] > 0 else 0
+        U, sig = left_svd(mul(Ux[:, k1:].T, C))
+        k2 = choose_rank(sig, eps, rule)
+        sig_out[t] = sig
+        return np.hstack([Ux[:, :k1], mul(Ux[:, k1:], U[:, :k2])])
 
     def rep_of_child(tc, rc):
         ty = G.bt.type[(tc, rc)]
@@ -1090,13 +1123,13 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
             for r in inad:
                 cols.append(omega[tag[(t, r)]] * G.N[(t, r)])
             Cm[t] = np.hstack(cols)
-            U, sig = left_svd(Cm[t])
-            kz = choose_rank(sig, eps, rule)
-            sig_out[t] = sig
-            Qt = U[:, :kz]
+            Qt = truncate(t, Cm[t], Vold.leaf[t] if Vold is not None else None)
+            kz = Qt.shape[1]
             Q.leaf[t] = Qt
             Q.rank[t] = kz
             R[t] = mul(Qt.T, G.V.leaf[t])
+            if Vold is not None:
+                RZ[t] = mul(Qt.T, Vold.leaf[t])
             for r in inad:
                 A[(t, r)] = {r: (False, mul(Qt.T, G.N[(t, r)]))}
             return
@@ -1128,11 +1161,16 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
             Ahat[r] = [(lf, T.adm[lf], np.vstack(pieces[lf])) for lf in leaves]
             cols.append(omega[tag[(t, r)]] * np.hstack([M for _, _, M in Ahat[r]]))
         Cm[t] = np.hstack(cols)
-        U, sig = left_svd(Cm[t])
-        kz = choose_rank(sig, eps, rule)
-        sig_out[t] = sig
-        Qhat = U[:, :kz]
+        VZhat = None
+        if Vold is not None:
+            VZhat = np.zeros((rows, Vold.rank[t]))
+            for ch in kids:
+                VZhat[offs[ch]:offs[ch] + Q.rank[ch]] = mul(RZ[ch], Vold.transfer[ch])
+        Qhat = truncate(t, Cm[t], VZhat)
+        kz = Qhat.shape[1]
         Q.rank[t] = kz
+        if Vold is not None:
+            RZ[t] = mul(Qhat.T, VZhat)
         for ch in kids:
             Q.transfer[ch] = Qhat[offs[ch]:offs[ch] + Q.rank[ch], :]
         R[t] = mul(Qhat.T, Vhat)
@@ -1140,11 +1178,14 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS) -
             A[(t, r)] = {lf: (adm, mul(Qhat.T, M)) for lf, adm, M in Ahat[r]}
 
     rec(0, None)
-    return CoarseBasis(Q, R, A, sig_out, omega, tag, Z, Cm)
+    return CoarseBasis(Q, R, A, sig_out, omega, tag, Z, Cm, RZ if Vold is not None else None)
 
 
-def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasis) -> H2Matrix:
-    """R15: Z = sum_{b in L+_IK} Q^Z Q^Z* G|_b Q^ZW Q^ZW* + sum_{b in L-_IK} G|_b.
+def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasis, Zold: H2Matrix = None) -> H2Matrix:
+    """R15: Z = sum_{b in L+_IK} Q^Z Q^Z* G|_b Q^ZW Q^ZW* + sum_{b in L-_IK} G|_b,
+    plus the old Z when it is not zero (R16: its couplings written in the new
+    bases, RZ S^Z_b RZW^*, exact because its ranges are kept; its nearfield
+    added).
 
     Couplings Q^Z_t^* G|_b Q^ZW_r are accumulated bottom-up over the blocks of
     T^XY inside b: R_t S_tr R^W_r^* on admissible leaves, Q^Z_t^* N_tr Q^ZW_r
@@ -1167,10 +1208,11 @@ def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasi
             L[b] = sum(mul(QZ.transfer[tc].T, L[(tc, rc)], QZW.transfer[rc])
                        for (tc, rc) in G.bt.children[b])
     S, N = {}, {}
-    Gf = None
     for b, ty in TIK.type.items():
         if ty == ADM:
             S[b] = L[b] if b in L else np.zeros((QZ.rank[b[0]], QZW.rank[b[1]]))
+            if Zold is not None:
+                S[b] = S[b] + mul(rowc.RZ[b[0]], Zold.S[b], colc.RZ[b[1]].T)
         elif ty == INADM:
             gt = G.bt.type.get(b)
             if gt == INADM:
@@ -1179,25 +1221,32 @@ def form_coarse(G: H2Matrix, TIK: BlockTree, rowc: CoarseBasis, colc: CoarseBasi
                 N[b] = mul(G.V.leaf[b[0]], G.S[b], G.W.leaf[b[1]].T)
             else:
                 raise ValueError("inadmissible leaf of T_IK not a leaf of T^XY")
+            if Zold is not None:
+                N[b] = N[b] + Zold.N[b]
     return H2Matrix(QZ, QZW, TIK, S, N)
 
 
 class Phase2:
-    def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS):
+    """Z <- Z + G in T_IK; Zold (on T_IK) is the Z before the update, None
+    for Z = 0."""
+
+    def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS, Zold: H2Matrix = None):
         with _stage("p2_row"):
-            self.row = build_basis(G, TIK, eps, rule)
+            self.row = build_basis(G, TIK, eps, rule, Zold.V if Zold is not None else None)
         with _stage("p2_col"):
-            self.col = build_basis(G.transposed(), TIK.transposed(), eps, rule)
+            self.col = build_basis(G.transposed(), TIK.transposed(), eps, rule,
+                                   Zold.W if Zold is not None else None)
         with _stage("p2_mat"):
-            self.Z = form_coarse(G, TIK, self.row, self.col)
+            self.Z = form_coarse(G, TIK, self.row, self.col, Zold)
 
 
-def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float = None, rule: str = RANK_ABS):
-    """Both phases: returns (Phase1, Phase2); Z = phase2.Z approximates X Y.
-    rule: the truncation rule of both phases (R9 "abs", or the variant R21
-    "relF")."""
+def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float = None, rule: str = RANK_ABS,
+             Zold: H2Matrix = None):
+    """Both phases: returns (Phase1, Phase2); Z = phase2.Z approximates
+    Zold + X Y (Zold on TIK, None for zero).  rule: the truncation rule of
+    both phases (R9 "abs", or the variant R21 "relF")."""
     p1 = Phase1(X, Y, eps1, rule)
-    p2 = Phase2(p1.G, TIK, eps1 if eps2 is None else eps2, rule)
+    p2 = Phase2(p1.G, TIK, eps1 if eps2 is None else eps2, rule, Zold)
     return p1, p2
 
 

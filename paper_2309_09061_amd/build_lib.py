@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libh2.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "runtime.cpp", "tree.cpp", "h2mat.cpp", "phase1.cpp", "phase2.cpp", "export.cpp",
+SOURCES = ["api.cpp", "runtime.cpp", "tree.cpp", "h2mat.cpp", "phase1.cpp", "phase2.cpp", "export.cpp", "kept.cpp",
            "dev_hip.hip", "kernels_la.hip", "kernels_cheb.hip", "kernels_rank.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -259,7 +259,6 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     for (int i = 0; i < count; ++i) H2_REQUIRE(G[i] && Z[i], H2_ERR_ARG, "NULL operand");
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
     check_precision((int)prec, eps);
-    for (int i = 0; i < count; ++i) H2_REQUIRE(Z[i]->zero, H2_ERR_UNSUPPORTED, "Z must be zero");
     need_device(ctx);
     begin_call(ctx);
     for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);

@@ -369,6 +369,17 @@ struct Arena {
   // (h2_ctx_destroy is deferred) until the arena is gone
   void bind(h2_ctx* c);
   void release();  // chunks go back to the context (its returned list)
+  void swap(Arena& o) {
+    std::swap(ctx, o.ctx);
+    std::swap(owner, o.owner);
+    chunks.swap(o.chunks);
+    std::swap(cur, o.cur);
+    std::swap(used, o.used);
+    std::swap(total, o.total);
+    std::swap(fixed, o.fixed);
+    std::swap(fixed_cap, o.fixed_cap);
+    std::swap(fixed_used, o.fixed_used);
+  }
   ~Arena();
 };
 
@@ -714,6 +725,25 @@ constexpr size_t kNoAllocTableReserve = (size_t)8 << 20;
 char* noalloc_scratch_resolve(int device);
 void matvec_noalloc(h2_ctx* ctx, const H2Core& A, bool trans, double alpha, const double* x, double beta,
                     double* y, int nvec);
+
+// Bases keeping range(K) exactly plus the truncated SVD of the rest of C
+// (Section 4, leaf case): K (m x kc, ldk), C (m x nc, ldc; overwritten).
+struct KeptItem {
+  int m;
+  const double* K;
+  int64_t ldk;
+  int kc;
+  double* C;
+  int64_t ldc;
+  int nc;
+};
+struct KeptOut {
+  std::vector<int32_t> k1, k2;  // numerical rank of K; kept singular values of the rest
+  std::vector<double*> Q;       // m x (k1 + k2), ld m (from `keep`)
+  std::vector<double*> RKP;     // Q^* K = [R_K; 0]: (k1 + k2) x kc, ld max(k1 + k2, 1) (workspace)
+};
+// one launch per step over all items; reads the ranks back (one stream sync)
+void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, Arena& keep, KeptOut& out);
 
 // h2_stats / h2_export
 void handle_stats(const void* handle, int kind, h2_stats_t* out);

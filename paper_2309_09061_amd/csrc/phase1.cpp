@@ -84,9 +84,6 @@ struct LevelSignal {
   }
 };
 
-// relative tolerance of the numerical rank of V_X (the kept range)
-static constexpr double kVxRtol = 1e-12;
-
 static int uniform_rank(const Basis& B) {
   int k = B.rank.empty() ? 0 : B.rank[0];
   for (int r : B.rank) H2_REQUIRE(r == k, H2_ERR_UNSUPPORTED, "input bases must have one rank");
@@ -252,7 +249,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
     const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
     const bool leaf = l == D;
     std::vector<int> rows(nc), ncols(nc), kk1(nc);
-    std::vector<double*> Bt(nc), Vr(nc), VXw(nc), Rt(nc), U(nc), sg(nc);
+    std::vector<double*> Bt(nc), Vr(nc), VXw(nc);
     std::vector<std::vector<int>> offs(nc);
     // (a) the blocks X|_{t x s} V_{Y,s} (leaf) or Ahat_{t,s} (non-leaf), the V_X part
     for (int i = 0; i < nc; ++i) {
@@ -313,16 +310,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       }
     }
     std::vector<const double*> ns = nrm.run(ctx);
-    // (c) scaled remainder blocks X V_Y Z_s^* / ||.||, and the numerical range
-    //     of V_X: SVD V_X = U S V'^* from the k x k R factor of V_X, then the
-    //     Householder QR of Y = V_X V' (columns by descending sigma), whose
-    //     orthogonal factor Q_X has the dominant k1 directions (k1 =
-    //     #{sigma > 1e-12 sigma_max}) in its first k1 columns
-    TsqrBatch ts;
-    JacobiBatch jb;
-    int32_t* rk = ws.get<int32_t>(2 * nc);  // [k1 | k2] per cluster
-    dev_zero(rk, sizeof(int32_t) * 2 * nc, ctx->stream);
-    std::vector<double*> Rv(nc), Vp(nc), Yq(nc), tau(nc), RYq(nc);
+    // (c) scaled remainder blocks X V_Y Z_s^* / ||.||
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, m = rows[i];
       int nco = 0;
@@ -337,74 +325,25 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
         g.term(Bt[i] + j * k * m, m, false, Z[s], k, true, k, 1.0, ns[ni[i][j]], 2);
         col += zr[s];
       }
-      int p1 = std::min(k, m);
-      Rv[i] = ws.get<double>((size_t)k * k);
-      Vp[i] = ws.get<double>((size_t)k * k);
-      sg[i] = ws.get<double>(k);
-      ts.add(VXw[i], m, m, k, false, Rv[i], k);
-      jb.add(Rv[i], k, p1, k, Vp[i], k, sg[i], rk + i, 0.0, kVxRtol, nullptr, 1);
     }
     g.run(ctx);
-    ts.run(ctx);
-    jb.run(ctx);
-    QrBatch qr;
-    for (int i = 0; i < nc; ++i) {
-      int m = rows[i];
-      Yq[i] = ws.get<double>((size_t)m * k);
-      tau[i] = ws.get<double>(k);
-      RYq[i] = ws.get<double>((size_t)k * k);
-      g.out(Yq[i], m, m, k);
-      g.term(VXw[i], m, false, Vp[i], k, false, k);
-      qr.add(Yq[i], m, m, k, tau[i], RYq[i], k, std::min(m, k));
-    }
-    g.run(ctx);
-    qr.run(ctx);
-    // (d) remainder: Q_X^* [blocks] with the first k1 rows masked, its SVD
-    ApplyBatch ap;
-    for (int i = 0; i < nc; ++i)
-      ap.add(Yq[i], rows[i], tau[i], rows[i], std::min(rows[i], k), Vr[i], rows[i], ncols[i], true);
-    ap.run(ctx);
-    for (int i = 0; i < nc; ++i) {
-      int m = rows[i];
-      int p = std::min(ncols[i], m);
-      Rt[i] = ws.get<double>((size_t)m * m);
-      U[i] = ws.get<double>((size_t)m * m);
-      double* sg2 = ws.get<double>(m);
-      ts.add(Vr[i], m, ncols[i], m, true, Rt[i], m, 0, rk + i);
-      jb.add(Rt[i], m, p, m, U[i], m, sg2, rk + nc + i, eps, 0.0, rk + i, 1, ctx->rank_rule);
-    }
-    ts.run(ctx);
-    jb.run(ctx);
-    const int32_t* kkh = read_back(ctx, rk, 2 * nc);
-    ctx_sync(ctx);
-    const std::vector<int32_t> kk(kkh, kkh + 2 * nc);
-    // (e) Q_t = Q_X [I 0; 0 U2(:, 1:k2)], transfers, A_{t,s} = Q_t^* (...),
-    //     [R_X; 0] with R_X = (R_Y V'^*)(1:k1, :)
+    // (d) the range of V_X kept, the remainder truncated at eps (SVD of V_X
+    //     from its R factor, Householder QR of V_X V', SVD of the rest)
+    std::vector<KeptItem> kit(nc);
+    for (int i = 0; i < nc; ++i) kit[i] = {rows[i], VXw[i], rows[i], k, Vr[i], rows[i], ncols[i]};
+    KeptOut ko;
+    kept_compress(ctx, kit, eps, keep, ko);
+    // (e) Q_t, transfers, A_{t,s} = Q_t^* (...), [R_X; 0]
     std::vector<double*> Qn(nc);
-    FillBatch fb;
     for (int i = 0; i < nc; ++i) {
-      int t = c0 + i, m = rows[i];
-      kk1[i] = kk[i];
-      int k2 = kk[nc + i];
-      int kt = kk1[i] + k2;
+      int t = c0 + i;
+      kk1[i] = ko.k1[i];
+      int kt = ko.k1[i] + ko.k2[i];
       H2_REQUIRE(kt >= 1, H2_ERR_NUMERIC, "phase 1: empty cluster basis");
       out.Q.rank[t] = kt;
       out.k1[t] = kk1[i];
-      Qn[i] = keep.get<double>((size_t)m * kt);
-      fb.add(Qn[i], m, m, kt, 1.0);
+      Qn[i] = ko.Q[i];
     }
-    fb.run(ctx);
-    for (int i = 0; i < nc; ++i) {
-      int m = rows[i], k2 = out.Q.rank[c0 + i] - kk1[i];
-      if (k2 > 0) {
-        g.out(Qn[i] + (size_t)kk1[i] * m, m, m, k2);
-        g.copy(U[i], m, false, k2);
-      }
-    }
-    g.run(ctx);
-    for (int i = 0; i < nc; ++i)
-      ap.add(Yq[i], rows[i], tau[i], rows[i], std::min(rows[i], k), Qn[i], rows[i], out.Q.rank[c0 + i], false);
-    ap.run(ctx);
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, m = rows[i], kt = out.Q.rank[t];
       if (leaf) {
@@ -422,10 +361,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
         g.out(out.A[t], kt, kt, k * nC);
         g.term(Qn[i], m, true, Bt[i], m, false, m);
       }
-      out.RXP[t] = ws.get<double>((size_t)kt * k);
-      g.out(out.RXP[t], kt, kk1[i], k);
-      g.term(RYq[i], k, false, Vp[i], k, true, k);
-      g.out(out.RXP[t] + kk1[i], kt, kt - kk1[i], k);  // zero rows below R_X
+      out.RXP[t] = ko.RKP[i];
     }
     g.run(ctx);
     if (lsig) lsig->done(side, l, ctx->stream);

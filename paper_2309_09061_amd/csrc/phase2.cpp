@@ -36,6 +36,7 @@ struct P2Side {
   std::vector<double*> R;    // R_t = Q_t^* V_t: kz_t x k_t, ld max(kz_t, 1)
   std::vector<double*> A;    // per stored G block: A_{t,r} (kz_t x width), ld max(kz_t, 1)
   std::vector<double*> RS;   // per stored admissible G leaf: R_t S_{t,r}, kz_t x kW_r
+  std::vector<double*> RZ;   // Z != 0: Q_t^* V^Z_t (the old Z's basis in the new one), kz_t x kold_t
 };
 
 // Column trees of all blocks in one array (per pass): the leaves of block b
@@ -71,9 +72,12 @@ static void leaf_union_into(const TreeH& T, ColTrees& C, int c1, int c2) {
   H2_REQUIRE(i == na && j == nb, H2_ERR_SHAPE, "column trees do not cover one range");
 }
 
+// Kb: for Z <- Z + G with Z != 0, the old Z's basis on this side (row
+// basis for the row pass, column basis for the column pass), whose range is
+// kept exactly (as phase 1 keeps range(V_X)); null for Z = 0.
 static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
                         const BlockTreeH& TIK, const double* omega, double eps, Arena& keep,
-                        P2Side& out, int step) {
+                        P2Side& out, int step, const Basis* Kb) {
   const TreeH& T = *G.m->ct;
   const BlockTreeH& B = G.bt();
   const int ncl = T.ncl, D = T.depth, nb = B.nblocks();
@@ -267,6 +271,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   out.R.assign(ncl, nullptr);
   out.A.assign(nb, nullptr);
   out.RS.assign(nb, nullptr);
+  out.RZ.assign(ncl, nullptr);
   for (int l = D; l >= 0; --l) {
     const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
     const bool leaf = l == D;
@@ -365,34 +370,82 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       }
     }
     g.run(ctx);
-    // SVD of C_t: R factor of C_t^*, one-sided Jacobi
-    TsqrBatch ts;
-    JacobiBatch jb;
-    int32_t* rk = ws.get<int32_t>(nc);
-    dev_zero(rk, sizeof(int32_t) * nc, ctx->stream);
-    for (int i = 0; i < nc; ++i) {
-      if (m[i] == 0) continue;
-      int p = std::min(ncols[i], m[i]);
-      Rt[i] = ws.get<double>((size_t)m[i] * m[i]);  // rows < p are written
-      U[i] = ws.get<double>((size_t)m[i] * m[i]);
-      sg[i] = ws.get<double>(m[i]);
-      ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
-      jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, eps, 0.0, nullptr, 1, ctx->rank_rule);
+    std::vector<int32_t> kz(nc, 0);
+    std::vector<double*> Qk(nc, nullptr);
+    if (Kb) {
+      // Z != 0: keep range(V^Z_t) (leaf) or range(Vhat^Z_t = [RZ_{t'} E^Z_{t'}]),
+      // truncate the rest of C_t (a copy: the inner levels read C_t below)
+      std::vector<KeptItem> kit(nc);
+      for (int i = 0; i < nc; ++i) {
+        int t = c0 + i, kold = Kb->rank[t];
+        const double* K = nullptr;
+        int64_t ldk = std::max(m[i], 1);
+        if (leaf) {
+          K = Kb->leaf[t];
+          ldk = Kb->leaf_ld[t];
+        } else if (m[i] > 0 && kold > 0) {
+          double* Kh = ws.get<double>((size_t)m[i] * kold);
+          int o = 0;
+          for (int q = 1; q <= 2; ++q) {
+            int ch = 2 * t + q, kc = out.Q.rank[ch];
+            if (kc > 0) {
+              g.out(Kh + o, m[i], kc, kold);
+              if (Kb->rank[ch] > 0)
+                g.term(out.RZ[ch], kc, false, Kb->tr[ch], Kb->tr_ld[ch], false, Kb->rank[ch]);
+            }
+            o += kc;
+          }
+          K = Kh;
+        }
+        double* Cw = ws.get<double>((size_t)std::max(m[i], 1) * std::max(ncols[i], 1));
+        if (m[i] > 0 && ncols[i] > 0) {
+          g.out(Cw, m[i], m[i], ncols[i]);
+          g.copy(C[i], m[i], false, ncols[i]);
+        }
+        kit[i] = {m[i], K, ldk, K ? kold : 0, Cw, std::max(m[i], 1), ncols[i]};
+      }
+      g.run(ctx);
+      KeptOut ko;
+      if (leaf) build_columns();  // host work while the device factorizes
+      kept_compress(ctx, kit, eps, keep, ko);
+      for (int i = 0; i < nc; ++i) {
+        kz[i] = ko.k1[i] + ko.k2[i];
+        Qk[i] = ko.Q[i];
+        out.RZ[c0 + i] = ko.RKP[i];
+      }
+    } else {
+      // SVD of C_t: R factor of C_t^*, one-sided Jacobi
+      TsqrBatch ts;
+      JacobiBatch jb;
+      int32_t* rk = ws.get<int32_t>(nc);
+      dev_zero(rk, sizeof(int32_t) * nc, ctx->stream);
+      for (int i = 0; i < nc; ++i) {
+        if (m[i] == 0) continue;
+        int p = std::min(ncols[i], m[i]);
+        Rt[i] = ws.get<double>((size_t)m[i] * m[i]);  // rows < p are written
+        U[i] = ws.get<double>((size_t)m[i] * m[i]);
+        sg[i] = ws.get<double>(m[i]);
+        ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
+        jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, eps, 0.0, nullptr, 1, ctx->rank_rule);
+      }
+      ts.run(ctx);
+      jb.run(ctx);
+      const int32_t* kzh = read_back(ctx, rk, nc);
+      if (leaf) build_columns();
+      ctx_sync(ctx);
+      for (int i = 0; i < nc; ++i) kz[i] = kzh[i];
     }
-    ts.run(ctx);
-    jb.run(ctx);
-    const int32_t* kzh = read_back(ctx, rk, nc);
-    if (leaf) build_columns();
-    ctx_sync(ctx);
-    const std::vector<int32_t> kz(kzh, kzh + nc);
     // new basis, R_t, A_{t,r}
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, kt = Vb.rank[t], k = kz[i];
       out.Q.rank[t] = k;
-      double* Qn = keep.get<double>((size_t)std::max(m[i], 1) * std::max(k, 1));
-      if (k > 0) {
-        g.out(Qn, m[i], m[i], k);
-        g.copy(U[i], m[i], false, k);
+      double* Qn = Qk[i];
+      if (!Qn) {
+        Qn = keep.get<double>((size_t)std::max(m[i], 1) * std::max(k, 1));
+        if (k > 0) {
+          g.out(Qn, m[i], m[i], k);
+          g.copy(U[i], m[i], false, k);
+        }
       }
       if (leaf) {
         out.Q.leaf[t] = Qn;
@@ -457,7 +510,6 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
 }
 
 void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
-  H2_REQUIRE(Z->zero, H2_ERR_UNSUPPORTED, "Z must be zero (Z <- Z + XY with Z != 0 is not supported)");
   const TreeH& T = *Gp->c.ct;
   H2_REQUIRE(T.same_as(*Z->c.ct), H2_ERR_SHAPE, "Z must be built on the cluster tree of X and Y");
   ctx->prec = prec;
@@ -514,13 +566,24 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
   k_sumsq(upload(ctx, items), upload(ctx, sp), TIK.nblocks(), omega, 1, ctx->stream);
 
   View Gr{&Gp->c, false}, Gc{&Gp->c, true};
+  // Z <- Z + G: a non-zero Z keeps the ranges of its bases (the passes keep
+  // them exactly), its couplings are written in the new bases and its
+  // nearfield is added; the new Z is built in fresh arenas and replaces the
+  // old one at the end
+  const bool add_old = !Z->zero;
+  H2Core old;
+  if (add_old) old = Z->c;
+  Arena nmem, naux;
+  nmem.bind(ctx);
+  naux.bind(aux_ctx(ctx));
   // row pass on G here, column pass on G^* concurrently on the auxiliary
-  // context; both read G, tag and omega only
+  // context; both read G, tag, omega and the old Z only
   P2Side row, col;
-  Z->mem_aux.bind(aux_ctx(ctx));
   {
-    AuxRun colrun(ctx, [&](h2_ctx* a) { coarse_pass(a, Gc, tag, TIK, omega, eps, Z->mem_aux, col, 6); });
-    coarse_pass(ctx, Gr, tag, TIK, omega, eps, Z->mem, row, 5);
+    AuxRun colrun(ctx, [&](h2_ctx* a) {
+      coarse_pass(a, Gc, tag, TIK, omega, eps, naux, col, 6, add_old ? &old.W : nullptr);
+    });
+    coarse_pass(ctx, Gr, tag, TIK, omega, eps, nmem, row, 5, add_old ? &old.V : nullptr);
     colrun.join();
   }
 
@@ -529,7 +592,7 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
   Arena& ws = ctx->ws;
   GemmBatch g;
   g.prec = prec;
-  H2Core& Zc = Z->c;
+  H2Core Zc = Z->c;  // assigned to Z at the end (Z is untouched on an error)
   Zc.V = row.Q;
   Zc.W = col.Q;
   Zc.blk.assign(TIK.nblocks(), nullptr);
@@ -541,7 +604,7 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
       if (tag[b] < 0 || TIK.type[tag[b]] != BT_ADM) continue;
       int t = B.t[b], r = B.s[b], kz = QZ.rank[t], kw = QZW.rank[r];
       bool top = same[b] >= 0 && same[b] == tag[b];  // b is the T_IK leaf itself
-      L[b] = top ? Z->mem.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1))
+      L[b] = top ? nmem.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1))
                  : ws.get<double>((size_t)std::max(kz, 1) * std::max(kw, 1));
       if (B.type[b] == BT_SPLIT)
         for (int q = 0; q < 4; ++q) {
@@ -576,6 +639,29 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
   std::vector<int> of_tik(TIK.nblocks(), -1);  // the block of T^XY equal to a T_IK block
   for (int b = 0; b < nb; ++b)
     if (same[b] >= 0) of_tik[same[b]] = b;
+  if (add_old) {
+    // the old couplings in the new bases: L_b += RZ_t S^old_b RZW_r^*
+    std::vector<double*> T1(TIK.nblocks(), nullptr);
+    for (int zb = 0; zb < TIK.nblocks(); ++zb) {
+      if (TIK.type[zb] != BT_ADM || !old.blk[zb]) continue;
+      int t = TIK.t[zb], r = TIK.s[zb], kz = QZ.rank[t], ko = old.V.rank[t], kor = old.W.rank[r];
+      if (kz == 0 || ko == 0 || kor == 0) continue;
+      T1[zb] = ws.get<double>((size_t)kz * kor);
+      g.out(T1[zb], kz, kz, kor);
+      g.term(row.RZ[t], kz, false, old.blk[zb], old.ld_of(zb), false, ko);
+    }
+    g.run(ctx);
+    for (int zb = 0; zb < TIK.nblocks(); ++zb) {
+      if (!T1[zb]) continue;
+      int t = TIK.t[zb], r = TIK.s[zb], kz = QZ.rank[t], kw = QZW.rank[r], kor = old.W.rank[r];
+      const int b = of_tik[zb];
+      H2_REQUIRE(b >= 0 && L[b], H2_ERR_NOT_REFINED, "admissible leaf of T_IK missing from T^XY");
+      if (kw == 0) continue;
+      g.out(L[b], kz, kz, kw, true);
+      g.term(T1[zb], kz, false, col.RZ[r], std::max(kw, 1), true, kor);
+    }
+    g.run(ctx);
+  }
   for (int zb = 0; zb < TIK.nblocks(); ++zb) {
     if (TIK.type[zb] == BT_SPLIT) continue;
     int t = TIK.t[zb], r = TIK.s[zb];
@@ -584,7 +670,7 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
     if (TIK.type[zb] == BT_ADM) {
       Zc.blk[zb] = L[b];
     } else {
-      double* Nz = Z->mem.get<double>((size_t)T.size[t] * T.size[r]);
+      double* Nz = nmem.get<double>((size_t)T.size[t] * T.size[r]);
       Zc.blk[zb] = Nz;
       g.out(Nz, T.size[t], (int)T.size[t], (int)T.size[r]);
       if (B.type[b] == BT_INADM) {
@@ -600,9 +686,15 @@ void phase2(h2_ctx* ctx, h2_product* Gp, h2_matrix* Z, double eps, int prec) {
         g0.run(ctx);
         g.term(QS, T.size[t], false, Gp->c.W.leaf[r], Gp->c.W.leaf_ld[r], true, kr);
       }
+      if (add_old && old.blk[zb]) g.copy(old.blk[zb], old.ld_of(zb), false, (int)T.size[r]);  // old nearfield
     }
   }
   g.run(ctx);
+  // the new Z replaces the old one; the old arrays return to the contexts'
+  // caches, where later work on these streams is ordered after their last use
+  Z->mem.swap(nmem);
+  Z->mem_aux.swap(naux);
+  Z->c = std::move(Zc);
   Z->zero = false;
   step_end(ctx, 7);
 }

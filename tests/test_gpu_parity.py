@@ -517,23 +517,40 @@ def test_single_leaf_tree():
     assert relF(dense_of(Z, n), XY) < 1e-13
 
 
-def test_recompress_rejects_nonzero_target():
-    """R16: Z <- Z + G is supported for Z = 0 only; a Z that already holds a
-    result is refused with H2_ERR_UNSUPPORTED, and the refused call leaves
-    the context usable."""
+@pytest.mark.parametrize("name", ["2d", "sph", "dlp", "1d"])
+def test_update_of_nonzero_target(name):
+    """Z <- Z + X Y with Z != 0: Z1 = X Y, then Z2 = Z1 + X Y and Z3 = Y + X Y
+    (a kernel matrix, non-isometric bases, as the old Z), each against the
+    oracle's update of the same old Z: identical ranks, relative Frobenius
+    <= 1e-10, and the exact sum within eps."""
     h2 = _h2()
+    n, d, leaf, order, kx, ky, eta, seed, dist, eps = CASES[name]
+    pts, tree, Xo, Yo, p1, p2, Xd, Yd = oracle_case(name)
+    bt = O.BlockTree(tree, tree, eta)
     c = ctx()
-    pts = W.make_points(12, 300, 2, "uniform")
-    T = h2.Tree(c, pts, 32, 1.0)
-    X = h2.Matrix.kernel(c, T, "log", 3)
-    G = h2.h2_mul_intermediate(c, X, X, 1e-6)
-    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
-    with pytest.raises(h2.H2Error) as e:
-        h2.h2_recompress(c, G, Z, 1e-6)
-    assert e.value.code == 6
-    Z2 = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), 1e-6)
-    torch.cuda.synchronize()
-    assert relF(dense_of(Z2, 300), dense_of(Z, 300)) < 1e-14
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order, normals_of(pts, dist))
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order, normals_of(pts, dist))
+    _say(f"[gpu] update of a non-zero Z: case={name}")
+    G = h2.h2_mul_intermediate(c, X, Y, eps)
+    Z1 = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    Z1_dense = dense_of(Z1, n)
+    XY = Xd @ Yd
+    nc = tree.nclusters
+    for label, Zg, old_o, old_dense in (("Z1 + XY", Z1, p2.Z, Z1_dense), ("Y + XY", Y if ky != kx else None, Yo, Yd)):
+        if Zg is None:  # X = Y: use a separate copy of the kernel matrix as the old Z
+            Zg = h2.Matrix.kernel(c, T, ky, order, normals_of(pts, dist))
+        G2 = h2.h2_mul_intermediate(c, X, Y, eps)
+        h2.h2_recompress(c, G2, Zg, eps)
+        torch.cuda.synchronize()
+        _, q2 = O.multiply(Xo, Yo, bt, eps, Zold=old_o)
+        assert list(Zg.ranks(0)) == [q2.row.Q.rank[t] for t in range(nc)], label
+        assert list(Zg.ranks(1)) == [q2.col.Q.rank[t] for t in range(nc)], label
+        Zd = dense_of(Zg, n)
+        e_or = relF(Zd, q2.Z.dense())
+        e_xy = np.linalg.norm(Zd - old_dense - XY, 2) / np.linalg.norm(XY, 2)
+        _say(f"[gpu] {name} {label}: relF vs oracle {e_or:.2e}, error vs exact sum {e_xy:.2e}")
+        assert e_or < 1e-10 and e_xy <= eps, label
 
 
 @pytest.mark.parametrize("phase,launches", [(1, 3), (1, 40), (2, 5), (2, 15)])

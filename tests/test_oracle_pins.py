@@ -769,3 +769,41 @@ def test_block_scaling_ignores_rounding_level_blocks():
         assert moved() > 0
     finally:
         OH.BLOCK_RTOL = saved
+
+
+# --------------------------------------------------------------------------
+# Z <- Z + X Y with Z != 0 (the operation of the Introduction; reading R16:
+# the old Z's bases are kept exactly, as phase 1 keeps range(V_X))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("name,eps", [("2d", 0.0), ("2d", 1e-6), ("sph", 1e-4), ("1d", 1e-8)])
+def test_update_of_nonzero_target(name, eps):
+    """Z1 = X Y, then Z2 = Z1 + X Y and Z3 = Y + X Y (a kernel matrix with
+    non-isometric bases as the old Z): exact at eps = 0, else within eps of
+    the exact sums; the old Z's row and column bases stay inside the new
+    ones at every cluster."""
+    _, tree, bt, X, Y = problem(name)
+    Xd, Yd, XY = dense(name)
+    _, p2a = O.multiply(X, Y, bt, eps)
+    for old, old_dense in ((p2a.Z, p2a.Z.dense()), (Y, Yd)):
+        _, p2 = O.multiply(X, Y, bt, eps, Zold=old)
+        err = rel2(p2.Z.dense() - old_dense, XY)
+        assert err <= (1e-12 if eps == 0 else eps), err
+        for new, kept in ((p2.row.Q, old.V), (p2.col.Q, old.W)):
+            Qf, Kf = new.full(), kept.full()
+            for c in range(tree.nclusters):
+                K = Kf[c]
+                if K.size == 0:
+                    continue
+                res = np.linalg.norm(K - Qf[c] @ (Qf[c].T @ K)) / np.linalg.norm(K)
+                assert res <= 1e-12, (c, res)
+
+
+def test_update_by_zero_product_keeps_target():
+    """X = 0: Z + 0 X Y equals Z (to rounding) with the old ranks."""
+    _, tree, bt, X, Y = problem("2d")
+    _, p2a = O.multiply(X, Y, bt, 1e-6)
+    _, p2 = O.multiply(O.scaled(X, 0.0), Y, bt, 1e-6, Zold=p2a.Z)
+    assert relF(p2.Z.dense(), p2a.Z.dense()) <= 1e-13
+    nc = tree.nclusters
+    assert [p2.row.Q.rank[c] for c in range(nc)] == [p2a.row.Q.rank[c] for c in range(nc)]
+    assert [p2.col.Q.rank[c] for c in range(nc)] == [p2a.col.Q.rank[c] for c in range(nc)]
