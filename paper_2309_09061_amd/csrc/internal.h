@@ -198,6 +198,39 @@ void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriF
 // one workgroup per output of at most 64 x 64 (untransposed operands)
 void k_gemm_tri_block(const TriOut* outs, int nouts, const TriFamily& fam, int prec, void* stream);
 void k_chain3(const Chain3* items, int n, void* stream);
+// The coefficients S_b of the admissible part of G on one level of T^XY,
+// one workgroup per block b = b0 + i (Section 6 opening with reading R14):
+//   TAA = sum over the block's AA triples of S_X P S_Y          (k x k)
+//   TNA = sum over NA triples of A_{t,s} S_Y                     (kt x k)
+//   MAN = sum over AN triples of S_X A^c_{r,s}^*                 (k x kr)
+//   S_b = TNA R^c_r^* + R_t (TAA R^c_r^* + MAN)                  (kt x kr)
+// with R_t = [R_{X,t}; 0] (row pass) and R^c_r (column pass).  Every
+// dimension at most 64.
+struct GformArgs {
+  // whole T^XY and the blocks of X and Y
+  const int32_t* bt;        // row cluster of block b at bt[2b], column cluster at bt[2b + 1]
+  const int32_t* tri_ptr;   // triples of block b: [tri_ptr[b], tri_ptr[b + 1])
+  const int32_t* tri;       // 4 ints per triple: s, bx, by, kind
+  const double* const* SX;  // per block of X (couplings where admissible)
+  const int64_t* ldSX;
+  const double* const* SY;  // per block of Y
+  const int64_t* ldSY;
+  const double* const* PS;  // per block of Y: P_{XY,s} S_{Y,sr} (k x k, ld k), admissible blocks
+  // the level's own (every factor of a triple of a block on level l lies on level l)
+  const double* const* Ar;  // per block bx0 + i of X: A_{t,s} (kt x k), non-admissible blocks
+  const int64_t* ldAr;
+  const double* const* Ac;  // per block by0 + i of Y: A^c (kr x k), non-admissible blocks
+  const int64_t* ldAc;
+  const int32_t* krow;      // per cluster c0 + i: rank of the row basis
+  const int32_t* kcol;      // per cluster c0 + i: rank of the column basis
+  const double* const* Rr;  // per cluster: [R_{X,t}; 0] (krow x k, ld max(krow, 1))
+  const double* const* Rc;  // per cluster: [R^c_{Y,r}; 0] (kcol x k, ld max(kcol, 1))
+  double* const* S;         // per block b0 + i of T^XY: S_b (kt x kr, ld max(kt, 1))
+  int32_t b0, c0, bx0, by0, k, ktmax, krmax;
+};
+// dynamic LDS in doubles of a launch (k, the level's largest kt and kr)
+size_t gform_lds_doubles(int k, int ktmax, int krmax);
+void k_gform(const GformArgs& a, int nblocks, int prec, void* stream);
 // Factorization launches: lds_doubles is the dynamic LDS of the launch (a
 // problem whose working set fits it runs in LDS), slot the doubles of global
 // scratch per workgroup for the others (0: none); scratch then holds

@@ -480,6 +480,172 @@ void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriF
 }
 
 // ---------------------------------------------------------------------------
+// Fused formation of G's coefficients on one level of T^XY (see GformArgs):
+// one workgroup per block, four wavefronts.  Each output of at most 64 x 64
+// is cut into 16 x 16 tiles; wavefront w owns tiles w, w + 4, ... and keeps
+// them in MFMA accumulators across all of the block's triples, reading the
+// operand fragments from device memory (they are shared by many blocks and
+// stay in L2).  TAA, TNA and the final Mm pass through LDS as operands of
+// the closing products.
+// ---------------------------------------------------------------------------
+constexpr int kGformMaxTiles = 4;  // 16 tiles of a 64 x 64 output over 4 wavefronts
+
+template <int P, class FA, class FB>
+__device__ __forceinline__ void gform_tile(typename Mfma16<P>::acc_t& acc, int i0, int j0, int m, int n, int K,
+                                           int r, int q, FA a_at, FB b_at) {
+  using M = Mfma16<P>;
+  const int i = i0 + r, j = j0 + r;
+  for (int l0 = 0; l0 < K; l0 += M::KG) {
+    double a[M::EPL], b[M::EPL];
+#pragma unroll
+    for (int u = 0; u < M::EPL; ++u) {
+      const int l = l0 + M::kof(u, q);
+      a[u] = (i < m && l < K) ? a_at(i, l) : 0.0;
+      b[u] = (j < n && l < K) ? b_at(l, j) : 0.0;
+    }
+    acc = M::step(a, b, acc);
+  }
+}
+
+template <int P, class FS>
+__device__ __forceinline__ void gform_store(const typename Mfma16<P>::acc_t& acc, int i0, int j0, int m, int n, int r,
+                                            int q, FS put) {
+  using M = Mfma16<P>;
+  const int j = j0 + r;
+  if (j >= n) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + M::row(v, q);
+    if (i < m) put(i, j, (double)acc[v]);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void gform_kernel(const GformArgs A) {
+  using M = Mfma16<P>;
+  using acc_t = typename M::acc_t;
+  const int b = A.b0 + blockIdx.x;
+  const int t = A.bt[2 * b] - A.c0, rr = A.bt[2 * b + 1] - A.c0;
+  const int k = A.k, kt = A.krow[t], kr = A.kcol[rr];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  // LDS: TAA (k x k, ld k), TNA (ktmax x k, ld ktmax), Mm (k x krmax, ld k)
+  double* Taa = lds_dyn;
+  double* Tna = Taa + (size_t)k * k;
+  double* Mm = Tna + (size_t)A.ktmax * k;
+  const int tk = (k + 15) / 16, tkt = (kt + 15) / 16, tkr = (kr + 15) / 16;
+  acc_t aa[kGformMaxTiles], na[kGformMaxTiles], an[kGformMaxTiles];
+#pragma unroll
+  for (int x = 0; x < kGformMaxTiles; ++x) aa[x] = na[x] = an[x] = M::zero();
+  bool any_aa = false, any_na = false, any_an = false;
+  const int4* tri = reinterpret_cast<const int4*>(A.tri);
+  for (int p = A.tri_ptr[b]; p < A.tri_ptr[b + 1]; ++p) {
+    const int4 T = tri[p];
+    if (T.w == TK_AA) {  // S_X (P S_Y)
+      any_aa = true;
+      const double* X = A.SX[T.y];
+      const int64_t lx = A.ldSX[T.y];
+      const double* Y = A.PS[T.z];
+#pragma unroll
+      for (int x = 0; x < kGformMaxTiles; ++x) {
+        const int tile = wave + 4 * x;
+        if (tile >= tk * tk) break;
+        gform_tile<P>(aa[x], (tile % tk) * 16, (tile / tk) * 16, k, k, k, r, q,
+                      [&](int i, int l) { return X[i + (int64_t)l * lx]; },
+                      [&](int l, int j) { return Y[l + (int64_t)j * k]; });
+      }
+    } else if (T.w == TK_NA && kt > 0) {  // A_{t,s} S_Y
+      any_na = true;
+      const double* X = A.Ar[T.y - A.bx0];
+      const int64_t lx = A.ldAr[T.y - A.bx0];
+      const double* Y = A.SY[T.z];
+      const int64_t ly = A.ldSY[T.z];
+#pragma unroll
+      for (int x = 0; x < kGformMaxTiles; ++x) {
+        const int tile = wave + 4 * x;
+        if (tile >= tkt * tk) break;
+        gform_tile<P>(na[x], (tile % tkt) * 16, (tile / tkt) * 16, kt, k, k, r, q,
+                      [&](int i, int l) { return X[i + (int64_t)l * lx]; },
+                      [&](int l, int j) { return Y[l + (int64_t)j * ly]; });
+      }
+    } else if (T.w == TK_AN && kr > 0) {  // S_X A^c^*
+      any_an = true;
+      const double* X = A.SX[T.y];
+      const int64_t lx = A.ldSX[T.y];
+      const double* Y = A.Ac[T.z - A.by0];
+      const int64_t ly = A.ldAc[T.z - A.by0];
+#pragma unroll
+      for (int x = 0; x < kGformMaxTiles; ++x) {
+        const int tile = wave + 4 * x;
+        if (tile >= tk * tkr) break;
+        gform_tile<P>(an[x], (tile % tk) * 16, (tile / tk) * 16, k, kr, k, r, q,
+                      [&](int i, int l) { return X[i + (int64_t)l * lx]; },
+                      [&](int l, int j) { return Y[j + (int64_t)l * ly]; });
+      }
+    }
+  }
+  // TAA and TNA to LDS (zero where the block has no such triple)
+#pragma unroll
+  for (int x = 0; x < kGformMaxTiles; ++x) {
+    const int tile = wave + 4 * x;
+    if (tile < tk * tk)
+      gform_store<P>(aa[x], (tile % tk) * 16, (tile / tk) * 16, k, k, r, q,
+                     [&](int i, int j, double v) { Taa[i + j * k] = any_aa ? v : 0.0; });
+    if (tile < tkt * tk)
+      gform_store<P>(na[x], (tile % tkt) * 16, (tile / tkt) * 16, kt, k, r, q,
+                     [&](int i, int j, double v) { Tna[i + j * A.ktmax] = any_na ? v : 0.0; });
+  }
+  __syncthreads();
+  const double* Rc = A.Rc[rr];
+  const int64_t lrc = kr > 1 ? kr : 1;
+  // Mm = TAA R^c^* + MAN (k x kr), to LDS
+#pragma unroll
+  for (int x = 0; x < kGformMaxTiles; ++x) {
+    const int tile = wave + 4 * x;
+    if (tile >= tk * tkr) break;
+    acc_t m = any_an ? an[x] : M::zero();
+    if (any_aa)
+      gform_tile<P>(m, (tile % tk) * 16, (tile / tk) * 16, k, kr, k, r, q,
+                    [&](int i, int l) { return Taa[i + l * k]; },
+                    [&](int l, int j) { return Rc[j + (int64_t)l * lrc]; });
+    gform_store<P>(m, (tile % tk) * 16, (tile / tk) * 16, k, kr, r, q,
+                   [&](int i, int j, double v) { Mm[i + j * k] = v; });
+  }
+  __syncthreads();
+  // S = TNA R^c^* + R_t Mm (kt x kr), to device memory
+  if (kt == 0 || kr == 0) return;
+  const double* Rt = A.Rr[t];
+  const int64_t lrt = kt > 1 ? kt : 1;
+  double* S = A.S[blockIdx.x];
+  const int ntile = tkt * tkr;
+  for (int tile = wave; tile < ntile; tile += 4) {
+    acc_t s = M::zero();
+    const int i0 = (tile % tkt) * 16, j0 = (tile / tkt) * 16;
+    if (any_na)
+      gform_tile<P>(s, i0, j0, kt, kr, k, r, q, [&](int i, int l) { return Tna[i + l * A.ktmax]; },
+                    [&](int l, int j) { return Rc[j + (int64_t)l * lrc]; });
+    if (any_aa || any_an)
+      gform_tile<P>(s, i0, j0, kt, kr, k, r, q, [&](int i, int l) { return Rt[i + (int64_t)l * lrt]; },
+                    [&](int l, int j) { return Mm[l + j * k]; });
+    gform_store<P>(s, i0, j0, kt, kr, r, q, [&](int i, int j, double v) { S[i + (int64_t)j * lrt] = v; });
+  }
+}
+
+size_t gform_lds_doubles(int k, int ktmax, int krmax) {
+  return (size_t)k * k + (size_t)ktmax * k + (size_t)k * krmax;
+}
+
+void k_gform(const GformArgs& a, int nblocks, int prec, void* stream) {
+  if (nblocks <= 0) return;
+  H2_REQUIRE(a.k <= 64 && a.ktmax <= 64 && a.krmax <= 64, H2_ERR_ARG, "gform: dimensions above 64");
+  const size_t lds = gform_lds_doubles(a.k, std::max(a.ktmax, 1), std::max(a.krmax, 1)) * sizeof(double);
+  H2_REQUIRE(lds <= (size_t)lds_limit_doubles() * sizeof(double), H2_ERR_ARG, "gform: LDS above the device's limit");
+  auto kern = prec == 1 ? gform_kernel<1> : prec == 2 ? gform_kernel<2> : prec == 3 ? gform_kernel<3> : gform_kernel<0>;
+  hipLaunchKernelGGL(kern, dim3(nblocks), dim3(256), lds, (hipStream_t)stream, a);
+  HIP_OK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // Householder QR of one m x n matrix W (ld) by a 256-thread workgroup
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void householder_qr(double* W, int64_t ld, int m, int n, double* tau, double* red) {
@@ -574,7 +740,8 @@ int lds_limit_doubles() {
                         (const void*)jacobi_kernel<256>, (const void*)jacobi_kernel<1024>,
                         (const void*)jacobi_small_kernel, (const void*)norm2_kernel,
                         (const void*)tsqr_rb_kernel<16, 1, 8>, (const void*)tsqr_rb_kernel<8, 1, 16>,
-                        (const void*)tsqr_rb_kernel<8, 2, 8>};
+                        (const void*)tsqr_rb_kernel<8, 2, 8>, (const void*)gform_kernel<0>,
+                        (const void*)gform_kernel<1>, (const void*)gform_kernel<2>, (const void*)gform_kernel<3>};
     for (const void* k : ks)
       if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) {
         (void)hipGetLastError();

@@ -520,6 +520,8 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     std::vector<const double*> tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
     std::vector<int64_t> lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
     TriFamily fAA{};
+    const int32_t* d_bt = nullptr;    // (t, r) per block of T^XY, for the fused launches
+    const int32_t* d_tptr = nullptr;  // triple ranges per block of T^XY
     for (int l = T.depth; l >= 0; --l) {
       H2_REQUIRE(sig.wait(l), H2_ERR_DEVICE, "phase 1: a basis pass stopped early");
       dev_stream_wait(a->stream, sig.ev[0][l]);
@@ -549,6 +551,94 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
           lAc[b] = std::max(kr, 1);
         }
       const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
+      if (b1 == b0) continue;
+      int ktmax = 0, krmax = 0;
+      for (int c = T.first(l); c < T.first(l + 1); ++c) {
+        ktmax = std::max(ktmax, row.Q.rank[c]);
+        krmax = std::max(krmax, col.Q.rank[c]);
+      }
+      if (k <= 64 && ktmax <= 64 && krmax <= 64) {
+        // one fused launch: the three triple sums and both closing products
+        if (!d_bt) {
+          std::vector<int32_t> bt(2 * (size_t)B.nblocks());
+          for (int b = 0; b < B.nblocks(); ++b) {
+            bt[2 * (size_t)b] = B.t[b];
+            bt[2 * (size_t)b + 1] = B.s[b];
+          }
+          d_bt = upload(a, bt);
+          d_tptr = upload(a, PT.tri_ptr);
+        }
+        const int c0 = T.first(l), nc = T.first(l + 1) - c0;
+        const int bx0 = BX.lvl[l], nbxl = BX.lvl[l + 1] - bx0, by0 = BY.lvl[l], nbyl = BY.lvl[l + 1] - by0;
+        const int nb = b1 - b0;
+        size_t total = 0;
+        double flops = 0, bytes = 0;
+        for (int b = b0; b < b1; ++b) {
+          const int kt = row.Q.rank[B.t[b]], kr = col.Q.rank[B.s[b]];
+          total += (size_t)std::max(kt, 1) * std::max(kr, 1);
+          const double naa = cnt(b, TK_AA), nna = kt ? cnt(b, TK_NA) : 0, nan = kr ? cnt(b, TK_AN) : 0;
+          flops += 2.0 * k * k * (k * naa + kt * nna + kr * nan) + 2.0 * kt * k * kr * ((nna > 0) + (naa + nan > 0)) +
+                   (naa > 0 ? 2.0 * k * k * kr : 0.0);
+          bytes += 8.0 * kt * kr;
+        }
+        double* Sl = G->mem_nf.get<double>(total);
+        // the level's tables, packed into one upload
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        const size_t o_kc = al(4 * (size_t)nc), o_rr = o_kc + al(4 * (size_t)nc), o_rc = o_rr + al(8 * (size_t)nc),
+                     o_s = o_rc + al(8 * (size_t)nc), o_ar = o_s + al(8 * (size_t)nb),
+                     o_lar = o_ar + al(8 * (size_t)nbxl), o_ac = o_lar + al(8 * (size_t)nbxl),
+                     o_lac = o_ac + al(8 * (size_t)nbyl), o_end = o_lac + al(8 * (size_t)nbyl);
+        char* h = stage_alloc(a, o_end);
+        int32_t* hkr = (int32_t*)h;
+        int32_t* hkc = (int32_t*)(h + o_kc);
+        const double** hrr = (const double**)(h + o_rr);
+        const double** hrc = (const double**)(h + o_rc);
+        double** hs = (double**)(h + o_s);
+        for (int i = 0; i < nc; ++i) {
+          hkr[i] = row.Q.rank[c0 + i];
+          hkc[i] = col.Q.rank[c0 + i];
+          hrr[i] = row.RXP[c0 + i];
+          hrc[i] = col.RXP[c0 + i];
+        }
+        for (int b = b0, off = 0; b < b1; ++b) {
+          const int kt = row.Q.rank[B.t[b]], kr = col.Q.rank[B.s[b]];
+          S[b] = hs[b - b0] = Sl + off;
+          off += std::max(kt, 1) * std::max(kr, 1);
+        }
+        std::memcpy(h + o_ar, tAr.data() + bx0, 8 * (size_t)nbxl);
+        std::memcpy(h + o_lar, lAr.data() + bx0, 8 * (size_t)nbxl);
+        std::memcpy(h + o_ac, tAc.data() + by0, 8 * (size_t)nbyl);
+        std::memcpy(h + o_lac, lAc.data() + by0, 8 * (size_t)nbyl);
+        char* d = (char*)stage_launch(a, h, o_end);
+        GformArgs ga{};
+        ga.bt = d_bt;
+        ga.tri_ptr = d_tptr;
+        ga.tri = d_tri;
+        ga.SX = d_tX;
+        ga.ldSX = d_lX;
+        ga.SY = d_tY;
+        ga.ldSY = d_lY;
+        ga.PS = fAA.B;
+        ga.Ar = (const double* const*)(d + o_ar);
+        ga.ldAr = (const int64_t*)(d + o_lar);
+        ga.Ac = (const double* const*)(d + o_ac);
+        ga.ldAc = (const int64_t*)(d + o_lac);
+        ga.krow = (const int32_t*)d;
+        ga.kcol = (const int32_t*)(d + o_kc);
+        ga.Rr = (const double* const*)(d + o_rr);
+        ga.Rc = (const double* const*)(d + o_rc);
+        ga.S = (double* const*)(d + o_s);
+        ga.b0 = b0;
+        ga.c0 = c0;
+        ga.bx0 = bx0;
+        ga.by0 = by0;
+        ga.k = k;
+        ga.ktmax = ktmax;
+        ga.krmax = krmax;
+        LaunchTimer lt(a, KK_GEMM, flops, bytes);
+        k_gform(ga, nb, prec, a->stream);
+        continue;
+      }
       TriBatch taa, tna, tan_;
       taa.fam = fAA;
       tna.fam = family(d_tri, upload(a, tAr), upload(a, lAr), d_tY, d_lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
