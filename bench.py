@@ -302,7 +302,7 @@ def main():
                     help="only copy 256 MiB on the GPU (the reference for the HBM traffic counters) and exit")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many steps of the headline workload (for profilers) and exit")
-    ap.add_argument("--profile-precision", default="fp64", choices=["fp64", "fp32"],
+    ap.add_argument("--profile-precision", default="fp64", choices=["fp64", "fp32", "bf16x2", "bf16"],
                     help="form of the --profile-steps run")
     args = ap.parse_args()
     if args.copy_calibration:

@@ -135,76 +135,98 @@ struct Mfma16 {
   static __device__ __forceinline__ int row(int v, int q) { return P ? 4 * q + v : 4 * v + q; }
 };
 
-template <int P>
-__global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict__ outs,
-                                                       const GemmTerm* __restrict__ terms,
-                                                       const int32_t* __restrict__ tiles, int ntiles) {
+// One 16 x 16 output tile accumulated over an inner dimension K: the
+// operand fragments of U consecutive MFMA steps are loaded before those
+// steps issue, so a wavefront keeps U loads of each operand in flight
+// instead of one.  a_at(l) is op(A)(i, l) of this lane's row i, b_at(l) is
+// op(B)(l, j) of its column j; lanes outside the tile (ia, jb false) and
+// l >= K contribute zeros.
+template <int P, class FA, class FB>
+__device__ __forceinline__ void mfma_span(typename Mfma16<P>::acc_t& acc, int K, int q, bool ia, bool jb, FA a_at,
+                                          FB b_at) {
   using M = Mfma16<P>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tix = blockIdx.x * 4 + wave;
-  if (tix >= ntiles) return;
-  const int oi = tiles[3 * tix], i0 = tiles[3 * tix + 1], j0 = tiles[3 * tix + 2];
-  const GemmOut o = outs[oi];
-  const int r = lane & 15, q = lane >> 4;
-  typename M::acc_t acc = M::zero();
-  const int i = i0 + r, j = j0 + r;
-  const bool ia = i < o.m, jb = j < o.n;
-  for (int ti = o.t0; ti < o.t1; ++ti) {
-    const GemmTerm T = terms[ti];
-    double alpha = T.alpha;
-    if (T.flags & GT_SCALE_MUL) {
-      alpha *= *T.scale;
-    } else if (T.flags & GT_SCALE_INV) {
-      const double s = *T.scale;
-      alpha = s > 0.0 ? alpha / s : 0.0;
-    }
-    const double* A = (const double*)T.A;
-    const double* B = (const double*)T.B;
-    const bool tA = T.flags & GT_TA, tB = T.flags & GT_TB;
-    const int64_t sa_i = tA ? T.lda : 1, sa_l = tA ? 1 : T.lda;
-    if (T.flags & GT_BEYE) {
-      // op(A) times the identity: the tile's own entries of op(A), added in
-      // the accumulator layout (no products, no re-reads across the tile)
+  constexpr int U = P >= 2 ? 2 : 4;
+  for (int l0 = 0; l0 < K; l0 += U * M::KG) {
+    double a[U][M::EPL], b[U][M::EPL];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ia_ = i0 + M::row(v, q), jc = j0 + r;
-        if (ia_ < o.m && jc < o.n && jc < T.k) acc[v] += alpha * A[(int64_t)ia_ * sa_i + (int64_t)jc * sa_l];
-      }
-      continue;
-    }
-    const int64_t sb_l = tB ? T.ldb : 1, sb_j = tB ? 1 : T.ldb;
-    for (int l0 = 0; l0 < T.k; l0 += M::KG) {
-      double a[M::EPL], b[M::EPL];
+    for (int s = 0; s < U; ++s)
 #pragma unroll
       for (int u = 0; u < M::EPL; ++u) {
-        const int l = l0 + M::kof(u, q);
-        a[u] = (ia && l < T.k) ? A[(int64_t)i * sa_i + (int64_t)l * sa_l] * alpha : 0.0;
-        b[u] = (jb && l < T.k) ? B[(int64_t)l * sb_l + (int64_t)j * sb_j] : 0.0;
+        const int l = l0 + s * M::KG + M::kof(u, q);
+        a[s][u] = (ia && l < K) ? a_at(l) : 0.0;
+        b[s][u] = (jb && l < K) ? b_at(l) : 0.0;
       }
-      acc = M::step(a, b, acc);
-    }
-  }
-  double* C = (double*)o.C;
-  const int jc = j0 + r;
-  if (jc < o.n) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int ic = i0 + M::row(v, q);
-      if (ic < o.m) {
-        double* p = C + ic + (int64_t)jc * o.ldc;
-        *p = o.beta ? *p + (double)acc[v] : (double)acc[v];
+    for (int s = 0; s < U; ++s)
+      if (l0 + s * M::KG < K) acc = M::step(a[s], b[s], acc);
+  }
+}
+
+// One workgroup per output; its 16 x 16 tiles are dealt to the four
+// wavefronts (tile w, w + 4, ...), i fastest, and each tile sums all terms.
+template <int P>
+__global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict__ outs,
+                                                       const GemmTerm* __restrict__ terms) {
+  using M = Mfma16<P>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const GemmOut o = outs[blockIdx.x];
+  if (o.m <= 0 || o.n <= 0 || (o.t0 == o.t1 && o.beta)) return;
+  const int mt = (o.m + 15) / 16, ntile = mt * ((o.n + 15) / 16);
+  const int r = lane & 15, q = lane >> 4;
+  for (int tile = wave; tile < ntile; tile += 4) {
+    const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
+    typename M::acc_t acc = M::zero();
+    const int i = i0 + r, j = j0 + r;
+    const bool ia = i < o.m, jb = j < o.n;
+    for (int ti = o.t0; ti < o.t1; ++ti) {
+      const GemmTerm T = terms[ti];
+      double alpha = T.alpha;
+      if (T.flags & GT_SCALE_MUL) {
+        alpha *= *T.scale;
+      } else if (T.flags & GT_SCALE_INV) {
+        const double s = *T.scale;
+        alpha = s > 0.0 ? alpha / s : 0.0;
+      }
+      const double* A = (const double*)T.A;
+      const double* B = (const double*)T.B;
+      const bool tA = T.flags & GT_TA, tB = T.flags & GT_TB;
+      const int64_t sa_i = tA ? T.lda : 1, sa_l = tA ? 1 : T.lda;
+      if (T.flags & GT_BEYE) {
+        // op(A) times the identity: the tile's own entries of op(A), added in
+        // the accumulator layout (no products, no re-reads across the tile)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ia_ = i0 + M::row(v, q), jc = j0 + r;
+          if (ia_ < o.m && jc < o.n && jc < T.k) acc[v] += alpha * A[(int64_t)ia_ * sa_i + (int64_t)jc * sa_l];
+        }
+        continue;
+      }
+      const int64_t sb_l = tB ? T.ldb : 1, sb_j = tB ? 1 : T.ldb;
+      const double* Ai = A + (int64_t)i * sa_i;
+      const double* Bj = B + (int64_t)j * sb_j;
+      mfma_span<P>(acc, T.k, q, ia, jb, [&](int l) { return Ai[(int64_t)l * sa_l] * alpha; },
+                   [&](int l) { return Bj[(int64_t)l * sb_l]; });
+    }
+    double* C = (double*)o.C;
+    const int jc = j0 + r;
+    if (jc < o.n) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ic = i0 + M::row(v, q);
+        if (ic < o.m) {
+          double* p = C + ic + (int64_t)jc * o.ldc;
+          *p = o.beta ? *p + (double)acc[v] : (double)acc[v];
+        }
       }
     }
   }
 }
 
-void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* tiles, int ntiles,
-                int prec, void* stream) {
-  if (ntiles <= 0) return;
-  dim3 grid((ntiles + 3) / 4);
+void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, int nouts, int prec, void* stream) {
+  if (nouts <= 0) return;
   auto k = prec == 1 ? gemm_sum_kernel<1> : prec == 2 ? gemm_sum_kernel<2> : prec == 3 ? gemm_sum_kernel<3>
                                                                                       : gemm_sum_kernel<0>;
-  hipLaunchKernelGGL(k, grid, dim3(256), 0, (hipStream_t)stream, outs, terms, tiles, ntiles);
+  hipLaunchKernelGGL(k, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, terms);
   HIP_OK(hipGetLastError());
 }
 
@@ -317,16 +339,10 @@ __global__ __launch_bounds__(256) void gemm_tri_kernel(const TriOut* __restrict_
     const int k = F.ks ? F.ks[tr.x] : F.k;
     const int64_t sa_i = F.tA ? lda : 1, sa_l = F.tA ? 1 : lda;
     const int64_t sb_l = F.tB ? ldb : 1, sb_j = F.tB ? 1 : ldb;
-    for (int l0 = 0; l0 < k; l0 += M::KG) {
-      double a[M::EPL], b[M::EPL];
-#pragma unroll
-      for (int u = 0; u < M::EPL; ++u) {
-        const int l = l0 + M::kof(u, q);
-        a[u] = (ia && l < k) ? A[(int64_t)i * sa_i + (int64_t)l * sa_l] : 0.0;
-        b[u] = (jb && l < k) ? B[(int64_t)l * sb_l + (int64_t)j * sb_j] : 0.0;
-      }
-      acc = M::step(a, b, acc);
-    }
+    const double* Ai = A + (int64_t)i * sa_i;
+    const double* Bj = B + (int64_t)j * sb_j;
+    mfma_span<P>(acc, k, q, ia, jb, [&](int l) { return Ai[(int64_t)l * sa_l]; },
+                 [&](int l) { return Bj[(int64_t)l * sb_l]; });
   }
   double* C = o.C;
   const int jc = j0 + r;
@@ -493,18 +509,8 @@ constexpr int kGformMaxTiles = 4;  // 16 tiles of a 64 x 64 output over 4 wavefr
 template <int P, class FA, class FB>
 __device__ __forceinline__ void gform_tile(typename Mfma16<P>::acc_t& acc, int i0, int j0, int m, int n, int K,
                                            int r, int q, FA a_at, FB b_at) {
-  using M = Mfma16<P>;
   const int i = i0 + r, j = j0 + r;
-  for (int l0 = 0; l0 < K; l0 += M::KG) {
-    double a[M::EPL], b[M::EPL];
-#pragma unroll
-    for (int u = 0; u < M::EPL; ++u) {
-      const int l = l0 + M::kof(u, q);
-      a[u] = (i < m && l < K) ? a_at(i, l) : 0.0;
-      b[u] = (j < n && l < K) ? b_at(l, j) : 0.0;
-    }
-    acc = M::step(a, b, acc);
-  }
+  mfma_span<P>(acc, K, q, i < m, j < n, [&](int l) { return a_at(i, l); }, [&](int l) { return b_at(l, j); });
 }
 
 template <int P, class FS>

@@ -443,40 +443,25 @@ void GemmBatch::copy(const double* A, int64_t lda, bool tA, int k, double alpha,
 }
 
 void GemmBatch::run(h2_ctx* ctx) {
-  size_t ntiles = 0;
-  for (const GemmOut& o : outs) {
-    if (o.m <= 0 || o.n <= 0) continue;
-    if (o.t0 == o.t1 && o.beta) continue;  // nothing to add
-    ntiles += (size_t)((o.m + 15) / 16) * ((o.n + 15) / 16);
-  }
-  if (ntiles == 0) {
+  bool any = false;
+  for (const GemmOut& o : outs)
+    if (o.m > 0 && o.n > 0 && !(o.t0 == o.t1 && o.beta)) {
+      any = true;
+      break;
+    }
+  if (!any) {
     outs.clear();
     terms.clear();
     return;
   }
-  // outputs, terms and tiles written straight into pinned staging, one copy
+  // outputs and terms written straight into pinned staging, one copy; the
+  // kernel deals each output's tiles to its own workgroup
   const size_t so = outs.size() * sizeof(GemmOut), st = std::max<size_t>(terms.size(), 1) * sizeof(GemmTerm);
-  const size_t sti = ntiles * 3 * sizeof(int32_t);
-  const size_t o_t = (so + 255) & ~(size_t)255, o_ti = o_t + ((st + 255) & ~(size_t)255);
-  char* h = stage_alloc(ctx, o_ti + sti);
+  const size_t o_t = (so + 255) & ~(size_t)255;
+  char* h = stage_alloc(ctx, o_t + st);
   std::memcpy(h, outs.data(), so);
   if (!terms.empty()) std::memcpy(h + o_t, terms.data(), terms.size() * sizeof(GemmTerm));
-  int32_t* tl = (int32_t*)(h + o_ti);
-  for (size_t i = 0; i < outs.size(); ++i) {
-    const GemmOut& o = outs[i];
-    if (o.m <= 0 || o.n <= 0) continue;
-    if (o.t0 == o.t1 && o.beta) continue;
-    for (int j0 = 0; j0 < o.n; j0 += 16)
-      for (int i0 = 0; i0 < o.m; i0 += 16) {
-        *tl++ = (int32_t)i;
-        *tl++ = i0;
-        *tl++ = j0;
-      }
-  }
-  char* dev = (char*)stage_launch(ctx, h, o_ti + sti);
-  GemmOut* d_o = (GemmOut*)dev;
-  GemmTerm* d_t = (GemmTerm*)(dev + o_t);
-  int32_t* d_tiles = (int32_t*)(dev + o_ti);
+  char* dev = (char*)stage_launch(ctx, h, o_t + st);
   // algorithmic work: 2 m n k per term; bytes: operands read once, C written
   double flops = 0, bytes = 0;
   const double es = prec ? 4.0 : 8.0;
@@ -490,7 +475,7 @@ void GemmBatch::run(h2_ctx* ctx) {
     }
   }
   LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
-  k_gemm_sum(d_o, d_t, d_tiles, (int)ntiles, prec, ctx->stream);
+  k_gemm_sum((GemmOut*)dev, (GemmTerm*)(dev + o_t), (int)outs.size(), prec, ctx->stream);
   outs.clear();
   terms.clear();
 }
