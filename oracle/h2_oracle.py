@@ -604,6 +604,18 @@ def choose_rank(sig: np.ndarray, eps: float, rule: str = RANK_ABS) -> int:
     return int(np.count_nonzero(tail > eps * tail[0]))
 
 
+def level_eps(eps: float, zeta: float, tree: "ClusterTree", t: int) -> float:
+    """R23 (variant, level-dependent tolerances): the truncation of cluster t
+    uses eps_l = eps * zeta**(D - l), l the level of t and D the depth of the
+    tree, 0 < zeta <= 1.  Leaves keep eps and each level above tightens it by
+    zeta, so the truncation errors met on the way from the leaves to a block
+    of any level sum to at most eps / (1 - zeta) (zeta < 1).  zeta = 1 is the
+    paper's uniform tolerance."""
+    if not 0.0 < zeta <= 1.0:
+        raise ValueError("zeta must lie in (0, 1]")
+    return eps * zeta ** (tree.depth - tree.level[t])
+
+
 # ----------------------------------------------------------------------------
 # Phase 1 set-up: basis weights, cluster basis products, total weights
 # (Section 4)
@@ -692,7 +704,7 @@ def _pad_rows(M: np.ndarray, rows: int) -> np.ndarray:
     return out
 
 
-def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) -> InducedBasis:
+def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS, zeta: float = 1.0) -> InducedBasis:
     """Compressed induced row basis of the product X Y.
 
     R18: Q_{X,t} is a full orthogonal factor whose first k1 columns span the
@@ -705,7 +717,8 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
     blocks of norm zero, or at most BLOCK_RTOL times the largest block norm
     of the level, are dropped (zero up to rounding: for the double-layer
     kernel the blocks of two clusters on one face of the cube).
-    R9: rank k2 = #{sigma > eps}.  The recursion of Figure "induced_basis"
+    R9: rank k2 = #{sigma > eps} (R23: eps of the cluster's level).  The
+    recursion of Figure "induced_basis"
     is taken level by level from the leaves (the clusters of a level are
     independent), so that each level's largest block norm is known.
     """
@@ -734,7 +747,7 @@ def induced_basis(X: H2Matrix, Y: H2Matrix, eps: float, rule: str = RANK_ABS) ->
         assembled[t] = (VX, Vrest)
         Vtil = mul(Ux[:, k1:].T, Vrest)
         U, sig = left_svd(Vtil)
-        k2 = choose_rank(sig, eps, rule)
+        k2 = choose_rank(sig, level_eps(eps, zeta, rt, t), rule)
         sig_out[t] = sig
         Qt = np.hstack([Ux[:, :k1], mul(Ux[:, k1:], U[:, :k2])])
         Q.rank[t] = k1 + k2
@@ -895,11 +908,11 @@ def form_product(X: H2Matrix, Y: H2Matrix, rowb: InducedBasis, colb: InducedBasi
 
 
 class Phase1:
-    def __init__(self, X, Y, eps, rule=RANK_ABS):
+    def __init__(self, X, Y, eps, rule=RANK_ABS, zeta=1.0):
         with _stage("p1_row"):
-            self.row = induced_basis(X, Y, eps, rule)
+            self.row = induced_basis(X, Y, eps, rule, zeta)
         with _stage("p1_col"):
-            self.col = induced_basis(Y.transposed(), X.transposed(), eps, rule)
+            self.col = induced_basis(Y.transposed(), X.transposed(), eps, rule, zeta)
         with _stage("p1_mat"):
             self.PT = ProductTree(X, Y)
             self.G = form_product(X, Y, self.row, self.col, self.PT)
@@ -1042,7 +1055,7 @@ class CoarseBasis:
 
 
 def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS,
-                Vold: ClusterBasis = None) -> CoarseBasis:
+                Vold: ClusterBasis = None, zeta: float = 1.0) -> CoarseBasis:
     """Figure "basis": adaptive isometric nested row basis for the coarse
     block tree T_IK, with the product total weights Z_t of
     eq. (Zt_condensation), leaf matrices C_t (eq. (ct_leaf)) and non-leaf
@@ -1082,9 +1095,10 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS,
     def truncate(t, C, VZ):
         """Orthonormal basis of C_t truncated at eps; with VZ the exact range
         of VZ followed by the truncated part of C_t outside it."""
+        eps_t = level_eps(eps, zeta, rt, t)
         if VZ is None:
             U, sig = left_svd(C)
-            kz = choose_rank(sig, eps, rule)
+            kz = choose_rank(sig, eps_t, rule)
             sig_out[t] = sig
             return U[:, :kz]
         rows = VZ.shape[0]
@@ -1097,7 +1111,7 @@ def build_basis(G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS,
             Ux, sx, _ = np.linalg.svd(VZ, full_matrices=True)
         k1 = int(np.count_nonzero(sx > VX_RTOL * sx[0])) if sx.size and sx[0] > 0 else 0
         U, sig = left_svd(mul(Ux[:, k1:].T, C))
-        k2 = choose_rank(sig, eps, rule)
+        k2 = choose_rank(sig, eps_t, rule)
         sig_out[t] = sig
         return np.hstack([Ux[:, :k1], mul(Ux[:, k1:], U[:, :k2])])
 
@@ -1230,23 +1244,25 @@ class Phase2:
     """Z <- Z + G in T_IK; Zold (on T_IK) is the Z before the update, None
     for Z = 0."""
 
-    def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS, Zold: H2Matrix = None):
+    def __init__(self, G: H2Matrix, TIK: BlockTree, eps: float, rule: str = RANK_ABS, Zold: H2Matrix = None,
+                 zeta: float = 1.0):
         with _stage("p2_row"):
-            self.row = build_basis(G, TIK, eps, rule, Zold.V if Zold is not None else None)
+            self.row = build_basis(G, TIK, eps, rule, Zold.V if Zold is not None else None, zeta)
         with _stage("p2_col"):
             self.col = build_basis(G.transposed(), TIK.transposed(), eps, rule,
-                                   Zold.W if Zold is not None else None)
+                                   Zold.W if Zold is not None else None, zeta)
         with _stage("p2_mat"):
             self.Z = form_coarse(G, TIK, self.row, self.col, Zold)
 
 
 def multiply(X: H2Matrix, Y: H2Matrix, TIK: BlockTree, eps1: float, eps2: float = None, rule: str = RANK_ABS,
-             Zold: H2Matrix = None):
+             Zold: H2Matrix = None, zeta: float = 1.0):
     """Both phases: returns (Phase1, Phase2); Z = phase2.Z approximates
     Zold + X Y (Zold on TIK, None for zero).  rule: the truncation rule of
-    both phases (R9 "abs", or the variant R21 "relF")."""
-    p1 = Phase1(X, Y, eps1, rule)
-    p2 = Phase2(p1.G, TIK, eps1 if eps2 is None else eps2, rule, Zold)
+    both phases (R9 "abs", or the variant R21 "relF"); zeta: the level
+    factor of R23 (1: one tolerance on every level)."""
+    p1 = Phase1(X, Y, eps1, rule, zeta)
+    p2 = Phase2(p1.G, TIK, eps1 if eps2 is None else eps2, rule, Zold, zeta)
     return p1, p2
 
 

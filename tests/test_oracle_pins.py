@@ -807,3 +807,79 @@ def test_update_by_zero_product_keeps_target():
     nc = tree.nclusters
     assert [p2.row.Q.rank[c] for c in range(nc)] == [p2a.row.Q.rank[c] for c in range(nc)]
     assert [p2.col.Q.rank[c] for c in range(nc)] == [p2a.col.Q.rank[c] for c in range(nc)]
+
+
+# --------------------------------------------------------------------------
+# R23 (variant of R9): level-dependent tolerances eps_l = eps zeta^(D - l)
+# --------------------------------------------------------------------------
+def test_level_eps_geometric_in_the_level():
+    """Leaves get eps; each level towards the root multiplies it by zeta;
+    zeta outside (0, 1] is refused."""
+    _, tree, _, _, _ = problem("2d")
+    eps, zeta = 1e-5, 0.3
+    for c in range(tree.nclusters):
+        e = OH.level_eps(eps, zeta, tree, c)
+        if tree.is_leaf(c):
+            assert e == eps
+        for ch in tree.children[c]:
+            assert np.isclose(OH.level_eps(eps, zeta, tree, ch) * zeta, e, rtol=1e-14)
+    assert OH.level_eps(eps, zeta, tree, 0) == pytest.approx(eps * zeta ** tree.depth, rel=1e-14)
+    for bad in (0.0, -0.5, 1.5):
+        with pytest.raises(ValueError):
+            OH.level_eps(eps, bad, tree, 0)
+
+
+@pytest.mark.parametrize("name", ["1d", "2d"])
+def test_level_factor_one_is_the_uniform_rule(name):
+    _, tree, bt, X, Y = problem(name)
+    p1, p2 = product(name, 1e-6)
+    q1, q2 = O.multiply(X, Y, bt, 1e-6, zeta=1.0)
+    nc = tree.nclusters
+    for a, b in ((p1.row, q1.row), (p1.col, q1.col), (p2.row, q2.row), (p2.col, q2.col)):
+        assert [a.Q.rank[c] for c in range(nc)] == [b.Q.rank[c] for c in range(nc)]
+    assert np.array_equal(p2.Z.dense(), q2.Z.dense())
+
+
+def _spectral(M):
+    return np.linalg.norm(M, 2) if M.size else 0.0
+
+
+@pytest.mark.parametrize("name,eps,zeta", [("1d", 1e-4, 0.5), ("2d", 1e-5, 0.25), ("2d", 1e-7, 0.5)])
+def test_level_tolerance_truncation_of_each_cluster(name, eps, zeta):
+    """Under R23 every truncation meets its own level's tolerance, checked
+    from the matrices themselves: the projection residual of C_t (Chat_t)
+    onto the new basis is at most eps_l in the spectral norm, and the rank is
+    minimal (the smallest kept singular value of C_t exceeds eps_l); phase 1
+    likewise for the remainder outside the kept range of V_X.  The leaf
+    ranks of phase 1 equal those of the uniform rule (same eps, same input)."""
+    _, tree, bt, X, Y = problem(name)
+    p1, p2 = O.multiply(X, Y, bt, eps, zeta=zeta)
+    u1, u2 = product(name, eps)
+    D = tree.depth
+    for side in (p2.row, p2.col):
+        for t, C in side.C.items():
+            if C.size == 0:
+                continue
+            el = eps * zeta ** (D - tree.level[t])
+            Q = side.Q.leaf[t] if tree.is_leaf(t) else (
+                _stacked_transfers(side.Q, tree, t) if side.Q.rank[t] else np.zeros((C.shape[0], 0)))
+            assert _spectral(C - Q @ (Q.T @ C)) <= el * (1 + 1e-9) + 1e-13 * _spectral(C)
+            sv = np.linalg.svd(C, compute_uv=False)
+            k = Q.shape[1]
+            assert k == 0 or sv[k - 1] > el * (1 - 1e-9)
+    Qf = p1.row.Q.full()
+    for t, (VX, Vrest) in p1.row.assembled.items():
+        if Vrest.size == 0:
+            continue
+        el = eps * zeta ** (D - tree.level[t])
+        Q = Qf[t] if tree.is_leaf(t) else _stacked_transfers(p1.row.Q, tree, t)
+        Ux, sx, _ = np.linalg.svd(VX, full_matrices=True)
+        k1 = int(np.count_nonzero(sx > OH.VX_RTOL * sx[0])) if sx.size and sx[0] > 0 else 0
+        assert _spectral(Vrest - Q @ (Q.T @ Vrest)) <= el * (1 + 1e-9) + 1e-13 * _spectral(Vrest)
+    for a, b in ((p1.row, u1.row), (p1.col, u1.col)):
+        for t in tree.leaves:
+            assert a.Q.rank[t] == b.Q.rank[t]
+    # the tighter inner tolerances change some decision (the variant is active)
+    nc = tree.nclusters
+    assert any([a.Q.rank[c] for c in range(nc)] != [b.Q.rank[c] for c in range(nc)]
+               for a, b in ((p1.row, u1.row), (p2.row, u2.row)))
