@@ -334,6 +334,15 @@ int h2_step_times(h2_ctx* ctx, double* out, int n, int reset);
  * unknown rule or a NULL context. */
 h2_status h2_set_rank_rule(h2_ctx* ctx, int rule);
 
+/* Level-dependent tolerances, a variant of the Section 5 error control: the
+ * truncations of clusters on level l of a cluster tree of depth D use
+ * eps * zeta^(D - l) in place of eps (leaves eps, each level towards the
+ * root tightened by zeta), in both passes of both phases, under either rank
+ * rule.  The default zeta = 1 is the paper's single tolerance.  Applies to
+ * the later h2_mul_intermediate and h2_recompress calls on ctx.  H2_ERR_ARG
+ * for zeta outside (0, 1] or a NULL context. */
+h2_status h2_set_level_factor(h2_ctx* ctx, double zeta);
+
 /* Test hook for the error paths: the `launches`-th batched kernel launch that
  * the context's own host thread issues from now on (0 = the next one) fails
  * with H2_ERR_DEVICE before it is launched, as a host-side failure in the

@@ -389,6 +389,14 @@ h2_status h2_set_rank_rule(h2_ctx* ctx, int rule) {
   });
 }
 
+h2_status h2_set_level_factor(h2_ctx* ctx, double zeta) {
+  return guard([&] {
+    H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
+    H2_REQUIRE(zeta > 0.0 && zeta <= 1.0, H2_ERR_ARG, "level factor outside (0, 1]");
+    ctx->level_factor = zeta;
+  });
+}
+
 h2_status h2_debug_fail_after(h2_ctx* ctx, int launches) {
   return guard([&] {
     H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");

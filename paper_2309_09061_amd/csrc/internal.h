@@ -384,6 +384,10 @@ struct h2_ctx;
 
 namespace h2 {
 
+// tolerance of the truncations on level l of a tree of depth D (the
+// level-dependent variant; zeta = 1 gives eps on every level)
+inline double level_eps(const h2_ctx* ctx, double eps, int D, int l);
+
 struct Arena {
   h2_ctx* ctx = nullptr;
   h2_ctx* owner = nullptr;  // root context referenced by a handle's arena (bind)
@@ -457,6 +461,7 @@ struct h2_ctx {
   std::chrono::steady_clock::time_point host_t0[8];
   int prec = 0;                        // bulk precision of the running call
   int rank_rule = 0;                   // h2_rank_rule of the truncating SVDs
+  double level_factor = 1.0;           // zeta: level l truncates at eps zeta^(depth - l)
   int profile = 0;                     // bit k: time the launches of kernel family k
   int fail_after = -1;                 // test hook: launches left before an injected failure (-1: off)
   h2_alloc_fn alloc_fn = nullptr;      // caller's device allocator (nullptr: hipMalloc / hipFree)
@@ -476,6 +481,14 @@ struct h2_ctx {
   bool own_stream = false;
   ~h2_ctx();
 };
+
+namespace h2 {
+inline double level_eps(const h2_ctx* ctx, double eps, int D, int l) {
+  double e = eps;
+  for (int j = l; j < D; ++j) e *= ctx->level_factor;
+  return e;
+}
+}  // namespace h2
 
 struct h2_tree {
   std::shared_ptr<h2::TreeH> ct;

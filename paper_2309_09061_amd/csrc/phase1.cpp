@@ -332,7 +332,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
     std::vector<KeptItem> kit(nc);
     for (int i = 0; i < nc; ++i) kit[i] = {rows[i], VXw[i], rows[i], k, Vr[i], rows[i], ncols[i]};
     KeptOut ko;
-    kept_compress(ctx, kit, eps, keep, ko);
+    kept_compress(ctx, kit, level_eps(ctx, eps, D, l), keep, ko);
     // (e) Q_t, transfers, A_{t,s} = Q_t^* (...), [R_X; 0]
     std::vector<double*> Qn(nc);
     for (int i = 0; i < nc; ++i) {

@@ -407,7 +407,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       g.run(ctx);
       KeptOut ko;
       if (leaf) build_columns();  // host work while the device factorizes
-      kept_compress(ctx, kit, eps, keep, ko);
+      kept_compress(ctx, kit, level_eps(ctx, eps, D, l), keep, ko);
       for (int i = 0; i < nc; ++i) {
         kz[i] = ko.k1[i] + ko.k2[i];
         Qk[i] = ko.Q[i];
@@ -426,7 +426,8 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         U[i] = ws.get<double>((size_t)m[i] * m[i]);
         sg[i] = ws.get<double>(m[i]);
         ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
-        jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, eps, 0.0, nullptr, 1, ctx->rank_rule);
+        jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, level_eps(ctx, eps, D, l), 0.0, nullptr, 1,
+               ctx->rank_rule);
       }
       ts.run(ctx);
       jb.run(ctx);

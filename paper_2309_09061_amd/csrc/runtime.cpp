@@ -303,6 +303,7 @@ AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), 
   aux->profile = ctx->profile;
   aux->prec = ctx->prec;
   aux->rank_rule = ctx->rank_rule;
+  aux->level_factor = ctx->level_factor;
   // the staging of the previous run is free once that run's work is done
   // (usually long ago): wait for its end event, not for the stream, which is
   // about to wait for ctx's queue

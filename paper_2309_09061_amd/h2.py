@@ -127,6 +127,7 @@ def _declare(lib):
         "h2_product_sizes": (ctypes.c_int, [_c_p, _c_p]),
         "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int]),
         "h2_set_rank_rule": (ctypes.c_int, [_c_p, ctypes.c_int]),
+        "h2_set_level_factor": (ctypes.c_int, [_c_p, ctypes.c_double]),
         "h2_debug_fail_after": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_profile": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_kernel_stats": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int]),
@@ -208,6 +209,11 @@ class Context:
         above eps of the scaled matrices) or "relF" (relative-Frobenius tail
         at most eps)."""
         _check(self.lib, self.lib.h2_set_rank_rule(self.h, RANK_RULES[rule]))
+
+    def set_level_factor(self, zeta: float):
+        """Level-dependent tolerances: clusters on level l of a tree of depth
+        D truncate at eps * zeta**(D - l) (1: one tolerance on all levels)."""
+        _check(self.lib, self.lib.h2_set_level_factor(self.h, float(zeta)))
 
     def fail_after(self, launches: int):
         """Test hook: the launches-th batched launch issued by this context's

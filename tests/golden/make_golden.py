@@ -3,6 +3,9 @@
 Calls only oracle/ and workloads.py.  Run:
     python tests/golden/make_golden.py c2      (or c3, dlp, or c4)
 
+dlp is the double-layer recipe at n = 49152 (the oracle's memory at
+n = 110592 exceeds what the generating host holds).
+
 For the single-product workloads (c2, c3, dlp) the file holds
   - the rank profiles of both phases (row and column bases);
   - a two-sided randomized sketch of G, Z and X Y:  Psi^T M Omega with
@@ -36,7 +39,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle as O  # noqa: E402
 import workloads as W  # noqa: E402
 
-NAMES = {"c2": W.C2, "c3": W.C3, "dlp": W.C6}
+NAMES = {"c2": W.C2, "c3": W.C3, "dlp": W.C6S}
 PROBE_SEED, SKETCH_SEED, INDEX_SEED, POWER_SEED = 101, 103, 102, 104
 NPROBE = 32
 POWER_STEPS = 20

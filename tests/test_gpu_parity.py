@@ -499,6 +499,40 @@ def test_rel_frobenius_rank_rule(name):
     assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
 
 
+@pytest.mark.parametrize("name,zeta,rule", [("1d", 0.5, "abs"), ("2d", 0.25, "abs"), ("ragged", 0.3, "abs"),
+                                             ("2d", 0.5, "relF")])
+def test_level_dependent_tolerances(name, zeta, rule):
+    """Level-dependent tolerances (h2_set_level_factor) against the oracle
+    with the same level factor: identical rank profiles in both phases and the
+    FP64 bar for G and Z; the ranks differ from those of the single tolerance
+    somewhere (the variant is active)."""
+    h2 = _h2()
+    n, d, leaf, order, kx, ky, eta, seed, dist, eps = CASES[name]
+    pts, tree, X, Y, _, _, _, _ = oracle_case(name)
+    bt = O.BlockTree(tree, tree, eta)
+    orule = O.RANK_REL_FROB if rule == "relF" else O.RANK_ABS
+    p1, p2 = O.multiply(X, Y, bt, eps, rule=orule, zeta=zeta)
+    u1, u2 = O.multiply(X, Y, bt, eps, rule=orule)
+    c = h2.Context(0)
+    c.set_rank_rule(rule)
+    c.set_level_factor(zeta)
+    _say(f"[gpu] level factor: case={name} n={n} eps={eps} zeta={zeta} rule={rule}")
+    T = h2.Tree(c, pts, leaf, eta)
+    Xg = h2.Matrix.kernel(c, T, kx, order)
+    Yg = Xg if ky == kx else h2.Matrix.kernel(c, T, ky, order)
+    G = h2.h2_mul_intermediate(c, Xg, Yg, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    torch.cuda.synchronize()
+    nc = tree.nclusters
+    got = [list(G.ranks(0)), list(G.ranks(1)), list(Z.ranks(0)), list(Z.ranks(1))]
+    want = [[s.Q.rank[t] for t in range(nc)] for s in (p1.row, p1.col, p2.row, p2.col)]
+    uniform = [[s.Q.rank[t] for t in range(nc)] for s in (u1.row, u1.col, u2.row, u2.col)]
+    assert got == want
+    assert want != uniform
+    assert relF(dense_of(G, n), p1.G.dense()) < 1e-10
+    assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
+
+
 def test_single_leaf_tree():
     """Degenerate tree: fewer points than the leaf size, one cluster, one
     inadmissible block; the product is the dense product."""
