@@ -386,9 +386,54 @@ def main():
                                  "speedup_vs_fp64": s64["ms_per_step"] / smx["ms_per_step"],
                                  "error": smx["error"]}}
         del Q
+    if not args.no_side:
+        out["batched"] = measure_batched(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(main_w, gold)
     print(json.dumps(out), flush=True)
+
+
+def measure_batched(steps: int, warmup: int) -> dict:
+    """The batched workload (64 independent 2-D products, n 2048..32768,
+    orders 3..5): both phases for all 64 in one call of each (instances run
+    concurrently on the library's lanes) against a loop of single-product
+    calls, inputs resident; FP64."""
+    import torch
+
+    import workloads as W
+    from paper_2309_09061_amd import h2
+    c = h2.Context(0)
+    inst = W.batched_instances()
+    Ts = [h2.Tree(c, pts, w.leaf_size, w.eta) for w, pts in inst]
+    Xs = [h2.Matrix.kernel(c, T, w.kernel_x, w.order) for T, (w, _) in zip(Ts, inst)]
+    eps = inst[0][0].eps
+    torch.cuda.synchronize()
+
+    def batched():
+        Gs = h2.h2_mul_intermediate(c, Xs, Xs, eps)
+        h2.h2_recompress(c, Gs, [h2.Matrix.zero(c, T) for T in Ts], eps)
+
+    def serial():
+        for T, X in zip(Ts, Xs):
+            G = h2.h2_mul_intermediate(c, [X], [X], eps)
+            h2.h2_recompress(c, G, [h2.Matrix.zero(c, T)], eps)
+
+    res = {}
+    for name, f in (("batched", batched), ("serial", serial)):
+        for _ in range(max(warmup, 1)):
+            f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps * 1e3
+        print(f"[c4 {name}] {steps} steps done", file=sys.stderr, flush=True)
+    return {"workload": "c4_batched_64", "instances": len(inst), "n_total": int(sum(w.n for w, _ in inst)),
+            "ms_per_step_batched": res["batched"], "ms_per_step_serial": res["serial"],
+            "speedup_vs_serial": res["serial"] / res["batched"],
+            "note": "one call of each phase for all 64 products (up to 4 concurrent instances, each on its "
+                    "own streams and host threads) against 64 single-product calls"}
 
 
 if __name__ == "__main__":

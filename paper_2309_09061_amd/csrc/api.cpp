@@ -49,6 +49,53 @@ static void check_precision(int prec, double eps) {
 // before it.
 static void begin_call(h2_ctx* ctx) {
   for (h2_ctx* c = ctx; c; c = c->aux) c->ws.reset();
+  for (h2_ctx* l : ctx->lanes)
+    for (h2_ctx* c = l; c; c = c->aux) c->ws.reset();
+}
+
+// Runs body(lane, i) for the instances i = 0..count-1 of a batched call, at
+// most kBatchLanes at a time, each lane on its own host thread, stream and
+// workspace; instances are taken largest first (weight w[i]) from a shared
+// counter.  Every lane is ordered after the work queued on ctx->stream so
+// far, and ctx->stream after every lane's work.  The first exception stops
+// the lanes from taking further instances and is rethrown once all have
+// been joined.
+static void run_lanes(h2_ctx* ctx, int count, const std::vector<int64_t>& w,
+                      const std::function<void(h2_ctx*, int)>& body) {
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+  const int nl = std::min(count, h2::kBatchLanes);
+  std::atomic<int> next{0};
+  std::atomic<bool> stop{false};
+  std::vector<std::unique_ptr<h2::AuxRun>> runs;
+  std::exception_ptr first;
+  try {
+    for (int l = 0; l < nl; ++l)
+      runs.push_back(std::make_unique<h2::AuxRun>(ctx, h2::lane_ctx(ctx, l), [&](h2_ctx* a) {
+        for (;;) {
+          const int j = next.fetch_add(1);
+          if (j >= count || stop.load()) return;
+          try {
+            body(a, order[j]);
+          } catch (...) {
+            stop.store(true);
+            throw;
+          }
+        }
+      }));
+  } catch (...) {
+    stop.store(true);
+    first = std::current_exception();
+  }
+  for (auto& r : runs) {
+    try {
+      r->join();
+    } catch (...) {
+      if (!first) first = std::current_exception();
+    }
+  }
+  if (first) std::rethrow_exception(first);
 }
 
 extern "C" {
@@ -199,19 +246,30 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
     check_precision((int)prec, eps);
     need_device(ctx);
     begin_call(ctx);
-    for (int i = 0; i < count; ++i) {
+    auto one = [&](h2_ctx* c, int i) {
       auto* G = new h2_product();
       try {
-        phase1(ctx, X[i], Y[i], eps, (int)prec, G);
+        phase1(c, X[i], Y[i], eps, (int)prec, G);
       } catch (...) {
         delete G;
-        for (int j = 0; j < i; ++j) {
-          delete G_out[j];
-          G_out[j] = nullptr;
-        }
         throw;
       }
       G_out[i] = G;
+    };
+    try {
+      if (count == 1 || ctx->root) {
+        for (int i = 0; i < count; ++i) one(ctx, i);
+      } else {
+        std::vector<int64_t> w(count);
+        for (int i = 0; i < count; ++i) w[i] = X[i]->c.ct->n;
+        run_lanes(ctx, count, w, one);
+      }
+    } catch (...) {
+      for (int j = 0; j < count; ++j) {
+        delete G_out[j];
+        G_out[j] = nullptr;
+      }
+      throw;
     }
   });
 }
@@ -261,7 +319,13 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     check_precision((int)prec, eps);
     need_device(ctx);
     begin_call(ctx);
-    for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);
+    if (count == 1 || ctx->root) {
+      for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);
+    } else {
+      std::vector<int64_t> w(count);
+      for (int i = 0; i < count; ++i) w[i] = G[i]->c.bt ? (int64_t)G[i]->c.bt->nblocks() : 0;
+      run_lanes(ctx, count, w, [&](h2_ctx* c, int i) { phase2(c, G[i], Z[i], eps, (int)prec); });
+    }
   });
 }
 

@@ -477,6 +477,9 @@ struct h2_ctx {
   // second context on the same device (own stream, workspace, staging) for
   // the column passes, which run concurrently with the row passes
   h2_ctx* aux = nullptr;
+  // root contexts: one context per concurrent instance of a batched call
+  // (each with its own auxiliary chain), created on first use
+  std::vector<h2_ctx*> lanes;
   void* drain = nullptr;  // auxiliary contexts: end of the last run's work on the stream
   bool own_stream = false;
   ~h2_ctx();
@@ -570,6 +573,12 @@ void* pool_event(h2_ctx* ctx);
 // the auxiliary context of ctx (created on first use); the auxiliary
 // context's own one, aux_ctx(aux_ctx(ctx)), is a third stream
 h2_ctx* aux_ctx(h2_ctx* ctx);
+// instances of a batched call run concurrently, at most this many at a time,
+// each on a lane context of the root context (own stream, workspace and
+// staging, and its own auxiliary contexts for its column pass and dense
+// products); lane_ctx(ctx, w) creates lane w on first use
+constexpr int kBatchLanes = 4;
+h2_ctx* lane_ctx(h2_ctx* ctx, int w);
 // Runs f(aux) on a host thread, on the auxiliary stream, ordered after the
 // work queued so far on ctx->stream.  join() waits for the thread, makes
 // ctx->stream wait for the auxiliary work, and rethrows its exception.

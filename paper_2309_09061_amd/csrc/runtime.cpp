@@ -271,29 +271,38 @@ WorkCounts work_counts(h2_ctx* ctx, int n, int kind) {
 // auxiliary context: the column passes run on it concurrently with the row
 // passes (own stream, workspace, staging, events; same device)
 // ---------------------------------------------------------------------------
-h2_ctx* aux_ctx(h2_ctx* ctx) {
-  if (!ctx->aux) {
-    auto* a = new h2_ctx();
-    a->device = ctx->device;
-    a->host_only = false;
-    a->ws.ctx = a;
-    a->root = root_of(ctx);
-    a->alloc_fn = ctx->alloc_fn;
-    a->free_fn = ctx->free_fn;
-    a->alloc_user = ctx->alloc_user;
-    a->scratch_dev = ctx->scratch_dev;
-    try {
-      a->stream = dev_stream_create();
-      a->own_stream = true;
-      a->stage_cap = (size_t)16 << 20;
-      a->stage = (char*)dev_malloc_host(a->stage_cap);
-      a->stage_dev = (char*)dev_host_view(a->stage);
-    } catch (...) {
-      delete a;
-      throw;
-    }
-    ctx->aux = a;
+static h2_ctx* side_ctx(h2_ctx* ctx) {
+  auto* a = new h2_ctx();
+  a->device = ctx->device;
+  a->host_only = false;
+  a->ws.ctx = a;
+  a->root = root_of(ctx);
+  a->alloc_fn = ctx->alloc_fn;
+  a->free_fn = ctx->free_fn;
+  a->alloc_user = ctx->alloc_user;
+  a->scratch_dev = ctx->scratch_dev;
+  try {
+    a->stream = dev_stream_create();
+    a->own_stream = true;
+    a->stage_cap = (size_t)16 << 20;
+    a->stage = (char*)dev_malloc_host(a->stage_cap);
+    a->stage_dev = (char*)dev_host_view(a->stage);
+  } catch (...) {
+    delete a;
+    throw;
   }
+  return a;
+}
+
+h2_ctx* lane_ctx(h2_ctx* ctx, int w) {
+  H2_REQUIRE(w >= 0 && w < kBatchLanes && !ctx->root, H2_ERR_ARG, "lane of a non-root context");
+  if ((int)ctx->lanes.size() <= w) ctx->lanes.resize(w + 1, nullptr);
+  if (!ctx->lanes[w]) ctx->lanes[w] = side_ctx(ctx);
+  return ctx->lanes[w];
+}
+
+h2_ctx* aux_ctx(h2_ctx* ctx) {
+  if (!ctx->aux) ctx->aux = side_ctx(ctx);
   return ctx->aux;
 }
 
@@ -358,27 +367,33 @@ AuxRun::~AuxRun() {
 }
 
 void aux_collect(h2_ctx* ctx) {
-  h2_ctx* a = ctx->aux;
-  if (!a) return;
-  aux_collect(a);  // the auxiliary context's own one first
-  steps_collect(a);
-  for (int i = 0; i < 8; ++i) {
-    ctx->step_ms[i] += a->step_ms[i];
-    ctx->host_ms[i] += a->host_ms[i];
-    a->step_ms[i] = 0.0;
-    a->host_ms[i] = 0.0;
+  std::vector<h2_ctx*> side = ctx->lanes;
+  side.push_back(ctx->aux);
+  for (h2_ctx* a : side) {
+    if (!a) continue;
+    aux_collect(a);  // the side context's own ones first
+    steps_collect(a);
+    for (int i = 0; i < 8; ++i) {
+      ctx->step_ms[i] += a->step_ms[i];
+      ctx->host_ms[i] += a->host_ms[i];
+      a->step_ms[i] = 0.0;
+      a->host_ms[i] = 0.0;
+    }
   }
 }
 
 void kernel_stats_collect(h2_ctx* ctx) {
-  if (ctx->aux) {
-    kernel_stats_collect(ctx->aux);
+  std::vector<h2_ctx*> side = ctx->lanes;
+  side.push_back(ctx->aux);
+  for (h2_ctx* a : side) {
+    if (!a) continue;
+    kernel_stats_collect(a);
     for (int k = 0; k < KK_COUNT; ++k) {
-      ctx->kstat[k].ms += ctx->aux->kstat[k].ms;
-      ctx->kstat[k].flops += ctx->aux->kstat[k].flops;
-      ctx->kstat[k].bytes += ctx->aux->kstat[k].bytes;
-      ctx->kstat[k].launches += ctx->aux->kstat[k].launches;
-      ctx->aux->kstat[k] = KernelStat{};
+      ctx->kstat[k].ms += a->kstat[k].ms;
+      ctx->kstat[k].flops += a->kstat[k].flops;
+      ctx->kstat[k].bytes += a->kstat[k].bytes;
+      ctx->kstat[k].launches += a->kstat[k].launches;
+      a->kstat[k] = KernelStat{};
     }
   }
   for (auto& p : ctx->pending) {
@@ -961,6 +976,7 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
 }  // namespace h2
 
 h2_ctx::~h2_ctx() {
+  for (h2_ctx* l : lanes) delete l;
   delete aux;
   for (auto& p : pending) {
     h2::dev_event_destroy(p.a);
