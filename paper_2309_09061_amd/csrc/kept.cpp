@@ -11,8 +11,11 @@
 //      factor Q_K has range(K) in its first k1 columns;
 //   3. C <- Q_K^* C; the SVD of its rows k1.. (TSQR of their transpose,
 //      Jacobi), rank k2 by the truncation rule at eps;
-//   4. Q = Q_K [I 0; 0 U2(:, 1:k2)] and [R_K; 0] = Q^* K, R_K = (R_Y V'^*)(1:k1, :)
-//      with R_Y the triangular factor of step 2.
+//   4. Q = Q_K [I 0; 0 U2(:, 1:k2)] and [R_K; 0] = Q^* K, R_K = (Q_K^* K)(1:k1, :),
+//      the reflectors of step 2 applied to K itself.  (R_Y V'^* equals it only
+//      as far as V' is orthogonal: a rank-deficient K leaves V' orthogonal to
+//      about the Jacobi tolerance, and that error, carried up through the
+//      transfers, would add spurious directions to the parents' kept ranges.)
 #include "internal.h"
 
 namespace h2 {
@@ -28,13 +31,14 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
   out.Q.assign(n, nullptr);
   out.RKP.assign(n, nullptr);
   if (n == 0) return;
-  GemmBatch g;
+  GemmBatch g, g64;  // g64: plain copies, always in FP64
   g.prec = ctx->prec;
   TsqrBatch ts;
   JacobiBatch jb;
   int32_t* rk = ws.get<int32_t>(2 * n);  // [k1 | k2] per item
   dev_zero(rk, sizeof(int32_t) * 2 * n, ctx->stream);
   std::vector<double*> Vp(n, nullptr), Yq(n, nullptr), tau(n, nullptr), RYq(n, nullptr), U(n, nullptr);
+  std::vector<double*> KQ(n, nullptr);
   // 1. SVD of K from its R factor
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
@@ -58,14 +62,19 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
     g.out(Yq[i], it.m, it.m, it.kc);
     g.term(it.K, it.ldk, false, Vp[i], it.kc, false, it.kc);
     qr.add(Yq[i], it.m, it.m, it.kc, tau[i], RYq[i], it.kc, std::min(it.m, it.kc));
+    KQ[i] = ws.get<double>((size_t)it.m * it.kc);  // K, to become Q_K^* K
+    g64.out(KQ[i], it.m, it.m, it.kc);
+    g64.copy(it.K, it.ldk, false, it.kc);
   }
   g.run(ctx);
+  g64.run(ctx);
   qr.run(ctx);
   // 3. remainder: Q_K^* C with the first k1 rows masked, its SVD
   ApplyBatch ap;
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
     if (Yq[i] && it.nc > 0) ap.add(Yq[i], it.m, tau[i], it.m, std::min(it.m, it.kc), it.C, it.ldc, it.nc, true);
+    if (Yq[i]) ap.add(Yq[i], it.m, tau[i], it.m, std::min(it.m, it.kc), KQ[i], it.m, it.kc, true);
   }
   ap.run(ctx);
   for (int i = 0; i < n; ++i) {
@@ -97,11 +106,11 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
     if (out.k2[i] > 0) {
-      g.out(out.Q[i] + (size_t)out.k1[i] * it.m, it.m, it.m, out.k2[i]);
-      g.copy(U[i], it.m, false, out.k2[i]);
+      g64.out(out.Q[i] + (size_t)out.k1[i] * it.m, it.m, it.m, out.k2[i]);
+      g64.copy(U[i], it.m, false, out.k2[i]);
     }
   }
-  g.run(ctx);
+  g64.run(ctx);
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
     const int kt = out.k1[i] + out.k2[i];
@@ -113,13 +122,13 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
     const int kt = out.k1[i] + out.k2[i], k1 = out.k1[i];
     out.RKP[i] = ws.get<double>((size_t)std::max(kt, 1) * std::max(it.kc, 1));
     if (kt == 0 || it.kc == 0) continue;
-    if (k1 > 0) {
-      g.out(out.RKP[i], kt, k1, it.kc);
-      g.term(RYq[i], it.kc, false, Vp[i], it.kc, true, it.kc);
+    if (k1 > 0) {  // rows 0..k1-1 of Q_K^* K
+      g64.out(out.RKP[i], kt, k1, it.kc);
+      g64.copy(KQ[i], it.m, false, it.kc);
     }
-    if (kt > k1) g.out(out.RKP[i] + k1, kt, kt - k1, it.kc);  // zero rows below R_K
+    if (kt > k1) g64.out(out.RKP[i] + k1, kt, kt - k1, it.kc);  // zero rows below R_K
   }
-  g.run(ctx);
+  g64.run(ctx);
 }
 
 }  // namespace h2

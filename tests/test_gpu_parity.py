@@ -182,7 +182,7 @@ def test_exact_without_truncation(name):
     assert relF(dense_of(Z, tree.n), XY) < 1e-12
 
 
-FULL = {"c2": W.C2, "c3": W.C3}
+FULL = {"c2": W.C2, "c3": W.C3, "dlp": W.C6S}
 
 
 def power_eps2(Z, X, Y, n, seed, steps):
@@ -240,8 +240,9 @@ def sketch_errors(M, gold, key, n):
 
 @pytest.mark.parametrize("key", list(FULL))
 def test_workload_full_size(key):
-    """The 2-D workload at n = 16384 and the sphere workload at n = 131072
-    against the stored oracle results: rank profiles of both phases; G and Z
+    """The 2-D workload at n = 16384, the sphere workload at n = 131072 and
+    the double-layer workload at n = 49152 against the stored oracle results:
+    rank profiles of both phases; G and Z
     through 32 seeded probes over all n entries (two-sided sketch, relative
     Frobenius <= 1e-10 overall and per probe, column norms to 1e-10);
     sampled entries; the spectral error against X Y by power iteration; and
@@ -252,8 +253,8 @@ def test_workload_full_size(key):
     _say(f"[gpu] workload {key} n={w.n}: build")
     c = ctx()
     T = h2.Tree(c, w.points(), w.leaf_size, w.eta)
-    X = h2.Matrix.kernel(c, T, w.kernel_x, w.order)
-    Y = X if w.kernel_y == w.kernel_x else h2.Matrix.kernel(c, T, w.kernel_y, w.order)
+    X = h2.Matrix.kernel(c, T, w.kernel_x, w.order, w.normals())
+    Y = X if w.kernel_y == w.kernel_x else h2.Matrix.kernel(c, T, w.kernel_y, w.order, w.normals())
     _say(f"[gpu] workload {key}: phase 1")
     G = h2.h2_mul_intermediate(c, X, Y, w.eps)
     _say(f"[gpu] workload {key}: phase 2")
