@@ -1778,6 +1778,32 @@ static __host__ __device__ inline size_t norm2_need(int g, int chunk) {
 }
 size_t norm2_need_doubles(int g, int chunk) { return norm2_need(g, chunk); }
 
+// sum_{k < n} a[k sa] b[k sb] over LDS operands: the loads of eight terms
+// are issued together and summed into four partial sums, so a lane waits
+// for one LDS round trip per eight terms rather than per term
+__device__ __forceinline__ double lds_dot(const double* a, int sa, const double* b, int sb, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+  for (; k + 8 <= n; k += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = a[(k + u) * sa];
+      y[u] = b[(k + u) * sb];
+    }
+    s0 += x[0] * y[0];
+    s1 += x[1] * y[1];
+    s2 += x[2] * y[2];
+    s3 += x[3] * y[3];
+    s0 += x[4] * y[4];
+    s1 += x[5] * y[5];
+    s2 += x[6] * y[6];
+    s3 += x[7] * y[7];
+  }
+  for (; k < n; ++k) s0 += a[k * sa] * b[k * sb];
+  return (s0 + s1) + (s2 + s3);
+}
+
 __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict__ probs, int nprob, int per,
                                                      int cshift) {
   const int chunk = 1 << cshift;  // samples staged per step (16, 32 or 64)
@@ -1793,9 +1819,22 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   }
   // the entries are scaled by a power of two (exact) that brings the largest
   // to [1/2, 1), so the Gram matrix neither overflows nor underflows
+  // (global loads eight at a time: the block is read with eight loads in
+  // flight per lane instead of a chain of dependent ones)
   double amax = 0.0;
-  for (int j = 0; j < P.cols; ++j)
-    for (int i = lane; i < P.rows; i += 64) amax = fmax(amax, fabs(P.A[i + (int64_t)j * P.lda]));
+  {
+    const int total = P.rows * P.cols;
+    for (int e0 = lane; e0 < total; e0 += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 64 * u;
+        v[u] = e < total ? fabs(P.A[(e % P.rows) + (int64_t)(e / P.rows) * P.lda]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) amax = fmax(amax, v[u]);
+    }
+  }
   for (int o = 1; o < 64; o <<= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
   if (!(amax > 0.0) || !(amax <= DBL_MAX)) {  // zero, or not finite: passed through
     if (lane == 0) *P.out = amax;
@@ -1819,20 +1858,39 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
     const int cnt = min(chunk, ns - s0);
     team_sync<64>();  // the previous chunk's reads are done
     if (tall) {
-      for (int e = lane; e < chunk * g; e += 64) {
-        const int sm = e & (chunk - 1), f = e >> cshift;
-        if (sm < cnt) X[sm * g + f] = sc * P.A[(s0 + sm) + (int64_t)f * P.lda];
+      for (int e0 = lane; e0 < chunk * g; e0 += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + 64 * u, sm = e & (chunk - 1), f = e >> cshift;
+          v[u] = (e < chunk * g && sm < cnt) ? P.A[(s0 + sm) + (int64_t)f * P.lda] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + 64 * u, sm = e & (chunk - 1), f = e >> cshift;
+          if (e < chunk * g && sm < cnt) X[sm * g + f] = sc * v[u];
+        }
       }
     } else {
-      for (int e = lane; e < cnt * g; e += 64) X[e] = sc * P.A[(e % g) + (int64_t)(s0 + e / g) * P.lda];
+      for (int e0 = lane; e0 < cnt * g; e0 += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + 64 * u;
+          v[u] = e < cnt * g ? P.A[(e % g) + (int64_t)(s0 + e / g) * P.lda] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + 64 * u;
+          if (e < cnt * g) X[e] = sc * v[u];
+        }
+      }
     }
     team_sync<64>();
     for (int e = lane; e < g * g; e += 64) {
       const int f1 = e % g, f2 = e / g;
       if (f1 > f2) continue;
-      double acc = 0.0;
-      for (int sm = 0; sm < cnt; ++sm) acc += X[sm * g + f1] * X[sm * g + f2];
-      Gm[e] += acc;
+      Gm[e] += lds_dot(X + f1, g, X + f2, g, cnt);
     }
   }
   team_sync<64>();
@@ -1869,21 +1927,15 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
     }
     team_sync<64>();
     double w = 0.0;
-    if (lane < g)
-      for (int k = 0; k < g; ++k) w += Gm[k * g + lane] * Qr[j * g + k];  // Gm symmetric: column access
+    if (lane < g) w = lds_dot(Gm + lane, g, Qr + j * g, 1, g);  // Gm symmetric: column access
     const double al = wave_sum(w * q);
     w -= al * q + bprev * qp;
     for (int pass = 0; pass < 2; ++pass) {
       if (lane < g) Wv[lane] = w;
       team_sync<64>();
-      if (lane <= j) {
-        double h = 0.0;
-        for (int i = 0; i < g; ++i) h += Wv[i] * Qt[i * g + lane];
-        Hv[lane] = h;
-      }
+      if (lane <= j) Hv[lane] = lds_dot(Wv, 1, Qt + lane, g, g);
       team_sync<64>();
-      if (lane < g)
-        for (int t = 0; t <= j; ++t) w -= Hv[t] * Qr[t * g + lane];
+      if (lane < g) w -= lds_dot(Hv, 1, Qr + lane, g, j + 1);
       team_sync<64>();
     }
     const double bt = sqrt(wave_sum(w * w));
