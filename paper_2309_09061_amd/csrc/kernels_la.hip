@@ -1774,7 +1774,7 @@ void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* strea
 constexpr int kNorm2MaxG = 64;
 int norm2_max_dim() { return kNorm2MaxG; }
 static __host__ __device__ inline size_t norm2_need(int g, int chunk) {
-  return (size_t)g * g + (size_t)max(2 * g * g, chunk * g) + 4 * (size_t)g;
+  return (size_t)g * g + (size_t)max(g * g, chunk * g) + 4 * (size_t)g;
 }
 size_t norm2_need_doubles(int g, int chunk) { return norm2_need(g, chunk); }
 
@@ -1845,9 +1845,8 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   const double sc = ldexp(1.0, -ex);
   double* Gm = lds_dyn + (size_t)wave * per;
   double* Qr = Gm + g * g;  // Qr[t g + i]: component i of Lanczos vector t
-  double* Qt = Qr + g * g;  // Qt[i g + t]: the same, transposed
   double* X = Qr;           // staging of `chunk` samples (rows, or columns) x g
-  double* Wv = Gm + g * g + max(2 * g * g, chunk * g);
+  double* Wv = Gm + g * g + max(g * g, chunk * g);
   double* Hv = Wv + g;
   double* Ta = Hv + g;
   double* Tb = Ta + g;
@@ -1921,10 +1920,7 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   double qp = 0.0, bprev = 0.0;
   int nt = g;
   for (int j = 0; j < g; ++j) {
-    if (lane < g) {
-      Qr[j * g + lane] = q;
-      Qt[lane * g + j] = q;
-    }
+    if (lane < g) Qr[j * g + lane] = q;
     team_sync<64>();
     double w = 0.0;
     if (lane < g) w = lds_dot(Gm + lane, g, Qr + j * g, 1, g);  // Gm symmetric: column access
@@ -1933,7 +1929,7 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
     for (int pass = 0; pass < 2; ++pass) {
       if (lane < g) Wv[lane] = w;
       team_sync<64>();
-      if (lane <= j) Hv[lane] = lds_dot(Wv, 1, Qt + lane, g, g);
+      if (lane <= j) Hv[lane] = lds_dot(Wv, 1, Qr + lane * g, 1, g);  // stride g (odd or not) across lanes
       team_sync<64>();
       if (lane < g) w -= lds_dot(Hv, 1, Qr + lane, g, j + 1);
       team_sync<64>();
@@ -1994,7 +1990,19 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
 void k_norm2(const Norm2Prob* probs, int n, int per_doubles, int chunk, void* stream) {
   if (n <= 0) return;
   H2_REQUIRE(chunk == 16 || chunk == 32 || chunk == 64, H2_ERR_ARG, "norm2: chunk must be 16, 32 or 64");
-  int wpb = std::min(4, lds_limit_doubles() / std::max(per_doubles, 1));
+  // problems per workgroup (one wavefront each): the most wavefronts per
+  // compute unit that its 160 KiB of LDS hold, more per workgroup on ties
+  constexpr size_t kCuLds = 160 * 1024;
+  const size_t per_bytes = (size_t)std::max(per_doubles, 1) * 8;
+  int wpb = 0, best = 0;
+  for (int w = 1; w <= 4; w *= 2) {
+    if (w * std::max(per_doubles, 1) > lds_limit_doubles()) break;
+    const int waves = w * (int)(kCuLds / (w * per_bytes));
+    if (waves >= best) {
+      best = waves;
+      wpb = w;
+    }
+  }
   if (n < 4 * 256) wpb = std::min(wpb, 1);
   H2_REQUIRE(wpb >= 1, H2_ERR_ARG, "norm2: problems too large");
   const int cshift = chunk == 16 ? 4 : chunk == 32 ? 5 : 6;

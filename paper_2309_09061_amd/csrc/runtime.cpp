@@ -952,7 +952,11 @@ std::vector<const double*> NormBatch::run(h2_ctx* ctx) {
     LaunchTimer lt(ctx, KK_OTHER, nflops, nbytes);
     int ns_max = 0;
     for (const Norm2Prob& q : np) ns_max = std::max(ns_max, std::max(q.rows, q.cols));
-    const int chunk = ns_max <= 16 ? 16 : ns_max <= 32 ? 32 : 64;
+    // samples staged per step: enough for the longest side, but no more
+    // than the Lanczos vectors' space (g^2) holds, which keeps LDS per
+    // problem, and so the problems resident per compute unit, at g^2 size
+    int chunk = ns_max <= 16 ? 16 : ns_max <= 32 ? 32 : 64;
+    while (chunk > 16 && chunk * gmax > gmax * gmax) chunk >>= 1;
     k_norm2(d, (int)np.size(), (int)norm2_need_doubles(gmax, chunk), chunk, ctx->stream);
   }
   ts.run(ctx);
