@@ -41,7 +41,8 @@ PEAK = {"fp64_mfma": 78.6e12, "fp32_mfma": 157.3e12, "bf16_mfma": 2.5e15, "fp64_
         "hbm": 8.0e12}
 # kernel family of the library -> kind of algorithmic work in the oracle's ledger
 FAMILY_KIND = {"gemm_sum": ("gemm",), "tsqr": ("qr",), "jacobi": ("svd",), "other": ("norm", "sumsq")}
-FAMILY_KERNELS = {"gemm_sum": ("gemm_sum_kernel", "gemm_tri_kernel", "gemm_tri_block_kernel", "chain3_kernel"),
+FAMILY_KERNELS = {"gemm_sum": ("gemm_sum_kernel", "gemm_tri_kernel", "gemm_tri_block_kernel", "chain3_kernel",
+                               "gform_kernel"),
                   "tsqr": ("tsqr_rb_kernel", "tsqr_kernel"),
                   "jacobi": ("jacobi_kernel", "jacobi_small_kernel")}
 STEP_NAMES = ("setup", "p1_row", "p1_col", "p1_mat", "p2_row", "p2_col", "p2_mat")
@@ -252,7 +253,7 @@ def measure_form(P, precision, steps, warmup, gold, peak_bulk):
         "kernel_ms_per_step": fam_ms,
         "roofline": {"kernel": dom, "bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(P.w.name[:2], dom, "fp64" if precision == "fp64" else "mixed"),
+                     "traffic": measured_traffic(P.w.name, dom, "fp64" if precision == "fp64" else precision),
                      "avg_launch_ms": avg_launch_s * 1e3, "launches_per_step": launches_per_step,
                      "flops_per_launch": kind_flops / max(launches_per_step, 1e-30),
                      "flops_source": f"oracle work ledger, kind {'+'.join(FAMILY_KIND.get(dom, ()))}"},
