@@ -1774,7 +1774,7 @@ void k_jacobi_small(const JacobiProb* probs, int n, int per_doubles, void* strea
 constexpr int kNorm2MaxG = 64;
 int norm2_max_dim() { return kNorm2MaxG; }
 static __host__ __device__ inline size_t norm2_need(int g, int chunk) {
-  return (size_t)g * g + (size_t)max(g * g, chunk * g) + 4 * (size_t)g;
+  return (size_t)g * g + (size_t)chunk * g + 4 * (size_t)g;
 }
 size_t norm2_need_doubles(int g, int chunk) { return norm2_need(g, chunk); }
 
@@ -1844,9 +1844,8 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   (void)frexp(amax, &ex);
   const double sc = ldexp(1.0, -ex);
   double* Gm = lds_dyn + (size_t)wave * per;
-  double* Qr = Gm + g * g;  // Qr[t g + i]: component i of Lanczos vector t
-  double* X = Qr;           // staging of `chunk` samples (rows, or columns) x g
-  double* Wv = Gm + g * g + max(g * g, chunk * g);
+  double* X = Gm + g * g;  // staging of `chunk` samples (rows, or columns) x g
+  double* Wv = X + chunk * g;
   double* Hv = Wv + g;
   double* Ta = Hv + g;
   double* Tb = Ta + g;
@@ -1910,45 +1909,58 @@ __global__ __launch_bounds__(256) void norm2_kernel(const Norm2Prob* __restrict_
   }
   team_sync<64>();
 
-  // ---- Lanczos: T = Q^T Gm Q, fixed start vector with unequal entries ----
-  double q = 0.0;
-  if (lane < g) {
-    const double u = (double)lane * 0.6180339887498949;
-    q = 1.0 + (u - floor(u));
-  }
-  q *= rsqrt(wave_sum(q * q));
-  double qp = 0.0, bprev = 0.0;
-  int nt = g;
-  for (int j = 0; j < g; ++j) {
-    if (lane < g) Qr[j * g + lane] = q;
+  // ---- Householder reduction of Gm to tridiagonal form T (diagonal Ta,
+  //      subdiagonal Tb): g - 2 reflectors, each applied to the trailing block
+  //      as A <- A - v w^T - w v^T with p = beta A v, w = p - (beta/2)(p.v) v.
+  //      Backward stable, so lambda_max(T) = lambda_max(Gm) to rounding. ----
+  double* Vv = Wv;
+  double* Ww = Hv;
+  for (int k = 0; k + 2 < g; ++k) {
+    const double xi = (lane > k && lane < g) ? Gm[lane + k * g] : 0.0;  // column k below the diagonal
+    const double nx2 = wave_sum(xi * xi);
+    const double x0 = Gm[(k + 1) + k * g];
+    if (lane == 0) Ta[k] = Gm[k + k * g];
+    if (!(nx2 > 0.0)) {  // already reduced (uniform across the wavefront)
+      if (lane == 0) Tb[k] = 0.0;
+      continue;
+    }
+    const double nx = sqrt(nx2);
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    const double vi = lane == k + 1 ? xi - alpha : xi;
+    const double beta = 1.0 / (nx2 - alpha * x0);  // 2 / (v.v)
+    if (lane == 0) Tb[k] = alpha;
+    if (lane < g) Vv[lane] = vi;
     team_sync<64>();
-    double w = 0.0;
-    if (lane < g) w = lds_dot(Gm + lane, g, Qr + j * g, 1, g);  // Gm symmetric: column access
-    const double al = wave_sum(w * q);
-    w -= al * q + bprev * qp;
-    for (int pass = 0; pass < 2; ++pass) {
-      if (lane < g) Wv[lane] = w;
-      team_sync<64>();
-      if (lane <= j) Hv[lane] = lds_dot(Wv, 1, Qr + lane * g, 1, g);  // stride g (odd or not) across lanes
-      team_sync<64>();
-      if (lane < g) w -= lds_dot(Hv, 1, Qr + lane, g, j + 1);
-      team_sync<64>();
+    const int L = g - k - 1;
+    double pi = 0.0;
+    if (lane > k && lane < g) pi = beta * lds_dot(Gm + lane + (k + 1) * g, g, Vv + k + 1, 1, L);
+    const double kc = 0.5 * beta * wave_sum(pi * vi);
+    if (lane < g) Ww[lane] = pi - kc * vi;
+    team_sync<64>();
+    for (int e0 = lane; e0 < L * L; e0 += 8 * 64) {
+      double gv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 64 * u;
+        const int a = k + 1 + e % L, b = k + 1 + e / L;
+        gv[u] = e < L * L ? Gm[a + b * g] - (Vv[a] * Ww[b] + Ww[a] * Vv[b]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 64 * u;
+        if (e < L * L) Gm[(k + 1 + e % L) + (k + 1 + e / L) * g] = gv[u];
+      }
     }
-    const double bt = sqrt(wave_sum(w * w));
-    if (lane == 0) {
-      Ta[j] = al;
-      Tb[j] = bt;
-    }
-    // an invariant subspace (or the whole space) is reached; a residual at
-    // the rounding level moves the eigenvalues by no more than itself
-    if (j + 1 == g || !(bt > 0x1p-60)) {
-      nt = j + 1;
-      break;
-    }
-    qp = q;
-    q = w / bt;
-    bprev = bt;
+    team_sync<64>();
   }
+  if (lane == 0) {
+    if (g >= 2) {
+      Ta[g - 2] = Gm[(g - 2) + (g - 2) * g];
+      Tb[g - 2] = Gm[(g - 1) + (g - 2) * g];
+    }
+    Ta[g - 1] = Gm[(g - 1) + (g - 1) * g];
+  }
+  const int nt = g;
   team_sync<64>();
 
   // ---- lambda_max(T) by multisection with Sturm counts ----
