@@ -190,7 +190,11 @@ struct FillItem {
 };
 
 // launchers (descriptor arrays are device pointers)
-void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, int nouts, int prec, void* stream);
+// workgroups of the grouped products: one per output, or (work non-null,
+// pairs output / first tile) one per run of kGemmTilesPerGroup tiles
+constexpr int kGemmTilesPerGroup = 16;
+void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* work, int ngroups, int prec,
+                void* stream);
 // prec 1: the products run on FP32 MFMA (operands rounded to FP32, FP32
 // accumulation, FP64 storage); 0: FP64 MFMA
 void k_gemm_tri(const TriOut* outs, const int32_t* tiles, int ntiles, const TriFamily& fam, int prec, void* stream);

@@ -162,18 +162,24 @@ __device__ __forceinline__ void mfma_span(typename Mfma16<P>::acc_t& acc, int K,
   }
 }
 
-// One workgroup per output; its 16 x 16 tiles are dealt to the four
+// One workgroup per output, or per run of kGemmTilesPerGroup tiles of a
+// large output (work[2 g] = output, work[2 g + 1] = first tile; null work:
+// workgroup g takes output g whole); the tiles are dealt to the four
 // wavefronts (tile w, w + 4, ...), i fastest, and each tile sums all terms.
 template <int P>
 __global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict__ outs,
-                                                       const GemmTerm* __restrict__ terms) {
+                                                       const GemmTerm* __restrict__ terms,
+                                                       const int32_t* __restrict__ work) {
   using M = Mfma16<P>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const GemmOut o = outs[blockIdx.x];
+  const int oi = work ? work[2 * blockIdx.x] : (int)blockIdx.x;
+  const int tfirst = work ? work[2 * blockIdx.x + 1] : 0;
+  const GemmOut o = outs[oi];
   if (o.m <= 0 || o.n <= 0 || (o.t0 == o.t1 && o.beta)) return;
-  const int mt = (o.m + 15) / 16, ntile = mt * ((o.n + 15) / 16);
+  const int mt = (o.m + 15) / 16;
+  const int tend = work ? min(mt * ((o.n + 15) / 16), tfirst + kGemmTilesPerGroup) : mt * ((o.n + 15) / 16);
   const int r = lane & 15, q = lane >> 4;
-  for (int tile = wave; tile < ntile; tile += 4) {
+  for (int tile = tfirst + wave; tile < tend; tile += 4) {
     const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
     typename M::acc_t acc = M::zero();
     const int i = i0 + r, j = j0 + r;
@@ -222,11 +228,12 @@ __global__ __launch_bounds__(256) void gemm_sum_kernel(const GemmOut* __restrict
   }
 }
 
-void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, int nouts, int prec, void* stream) {
-  if (nouts <= 0) return;
+void k_gemm_sum(const GemmOut* outs, const GemmTerm* terms, const int32_t* work, int ngroups, int prec,
+                void* stream) {
+  if (ngroups <= 0) return;
   auto k = prec == 1 ? gemm_sum_kernel<1> : prec == 2 ? gemm_sum_kernel<2> : prec == 3 ? gemm_sum_kernel<3>
                                                                                       : gemm_sum_kernel<0>;
-  hipLaunchKernelGGL(k, dim3(nouts), dim3(256), 0, (hipStream_t)stream, outs, terms);
+  hipLaunchKernelGGL(k, dim3(ngroups), dim3(256), 0, (hipStream_t)stream, outs, terms, work);
   HIP_OK(hipGetLastError());
 }
 

@@ -471,13 +471,34 @@ void GemmBatch::run(h2_ctx* ctx) {
     return;
   }
   // outputs and terms written straight into pinned staging, one copy; the
-  // kernel deals each output's tiles to its own workgroup
+  // kernel deals each output's tiles to its own workgroup, or, when some
+  // output has more than kGemmTilesPerGroup tiles, to one workgroup per run
+  // of that many tiles (a list of output / first-tile pairs)
+  int64_t ngroups = 0;
+  bool split = false;
+  for (const GemmOut& o : outs) {
+    const int64_t tiles = (int64_t)((std::max(o.m, 0) + 15) / 16) * ((std::max(o.n, 0) + 15) / 16);
+    ngroups += std::max<int64_t>(1, (tiles + kGemmTilesPerGroup - 1) / kGemmTilesPerGroup);
+    split = split || tiles > kGemmTilesPerGroup;
+  }
   const size_t so = outs.size() * sizeof(GemmOut), st = std::max<size_t>(terms.size(), 1) * sizeof(GemmTerm);
-  const size_t o_t = (so + 255) & ~(size_t)255;
-  char* h = stage_alloc(ctx, o_t + st);
+  const size_t o_t = (so + 255) & ~(size_t)255, o_w = o_t + ((st + 255) & ~(size_t)255);
+  const size_t sw = split ? (size_t)ngroups * 2 * sizeof(int32_t) : 0;
+  char* h = stage_alloc(ctx, o_w + sw);
   std::memcpy(h, outs.data(), so);
   if (!terms.empty()) std::memcpy(h + o_t, terms.data(), terms.size() * sizeof(GemmTerm));
-  char* dev = (char*)stage_launch(ctx, h, o_t + st);
+  if (split) {
+    int32_t* w = (int32_t*)(h + o_w);
+    for (size_t i = 0; i < outs.size(); ++i) {
+      const GemmOut& o = outs[i];
+      const int tiles = ((std::max(o.m, 0) + 15) / 16) * ((std::max(o.n, 0) + 15) / 16);
+      for (int t0 = 0; t0 < std::max(tiles, 1); t0 += kGemmTilesPerGroup) {
+        *w++ = (int32_t)i;
+        *w++ = t0;
+      }
+    }
+  }
+  char* dev = (char*)stage_launch(ctx, h, o_w + sw);
   // algorithmic work: 2 m n k per term; bytes: operands read once, C written
   double flops = 0, bytes = 0;
   const double es = prec ? 4.0 : 8.0;
@@ -491,7 +512,8 @@ void GemmBatch::run(h2_ctx* ctx) {
     }
   }
   LaunchTimer lt(ctx, KK_GEMM, flops, bytes);
-  k_gemm_sum((GemmOut*)dev, (GemmTerm*)(dev + o_t), (int)outs.size(), prec, ctx->stream);
+  k_gemm_sum((GemmOut*)dev, (GemmTerm*)(dev + o_t), split ? (int32_t*)(dev + o_w) : nullptr,
+             split ? (int)ngroups : (int)outs.size(), prec, ctx->stream);
   outs.clear();
   terms.clear();
 }
