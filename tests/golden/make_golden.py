@@ -1,10 +1,11 @@
 """Write the oracle's results on a full-size workload to <workload>_oracle.json.
 
 Calls only oracle/ and workloads.py.  Run:
-    python tests/golden/make_golden.py c2      (or c3, dlp, or c4)
+    python tests/golden/make_golden.py c2      (or c3, dlp, c5s, or c4)
 
 dlp is the double-layer recipe at n = 49152 (the oracle's memory at
-n = 110592 exceeds what the generating host holds).
+n = 110592 exceeds what the generating host holds); c5s is the recipe of
+the cube workload (1/r, k = 64) at n = 16384.
 
 For the single-product workloads (c2, c3, dlp) the file holds
   - the rank profiles of both phases (row and column bases);
@@ -39,7 +40,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle as O  # noqa: E402
 import workloads as W  # noqa: E402
 
-NAMES = {"c2": W.C2, "c3": W.C3, "dlp": W.C6S}
+NAMES = {"c2": W.C2, "c3": W.C3, "dlp": W.C6S, "c5s": W.C5S}
 PROBE_SEED, SKETCH_SEED, INDEX_SEED, POWER_SEED = 101, 103, 102, 104
 NPROBE = 32
 POWER_STEPS = 20

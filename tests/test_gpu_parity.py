@@ -182,7 +182,7 @@ def test_exact_without_truncation(name):
     assert relF(dense_of(Z, tree.n), XY) < 1e-12
 
 
-FULL = {"c2": W.C2, "c3": W.C3, "dlp": W.C6S}
+FULL = {"c2": W.C2, "c3": W.C3, "dlp": W.C6S, "c5s": W.C5S}
 
 
 def power_eps2(Z, X, Y, n, seed, steps):
@@ -240,8 +240,9 @@ def sketch_errors(M, gold, key, n):
 
 @pytest.mark.parametrize("key", list(FULL))
 def test_workload_full_size(key):
-    """The 2-D workload at n = 16384, the sphere workload at n = 131072 and
-    the double-layer workload at n = 49152 against the stored oracle results:
+    """The 2-D workload at n = 16384, the sphere workload at n = 131072, the
+    double-layer workload at n = 49152 and the cube workload's recipe (1/r,
+    k = 64, G's ranks up to 165) at n = 16384 against the stored oracle results:
     rank profiles of both phases; G and Z
     through 32 seeded probes over all n entries (two-sided sketch, relative
     Frobenius <= 1e-10 overall and per probe, column norms to 1e-10);

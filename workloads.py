@@ -111,7 +111,12 @@ C6 = Workload("dlp_cube_n110592", 60, 110592, 3, "cube_surface", 64, 2.0, 3, "dl
 C6S = Workload("dlp_cube_n49152", 61, 49152, 3, "cube_surface", 64, 2.0, 3, "dlp", "dlp", 1e-4,
                "cube surface, double-layer kernel, X = Y (not symmetric)")
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C5, C6, C6S)}
+# The recipe of c5 at n = 16384 (leaf 128, order 4: k = 64): the size at which
+# the oracle's results are stored for parity, with G's ranks up to 165.
+C5S = Workload("c5_cube_inv_n16384", 5, 16384, 3, "uniform", 128, 2.0, 4, "inv", "inv", 1e-5,
+               "unit cube volume, X = Y, k = 64")
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C5, C5S, C6, C6S)}
 
 
 def batched_instances(count: int = 64):
