@@ -231,3 +231,39 @@ def test_handles_outlive_their_context():
     del G
     del X, Y
     assert count[1] == count[0]
+
+
+def test_batched_call_with_a_failing_instance():
+    """A batched call runs its instances concurrently on lane contexts; an
+    instance that fails validation inside phase 1 (X and Y of different
+    ranks) fails the whole call with every output handle cleared, and the
+    next batched call on the same context gives the results of
+    single-product calls bit for bit."""
+    h2 = _h2()
+    c = h2.Context(0)
+    trees, xs, x4 = [], [], None
+    for i, n in enumerate((600, 900, 1200, 1500, 700, 1100)):
+        pts = W.make_points(70 + i, n, 2, "uniform")
+        T = h2.Tree(c, pts, 32, 1.0)
+        trees.append(T)
+        xs.append(h2.Matrix.kernel(c, T, "log", 3))
+        if i == 3:
+            x4 = h2.Matrix.kernel(c, T, "log", 4)  # rank 16 against rank 9
+    ys = list(xs)
+    ys[3] = x4
+    _say("[gpu] batched call with one failing instance")
+    with pytest.raises(h2.H2Error):
+        h2.h2_mul_intermediate(c, xs, ys, 1e-6)
+    torch.cuda.synchronize()
+    _say("[gpu] batched call after the failure")
+    Gs = h2.h2_mul_intermediate(c, xs, xs, 1e-6)
+    Zs = h2.h2_recompress(c, Gs, [h2.Matrix.zero(c, T) for T in trees], 1e-6)
+    torch.cuda.synchronize()
+    for T, X, G, Z in zip(trees, xs, Gs, Zs):
+        G1 = h2.h2_mul_intermediate(c, X, X, 1e-6)
+        Z1 = h2.h2_recompress(c, G1, h2.Matrix.zero(c, T), 1e-6)
+        torch.cuda.synchronize()
+        assert list(G.ranks(0)) == list(G1.ranks(0)) and list(Z.ranks(1)) == list(Z1.ranks(1))
+        n = T.n
+        assert np.array_equal(dense_of(Z, n), dense_of(Z1, n))
+        assert np.array_equal(dense_of(G, n), dense_of(G1, n))
