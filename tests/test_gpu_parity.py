@@ -589,6 +589,34 @@ def test_update_of_nonzero_target(name):
         assert e_or < 1e-10 and e_xy <= eps, label
 
 
+def test_level_factor_with_nonzero_target():
+    """Level-dependent tolerances (zeta = 0.5) together with Z != 0 (the old
+    Z a kernel matrix of the 2-D case): the kept ranges of the old bases and
+    the level's tolerance at every truncation, against the oracle with the
+    same old Z and level factor."""
+    h2 = _h2()
+    name, zeta = "2d", 0.5
+    n, d, leaf, order, kx, ky, eta, seed, dist, eps = CASES[name]
+    pts, tree, Xo, Yo, _, _, _, _ = oracle_case(name)
+    bt = O.BlockTree(tree, tree, eta)
+    c = h2.Context(0)
+    c.set_level_factor(zeta)
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order)
+    Y = h2.Matrix.kernel(c, T, ky, order)
+    Zg = h2.Matrix.kernel(c, T, ky, order)  # the old Z: a copy of Y
+    _say(f"[gpu] level factor {zeta} with a non-zero target: case={name}")
+    G = h2.h2_mul_intermediate(c, X, Y, eps)
+    h2.h2_recompress(c, G, Zg, eps)
+    torch.cuda.synchronize()
+    q1, q2 = O.multiply(Xo, Yo, bt, eps, Zold=Yo, zeta=zeta)
+    nc = tree.nclusters
+    assert list(G.ranks(0)) == [q1.row.Q.rank[t] for t in range(nc)]
+    assert list(Zg.ranks(0)) == [q2.row.Q.rank[t] for t in range(nc)]
+    assert list(Zg.ranks(1)) == [q2.col.Q.rank[t] for t in range(nc)]
+    assert relF(dense_of(Zg, n), q2.Z.dense()) < 1e-10
+
+
 @pytest.mark.parametrize("phase,launches", [(1, 3), (1, 40), (2, 5), (2, 15)])
 def test_context_usable_after_failure_mid_pass(phase, launches):
     """A host-side failure in the middle of a pass (injected before a launch,
