@@ -47,11 +47,7 @@ static void check_precision(int prec, double eps) {
 // is ordered after the earlier ones on the context stream, and the auxiliary
 // stream's work of a call is ordered after the context stream's work queued
 // before it.
-static void begin_call(h2_ctx* ctx) {
-  for (h2_ctx* c = ctx; c; c = c->aux) c->ws.reset();
-  for (h2_ctx* l : ctx->lanes)
-    for (h2_ctx* c = l; c; c = c->aux) c->ws.reset();
-}
+static void begin_call(h2_ctx* ctx) { pool_idle_memory(ctx); }
 
 // Runs body(lane, i) for the instances i = 0..count-1 of a batched call, at
 // most kBatchLanes at a time, each lane on its own host thread, stream and
@@ -247,6 +243,7 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
     need_device(ctx);
     begin_call(ctx);
     auto one = [&](h2_ctx* c, int i) {
+      if (count > 1) rewind_workspaces(c);
       auto* G = new h2_product();
       try {
         phase1(c, X[i], Y[i], eps, (int)prec, G);
@@ -320,11 +317,17 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
     need_device(ctx);
     begin_call(ctx);
     if (count == 1 || ctx->root) {
-      for (int i = 0; i < count; ++i) phase2(ctx, G[i], Z[i], eps, (int)prec);
+      for (int i = 0; i < count; ++i) {
+        if (count > 1) rewind_workspaces(ctx);
+        phase2(ctx, G[i], Z[i], eps, (int)prec);
+      }
     } else {
       std::vector<int64_t> w(count);
       for (int i = 0; i < count; ++i) w[i] = G[i]->c.bt ? (int64_t)G[i]->c.bt->nblocks() : 0;
-      run_lanes(ctx, count, w, [&](h2_ctx* c, int i) { phase2(c, G[i], Z[i], eps, (int)prec); });
+      run_lanes(ctx, count, w, [&](h2_ctx* c, int i) {
+        rewind_workspaces(c);
+        phase2(c, G[i], Z[i], eps, (int)prec);
+      });
     }
   });
 }

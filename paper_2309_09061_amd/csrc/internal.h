@@ -423,6 +423,17 @@ struct Arena {
   ~Arena();
 };
 
+// Scratch of one scope on one context: allocated like the workspace, its
+// chunks go back to that context's cache when the scope ends (or at
+// reset()), where only the same context takes them again, after the work
+// already queued on its stream.  Per-level temporaries live here, so that a
+// pass holds one level's scratch at a time rather than the sum over levels.
+struct ScopedArena : Arena {
+  explicit ScopedArena(h2_ctx* c) { ctx = c; }
+  ScopedArena(const ScopedArena&) = delete;
+  ScopedArena& operator=(const ScopedArena&) = delete;
+};
+
 }  // namespace h2
 
 namespace h2 {
@@ -451,6 +462,13 @@ struct h2_ctx {
   // inside an allocator callback): merged into `cache` before it is searched
   std::mutex ret_mu;
   std::vector<std::pair<char*, size_t>> returned;
+  // root contexts: idle chunks of every context of the family (the root,
+  // its auxiliary chain and its lanes), pooled at the start of each call
+  // once the previous call's work is ordered before the root stream; any
+  // context of the family takes from it, and it is handed back to the
+  // allocator when an allocation fails
+  std::mutex pool_mu;
+  std::vector<std::pair<char*, size_t>> pool;
   h2_ctx* root = nullptr;              // auxiliary contexts: the context they belong to
   // references on a root context: the caller's (dropped by h2_ctx_destroy)
   // plus one per handle arena holding its memory; the last drop deletes it
@@ -692,6 +710,14 @@ constexpr double kBlockRtol = 1e-12;
 
 // drops a reference on a root context; the last one deletes it
 void ctx_unref(h2_ctx* root);
+// start of a call on a root context (the previous call's work is ordered
+// before its stream): every context of the family rewinds its workspace and
+// hands its idle chunks to the root's pool
+void pool_idle_memory(h2_ctx* root);
+// start of one instance of a batched call on ctx: ctx and its auxiliary
+// chain rewind their workspaces (the previous instance's work on them is
+// ordered before ctx's stream)
+void rewind_workspaces(h2_ctx* ctx);
 
 // device memory of a context: the caller's allocator callbacks when given,
 // else the HIP runtime

@@ -25,7 +25,8 @@ static constexpr double kKeptRtol = 1e-12;
 
 void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, Arena& keep, KeptOut& out) {
   const int n = (int)items.size();
-  Arena& ws = ctx->ws;
+  Arena& ws = ctx->ws;  // R_K P (kept by the caller)
+  ScopedArena tmp(ctx);  // everything else
   out.k1.assign(n, 0);
   out.k2.assign(n, 0);
   out.Q.assign(n, nullptr);
@@ -35,7 +36,7 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
   g.prec = ctx->prec;
   TsqrBatch ts;
   JacobiBatch jb;
-  int32_t* rk = ws.get<int32_t>(2 * n);  // [k1 | k2] per item
+  int32_t* rk = tmp.get<int32_t>(2 * n);  // [k1 | k2] per item
   dev_zero(rk, sizeof(int32_t) * 2 * n, ctx->stream);
   std::vector<double*> Vp(n, nullptr), Yq(n, nullptr), tau(n, nullptr), RYq(n, nullptr), U(n, nullptr);
   std::vector<double*> KQ(n, nullptr);
@@ -43,9 +44,9 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
     if (it.m == 0 || it.kc == 0) continue;
-    double* Rv = ws.get<double>((size_t)it.kc * it.kc);
-    Vp[i] = ws.get<double>((size_t)it.kc * it.kc);
-    double* sg = ws.get<double>(it.kc);
+    double* Rv = tmp.get<double>((size_t)it.kc * it.kc);
+    Vp[i] = tmp.get<double>((size_t)it.kc * it.kc);
+    double* sg = tmp.get<double>(it.kc);
     ts.add(it.K, it.ldk, it.m, it.kc, false, Rv, it.kc);
     jb.add(Rv, it.kc, std::min(it.kc, it.m), it.kc, Vp[i], it.kc, sg, rk + i, 0.0, kKeptRtol, nullptr, 1);
   }
@@ -56,13 +57,13 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
     if (!Vp[i]) continue;
-    Yq[i] = ws.get<double>((size_t)it.m * it.kc);
-    tau[i] = ws.get<double>(it.kc);
-    RYq[i] = ws.get<double>((size_t)it.kc * it.kc);
+    Yq[i] = tmp.get<double>((size_t)it.m * it.kc);
+    tau[i] = tmp.get<double>(it.kc);
+    RYq[i] = tmp.get<double>((size_t)it.kc * it.kc);
     g.out(Yq[i], it.m, it.m, it.kc);
     g.term(it.K, it.ldk, false, Vp[i], it.kc, false, it.kc);
     qr.add(Yq[i], it.m, it.m, it.kc, tau[i], RYq[i], it.kc, std::min(it.m, it.kc));
-    KQ[i] = ws.get<double>((size_t)it.m * it.kc);  // K, to become Q_K^* K
+    KQ[i] = tmp.get<double>((size_t)it.m * it.kc);  // K, to become Q_K^* K
     g64.out(KQ[i], it.m, it.m, it.kc);
     g64.copy(it.K, it.ldk, false, it.kc);
   }
@@ -80,9 +81,9 @@ void kept_compress(h2_ctx* ctx, const std::vector<KeptItem>& items, double eps, 
   for (int i = 0; i < n; ++i) {
     const KeptItem& it = items[i];
     if (it.m == 0 || it.nc == 0) continue;
-    double* Rt = ws.get<double>((size_t)it.m * it.m);
-    U[i] = ws.get<double>((size_t)it.m * it.m);
-    double* sg2 = ws.get<double>(it.m);
+    double* Rt = tmp.get<double>((size_t)it.m * it.m);
+    U[i] = tmp.get<double>((size_t)it.m * it.m);
+    double* sg2 = tmp.get<double>(it.m);
     ts.add(it.C, it.ldc, it.nc, it.m, true, Rt, it.m, 0, rk + i);
     jb.add(Rt, it.m, std::min(it.nc, it.m), it.m, U[i], it.m, sg2, rk + n + i, eps, 0.0, rk + i, 1,
            ctx->rank_rule);

@@ -182,7 +182,9 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
   std::vector<const double*> sig = nb.run(ctx);
   std::vector<double*> Z(ncl, nullptr);
   std::vector<int> zr(ncl, 0);
+  ScopedArena lvl(ctx);  // one level's stacked weights at a time
   for (int l = 0; l <= D; ++l) {
+    lvl.reset();
     TsqrBatch ts;
     for (int s = T.first(l); s < T.first(l + 1); ++s) {
       const int32_t* bl;
@@ -194,7 +196,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       Z[s] = ws.get<double>((size_t)k * k);
       zr[s] = std::min(N, k);
       if (N == 0) continue;
-      double* Gh = ws.get<double>((size_t)N * k);
+      double* Gh = lvl.get<double>((size_t)N * k);
       int row = 0;
       if (l > 0 && zr[TreeH::parent(s)] > 0) {
         int zp = zr[TreeH::parent(s)];
@@ -246,6 +248,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       }
   }
   for (int l = D; l >= 0; --l) {
+    lvl.reset();  // B_t, V_X and the scaled remainder of one level at a time
     const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
     const bool leaf = l == D;
     std::vector<int> rows(nc), ncols(nc), kk1(nc);
@@ -257,8 +260,8 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       int m = leaf ? (int)T.size[t] : out.Q.rank[2 * t + 1] + out.Q.rank[2 * t + 2];
       rows[i] = m;
       int nC = (int)Cb[t].size();
-      Bt[i] = ws.get<double>((size_t)std::max(m, 1) * k * std::max(nC, 1));
-      VXw[i] = ws.get<double>((size_t)std::max(m, 1) * k);
+      Bt[i] = lvl.get<double>((size_t)std::max(m, 1) * k * std::max(nC, 1));
+      VXw[i] = lvl.get<double>((size_t)std::max(m, 1) * k);
       if (leaf) {
         for (int j = 0; j < nC; ++j) {
           int b = Cb[t][j], s = X.vcol(b);
@@ -316,7 +319,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       int nco = 0;
       for (int b : Cb[t]) nco += zr[X.vcol(b)];
       ncols[i] = nco;
-      Vr[i] = ws.get<double>((size_t)m * std::max(nco, 1));
+      Vr[i] = lvl.get<double>((size_t)m * std::max(nco, 1));
       int col = 0;
       for (size_t j = 0; j < Cb[t].size(); ++j) {
         int s = X.vcol(Cb[t][j]);
@@ -520,6 +523,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     std::vector<const double*> tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
     std::vector<int64_t> lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
     TriFamily fAA{};
+    ScopedArena tmp(a);  // the triple sums of one level at a time
     const int32_t* d_bt = nullptr;    // (t, r) per block of T^XY, for the fused launches
     const int32_t* d_tptr = nullptr;  // triple ranges per block of T^XY
     for (int l = T.depth; l >= 0; --l) {
@@ -644,18 +648,19 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       tna.fam = family(d_tri, upload(a, tAr), upload(a, lAr), d_tY, d_lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
       tan_.fam = family(d_tri, d_tX, d_lX, upload(a, tAc), upload(a, lAc), TK_AN, true, nullptr);  // S_X A^c^*
       taa.prec = tna.prec = tan_.prec = prec;
+      tmp.reset();
       std::vector<double*> TAA(b1 - b0, nullptr), TNA(b1 - b0, nullptr), Mm(b1 - b0, nullptr);
       double f_aa = 0, f_na = 0, f_an = 0;
       for (int b = b0; b < b1; ++b) {
         const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
         S[b] = G->mem_nf.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1));
         if (cnt(b, TK_AA)) {
-          TAA[i] = ws.get<double>((size_t)k * k);
+          TAA[i] = tmp.get<double>((size_t)k * k);
           taa.out(TAA[i], k, k, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
           f_aa += 2.0 * k * k * k * cnt(b, TK_AA);
         }
         if (cnt(b, TK_NA) && kt > 0) {
-          TNA[i] = ws.get<double>((size_t)kt * k);
+          TNA[i] = tmp.get<double>((size_t)kt * k);
           tna.out(TNA[i], kt, kt, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
           f_na += 2.0 * kt * k * k * cnt(b, TK_NA);
         }
@@ -665,7 +670,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       for (int b = b0; b < b1; ++b) {
         const int i = b - b0, r = B.s[b], kr = col.Q.rank[r];
         if ((cnt(b, TK_AN) || TAA[i]) && kr > 0) {
-          Mm[i] = ws.get<double>((size_t)k * kr);
+          Mm[i] = tmp.get<double>((size_t)k * kr);
           g.out(Mm[i], k, k, kr);
           if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
           if (cnt(b, TK_AN)) {
@@ -717,7 +722,9 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   // bases); one fused launch per level, two grouped products where a rank
   // exceeds the fused kernel's 64
   Chain3Batch ch;
+  ScopedArena tmp(ctx);  // the two-step paths' middle products, one level at a time
   for (int l = 1; l <= T.depth; ++l) {
+    tmp.reset();
     const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
     std::vector<int> parent(b1 - b0, -1);
     for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
@@ -735,7 +742,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
                col.Q.tr_ld[r], true, true);
         continue;
       }
-      double* Pp = ws.get<double>((size_t)kt * kpr);
+      double* Pp = tmp.get<double>((size_t)kt * kpr);
       g.out(Pp, kt, kt, kpr);
       g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], kpt, false, kpt);
       wide.push_back({b, Pp});
@@ -755,6 +762,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   // dense inadmissible leaves: the nearfield products (already there) plus Q_t S Q^W_r^*
   {
     const int l = T.depth;
+    tmp.reset();
     std::vector<std::pair<int, double*>> wide;  // (block, Q_t S) of the two-step path
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (B.type[b] != BT_INADM) continue;
@@ -771,7 +779,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
                col.Q.leaf_ld[r], true, true);
         continue;
       }
-      double* QS = ws.get<double>((size_t)mt * kr);
+      double* QS = tmp.get<double>((size_t)mt * kr);
       g.out(QS, mt, mt, kr);
       g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], kt, false, kt);
       wide.push_back({b, QS});

@@ -93,7 +93,11 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   // ---- product total weights Z_t, top-down ----
   std::vector<double*> Zt(ncl, nullptr);
   std::vector<int> zr(ncl, 0);
+  // per-level temporaries (the stacked weights here, C_t and its factors in
+  // the sweep below): one level at a time
+  ScopedArena lvl(ctx);
   for (int l = 0; l <= D; ++l) {
+    lvl.reset();
     TsqrBatch ts;
     for (int t = T.first(l); t < T.first(l + 1); ++t) {
       int kt = Vb.rank[t];
@@ -110,7 +114,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         zr[t] = 0;
         continue;
       }
-      double* Gh = ws.get<double>((size_t)N * kt);
+      double* Gh = lvl.get<double>((size_t)N * kt);
       int row = 0;
       if (zp > 0) {
         int kp = Vb.rank[TreeH::parent(t)];
@@ -273,6 +277,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   out.RS.assign(nb, nullptr);
   out.RZ.assign(ncl, nullptr);
   for (int l = D; l >= 0; --l) {
+    lvl.reset();
     const int c0 = T.first(l), c1 = T.first(l + 1), nc = c1 - c0;
     const bool leaf = l == D;
     std::vector<int> m(nc), ncols(nc);
@@ -287,7 +292,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       }
       int o = 0;
       m[i] = out.Q.rank[2 * t + 1] + out.Q.rank[2 * t + 2];
-      Vh[i] = ws.get<double>((size_t)std::max(m[i], 1) * std::max(kt, 1));
+      Vh[i] = lvl.get<double>((size_t)std::max(m[i], 1) * std::max(kt, 1));
       for (int q = 1; q <= 2; ++q) {
         int ch = 2 * t + q, kc = out.Q.rank[ch];
         if (kc > 0) {
@@ -320,7 +325,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         }
       }
       ncols[i] = nco;
-      C[i] = ws.get<double>((size_t)std::max(m[i], 1) * std::max(nco, 1));
+      C[i] = lvl.get<double>((size_t)std::max(m[i], 1) * std::max(nco, 1));
       if (m[i] == 0) continue;
       if (zr[t] > 0) {
         g.out(C[i], m[i], m[i], zr[t]);
@@ -384,7 +389,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
           K = Kb->leaf[t];
           ldk = Kb->leaf_ld[t];
         } else if (m[i] > 0 && kold > 0) {
-          double* Kh = ws.get<double>((size_t)m[i] * kold);
+          double* Kh = lvl.get<double>((size_t)m[i] * kold);
           int o = 0;
           for (int q = 1; q <= 2; ++q) {
             int ch = 2 * t + q, kc = out.Q.rank[ch];
@@ -397,7 +402,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
           }
           K = Kh;
         }
-        double* Cw = ws.get<double>((size_t)std::max(m[i], 1) * std::max(ncols[i], 1));
+        double* Cw = lvl.get<double>((size_t)std::max(m[i], 1) * std::max(ncols[i], 1));
         if (m[i] > 0 && ncols[i] > 0) {
           g.out(Cw, m[i], m[i], ncols[i]);
           g.copy(C[i], m[i], false, ncols[i]);
@@ -417,14 +422,14 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       // SVD of C_t: R factor of C_t^*, one-sided Jacobi
       TsqrBatch ts;
       JacobiBatch jb;
-      int32_t* rk = ws.get<int32_t>(nc);
+      int32_t* rk = lvl.get<int32_t>(nc);
       dev_zero(rk, sizeof(int32_t) * nc, ctx->stream);
       for (int i = 0; i < nc; ++i) {
         if (m[i] == 0) continue;
         int p = std::min(ncols[i], m[i]);
-        Rt[i] = ws.get<double>((size_t)m[i] * m[i]);  // rows < p are written
-        U[i] = ws.get<double>((size_t)m[i] * m[i]);
-        sg[i] = ws.get<double>(m[i]);
+        Rt[i] = lvl.get<double>((size_t)m[i] * m[i]);  // rows < p are written
+        U[i] = lvl.get<double>((size_t)m[i] * m[i]);
+        sg[i] = lvl.get<double>(m[i]);
         ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
         jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, level_eps(ctx, eps, D, l), 0.0, nullptr, 1,
                ctx->rank_rule);

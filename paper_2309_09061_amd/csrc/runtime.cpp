@@ -13,6 +13,29 @@ namespace h2 {
 // ---------------------------------------------------------------------------
 static constexpr size_t kChunk = (size_t)64 << 20;
 
+static h2_ctx* root_of(h2_ctx* c) { return c->root ? c->root : c; }
+
+// index of the smallest chunk of `v` with at least `bytes`, or -1
+static int smallest_fit(const std::vector<std::pair<char*, size_t>>& v, size_t bytes) {
+  size_t best = (size_t)-1;
+  int bi = -1;
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].second >= bytes && v[i].second < best) {
+      best = v[i].second;
+      bi = (int)i;
+    }
+  return bi;
+}
+
+// the root pool's chunks back to the allocator; false if it was empty
+static bool pool_flush(h2_ctx* root) {
+  std::lock_guard<std::mutex> lock(root->pool_mu);
+  if (root->pool.empty()) return false;
+  for (auto& c : root->pool) ctx_free(root, c.first);
+  root->pool.clear();
+  return true;
+}
+
 void* ctx_malloc(h2_ctx* ctx, size_t bytes) {
   if (ctx && ctx->alloc_fn) {
     void* p = ctx->alloc_fn(bytes, ctx->alloc_user);
@@ -49,27 +72,39 @@ void* Arena::alloc(size_t bytes) {
     ++cur;
     used = 0;
   }
-  // take the smallest cached chunk that fits, else allocate
+  // the smallest chunk that fits from the context's own cache, else from
+  // the family's pool, else a new one (after handing the pool back to the
+  // allocator if the first attempt fails)
   if (ctx) {
     std::lock_guard<std::mutex> lock(ctx->ret_mu);
     for (auto& c : ctx->returned) ctx->cache.push_back(c);
     ctx->returned.clear();
   }
-  size_t best = (size_t)-1;
-  int bi = -1;
-  if (ctx)
-    for (size_t i = 0; i < ctx->cache.size(); ++i)
-      if (ctx->cache[i].second >= bytes && ctx->cache[i].second < best) {
-        best = ctx->cache[i].second;
-        bi = (int)i;
-      }
-  std::pair<char*, size_t> ch;
-  if (bi >= 0) {
-    ch = ctx->cache[bi];
-    ctx->cache.erase(ctx->cache.begin() + bi);
-  } else {
-    size_t sz = std::max(bytes, kChunk);
-    ch = {(char*)ctx_malloc(ctx, sz), sz};
+  std::pair<char*, size_t> ch{nullptr, 0};
+  if (ctx) {
+    const int bi = smallest_fit(ctx->cache, bytes);
+    if (bi >= 0) {
+      ch = ctx->cache[bi];
+      ctx->cache.erase(ctx->cache.begin() + bi);
+    }
+  }
+  if (!ch.first && ctx) {
+    h2_ctx* r = root_of(ctx);
+    std::lock_guard<std::mutex> lock(r->pool_mu);
+    const int bi = smallest_fit(r->pool, bytes);
+    if (bi >= 0) {
+      ch = r->pool[bi];
+      r->pool.erase(r->pool.begin() + bi);
+    }
+  }
+  if (!ch.first) {
+    const size_t sz = std::max(bytes, kChunk);
+    try {
+      ch = {(char*)ctx_malloc(ctx, sz), sz};
+    } catch (const Error&) {
+      if (!ctx || !pool_flush(root_of(ctx))) throw;
+      ch = {(char*)ctx_malloc(ctx, sz), sz};
+    }
   }
   chunks.push_back(ch);
   cur = chunks.size() - 1;
@@ -89,7 +124,28 @@ void Arena::release() {
   cur = used = total = 0;
 }
 
-static h2_ctx* root_of(h2_ctx* c) { return c->root ? c->root : c; }
+void pool_idle_memory(h2_ctx* root) {
+  std::vector<h2_ctx*> fam;
+  for (h2_ctx* c = root; c; c = c->aux) fam.push_back(c);
+  for (h2_ctx* l : root->lanes)
+    for (h2_ctx* c = l; c; c = c->aux) fam.push_back(c);
+  for (h2_ctx* c : fam) {
+    c->ws.release();
+    std::vector<std::pair<char*, size_t>> idle;
+    {
+      std::lock_guard<std::mutex> lock(c->ret_mu);
+      idle.swap(c->returned);
+    }
+    idle.insert(idle.end(), c->cache.begin(), c->cache.end());
+    c->cache.clear();
+    std::lock_guard<std::mutex> lock(root->pool_mu);
+    root->pool.insert(root->pool.end(), idle.begin(), idle.end());
+  }
+}
+
+void rewind_workspaces(h2_ctx* ctx) {
+  for (h2_ctx* c = ctx; c; c = c->aux) c->ws.reset();
+}
 
 void Arena::bind(h2_ctx* c) {
   if (ctx == c) return;
@@ -1015,6 +1071,8 @@ h2_ctx::~h2_ctx() {
   returned.clear();
   for (auto& c : cache) h2::ctx_free(this, c.first);
   cache.clear();
+  for (auto& c : pool) h2::ctx_free(this, c.first);
+  pool.clear();
   if (stage) h2::dev_free_host(stage);
   for (auto& c : prof_host) h2::dev_free_host(c.first);
   for (void* e : events) h2::dev_event_destroy(e);
