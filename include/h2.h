@@ -343,6 +343,18 @@ h2_status h2_set_rank_rule(h2_ctx* ctx, int rule);
  * for zeta outside (0, 1] or a NULL context. */
 h2_status h2_set_level_factor(h2_ctx* ctx, double zeta);
 
+/* Memory bound of the steps that take a tree level in runs: the sums over
+ * the triples of T^XY of blocks whose ranks exceed 64 (Section 3, eq. XY;
+ * Section 4), the projections E_t S F_r^* and Q_t S Q_r^* of G's couplings
+ * onto the blocks below them (eq. transfer), and phase 2's leaf-level C_t
+ * without an old Z (Section 6, eq. ct_leaf).  Each run holds at most `bytes`
+ * of device scratch (at least one block or cluster); results do not depend
+ * on the bound up to rounding.  Smaller bounds lower the peak device memory
+ * of a call at the cost of more, smaller launches.  bytes <= 0 restores the
+ * default of 4 GiB.  Applies to the later h2_mul_intermediate and
+ * h2_recompress calls on ctx.  H2_ERR_ARG for a NULL context. */
+h2_status h2_set_run_scratch(h2_ctx* ctx, int64_t bytes);
+
 /* Test hook for the error paths: the `launches`-th batched kernel launch that
  * the context's own host thread issues from now on (0 = the next one) fails
  * with H2_ERR_DEVICE before it is launched, as a host-side failure in the

@@ -464,6 +464,13 @@ h2_status h2_set_level_factor(h2_ctx* ctx, double zeta) {
   });
 }
 
+h2_status h2_set_run_scratch(h2_ctx* ctx, int64_t bytes) {
+  return guard([&] {
+    H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");
+    ctx->run_scratch = bytes <= 0 ? kRunScratchDefault : (size_t)bytes;
+  });
+}
+
 h2_status h2_debug_fail_after(h2_ctx* ctx, int launches) {
   return guard([&] {
     H2_REQUIRE(ctx, H2_ERR_ARG, "NULL context");

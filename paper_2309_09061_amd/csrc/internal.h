@@ -452,6 +452,8 @@ struct PendingLaunch {
 };
 }  // namespace h2
 
+constexpr size_t kRunScratchDefault = (size_t)4 << 30;
+
 struct h2_ctx {
   int device = -1;
   void* stream = nullptr;
@@ -484,6 +486,9 @@ struct h2_ctx {
   int prec = 0;                        // bulk precision of the running call
   int rank_rule = 0;                   // h2_rank_rule of the truncating SVDs
   double level_factor = 1.0;           // zeta: level l truncates at eps zeta^(depth - l)
+  // bound on the device scratch of one run of blocks or clusters in the
+  // steps that take a level in runs (h2_set_run_scratch)
+  size_t run_scratch = kRunScratchDefault;
   int profile = 0;                     // bit k: time the launches of kernel family k
   int fail_after = -1;                 // test hook: launches left before an injected failure (-1: off)
   h2_alloc_fn alloc_fn = nullptr;      // caller's device allocator (nullptr: hipMalloc / hipFree)

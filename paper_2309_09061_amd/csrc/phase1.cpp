@@ -182,10 +182,19 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
   std::vector<const double*> sig = nb.run(ctx);
   std::vector<double*> Z(ncl, nullptr);
   std::vector<int> zr(ncl, 0);
-  ScopedArena lvl(ctx);  // one level's stacked weights at a time
+  ScopedArena lvl(ctx);  // per-level temporaries
   for (int l = 0; l <= D; ++l) {
     lvl.reset();
+    // the stacked weights in runs of at most run_scratch bytes, each reduced
+    // to its R factors before the run's memory is reused
     TsqrBatch ts;
+    size_t pend = 0;
+    auto flush = [&] {
+      g.run(ctx);
+      ts.run(ctx);
+      lvl.reset();
+      pend = 0;
+    };
     for (int s = T.first(l); s < T.first(l + 1); ++s) {
       const int32_t* bl;
       int cnt;
@@ -196,7 +205,10 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       Z[s] = ws.get<double>((size_t)k * k);
       zr[s] = std::min(N, k);
       if (N == 0) continue;
+      const size_t e = 8 * (size_t)N * k;
+      if (pend > 0 && pend + e > ctx->run_scratch) flush();
       double* Gh = lvl.get<double>((size_t)N * k);
+      pend += e;
       int row = 0;
       if (l > 0 && zr[TreeH::parent(s)] > 0) {
         int zp = zr[TreeH::parent(s)];
@@ -214,8 +226,7 @@ static void induced_pass(h2_ctx* ctx, const View& X, const View& Y, double eps, 
       }
       ts.add(Gh, N, N, k, false, Z[s], k);
     }
-    g.run(ctx);
-    ts.run(ctx);
+    flush();
   }
   // S_{X,t's'} P_{s'} E_{Y,s'} for admissible blocks of X below the root
   const BlockTreeH& BX = X.bt();
@@ -424,6 +435,12 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     }
   });
   std::vector<std::vector<std::pair<int, double*>>> dn_of(T.ncl);  // leaf t: (r, block) by r
+  auto dense_block = [&](int t, int r) {
+    const auto& dl = dn_of[t];
+    auto it = std::lower_bound(dl.begin(), dl.end(), std::make_pair(r, (double*)nullptr));
+    H2_REQUIRE(it != dl.end() && it->first == r, H2_ERR_SHAPE, "dense leaf of T^XY without nearfield triple");
+    return it->second;
+  };
   h2_ctx* nf_ctx = aux_ctx(aux_ctx(ctx));
   G->mem_nf.bind(nf_ctx);
   const int k = uniform_rank(Xm->c.V);
@@ -523,7 +540,77 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     std::vector<const double*> tPS(nby, nullptr), tAr(nbx, nullptr), tAc(nby, nullptr);
     std::vector<int64_t> lPS(nby, k), lAr(nbx, 1), lAc(nby, 1);
     TriFamily fAA{};
-    ScopedArena tmp(a);  // the triple sums of one level at a time
+    ScopedArena tmp(a);  // the triple sums of one run of blocks at a time
+    // blocks [c0b, c1b) of one level whose ranks exceed the fused kernel's:
+    // the three triple sums, then S_b = TNA_b R^c_r^* + R_t Mm_b
+    auto unfused_run = [&](int c0b, int c1b, const TriFamily& fNA, const TriFamily& fAN) {
+      tmp.reset();
+      TriBatch taa, tna, tan_;
+      taa.fam = fAA;
+      tna.fam = fNA;
+      tan_.fam = fAN;
+      taa.prec = tna.prec = tan_.prec = prec;
+      const int nb = c1b - c0b;
+      std::vector<double*> TAA(nb, nullptr), TNA(nb, nullptr), Mm(nb, nullptr);
+      double f_aa = 0, f_na = 0, f_an = 0;
+      for (int b = c0b; b < c1b; ++b) {
+        const int i = b - c0b, kt = row.Q.rank[B.t[b]];
+        if (cnt(b, TK_AA)) {
+          TAA[i] = tmp.get<double>((size_t)k * k);
+          taa.out(TAA[i], k, k, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
+          f_aa += 2.0 * k * k * k * cnt(b, TK_AA);
+        }
+        if (cnt(b, TK_NA) && kt > 0) {
+          TNA[i] = tmp.get<double>((size_t)kt * k);
+          tna.out(TNA[i], kt, kt, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
+          f_na += 2.0 * kt * k * k * cnt(b, TK_NA);
+        }
+      }
+      taa.run(a, f_aa);
+      tna.run(a, f_na);
+      for (int b = c0b; b < c1b; ++b) {
+        const int i = b - c0b, r = B.s[b], kr = col.Q.rank[r];
+        if ((cnt(b, TK_AN) || TAA[i]) && kr > 0) {
+          Mm[i] = tmp.get<double>((size_t)k * kr);
+          g.out(Mm[i], k, k, kr);
+          if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
+          if (cnt(b, TK_AN)) {
+            tan_.out(Mm[i], k, k, kr, PT.tri_ptr[b], PT.tri_ptr[b + 1], TAA[i] != nullptr);
+            f_an += 2.0 * k * k * kr * cnt(b, TK_AN);
+          }
+        }
+      }
+      g.run(a);  // TAA R^c^* first (overwrites), then the AN triples accumulate
+      tan_.run(a, f_an);
+      // dense leaves (S[b] null) keep their coupling in the run's scratch
+      // and add Q_t S Q^W_r^* to their block at once
+      std::vector<double*> Sd(nb, nullptr), QS(nb, nullptr);
+      for (int b = c0b; b < c1b; ++b) {
+        const int i = b - c0b, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+        double* Sb = S[b] ? S[b] : (Sd[i] = tmp.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1)));
+        g.out(Sb, std::max(kt, 1), kt, kr);  // zero without terms
+        if (TNA[i]) g.term(TNA[i], kt, false, col.RXP[r], std::max(kr, 1), true, k);
+        if (Mm[i]) g.term(row.RXP[t], std::max(kt, 1), false, Mm[i], k, false, k);
+      }
+      g.run(a);
+      for (int b = c0b; b < c1b; ++b) {
+        const int i = b - c0b, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+        if (!Sd[i] || kt == 0 || kr == 0) continue;
+        const int mt = (int)T.size[t];
+        QS[i] = tmp.get<double>((size_t)mt * kr);
+        g.out(QS[i], mt, mt, kr);
+        g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, Sd[i], kt, false, kt);
+      }
+      g.run(a);
+      for (int b = c0b; b < c1b; ++b) {
+        const int i = b - c0b, t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
+        if (!QS[i]) continue;
+        const int mt = (int)T.size[t], nr = (int)T.size[r];
+        g.out(dense_block(t, r), mt, mt, nr, true);
+        g.term(QS[i], mt, false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
+      }
+      g.run(a);
+    };
     const int32_t* d_bt = nullptr;    // (t, r) per block of T^XY, for the fused launches
     const int32_t* d_tptr = nullptr;  // triple ranges per block of T^XY
     for (int l = T.depth; l >= 0; --l) {
@@ -575,17 +662,23 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
         const int c0 = T.first(l), nc = T.first(l + 1) - c0;
         const int bx0 = BX.lvl[l], nbxl = BX.lvl[l + 1] - bx0, by0 = BY.lvl[l], nbyl = BY.lvl[l + 1] - by0;
         const int nb = b1 - b0;
-        size_t total = 0;
+        size_t total = 0, total_adm = 0;
         double flops = 0, bytes = 0;
         for (int b = b0; b < b1; ++b) {
           const int kt = row.Q.rank[B.t[b]], kr = col.Q.rank[B.s[b]];
-          total += (size_t)std::max(kt, 1) * std::max(kr, 1);
+          const size_t e = (size_t)std::max(kt, 1) * std::max(kr, 1);
+          total += e;
+          if (B.type[b] == BT_ADM) total_adm += e;
           const double naa = cnt(b, TK_AA), nna = kt ? cnt(b, TK_NA) : 0, nan = kr ? cnt(b, TK_AN) : 0;
           flops += 2.0 * k * k * (k * naa + kt * nna + kr * nan) + 2.0 * kt * k * kr * ((nna > 0) + (naa + nan > 0)) +
                    (naa > 0 ? 2.0 * k * k * kr : 0.0);
           bytes += 8.0 * kt * kr;
         }
-        double* Sl = G->mem_nf.get<double>(total);
+        // couplings of admissible blocks stay in G; the others (subdivided
+        // blocks and dense leaves) are needed only until the top-down
+        // projections below, and live in the workspace
+        double* Sl = G->mem_nf.get<double>(std::max<size_t>(total_adm, 1));
+        double* Sw = ws.get<double>(std::max<size_t>(total - total_adm, 1));
         // the level's tables, packed into one upload
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         const size_t o_kc = al(4 * (size_t)nc), o_rr = o_kc + al(4 * (size_t)nc), o_rc = o_rr + al(8 * (size_t)nc),
@@ -604,10 +697,16 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
           hrr[i] = row.RXP[c0 + i];
           hrc[i] = col.RXP[c0 + i];
         }
-        for (int b = b0, off = 0; b < b1; ++b) {
+        for (int b = b0, off = 0, offw = 0; b < b1; ++b) {
           const int kt = row.Q.rank[B.t[b]], kr = col.Q.rank[B.s[b]];
-          S[b] = hs[b - b0] = Sl + off;
-          off += std::max(kt, 1) * std::max(kr, 1);
+          const int e = std::max(kt, 1) * std::max(kr, 1);
+          if (B.type[b] == BT_ADM) {
+            S[b] = hs[b - b0] = Sl + off;
+            off += e;
+          } else {
+            S[b] = hs[b - b0] = Sw + offw;
+            offw += e;
+          }
         }
         std::memcpy(h + o_ar, tAr.data() + bx0, 8 * (size_t)nbxl);
         std::memcpy(h + o_lar, lAr.data() + bx0, 8 * (size_t)nbxl);
@@ -643,51 +742,31 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
         k_gform(ga, nb, prec, a->stream);
         continue;
       }
-      TriBatch taa, tna, tan_;
-      taa.fam = fAA;
-      tna.fam = family(d_tri, upload(a, tAr), upload(a, lAr), d_tY, d_lY, TK_NA, false, nullptr);  // A_{t,s} S_Y
-      tan_.fam = family(d_tri, d_tX, d_lX, upload(a, tAc), upload(a, lAc), TK_AN, true, nullptr);  // S_X A^c^*
-      taa.prec = tna.prec = tan_.prec = prec;
-      tmp.reset();
-      std::vector<double*> TAA(b1 - b0, nullptr), TNA(b1 - b0, nullptr), Mm(b1 - b0, nullptr);
-      double f_aa = 0, f_na = 0, f_an = 0;
+      const TriFamily fNA = family(d_tri, upload(a, tAr), upload(a, lAr), d_tY, d_lY, TK_NA, false,
+                                   nullptr);  // A_{t,s} S_Y
+      const TriFamily fAN = family(d_tri, d_tX, d_lX, upload(a, tAc), upload(a, lAc), TK_AN, true,
+                                   nullptr);  // S_X A^c^*
+      // couplings: admissible blocks in G, subdivided blocks in the
+      // workspace until the top-down projections, dense leaves not stored
+      // (folded into their blocks by the run that forms them)
       for (int b = b0; b < b1; ++b) {
-        const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-        S[b] = G->mem_nf.get<double>((size_t)std::max(kt, 1) * std::max(kr, 1));
-        if (cnt(b, TK_AA)) {
-          TAA[i] = tmp.get<double>((size_t)k * k);
-          taa.out(TAA[i], k, k, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
-          f_aa += 2.0 * k * k * k * cnt(b, TK_AA);
-        }
-        if (cnt(b, TK_NA) && kt > 0) {
-          TNA[i] = tmp.get<double>((size_t)kt * k);
-          tna.out(TNA[i], kt, kt, k, PT.tri_ptr[b], PT.tri_ptr[b + 1]);
-          f_na += 2.0 * kt * k * k * cnt(b, TK_NA);
-        }
+        const int kt = row.Q.rank[B.t[b]], kr = col.Q.rank[B.s[b]];
+        const size_t e = (size_t)std::max(kt, 1) * std::max(kr, 1);
+        S[b] = B.type[b] == BT_ADM ? G->mem_nf.get<double>(e) : B.type[b] == BT_INADM ? nullptr : ws.get<double>(e);
       }
-      taa.run(a, f_aa);
-      tna.run(a, f_na);
-      for (int b = b0; b < b1; ++b) {
-        const int i = b - b0, r = B.s[b], kr = col.Q.rank[r];
-        if ((cnt(b, TK_AN) || TAA[i]) && kr > 0) {
-          Mm[i] = tmp.get<double>((size_t)k * kr);
-          g.out(Mm[i], k, k, kr);
-          if (TAA[i]) g.term(TAA[i], k, false, col.RXP[r], kr, true, k);
-          if (cnt(b, TK_AN)) {
-            tan_.out(Mm[i], k, k, kr, PT.tri_ptr[b], PT.tri_ptr[b + 1], TAA[i] != nullptr);
-            f_an += 2.0 * k * k * kr * cnt(b, TK_AN);
-          }
+      // the level's blocks in runs whose scratch fits in run_scratch
+      for (int cb0 = b0, cb1; cb0 < b1; cb0 = cb1) {
+        size_t need = 0;
+        for (cb1 = cb0; cb1 < b1; ++cb1) {
+          const int kt = row.Q.rank[B.t[cb1]], kr = col.Q.rank[B.s[cb1]];
+          size_t e = 8 * ((size_t)k * k + (size_t)kt * k + (size_t)k * kr) + 768;
+          if (B.type[cb1] == BT_INADM)
+            e += 8 * ((size_t)std::max(kt, 1) * std::max(kr, 1) + (size_t)T.size[B.t[cb1]] * kr) + 512;
+          if (cb1 > cb0 && need + e > a->run_scratch) break;
+          need += e;
         }
+        unfused_run(cb0, cb1, fNA, fAN);
       }
-      g.run(a);  // TAA R^c^* first (overwrites), then the AN triples accumulate
-      tan_.run(a, f_an);
-      for (int b = b0; b < b1; ++b) {
-        const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-        g.out(S[b], std::max(kt, 1), kt, kr);  // zero without terms
-        if (TNA[i]) g.term(TNA[i], kt, false, col.RXP[r], std::max(kr, 1), true, k);
-        if (Mm[i]) g.term(row.RXP[t], std::max(kt, 1), false, Mm[i], k, false, k);
-      }
-      g.run(a);
     }
     step_end(a, 4);
   });
@@ -722,18 +801,35 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
   // bases); one fused launch per level, two grouped products where a rank
   // exceeds the fused kernel's 64
   Chain3Batch ch;
-  ScopedArena tmp(ctx);  // the two-step paths' middle products, one level at a time
+  // the two-step paths' middle products, in runs of at most run_scratch:
+  // a run is flushed (chained products, first and second products) before
+  // its scratch is reused
+  ScopedArena tmp(ctx);
+  std::vector<std::pair<int, double*>> wide;  // (block, middle product) of the two-step path
+  size_t pend = 0;
   for (int l = 1; l <= T.depth; ++l) {
-    tmp.reset();
     const int b0 = B.lvl[l], b1 = B.lvl[l + 1];
     std::vector<int> parent(b1 - b0, -1);
     for (int pb = B.lvl[l - 1]; pb < b0; ++pb)
       if (B.type[pb] == BT_SPLIT)
         for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - b0] = pb;
-    std::vector<std::pair<int, double*>> wide;  // (block, E_t S_parent) of the two-step path
+    auto flush = [&] {  // S_b += (E_t S_parent) F_r^*
+      ch.run(ctx);
+      g.run(ctx);
+      for (auto [b, Pp] : wide) {
+        const int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
+        const int kpr = col.Q.rank[B.s[parent[b - b0]]];
+        g.out(S[b], kt, kt, kr, true);
+        g.term(Pp, kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
+      }
+      g.run(ctx);
+      wide.clear();
+      tmp.reset();
+      pend = 0;
+    };
     for (int b = b0; b < b1; ++b) {
       const int i = b - b0, t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      if (parent[i] < 0 || kt == 0 || kr == 0) continue;
+      if (parent[i] < 0 || kt == 0 || kr == 0 || !S[b]) continue;  // S[b] null: dense leaf, below
       const int pt = B.t[parent[i]], pr = B.s[parent[i]];
       const int kpt = row.Q.rank[pt], kpr = col.Q.rank[pr];
       if (kpt == 0 || kpr == 0) continue;
@@ -746,32 +842,79 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       g.out(Pp, kt, kt, kpr);
       g.term(row.Q.tr[t], row.Q.tr_ld[t], false, S[parent[i]], kpt, false, kpt);
       wide.push_back({b, Pp});
+      pend += 8 * (size_t)kt * kpr;
+      if (pend > ctx->run_scratch) flush();
     }
-    ch.run(ctx);
-    g.run(ctx);
-    for (auto [b, Pp] : wide) {
-      const int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      const int kpr = col.Q.rank[B.s[parent[b - b0]]];
-      g.out(S[b], kt, kt, kr, true);
-      g.term(Pp, kt, false, col.Q.tr[r], col.Q.tr_ld[r], true, kpr);
-    }
-    g.run(ctx);
+    flush();
   }
   for (int b = 0; b < B.nblocks(); ++b)
     if (B.type[b] == BT_ADM) C.blk[b] = S[b];
-  // dense inadmissible leaves: the nearfield products (already there) plus Q_t S Q^W_r^*
+  // dense inadmissible leaves: the nearfield products (already there) plus
+  // Q_t S Q^W_r^*.  A leaf whose coupling was folded in when it was formed
+  // (S[b] null) adds its parent's part (Q_t E_t) S_parent (Q^W_r F_r)^*.
   {
     const int l = T.depth;
-    tmp.reset();
-    std::vector<std::pair<int, double*>> wide;  // (block, Q_t S) of the two-step path
+    std::vector<int> parent(B.lvl[l + 1] - B.lvl[l], -1);
+    if (l > 0)
+      for (int pb = B.lvl[l - 1]; pb < B.lvl[l]; ++pb)
+        if (B.type[pb] == BT_SPLIT)
+          for (int q = 0; q < 4; ++q) parent[B.child0[pb] + q - B.lvl[l]] = pb;
+    // Q_t E_t and Q^W_r F_r of the leaves that need them
+    std::vector<double*> Wr(T.ncl, nullptr), Wc(T.ncl, nullptr);
+    std::vector<std::pair<int, int>> folded;  // (block, parent) of the folded leaves with a parent part
     for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
       if (B.type[b] != BT_INADM) continue;
+      const int t = B.t[b], r = B.s[b];
+      C.blk[b] = dense_block(t, r);
+      const int pb = parent[b - B.lvl[l]];
+      if (S[b] || pb < 0) continue;
+      const int kt = row.Q.rank[t], kr = col.Q.rank[r], pt = B.t[pb], pr = B.s[pb];
+      const int kpt = row.Q.rank[pt], kpr = col.Q.rank[pr];
+      if (kt == 0 || kr == 0 || kpt == 0 || kpr == 0) continue;
+      folded.push_back({b, pb});
+      const int mt = (int)T.size[t], nr = (int)T.size[r];
+      if (!Wr[t]) {
+        Wr[t] = ws.get<double>((size_t)mt * kpt);
+        g.out(Wr[t], mt, mt, kpt);
+        g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, row.Q.tr[t], row.Q.tr_ld[t], false, kt);
+      }
+      if (!Wc[r]) {
+        Wc[r] = ws.get<double>((size_t)nr * kpr);
+        g.out(Wc[r], nr, nr, kpr);
+        g.term(col.Q.leaf[r], col.Q.leaf_ld[r], false, col.Q.tr[r], col.Q.tr_ld[r], false, kr);
+      }
+    }
+    g.run(ctx);
+    auto flush = [&] {  // D += (Q_t S) Q^W_r^*, or D += ((Q_t E_t) S_parent) (Q^W_r F_r)^*
+      ch.run(ctx);
+      g.run(ctx);
+      for (auto [b, P] : wide) {
+        const int t = B.t[b], r = B.s[b], mt = (int)T.size[t], nr = (int)T.size[r];
+        g.out(C.blk[b], mt, mt, nr, true);
+        if (S[b])
+          g.term(P, mt, false, col.Q.leaf[r], col.Q.leaf_ld[r], true, col.Q.rank[r]);
+        else
+          g.term(P, mt, false, Wc[r], nr, true, col.Q.rank[B.s[parent[b - B.lvl[l]]]]);
+      }
+      g.run(ctx);
+      wide.clear();
+      tmp.reset();
+      pend = 0;
+    };
+    for (auto [b, pb] : folded) {
+      const int t = B.t[b], mt = (int)T.size[t];
+      const int kpt = row.Q.rank[B.t[pb]], kpr = col.Q.rank[B.s[pb]];
+      double* P = tmp.get<double>((size_t)mt * kpr);
+      g.out(P, mt, mt, kpr);
+      g.term(Wr[t], mt, false, S[pb], kpt, false, kpt);
+      wide.push_back({b, P});
+      pend += 8 * (size_t)mt * kpr;
+      if (pend > ctx->run_scratch) flush();
+    }
+    for (int b = B.lvl[l]; b < B.lvl[l + 1]; ++b) {
+      if (B.type[b] != BT_INADM || !S[b]) continue;
       int t = B.t[b], r = B.s[b], kt = row.Q.rank[t], kr = col.Q.rank[r];
-      const auto& dl = dn_of[t];
-      auto it = std::lower_bound(dl.begin(), dl.end(), std::make_pair(r, (double*)nullptr));
-      H2_REQUIRE(it != dl.end() && it->first == r, H2_ERR_SHAPE, "dense leaf of T^XY without nearfield triple");
-      double* Dn = it->second;
-      C.blk[b] = Dn;
+      double* Dn = C.blk[b];
       if (kt == 0 || kr == 0) continue;
       const int mt = (int)T.size[t], nr = (int)T.size[r];
       if (Chain3Batch::fits(mt, nr, kt, kr)) {
@@ -783,17 +926,10 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       g.out(QS, mt, mt, kr);
       g.term(row.Q.leaf[t], row.Q.leaf_ld[t], false, S[b], kt, false, kt);
       wide.push_back({b, QS});
+      pend += 8 * (size_t)mt * kr;
+      if (pend > ctx->run_scratch) flush();
     }
-    ch.run(ctx);
-    g.run(ctx);
-    for (auto [b, QS] : wide) {
-      const int t = B.t[b], r = B.s[b], kr = col.Q.rank[r];
-      const int mt = (int)T.size[t], nr = (int)T.size[r];
-      double* Dn = C.blk[b];
-      g.out(Dn, mt, mt, nr, true);
-      g.term(QS, mt, false, col.Q.leaf[r], col.Q.leaf_ld[r], true, kr);
-    }
-    g.run(ctx);
+    flush();
   }
   step_end(ctx, 4);
 }

@@ -98,7 +98,16 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
   ScopedArena lvl(ctx);
   for (int l = 0; l <= D; ++l) {
     lvl.reset();
+    // the stacked weights in runs of at most run_scratch bytes, each reduced
+    // to its R factors before the run's memory is reused
     TsqrBatch ts;
+    size_t pend = 0;
+    auto flush = [&] {
+      g.run(ctx);
+      ts.run(ctx);
+      lvl.reset();
+      pend = 0;
+    };
     for (int t = T.first(l); t < T.first(l + 1); ++t) {
       int kt = Vb.rank[t];
       int zp = l > 0 ? zr[TreeH::parent(t)] : 0;
@@ -114,7 +123,10 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         zr[t] = 0;
         continue;
       }
+      const size_t e = 8 * (size_t)N * kt;
+      if (pend > 0 && pend + e > ctx->run_scratch) flush();
       double* Gh = lvl.get<double>((size_t)N * kt);
+      pend += e;
       int row = 0;
       if (zp > 0) {
         int kp = Vb.rank[TreeH::parent(t)];
@@ -133,8 +145,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       }
       ts.add(Gh, N, N, kt, false, Zt[t], std::max(kt, 1));
     }
-    g.run(ctx);
-    ts.run(ctx);
+    flush();
   }
 
   // Column trees (leaf lists over the view column) of blocks inside
@@ -303,7 +314,34 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
       }
     }
     g.run(ctx);
-    // C_t / Chat_t
+    // C_t / Chat_t.  Without an old Z, the leaves' C_t are needed only for
+    // their R factors: they are built and reduced in runs below, so that the
+    // level holds one run of them at a time.
+    const bool stream_leaf = leaf && !Kb;
+    auto fill_C = [&](int i, Arena& ar) {
+      const int t = c0 + i, kt = Vb.rank[t];
+      C[i] = ar.get<double>((size_t)std::max(m[i], 1) * std::max(ncols[i], 1));
+      if (m[i] == 0) return;
+      if (zr[t] > 0) {
+        g.out(C[i], m[i], m[i], zr[t]);
+        if (leaf)
+          g.term(Vb.leaf[t], Vb.leaf_ld[t], false, Zt[t], std::max(kt, 1), true, kt);
+        else
+          g.term(Vh[i], m[i], false, Zt[t], std::max(kt, 1), true, kt);
+      }
+      if (leaf) {
+        const int32_t* bl;
+        int cnt;
+        G.row_blocks(t, bl, cnt);
+        for (int q = 0; q < cnt; ++q) {
+          int b = bl[q];
+          if (cols_of[i][q] < 0) continue;
+          int r = G.vcol(b);
+          g.out(C[i] + (size_t)cols_of[i][q] * m[i], m[i], m[i], (int)T.size[r]);
+          g.copy(G.ptr(b), G.ld(b), G.T, (int)T.size[r], 1.0, om + tag[b], 1);
+        }
+      }
+    };
     for (int i = 0; i < nc; ++i) {
       int t = c0 + i, kt = Vb.rank[t];
       const int32_t* bl;
@@ -325,23 +363,7 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         }
       }
       ncols[i] = nco;
-      C[i] = lvl.get<double>((size_t)std::max(m[i], 1) * std::max(nco, 1));
-      if (m[i] == 0) continue;
-      if (zr[t] > 0) {
-        g.out(C[i], m[i], m[i], zr[t]);
-        if (leaf)
-          g.term(Vb.leaf[t], Vb.leaf_ld[t], false, Zt[t], std::max(kt, 1), true, kt);
-        else
-          g.term(Vh[i], m[i], false, Zt[t], std::max(kt, 1), true, kt);
-      }
-      if (leaf)
-        for (int q = 0; q < cnt; ++q) {
-          int b = bl[q];
-          if (cols_of[i][q] < 0) continue;
-          int r = G.vcol(b);
-          g.out(C[i] + (size_t)cols_of[i][q] * m[i], m[i], m[i], (int)T.size[r]);
-          g.copy(G.ptr(b), G.ld(b), G.T, (int)T.size[r], 1.0, om + tag[b], 1);
-        }
+      if (!stream_leaf) fill_C(i, lvl);
     }
     if (!leaf) {
       // Ahat_{t,r}: the children's representations matched to the column tree of (t,r)
@@ -430,11 +452,33 @@ static void coarse_pass(h2_ctx* ctx, const View& G, const std::vector<int>& tag,
         Rt[i] = lvl.get<double>((size_t)m[i] * m[i]);  // rows < p are written
         U[i] = lvl.get<double>((size_t)m[i] * m[i]);
         sg[i] = lvl.get<double>(m[i]);
-        ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
+        if (!stream_leaf) ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
         jb.add(Rt[i], m[i], p, m[i], U[i], m[i], sg[i], rk + i, level_eps(ctx, eps, D, l), 0.0, nullptr, 1,
                ctx->rank_rule);
       }
-      ts.run(ctx);
+      if (stream_leaf) {
+        // runs of at most run_scratch bytes of C_t: built, then reduced to
+        // their R factors, before the run's memory is reused
+        ScopedArena run(ctx);
+        size_t pend = 0;
+        auto flush = [&] {
+          g.run(ctx);
+          ts.run(ctx);
+          run.reset();
+          pend = 0;
+        };
+        for (int i = 0; i < nc; ++i) {
+          if (m[i] == 0) continue;
+          const size_t e = 8 * (size_t)m[i] * std::max(ncols[i], 1);
+          if (pend > 0 && pend + e > ctx->run_scratch) flush();
+          fill_C(i, run);
+          pend += e;
+          ts.add(C[i], m[i], ncols[i], m[i], true, Rt[i], m[i]);
+        }
+        flush();
+      } else {
+        ts.run(ctx);
+      }
       jb.run(ctx);
       const int32_t* kzh = read_back(ctx, rk, nc);
       if (leaf) build_columns();

@@ -369,6 +369,7 @@ AuxRun::AuxRun(h2_ctx* c, h2_ctx* a_, std::function<void(h2_ctx*)> f) : ctx(c), 
   aux->prec = ctx->prec;
   aux->rank_rule = ctx->rank_rule;
   aux->level_factor = ctx->level_factor;
+  aux->run_scratch = ctx->run_scratch;
   // the staging of the previous run is free once that run's work is done
   // (usually long ago): wait for its end event, not for the stream, which is
   // about to wait for ctx's queue
@@ -770,11 +771,10 @@ void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
   // per problem: a register-blocked variant sized by m (the widest factored
   // width), else the streaming kernel in LDS, else in a global scratch slot.
-  // When the batch leaves most of the device idle, tall problems of the
-  // register-blocked variants are cut into row segments factored by separate
-  // workgroups, and a second launch factors each stack of segment factors (a
-  // two-level TSQR tree; R agrees with the one-level result up to the signs
-  // of its rows).
+  // When the batch leaves most of the device idle, tall problems are cut into
+  // row segments factored by separate workgroups, and a second launch
+  // factors each stack of segment factors (a two-level TSQR tree; R agrees
+  // with the one-level result up to the signs of its rows).
   const int lim = lds_limit_doubles();
   constexpr size_t kFillGroups = 1024;  // four workgroups per compute unit
   const size_t want = p.size() < kFillGroups ? kFillGroups / p.size() : 1;
@@ -782,8 +782,10 @@ void TsqrBatch::run(h2_ctx* ctx) {
   for (const TsqrProb& t : p) {
     const int v = tsqr_rb_variant(t.m, lim);
     int parts = 1;
-    if (v && want > 1) {
-      const int64_t seg_min = std::max<int64_t>(2 * tsqr_rb_chunk(v), t.m + 1);
+    if (want > 1) {
+      // segments of at least two row chunks of the variant (four times the
+      // width for the streaming kernel), and taller than wide
+      const int64_t seg_min = std::max<int64_t>(v ? 2 * tsqr_rb_chunk(v) : 4 * (int64_t)t.m, t.m + 1);
       parts = (int)std::min<int64_t>({(int64_t)want, t.N / seg_min, 16});
     }
     if (parts < 2) {

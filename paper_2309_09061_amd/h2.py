@@ -128,6 +128,7 @@ def _declare(lib):
         "h2_step_times": (ctypes.c_int, [_c_p, _c_p, ctypes.c_int, ctypes.c_int]),
         "h2_set_rank_rule": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_set_level_factor": (ctypes.c_int, [_c_p, ctypes.c_double]),
+        "h2_set_run_scratch": (ctypes.c_int, [_c_p, ctypes.c_int64]),
         "h2_debug_fail_after": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_profile": (ctypes.c_int, [_c_p, ctypes.c_int]),
         "h2_kernel_stats": (ctypes.c_int, [_c_p, ctypes.c_int, _c_p, ctypes.c_int]),
@@ -214,6 +215,11 @@ class Context:
         """Level-dependent tolerances: clusters on level l of a tree of depth
         D truncate at eps * zeta**(D - l) (1: one tolerance on all levels)."""
         _check(self.lib, self.lib.h2_set_level_factor(self.h, float(zeta)))
+
+    def set_run_scratch(self, nbytes: int):
+        """Device scratch bound of one run in the steps that take a level in
+        runs (<= 0: the default of 4 GiB); lower peak memory, more launches."""
+        _check(self.lib, self.lib.h2_set_run_scratch(self.h, int(nbytes)))
 
     def fail_after(self, launches: int):
         """Test hook: the launches-th batched launch issued by this context's

@@ -91,6 +91,15 @@ def test_rank_rule_setting_host_only():
     assert lib.h2_set_rank_rule(None, 0) == 1           # NULL context
 
 
+def test_run_scratch_setting_host_only():
+    lib = h2.load()
+    ctx = h2.Context(device=-1)
+    ctx.set_run_scratch(1 << 20)
+    ctx.set_run_scratch(0)                               # back to the default
+    ctx.set_run_scratch(-5)
+    assert lib.h2_set_run_scratch(None, 1 << 20) == 1    # NULL context
+
+
 def test_stats_and_export_of_a_tree(tmp_path):
     """h2_stats and h2_export on a tree (host data only)."""
     lib = h2.load()

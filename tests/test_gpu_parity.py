@@ -292,6 +292,51 @@ def test_workload_full_size(key):
         assert e2m <= w.eps
 
 
+@pytest.mark.parametrize("name,bound", [("sph", 1 << 16), ("ragged", 1 << 14), ("dlp", 1 << 16), ("c5s", 4 << 20)])
+def test_runs_of_bounded_scratch(name, bound):
+    """With a small run bound the steps taken in runs (the triple sums of
+    blocks whose ranks exceed 64, the two-step projections of G's couplings,
+    phase 2's leaf-level C_t) split every level into many runs; G and Z meet
+    the same bars against the oracle as with one run per level (small cases:
+    ranks and dense relative Frobenius distance; the cube recipe at n = 16384,
+    whose ranks reach 165: stored oracle results through the sketches)."""
+    h2 = _h2()
+    c = h2.Context(0)
+    c.set_run_scratch(bound)
+    if name == "c5s":
+        gold = json.load(open(os.path.join(HERE, "golden", "c5s_oracle.json")))
+        w = W.C5S
+        _say(f"[gpu] runs of {bound} bytes: cube recipe n={w.n}")
+        T = h2.Tree(c, w.points(), w.leaf_size, w.eta)
+        X = h2.Matrix.kernel(c, T, w.kernel_x, w.order)
+        G = h2.h2_mul_intermediate(c, X, X, w.eps)
+        Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), w.eps)
+        torch.cuda.synchronize()
+        assert list(G.ranks(0)) == gold["ranks_p1_row"] and list(G.ranks(1)) == gold["ranks_p1_col"]
+        assert list(Z.ranks(0)) == gold["ranks_p2_row"] and list(Z.ranks(1)) == gold["ranks_p2_col"]
+        for M, k in ((G, "G"), (Z, "Z")):
+            whole, cols, scaled, norms, _ = sketch_errors(M, gold, k, w.n)
+            _say(f"[gpu] runs of {bound} bytes: {k} sketch relF {whole:.2e}, worst probe {cols.max():.2e}")
+            assert whole <= 1e-10 and cols.max() <= 1e-10 and scaled.max() <= 1e-10
+        return
+    n, d, leaf, order, kx, ky, eta, seed, dist, eps = CASES[name]
+    _, tree, _, _, p1, p2, _, _ = oracle_case(name)
+    _say(f"[gpu] runs of {bound} bytes: case={name}")
+    pts = W.make_points(seed, n, d, dist)
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, kx, order, normals_of(pts, dist))
+    Y = X if ky == kx else h2.Matrix.kernel(c, T, ky, order, normals_of(pts, dist))
+    G = h2.h2_mul_intermediate(c, X, Y, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    torch.cuda.synchronize()
+    nc = tree.nclusters
+    assert list(G.ranks(0)) == [p1.row.Q.rank[i] for i in range(nc)]
+    assert list(Z.ranks(0)) == [p2.row.Q.rank[i] for i in range(nc)]
+    assert list(Z.ranks(1)) == [p2.col.Q.rank[i] for i in range(nc)]
+    assert relF(dense_of(G, n), p1.G.dense()) < 1e-10
+    assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
+
+
 def test_workload_batched_full_size():
     """The batched workload at full size: 64 independent 2-D products (n from
     2048 to 32768, orders 3 to 5) in one call of each phase; per instance the
