@@ -309,9 +309,15 @@ def main():
                     help="run only this many steps of the headline workload (for profilers) and exit")
     ap.add_argument("--profile-precision", default="fp64", choices=["fp64", "fp32", "bf16x2", "bf16"],
                     help="form of the --profile-steps run")
+    ap.add_argument("--cube-n", type=int, default=0,
+                    help="only the cube recipe (1/r, k = 64, leaf 128) at this n: one warm-up and --steps steps, "
+                         "time, error against X Y and the library's peak device memory, then exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cube_n:
+        cube_only(args.cube_n, max(1, args.steps))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -401,8 +407,62 @@ def main():
         out["cube_k64"] = {"workload": w5.name, "n": w5.n, "order": w5.order, "rank": w5.rank, "eps": w5.eps,
                            "kernel": w5.kernel_x, **r5}
         del P5
+        # the same recipe at n = 2^17 (no stored oracle results: the error
+        # is against X Y), one step after one warm-up
+        w5m = W.C5M
+        P5m = Problem(w5m)
+        r5m = measure_light(P5m, "fp64", 1, 1, None)
+        out["cube_k64_large"] = {"workload": w5m.name, "n": w5m.n, "order": w5m.order, "rank": w5m.rank,
+                                 "eps": w5m.eps, "kernel": w5m.kernel_x, **r5m}
+        del P5m
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(main_w, gold)
+    print(json.dumps(out), flush=True)
+
+
+def cube_only(n: int, steps: int) -> None:
+    """The cube recipe at size n alone (for its largest single-GPU sizes and
+    their profiles); the library allocates through counting callbacks on
+    PyTorch's caching allocator, so the line carries its peak device memory."""
+    import dataclasses
+    import threading
+
+    import torch
+
+    import workloads as W
+    from paper_2309_09061_amd import h2
+    lock = threading.Lock()
+    live, held = {}, {"now": 0, "peak": 0}
+
+    def _alloc(nbytes, _user):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), 0, torch.cuda.current_stream(0).cuda_stream)
+        except Exception:
+            return None
+        with lock:
+            live[p] = int(nbytes)
+            held["now"] += int(nbytes)
+            held["peak"] = max(held["peak"], held["now"])
+        return p
+
+    def _free(p, _user):
+        try:
+            with lock:
+                held["now"] -= live.pop(p, 0)
+            torch.cuda.caching_allocator_delete(p)
+        except Exception:  # interpreter shutdown
+            pass
+    cb = (h2.ALLOC_FN(_alloc), h2.FREE_FN(_free))
+    w = dataclasses.replace(W.C5, name=f"c5_cube_inv_n{n}", n=n)
+    P = Problem.__new__(Problem)
+    P.w = w
+    P.ctx = h2.Context(0, allocator=cb)
+    P.T = h2.Tree(P.ctx, w.points(), w.leaf_size, w.eta)
+    P.X = P.Y = h2.Matrix.kernel(P.ctx, P.T, w.kernel_x, w.order)
+    torch.cuda.synchronize()
+    r = measure_light(P, "fp64", steps, 1, None)
+    out = {"workload": w.name, "n": n, "order": w.order, "rank": w.rank, "eps": w.eps, "kernel": w.kernel_x,
+           "steps": steps, **r, "peak_library_device_bytes": held["peak"]}
     print(json.dumps(out), flush=True)
 
 

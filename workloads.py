@@ -116,7 +116,12 @@ C6S = Workload("dlp_cube_n49152", 61, 49152, 3, "cube_surface", 64, 2.0, 3, "dlp
 C5S = Workload("c5_cube_inv_n16384", 5, 16384, 3, "uniform", 128, 2.0, 4, "inv", "inv", 1e-5,
                "unit cube volume, X = Y, k = 64")
 
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C5, C5S, C6, C6S)}
+# The same recipe at n = 2^17, the bench's large cube case (no stored
+# oracle results: its error is reported against X Y).
+C5M = Workload("c5_cube_inv_n131072", 5, 1 << 17, 3, "uniform", 128, 2.0, 4, "inv", "inv", 1e-5,
+               "unit cube volume, X = Y, k = 64")
+
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C5, C5M, C5S, C6, C6S)}
 
 
 def batched_instances(count: int = 64):
