@@ -337,6 +337,62 @@ def test_runs_of_bounded_scratch(name, bound):
     assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
 
 
+def counting_allocator():
+    """Allocator callbacks on PyTorch's caching allocator that record the
+    bytes the library holds and their peak."""
+    import threading
+    h2 = _h2()
+    lock = threading.Lock()
+    live, held = {}, {"now": 0, "peak": 0}
+    stream = torch.cuda.current_stream(0).cuda_stream
+
+    def _alloc(nbytes, _user):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), 0, stream)
+        except Exception:
+            return None
+        with lock:
+            live[p] = int(nbytes)
+            held["now"] += int(nbytes)
+            held["peak"] = max(held["peak"], held["now"])
+        return p
+
+    def _free(p, _user):
+        try:
+            with lock:
+                held["now"] -= live.pop(p, 0)
+            torch.cuda.caching_allocator_delete(p)
+        except Exception:
+            pass
+    return (h2.ALLOC_FN(_alloc), h2.FREE_FN(_free)), held
+
+
+def test_run_bound_lowers_peak_memory():
+    """The cube recipe at n = 16384 (ranks of G up to 165) with a 4 MiB run
+    bound holds less device memory at its peak than with the default bound,
+    and its G and Z ranks are unchanged; the library's memory comes through
+    the caller's allocator callbacks, which see every chunk."""
+    h2 = _h2()
+    gold = json.load(open(os.path.join(HERE, "golden", "c5s_oracle.json")))
+    w = W.C5S
+    peaks = {}
+    for bound in (0, 4 << 20):
+        cb, held = counting_allocator()
+        c = h2.Context(0, allocator=cb)
+        c.set_run_scratch(bound)
+        T = h2.Tree(c, w.points(), w.leaf_size, w.eta)
+        X = h2.Matrix.kernel(c, T, w.kernel_x, w.order)
+        G = h2.h2_mul_intermediate(c, X, X, w.eps)
+        Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), w.eps)
+        torch.cuda.synchronize()
+        assert list(G.ranks(0)) == gold["ranks_p1_row"] and list(Z.ranks(0)) == gold["ranks_p2_row"]
+        peaks[bound] = held["peak"]
+        _say(f"[gpu] run bound {bound}: peak {held['peak'] / 2**30:.2f} GiB held by the library")
+        del Z, G, X, T
+        c.close()
+    assert peaks[4 << 20] < peaks[0]
+
+
 def test_workload_batched_full_size():
     """The batched workload at full size: 64 independent 2-D products (n from
     2048 to 32768, orders 3 to 5) in one call of each phase; per instance the
