@@ -310,8 +310,9 @@ def main():
     ap.add_argument("--profile-precision", default="fp64", choices=["fp64", "fp32", "bf16x2", "bf16"],
                     help="form of the --profile-steps run")
     ap.add_argument("--cube-n", type=int, default=0,
-                    help="only the cube recipe (1/r, k = 64, leaf 128) at this n: one warm-up and --steps steps, "
-                         "time, error against X Y and the library's peak device memory, then exit")
+                    help="only the cube recipe (1/r, k = 64, leaf 128) at this n, FP64 and FP32-bulk forms: one "
+                         "warm-up and --steps steps each, time, error against X Y and the library's peak device "
+                         "memory, then exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -404,16 +405,22 @@ def main():
         w5 = W.C5S
         P5 = Problem(w5)
         r5 = measure_light(P5, "fp64", max(2, args.steps // 2), 1, load_gold(w5))
+        r5x = measure_light(P5, "fp32", max(2, args.steps // 2), 1, load_gold(w5))
         out["cube_k64"] = {"workload": w5.name, "n": w5.n, "order": w5.order, "rank": w5.rank, "eps": w5.eps,
-                           "kernel": w5.kernel_x, **r5}
+                           "kernel": w5.kernel_x, **r5,
+                           "mixed": {"precision": "fp32 bulk products", **r5x,
+                                     "speedup_vs_fp64": r5["ms_per_step"] / r5x["ms_per_step"]}}
         del P5
         # the same recipe at n = 2^17 (no stored oracle results: the error
         # is against X Y), one step after one warm-up
         w5m = W.C5M
         P5m = Problem(w5m)
         r5m = measure_light(P5m, "fp64", 1, 1, None)
+        r5mx = measure_light(P5m, "fp32", 1, 1, None)
         out["cube_k64_large"] = {"workload": w5m.name, "n": w5m.n, "order": w5m.order, "rank": w5m.rank,
-                                 "eps": w5m.eps, "kernel": w5m.kernel_x, **r5m}
+                                 "eps": w5m.eps, "kernel": w5m.kernel_x, **r5m,
+                                 "mixed": {"precision": "fp32 bulk products", **r5mx,
+                                           "speedup_vs_fp64": r5m["ms_per_step"] / r5mx["ms_per_step"]}}
         del P5m
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(main_w, gold)
@@ -461,8 +468,12 @@ def cube_only(n: int, steps: int) -> None:
     P.X = P.Y = h2.Matrix.kernel(P.ctx, P.T, w.kernel_x, w.order)
     torch.cuda.synchronize()
     r = measure_light(P, "fp64", steps, 1, None)
+    peak64 = held["peak"]
+    rx = measure_light(P, "fp32", steps, 1, None)
     out = {"workload": w.name, "n": n, "order": w.order, "rank": w.rank, "eps": w.eps, "kernel": w.kernel_x,
-           "steps": steps, **r, "peak_library_device_bytes": held["peak"]}
+           "steps": steps, **r, "peak_library_device_bytes": peak64,
+           "mixed": {"precision": "fp32 bulk products", **rx, "speedup_vs_fp64": r["ms_per_step"] / rx["ms_per_step"],
+                     "peak_library_device_bytes": held["peak"]}}
     print(json.dumps(out), flush=True)
 
 
@@ -470,7 +481,8 @@ def measure_batched(steps: int, warmup: int) -> dict:
     """The batched workload (64 independent 2-D products, n 2048..32768,
     orders 3..5): both phases for all 64 in one call of each (instances run
     concurrently on the library's lanes) against a loop of single-product
-    calls, inputs resident; FP64."""
+    calls, inputs resident; FP64, and the batched call with FP32 bulk
+    products."""
     import torch
 
     import workloads as W
@@ -482,9 +494,9 @@ def measure_batched(steps: int, warmup: int) -> dict:
     eps = inst[0][0].eps
     torch.cuda.synchronize()
 
-    def batched():
-        Gs = h2.h2_mul_intermediate(c, Xs, Xs, eps)
-        h2.h2_recompress(c, Gs, [h2.Matrix.zero(c, T) for T in Ts], eps)
+    def batched(prec="fp64"):
+        Gs = h2.h2_mul_intermediate(c, Xs, Xs, eps, prec)
+        h2.h2_recompress(c, Gs, [h2.Matrix.zero(c, T) for T in Ts], eps, prec)
 
     def serial():
         for T, X in zip(Ts, Xs):
@@ -492,7 +504,7 @@ def measure_batched(steps: int, warmup: int) -> dict:
             h2.h2_recompress(c, G, [h2.Matrix.zero(c, T)], eps)
 
     res = {}
-    for name, f in (("batched", batched), ("serial", serial)):
+    for name, f in (("batched", batched), ("serial", serial), ("batched_fp32", lambda: batched("fp32"))):
         for _ in range(max(warmup, 1)):
             f()
         torch.cuda.synchronize()
@@ -505,6 +517,8 @@ def measure_batched(steps: int, warmup: int) -> dict:
     return {"workload": "c4_batched_64", "instances": len(inst), "n_total": int(sum(w.n for w, _ in inst)),
             "ms_per_step_batched": res["batched"], "ms_per_step_serial": res["serial"],
             "speedup_vs_serial": res["serial"] / res["batched"],
+            "ms_per_step_batched_fp32_bulk": res["batched_fp32"],
+            "fp32_bulk_speedup_vs_fp64": res["batched"] / res["batched_fp32"],
             "note": "one call of each phase for all 64 products (up to 4 concurrent instances, each on its "
                     "own streams and host threads) against 64 single-product calls"}
 
