@@ -244,6 +244,7 @@ int lds_limit_doubles();
 size_t qr_need_doubles(int m, int n);
 size_t tsqr_lds_need(int m, int cap);
 size_t tsqr_scratch_need(int m);
+size_t tsqr_chunk_need(int m, int cap);  // LDS doubles of the chunks-only mode
 // register-blocked TSQR variants (1..3; 0 = none fits) for problems whose
 // factored width is at most m, and their LDS need in doubles
 int tsqr_rb_variant(int m, int cap);

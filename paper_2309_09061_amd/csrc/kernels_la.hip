@@ -922,11 +922,21 @@ void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_dou
 constexpr int kTsqrThreads = 512;
 constexpr int kTsqrScratchChunk = 64;
 
-// chunk rows of an m-column problem held in LDS of `cap` doubles; 0: no fit
+// chunk rows of an m-column problem held in LDS of `cap` doubles together
+// with its R factor; 0: no fit
 static __host__ __device__ inline int tsqr_lds_chunk(int m, int cap) {
   const int mm = m > 0 ? m : 1;
   int c = cap / mm - mm;
   if (c > 256) c = 256;
+  c &= ~31;
+  return c >= 32 ? c : 0;
+}
+// chunk rows of a problem whose R factor does not fit beside them: the
+// chunks alone in LDS (R in the global scratch slot); 0: no fit
+static __host__ __device__ inline int tsqr_chunk_rows(int m, int cap) {
+  const int mm = m > 0 ? m : 1;
+  int c = cap / mm;
+  if (c > 64) c = 64;
   c &= ~31;
   return c >= 32 ? c : 0;
 }
@@ -936,34 +946,36 @@ size_t tsqr_lds_need(int m, int cap) {
   return c ? (size_t)(m + c) * m : 0;
 }
 size_t tsqr_scratch_need(int m) { return (size_t)(m + kTsqrScratchChunk) * m; }
+size_t tsqr_chunk_need(int m, int cap) { return (size_t)tsqr_chunk_rows(m, cap) * m; }
 
 __device__ __forceinline__ double tsqr_src(const TsqrProb& P, int64_t idx) {
   return P.prec ? (double)((const float*)P.A)[idx] : ((const double*)P.A)[idx];
 }
 
-// one problem with N > me on the buffer B ((me + ch) x me doubles)
-__device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch, int me, int off, double* red) {
+// one problem with N > me: R (me x me, leading dimension ldr) in Rw and the
+// row chunks (at most ch x me, leading dimension ldc) in C; each lies in LDS
+// or in the workgroup's global scratch slot
+__device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* Rw, int64_t ldr, double* C, int64_t ldc,
+                                            int ch, int me, int off, double* red) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const int m = P.m, N = P.N;
-  const int64_t ld = me + ch;  // rows: R in [0, me), chunk in [me, me + ch)
-  for (int e = tid; e < me * me; e += kTsqrThreads) B[(e % me) + (int64_t)(e / me) * ld] = 0.0;
-  double* C = B + me;
+  for (int e = tid; e < me * me; e += kTsqrThreads) Rw[(e % me) + (int64_t)(e / me) * ldr] = 0.0;
   for (int q0 = 0; q0 < N; q0 += ch) {
     const int cr = min(ch, N - q0);
     if (P.transA) {  // T(i, j) = A[j + i lda], consecutive threads along j
       for (int e = tid; e < cr * me; e += kTsqrThreads) {
         const int j = e % me, i = e / me;
-        C[i + (int64_t)j * ld] = tsqr_src(P, off + j + (int64_t)(q0 + i) * P.lda);
+        C[i + (int64_t)j * ldc] = tsqr_src(P, off + j + (int64_t)(q0 + i) * P.lda);
       }
     } else {
       for (int e = tid; e < cr * me; e += kTsqrThreads) {
         const int i = e % cr, j = e / cr;
-        C[i + (int64_t)j * ld] = tsqr_src(P, (q0 + i) + (int64_t)(off + j) * P.lda);
+        C[i + (int64_t)j * ldc] = tsqr_src(P, (q0 + i) + (int64_t)(off + j) * P.lda);
       }
     }
     __syncthreads();
     for (int jj = 0; jj < me; ++jj) {
-      const double* cj = C + (int64_t)jj * ld;
+      const double* cj = C + (int64_t)jj * ldc;
       double s = 0.0;
       for (int i = tid; i < cr; i += kTsqrThreads) s += cj[i] * cj[i];
       s = wave_sum(s);
@@ -972,7 +984,7 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch
       s = 0.0;
 #pragma unroll
       for (int w = 0; w < kTsqrThreads / 64; ++w) s += red[w];
-      const double alpha = B[jj + (int64_t)jj * ld];
+      const double alpha = Rw[jj + (int64_t)jj * ldr];
       if (s > 0.0) {
         const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
         const double tau = (beta - alpha) / beta;
@@ -985,7 +997,7 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch
           const int c = jj + 1 + c0 + grp;
           const bool live = c0 + grp < nt;
           double d0 = 0.0, d1 = 0.0;
-          double* cc = C + (int64_t)c * ld;
+          double* cc = C + (int64_t)c * ldc;
           if (live) {
             int i = gl;
             for (; i + tpc < cr; i += 2 * tpc) {
@@ -996,7 +1008,7 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch
           }
           const double dsum = group_sum(d0 + d1, tpc);
           if (live) {
-            double* rj = B + jj + (int64_t)c * ld;
+            double* rj = Rw + jj + (int64_t)c * ldr;
             const double d = tau * (*rj + scal * dsum);
             if (gl == 0) *rj -= d;
             const double f = d * scal;
@@ -1004,7 +1016,7 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch
             for (int i = gl; i < cr; i += tpc) cc[i] -= f * cj[i];
           }
         }
-        if (tid == 0) B[jj + (int64_t)jj * ld] = beta;
+        if (tid == 0) Rw[jj + (int64_t)jj * ldr] = beta;
       }
       __syncthreads();
     }
@@ -1012,7 +1024,7 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* B, int ch
   const int p = min(N, m);
   for (int e = tid; e < p * m; e += kTsqrThreads) {
     const int i = e % p, j = e / p;
-    P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? B[i + (int64_t)j * ld] : 0.0;
+    P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? Rw[i + (int64_t)j * ldr] : 0.0;
   }
 }
 
@@ -1039,11 +1051,15 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __re
       }
       if (tid == 0 && P.work) *P.work = 0.0;
     } else {
-      const int ch = tsqr_lds_chunk(m, lds_cap);
-      if (ch > 0)
-        tsqr_reduce(P, lds_dyn, ch, me, off, red);
+      const int ch = tsqr_lds_chunk(m, lds_cap), chh = tsqr_chunk_rows(m, lds_cap);
+      double* slot_p = scratch + (size_t)blockIdx.x * slot;
+      if (ch > 0)  // R and the chunks in LDS
+        tsqr_reduce(P, lds_dyn, me + ch, lds_dyn + me, me + ch, ch, me, off, red);
+      else if (chh > 0)  // R in the global scratch slot, the chunks in LDS
+        tsqr_reduce(P, slot_p, me, lds_dyn, chh, chh, me, off, red);
       else
-        tsqr_reduce(P, scratch + (size_t)blockIdx.x * slot, kTsqrScratchChunk, me, off, red);
+        tsqr_reduce(P, slot_p, me + kTsqrScratchChunk, slot_p + me, me + kTsqrScratchChunk, kTsqrScratchChunk, me,
+                    off, red);
       if (tid == 0 && P.work) {  // Householder QR of an N x me matrix
         const double dn = N, dm = me;
         *P.work = 2.0 * dn * dm * dm - 2.0 * dm * dm * dm / 3.0;

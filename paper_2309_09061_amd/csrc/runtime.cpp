@@ -770,7 +770,9 @@ void TsqrBatch::add(const void* A, int64_t lda, int N, int m, bool transA, doubl
 void TsqrBatch::run(h2_ctx* ctx) {
   if (p.empty()) return;
   // per problem: a register-blocked variant sized by m (the widest factored
-  // width), else the streaming kernel in LDS, else in a global scratch slot.
+  // width), else the streaming kernel in LDS, else the streaming kernel with
+  // R in a global scratch slot and the row chunks in LDS (both in the slot
+  // when even the chunks do not fit).
   // When the batch leaves most of the device idle, tall problems are cut into
   // row segments factored by separate workgroups, and a second launch
   // factors each stack of segment factors (a two-level TSQR tree; R agrees
@@ -838,10 +840,12 @@ void TsqrBatch::run(h2_ctx* ctx) {
         rb_need[v] = std::max(rb_need[v], tsqr_rb_need(v, t.m));
       } else {
         size_t need = tsqr_lds_need(t.m, lim);
-        if (need == 0)
+        if (need == 0) {  // R in a global scratch slot, the row chunks in LDS if they fit
           slot = std::max(slot, tsqr_scratch_need(t.m));
-        else
+          lds = std::max(lds, tsqr_chunk_need(t.m, lim));
+        } else {
           lds = std::max(lds, need);
+        }
       }
     }
     for (int v = 1; v <= 3; ++v) {
