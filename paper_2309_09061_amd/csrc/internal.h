@@ -113,6 +113,9 @@ struct TriOut {
   int32_t m, n;
   int32_t q0, q1;
   int32_t beta, pad;
+  // block kernel only: the output is rows ro.. of op(A) times columns co.. of
+  // op(B) (a 64 x 64 part of a larger output)
+  int32_t ro, co;
 };
 struct TriFamily {
   const int32_t* tri;          // 4 ints per triple: s, bx, by, kind
@@ -653,7 +656,9 @@ struct Chain3Batch {
 struct TriBatch {
   std::vector<TriOut> outs;
   TriFamily fam{};
-  bool block = false;  // outputs <= 64 x 64: one workgroup per output
+  // untransposed operands: one workgroup per output of at most 64 x 64; out()
+  // then cuts a larger output into 64 x 64 parts
+  bool block = false;
   int prec = 0;
   void out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate = false);
   void run(h2_ctx* ctx, double flops);

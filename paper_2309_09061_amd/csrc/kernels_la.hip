@@ -367,7 +367,8 @@ __global__ __launch_bounds__(256) void gemm_tri_kernel(const TriOut* __restrict_
 
 // ---------------------------------------------------------------------------
 // Block form of the triple products for outputs up to 64 x 64 (the dense
-// leaf blocks): one workgroup per output, operands staged through LDS in
+// leaf blocks, or 64 x 64 parts of larger ones: rows ro.. of A times columns
+// co.. of B): one workgroup per output, operands staged through LDS in
 // k-chunks of 16 (A as loaded, B transposed so that both MFMA operands are
 // read along consecutive lanes), each wavefront owning a 32 x 32 quadrant
 // (2 x 2 tiles of 16 x 16).  Global loads run along columns (coalesced).
@@ -405,10 +406,10 @@ __global__ __launch_bounds__(256) void gemm_tri_block_kernel(const TriOut* __res
   int k = 0;
   auto bind = [&](int t) {
     const int4 tr = tri[t];
-    A = F.A[tr.y];
-    B = F.B[tr.z];
     lda = F.lda[tr.y];
     ldb = F.ldb[tr.z];
+    A = F.A[tr.y] + o.ro;                 // rows ro.. of A
+    B = F.B[tr.z] + (int64_t)o.co * ldb;  // columns co.. of B
     k = F.ks ? F.ks[tr.x] : F.k;
   };
   double ra[kPer], rb[kPer];

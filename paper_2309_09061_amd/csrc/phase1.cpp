@@ -458,7 +458,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
     }
     TriBatch tnn;
     tnn.prec = prec;
-    tnn.block = leaf_max <= 64;
+    tnn.block = true;  // 64 x 64 parts of the dense products, one workgroup each
     std::vector<Triple> nn;
     std::vector<std::array<int32_t, 4>> rowl;  // (r, s, bx, by) of one leaf t
     double f_nn = 0;

@@ -615,15 +615,21 @@ void Chain3Batch::run(h2_ctx* ctx) {
 
 void TriBatch::out(double* C, int64_t ldc, int m, int n, int q0, int q1, bool accumulate) {
   if (m <= 0 || n <= 0) return;
-  TriOut o{};
-  o.C = C;
-  o.ldc = std::max<int64_t>(ldc, 1);
-  o.m = m;
-  o.n = n;
-  o.q0 = q0;
-  o.q1 = q1;
-  o.beta = accumulate ? 1 : 0;
-  outs.push_back(o);
+  const int bs = block ? 64 : std::max(m, n);
+  for (int i0 = 0; i0 < m; i0 += bs)
+    for (int j0 = 0; j0 < n; j0 += bs) {
+      TriOut o{};
+      o.C = C + i0 + (int64_t)j0 * std::max<int64_t>(ldc, 1);
+      o.ldc = std::max<int64_t>(ldc, 1);
+      o.m = std::min(bs, m - i0);
+      o.n = std::min(bs, n - j0);
+      o.q0 = q0;
+      o.q1 = q1;
+      o.beta = accumulate ? 1 : 0;
+      o.ro = i0;
+      o.co = j0;
+      outs.push_back(o);
+    }
 }
 
 void TriBatch::run(h2_ctx* ctx, double flops) {
