@@ -550,6 +550,7 @@ void phase1(h2_ctx* ctx, const h2_matrix* Xm, const h2_matrix* Ym, double eps, i
       tna.fam = fNA;
       tan_.fam = fAN;
       taa.prec = tna.prec = tan_.prec = prec;
+      taa.block = tna.block = true;  // untransposed operands: 64 x 64 parts on the block kernel
       const int nb = c1b - c0b;
       std::vector<double*> TAA(nb, nullptr), TNA(nb, nullptr), Mm(nb, nullptr);
       double f_aa = 0, f_na = 0, f_an = 0;
