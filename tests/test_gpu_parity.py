@@ -396,8 +396,9 @@ def test_run_bound_lowers_peak_memory():
 def test_workload_batched_full_size():
     """The batched workload at full size: 64 independent 2-D products (n from
     2048 to 32768, orders 3 to 5) in one call of each phase; per instance the
-    rank profiles of both phases (digest and per-level sums) and Z x at
-    sampled positions against the stored oracle results."""
+    rank profiles of both phases (digest and per-level sums), Z x at sampled
+    positions and G and Z through two-sided sketches against the stored
+    oracle results; the FP32-bulk form of the same call within 2 eps."""
     import hashlib
     path = os.path.join(HERE, "golden", "c4_oracle.json")
     if not os.path.exists(path):
@@ -445,6 +446,25 @@ def test_workload_batched_full_size():
             sk = psi.T @ out.cpu().numpy()
             ref = np.array(g["sketch_" + k])
             assert np.linalg.norm(sk - ref) <= 1e-10 * np.linalg.norm(ref), (w.name, k)
+    # the FP32-bulk form of the same call: G and Z within 2 eps of the oracle's
+    eps = inst[0][0].eps
+    Gm = h2.h2_mul_intermediate(c, Xs, Xs, eps, "fp32")
+    Zm = h2.h2_recompress(c, Gm, [h2.Matrix.zero(c, T) for T in Ts], eps, "fp32")
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (w, _), G, Z, g in zip(inst, Gm, Zm, gold["instances"]):
+        om = colmajor(W.probe_vectors(g["sketch_probe_seed"], w.n, 8))
+        psi = W.probe_vectors(g["sketch_seed"], w.n, 8)
+        for M, k in ((G, "G"), (Z, "Z")):
+            out = zeros_colmajor(w.n, 8)
+            M.matvec(om, out)
+            torch.cuda.synchronize()
+            sk = psi.T @ out.cpu().numpy()
+            ref = np.array(g["sketch_" + k])
+            d = np.linalg.norm(sk - ref) / np.linalg.norm(ref)
+            worst = max(worst, d)
+            assert d <= 2 * eps, (w.name, k, d)
+    _say(f"[gpu] batched workload fp32 bulk: worst sketch distance {worst:.2e}")
 
 
 # ---------------------------------------------------------------------------
@@ -572,6 +592,13 @@ def test_batched_products():
     for (n, _, _), G, Z, (p1, p2) in zip(specs, Gs, Zs, refs):
         assert relF(dense_of(G, n), p1.G.dense()) < 1e-10
         assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
+    # the batched workload's mixed form: FP32 bulk products, within 2 eps
+    Gm = h2.h2_mul_intermediate(c, Xs, Xs, eps, "fp32")
+    Zm = h2.h2_recompress(c, Gm, [h2.Matrix.zero(c, T) for T in Ts], eps, "fp32")
+    torch.cuda.synchronize()
+    for (n, _, _), G, Z, (p1, p2) in zip(specs, Gm, Zm, refs):
+        assert relF(dense_of(G, n), p1.G.dense()) <= 2 * eps
+        assert relF(dense_of(Z, n), p2.Z.dense()) <= 2 * eps
 
 
 @pytest.mark.parametrize("name", ["1d", "2d", "ragged"])
