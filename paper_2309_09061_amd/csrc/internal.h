@@ -608,7 +608,7 @@ h2_ctx* aux_ctx(h2_ctx* ctx);
 // each on a lane context of the root context (own stream, workspace and
 // staging, and its own auxiliary contexts for its column pass and dense
 // products); lane_ctx(ctx, w) creates lane w on first use
-constexpr int kBatchLanes = 4;
+constexpr int kBatchLanes = 8;
 h2_ctx* lane_ctx(h2_ctx* ctx, int w);
 // Runs f(aux) on a host thread, on the auxiliary stream, ordered after the
 // work queued so far on ctx->stream.  join() waits for the thread, makes
