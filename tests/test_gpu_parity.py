@@ -393,6 +393,49 @@ def test_run_bound_lowers_peak_memory():
     assert peaks[4 << 20] < peaks[0]
 
 
+def test_cube_recipe_at_n131072():
+    """The cube recipe (1/r, k = 64, leaf 128) at n = 131072, eight times the
+    size of its stored oracle results: every level step there takes several
+    runs of the default bound and the dense leaves' couplings are folded in
+    when formed.  Properties that hold at any size: Z within eps of X Y by
+    power iteration; the product again with a 1 GiB run bound (other runs,
+    other TSQR segments) has the same rank profiles and agrees with the first
+    through a two-sided sketch of 8 probes to 1e-10."""
+    h2 = _h2()
+    w = W.C5M
+    c = h2.Context(0)
+    _say(f"[gpu] cube recipe n={w.n}: build")
+    T = h2.Tree(c, w.points(), w.leaf_size, w.eta)
+    X = h2.Matrix.kernel(c, T, w.kernel_x, w.order)
+    om = colmajor(W.probe_vectors(71, w.n, 8))
+    psi = W.probe_vectors(72, w.n, 8)
+    res = []
+    for bound in (0, 1 << 30):
+        c.set_run_scratch(bound)
+        _say(f"[gpu] cube recipe n={w.n}: run bound {bound}")
+        G = h2.h2_mul_intermediate(c, X, X, w.eps)
+        Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), w.eps)
+        torch.cuda.synchronize()
+        sk = {}
+        for M, k in ((G, "G"), (Z, "Z")):
+            out = zeros_colmajor(w.n, 8)
+            M.matvec(om, out)
+            torch.cuda.synchronize()
+            sk[k] = psi.T @ out.cpu().numpy()
+        ranks = [list(G.ranks(0)), list(G.ranks(1)), list(Z.ranks(0)), list(Z.ranks(1))]
+        if bound == 0:
+            e2 = power_eps2(Z, X, X, w.n, 73, 20)
+            _say(f"[gpu] cube recipe n={w.n}: eps2 = {e2:.3e}")
+            assert e2 <= w.eps
+        res.append((ranks, sk))
+        del G, Z
+    assert res[0][0] == res[1][0]
+    for k in ("G", "Z"):
+        d = np.linalg.norm(res[0][1][k] - res[1][1][k]) / np.linalg.norm(res[0][1][k])
+        _say(f"[gpu] cube recipe n={w.n}: {k} default against 1 GiB runs: {d:.2e}")
+        assert d <= 1e-10
+
+
 def test_workload_batched_full_size():
     """The batched workload at full size: 64 independent 2-D products (n from
     2048 to 32768, orders 3 to 5) in one call of each phase; per instance the
