@@ -44,7 +44,7 @@ typedef enum {
   H2_ERR_ALLOC = 3,        /* device or host allocation failed */
   H2_ERR_DEVICE = 4,       /* a HIP call or kernel launch failed */
   H2_ERR_NOT_REFINED = 5,  /* T^XY does not refine the target block tree T_IK */
-  H2_ERR_UNSUPPORTED = 6,  /* e.g. Z with non-zero blocks, general (non-uniform) trees */
+  H2_ERR_UNSUPPORTED = 6,  /* e.g. bases of unequal rank, a block structure outside the method's */
   H2_ERR_NUMERIC = 7       /* NaN or Inf met where a finite value is required */
 } h2_status;
 
@@ -190,7 +190,12 @@ h2_status h2_compress_kernel_normals(h2_ctx* ctx, const h2_tree* tree, h2_kernel
  *              matrices (the default rule; h2_set_rank_rule selects the
  *              relative-Frobenius variant); eps = 0 keeps every non-zero
  *              singular value and G then represents X Y exactly.
- * G_out[i] receives a new handle per product. */
+ * G_out[i] receives a new handle per product.  With count > 1 the products
+ * run concurrently, up to eight at a time, each on its own streams and host
+ * thread (results equal to count separate calls); HIP's default of four
+ * hardware queues per process then limits their overlap, and a process
+ * that batches may start with GPU_MAX_HW_QUEUES=16 (measured best).  On an
+ * error every G_out[i] is left NULL. */
 h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
                               const h2_matrix* const* Y, double eps, h2_precision prec,
                               h2_product** G_out);
