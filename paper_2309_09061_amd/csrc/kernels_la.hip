@@ -920,7 +920,8 @@ void k_apply(const ApplyProb* probs, const int32_t* work, int nwork, int lds_dou
 // reflector whose vector is e_jj on the R part and C(:, jj) / (alpha - beta)
 // on the chunk part, so each step touches row jj of R and the chunk only.
 // ---------------------------------------------------------------------------
-constexpr int kTsqrThreads = 512;
+constexpr int kTsqrThreads = 512;        // register-blocked variants
+constexpr int kTsqrStreamThreads = 1024;  // streaming kernel: one problem per 1024-thread workgroup
 constexpr int kTsqrScratchChunk = 64;
 
 // chunk rows of an m-column problem held in LDS of `cap` doubles together
@@ -960,16 +961,16 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* Rw, int64
                                             int ch, int me, int off, double* red) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const int m = P.m, N = P.N;
-  for (int e = tid; e < me * me; e += kTsqrThreads) Rw[(e % me) + (int64_t)(e / me) * ldr] = 0.0;
+  for (int e = tid; e < me * me; e += kTsqrStreamThreads) Rw[(e % me) + (int64_t)(e / me) * ldr] = 0.0;
   for (int q0 = 0; q0 < N; q0 += ch) {
     const int cr = min(ch, N - q0);
     if (P.transA) {  // T(i, j) = A[j + i lda], consecutive threads along j
-      for (int e = tid; e < cr * me; e += kTsqrThreads) {
+      for (int e = tid; e < cr * me; e += kTsqrStreamThreads) {
         const int j = e % me, i = e / me;
         C[i + (int64_t)j * ldc] = tsqr_src(P, off + j + (int64_t)(q0 + i) * P.lda);
       }
     } else {
-      for (int e = tid; e < cr * me; e += kTsqrThreads) {
+      for (int e = tid; e < cr * me; e += kTsqrStreamThreads) {
         const int i = e % cr, j = e / cr;
         C[i + (int64_t)j * ldc] = tsqr_src(P, (q0 + i) + (int64_t)(off + j) * P.lda);
       }
@@ -978,13 +979,13 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* Rw, int64
     for (int jj = 0; jj < me; ++jj) {
       const double* cj = C + (int64_t)jj * ldc;
       double s = 0.0;
-      for (int i = tid; i < cr; i += kTsqrThreads) s += cj[i] * cj[i];
+      for (int i = tid; i < cr; i += kTsqrStreamThreads) s += cj[i] * cj[i];
       s = wave_sum(s);
       if ((tid & 63) == 0) red[wave] = s;
       __syncthreads();
       s = 0.0;
 #pragma unroll
-      for (int w = 0; w < kTsqrThreads / 64; ++w) s += red[w];
+      for (int w = 0; w < kTsqrStreamThreads / 64; ++w) s += red[w];
       const double alpha = Rw[jj + (int64_t)jj * ldr];
       if (s > 0.0) {
         const double beta = -copysign(sqrt(alpha * alpha + s), alpha);
@@ -992,8 +993,8 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* Rw, int64
         const double scal = 1.0 / (alpha - beta);  // v = [1; scal * C(:, jj)]
         const int nt = me - jj - 1;
         int tpc = 64;
-        while (tpc > 1 && tpc * nt > kTsqrThreads) tpc >>= 1;
-        const int grp = tid / tpc, gl = tid % tpc, ngrp = kTsqrThreads / tpc;
+        while (tpc > 1 && tpc * nt > kTsqrStreamThreads) tpc >>= 1;
+        const int grp = tid / tpc, gl = tid % tpc, ngrp = kTsqrStreamThreads / tpc;
         for (int c0 = 0; c0 < nt; c0 += ngrp) {
           const int c = jj + 1 + c0 + grp;
           const bool live = c0 + grp < nt;
@@ -1023,16 +1024,16 @@ __device__ __forceinline__ void tsqr_reduce(const TsqrProb& P, double* Rw, int64
     }
   }
   const int p = min(N, m);
-  for (int e = tid; e < p * m; e += kTsqrThreads) {
+  for (int e = tid; e < p * m; e += kTsqrStreamThreads) {
     const int i = e % p, j = e / p;
     P.R[i + (int64_t)j * P.ldr] = (i <= j && j < me) ? Rw[i + (int64_t)j * ldr] : 0.0;
   }
 }
 
-__global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
+__global__ __launch_bounds__(kTsqrStreamThreads) void tsqr_kernel(const TsqrProb* __restrict__ probs, int nprob,
                                                             double* __restrict__ scratch, size_t slot,
                                                             int lds_cap) {
-  __shared__ double red[kTsqrThreads / 64];
+  __shared__ double red[kTsqrStreamThreads / 64];
   const int tid = threadIdx.x;
   for (int pi = blockIdx.x; pi < nprob; pi += gridDim.x) {
     const TsqrProb P = probs[pi];
@@ -1044,7 +1045,7 @@ __global__ __launch_bounds__(kTsqrThreads) void tsqr_kernel(const TsqrProb* __re
       // T itself is a factor with T^T T = R^T R (N rows): no reduction.  (The
       // structured step needs N > me: with fewer rows its R is not confined
       // to the first N rows.)
-      for (int e = tid; e < p * m; e += kTsqrThreads) {
+      for (int e = tid; e < p * m; e += kTsqrStreamThreads) {
         const int i = e % p, j = e / p;
         double v = 0.0;
         if (j < me) v = tsqr_src(P, P.transA ? off + j + (int64_t)i * P.lda : i + (int64_t)(off + j) * P.lda);
@@ -1265,7 +1266,7 @@ void k_tsqr(const TsqrProb* probs, int n, size_t lds_doubles, size_t slot, doubl
   if (n <= 0) return;
   H2_REQUIRE(slot == 0 || scratch, H2_ERR_ARG, "tsqr: global scratch missing");
   const int grid = slot == 0 ? n : std::min(n, 1024);
-  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(kTsqrThreads), lds_doubles * 8, (hipStream_t)stream, probs,
+  hipLaunchKernelGGL(tsqr_kernel, dim3(grid), dim3(kTsqrStreamThreads), lds_doubles * 8, (hipStream_t)stream, probs,
                      n, scratch, slot, lds_limit_doubles());
   HIP_OK(hipGetLastError());
 }
