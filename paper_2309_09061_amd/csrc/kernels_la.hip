@@ -934,12 +934,13 @@ static __host__ __device__ inline int tsqr_lds_chunk(int m, int cap) {
   return c >= 32 ? c : 0;
 }
 // chunk rows of a problem whose R factor does not fit beside them: the
-// chunks alone in LDS (R in the global scratch slot); 0: no fit
+// chunks alone in LDS (R in the global scratch slot), as many rows as fit,
+// up to 128 in steps of 16; 0: no fit
 static __host__ __device__ inline int tsqr_chunk_rows(int m, int cap) {
   const int mm = m > 0 ? m : 1;
   int c = cap / mm;
-  if (c > 64) c = 64;
-  c &= ~31;
+  if (c > 128) c = 128;
+  c &= ~15;
   return c >= 32 ? c : 0;
 }
 
