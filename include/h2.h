@@ -185,7 +185,10 @@ h2_status h2_compress_kernel_normals(h2_ctx* ctx, const h2_tree* tree, h2_kernel
 /* Phase 1 for `count` independent products X[i] Y[i] (Section 4, Figure
  * "induced_basis", for the row basis and, on the adjoint pair (Y*, X*), for
  * the column basis; Section 5 block scaling; intermediate product G on
- * T^XY).  X[i] and Y[i] must be built on the same cluster tree.
+ * T^XY).  X[i] and Y[i] must be built on the same cluster tree.  A zero
+ * matrix (h2_zero_like, not yet filled by h2_recompress) as a factor is
+ * H2_ERR_ARG, checked before any device work: it has no bases from which
+ * the induced bases could be formed, and its product is zero.
  *   eps > = 0: ranks keep the singular values > eps of the block-scaled
  *              matrices (the default rule; h2_set_rank_rule selects the
  *              relative-Frobenius variant); eps = 0 keeps every non-zero

@@ -237,6 +237,8 @@ h2_status h2_mul_intermediate(h2_ctx* ctx, int count, const h2_matrix* const* X,
     for (int i = 0; i < count; ++i) {
       G_out[i] = nullptr;
       H2_REQUIRE(X[i] && Y[i], H2_ERR_ARG, "NULL factor");
+      H2_REQUIRE(!X[i]->zero && !Y[i]->zero, H2_ERR_ARG,
+                 "a factor is a zero matrix (h2_zero_like, not yet filled by h2_recompress)");
     }
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
     check_precision((int)prec, eps);

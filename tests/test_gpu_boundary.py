@@ -233,6 +233,45 @@ def test_handles_outlive_their_context():
     assert count[1] == count[0]
 
 
+def test_zero_factor_is_rejected():
+    """A zero matrix (h2_zero_like, not yet filled by phase 2) as a factor of
+    phase 1 is H2_ERR_ARG in either position, in both and inside a batch,
+    checked before any device work.  The zero matrix itself densifies and
+    multiplies vectors as zero, and a product on the same context after the
+    rejected calls equals the one before them bit for bit."""
+    h2 = _h2()
+    c = h2.Context(0)
+    n, eps = 900, 1e-6
+    _, T, X, _ = _problem(c, n, 2, 32, 3, "log", "log", 1.0, 41)
+    Z0 = h2.Matrix.zero(c, T)
+    _say("[gpu] zero matrix: dense form and matvec")
+    assert not dense_of(Z0, n).any()
+    x = zeros_colmajor(n, 2)
+    x.copy_(torch.from_numpy(np.random.default_rng(41).standard_normal((n, 2))))
+    y = zeros_colmajor(n, 2)
+    y.fill_(3.0)
+    Z0.matvec(x, y, alpha=2.0, beta=0.5)
+    torch.cuda.synchronize()
+    assert bool((y == 1.5).all())
+    _say("[gpu] reference product before the rejected calls")
+    G = h2.h2_mul_intermediate(c, X, X, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    ref_g, ref_z, ref_r = dense_of(G, n), dense_of(Z, n), list(Z.ranks(0))
+    for a, b in ((Z0, X), (X, Z0), (Z0, Z0)):
+        with pytest.raises(h2.H2Error) as e:
+            h2.h2_mul_intermediate(c, a, b, eps)
+        assert e.value.code == 1
+    with pytest.raises(h2.H2Error) as e:
+        h2.h2_mul_intermediate(c, [X, Z0], [X, X], eps)
+    assert e.value.code == 1
+    _say("[gpu] product after the rejected calls")
+    G2 = h2.h2_mul_intermediate(c, X, X, eps)
+    Z2 = h2.h2_recompress(c, G2, h2.Matrix.zero(c, T), eps)
+    assert np.array_equal(dense_of(G2, n), ref_g)
+    assert np.array_equal(dense_of(Z2, n), ref_z)
+    assert list(Z2.ranks(0)) == ref_r
+
+
 def test_batched_call_with_a_failing_instance():
     """A batched call runs its instances concurrently on lane contexts; an
     instance that fails validation inside phase 1 (X and Y of different
