@@ -225,7 +225,10 @@ h2_status h2_zero_like(h2_ctx* ctx, const h2_tree* tree, double eta_Z, h2_matrix
  * leaf case): the new bases start with an orthonormal basis of them
  * (numerical rank at 1e-12 relative) and add the truncated part of G outside
  * them, so the old Z is represented exactly and only G is compressed.  Z's
- * memory is replaced at the end of the call; on an error Z is unchanged. */
+ * memory is replaced at the end of the call; on an error Z is unchanged.
+ * The Z[i] of one call must be distinct handles (H2_ERR_ARG otherwise,
+ * checked before any device work): the instances run concurrently.  The
+ * G[i] are only read and may repeat. */
 h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix* const* Z,
                         double eps, h2_precision prec);
 

@@ -1,5 +1,6 @@
 // extern "C" entry points of include/h2.h.  Arguments are validated here
 // before any launch; internal errors are exceptions mapped to status codes.
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -314,6 +315,13 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
   return guard([&] {
     H2_REQUIRE(G && Z && count >= 1, H2_ERR_ARG, "bad arguments");
     for (int i = 0; i < count; ++i) H2_REQUIRE(G[i] && Z[i], H2_ERR_ARG, "NULL operand");
+    {
+      // the instances run concurrently and each replaces its Z at the end
+      std::vector<const h2_matrix*> zs(Z, Z + count);
+      std::sort(zs.begin(), zs.end());
+      H2_REQUIRE(std::adjacent_find(zs.begin(), zs.end()) == zs.end(), H2_ERR_ARG,
+                 "a target Z appears more than once in one call");
+    }
     H2_REQUIRE(std::isfinite(eps) && eps >= 0, H2_ERR_ARG, "eps must be >= 0");
     check_precision((int)prec, eps);
     need_device(ctx);

@@ -272,6 +272,28 @@ def test_zero_factor_is_rejected():
     assert list(Z2.ranks(0)) == ref_r
 
 
+def test_target_given_twice_is_rejected():
+    """One target Z twice in a batched phase 2: H2_ERR_ARG before any device
+    work, Z unchanged.  One product G twice with distinct targets is allowed
+    (G is only read): both results equal the single call's bit for bit."""
+    h2 = _h2()
+    c = h2.Context(0)
+    n, eps = 900, 1e-6
+    _, T, X, _ = _problem(c, n, 2, 32, 3, "log", "log", 1.0, 43)
+    G = h2.h2_mul_intermediate(c, X, X, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    before = dense_of(Z, n)
+    _say("[gpu] batched phase 2 with one target twice")
+    with pytest.raises(h2.H2Error) as e:
+        h2.h2_recompress(c, [G, G], [Z, Z], eps)
+    assert e.value.code == 1
+    assert np.array_equal(dense_of(Z, n), before)
+    _say("[gpu] batched phase 2 with one product twice")
+    Za, Zb = h2.h2_recompress(c, [G, G], [h2.Matrix.zero(c, T), h2.Matrix.zero(c, T)], eps)
+    assert np.array_equal(dense_of(Za, n), before)
+    assert np.array_equal(dense_of(Zb, n), before)
+
+
 def test_batched_call_with_a_failing_instance():
     """A batched call runs its instances concurrently on lane contexts; an
     instance that fails validation inside phase 1 (X and Y of different
