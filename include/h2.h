@@ -234,7 +234,8 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
 
 /* y <- alpha op(A) x + beta y for nvec column-major device vectors in cluster
  * order (O(nk) H^2 matrix-vector product: forward transform, couplings,
- * backward transform, nearfield).  op is 'N' or 'T'.  x and y must not overlap. */
+ * backward transform, nearfield).  op is 'N' or 'T'.  x and y (n x nvec
+ * doubles each) must not overlap: H2_ERR_ARG, before anything is launched. */
 h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x,
                     double beta, double* y, int nvec);
 

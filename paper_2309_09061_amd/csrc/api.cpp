@@ -342,11 +342,18 @@ h2_status h2_recompress(h2_ctx* ctx, int count, h2_product* const* G, h2_matrix*
   });
 }
 
+// [x, x + len) and [y, y + len) share an address
+static bool vectors_overlap(const double* x, const double* y, int64_t len) {
+  const uintptr_t a = (uintptr_t)x, b = (uintptr_t)y, bytes = (uintptr_t)len * sizeof(double);
+  return a < b + bytes && b < a + bytes;
+}
+
 h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* A, char op, double alpha, const double* x, double beta,
                     double* y, int nvec) {
   return guard([&] {
     H2_REQUIRE(A && x && y && nvec >= 1, H2_ERR_ARG, "bad arguments");
     H2_REQUIRE(op == 'N' || op == 'T', H2_ERR_ARG, "op must be 'N' or 'T'");
+    H2_REQUIRE(!vectors_overlap(x, y, A->c.ct->n * (int64_t)nvec), H2_ERR_ARG, "x and y overlap");
     need_device(ctx);
     begin_call(ctx);
     matvec(ctx, A->c, op == 'T', alpha, x, beta, y, nvec);
@@ -358,6 +365,7 @@ h2_status h2_matvec_noalloc(h2_ctx* ctx, const h2_matrix* A, char op, double alp
   return guard([&] {
     H2_REQUIRE(A && x && y && nvec >= 1, H2_ERR_ARG, "bad arguments");
     H2_REQUIRE(op == 'N' || op == 'T', H2_ERR_ARG, "op must be 'N' or 'T'");
+    H2_REQUIRE(!vectors_overlap(x, y, A->c.ct->n * (int64_t)nvec), H2_ERR_ARG, "x and y overlap");
     need_device(ctx);
     begin_call(ctx);
     matvec_noalloc(ctx, A->c, op == 'T', alpha, x, beta, y, nvec);
@@ -369,6 +377,7 @@ h2_status h2_product_matvec(h2_ctx* ctx, const h2_product* G, char op, double al
   return guard([&] {
     H2_REQUIRE(G && x && y && nvec >= 1, H2_ERR_ARG, "bad arguments");
     H2_REQUIRE(op == 'N' || op == 'T', H2_ERR_ARG, "op must be 'N' or 'T'");
+    H2_REQUIRE(!vectors_overlap(x, y, G->c.ct->n * (int64_t)nvec), H2_ERR_ARG, "x and y overlap");
     need_device(ctx);
     begin_call(ctx);
     matvec(ctx, G->c, op == 'T', alpha, x, beta, y, nvec);

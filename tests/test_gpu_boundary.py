@@ -294,6 +294,35 @@ def test_target_given_twice_is_rejected():
     assert np.array_equal(dense_of(Zb, n), before)
 
 
+def test_overlapping_vectors_are_rejected():
+    """x and y of a matrix-vector product that share memory: H2_ERR_ARG from
+    h2_matvec, h2_matvec_noalloc and h2_product_matvec before anything is
+    launched (y unchanged); adjacent halves of one buffer are accepted and
+    give the result of separate buffers bit for bit."""
+    h2 = _h2()
+    c = h2.Context(0)
+    n, eps = 900, 1e-6
+    _, T, X, _ = _problem(c, n, 2, 32, 3, "log", "log", 1.0, 47)
+    G = h2.h2_mul_intermediate(c, X, X, eps)
+    buf = torch.from_numpy(np.random.default_rng(47).standard_normal(2 * n)).cuda()
+    keep = buf.clone()
+    _say("[gpu] matvec with overlapping x and y")
+    for call in (X.matvec, X.matvec_noalloc, G.matvec):
+        with pytest.raises(h2.H2Error) as e:
+            call(buf[: n], buf[n // 2: n // 2 + n])
+        assert e.value.code == 1
+        torch.cuda.synchronize()
+        assert torch.equal(buf, keep)
+    _say("[gpu] matvec with adjacent halves of one buffer")
+    for call in (X.matvec, X.matvec_noalloc, G.matvec):
+        ref = torch.zeros(n, dtype=torch.float64, device="cuda")
+        call(keep[: n], ref)
+        buf.copy_(keep)
+        call(buf[: n], buf[n:])
+        torch.cuda.synchronize()
+        assert torch.equal(buf[n:], ref) and torch.equal(buf[: n], keep[: n])
+
+
 def test_batched_call_with_a_failing_instance():
     """A batched call runs its instances concurrently on lane contexts; an
     instance that fails validation inside phase 1 (X and Y of different
