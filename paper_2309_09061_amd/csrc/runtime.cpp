@@ -800,13 +800,15 @@ void TsqrBatch::run(h2_ctx* ctx) {
       first.push_back({v, t});
       continue;
     }
-    const int64_t seg = (t.N + parts - 1) / parts;
-    parts = (int)((t.N + seg - 1) / seg);
+    // balanced segments of at least floor(N / parts) >= seg_min > m rows: the
+    // factor of each fills all m rows of its slot in the stack (a factor of
+    // fewer rows than m would leave rows of the slot unwritten)
     const int64_t ld_stack = (int64_t)parts * t.m;
     double* stack = ctx->ws.get<double>((size_t)ld_stack * t.m);
     const size_t es = t.prec ? sizeof(float) : sizeof(double);
     for (int q = 0; q < parts; ++q) {
-      const int64_t r0 = q * seg, r1 = std::min<int64_t>(t.N, r0 + seg);
+      const int64_t r0 = (int64_t)t.N * q / parts, r1 = (int64_t)t.N * (q + 1) / parts;
+      H2_REQUIRE(r1 - r0 >= t.m, H2_ERR_ARG, "tsqr: a row segment shorter than the width");
       TsqrProb u = t;
       u.A = (const char*)t.A + (size_t)(t.transA ? r0 * t.lda : r0) * es;
       u.N = (int32_t)(r1 - r0);
