@@ -706,6 +706,32 @@ def test_level_dependent_tolerances(name, zeta, rule):
     assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
 
 
+def test_largest_rank_in_one_dimension():
+    """k = 128 exactly (order 128 in 1-D, the largest k the library takes)
+    with the log kernel, n = 4096, leaf 256, eps 1e-8: phase-1 ranks reach
+    132.  Ranks of both phases and both sides equal the oracle's; G and Z
+    lie within relative Frobenius 1e-10 of its results."""
+    h2 = _h2()
+    n, leaf, order, eta, eps = 4096, 256, 128, 1.0, 1e-8
+    pts = W.make_points(59, n, 1, "uniform")
+    tree, bt, Xo, _ = O.build_problem(pts, leaf, eta, order, "log", "log")
+    p1, p2 = O.multiply(Xo, Xo, bt, eps)
+    c = ctx()
+    T = h2.Tree(c, pts, leaf, eta)
+    X = h2.Matrix.kernel(c, T, "log", order)
+    _say(f"[gpu] k = {order}: 1-D n={n}")
+    G = h2.h2_mul_intermediate(c, X, X, eps)
+    Z = h2.h2_recompress(c, G, h2.Matrix.zero(c, T), eps)
+    torch.cuda.synchronize()
+    nc = tree.nclusters
+    assert list(G.ranks(0)) == [p1.row.Q.rank[i] for i in range(nc)]
+    assert list(G.ranks(1)) == [p1.col.Q.rank[i] for i in range(nc)]
+    assert list(Z.ranks(0)) == [p2.row.Q.rank[i] for i in range(nc)]
+    assert list(Z.ranks(1)) == [p2.col.Q.rank[i] for i in range(nc)]
+    assert relF(dense_of(G, n), p1.G.dense()) < 1e-10
+    assert relF(dense_of(Z, n), p2.Z.dense()) < 1e-10
+
+
 def test_maximum_interpolation_rank():
     """k = 125 (order 5 in 3-D, near the largest k = 128 the library takes)
     on the cube with the 1/r kernel, n = 4096, leaf 128, eps 1e-5: phase-1
